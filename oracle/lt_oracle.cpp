@@ -1,0 +1,647 @@
+// Plain FP64 CPU oracle for constant-memory differentiable light tracing.
+//
+// TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+// benchmark's CPU-baseline leg may load this library.  It shares no code with
+// the HIP path; both read the same seeded scene arrays and nothing else.
+//
+// What it computes (plain definitions, no blocking or fusion):
+//  * the light-tracing image: every light path x0..xk from the emitter, with a
+//    sensor connection at every non-specular vertex i >= 1, each contribution
+//    L_i = W_e f_i G V splatted through a tent reconstruction filter
+//    (Sec. 3.1, Eq. 1-2; splat of Eq. 20);
+//  * the gradient of the loss by *generic taped reverse-mode AD* of the whole
+//    per-path computation (the naive AD baseline of Sec. 3.2), with the
+//    image adjoint dI supplied by the caller: d/dtheta <dI, I(theta)>;
+//  * the ResLRB estimator's gradient: the same tape seeded only at the
+//    reservoir-selected connection R with the weight Omega_k / omega_R held
+//    fixed (Sec. 4.2, Eq. 8-11);
+//  * per-path decision signatures (hit primitive, texel, validity, lobe, R)
+//    so that FP32/FP64 decision flips can be told apart from arithmetic
+//    differences.
+// Parity pins live in the test suite (closed forms, invariants, finite
+// differences, reservoir pmf).
+//
+// Scene conventions (shared *specification*, implemented separately here):
+//  - RNG: Philox-4x32-10 (Salmon et al., SC'11), key = 64-bit seed,
+//    counter = (path, vertex, block, 0); u = (x >> 8) * 2^-24.
+//    Vertex 0: u0,u1 emitter position, u2,u3 emitted direction.
+//    Vertex j>=1: u0,u1 diffuse direction, u2 Fresnel lobe, u3 reservoir.
+//  - Only the primitive choice uses the offset ray origin; the differentiable
+//    hit point is recomputed from the true origin and the hit triangle's plane.
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <algorithm>
+#include <omp.h>
+
+namespace {
+
+// ----------------------------------------------------------------- Philox
+struct U4 { uint32_t x[4]; };
+
+U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += W0; k1 += W1; }
+    uint64_t p0 = (uint64_t)M0 * c.x[0];
+    uint64_t p1 = (uint64_t)M1 * c.x[2];
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    U4 n;
+    n.x[0] = hi1 ^ c.x[1] ^ k0;
+    n.x[1] = lo1;
+    n.x[2] = hi0 ^ c.x[3] ^ k1;
+    n.x[3] = lo0;
+    c = n;
+  }
+  return c;
+}
+
+struct Uniform4 { double u[4]; };
+
+Uniform4 rng4(uint64_t seed, uint32_t path, uint32_t vertex, uint32_t block) {
+  U4 c{{path, vertex, block, 0u}};
+  U4 r = philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  Uniform4 o;
+  for (int i = 0; i < 4; ++i) o.u[i] = (double)(r.x[i] >> 8) * (1.0 / 16777216.0);
+  return o;
+}
+
+uint32_t fnv1a(uint32_t h, uint32_t w) {
+  for (int b = 0; b < 4; ++b) { h ^= (w >> (8 * b)) & 0xFFu; h *= 0x01000193u; }
+  return h;
+}
+
+// ----------------------------------------------------------------- tape AD
+struct Tape {
+  std::vector<int> a, b;
+  std::vector<double> da, db;
+  std::vector<std::pair<int, long>> leaves;  // (node, parameter slot)
+  void clear() { a.clear(); b.clear(); da.clear(); db.clear(); leaves.clear(); }
+  int push(int ia, double pa, int ib, double pb) {
+    a.push_back(ia); da.push_back(pa); b.push_back(ib); db.push_back(pb);
+    return (int)a.size() - 1;
+  }
+};
+thread_local Tape* g_tape = nullptr;
+
+struct V {
+  double v; int i;
+  V() : v(0.0), i(-1) {}
+  V(double x) : v(x), i(-1) {}
+  V(double x, int idx) : v(x), i(idx) {}
+};
+
+inline V node(double v, const V& a, double da) {
+  if (a.i < 0) return V(v);
+  return V(v, g_tape->push(a.i, da, -1, 0.0));
+}
+inline V node(double v, const V& a, double da, const V& b, double db) {
+  if (a.i < 0 && b.i < 0) return V(v);
+  return V(v, g_tape->push(a.i, da, b.i, db));
+}
+V leaf(double v, long slot) {
+  int id = g_tape->push(-1, 0.0, -1, 0.0);
+  g_tape->leaves.push_back({id, slot});
+  return V(v, id);
+}
+
+inline V operator+(const V& a, const V& b) { return node(a.v + b.v, a, 1.0, b, 1.0); }
+inline V operator-(const V& a, const V& b) { return node(a.v - b.v, a, 1.0, b, -1.0); }
+inline V operator*(const V& a, const V& b) { return node(a.v * b.v, a, b.v, b, a.v); }
+inline V operator/(const V& a, const V& b) {
+  double q = a.v / b.v;
+  return node(q, a, 1.0 / b.v, b, -q / b.v);
+}
+inline V operator-(const V& a) { return node(-a.v, a, -1.0); }
+inline V vsqrt(const V& a) { double s = std::sqrt(a.v); return node(s, a, 0.5 / s); }
+inline V vabs(const V& a) { return node(std::fabs(a.v), a, a.v >= 0 ? 1.0 : -1.0); }
+
+struct V3 { V x, y, z; };
+inline V3 operator+(const V3& a, const V3& b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline V3 operator-(const V3& a, const V3& b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 operator*(const V3& a, const V& s) { return {a.x * s, a.y * s, a.z * s}; }
+inline V dot(const V3& a, const V3& b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 cross(const V3& a, const V3& b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+inline V3 normalize(const V3& a) { V l = vsqrt(dot(a, a)); return {a.x / l, a.y / l, a.z / l}; }
+
+struct D3 { double x, y, z; };
+inline D3 val(const V3& a) { return {a.x.v, a.y.v, a.z.v}; }
+inline D3 operator+(D3 a, D3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline D3 operator-(D3 a, D3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline D3 operator*(D3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+inline double dot(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline D3 cross(D3 a, D3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+inline D3 normalize(D3 a) { double l = std::sqrt(dot(a, a)); return {a.x / l, a.y / l, a.z / l}; }
+inline V3 cst(D3 a) { return {V(a.x), V(a.y), V(a.z)}; }
+
+// Orthonormal basis from a unit normal (Duff et al., "Building an
+// Orthonormal Basis, Revisited", JCGT 2017).
+void onb(D3 n, D3& b1, D3& b2) {
+  double sign = std::copysign(1.0, n.z);
+  double a = -1.0 / (sign + n.z);
+  double b = n.x * n.y * a;
+  b1 = {1.0 + sign * n.x * n.x * a, sign * b, -sign * n.x};
+  b2 = {b, sign + n.y * n.y * a, -n.y};
+}
+
+void onbv(const V3& n, V3& b1, V3& b2) {
+  double sign = std::copysign(1.0, n.z.v);
+  V a = V(-1.0) / (V(sign) + n.z);
+  V b = n.x * n.y * a;
+  b1 = {V(1.0) + V(sign) * n.x * n.x * a, V(sign) * b, -(V(sign) * n.x)};
+  b2 = {b, V(sign) + n.y * n.y * a, -n.y};
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- C API
+extern "C" {
+
+enum { ORA_ABSORBER = 0, ORA_LAMBERT = 1, ORA_DIELECTRIC = 2 };
+enum { ORA_EMIT_QUAD = 0, ORA_EMIT_POINT = 1 };
+enum { ORA_F_ATTACHED = 1, ORA_F_SPLAT_SELECTED = 2 };
+enum { ORA_MODE_NAIVE = 0, ORA_MODE_RESLRB = 1 };
+
+typedef struct {
+  int32_t n_tris; const double* tri_v; const double* tri_uv; const int32_t* tri_mat;
+  int32_t n_mats; const int32_t* mat_type; const int32_t* mat_tex; const double* mat_ior;
+  int32_t n_tex, tex_res;
+  int32_t em_type; double em_o[3], em_e1[3], em_e2[3];
+  double cam_pos[3], cam_target[3], cam_up[3], cam_fov_deg; int32_t width, height;
+  int32_t hf_G; double hf_x0, hf_z0, hf_dx, hf_base; int32_t hf_mat;
+} ora_scene;
+
+typedef struct {
+  uint64_t seed; int64_t n_paths; int32_t max_depth; int32_t flags; int32_t n_threads;
+  const uint32_t* path_list; int64_t n_list;   // NULL: all paths [0, n_paths)
+} ora_args;
+
+}  // extern "C"
+
+namespace {
+
+const double kTmin = 1e-4, kEps = 1e-4, kInvPi = 0.31830988618379067154;
+const double kLumR = 0.2126, kLumG = 0.7152, kLumB = 0.0722;
+
+struct Scene {
+  const ora_scene* s;
+  int n_static, n_hf, n_all;
+  const double* albedo; const double* Le; const double* heights;
+  bool attached;
+  long slot_Le, slot_h;
+  std::vector<D3> tv;   // [n_all][3] primal vertex positions
+  // camera frame
+  D3 cpos, f, r, u; double tan_half, aspect, K_area;
+
+  int hf_corner(int tri, int k, int& gi, int& gj) const {
+    // heightfield triangle -> grid corner (gi, gj); returns 1 if on heightfield
+    int local = tri - n_static;
+    int cell = local >> 1, half = local & 1, G = s->hf_G;
+    int ci = cell % (G - 1), cj = cell / (G - 1);
+    // half 0: (A, C, B); half 1: (A, D, C) with A=(i,j) B=(i+1,j) C=(i+1,j+1) D=(i,j+1)
+    static const int o0[3][2] = {{0, 0}, {1, 1}, {1, 0}};
+    static const int o1[3][2] = {{0, 0}, {0, 1}, {1, 1}};
+    const int (*o)[2] = half == 0 ? o0 : o1;
+    gi = ci + o[k][0]; gj = cj + o[k][1];
+    return 1;
+  }
+  double hval(int gi, int gj) const { return heights ? heights[gj * s->hf_G + gi] : 0.0; }
+  V hvar(int gi, int gj) const {
+    double v = hval(gi, gj);
+    if (attached) return leaf(v, slot_h + (long)gj * s->hf_G + gi);
+    return V(v);
+  }
+
+  void init(const ora_scene* sc, const double* alb, const double* le, const double* h, bool att) {
+    s = sc; albedo = alb; Le = le; heights = h; attached = att && sc->hf_G > 1 && h;
+    n_static = sc->n_tris;
+    n_hf = sc->hf_G > 1 ? 2 * (sc->hf_G - 1) * (sc->hf_G - 1) : 0;
+    n_all = n_static + n_hf;
+    slot_Le = (long)sc->n_tex * sc->tex_res * sc->tex_res * 3;
+    slot_h = slot_Le + 3;
+    tv.resize((size_t)n_all * 3);
+    for (int t = 0; t < n_static; ++t)
+      for (int k = 0; k < 3; ++k)
+        tv[t * 3 + k] = {sc->tri_v[(t * 3 + k) * 3 + 0], sc->tri_v[(t * 3 + k) * 3 + 1],
+                         sc->tri_v[(t * 3 + k) * 3 + 2]};
+    for (int t = n_static; t < n_all; ++t)
+      for (int k = 0; k < 3; ++k) {
+        int gi, gj; hf_corner(t, k, gi, gj);
+        tv[t * 3 + k] = {sc->hf_x0 + gi * sc->hf_dx, sc->hf_base + hval(gi, gj),
+                         sc->hf_z0 + gj * sc->hf_dx};
+      }
+    cpos = {sc->cam_pos[0], sc->cam_pos[1], sc->cam_pos[2]};
+    D3 tgt = {sc->cam_target[0], sc->cam_target[1], sc->cam_target[2]};
+    D3 up = {sc->cam_up[0], sc->cam_up[1], sc->cam_up[2]};
+    f = normalize(tgt - cpos);
+    r = normalize(cross(f, up));
+    u = cross(r, f);
+    tan_half = std::tan(sc->cam_fov_deg * M_PI / 360.0);
+    aspect = (double)sc->width / (double)sc->height;
+  }
+
+  int mat_of(int tri) const { return tri < n_static ? s->tri_mat[tri] : s->hf_mat; }
+
+  // Closest hit (discrete choice), brute force over every triangle.
+  // Moller-Trumbore with inclusive edges; ties go to the lower index.
+  int closest(D3 o, D3 d, double tmin, double tmax, double* t_out) const {
+    int best = -1; double bt = tmax;
+    for (int t = 0; t < n_all; ++t) {
+      D3 p0 = tv[t * 3], e1 = tv[t * 3 + 1] - p0, e2 = tv[t * 3 + 2] - p0;
+      D3 pv = cross(d, e2);
+      double det = dot(e1, pv);
+      if (std::fabs(det) < 1e-300) continue;
+      double inv = 1.0 / det;
+      D3 tvec = o - p0;
+      double b1 = dot(tvec, pv) * inv;
+      if (b1 < 0.0 || b1 > 1.0) continue;
+      D3 q = cross(tvec, e1);
+      double b2 = dot(d, q) * inv;
+      if (b2 < 0.0 || b1 + b2 > 1.0) continue;
+      double tt = dot(e2, q) * inv;
+      if (tt > tmin && tt < bt) { bt = tt; best = t; }
+    }
+    if (t_out) *t_out = bt;
+    return best;
+  }
+
+  // Differentiable triangle corners.
+  void corners(int tri, V3 P[3]) const {
+    if (tri < n_static) {
+      for (int k = 0; k < 3; ++k) P[k] = cst(tv[tri * 3 + k]);
+      return;
+    }
+    for (int k = 0; k < 3; ++k) {
+      int gi, gj; hf_corner(tri, k, gi, gj);
+      P[k] = {V(s->hf_x0 + gi * s->hf_dx), V(s->hf_base) + hvar(gi, gj), V(s->hf_z0 + gj * s->hf_dx)};
+    }
+  }
+
+  // Central-difference slope of the heightfield at grid vertex (gi, gj),
+  // one-sided on the border.
+  void slope(int gi, int gj, V& sx, V& sz) const {
+    int G = s->hf_G; double dx = s->hf_dx;
+    int a = std::max(gi - 1, 0), b = std::min(gi + 1, G - 1);
+    sx = (hvar(b, gj) - hvar(a, gj)) / V((b - a) * dx);
+    int c = std::max(gj - 1, 0), d = std::min(gj + 1, G - 1);
+    sz = (hvar(gi, d) - hvar(gi, c)) / V((d - c) * dx);
+  }
+};
+
+struct Conn { V C[3]; V ux, uy; int depth; };
+
+struct PathResult {
+  std::vector<Conn> conns;
+  uint32_t sig; int R; double W;
+};
+
+// Trace one light path as an AD expression of the parameters.
+void trace_path(const Scene& S, const ora_args& A, uint32_t path, PathResult& out) {
+  const ora_scene& sc = *S.s;
+  out.conns.clear(); out.sig = 0x811C9DC5u; out.R = 0; out.W = 0.0;
+  const int W = sc.width, H = sc.height;
+  const double Kfilm = (double)W * H / (4.0 * S.aspect * S.tan_half * S.tan_half * (double)A.n_paths);
+
+  // --- emission (vertex 0)
+  Uniform4 u0 = rng4(A.seed, path, 0, 0);
+  V Le[3];
+  for (int c = 0; c < 3; ++c) Le[c] = leaf(S.Le[c], S.slot_Le + c);
+  D3 x0, w0, n_off; bool has_off;
+  V beta[3];
+  if (sc.em_type == ORA_EMIT_QUAD) {
+    D3 o = {sc.em_o[0], sc.em_o[1], sc.em_o[2]};
+    D3 e1 = {sc.em_e1[0], sc.em_e1[1], sc.em_e1[2]}, e2 = {sc.em_e2[0], sc.em_e2[1], sc.em_e2[2]};
+    D3 cr = cross(e1, e2);
+    double area = std::sqrt(dot(cr, cr));
+    D3 ne = cr * (1.0 / area);
+    x0 = o + e1 * u0.u[0] + e2 * u0.u[1];
+    double rr = std::sqrt(u0.u[2]), phi = 2.0 * M_PI * u0.u[3];
+    double lx = rr * std::cos(phi), ly = rr * std::sin(phi), lz = std::sqrt(std::max(0.0, 1.0 - u0.u[2]));
+    D3 t1, t2; onb(ne, t1, t2);
+    w0 = t1 * lx + t2 * ly + ne * lz;
+    n_off = ne; has_off = true;
+    for (int c = 0; c < 3; ++c) beta[c] = Le[c] * V(area * M_PI);
+  } else {
+    x0 = {sc.em_o[0], sc.em_o[1], sc.em_o[2]};
+    double z = 1.0 - 2.0 * u0.u[2];
+    double rr = std::sqrt(std::max(0.0, 1.0 - z * z)), phi = 2.0 * M_PI * u0.u[3];
+    w0 = {rr * std::cos(phi), rr * std::sin(phi), z};
+    n_off = {0, 0, 0}; has_off = false;
+    for (int c = 0; c < 3; ++c) beta[c] = Le[c] * V(4.0 * M_PI);
+  }
+
+  V3 xprev = cst(x0), wcur = cst(w0);
+  D3 offn = n_off; bool off = has_off;
+  double Omega = 0.0, omegaR = 0.0;
+
+  for (int j = 1; j <= A.max_depth; ++j) {
+    // --- closest hit (discrete) from the offset origin
+    D3 xo = val(xprev), wd = val(wcur);
+    if (off) xo = xo + offn * (dot(wd, offn) >= 0 ? kEps : -kEps);
+    double th;
+    int tri = S.closest(xo, wd, kTmin, 1e300, &th);
+    if (tri < 0) { out.sig = fnv1a(out.sig, 0u); break; }
+    out.sig = fnv1a(out.sig, (uint32_t)tri + 1u);
+    int mat = S.mat_of(tri);
+    int mtype = sc.mat_type[mat];
+    if (mtype == ORA_ABSORBER) break;
+
+    // --- differentiable hit point from the true origin
+    V3 P[3]; S.corners(tri, P);
+    V3 e1 = P[1] - P[0], e2 = P[2] - P[0];
+    V3 N = cross(e1, e2);
+    V t = dot(P[0] - xprev, N) / dot(wcur, N);
+    V3 x = xprev + wcur * t;
+    V nn = dot(N, N);
+    V3 dx = x - P[0];
+    V b1 = dot(cross(dx, e2), N) / nn;
+    V b2 = dot(cross(e1, dx), N) / nn;
+    V3 ng = normalize(N);
+    D3 ngd = val(ng), wd_in = val(wcur);
+    double cos_in = dot(wd_in, ngd);
+    Uniform4 uj = rng4(A.seed, path, (uint32_t)j, 0);
+
+    if (mtype == ORA_LAMBERT) {
+      // texel (nearest), from primal chart coordinates
+      int tex = sc.mat_tex[mat], R = sc.tex_res;
+      double uvx, uvy;
+      if (tri < S.n_static) {
+        const double* uv = sc.tri_uv + (size_t)tri * 6;
+        double c0 = 1.0 - b1.v - b2.v;
+        uvx = c0 * uv[0] + b1.v * uv[2] + b2.v * uv[4];
+        uvy = c0 * uv[1] + b1.v * uv[3] + b2.v * uv[5];
+      } else { uvx = uvy = 0.0; }
+      int tx = (int)std::floor(uvx * R), ty = (int)std::floor(uvy * R);
+      tx = std::min(std::max(tx, 0), R - 1); ty = std::min(std::max(ty, 0), R - 1);
+      long texel = ((long)tex * R + ty) * R + tx;
+      out.sig = fnv1a(out.sig, (uint32_t)texel + 1u);
+      V rho[3];
+      for (int c = 0; c < 3; ++c) rho[c] = leaf(S.albedo[texel * 3 + c], texel * 3 + c);
+
+      // --- sensor connection (Eq. 1 term i)
+      uint32_t valid = 0;
+      V3 dv = x - cst(S.cpos);
+      V zc = dot(dv, cst(S.f));
+      if (zc.v > 0.0) {
+        V qx = dot(dv, cst(S.r)) / zc, qy = dot(dv, cst(S.u)) / zc;
+        V ux = V(0.5 * W) * (V(1.0) + qx / V(S.aspect * S.tan_half));
+        V uy = V(0.5 * H) * (V(1.0) - qy / V(S.tan_half));
+        if (ux.v >= 0.0 && ux.v < W && uy.v >= 0.0 && uy.v < H) {
+          D3 dvd = val(dv);
+          double dist = std::sqrt(dot(dvd, dvd));
+          D3 wc = dvd * (-1.0 / dist);
+          double cg = dot(ngd, wc);
+          if (cg * (-cos_in) > 0.0) {
+            D3 so = val(x) + ngd * (cg >= 0 ? kEps : -kEps);
+            D3 sd = S.cpos - so;
+            double sl = std::sqrt(dot(sd, sd));
+            sd = sd * (1.0 / sl);
+            if (S.closest(so, sd, kTmin, sl * (1.0 - 1e-4), nullptr) < 0) {
+              valid = 1;
+              V dist2 = dot(dv, dv);
+              V distv = vsqrt(dist2);
+              V cosc = zc / distv;
+              V cosx = vabs(dot(ng, dv)) / distv;
+              V g = V(kInvPi * Kfilm) * cosx / (cosc * cosc * cosc * dist2);
+              Conn cn;
+              for (int c = 0; c < 3; ++c) cn.C[c] = beta[c] * rho[c] * g;
+              cn.ux = ux; cn.uy = uy; cn.depth = j;
+              // reservoir (Eq. 8): luminance weight, replace w.p. omega/Omega
+              double om = kLumR * cn.C[0].v + kLumG * cn.C[1].v + kLumB * cn.C[2].v;
+              if (om > 0.0) {
+                Omega += om;
+                if (uj.u[3] < om / Omega) { out.R = j; omegaR = om; }
+              }
+              out.conns.push_back(cn);
+            }
+          }
+        }
+      }
+      out.sig = fnv1a(out.sig, valid);
+      if (j == A.max_depth) break;
+
+      // --- cosine-weighted scatter on the arrival side
+      double rr = std::sqrt(uj.u[0]), phi = 2.0 * M_PI * uj.u[1];
+      double lx = rr * std::cos(phi), ly = rr * std::sin(phi), lz = std::sqrt(std::max(0.0, 1.0 - uj.u[0]));
+      // the sampled direction is held fixed in the local frame of the
+      // arrival-side normal, so the frame moves with the surface
+      V3 nav = cos_in < 0 ? ng : ng * V(-1.0);
+      V3 t1, t2; onbv(nav, t1, t2);
+      V3 wo = t1 * V(lx) + t2 * V(ly) + nav * V(lz);
+      for (int c = 0; c < 3; ++c) beta[c] = beta[c] * rho[c];
+      xprev = x; wcur = wo;
+      offn = ngd; off = true;
+    } else {  // dielectric: Fresnel-sampled reflect / refract, weight 1
+      V3 ns = ng;
+      if (tri >= S.n_static) {
+        // interpolated central-difference slope -> shading normal
+        V sx[3], sz[3];
+        for (int k = 0; k < 3; ++k) { int gi, gj; S.hf_corner(tri, k, gi, gj); S.slope(gi, gj, sx[k], sz[k]); }
+        V c0 = V(1.0) - b1 - b2;
+        V Sx = c0 * sx[0] + b1 * sx[1] + b2 * sx[2];
+        V Sz = c0 * sz[0] + b1 * sz[1] + b2 * sz[2];
+        ns = normalize(V3{-Sx, V(1.0), -Sz});
+      }
+      if (j == A.max_depth) break;
+      bool entering = cos_in < 0.0;
+      double ior = sc.mat_ior[mat];
+      double eta = entering ? 1.0 / ior : ior;
+      V3 n = entering ? ns : ns * V(-1.0);
+      V cosi = -dot(wcur, n);
+      if (cosi.v <= 0.0) { out.sig = fnv1a(out.sig, 7u); break; }
+      double sin2t = eta * eta * (1.0 - cosi.v * cosi.v);
+      double F;
+      double cost_d = 0.0;
+      if (sin2t >= 1.0) F = 1.0;
+      else {
+        cost_d = std::sqrt(1.0 - sin2t);
+        double ei = entering ? 1.0 : ior, et = entering ? ior : 1.0;
+        double rs = (ei * cosi.v - et * cost_d) / (ei * cosi.v + et * cost_d);
+        double rp = (et * cosi.v - ei * cost_d) / (et * cosi.v + ei * cost_d);
+        F = 0.5 * (rs * rs + rp * rp);
+      }
+      bool reflect = uj.u[2] < F;
+      out.sig = fnv1a(out.sig, reflect ? 2u : 4u);
+      V3 wo;
+      if (reflect) wo = wcur + n * (V(2.0) * cosi);
+      else {
+        V cost = vsqrt(V(1.0) - V(eta * eta) * (V(1.0) - cosi * cosi));
+        wo = wcur * V(eta) + n * (V(eta) * cosi - cost);
+      }
+      double side_in = -cos_in;  // > 0 when the ray arrived on the +ng side
+      double s_out = dot(val(wo), ngd);
+      if (reflect ? (s_out * side_in <= 0.0) : (s_out * side_in >= 0.0)) {
+        out.sig = fnv1a(out.sig, 8u); break;
+      }
+      xprev = x; wcur = wo;
+      offn = ngd; off = true;
+    }
+  }
+  if (out.R > 0) out.W = Omega / omegaR;
+  out.sig = fnv1a(out.sig, (uint32_t)out.R);
+}
+
+// tent filter taps (radius 1 pixel, taps outside the film dropped)
+struct Tap { int px, py; V w; };
+int taps(const Conn& cn, int W, int H, Tap t[4]) {
+  int px0 = (int)std::floor(cn.ux.v - 0.5), py0 = (int)std::floor(cn.uy.v - 0.5);
+  int n = 0;
+  for (int dy = 0; dy < 2; ++dy)
+    for (int dx = 0; dx < 2; ++dx) {
+      int px = px0 + dx, py = py0 + dy;
+      if (px < 0 || px >= W || py < 0 || py >= H) continue;
+      V wx = V(1.0) - vabs(cn.ux - V(px + 0.5));
+      V wy = V(1.0) - vabs(cn.uy - V(py + 0.5));
+      t[n++] = {px, py, wx * wy};
+    }
+  return n;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ora_version() { return 1; }
+
+// u = (philox(...) >> 8) * 2^-24 for external known-answer checks.
+void ora_philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t* out) {
+  U4 c{{c0, c1, c2, c3}};
+  U4 r = philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  for (int i = 0; i < 4; ++i) out[i] = r.x[i];
+}
+
+// Weighted reservoir of capacity one over a candidate stream (Eq. 8):
+// returns the 1-based selected index (0 if every weight is zero).
+int ora_reservoir(const double* w, const double* u, int k, double* W_out) {
+  double Om = 0.0, wr = 0.0; int R = 0;
+  for (int i = 0; i < k; ++i) {
+    if (!(w[i] > 0.0)) continue;
+    Om += w[i];
+    if (u[i] < w[i] / Om) { R = i + 1; wr = w[i]; }
+  }
+  if (W_out) *W_out = R ? Om / wr : 0.0;
+  return R;
+}
+
+// Forward render.  image: [H][W][3] (overwritten).  Optional outputs:
+// slices [D][H][W][3] (connections of vertex i land in slice i-1),
+// sig/R/Wres per listed path, flux = sum over connections of C (3 doubles).
+int ora_render(const ora_scene* sc, const ora_args* A, const double* albedo, const double* Le,
+               const double* heights, double* image, double* slices, uint32_t* sig, int32_t* Rout,
+               double* Wout, double* flux) {
+  Scene S; S.init(sc, albedo, Le, heights, false);
+  const int W = sc->width, H = sc->height, D = A->max_depth;
+  const long npix = (long)W * H * 3;
+  const int64_t n = A->path_list ? A->n_list : A->n_paths;
+  int nt = A->n_threads > 0 ? A->n_threads : omp_get_max_threads();
+  std::vector<std::vector<double>> img(nt, std::vector<double>(npix, 0.0));
+  std::vector<std::vector<double>> sl(slices ? nt : 0, std::vector<double>(slices ? npix * D : 0, 0.0));
+  std::vector<double> fl((size_t)nt * 3, 0.0);
+  const bool selected = (A->flags & ORA_F_SPLAT_SELECTED) != 0;
+#pragma omp parallel num_threads(nt)
+  {
+    int tid = omp_get_thread_num();
+    Tape tape; g_tape = &tape;
+    PathResult pr;
+#pragma omp for schedule(dynamic, 256)
+    for (int64_t k = 0; k < n; ++k) {
+      uint32_t path = A->path_list ? A->path_list[k] : (uint32_t)k;
+      tape.clear();
+      trace_path(S, *A, path, pr);
+      if (sig) sig[k] = pr.sig;
+      if (Rout) Rout[k] = pr.R;
+      if (Wout) Wout[k] = pr.W;
+      for (size_t ci = 0; ci < pr.conns.size(); ++ci) {
+        const Conn& cn = pr.conns[ci];
+        double scale = 1.0;
+        if (selected) { if (cn.depth != pr.R) continue; scale = pr.W; }
+        for (int c = 0; c < 3; ++c) fl[tid * 3 + c] += scale * cn.C[c].v;
+        Tap t[4]; int nt4 = taps(cn, W, H, t);
+        for (int q = 0; q < nt4; ++q) {
+          long p = ((long)t[q].py * W + t[q].px) * 3;
+          for (int c = 0; c < 3; ++c) {
+            double v = scale * t[q].w.v * cn.C[c].v;
+            img[tid][p + c] += v;
+            if (slices) sl[tid][(long)(cn.depth - 1) * npix + p + c] += v;
+          }
+        }
+      }
+    }
+    g_tape = nullptr;
+  }
+  for (long p = 0; p < npix; ++p) { double s = 0; for (int t = 0; t < nt; ++t) s += img[t][p]; image[p] = s; }
+  if (slices)
+    for (long p = 0; p < npix * D; ++p) { double s = 0; for (int t = 0; t < nt; ++t) s += sl[t][p]; slices[p] = s; }
+  if (flux) for (int c = 0; c < 3; ++c) { double s = 0; for (int t = 0; t < nt; ++t) s += fl[t * 3 + c]; flux[c] = s; }
+  return 0;
+}
+
+// Gradient of <dI, I(theta)> (= dLoss/dtheta when dI = dLoss/dI) by taped
+// reverse-mode AD of each path.  mode NAIVE: every connection;
+// mode RESLRB: only the reservoir-selected connection, scaled by the fixed
+// weight Omega_k/omega_R (Eq. 11).  Gradients are accumulated into g_*
+// (g_heights only when ORA_F_ATTACHED and the scene has a heightfield).
+int ora_gradient(const ora_scene* sc, const ora_args* A, int mode, const double* albedo,
+                 const double* Le, const double* heights, const double* dI, double* g_albedo,
+                 double* g_Le, double* g_heights) {
+  Scene S; S.init(sc, albedo, Le, heights, (A->flags & ORA_F_ATTACHED) != 0);
+  const int W = sc->width, H = sc->height;
+  const int64_t n = A->path_list ? A->n_list : A->n_paths;
+  const long n_alb = S.slot_Le, n_h = sc->hf_G > 1 ? (long)sc->hf_G * sc->hf_G : 0;
+  const long nslot = n_alb + 3 + n_h;
+  int nt = A->n_threads > 0 ? A->n_threads : omp_get_max_threads();
+  std::vector<std::vector<double>> gr(nt, std::vector<double>(nslot, 0.0));
+#pragma omp parallel num_threads(nt)
+  {
+    int tid = omp_get_thread_num();
+    Tape tape; g_tape = &tape;
+    PathResult pr;
+    std::vector<double> adj;
+#pragma omp for schedule(dynamic, 256)
+    for (int64_t k = 0; k < n; ++k) {
+      uint32_t path = A->path_list ? A->path_list[k] : (uint32_t)k;
+      tape.clear();
+      trace_path(S, *A, path, pr);
+      // scalar objective lambda = sum_i sum_taps F(u_i,p) <dI[p], C_i>
+      V lam(0.0);
+      for (size_t ci = 0; ci < pr.conns.size(); ++ci) {
+        const Conn& cn = pr.conns[ci];
+        if (mode == ORA_MODE_RESLRB && cn.depth != pr.R) continue;
+        Tap t[4]; int nt4 = taps(cn, W, H, t);
+        V term(0.0);
+        for (int q = 0; q < nt4; ++q) {
+          long p = ((long)t[q].py * W + t[q].px) * 3;
+          V inner = cn.C[0] * V(dI[p]) + cn.C[1] * V(dI[p + 1]) + cn.C[2] * V(dI[p + 2]);
+          term = term + t[q].w * inner;
+        }
+        if (mode == ORA_MODE_RESLRB) term = term * V(pr.W);
+        lam = lam + term;
+      }
+      if (lam.i < 0) continue;
+      adj.assign(tape.a.size(), 0.0);
+      adj[lam.i] = 1.0;
+      for (int q = lam.i; q >= 0; --q) {
+        double g = adj[q];
+        if (g == 0.0) continue;
+        if (tape.a[q] >= 0) adj[tape.a[q]] += g * tape.da[q];
+        if (tape.b[q] >= 0) adj[tape.b[q]] += g * tape.db[q];
+      }
+      for (auto& lf : tape.leaves) gr[tid][lf.second] += adj[lf.first];
+    }
+    g_tape = nullptr;
+  }
+  for (long q = 0; q < nslot; ++q) {
+    double s = 0; for (int t = 0; t < nt; ++t) s += gr[t][q];
+    if (q < n_alb) { if (g_albedo) g_albedo[q] += s; }
+    else if (q < n_alb + 3) { if (g_Le) g_Le[q - n_alb] += s; }
+    else if (g_heights) g_heights[q - n_alb - 3] += s;
+  }
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,218 @@
+"""ctypes front end of the FP64 CPU oracle (test infrastructure only).
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  The product path never does.
+
+Functions mirror the oracle's C entry points:
+  render(scene, ...)    light-tracing image (Sec. 3.1, Eq. 1-2, Eq. 20)
+  gradient(scene, ...)  d<dI, I(theta)>/dtheta by taped reverse-mode AD
+                        (naive) or of the ResLRB estimator (Eq. 11)
+  loss_and_adjoint(I, T)  mean-squared error and dLoss/dI
+  reservoir(w, u)       capacity-one weighted reservoir (Eq. 8)
+  philox(seed, ctr)     Philox-4x32-10 block (Salmon et al. 2011)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lt_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+ATTACHED = 1
+SPLAT_SELECTED = 2
+MODE_NAIVE = 0
+MODE_RESLRB = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (FP64, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Scene(C.Structure):
+    _fields_ = [
+        ("n_tris", C.c_int32), ("tri_v", C.POINTER(C.c_double)), ("tri_uv", C.POINTER(C.c_double)),
+        ("tri_mat", C.POINTER(C.c_int32)),
+        ("n_mats", C.c_int32), ("mat_type", C.POINTER(C.c_int32)), ("mat_tex", C.POINTER(C.c_int32)),
+        ("mat_ior", C.POINTER(C.c_double)),
+        ("n_tex", C.c_int32), ("tex_res", C.c_int32),
+        ("em_type", C.c_int32), ("em_o", C.c_double * 3), ("em_e1", C.c_double * 3),
+        ("em_e2", C.c_double * 3),
+        ("cam_pos", C.c_double * 3), ("cam_target", C.c_double * 3), ("cam_up", C.c_double * 3),
+        ("cam_fov_deg", C.c_double), ("width", C.c_int32), ("height", C.c_int32),
+        ("hf_G", C.c_int32), ("hf_x0", C.c_double), ("hf_z0", C.c_double), ("hf_dx", C.c_double),
+        ("hf_base", C.c_double), ("hf_mat", C.c_int32),
+    ]
+
+
+class _Args(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("n_paths", C.c_int64), ("max_depth", C.c_int32),
+                ("flags", C.c_int32), ("n_threads", C.c_int32),
+                ("path_list", C.POINTER(C.c_uint32)), ("n_list", C.c_int64)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = C.CDLL(_LIB)
+        dp, ip, up = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_uint32)
+        _lib.ora_render.argtypes = [C.POINTER(_Scene), C.POINTER(_Args), dp, dp, dp, dp, dp, up, ip, dp, dp]
+        _lib.ora_gradient.argtypes = [C.POINTER(_Scene), C.POINTER(_Args), C.c_int, dp, dp, dp, dp, dp, dp, dp]
+        _lib.ora_reservoir.argtypes = [dp, dp, C.c_int, dp]
+        _lib.ora_reservoir.restype = C.c_int
+        _lib.ora_philox.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, up]
+    return _lib
+
+
+def _p(a, t=C.c_double):
+    return None if a is None else a.ctypes.data_as(C.POINTER(t))
+
+
+class _Keep:
+    """Holds the numpy arrays a ctypes struct points into."""
+
+    def __init__(self):
+        self.refs = []
+
+    def f64(self, a):
+        a = np.ascontiguousarray(a, np.float64)
+        self.refs.append(a)
+        return a
+
+    def i32(self, a):
+        a = np.ascontiguousarray(a, np.int32)
+        self.refs.append(a)
+        return a
+
+
+def _scene(sc, keep):
+    s = _Scene()
+    tv, tuv, tm = keep.f64(sc["tri_v"]), keep.f64(sc["tri_uv"]), keep.i32(sc["tri_mat"])
+    s.n_tris = tv.shape[0]
+    s.tri_v, s.tri_uv, s.tri_mat = _p(tv), _p(tuv), _p(tm, C.c_int32)
+    mt, mx, mi = keep.i32(sc["mat_type"]), keep.i32(sc["mat_tex"]), keep.f64(sc["mat_ior"])
+    s.n_mats = mt.shape[0]
+    s.mat_type, s.mat_tex, s.mat_ior = _p(mt, C.c_int32), _p(mx, C.c_int32), _p(mi)
+    s.n_tex, s.tex_res = int(sc["n_tex"]), int(sc["tex_res"])
+    em = sc["emitter"]
+    s.em_type = int(em["type"])
+    for k in range(3):
+        s.em_o[k], s.em_e1[k], s.em_e2[k] = em["o"][k], em["e1"][k], em["e2"][k]
+    cam = sc["camera"]
+    for k in range(3):
+        s.cam_pos[k], s.cam_target[k], s.cam_up[k] = cam["pos"][k], cam["target"][k], cam["up"][k]
+    s.cam_fov_deg = float(cam["fov_deg"])
+    s.width, s.height = int(cam["width"]), int(cam["height"])
+    hf = sc.get("hf")
+    if hf is not None:
+        s.hf_G, s.hf_x0, s.hf_z0 = int(hf["G"]), float(hf["x0"]), float(hf["z0"])
+        s.hf_dx, s.hf_base, s.hf_mat = float(hf["dx"]), float(hf["base"]), int(hf["mat"])
+    else:
+        s.hf_G = 0
+    return s
+
+
+def _args(seed, n_paths, depth, flags, threads, path_list, keep):
+    a = _Args()
+    a.seed, a.n_paths, a.max_depth, a.flags, a.n_threads = int(seed), int(n_paths), int(depth), int(flags), int(threads)
+    if path_list is not None:
+        pl = np.ascontiguousarray(path_list, np.uint32)
+        keep.refs.append(pl)
+        a.path_list, a.n_list = _p(pl, C.c_uint32), pl.shape[0]
+    else:
+        a.path_list, a.n_list = None, 0
+    return a
+
+
+def _params(sc, albedo, Le, heights, keep):
+    albedo = keep.f64(sc["albedo"] if albedo is None else albedo)
+    Le = keep.f64(sc["Le"] if Le is None else Le)
+    if heights is None:
+        heights = sc.get("heights")
+    heights = None if heights is None else keep.f64(heights)
+    return albedo, Le, heights
+
+
+def render(sc, seed, n_paths, depth, albedo=None, Le=None, heights=None, flags=0,
+           path_list=None, slices=False, per_path=False, threads=0):
+    """FP64 light-tracing image [H,W,3] (plus optional per-depth slices,
+    per-path signature / reservoir index R / weight W, and total flux)."""
+    lib = _load()
+    keep = _Keep()
+    s = _scene(sc, keep)
+    a = _args(seed, n_paths, depth, flags, threads, path_list, keep)
+    alb, le, h = _params(sc, albedo, Le, heights, keep)
+    H, W = int(sc["camera"]["height"]), int(sc["camera"]["width"])
+    img = np.zeros((H, W, 3))
+    sl = np.zeros((depth, H, W, 3)) if slices else None
+    n = len(path_list) if path_list is not None else int(n_paths)
+    sig = np.zeros(n, np.uint32) if per_path else None
+    R = np.zeros(n, np.int32) if per_path else None
+    Wr = np.zeros(n) if per_path else None
+    flux = np.zeros(3)
+    lib.ora_render(C.byref(s), C.byref(a), _p(alb), _p(le), _p(h), _p(img), _p(sl),
+                   _p(sig, C.c_uint32), _p(R, C.c_int32), _p(Wr), _p(flux))
+    out = dict(image=img, flux=flux)
+    if slices:
+        out["slices"] = sl
+    if per_path:
+        out.update(sig=sig, R=R, W=Wr)
+    return out
+
+
+def gradient(sc, seed, n_paths, depth, dI, mode=MODE_NAIVE, albedo=None, Le=None, heights=None,
+             flags=0, path_list=None, threads=0):
+    """Gradient of <dI, I(theta)> w.r.t. albedo texels, emitter radiance and
+    (attached) heights, by taped reverse-mode AD of each light path."""
+    lib = _load()
+    keep = _Keep()
+    s = _scene(sc, keep)
+    a = _args(seed, n_paths, depth, flags, threads, path_list, keep)
+    alb, le, h = _params(sc, albedo, Le, heights, keep)
+    dI = keep.f64(dI)
+    g_alb = np.zeros_like(alb)
+    g_le = np.zeros(3)
+    g_h = np.zeros_like(h) if h is not None else None
+    lib.ora_gradient(C.byref(s), C.byref(a), int(mode), _p(alb), _p(le), _p(h), _p(dI),
+                     _p(g_alb), _p(g_le), _p(g_h))
+    return dict(albedo=g_alb, Le=g_le, heights=g_h)
+
+
+def loss_and_adjoint(image, target):
+    """Mean squared error over all 3*W*H entries and its image adjoint."""
+    image = np.asarray(image, np.float64)
+    target = np.asarray(target, np.float64)
+    n = image.size
+    diff = image - target
+    return float(np.sum(diff * diff) / n), 2.0 * diff / n
+
+
+def reservoir(w, u):
+    lib = _load()
+    w = np.ascontiguousarray(w, np.float64)
+    u = np.ascontiguousarray(u, np.float64)
+    Wr = C.c_double(0.0)
+    R = lib.ora_reservoir(_p(w), _p(u), len(w), C.byref(Wr))
+    return R, Wr.value
+
+
+def philox(seed, ctr):
+    lib = _load()
+    out = np.zeros(4, np.uint32)
+    lib.ora_philox(int(seed), *(int(c) for c in ctr), _p(out, C.c_uint32))
+    return out

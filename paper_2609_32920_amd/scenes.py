@@ -1,0 +1,234 @@
+"""Seeded synthetic scene generators.
+
+This module only *describes* inputs: triangle lists, material tables, texture
+and height parameters, emitter and camera placement, and loss targets drawn
+from fixed seeds.  It holds none of the light-transport arithmetic; both the
+HIP library and the CPU oracle consume the arrays it returns and implement the
+method on their own.
+
+Scene dictionary layout (all arrays numpy, float64 unless noted):
+  tri_v    [T,3,3]  world-space triangle vertices (static geometry)
+  tri_uv   [T,3,2]  per-vertex chart/texture coordinates
+  tri_mat  [T]      int32 material index
+  mat_type [M]      int32: MAT_ABSORBER, MAT_LAMBERT, MAT_DIELECTRIC
+  mat_tex  [M]      int32 texture index of a Lambertian material (-1 otherwise)
+  mat_ior  [M]      refractive index of a dielectric material
+  n_tex, tex_res    albedo textures are [n_tex, tex_res, tex_res, 3]
+  emitter  dict(type=EMIT_QUAD|EMIT_POINT, o, e1, e2)  (point: o = position)
+  camera   dict(pos, target, up, fov_deg, width, height)
+  hf       dict(G, x0, z0, dx, base, mat) or None: heightfield top surface
+           with vertex (i, j) at (x0 + i*dx, base + h[j*G+i], z0 + j*dx)
+  albedo, Le, heights   initial parameters
+  albedo_target, heights_target   parameters that generate the loss target
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+MAT_ABSORBER = 0
+MAT_LAMBERT = 1
+MAT_DIELECTRIC = 2
+
+EMIT_QUAD = 0
+EMIT_POINT = 1
+
+SCENE_SEED = 2609
+TARGET_SEED = 0x7A6
+
+
+def _quad(o, e1, e2):
+    """Two triangles of the parallelogram (o, o+e1, o+e1+e2, o+e2).
+
+    The winding makes normalize(e1 x e2) the quad's front normal; chart
+    coordinates run (0,0) at o to (1,1) at o+e1+e2.
+    """
+    o, e1, e2 = (np.asarray(a, np.float64) for a in (o, e1, e2))
+    v = np.array([[o, o + e1, o + e1 + e2], [o, o + e1 + e2, o + e2]])
+    uv = np.array([[[0, 0], [1, 0], [1, 1]], [[0, 0], [1, 1], [0, 1]]], np.float64)
+    return v, uv
+
+
+class _Builder:
+    def __init__(self):
+        self.v, self.uv, self.mat = [], [], []
+
+    def quad(self, o, e1, e2, mat):
+        v, uv = _quad(o, e1, e2)
+        self.v.append(v)
+        self.uv.append(uv)
+        self.mat += [mat, mat]
+
+    def arrays(self):
+        return (np.concatenate(self.v).astype(np.float64),
+                np.concatenate(self.uv).astype(np.float64),
+                np.asarray(self.mat, np.int32))
+
+
+def box_scene(width=64, height=64, tex_res=16, seed=SCENE_SEED,
+              target_seed=TARGET_SEED, Le=10.0):
+    """Diffuse unit box: 10 textured inward quads + one ceiling emitter.
+
+    [0,1]^3 with the z=0 face open towards the camera.  Floor, ceiling and
+    back wall are split at x=0.5, the side walls at z=0.5, giving 10 quads
+    (20 triangles), each with its own tex_res^2 RGB albedo texture drawn
+    U(0.2, 0.8).  A 0.25 x 0.25 one-sided emitter hangs 1e-3 below the
+    ceiling, facing -y, and is a black absorber for paths that hit it.
+    Pinhole camera at (0.5, 0.5, -1.4) looking +z, 40 degree vertical FOV.
+    The loss target is rendered from albedo + N(0, 0.05), clipped to
+    [0.01, 0.99].
+    """
+    b = _Builder()
+    mats_type, mats_tex, mats_ior = [], [], []
+    quads = [
+        # floor (normal +y), split at x = 0.5
+        ((0, 0, 0), (0, 0, 1), (0.5, 0, 0)),
+        ((0.5, 0, 0), (0, 0, 1), (0.5, 0, 0)),
+        # ceiling (normal -y)
+        ((0, 1, 0), (0.5, 0, 0), (0, 0, 1)),
+        ((0.5, 1, 0), (0.5, 0, 0), (0, 0, 1)),
+        # back wall z = 1 (normal -z)
+        ((0, 0, 1), (0, 1, 0), (0.5, 0, 0)),
+        ((0.5, 0, 1), (0, 1, 0), (0.5, 0, 0)),
+        # left wall x = 0 (normal +x), split at z = 0.5
+        ((0, 0, 0), (0, 1, 0), (0, 0, 0.5)),
+        ((0, 0, 0.5), (0, 1, 0), (0, 0, 0.5)),
+        # right wall x = 1 (normal -x)
+        ((1, 0, 0), (0, 0, 0.5), (0, 1, 0)),
+        ((1, 0, 0.5), (0, 0, 0.5), (0, 1, 0)),
+    ]
+    for k, (o, e1, e2) in enumerate(quads):
+        mats_type.append(MAT_LAMBERT)
+        mats_tex.append(k)
+        mats_ior.append(1.0)
+        b.quad(o, e1, e2, k)
+    em_o, em_e1, em_e2 = (0.375, 1 - 1e-3, 0.375), (0.25, 0, 0), (0, 0, 0.25)
+    mats_type.append(MAT_ABSORBER)
+    mats_tex.append(-1)
+    mats_ior.append(1.0)
+    b.quad(em_o, em_e1, em_e2, len(quads))
+    tri_v, tri_uv, tri_mat = b.arrays()
+
+    rng = np.random.default_rng(seed)
+    albedo = rng.uniform(0.2, 0.8, size=(10, tex_res, tex_res, 3))
+    trng = np.random.default_rng(target_seed)
+    albedo_t = np.clip(albedo + trng.normal(0.0, 0.05, size=albedo.shape), 0.01, 0.99)
+    return dict(
+        name=f"box{width}x{height}",
+        tri_v=tri_v, tri_uv=tri_uv, tri_mat=tri_mat,
+        mat_type=np.asarray(mats_type, np.int32),
+        mat_tex=np.asarray(mats_tex, np.int32),
+        mat_ior=np.asarray(mats_ior, np.float64),
+        n_tex=10, tex_res=tex_res,
+        emitter=dict(type=EMIT_QUAD, o=np.array(em_o, float), e1=np.array(em_e1, float),
+                     e2=np.array(em_e2, float)),
+        camera=dict(pos=np.array([0.5, 0.5, -1.4]), target=np.array([0.5, 0.5, 0.5]),
+                    up=np.array([0.0, 1.0, 0.0]), fov_deg=40.0, width=width, height=height),
+        hf=None,
+        albedo=albedo, Le=np.full(3, float(Le)), heights=None,
+        albedo_target=albedo_t, heights_target=None,
+    )
+
+
+def caustic_scene(G=128, width=512, height=512, seed=SCENE_SEED, target_seed=TARGET_SEED,
+                  Le=1000.0, ior=1.5, h_sigma=0.002):
+    """Glass heightfield slab over a diffuse receiver (attached workload).
+
+    Receiver: y = 0, x,z in [-1, 1], grey albedo 0.8 (one 1x1 texture).
+    Slab: dielectric (IOR 1.5) closed solid over x,z in [-0.5, 0.5]; flat
+    bottom at y = 0.5 (outward normal -y), four vertical walls up to
+    y = 0.6, and a G x G vertex heightfield top at y = 0.6 + h whose boundary
+    ring stays at h = 0.  Heights start N(0, h_sigma) inside the ring.
+    Emitter: 0.05 x 0.05 quad at y = 1 facing down.  Camera at
+    (0, 0.45, -1.6) looking at (0, 0, 0.1), 50 degree FOV, kept below the slab
+    so sensor connections never cross glass.  The target heights are a seeded
+    product of sines that vanishes on the boundary ring.
+    """
+    b = _Builder()
+    # materials: 0 receiver (Lambert, tex 0), 1 glass, 2 absorber (emitter)
+    mat_type = np.array([MAT_LAMBERT, MAT_DIELECTRIC, MAT_ABSORBER], np.int32)
+    mat_tex = np.array([0, -1, -1], np.int32)
+    mat_ior = np.array([1.0, ior, 1.0])
+    b.quad((-1, 0, -1), (0, 0, 2), (2, 0, 0), 0)            # receiver, normal +y
+    b.quad((-0.5, 0.5, -0.5), (1, 0, 0), (0, 0, 1), 1)      # slab bottom, normal -y
+    b.quad((-0.5, 0.5, -0.5), (0, 0.1, 0), (1, 0, 0), 1)    # wall z=-0.5, normal -z
+    b.quad((-0.5, 0.5, 0.5), (1, 0, 0), (0, 0.1, 0), 1)     # wall z=+0.5, normal +z
+    b.quad((-0.5, 0.5, -0.5), (0, 0, 1), (0, 0.1, 0), 1)    # wall x=-0.5, normal -x
+    b.quad((0.5, 0.5, -0.5), (0, 0.1, 0), (0, 0, 1), 1)     # wall x=+0.5, normal +x
+    em_o, em_e1, em_e2 = (-0.025, 1.0, -0.025), (0.05, 0, 0), (0, 0, 0.05)
+    b.quad(em_o, em_e1, em_e2, 2)
+    tri_v, tri_uv, tri_mat = b.arrays()
+
+    rng = np.random.default_rng(seed)
+    h = rng.normal(0.0, h_sigma, size=(G, G))
+    h[0, :] = h[-1, :] = h[:, 0] = h[:, -1] = 0.0
+    trng = np.random.default_rng(target_seed)
+    amp = trng.uniform(0.005, 0.015)
+    kx, kz = trng.integers(1, 4, size=2)
+    xs = np.linspace(-0.5, 0.5, G)
+    X, Z = np.meshgrid(xs, xs, indexing="xy")   # X[j, i] = x_i, Z[j, i] = z_j
+    ht = amp * np.sin(math.pi * kx * (X + 0.5)) * np.sin(math.pi * kz * (Z + 0.5))
+    ht[0, :] = ht[-1, :] = ht[:, 0] = ht[:, -1] = 0.0
+    return dict(
+        name=f"caustic{G}_{width}x{height}",
+        tri_v=tri_v, tri_uv=tri_uv, tri_mat=tri_mat,
+        mat_type=mat_type, mat_tex=mat_tex, mat_ior=mat_ior,
+        n_tex=1, tex_res=1,
+        emitter=dict(type=EMIT_QUAD, o=np.array(em_o, float), e1=np.array(em_e1, float),
+                     e2=np.array(em_e2, float)),
+        camera=dict(pos=np.array([0.0, 0.45, -1.6]), target=np.array([0.0, 0.0, 0.1]),
+                    up=np.array([0.0, 1.0, 0.0]), fov_deg=50.0, width=width, height=height),
+        hf=dict(G=G, x0=-0.5, z0=-0.5, dx=1.0 / (G - 1), base=0.6, mat=1),
+        albedo=np.full((1, 1, 1, 3), 0.8), Le=np.full(3, float(Le)),
+        heights=h.reshape(-1).copy(),
+        albedo_target=None, heights_target=ht.reshape(-1).copy(),
+    )
+
+
+def plane_point_light_scene(width=32, height=32, rho=0.6, I0=5.0, light_h=0.8,
+                            cam_h=2.0, fov_deg=60.0):
+    """Point light over a large Lambertian plane seen by a pinhole camera.
+
+    Plane y = 0 spanning x,z in [-4, 4] with one constant albedo rho (a 1x1
+    texture); isotropic point light of intensity I0 at (0.3, light_h, -0.2);
+    camera at (0, cam_h, 0) looking straight down with up = +z.  With one
+    scattering vertex the expected image has a closed form (a pixel-filtered
+    integral of rho/pi * I0 cos(theta_l) / r^2).
+    """
+    b = _Builder()
+    b.quad((-4, 0, -4), (0, 0, 8), (8, 0, 0), 0)   # normal +y
+    tri_v, tri_uv, tri_mat = b.arrays()
+    return dict(
+        name="plane_point",
+        tri_v=tri_v, tri_uv=tri_uv, tri_mat=tri_mat,
+        mat_type=np.array([MAT_LAMBERT], np.int32), mat_tex=np.array([0], np.int32),
+        mat_ior=np.array([1.0]),
+        n_tex=1, tex_res=1,
+        emitter=dict(type=EMIT_POINT, o=np.array([0.3, light_h, -0.2]),
+                     e1=np.zeros(3), e2=np.zeros(3)),
+        camera=dict(pos=np.array([0.0, cam_h, 0.0]), target=np.array([0.0, 0.0, 0.0]),
+                    up=np.array([0.0, 0.0, 1.0]), fov_deg=fov_deg, width=width, height=height),
+        hf=None,
+        albedo=np.full((1, 1, 1, 3), rho), Le=np.full(3, float(I0)), heights=None,
+        albedo_target=None, heights_target=None,
+    )
+
+
+def batched_instances(n=48, seed=7):
+    """Size table of a batch of uneven inverse-rendering instances.
+
+    Half box, half caustic; heightfield side G log-uniform in [32, 256];
+    film side log-uniform in [128, 1024] rounded to a multiple of 16; path
+    count log-uniform in [1M, 32M]; depth uniform in [4, 12].
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        kind = "box" if rng.uniform() < 0.5 else "caustic"
+        G = int(round(math.exp(rng.uniform(math.log(32), math.log(256)))))
+        film = int(round(math.exp(rng.uniform(math.log(128), math.log(1024))) / 16.0)) * 16
+        paths = int(round(math.exp(rng.uniform(math.log(1 << 20), math.log(32 << 20)))))
+        depth = int(rng.integers(4, 13))
+        out.append(dict(kind=kind, G=G, film=film, n_paths=paths, depth=depth))
+    return out
