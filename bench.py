@@ -1,0 +1,205 @@
+"""Benchmark: differentiated light paths per second on one MI355X.
+
+One step = light-tracing forward (lt_trace) + L2 loss and image adjoint
+(lt_loss_l2) + LRB-3-pass backward (lt_backward_lrb3) over 4,194,304 light
+paths in the 256x256 textured box at max depth 32, inputs resident in HBM.
+Prints one JSON line with the roofline of the dominant kernel (the fused
+LRB-3 replay) and the FP64 CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per event (a 64-B two-child node, a 48-B triangle, a
+# tent splat = 4 taps x RGB float read-modify-write, a tent gather = 4 taps
+# x RGB float, one scattered gradient value = float read-modify-write)
+B_NODE, B_TRI, B_SPLAT, B_GATHER, B_GRAD, B_TAPE = 64, 48, 96, 48, 8, 32
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--paths", type=int, default=1 << 22)
+    ap.add_argument("--depth", type=int, default=32)
+    ap.add_argument("--film", type=int, default=256)
+    ap.add_argument("--no-sweep", action="store_true", help="skip the per-method / per-depth sweep")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-paths", type=int, default=1 << 15)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by "
+              "path index across GPUs but multi-GPU runs are not part of this build", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2609_32920_amd import lt, scenes
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    sc = scenes.box_scene(width=args.film, height=args.film)
+    N, D = args.paths, args.depth
+    ctx = lt.Context(0).scene_upload(sc)
+    albedo = torch.as_tensor(sc["albedo"], dtype=torch.float32, device=dev).contiguous()
+    Le = torch.as_tensor(sc["Le"], dtype=torch.float32, device=dev)
+    alb_t = torch.as_tensor(sc["albedo_target"], dtype=torch.float32, device=dev).contiguous()
+    H = W = args.film
+    img = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+    target = torch.empty_like(img)
+    dI = torch.empty_like(img)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    g_alb = torch.zeros_like(albedo)
+    g_le = torch.zeros_like(Le)
+    ctx.trace(ctx.args(0x7A6, N, D), ctx.params(alb_t, Le), target)
+    torch.cuda.synchronize()
+
+    p = ctx.params(albedo, Le)
+    stream = torch.cuda.current_stream(dev)
+
+    def step(seed, ev=None):
+        a = ctx.args(seed, N, D)
+        if ev: ev[0].record(stream)
+        ctx.trace(a, p, img)
+        if ev: ev[1].record(stream)
+        ctx.loss_l2(img, target, dI, loss)
+        if ev: ev[2].record(stream)
+        ctx.backward_lrb3(a, p, dI, g_alb, g_le)
+        if ev: ev[3].record(stream)
+
+    for k in range(args.warmup):
+        step(1000 + k)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(2000 + k, evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fwd = [e[0].elapsed_time(e[1]) for e in evs]
+    lss = [e[1].elapsed_time(e[2]) for e in evs]
+    bwd = [e[2].elapsed_time(e[3]) for e in evs]
+    step_ms = [e[0].elapsed_time(e[3]) for e in evs]
+    ms_per_step = wall * 1e3 / args.steps
+    value = N / (ms_per_step * 1e-3)
+    print(f"# fwd {np.median(fwd):.3f} ms  loss {np.median(lss):.3f} ms  bwd(lrb3) {np.median(bwd):.3f} ms  "
+          f"step(events) {np.median(step_ms):.3f} ms  step(wall) {ms_per_step:.3f} ms", file=sys.stderr, flush=True)
+
+    # ---- algorithmic byte model from the counters build, on a path sample
+    counts = {}
+    sample = min(N, 1 << 18)
+    try:
+        cctx = lt.Context(0, counters=True).scene_upload(sc)
+        cctx.read_counters(reset=True)
+        a = cctx.args(2000, sample, D)
+        cctx.trace(a, p, img)
+        counts["trace"] = cctx.read_counters(reset=True)
+        cctx.backward_lrb3(a, p, dI, torch.zeros_like(albedo), torch.zeros_like(Le))
+        counts["lrb3"] = cctx.read_counters(reset=True)
+        del cctx
+    except Exception as e:  # the diagnostic build is optional
+        print(f"# counters unavailable: {e}", file=sys.stderr)
+
+    def bytes_per_path(c, tape_bytes=0):
+        b = (c["nodes"] * B_NODE + c["tris"] * B_TRI + c["splats"] * B_SPLAT + c["gathers"] * B_GATHER
+             + c["grad_values"] * B_GRAD + (c["tape_written"] + c["tape_read"]) * B_TAPE)
+        return b / sample
+
+    roofline = None
+    if "lrb3" in counts:
+        bpp = bytes_per_path(counts["lrb3"])
+        t_launch = float(np.mean(bwd)) * 1e-3
+        achieved = bpp * N / t_launch / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": "k_lrb3_bwd", "bytes_per_path": round(bpp, 1),
+                    "launch_ms": round(t_launch * 1e3, 4),
+                    "events_per_path": {k: round(v / sample, 3) for k, v in counts["lrb3"].items()}}
+        print(f"# lrb3 algorithmic bytes/path {bpp:.0f}  achieved {achieved:.0f} GB/s", file=sys.stderr)
+
+    # ---- per-method / per-depth sweep: differentiated paths/s, bytes/path
+    sweep = {}
+    if not args.no_sweep:
+        for d in (8, 16, 32):
+            for mode in ("naive", "reslrb", "lrb3"):
+                rec = lt.RECORD_TAPE if mode == "naive" else lt.RECORD_RESERVOIR if mode == "reslrb" else 0
+                a = ctx.args(3000, N, d, rec)
+                nb = ctx.side_state_bytes(a)
+                side = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev) if nb else None
+                ts = []
+                for k in range(4):
+                    a = ctx.args(3000 + k, N, d, rec)
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    ctx.trace(a, p, img, side)
+                    ctx.loss_l2(img, target, dI, loss)
+                    if mode == "naive":
+                        ctx.backward_naive(a, p, dI, side, g_alb, g_le)
+                    elif mode == "reslrb":
+                        ctx.backward_reslrb(a, p, dI, side, g_alb, g_le)
+                    else:
+                        ctx.backward_lrb3(a, p, dI, g_alb, g_le)
+                    e1.record(stream)
+                    e1.synchronize()
+                    if k:
+                        ts.append(e0.elapsed_time(e1))
+                del side
+                ms = float(np.median(ts))
+                sweep[f"{mode}_d{d}"] = {"ms": round(ms, 3), "paths_per_s": round(N / (ms * 1e-3)),
+                                         "side_bytes_per_path": round(nb / N, 2),
+                                         "workspace_bytes": ctx.workspace_bytes(a)}
+        torch.cuda.synchronize()
+
+    # ---- CPU baseline: the FP64 oracle, forward + naive backward, on a sample
+    cpu = None
+    if not args.no_cpu:
+        from oracle import oracle as O
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+        ids = np.arange(args.cpu_paths, dtype=np.uint32)
+        dIh = dI.cpu().numpy().astype(np.float64)
+        t0 = time.perf_counter()
+        O.render(sc, 2000, N, D, path_list=ids, threads=threads)
+        O.gradient(sc, 2000, N, D, dIh, path_list=ids, threads=threads)
+        tc = time.perf_counter() - t0
+        cpu = {"value": round(args.cpu_paths / tc, 1), "unit": "paths/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {args.cpu_paths} of the {N} paths (same scene, seed, depth {D}); "
+                         f"forward + taped naive-AD backward in FP64, {tc:.2f} s"}
+
+    out = {
+        "metric": "differentiated light paths/s (fwd+bwd)",
+        "value": round(value, 1),
+        "unit": "paths/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"textured diffuse box, film {W}x{H}, max depth {D}, {N} light paths per step, "
+                               "forward + L2 loss + LRB-3-pass detached backward (albedo texels + emitter)",
+                   "paths": N, "depth": D, "film": [W, H], "method": "lrb3", "scene": "box"},
+        "step_ms": {"forward": round(float(np.median(fwd)), 4), "loss": round(float(np.median(lss)), 4),
+                    "backward": round(float(np.median(bwd)), 4)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "sweep": sweep,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,240 @@
+/*
+ * lt.h - C ABI of the MI355X (gfx950) constant-memory differentiable light
+ * tracer.  Plain C types only: pointers are host or device as stated, sizes
+ * are element or byte counts as stated.
+ *
+ * Paper: "Constant-Memory Differentiable Light Tracing" (Beresna, Fiume).
+ * The forward pass is the light-tracing estimator of Sec. 3.1 (Eq. 1-2):
+ * light paths start on the emitter, and at every non-specular vertex
+ * x_i (i >= 1) a sensor connection L_i = W_e f_i G V is splatted through a
+ * reconstruction filter at film position u_i (Eq. 20).  Three reverse modes
+ * compute the gradient of a loss whose image adjoint dL/dI the caller
+ * supplies (Sec. 3.2, Sec. 4.3.1 "Pass 1"):
+ *   - naive reverse-mode AD over a per-vertex tape (memory linear in depth);
+ *   - ResLRB: seed replay to the reservoir-selected connection
+ *     (Sec. 4.2, Eq. 8-13);
+ *   - LRB-3-pass: accumulate then consume downstream adjoints in two replays
+ *     (Sec. 4.3, Eq. 14-19).
+ * Attached variants also differentiate vertex positions and splat
+ * positions through per-segment ray Jacobians (Sec. 3.3, Eq. 4-7; Sec. 4.4,
+ * Eq. 21).
+ *
+ * Conventions shared by every call:
+ *   - The caller owns every buffer passed in (images, adjoints, parameters,
+ *     gradients, side state).  The library owns only its copy of the scene,
+ *     the BVH and a small workspace.  No pointer is retained after the call
+ *     returns.
+ *   - Calls are ordered on the context's HIP stream and asynchronous:
+ *     LT_OK means the work is enqueued.  A device fault surfaces as
+ *     LT_ERR_HIP from a later call that synchronizes.
+ *   - Arguments are validated before anything is enqueued; a rejected call
+ *     writes nothing and lt_last_error() says why.
+ *   - Randomness is counter-based (Philox-4x32-10 keyed by the seed,
+ *     counter = (path, vertex, block)), so the same (seed, n_paths,
+ *     max_depth, flags, params) gives the same paths and decisions on every
+ *     call; only the order of floating-point atomic sums may differ.
+ *   - No exception crosses this boundary.
+ */
+#ifndef LT_H
+#define LT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LT_OK = 0,
+  LT_ERR_ARG = 1,         /* invalid argument; nothing enqueued */
+  LT_ERR_OOM = 2,         /* allocation failed or the memory cap was exceeded */
+  LT_ERR_HIP = 3,         /* a HIP runtime call failed */
+  LT_ERR_STATE = 4,       /* call out of order (e.g. no scene uploaded) */
+  LT_ERR_UNSUPPORTED = 5  /* flag combination not implemented */
+} lt_status;
+
+/* material types (lt_scene_desc.mat_type) */
+enum { LT_MAT_ABSORBER = 0, LT_MAT_LAMBERT = 1, LT_MAT_DIELECTRIC = 2 };
+/* emitter types (lt_scene_desc.em_type) */
+enum { LT_EMIT_QUAD = 0, LT_EMIT_POINT = 1 };
+
+/* lt_trace_args.flags */
+enum {
+  LT_ATTACHED = 1u,         /* differentiate geometry (heightfield heights), Sec. 3.3 */
+  LT_SPLAT_SELECTED = 2u,   /* primal image splats only (Omega_k/w_R) L_R (Eq. 9) */
+  LT_RECORD_TAPE = 4u,      /* lt_trace writes the naive-AD tape */
+  LT_RECORD_RESERVOIR = 8u  /* lt_trace writes the per-path ResLRB record */
+};
+
+typedef struct lt_ctx lt_ctx;
+
+/* Scene description: HOST arrays, copied by lt_scene_upload.
+ *  tri_v  [n_tris][3][3]  static triangle vertices (world space)
+ *  tri_uv [n_tris][3][2]  per-vertex texture coordinates in [0,1]
+ *  tri_mat[n_tris]        material index in [0, n_mats)
+ *  mat_type/mat_tex/mat_ior [n_mats]: type, texture index (Lambertian),
+ *                         refractive index (dielectric)
+ *  n_tex, tex_res         albedo parameters are [n_tex][tex_res][tex_res][3]
+ *  emitter: quad (o, e1, e2; one-sided, normal normalize(e1 x e2)) or point (o)
+ *  camera: pinhole at cam_pos looking at cam_target, vertical FOV, film
+ *          width x height pixels; image row 0 is the top row
+ *  heightfield (hf_G >= 2, else none): vertex (i, j) at
+ *          (hf_x0 + i dx, hf_base + h[j*G + i], hf_z0 + j dx), material hf_mat;
+ *          cell (i, j) is split into triangles (A, C, B) and (A, D, C) with
+ *          A=(i,j) B=(i+1,j) C=(i+1,j+1) D=(i,j+1). */
+typedef struct {
+  int32_t n_tris;
+  const double* tri_v;
+  const double* tri_uv;
+  const int32_t* tri_mat;
+  int32_t n_mats;
+  const int32_t* mat_type;
+  const int32_t* mat_tex;
+  const double* mat_ior;
+  int32_t n_tex, tex_res;
+  int32_t em_type;
+  double em_o[3], em_e1[3], em_e2[3];
+  double cam_pos[3], cam_target[3], cam_up[3], cam_fov_deg;
+  int32_t width, height;
+  int32_t hf_G;
+  double hf_x0, hf_z0, hf_dx, hf_base;
+  int32_t hf_mat;
+} lt_scene_desc;
+
+/* Per-call trace arguments. */
+typedef struct {
+  uint64_t seed;            /* Philox key */
+  int64_t n_paths;          /* N light paths, 1 <= N < 2^31; also the 1/N of the estimator */
+  int32_t max_depth;        /* D: at most D scattering vertices x_1..x_D, 1 <= D <= 64 */
+  uint32_t flags;           /* LT_* flags above */
+  const uint8_t* path_mask; /* DEVICE [n_paths] or NULL: paths whose byte is 0
+                               contribute nothing (forward and backward) */
+  uint32_t* path_sig;       /* DEVICE [n_paths] or NULL: lt_trace writes each path's
+                               decision signature (FNV-1a of hit primitive, texel,
+                               connection validity, lobe and R) */
+} lt_trace_args;
+
+/* Parameters: DEVICE float arrays owned by the caller. */
+typedef struct {
+  const float* albedo;    /* [n_tex][tex_res][tex_res][3] */
+  const float* emitter_L; /* [3] radiance (quad) or intensity (point) */
+  const float* heights;   /* [G][G] heightfield offsets, or NULL when hf_G < 2 */
+} lt_params;
+
+/* Gradients: DEVICE float arrays, same shapes as lt_params, ACCUMULATED
+ * into (the caller zeroes them).  A NULL member is not written. */
+typedef struct {
+  float* albedo;
+  float* emitter_L;
+  float* heights;
+} lt_grads;
+
+/* Launch shape and strategy knobs (see lt_set_tuning). */
+typedef struct {
+  int32_t block;           /* threads per workgroup: 64..1024, multiple of 64 */
+  int32_t blocks_per_cu;   /* persistent workgroups per compute unit, 1..64 */
+  int32_t lds_grad;        /* 1: pre-reduce albedo gradients in LDS when they fit */
+} lt_tuning;
+
+/* Counters from the last call that produced them. */
+typedef struct {
+  uint64_t guard_triggers;  /* attached: singular accumulated Jacobians zeroed (Sec. 5) */
+  uint64_t nonfinite;       /* non-finite contributions dropped */
+} lt_stats;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the handle.
+ * Errors: LT_ERR_ARG (bad device / out == NULL), LT_ERR_HIP, LT_ERR_OOM. */
+lt_status lt_create(int device, void* hip_stream, lt_ctx** out);
+/* Release the context and everything the library owns. NULL is ignored. */
+void lt_destroy(lt_ctx* ctx);
+/* Message of the last non-OK status on this context ("" if none). */
+const char* lt_last_error(const lt_ctx* ctx);
+/* Switch the stream later calls enqueue on. */
+lt_status lt_set_stream(lt_ctx* ctx, void* hip_stream);
+/* Launch shape: NULL restores the defaults. Errors: LT_ERR_ARG. */
+lt_status lt_set_tuning(lt_ctx* ctx, const lt_tuning* tuning);
+lt_status lt_get_tuning(const lt_ctx* ctx, lt_tuning* out);
+/* Cap, in bytes, on side state plus library workspace a call may use
+ * (0 = no cap).  Calls above it fail with LT_ERR_OOM before any launch,
+ * which is how the linear memory of the naive tape is shown against the
+ * flat memory of the replay methods (Sec. 6.2). */
+lt_status lt_set_memory_cap(lt_ctx* ctx, uint64_t bytes);
+lt_status lt_get_stats(const lt_ctx* ctx, lt_stats* out);
+/* Diagnostic event counts (a library built with -DLT_COUNTERS only; others
+ * return LT_ERR_UNSUPPORTED).  Synchronizes the stream, copies 16 uint64
+ * totals to HOST out16 - [0] closest-hit rays, [1] shadow rays, [2] BVH
+ * node fetches, [3] triangle tests, [4] film splats, [5] adjoint gathers,
+ * [6] gradient values scattered, [7] paths emitted, [8] tape records
+ * written, [9] tape records read - and zeroes them when reset != 0.
+ * They feed the algorithmic byte model of the roofline. */
+lt_status lt_read_counters(lt_ctx* ctx, uint64_t* out16, int reset);
+
+/* Upload a scene (Sec. 3.1 setting): copies the host arrays, builds a
+ * binned-SAH BVH over static and heightfield triangles on the host and
+ * uploads it.  Synchronizes the context's stream.  Replaces any previous
+ * scene.  Errors: LT_ERR_ARG (inconsistent sizes/indices), LT_ERR_OOM,
+ * LT_ERR_HIP. */
+lt_status lt_scene_upload(lt_ctx* ctx, const lt_scene_desc* scene);
+
+/* Bytes of caller-provided side state lt_trace writes for these args:
+ * LT_RECORD_TAPE: the naive-AD tape, N*D records (linear in depth) plus one
+ * path length per path; LT_RECORD_RESERVOIR: one ResLRB record per path
+ * (Sec. 4.2.1: selected depth R, weight Omega_k/w_R, u_R, reweighted splat).
+ * 0 for neither. */
+size_t lt_side_state_bytes(const lt_ctx* ctx, const lt_trace_args* args);
+/* Library workspace bytes a call with these args uses (flat in depth). */
+size_t lt_workspace_bytes(const lt_ctx* ctx, const lt_trace_args* args);
+
+/* Light tracing forward (Eq. 1-2, Eq. 20; Sec. 4.3.1 Pass 1).
+ * image: DEVICE float [height][width][3], overwritten with the estimate
+ *   I[p] = sum over paths and connections of F(u_i, p) L_i, where L_i
+ *   carries the per-sample normalization s = width*height/(A_film N).
+ * With LT_SPLAT_SELECTED only the reservoir-selected (Omega_k/w_R) L_R is
+ * splatted (Listing "ResLRB primal" of Sec. 5).
+ * side/side_bytes: DEVICE buffer of at least lt_side_state_bytes(args)
+ * when a RECORD flag is set (else may be NULL/0).
+ * Errors: LT_ERR_ARG, LT_ERR_STATE, LT_ERR_OOM (memory cap), LT_ERR_HIP. */
+lt_status lt_trace(lt_ctx* ctx, const lt_trace_args* args, const lt_params* params,
+                   float* image, void* side, size_t side_bytes);
+
+/* Mean-squared-error loss and image adjoint (Sec. 6.1: L2 loss):
+ *   loss = sum_k (I_k - T_k)^2 / n,  d_image_k = 2 (I_k - T_k) / n.
+ * image, target, d_image: DEVICE float [n]; loss: DEVICE float [1].
+ * Errors: LT_ERR_ARG, LT_ERR_HIP. */
+lt_status lt_loss_l2(lt_ctx* ctx, const float* image, const float* target, int64_t n,
+                     float* d_image, float* loss);
+
+/* Naive reverse-mode AD (Sec. 3.2): sweeps the tape written by lt_trace
+ * with LT_RECORD_TAPE (same args and params) from the last vertex to the
+ * first, applying the exact chain rule with image adjoint d_image
+ * (DEVICE float [height][width][3]).  Gradients are accumulated into grads.
+ * Errors: LT_ERR_ARG (tape too small / flags), LT_ERR_STATE, LT_ERR_HIP. */
+lt_status lt_backward_naive(lt_ctx* ctx, const lt_trace_args* args, const lt_params* params,
+                            const float* d_image, const void* tape, size_t tape_bytes,
+                            lt_grads* grads);
+
+/* ResLRB adjoint pass (Sec. 4.2, Eq. 11; attached Eq. 12-13): replays each
+ * path from its seed up to the selected depth R read from `records`
+ * (written by lt_trace with LT_RECORD_RESERVOIR, same args and params) and
+ * applies the log-derivative identity weighted by dI(u_R) * S_hat.
+ * Errors: as lt_backward_naive. */
+lt_status lt_backward_reslrb(lt_ctx* ctx, const lt_trace_args* args, const lt_params* params,
+                             const float* d_image, const void* records, size_t records_bytes,
+                             lt_grads* grads);
+
+/* LRB-3-pass backward (Sec. 4.3): Pass 2 replays each path and accumulates
+ * delta_total = sum_i dI(u_i) * L_i (Eq. 14; attached also A_pos, Eq. 18);
+ * Pass 3 replays again, backpropagating the splat (Eq. 15), subtracting
+ * (Eq. 16) and applying the log-derivative with delta_rem (Eq. 17;
+ * attached Eq. 19).  Needs no side state.  Errors: LT_ERR_ARG,
+ * LT_ERR_STATE, LT_ERR_HIP. */
+lt_status lt_backward_lrb3(lt_ctx* ctx, const lt_trace_args* args, const lt_params* params,
+                           const float* d_image, lt_grads* grads);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LT_H */

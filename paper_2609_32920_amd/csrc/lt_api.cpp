@@ -1,0 +1,636 @@
+// Host runtime and C ABI of the light tracer (see include/lt.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lt.h"
+#include "lt_common.h"
+#include "lt_launch.h"
+
+using namespace lt;
+
+namespace {
+
+// ------------------------------------------------------------ BVH builder
+// Binned SAH over triangle bounds (16 bins per axis), leaves of at most 4
+// triangles, median split below a depth that keeps the traversal stack
+// within kStackMax.
+struct BPrim { float lo[3], hi[3], c[3]; int id; };
+struct BNode { float lo[3], hi[3]; int left = -1, right = -1, first = 0, count = 0; };
+
+struct Builder {
+  std::vector<BPrim> prims;
+  std::vector<BNode> bn;
+  int max_depth = 0;
+
+  static void grow(float* lo, float* hi, const float* plo, const float* phi) {
+    for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], plo[a]); hi[a] = std::max(hi[a], phi[a]); }
+  }
+  static float area(const float* lo, const float* hi) {
+    float d[3];
+    for (int a = 0; a < 3; ++a) d[a] = std::max(0.0f, hi[a] - lo[a]);
+    return 2.0f * (d[0] * d[1] + d[1] * d[2] + d[2] * d[0]);
+  }
+
+  int build(int b, int e, int depth) {
+    int idx = (int)bn.size();
+    bn.emplace_back();
+    BNode nd;
+    for (int a = 0; a < 3; ++a) { nd.lo[a] = 3e38f; nd.hi[a] = -3e38f; }
+    float clo[3] = {3e38f, 3e38f, 3e38f}, chi[3] = {-3e38f, -3e38f, -3e38f};
+    for (int i = b; i < e; ++i) {
+      grow(nd.lo, nd.hi, prims[i].lo, prims[i].hi);
+      grow(clo, chi, prims[i].c, prims[i].c);
+    }
+    max_depth = std::max(max_depth, depth);
+    int n = e - b;
+    if (n <= 4) { nd.first = b; nd.count = n; bn[idx] = nd; return idx; }
+    int mid = -1;
+    if (depth < kStackMax - 8) {
+      const int NB = 16;
+      float best = 3e38f; int best_axis = -1, best_bin = -1;
+      for (int a = 0; a < 3; ++a) {
+        float ext = chi[a] - clo[a];
+        if (!(ext > 0.0f)) continue;
+        int cnt[NB] = {0};
+        float blo[NB][3], bhi[NB][3];
+        for (int k = 0; k < NB; ++k) for (int q = 0; q < 3; ++q) { blo[k][q] = 3e38f; bhi[k][q] = -3e38f; }
+        for (int i = b; i < e; ++i) {
+          int k = std::min(NB - 1, (int)((prims[i].c[a] - clo[a]) / ext * NB));
+          cnt[k]++;
+          grow(blo[k], bhi[k], prims[i].lo, prims[i].hi);
+        }
+        for (int s = 1; s < NB; ++s) {
+          float llo[3] = {3e38f, 3e38f, 3e38f}, lhi[3] = {-3e38f, -3e38f, -3e38f};
+          float rlo[3] = {3e38f, 3e38f, 3e38f}, rhi[3] = {-3e38f, -3e38f, -3e38f};
+          int nl = 0, nr = 0;
+          for (int k = 0; k < s; ++k) if (cnt[k]) { grow(llo, lhi, blo[k], bhi[k]); nl += cnt[k]; }
+          for (int k = s; k < NB; ++k) if (cnt[k]) { grow(rlo, rhi, blo[k], bhi[k]); nr += cnt[k]; }
+          if (!nl || !nr) continue;
+          float cost = area(llo, lhi) * nl + area(rlo, rhi) * nr;
+          if (cost < best) { best = cost; best_axis = a; best_bin = s; }
+        }
+      }
+      if (best_axis >= 0) {
+        float ext = chi[best_axis] - clo[best_axis];
+        auto it = std::partition(prims.begin() + b, prims.begin() + e, [&](const BPrim& p) {
+          int k = std::min(NB - 1, (int)((p.c[best_axis] - clo[best_axis]) / ext * NB));
+          return k < best_bin;
+        });
+        mid = (int)(it - prims.begin());
+        if (mid == b || mid == e) mid = -1;
+      }
+    }
+    if (mid < 0) {  // object median on the widest centroid axis
+      int a = 0;
+      for (int q = 1; q < 3; ++q) if (chi[q] - clo[q] > chi[a] - clo[a]) a = q;
+      mid = (b + e) / 2;
+      std::nth_element(prims.begin() + b, prims.begin() + mid, prims.begin() + e,
+                       [a](const BPrim& x, const BPrim& y) { return x.c[a] < y.c[a]; });
+    }
+    int l = build(b, mid, depth + 1);
+    int r = build(mid, e, depth + 1);
+    nd.left = l; nd.right = r;
+    bn[idx] = nd;
+    return idx;
+  }
+};
+
+void pad_box(const float* lo, const float* hi, float* plo, float* phi) {
+  for (int a = 0; a < 3; ++a) {
+    float pad = 1e-5f + 1e-6f * std::max(std::fabs(lo[a]), std::fabs(hi[a]));
+    plo[a] = lo[a] - pad; phi[a] = hi[a] + pad;
+  }
+}
+
+struct Flat {
+  std::vector<Node> nodes;
+  std::vector<int> depth;
+};
+
+int flatten(const Builder& B, int bi, int depth, Flat& F) {
+  int idx = (int)F.nodes.size();
+  F.nodes.emplace_back();
+  F.depth.push_back(depth);
+  const BNode& b = B.bn[bi];
+  Node nd;
+  std::memset(&nd, 0, sizeof(nd));
+  int kids[2] = {b.left, b.right};
+  int cidx[2], ccnt[2];
+  float lo[2][3], hi[2][3];
+  for (int k = 0; k < 2; ++k) {
+    const BNode& c = B.bn[kids[k]];
+    pad_box(c.lo, c.hi, lo[k], hi[k]);
+    if (c.left < 0) { cidx[k] = c.first; ccnt[k] = c.count; }
+    else { cidx[k] = flatten(B, kids[k], depth + 1, F); ccnt[k] = 0; }
+  }
+  for (int a = 0; a < 3; ++a) {
+    nd.lo0[a] = lo[0][a]; nd.hi0[a] = hi[0][a];
+    nd.lo1[a] = lo[1][a]; nd.hi1[a] = hi[1][a];
+  }
+  nd.child0 = cidx[0]; nd.child1 = cidx[1]; nd.count0 = ccnt[0]; nd.count1 = ccnt[1];
+  F.nodes[idx] = nd;
+  return idx;
+}
+
+template <typename T>
+hipError_t upload(T** dst, const T* src, size_t n) {
+  if (*dst) { hipFree(*dst); *dst = nullptr; }
+  if (n == 0) return hipSuccess;
+  hipError_t e = hipMalloc((void**)dst, n * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+}
+
+}  // namespace
+
+struct lt_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  lt_tuning tune{256, 4, 0};
+  uint64_t cap = 0;
+  lt_stats stats{};
+  int n_cu = 256;
+  bool has_scene = false;
+  Node* d_nodes = nullptr;
+  Tri* d_tris = nullptr;
+  int32_t* d_prim_mat = nullptr;
+  float* d_prim_uv = nullptr;
+  int32_t* d_mat_type = nullptr;
+  int32_t* d_mat_tex = nullptr;
+  float* d_mat_ior = nullptr;
+  int32_t* d_slot_of_prim = nullptr;
+  int32_t* d_levels = nullptr;
+  std::vector<int> level_off;  // node-level ranges into d_levels, deepest last
+  DevScene dsc{};
+  size_t scene_bytes = 0;
+  float emit_factor = 0.f;
+  unsigned int* d_counter = nullptr;
+  double* d_acc = nullptr;  // [0..2] emitter gradient, [3] loss
+
+  lt_status fail(lt_status s, const char* fmt, const char* a = "") {
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), fmt, a);
+    err = buf;
+    return s;
+  }
+  lt_status hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return LT_OK;
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), "%s: %s", what, hipGetErrorString(e));
+    err = buf;
+    return LT_ERR_HIP;
+  }
+  void free_scene() {
+    hipFree(d_nodes); hipFree(d_tris); hipFree(d_prim_mat); hipFree(d_prim_uv);
+    hipFree(d_mat_type); hipFree(d_mat_tex); hipFree(d_mat_ior); hipFree(d_slot_of_prim); hipFree(d_levels);
+    d_nodes = nullptr; d_tris = nullptr; d_prim_mat = nullptr; d_prim_uv = nullptr; d_mat_type = nullptr;
+    d_mat_tex = nullptr; d_mat_ior = nullptr; d_slot_of_prim = nullptr; d_levels = nullptr;
+    has_scene = false; scene_bytes = 0;
+  }
+};
+
+namespace {
+
+int persistent_grid(const lt_ctx* c, int64_t n, int block) {
+  int64_t g = (int64_t)c->n_cu * c->tune.blocks_per_cu;
+  int64_t need = (n + block - 1) / block;
+  return (int)std::max<int64_t>(1, std::min(g, need));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct SideLayout { size_t tape = 0, len = 0, res = 0, total = 0; };
+
+SideLayout side_layout(const lt_trace_args* a) {
+  SideLayout L;
+  size_t N = (size_t)a->n_paths, D = (size_t)a->max_depth;
+  size_t off = 0;
+  if (a->flags & LT_RECORD_TAPE) {
+    L.tape = off; off = align256(off + N * D * sizeof(TapeRec));
+    L.len = off; off = align256(off + N * sizeof(int32_t));
+  }
+  if (a->flags & LT_RECORD_RESERVOIR) {
+    L.res = off; off = align256(off + N * sizeof(ResRec));
+  }
+  L.total = off;
+  return L;
+}
+
+lt_status check_args(lt_ctx* c, const lt_trace_args* a, const lt_params* p) {
+  if (!c) return LT_ERR_ARG;
+  if (!a || !p) return c->fail(LT_ERR_ARG, "null args or params%s");
+  if (!c->has_scene) return c->fail(LT_ERR_STATE, "no scene uploaded%s");
+  if (a->n_paths < 1 || a->n_paths >= (int64_t)1 << 31) return c->fail(LT_ERR_ARG, "n_paths out of range [1, 2^31)%s");
+  if (a->max_depth < 1 || a->max_depth > kMaxDepth) return c->fail(LT_ERR_ARG, "max_depth out of range [1, 64]%s");
+  if (a->flags & ~(uint32_t)(LT_ATTACHED | LT_SPLAT_SELECTED | LT_RECORD_TAPE | LT_RECORD_RESERVOIR))
+    return c->fail(LT_ERR_ARG, "unknown flag bits%s");
+  if (!p->albedo || !p->emitter_L) return c->fail(LT_ERR_ARG, "albedo and emitter_L are required%s");
+  if ((a->flags & LT_ATTACHED) && c->dsc.hf_G < 2) return c->fail(LT_ERR_ARG, "LT_ATTACHED needs a heightfield%s");
+  if (a->flags & LT_ATTACHED) return c->fail(LT_ERR_UNSUPPORTED, "attached mode is not available in this build%s");
+  return LT_OK;
+}
+
+lt_status prepare_geometry(lt_ctx* c, const lt_params* p) {
+  if (c->dsc.hf_G < 2 || !p->heights) return LT_OK;
+  lt_status s = c->hip(launch_hf_tris(c->dsc, c->d_slot_of_prim, c->d_tris, p->heights, c->stream), "hf tris");
+  if (s != LT_OK) return s;
+  for (int lv = (int)c->level_off.size() - 2; lv >= 0; --lv) {
+    int b = c->level_off[lv], e = c->level_off[lv + 1];
+    if (e > b) {
+      s = c->hip(launch_refit_level(c->d_nodes, c->d_tris, c->d_levels + b, e - b, c->stream), "refit");
+      if (s != LT_OK) return s;
+    }
+  }
+  return LT_OK;
+}
+
+PassArgs base_args(lt_ctx* c, const lt_trace_args* a, const lt_params* p) {
+  PassArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.sc = c->dsc;
+  A.seed = a->seed;
+  A.n_paths = (int32_t)a->n_paths;
+  A.D = a->max_depth;
+  A.flags = a->flags;
+  double Kfilm = (double)c->dsc.W * c->dsc.H / ((double)c->dsc.film_area * (double)a->n_paths);
+  A.Kfilm = (float)Kfilm;
+  A.emit_factor = c->emit_factor;
+  A.n_texels = c->dsc.n_tex * c->dsc.tex_res * c->dsc.tex_res;
+  A.mask = a->path_mask;
+  A.sig = a->path_sig;
+  A.albedo = p->albedo;
+  A.Le = p->emitter_L;
+  A.heights = p->heights;
+  A.counter = c->d_counter;
+  return A;
+}
+
+lt_status check_cap(lt_ctx* c, size_t side) {
+  if (c->cap && side + c->scene_bytes + 64 > c->cap) {
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "memory cap exceeded: %zu side-state bytes + %zu library bytes > %llu",
+                  side, c->scene_bytes + 64, (unsigned long long)c->cap);
+    c->err = buf;
+    return LT_ERR_OOM;
+  }
+  return LT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lt_status lt_create(int device, void* stream, lt_ctx** out) {
+  if (!out) return LT_ERR_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return LT_ERR_ARG;
+  if (hipSetDevice(device) != hipSuccess) return LT_ERR_HIP;
+  lt_ctx* c = new (std::nothrow) lt_ctx();
+  if (!c) return LT_ERR_OOM;
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->n_cu = prop.multiProcessorCount;
+  if (hipMalloc((void**)&c->d_counter, 256) != hipSuccess || hipMalloc((void**)&c->d_acc, 256) != hipSuccess) {
+    hipFree(c->d_counter); hipFree(c->d_acc);
+    delete c;
+    return LT_ERR_OOM;
+  }
+  *out = c;
+  return LT_OK;
+}
+
+void lt_destroy(lt_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  c->free_scene();
+  hipFree(c->d_counter);
+  hipFree(c->d_acc);
+  delete c;
+}
+
+const char* lt_last_error(const lt_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+lt_status lt_set_stream(lt_ctx* c, void* stream) {
+  if (!c) return LT_ERR_ARG;
+  c->stream = (hipStream_t)stream;
+  return LT_OK;
+}
+
+lt_status lt_set_tuning(lt_ctx* c, const lt_tuning* t) {
+  if (!c) return LT_ERR_ARG;
+  if (!t) { c->tune = lt_tuning{256, 4, 0}; return LT_OK; }
+  if (t->block < 64 || t->block > 1024 || (t->block % 64) != 0) return c->fail(LT_ERR_ARG, "block must be 64..1024, a multiple of 64%s");
+  if (t->blocks_per_cu < 1 || t->blocks_per_cu > 64) return c->fail(LT_ERR_ARG, "blocks_per_cu must be 1..64%s");
+  if ((size_t)kStackMax * t->block * sizeof(int) > 65536) return c->fail(LT_ERR_ARG, "traversal stack exceeds 64 KiB of LDS%s");
+  c->tune = *t;
+  return LT_OK;
+}
+
+lt_status lt_get_tuning(const lt_ctx* c, lt_tuning* out) {
+  if (!c || !out) return LT_ERR_ARG;
+  *out = c->tune;
+  return LT_OK;
+}
+
+lt_status lt_set_memory_cap(lt_ctx* c, uint64_t bytes) {
+  if (!c) return LT_ERR_ARG;
+  c->cap = bytes;
+  return LT_OK;
+}
+
+lt_status lt_get_stats(const lt_ctx* c, lt_stats* out) {
+  if (!c || !out) return LT_ERR_ARG;
+  *out = c->stats;
+  return LT_OK;
+}
+
+lt_status lt_read_counters(lt_ctx* c, uint64_t* out16, int reset) {
+  if (!c || !out16) return LT_ERR_ARG;
+  hipError_t e = read_counters(out16, reset != 0, c->stream);
+  if (e == hipErrorNotSupported) return c->fail(LT_ERR_UNSUPPORTED, "library built without LT_COUNTERS%s");
+  return c->hip(e, "read counters");
+}
+
+lt_status lt_scene_upload(lt_ctx* c, const lt_scene_desc* s) {
+  if (!c) return LT_ERR_ARG;
+  if (!s) return c->fail(LT_ERR_ARG, "null scene%s");
+  if (s->n_tris < 0 || (s->n_tris > 0 && (!s->tri_v || !s->tri_uv || !s->tri_mat)))
+    return c->fail(LT_ERR_ARG, "bad triangle arrays%s");
+  if (s->n_mats < 1 || !s->mat_type || !s->mat_tex || !s->mat_ior) return c->fail(LT_ERR_ARG, "bad material arrays%s");
+  if (s->n_tex < 1 || s->tex_res < 1 || (int64_t)s->n_tex * s->tex_res * s->tex_res >= (1 << 27))
+    return c->fail(LT_ERR_ARG, "bad texture shape%s");
+  if (s->width < 1 || s->height < 1 || s->width > 16384 || s->height > 16384) return c->fail(LT_ERR_ARG, "bad film size%s");
+  if (!(s->cam_fov_deg > 0.0 && s->cam_fov_deg < 180.0)) return c->fail(LT_ERR_ARG, "bad field of view%s");
+  if (s->em_type != LT_EMIT_QUAD && s->em_type != LT_EMIT_POINT) return c->fail(LT_ERR_ARG, "bad emitter type%s");
+  if (s->hf_G == 1 || s->hf_G < 0 || s->hf_G > 4096) return c->fail(LT_ERR_ARG, "bad heightfield size%s");
+  for (int m = 0; m < s->n_mats; ++m) {
+    if (s->mat_type[m] < 0 || s->mat_type[m] > 2) return c->fail(LT_ERR_ARG, "bad material type%s");
+    if (s->mat_type[m] == LT_MAT_LAMBERT && (s->mat_tex[m] < 0 || s->mat_tex[m] >= s->n_tex))
+      return c->fail(LT_ERR_ARG, "Lambertian material without a valid texture%s");
+    if (s->mat_type[m] == LT_MAT_DIELECTRIC && !(s->mat_ior[m] > 0.0)) return c->fail(LT_ERR_ARG, "bad IOR%s");
+  }
+  for (int t = 0; t < s->n_tris; ++t)
+    if (s->tri_mat[t] < 0 || s->tri_mat[t] >= s->n_mats) return c->fail(LT_ERR_ARG, "triangle material out of range%s");
+  if (s->hf_G >= 2 && (s->hf_mat < 0 || s->hf_mat >= s->n_mats)) return c->fail(LT_ERR_ARG, "heightfield material out of range%s");
+  if (hipSetDevice(c->device) != hipSuccess) return c->fail(LT_ERR_HIP, "hipSetDevice failed%s");
+
+  const int G = s->hf_G;
+  const int n_static = s->n_tris;
+  const int n_hf = G >= 2 ? 2 * (G - 1) * (G - 1) : 0;
+  const int n_prims = n_static + n_hf;
+  if (n_prims < 1) return c->fail(LT_ERR_ARG, "scene has no geometry%s");
+
+  // primitive geometry (double -> float), heightfield flat (h = 0)
+  std::vector<Tri> tri(n_prims);
+  auto setv = [](Tri& t, const double* v0, const double* v1, const double* v2, int prim) {
+    for (int a = 0; a < 3; ++a) {
+      t.p0[a] = (float)v0[a];
+      t.e1[a] = (float)(v1[a] - v0[a]);
+      t.e2[a] = (float)(v2[a] - v0[a]);
+    }
+    t.prim = prim; t.pad1 = t.pad2 = 0.f;
+  };
+  for (int t = 0; t < n_static; ++t)
+    setv(tri[t], s->tri_v + t * 9, s->tri_v + t * 9 + 3, s->tri_v + t * 9 + 6, t);
+  for (int q = 0; q < n_hf; ++q) {
+    int cell = q >> 1, half = q & 1, ci = cell % (G - 1), cj = cell / (G - 1);
+    static const int o0[3][2] = {{0, 0}, {1, 1}, {1, 0}};
+    static const int o1[3][2] = {{0, 0}, {0, 1}, {1, 1}};
+    const int (*o)[2] = half == 0 ? o0 : o1;
+    double v[3][3];
+    for (int k = 0; k < 3; ++k) {
+      v[k][0] = s->hf_x0 + (ci + o[k][0]) * s->hf_dx;
+      v[k][1] = s->hf_base;
+      v[k][2] = s->hf_z0 + (cj + o[k][1]) * s->hf_dx;
+    }
+    setv(tri[n_static + q], v[0], v[1], v[2], n_static + q);
+  }
+
+  Builder B;
+  B.prims.resize(n_prims);
+  for (int i = 0; i < n_prims; ++i) {
+    BPrim& p = B.prims[i];
+    const Tri& t = tri[i];
+    for (int a = 0; a < 3; ++a) {
+      float v0 = t.p0[a], v1 = t.p0[a] + t.e1[a], v2 = t.p0[a] + t.e2[a];
+      p.lo[a] = std::min(v0, std::min(v1, v2));
+      p.hi[a] = std::max(v0, std::max(v1, v2));
+      // a heightfield vertex can move in y: leave room for the refit
+      p.c[a] = 0.5f * (p.lo[a] + p.hi[a]);
+    }
+    p.id = i;
+  }
+  int root = B.build(0, n_prims, 0);
+  Flat F;
+  if (B.bn[root].left < 0) {  // the whole scene is one leaf
+    Node nd;
+    std::memset(&nd, 0, sizeof(nd));
+    pad_box(B.bn[root].lo, B.bn[root].hi, nd.lo0, nd.hi0);
+    for (int a = 0; a < 3; ++a) { nd.lo1[a] = 0.f; nd.hi1[a] = 0.f; }
+    nd.child0 = 0; nd.count0 = B.bn[root].count; nd.child1 = -1; nd.count1 = 0;
+    F.nodes.push_back(nd);
+    F.depth.push_back(0);
+  } else {
+    flatten(B, root, 0, F);
+  }
+  int maxd = 0;
+  for (int d : F.depth) maxd = std::max(maxd, d);
+  if (maxd + 2 > kStackMax) return c->fail(LT_ERR_UNSUPPORTED, "BVH deeper than the traversal stack%s");
+  std::vector<Tri> ordered(n_prims);
+  std::vector<int32_t> slot(n_prims);
+  for (int k = 0; k < n_prims; ++k) { ordered[k] = tri[B.prims[k].id]; slot[B.prims[k].id] = k; }
+  std::vector<int32_t> pmat(n_prims);
+  for (int t = 0; t < n_static; ++t) pmat[t] = s->tri_mat[t];
+  for (int q = 0; q < n_hf; ++q) pmat[n_static + q] = s->hf_mat;
+  std::vector<float> puv((size_t)std::max(n_static, 1) * 6, 0.f);
+  for (int t = 0; t < n_static; ++t)
+    for (int k = 0; k < 6; ++k) puv[(size_t)t * 6 + k] = (float)s->tri_uv[(size_t)t * 6 + k];
+  std::vector<int32_t> mtype(s->mat_type, s->mat_type + s->n_mats), mtex(s->mat_tex, s->mat_tex + s->n_mats);
+  std::vector<float> mior(s->n_mats);
+  for (int m = 0; m < s->n_mats; ++m) mior[m] = (float)s->mat_ior[m];
+  // refit levels: node indices grouped by depth
+  std::vector<int32_t> levels;
+  std::vector<int> loff;
+  for (int d = 0; d <= maxd; ++d) {
+    loff.push_back((int)levels.size());
+    for (size_t k = 0; k < F.nodes.size(); ++k) if (F.depth[k] == d) levels.push_back((int32_t)k);
+  }
+  loff.push_back((int)levels.size());
+
+  c->free_scene();
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = upload(&c->d_nodes, F.nodes.data(), F.nodes.size());
+  if (e == hipSuccess) e = upload(&c->d_tris, ordered.data(), ordered.size());
+  if (e == hipSuccess) e = upload(&c->d_prim_mat, pmat.data(), pmat.size());
+  if (e == hipSuccess) e = upload(&c->d_prim_uv, puv.data(), puv.size());
+  if (e == hipSuccess) e = upload(&c->d_mat_type, mtype.data(), mtype.size());
+  if (e == hipSuccess) e = upload(&c->d_mat_tex, mtex.data(), mtex.size());
+  if (e == hipSuccess) e = upload(&c->d_mat_ior, mior.data(), mior.size());
+  if (e == hipSuccess) e = upload(&c->d_slot_of_prim, slot.data(), slot.size());
+  if (e == hipSuccess) e = upload(&c->d_levels, levels.data(), levels.size());
+  if (e != hipSuccess) { c->free_scene(); return c->hip(e, "scene upload"); }
+  c->level_off = loff;
+  c->scene_bytes = F.nodes.size() * sizeof(Node) + ordered.size() * sizeof(Tri) + pmat.size() * 4 +
+                   puv.size() * 4 + slot.size() * 4 + levels.size() * 4 + 512;
+
+  DevScene& d = c->dsc;
+  std::memset(&d, 0, sizeof(d));
+  d.nodes = c->d_nodes; d.tris = c->d_tris; d.prim_mat = c->d_prim_mat; d.prim_uv = c->d_prim_uv;
+  d.mat_type = c->d_mat_type; d.mat_tex = c->d_mat_tex; d.mat_ior = c->d_mat_ior;
+  d.n_nodes = (int)F.nodes.size(); d.n_tris = n_prims; d.n_static = n_static;
+  d.hf_G = G >= 2 ? G : 0;
+  d.hf_x0 = (float)s->hf_x0; d.hf_z0 = (float)s->hf_z0; d.hf_dx = (float)s->hf_dx; d.hf_base = (float)s->hf_base;
+  d.hf_mat = s->hf_mat;
+  d.n_tex = s->n_tex; d.tex_res = s->tex_res;
+  d.em_type = s->em_type;
+  double cr[3] = {s->em_e1[1] * s->em_e2[2] - s->em_e1[2] * s->em_e2[1],
+                  s->em_e1[2] * s->em_e2[0] - s->em_e1[0] * s->em_e2[2],
+                  s->em_e1[0] * s->em_e2[1] - s->em_e1[1] * s->em_e2[0]};
+  double area = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+  for (int a = 0; a < 3; ++a) {
+    d.em_o[a] = (float)s->em_o[a]; d.em_e1[a] = (float)s->em_e1[a]; d.em_e2[a] = (float)s->em_e2[a];
+    d.em_n[a] = area > 0 ? (float)(cr[a] / area) : 0.f;
+  }
+  d.em_area = (float)area;
+  if (s->em_type == LT_EMIT_QUAD && !(area > 0)) { c->free_scene(); return c->fail(LT_ERR_ARG, "degenerate quad emitter%s"); }
+  c->emit_factor = s->em_type == LT_EMIT_QUAD ? (float)(area * M_PI) : (float)(4.0 * M_PI);
+  // camera frame: f = normalize(target - pos), r = normalize(f x up), u = r x f
+  double f[3], r[3], u[3];
+  for (int a = 0; a < 3; ++a) f[a] = s->cam_target[a] - s->cam_pos[a];
+  double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  if (!(fl > 0)) { c->free_scene(); return c->fail(LT_ERR_ARG, "camera target equals position%s"); }
+  for (int a = 0; a < 3; ++a) f[a] /= fl;
+  const double* up = s->cam_up;
+  r[0] = f[1] * up[2] - f[2] * up[1]; r[1] = f[2] * up[0] - f[0] * up[2]; r[2] = f[0] * up[1] - f[1] * up[0];
+  double rl = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  if (!(rl > 0)) { c->free_scene(); return c->fail(LT_ERR_ARG, "camera up parallel to view direction%s"); }
+  for (int a = 0; a < 3; ++a) r[a] /= rl;
+  u[0] = r[1] * f[2] - r[2] * f[1]; u[1] = r[2] * f[0] - r[0] * f[2]; u[2] = r[0] * f[1] - r[1] * f[0];
+  for (int a = 0; a < 3; ++a) {
+    d.cpos[a] = (float)s->cam_pos[a]; d.cf[a] = (float)f[a]; d.cr[a] = (float)r[a]; d.cu[a] = (float)u[a];
+  }
+  double th = std::tan(s->cam_fov_deg * M_PI / 360.0);
+  d.tan_half = (float)th;
+  d.aspect = (float)((double)s->width / (double)s->height);
+  d.film_area = (float)(4.0 * ((double)s->width / s->height) * th * th);
+  d.W = s->width; d.H = s->height;
+  c->has_scene = true;
+  c->err.clear();
+  return c->hip(hipStreamSynchronize(c->stream), "scene upload sync");
+}
+
+size_t lt_side_state_bytes(const lt_ctx* c, const lt_trace_args* a) {
+  (void)c;
+  if (!a || a->n_paths < 1 || a->max_depth < 1) return 0;
+  return side_layout(a).total;
+}
+
+size_t lt_workspace_bytes(const lt_ctx* c, const lt_trace_args* a) {
+  (void)a;
+  return c ? c->scene_bytes + 512 : 0;
+}
+
+lt_status lt_trace(lt_ctx* c, const lt_trace_args* a, const lt_params* p, float* image, void* side,
+                   size_t side_bytes) {
+  lt_status st = check_args(c, a, p);
+  if (st != LT_OK) return st;
+  if (!image) return c->fail(LT_ERR_ARG, "null image%s");
+  SideLayout L = side_layout(a);
+  if (L.total && (!side || side_bytes < L.total)) return c->fail(LT_ERR_ARG, "side state buffer too small%s");
+  if ((st = check_cap(c, L.total)) != LT_OK) return st;
+  if ((st = prepare_geometry(c, p)) != LT_OK) return st;
+  PassArgs A = base_args(c, a, p);
+  A.image = image;
+  char* sb = (char*)side;
+  if (a->flags & LT_RECORD_TAPE) { A.tape = (TapeRec*)(sb + L.tape); A.tape_len = (int32_t*)(sb + L.len); }
+  if (a->flags & LT_RECORD_RESERVOIR) A.res = (ResRec*)(sb + L.res);
+  size_t npix = (size_t)c->dsc.W * c->dsc.H * 3;
+  if ((st = c->hip(launch_fill_f32(image, npix, 0.f, c->stream), "image clear")) != LT_OK) return st;
+  if ((st = c->hip(launch_fill_u32(c->d_counter, 1, 0u, c->stream), "counter clear")) != LT_OK) return st;
+  bool tape = (a->flags & LT_RECORD_TAPE) != 0;
+  bool resv = (a->flags & (LT_RECORD_RESERVOIR | LT_SPLAT_SELECTED)) != 0;
+  int grid = persistent_grid(c, a->n_paths, c->tune.block);
+  return c->hip(launch_trace(A, tape, resv, grid, c->tune.block, c->stream), "trace launch");
+}
+
+lt_status lt_loss_l2(lt_ctx* c, const float* image, const float* target, int64_t n, float* d_image, float* loss) {
+  if (!c) return LT_ERR_ARG;
+  if (!image || !target || !d_image || !loss || n < 1) return c->fail(LT_ERR_ARG, "bad loss arguments%s");
+  lt_status st = c->hip(launch_fill_f64(c->d_acc + 3, 1, 0.0, c->stream), "loss clear");
+  if (st != LT_OK) return st;
+  return c->hip(launch_loss(image, target, (size_t)n, d_image, c->d_acc + 3, loss, c->stream), "loss launch");
+}
+
+static lt_status backward_common(lt_ctx* c, const lt_trace_args* a, const lt_params* p, const float* d_image,
+                                 lt_grads* g, PassArgs& A) {
+  lt_status st = check_args(c, a, p);
+  if (st != LT_OK) return st;
+  if (!d_image || !g) return c->fail(LT_ERR_ARG, "null d_image or grads%s");
+  if (!g->albedo) return c->fail(LT_ERR_ARG, "grads->albedo is required%s");
+  if ((st = prepare_geometry(c, p)) != LT_OK) return st;
+  A = base_args(c, a, p);
+  A.dI = d_image;
+  A.g_albedo = g->albedo;
+  A.g_Le_acc = c->d_acc;
+  A.g_heights = g->heights;
+  if ((st = c->hip(launch_fill_f64(c->d_acc, 3, 0.0, c->stream), "acc clear")) != LT_OK) return st;
+  return c->hip(launch_fill_u32(c->d_counter, 1, 0u, c->stream), "counter clear");
+}
+
+lt_status lt_backward_naive(lt_ctx* c, const lt_trace_args* a, const lt_params* p, const float* d_image,
+                            const void* tape, size_t tape_bytes, lt_grads* g) {
+  if (!c) return LT_ERR_ARG;
+  if (a && !(a->flags & LT_RECORD_TAPE)) return c->fail(LT_ERR_ARG, "naive backward needs LT_RECORD_TAPE args%s");
+  PassArgs A;
+  lt_status st = backward_common(c, a, p, d_image, g, A);
+  if (st != LT_OK) return st;
+  SideLayout L = side_layout(a);
+  if (!tape || tape_bytes < L.total) return c->fail(LT_ERR_ARG, "tape buffer too small%s");
+  if ((st = check_cap(c, L.total)) != LT_OK) return st;
+  const char* sb = (const char*)tape;
+  A.tape_in = (const TapeRec*)(sb + L.tape);
+  A.tape_len_in = (const int32_t*)(sb + L.len);
+  int grid = (int)std::max<int64_t>(1, std::min<int64_t>((a->n_paths + 255) / 256, (int64_t)c->n_cu * 16));
+  if ((st = c->hip(launch_naive_bwd(A, grid, c->stream), "naive backward")) != LT_OK) return st;
+  return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
+}
+
+lt_status lt_backward_reslrb(lt_ctx* c, const lt_trace_args* a, const lt_params* p, const float* d_image,
+                             const void* records, size_t bytes, lt_grads* g) {
+  if (!c) return LT_ERR_ARG;
+  if (a && !(a->flags & LT_RECORD_RESERVOIR)) return c->fail(LT_ERR_ARG, "ResLRB backward needs LT_RECORD_RESERVOIR args%s");
+  PassArgs A;
+  lt_status st = backward_common(c, a, p, d_image, g, A);
+  if (st != LT_OK) return st;
+  SideLayout L = side_layout(a);
+  if (!records || bytes < L.total) return c->fail(LT_ERR_ARG, "reservoir buffer too small%s");
+  if ((st = check_cap(c, L.total)) != LT_OK) return st;
+  A.res_in = (const ResRec*)((const char*)records + L.res);
+  int grid = persistent_grid(c, a->n_paths, c->tune.block);
+  if ((st = c->hip(launch_reslrb_bwd(A, grid, c->tune.block, c->stream), "reslrb backward")) != LT_OK) return st;
+  return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
+}
+
+lt_status lt_backward_lrb3(lt_ctx* c, const lt_trace_args* a, const lt_params* p, const float* d_image,
+                           lt_grads* g) {
+  if (!c) return LT_ERR_ARG;
+  PassArgs A;
+  lt_status st = backward_common(c, a, p, d_image, g, A);
+  if (st != LT_OK) return st;
+  if ((st = check_cap(c, 0)) != LT_OK) return st;
+  int grid = persistent_grid(c, a->n_paths, c->tune.block);
+  if ((st = c->hip(launch_lrb3_bwd(A, grid, c->tune.block, c->stream), "lrb3 backward")) != LT_OK) return st;
+  return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
+}
+
+}  // extern "C"

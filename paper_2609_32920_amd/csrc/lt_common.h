@@ -1,0 +1,73 @@
+// Layouts shared by the host runtime and the gfx950 kernels.
+#pragma once
+#include <stdint.h>
+
+namespace lt {
+
+constexpr int kStackMax = 32;     // BVH traversal stack entries per lane (LDS)
+constexpr int kMaxDepth = 64;     // largest max_depth accepted
+constexpr float kEps = 1e-4f;     // ray-origin offset along the geometric normal
+constexpr float kTmin = 1e-4f;    // closest/any-hit lower bound
+
+// Two-child BVH node, 64 bytes: both child boxes arrive with one fetch.
+// count > 0: the child is a leaf holding `count` triangles from `child`;
+// count == 0: `child` is an inner node index; child < 0: empty.
+struct alignas(16) Node {
+  float lo0[3], hi0[3];
+  float lo1[3], hi1[3];
+  int32_t child0, child1, count0, count1;
+};
+static_assert(sizeof(Node) == 64, "node layout");
+
+// Triangle in BVH order, 48 bytes: first vertex, two edges, primitive id.
+struct alignas(16) Tri {
+  float p0[3]; int32_t prim;
+  float e1[3]; float pad1;
+  float e2[3]; float pad2;
+};
+static_assert(sizeof(Tri) == 48, "tri layout");
+
+// Naive-AD tape: one record per (vertex, path), vertex-major [D][N].
+// flags bits: 0..26 texel index, 27 lambert, 28 valid connection,
+// 29 scattered (beta_{j+1} = beta_j * rho_j), 30 dielectric.
+struct alignas(16) TapeRec {
+  uint32_t tf;
+  float g;           // connection factor: C_j = beta_j * rho_j * g
+  float ux, uy;      // film position u_j
+  float b[3];        // beta_j, throughput arriving at x_j
+  float pad;
+};
+static_assert(sizeof(TapeRec) == 32, "tape layout");
+constexpr uint32_t kTexMask = (1u << 27) - 1u;
+constexpr uint32_t kTfLambert = 1u << 27, kTfValid = 1u << 28, kTfScatter = 1u << 29,
+                   kTfDielectric = 1u << 30;
+
+// ResLRB per-path record (Sec. 4.2.1): selected depth R (0 = none), weight
+// Omega_k/omega_R, film position u_R and the reweighted splat S_hat.
+struct alignas(16) ResRec {
+  int32_t R; float W;
+  float ux, uy;
+  float S[3];
+  float pad;
+};
+static_assert(sizeof(ResRec) == 32, "reservoir record layout");
+
+struct DevScene {
+  const Node* nodes;
+  const Tri* tris;
+  const int32_t* prim_mat;   // [n_prims]
+  const float* prim_uv;      // [n_static][6]
+  const int32_t* mat_type;
+  const int32_t* mat_tex;
+  const float* mat_ior;
+  int32_t n_nodes, n_tris, n_static;
+  int32_t hf_G; float hf_x0, hf_z0, hf_dx, hf_base; int32_t hf_mat;
+  int32_t n_tex, tex_res;
+  int32_t em_type;
+  float em_o[3], em_e1[3], em_e2[3], em_n[3], em_area;
+  float cpos[3], cf[3], cr[3], cu[3];
+  float tan_half, aspect, film_area;
+  int32_t W, H;
+};
+
+}  // namespace lt

@@ -1,0 +1,439 @@
+// Device-side building blocks of the light tracer (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "lt_common.h"
+
+namespace lt {
+
+// Diagnostic event counters, compiled only into the LT_COUNTERS build:
+// 0 closest-hit rays, 1 shadow rays, 2 BVH node fetches, 3 triangle tests,
+// 4 film splats, 5 adjoint gathers, 6 gradient values scattered,
+// 7 paths emitted, 8 tape records written, 9 tape records read.
+#ifdef LT_COUNTERS
+__device__ unsigned long long lt_counters[16];
+#define LT_COUNT(k, v) atomicAdd(&lt_counters[k], (unsigned long long)(v))
+#else
+#define LT_COUNT(k, v) ((void)0)
+#endif
+
+// ------------------------------------------------------------ vector math
+struct f3 { float x, y, z; };
+__device__ __forceinline__ f3 mk(float x, float y, float z) { return {x, y, z}; }
+__device__ __forceinline__ f3 ld3(const float* p) { return {p[0], p[1], p[2]}; }
+__device__ __forceinline__ f3 operator+(f3 a, f3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ f3 operator-(f3 a, f3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ f3 operator*(f3 a, float s) { return {a.x * s, a.y * s, a.z * s}; }
+__device__ __forceinline__ f3 mul(f3 a, f3 b) { return {a.x * b.x, a.y * b.y, a.z * b.z}; }
+__device__ __forceinline__ float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ f3 cross(f3 a, f3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ f3 normalize(f3 a) { return a * (1.0f / sqrtf(dot(a, a))); }
+
+// ------------------------------------------------------------ Philox RNG
+// Philox-4x32-10 (Salmon et al., SC'11) keyed by the 64-bit seed with
+// counter (path, vertex, block, 0); outputs become 24-bit uniforms in [0,1).
+struct u4f { float u0, u1, u2, u3; };
+
+__device__ __forceinline__ u4f rng4(uint64_t seed, uint32_t path, uint32_t vtx, uint32_t block) {
+  uint32_t c0 = path, c1 = vtx, c2 = block, c3 = 0u;
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  const float s = 5.9604644775390625e-8f;  // 2^-24
+  return {(float)(c0 >> 8) * s, (float)(c1 >> 8) * s, (float)(c2 >> 8) * s, (float)(c3 >> 8) * s};
+}
+
+__device__ __forceinline__ uint32_t fnv1a(uint32_t h, uint32_t w) {
+#pragma unroll
+  for (int b = 0; b < 4; ++b) { h ^= (w >> (8 * b)) & 0xFFu; h *= 0x01000193u; }
+  return h;
+}
+
+// Orthonormal basis around unit n (Duff et al., JCGT 2017).
+__device__ __forceinline__ void onb(f3 n, f3& b1, f3& b2) {
+  float sign = copysignf(1.0f, n.z);
+  float a = -1.0f / (sign + n.z);
+  float b = n.x * n.y * a;
+  b1 = {1.0f + sign * n.x * n.x * a, sign * b, -sign * n.x};
+  b2 = {b, sign + n.y * n.y * a, -n.y};
+}
+
+// cosine-weighted direction about n (Malley's method) from (u0, u1)
+__device__ __forceinline__ f3 cosine_dir(f3 n, float u0, float u1) {
+  float r = sqrtf(u0), phi = 6.283185307179586f * u1;
+  float s = sinf(phi), c = cosf(phi);
+  f3 t1, t2; onb(n, t1, t2);
+  float lz = sqrtf(fmaxf(0.0f, 1.0f - u0));
+  return t1 * (r * c) + t2 * (r * s) + n * lz;
+}
+
+// ------------------------------------------------------------ BVH traversal
+struct Hit { int tri; float t; };
+
+__device__ __forceinline__ void load_node(const Node* nodes, int i, float4& a, float4& b, float4& c, int4& d) {
+  const float4* p = reinterpret_cast<const float4*>(nodes + i);
+  a = p[0]; b = p[1]; c = p[2];
+  d = reinterpret_cast<const int4*>(nodes + i)[3];
+}
+
+__device__ __forceinline__ bool slab(float lox, float loy, float loz, float hix, float hiy, float hiz,
+                                     f3 o, f3 inv, float tmin, float tmax, float& tn) {
+  float tx0 = (lox - o.x) * inv.x, tx1 = (hix - o.x) * inv.x;
+  float ty0 = (loy - o.y) * inv.y, ty1 = (hiy - o.y) * inv.y;
+  float tz0 = (loz - o.z) * inv.z, tz1 = (hiz - o.z) * inv.z;
+  float n = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), tmin));
+  float f = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tmax));
+  tn = n;
+  return n <= f;
+}
+
+// Moller-Trumbore with inclusive edges; returns t or -1.
+__device__ __forceinline__ float tri_t(const Tri* tris, int k, f3 o, f3 d, int& prim) {
+  const float4* p = reinterpret_cast<const float4*>(tris + k);
+  float4 A = p[0], B = p[1], C = p[2];
+  prim = __float_as_int(A.w);
+  LT_COUNT(3, 1);
+  f3 p0 = {A.x, A.y, A.z}, e1 = {B.x, B.y, B.z}, e2 = {C.x, C.y, C.z};
+  f3 pv = cross(d, e2);
+  float det = dot(e1, pv);
+  if (det == 0.0f) return -1.0f;
+  float inv = 1.0f / det;
+  f3 tv = o - p0;
+  float b1 = dot(tv, pv) * inv;
+  if (b1 < 0.0f || b1 > 1.0f) return -1.0f;
+  f3 q = cross(tv, e1);
+  float b2 = dot(d, q) * inv;
+  if (b2 < 0.0f || b1 + b2 > 1.0f) return -1.0f;
+  return dot(e2, q) * inv;
+}
+
+__device__ __forceinline__ f3 safe_inv(f3 d) {
+  return {1.0f / d.x, 1.0f / d.y, 1.0f / d.z};
+}
+
+// Closest hit with t in (tmin, tmax): smallest t, ties to the lower
+// primitive id.  `stk` is this lane's LDS stack slice (stride `ss`).
+__device__ __forceinline__ Hit closest_hit(const DevScene& sc, f3 o, f3 d, float tmin, float tmax,
+                                           int* stk, int ss) {
+  Hit h{-1, tmax};
+  int best_prim = 0x7fffffff;
+  if (sc.n_nodes == 0) return h;
+  LT_COUNT(0, 1);
+  f3 inv = safe_inv(d);
+  int sp = 0, node = 0;
+  while (true) {
+    float4 a, b, c; int4 e;
+    load_node(sc.nodes, node, a, b, c, e);
+    LT_COUNT(2, 1);
+    float tn0, tn1;
+    bool h0 = e.x >= 0 && slab(a.x, a.y, a.z, a.w, b.x, b.y, o, inv, tmin, h.t, tn0);
+    bool h1 = e.y >= 0 && slab(b.z, b.w, c.x, c.y, c.z, c.w, o, inv, tmin, h.t, tn1);
+    if (h0 && e.z > 0) {
+      for (int k = e.x; k < e.x + e.z; ++k) {
+        int prim; float t = tri_t(sc.tris, k, o, d, prim);
+        if (t > tmin && (t < h.t || (t == h.t && prim < best_prim))) { h.t = t; h.tri = k; best_prim = prim; }
+      }
+      h0 = false;
+    }
+    if (h1 && e.w > 0) {
+      for (int k = e.y; k < e.y + e.w; ++k) {
+        int prim; float t = tri_t(sc.tris, k, o, d, prim);
+        if (t > tmin && (t < h.t || (t == h.t && prim < best_prim))) { h.t = t; h.tri = k; best_prim = prim; }
+      }
+      h1 = false;
+    }
+    if (h0 && h1) {
+      int nearc = tn0 <= tn1 ? e.x : e.y, farc = tn0 <= tn1 ? e.y : e.x;
+      stk[sp * ss] = farc; ++sp;
+      node = nearc;
+    } else if (h0) {
+      node = e.x;
+    } else if (h1) {
+      node = e.y;
+    } else {
+      if (sp == 0) break;
+      --sp; node = stk[sp * ss];
+    }
+  }
+  return h;
+}
+
+// Any hit with t in (tmin, tmax).
+__device__ __forceinline__ bool any_hit(const DevScene& sc, f3 o, f3 d, float tmin, float tmax,
+                                        int* stk, int ss) {
+  if (sc.n_nodes == 0) return false;
+  LT_COUNT(1, 1);
+  f3 inv = safe_inv(d);
+  int sp = 0, node = 0;
+  while (true) {
+    float4 a, b, c; int4 e;
+    load_node(sc.nodes, node, a, b, c, e);
+    LT_COUNT(2, 1);
+    float tn0, tn1;
+    bool h0 = e.x >= 0 && slab(a.x, a.y, a.z, a.w, b.x, b.y, o, inv, tmin, tmax, tn0);
+    bool h1 = e.y >= 0 && slab(b.z, b.w, c.x, c.y, c.z, c.w, o, inv, tmin, tmax, tn1);
+    if (h0 && e.z > 0) {
+      for (int k = e.x; k < e.x + e.z; ++k) {
+        int prim; float t = tri_t(sc.tris, k, o, d, prim);
+        if (t > tmin && t < tmax) return true;
+      }
+      h0 = false;
+    }
+    if (h1 && e.w > 0) {
+      for (int k = e.y; k < e.y + e.w; ++k) {
+        int prim; float t = tri_t(sc.tris, k, o, d, prim);
+        if (t > tmin && t < tmax) return true;
+      }
+      h1 = false;
+    }
+    if (h0 && h1) {
+      stk[sp * ss] = e.y; ++sp;
+      node = e.x;
+    } else if (h0) {
+      node = e.x;
+    } else if (h1) {
+      node = e.y;
+    } else {
+      if (sp == 0) break;
+      --sp; node = stk[sp * ss];
+    }
+  }
+  return false;
+}
+
+// ------------------------------------------------------------ path pieces
+struct Ray { f3 x, w, offn; bool off; };
+
+// Vertex 0: position on the emitter and emitted direction; returns the
+// initial throughput factor (beta_0 = L_e * factor).
+__device__ __forceinline__ float emit(const DevScene& sc, uint64_t seed, uint32_t path, Ray& r) {
+  LT_COUNT(7, 1);
+  u4f u = rng4(seed, path, 0u, 0u);
+  if (sc.em_type == 0) {
+    f3 o = ld3(sc.em_o), e1 = ld3(sc.em_e1), e2 = ld3(sc.em_e2), ne = ld3(sc.em_n);
+    r.x = o + e1 * u.u0 + e2 * u.u1;
+    r.w = cosine_dir(ne, u.u2, u.u3);
+    r.offn = ne; r.off = true;
+    return sc.em_area * 3.14159265358979323846f;
+  }
+  r.x = ld3(sc.em_o);
+  float z = 1.0f - 2.0f * u.u2;
+  float rr = sqrtf(fmaxf(0.0f, 1.0f - z * z)), phi = 6.283185307179586f * u.u3;
+  r.w = {rr * cosf(phi), rr * sinf(phi), z};
+  r.offn = {0.f, 0.f, 0.f}; r.off = false;
+  return 4.0f * 3.14159265358979323846f;
+}
+
+__device__ __forceinline__ f3 ray_origin(const Ray& r) {
+  if (!r.off) return r.x;
+  return r.x + r.offn * (dot(r.w, r.offn) >= 0.0f ? kEps : -kEps);
+}
+
+// Hit point recomputed from the true origin on the hit triangle's plane,
+// with barycentrics and the unit geometric normal.
+struct Surf { f3 x, ng; float b1, b2; int prim; };
+
+__device__ __forceinline__ Surf surface(const DevScene& sc, int k, const Ray& r) {
+  const float4* p = reinterpret_cast<const float4*>(sc.tris + k);
+  float4 A = p[0], B = p[1], C = p[2];
+  f3 p0 = {A.x, A.y, A.z}, e1 = {B.x, B.y, B.z}, e2 = {C.x, C.y, C.z};
+  f3 N = cross(e1, e2);
+  float t = dot(p0 - r.x, N) / dot(r.w, N);
+  Surf s;
+  s.x = r.x + r.w * t;
+  float nn = dot(N, N);
+  f3 dx = s.x - p0;
+  s.b1 = dot(cross(dx, e2), N) / nn;
+  s.b2 = dot(cross(e1, dx), N) / nn;
+  s.ng = N * (1.0f / sqrtf(nn));
+  s.prim = __float_as_int(A.w);
+  return s;
+}
+
+__device__ __forceinline__ int texel_of(const DevScene& sc, const Surf& s, int tex) {
+  const int R = sc.tex_res;
+  float uvx = 0.f, uvy = 0.f;
+  if (s.prim < sc.n_static) {
+    const float* uv = sc.prim_uv + (size_t)s.prim * 6;
+    float c0 = 1.0f - s.b1 - s.b2;
+    uvx = c0 * uv[0] + s.b1 * uv[2] + s.b2 * uv[4];
+    uvy = c0 * uv[1] + s.b1 * uv[3] + s.b2 * uv[5];
+  }
+  int tx = (int)floorf(uvx * R), ty = (int)floorf(uvy * R);
+  tx = min(max(tx, 0), R - 1);
+  ty = min(max(ty, 0), R - 1);
+  return (tex * R + ty) * R + tx;
+}
+
+// Sensor connection geometry at a Lambertian vertex (Eq. 1 term i):
+// returns true with film position u and factor g (C = beta * rho * g) when
+// the camera sees x from the side the light arrived on, unoccluded.
+__device__ __forceinline__ bool connect(const DevScene& sc, const Surf& s, f3 w_in, float Kfilm,
+                                        float& ux, float& uy, float& g, int* stk, int ss) {
+  f3 cpos = ld3(sc.cpos);
+  f3 dv = s.x - cpos;
+  float zc = dot(dv, ld3(sc.cf));
+  if (!(zc > 0.0f)) return false;
+  float qx = dot(dv, ld3(sc.cr)) / zc, qy = dot(dv, ld3(sc.cu)) / zc;
+  ux = 0.5f * sc.W * (1.0f + qx / (sc.aspect * sc.tan_half));
+  uy = 0.5f * sc.H * (1.0f - qy / sc.tan_half);
+  if (!(ux >= 0.0f && ux < (float)sc.W && uy >= 0.0f && uy < (float)sc.H)) return false;
+  float dist2 = dot(dv, dv);
+  float dist = sqrtf(dist2);
+  f3 wc = dv * (-1.0f / dist);
+  float cg = dot(s.ng, wc);
+  float cos_in = dot(w_in, s.ng);
+  if (!(cg * (-cos_in) > 0.0f)) return false;
+  f3 so = s.x + s.ng * (cg >= 0.0f ? kEps : -kEps);
+  f3 sd = cpos - so;
+  float sl = sqrtf(dot(sd, sd));
+  sd = sd * (1.0f / sl);
+  if (any_hit(sc, so, sd, kTmin, sl * (1.0f - 1e-4f), stk, ss)) return false;
+  float cosc = zc / dist;
+  float cosx = fabsf(dot(s.ng, dv)) / dist;
+  g = 0.31830988618379067f * Kfilm * cosx / (cosc * cosc * cosc * dist2);
+  return true;
+}
+
+// Tent reconstruction filter of radius one pixel: the four taps around u
+// with weights F(u, p), taps outside the film dropped (weight 0).
+struct Taps { int idx[4]; float w[4]; };
+
+__device__ __forceinline__ Taps tent_taps(const DevScene& sc, float ux, float uy) {
+  Taps t;
+  float fx = ux - 0.5f, fy = uy - 0.5f;
+  int px0 = (int)floorf(fx), py0 = (int)floorf(fy);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int px = px0 + (q & 1), py = py0 + (q >> 1);
+    float wx = 1.0f - fabsf(ux - ((float)px + 0.5f));
+    float wy = 1.0f - fabsf(uy - ((float)py + 0.5f));
+    bool in = px >= 0 && px < sc.W && py >= 0 && py < sc.H;
+    t.idx[q] = in ? (py * sc.W + px) * 3 : -1;
+    t.w[q] = in ? wx * wy : 0.0f;
+  }
+  return t;
+}
+
+__device__ __forceinline__ void splat(const DevScene& sc, float* image, float ux, float uy, f3 C) {
+  LT_COUNT(4, 1);
+  Taps t = tent_taps(sc, ux, uy);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (t.idx[q] < 0) continue;
+    float* p = image + t.idx[q];
+    atomicAdd(p + 0, t.w[q] * C.x);
+    atomicAdd(p + 1, t.w[q] * C.y);
+    atomicAdd(p + 2, t.w[q] * C.z);
+  }
+}
+
+// Filter-matched adjoint read: sum over taps of F(u, p) dI[p].
+__device__ __forceinline__ f3 gather(const DevScene& sc, const float* dI, float ux, float uy) {
+  LT_COUNT(5, 1);
+  Taps t = tent_taps(sc, ux, uy);
+  f3 a = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (t.idx[q] < 0) continue;
+    const float* p = dI + t.idx[q];
+    a = a + mk(p[0], p[1], p[2]) * t.w[q];
+  }
+  return a;
+}
+
+// Dielectric lobe choice and direction (weight 1): unpolarized Fresnel with
+// the shading normal ns (unit, same side as ng); the path ends when
+// cos_i <= 0 against the shading normal or the new direction falls on the
+// wrong side of the geometric normal.
+// Return value: 0 ok, 7 cos_i <= 0, 8 wrong side.
+__device__ __forceinline__ int dielectric(f3 w_in, f3 ng, f3 ns, float ior, float u_lobe, f3& wo,
+                                          bool& reflect) {
+  float cos_g = dot(w_in, ng);
+  bool entering = cos_g < 0.0f;
+  float eta = entering ? 1.0f / ior : ior;
+  f3 n = entering ? ns : ns * -1.0f;
+  float cosi = -dot(w_in, n);
+  if (!(cosi > 0.0f)) { reflect = false; return 7; }
+  float sin2t = eta * eta * (1.0f - cosi * cosi);
+  float F, cost = 0.0f;
+  if (sin2t >= 1.0f) F = 1.0f;
+  else {
+    cost = sqrtf(1.0f - sin2t);
+    float ei = entering ? 1.0f : ior, et = entering ? ior : 1.0f;
+    float rs = (ei * cosi - et * cost) / (ei * cosi + et * cost);
+    float rp = (et * cosi - ei * cost) / (et * cosi + ei * cost);
+    F = 0.5f * (rs * rs + rp * rp);
+  }
+  reflect = u_lobe < F;
+  if (reflect) wo = w_in + n * (2.0f * cosi);
+  else wo = w_in * eta + n * (eta * cosi - cost);
+  float side_in = -cos_g, s_out = dot(wo, ng);
+  if (reflect ? (s_out * side_in <= 0.0f) : (s_out * side_in >= 0.0f)) return 8;
+  return 0;
+}
+
+// Heightfield shading normal: barycentric blend of the corners'
+// central-difference slopes, n = normalize(-Sx, 1, -Sz).
+__device__ __forceinline__ float hget(const float* h, int G, int i, int j) { return h ? h[j * G + i] : 0.0f; }
+
+__device__ __forceinline__ void hf_corner(int G, int local, int k, int& gi, int& gj) {
+  int cell = local >> 1, half = local & 1;
+  int ci = cell % (G - 1), cj = cell / (G - 1);
+  // half 0: (A, C, B); half 1: (A, D, C)
+  int oi = half == 0 ? (k == 0 ? 0 : 1) : (k == 2 ? 1 : 0);
+  int oj = half == 0 ? (k == 1 ? 1 : 0) : (k == 0 ? 0 : 1);
+  gi = ci + oi; gj = cj + oj;
+}
+
+__device__ __forceinline__ void hf_slope(const float* h, int G, float dx, int i, int j, float& sx, float& sz) {
+  int a = max(i - 1, 0), b = min(i + 1, G - 1);
+  sx = (hget(h, G, b, j) - hget(h, G, a, j)) / ((float)(b - a) * dx);
+  int c = max(j - 1, 0), d = min(j + 1, G - 1);
+  sz = (hget(h, G, i, d) - hget(h, G, i, c)) / ((float)(d - c) * dx);
+}
+
+__device__ __forceinline__ f3 hf_shading_normal(const DevScene& sc, const float* h, const Surf& s) {
+  int local = s.prim - sc.n_static;
+  float Sx = 0.f, Sz = 0.f;
+  float wts[3] = {1.0f - s.b1 - s.b2, s.b1, s.b2};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    int gi, gj; hf_corner(sc.hf_G, local, k, gi, gj);
+    float sx, sz; hf_slope(h, sc.hf_G, sc.hf_dx, gi, gj, sx, sz);
+    Sx += wts[k] * sx; Sz += wts[k] * sz;
+  }
+  return normalize(mk(-Sx, 1.0f, -Sz));
+}
+
+// ------------------------------------------------------------ wave helpers
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  return (1ull << __lane_id()) - 1ull;
+}
+
+// Wave-aggregated work fetch: every lane with `need` set gets the next
+// unused path index (one atomic per wave).
+__device__ __forceinline__ uint32_t fetch_paths(unsigned int* counter, bool need) {
+  uint64_t m = __ballot(need);
+  unsigned int base = 0;
+  int leader = __ffsll((unsigned long long)m) - 1;
+  if (m && __lane_id() == leader) base = atomicAdd(counter, (unsigned int)__popcll(m));
+  base = __shfl(base, leader < 0 ? 0 : leader);
+  return base + (uint32_t)__popcll(m & lanemask_lt());
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+}  // namespace lt

@@ -1,0 +1,514 @@
+// gfx950 kernels of the light tracer and its three reverse modes.
+//
+// Every pass is a persistent kernel: each wave keeps all 64 lanes busy by
+// fetching new path indices (one atomic per wave) as soon as lanes finish
+// their path, so paths of uneven length do not idle the SIMD.  All path
+// state lives in registers; the BVH traversal stack lives in LDS.
+#include <hip/hip_runtime.h>
+#include "lt_device.h"
+#include "lt_launch.h"
+
+namespace lt {
+
+// One vertex of a light path: closest hit, material dispatch, sensor
+// connection geometry and the sampling of the next direction.
+struct Event {
+  int prim;        // hit primitive, -1 on a miss
+  int kind;        // 0 path ended at this hit (miss/absorber), 1 Lambertian, 2 dielectric
+  int texel;       // Lambertian texel
+  f3 rho;          // Lambertian albedo
+  bool valid;      // sensor connection exists
+  float ux, uy, g; // film position and connection factor (C = beta rho g)
+  float cos_in;
+  int lobe, fail;  // dielectric: lobe 2 reflect / 4 refract, fail 7/8
+  bool cont;       // the path continues with the updated ray
+  float u_res;     // reservoir uniform of this vertex
+};
+
+__device__ __forceinline__ Event bounce(const PassArgs& A, uint32_t path, int j, Ray& r, bool want_connect,
+                                        int* stk, int ss) {
+  const DevScene& sc = A.sc;
+  Event ev;
+  ev.prim = -1; ev.kind = 0; ev.texel = -1; ev.rho = {0.f, 0.f, 0.f}; ev.valid = false;
+  ev.ux = ev.uy = ev.g = 0.f; ev.lobe = 0; ev.fail = 0; ev.cont = false; ev.u_res = 1.0f; ev.cos_in = 0.f;
+  Hit h = closest_hit(sc, ray_origin(r), r.w, kTmin, 3.0e38f, stk, ss);
+  if (h.tri < 0) return ev;
+  Surf s = surface(sc, h.tri, r);
+  ev.prim = s.prim;
+  int mat = sc.prim_mat[s.prim];
+  int mt = sc.mat_type[mat];
+  if (mt == 0) return ev;
+  ev.cos_in = dot(r.w, s.ng);
+  u4f u = (mt == 1 || j < A.D) ? rng4(A.seed, path, (uint32_t)j, 0u) : u4f{0.f, 0.f, 0.f, 1.f};
+  ev.u_res = u.u3;
+  if (mt == 1) {
+    ev.kind = 1;
+    ev.texel = texel_of(sc, s, sc.mat_tex[mat]);
+    ev.rho = ld3(A.albedo + (size_t)ev.texel * 3);
+    if (want_connect) ev.valid = connect(sc, s, r.w, A.Kfilm, ev.ux, ev.uy, ev.g, stk, ss);
+    if (j < A.D) {
+      f3 na = ev.cos_in < 0.0f ? s.ng : s.ng * -1.0f;
+      r.w = cosine_dir(na, u.u0, u.u1);
+      r.x = s.x; r.offn = s.ng; r.off = true;
+      ev.cont = true;
+    }
+    return ev;
+  }
+  ev.kind = 2;
+  if (j >= A.D) return ev;
+  f3 ns = s.ng;
+  if (s.prim >= sc.n_static) ns = hf_shading_normal(sc, A.heights, s);
+  f3 wo; bool refl;
+  int code = dielectric(r.w, s.ng, ns, sc.mat_ior[mat], u.u2, wo, refl);
+  if (code == 7) { ev.fail = 7; return ev; }
+  ev.lobe = refl ? 2 : 4;
+  if (code == 8) { ev.fail = 8; return ev; }
+  r.w = wo; r.x = s.x; r.offn = s.ng; r.off = true;
+  ev.cont = true;
+  return ev;
+}
+
+__device__ __forceinline__ uint32_t sig_event(uint32_t h, const Event& ev) {
+  if (ev.prim < 0) return fnv1a(h, 0u);
+  h = fnv1a(h, (uint32_t)ev.prim + 1u);
+  if (ev.kind == 1) {
+    h = fnv1a(h, (uint32_t)ev.texel + 1u);
+    h = fnv1a(h, ev.valid ? 1u : 0u);
+  } else if (ev.kind == 2) {
+    if (ev.fail == 7) return fnv1a(h, 7u);
+    if (ev.lobe) h = fnv1a(h, (uint32_t)ev.lobe);
+    if (ev.fail == 8) h = fnv1a(h, 8u);
+  }
+  return h;
+}
+
+// Fetch the next unmasked path for every lane that needs one.  Paths
+// skipped by the mask get their per-path outputs cleared by `on_skip`.
+template <typename Skip>
+__device__ __forceinline__ void refill(const PassArgs& A, bool& alive, bool& exhausted, uint32_t& path,
+                                       Skip on_skip) {
+  while (true) {
+    bool need = !alive && !exhausted;
+    if (__ballot(need) == 0ull) break;
+    uint32_t p = fetch_paths(A.counter, need);
+    if (need) {
+      if (p >= (uint32_t)A.n_paths) exhausted = true;
+      else if (A.mask && A.mask[p] == 0) on_skip(p);
+      else { alive = true; path = p; }
+    }
+  }
+}
+
+__device__ __forceinline__ void flush_le(const PassArgs& A, double g0, double g1, double g2) {
+  g0 = wave_sum(g0); g1 = wave_sum(g1); g2 = wave_sum(g2);
+  if (__lane_id() == 0 && A.g_Le_acc) {
+    if (g0 != 0.0) atomicAdd(A.g_Le_acc + 0, g0);
+    if (g1 != 0.0) atomicAdd(A.g_Le_acc + 1, g1);
+    if (g2 != 0.0) atomicAdd(A.g_Le_acc + 2, g2);
+  }
+}
+
+// ---------------------------------------------------------------- forward
+// Light tracing with a connection + splat at every Lambertian vertex
+// (Eq. 1-2, Eq. 20).  RESV: streams valid connections through a capacity-1
+// weighted reservoir (Eq. 8) and records/splats the selection (Eq. 9).
+// TAPE: writes the per-vertex naive-AD tape.
+template <bool TAPE, bool RESV>
+__global__ void __launch_bounds__(1024) k_trace(PassArgs A) {
+  extern __shared__ int lds[];
+  int* stk = lds + threadIdx.x;
+  const int ss = blockDim.x;
+  const bool selected = (A.flags & 2u) != 0;
+  bool alive = false, exhausted = false;
+  uint32_t path = 0, sig = 0;
+  int j = 0, nrec = 0;
+  Ray r;
+  f3 beta = {0.f, 0.f, 0.f};
+  float Om = 0.f, omR = 0.f, uxR = 0.f, uyR = 0.f;
+  int R = 0;
+  f3 CR = {0.f, 0.f, 0.f};
+  const f3 Le = ld3(A.Le);
+  while (true) {
+    refill(A, alive, exhausted, path, [&](uint32_t p) {
+      if (TAPE) A.tape_len[p] = 0;
+      if (RESV && A.res) { ResRec z{}; A.res[p] = z; }
+      if (A.sig) A.sig[p] = 0u;
+    });
+    if (__ballot(alive) == 0ull) break;
+    if (!alive) continue;
+    if (j == 0) {  // new path: vertex 0 on the emitter
+      float f = emit(A.sc, A.seed, path, r);
+      beta = Le * f;
+      j = 1; nrec = 0; sig = 0x811C9DC5u;
+      Om = 0.f; omR = 0.f; R = 0;
+    }
+    Event ev = bounce(A, path, j, r, true, stk, ss);
+    if (A.sig) sig = sig_event(sig, ev);
+    if (ev.kind == 1 && ev.valid) {
+      f3 C = mul(beta, ev.rho) * ev.g;
+      if (!selected) splat(A.sc, A.image, ev.ux, ev.uy, C);
+      if (RESV) {
+        float om = 0.2126f * C.x + 0.7152f * C.y + 0.0722f * C.z;
+        if (om > 0.0f) {
+          Om += om;
+          if (ev.u_res < om / Om) { R = j; omR = om; uxR = ev.ux; uyR = ev.uy; CR = C; }
+        }
+      }
+    }
+    if (TAPE && ev.kind != 0) {
+      TapeRec t;
+      if (ev.kind == 1) {
+        t.tf = (uint32_t)ev.texel | kTfLambert | (ev.valid ? kTfValid : 0u) | (ev.cont ? kTfScatter : 0u);
+      } else {
+        t.tf = kTfDielectric;
+      }
+      t.g = ev.g; t.ux = ev.ux; t.uy = ev.uy;
+      t.b[0] = beta.x; t.b[1] = beta.y; t.b[2] = beta.z; t.pad = 0.f;
+      A.tape[(size_t)(j - 1) * (size_t)A.n_paths + path] = t;
+      LT_COUNT(8, 1);
+      ++nrec;
+    }
+    if (ev.kind == 1 && ev.cont) beta = mul(beta, ev.rho);
+    if (ev.cont) { ++j; continue; }
+    // path finished
+    float W = R > 0 ? Om / omR : 0.f;
+    if (RESV && selected && R > 0) splat(A.sc, A.image, uxR, uyR, CR * W);
+    if (RESV && A.res) {
+      ResRec rr;
+      rr.R = R; rr.W = W; rr.ux = uxR; rr.uy = uyR;
+      rr.S[0] = CR.x * W; rr.S[1] = CR.y * W; rr.S[2] = CR.z * W; rr.pad = 0.f;
+      A.res[path] = rr;
+    }
+    if (TAPE) A.tape_len[path] = nrec;
+    if (A.sig) A.sig[path] = fnv1a(sig, (uint32_t)R);
+    alive = false; j = 0;
+  }
+}
+
+// ---------------------------------------------------------------- naive AD
+// Reverse sweep over the tape, exact chain rule (no inverses, no division):
+//   C_j = beta_j rho_j g_j,  beta_{j+1} = beta_j rho_j (Lambertian scatter),
+//   beta_1 = L_e * emit_factor.
+__global__ void __launch_bounds__(256) k_naive_bwd(PassArgs A) {
+  const size_t N = (size_t)A.n_paths;
+  double gl0 = 0.0, gl1 = 0.0, gl2 = 0.0;
+  for (size_t path = (size_t)blockIdx.x * blockDim.x + threadIdx.x; path < N;
+       path += (size_t)gridDim.x * blockDim.x) {
+    if (A.mask && A.mask[path] == 0) continue;
+    int k = min(max(A.tape_len_in[path], 0), A.D);
+    f3 bb = {0.f, 0.f, 0.f};  // adjoint of beta_{j+1}
+    for (int j = k; j >= 1; --j) {
+      TapeRec t = A.tape_in[(size_t)(j - 1) * N + path];
+      LT_COUNT(9, 1);
+      if (!(t.tf & kTfLambert)) continue;  // dielectric: weight 1, adjoint passes through
+      int texel = min((int)(t.tf & kTexMask), A.n_texels - 1);
+      f3 rho = ld3(A.albedo + (size_t)texel * 3);
+      f3 b = {t.b[0], t.b[1], t.b[2]};
+      f3 gr = {0.f, 0.f, 0.f}, bj = {0.f, 0.f, 0.f};
+      if (t.tf & kTfValid) {
+        f3 Lb = gather(A.sc, A.dI, t.ux, t.uy);
+        gr = mul(Lb, b) * t.g;
+        bj = mul(Lb, rho) * t.g;
+      }
+      if (t.tf & kTfScatter) {
+        gr = gr + mul(bb, b);
+        bj = bj + mul(bb, rho);
+      }
+      float* gp = A.g_albedo + (size_t)texel * 3;
+      LT_COUNT(6, 3);
+      if (gr.x != 0.f) atomicAdd(gp + 0, gr.x);
+      if (gr.y != 0.f) atomicAdd(gp + 1, gr.y);
+      if (gr.z != 0.f) atomicAdd(gp + 2, gr.z);
+      bb = bj;
+    }
+    gl0 += (double)bb.x * A.emit_factor;
+    gl1 += (double)bb.y * A.emit_factor;
+    gl2 += (double)bb.z * A.emit_factor;
+  }
+  flush_le(A, gl0, gl1, gl2);
+}
+
+// ---------------------------------------------------------------- ResLRB
+// Replay each path up to its selected depth R and apply the log-derivative
+// identity with weight w = dI(u_R) * S_hat (Eq. 11): the emitter factor
+// gets w / L_e, every Lambertian factor rho_j (j < R scatter, j = R
+// connection) gets w / rho_j.  No connection is re-evaluated.
+__global__ void __launch_bounds__(1024) k_reslrb_bwd(PassArgs A) {
+  extern __shared__ int lds[];
+  int* stk = lds + threadIdx.x;
+  const int ss = blockDim.x;
+  bool alive = false, exhausted = false;
+  uint32_t path = 0;
+  int j = 0, R = 0;
+  Ray r;
+  f3 w = {0.f, 0.f, 0.f};
+  const f3 Le = ld3(A.Le);
+  double gl0 = 0.0, gl1 = 0.0, gl2 = 0.0;
+  while (true) {
+    refill(A, alive, exhausted, path, [&](uint32_t) {});
+    if (__ballot(alive) == 0ull) break;
+    if (!alive) continue;
+    if (j == 0) {
+      ResRec rec = A.res_in[path];
+      if (rec.R <= 0) { alive = false; continue; }
+      R = min(rec.R, A.D);
+      f3 Lb = gather(A.sc, A.dI, rec.ux, rec.uy);
+      w = mul(Lb, mk(rec.S[0], rec.S[1], rec.S[2]));
+      if (Le.x > 0.f) gl0 += (double)w.x / Le.x;
+      if (Le.y > 0.f) gl1 += (double)w.y / Le.y;
+      if (Le.z > 0.f) gl2 += (double)w.z / Le.z;
+      emit(A.sc, A.seed, path, r);
+      j = 1;
+    }
+    Event ev = bounce(A, path, j, r, false, stk, ss);
+    if (ev.kind == 1) {
+      float* gp = A.g_albedo + (size_t)ev.texel * 3;
+      LT_COUNT(6, 3);
+      if (w.x != 0.f && ev.rho.x > 0.f) atomicAdd(gp + 0, w.x / ev.rho.x);
+      if (w.y != 0.f && ev.rho.y > 0.f) atomicAdd(gp + 1, w.y / ev.rho.y);
+      if (w.z != 0.f && ev.rho.z > 0.f) atomicAdd(gp + 2, w.z / ev.rho.z);
+    }
+    if (ev.cont && j < R) { ++j; continue; }
+    alive = false; j = 0;
+  }
+  flush_le(A, gl0, gl1, gl2);
+}
+
+// ---------------------------------------------------------------- LRB-3
+// Pass 2 and Pass 3 fused per path (dI is read-only between them):
+// phase 2 replays and accumulates delta_total = sum_i dI(u_i) * C_i
+// (Eq. 14, FP64); phase 3 replays again: the splat term dI(u_i) * C_i / rho_i
+// (Eq. 15), the subtraction delta_rem -= dI(u_i) * C_i (Eq. 16) and the
+// log-derivative delta_rem / rho_i of the scatter factor (Eq. 17); the
+// emitter gets delta_total / L_e.
+__global__ void __launch_bounds__(1024) k_lrb3_bwd(PassArgs A) {
+  extern __shared__ int lds[];
+  int* stk = lds + threadIdx.x;
+  const int ss = blockDim.x;
+  bool alive = false, exhausted = false;
+  uint32_t path = 0;
+  int j = 0, phase = 2;
+  Ray r;
+  f3 beta = {0.f, 0.f, 0.f};
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0;  // delta_total, then delta_rem
+  const f3 Le = ld3(A.Le);
+  double gl0 = 0.0, gl1 = 0.0, gl2 = 0.0;
+  while (true) {
+    refill(A, alive, exhausted, path, [&](uint32_t) {});
+    if (__ballot(alive) == 0ull) break;
+    if (!alive) continue;
+    if (j == 0) {
+      float f = emit(A.sc, A.seed, path, r);
+      beta = Le * f;
+      j = 1;
+      if (phase == 2) { d0 = d1 = d2 = 0.0; }
+    }
+    Event ev = bounce(A, path, j, r, true, stk, ss);
+    if (ev.kind == 1) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+      if (ev.valid) {
+        f3 C = mul(beta, ev.rho) * ev.g;
+        f3 Lb = gather(A.sc, A.dI, ev.ux, ev.uy);
+        a0 = (double)Lb.x * C.x; a1 = (double)Lb.y * C.y; a2 = (double)Lb.z * C.z;
+      }
+      if (phase == 2) {
+        d0 += a0; d1 += a1; d2 += a2;
+      } else {
+        d0 -= a0; d1 -= a1; d2 -= a2;
+        double g0 = a0, g1 = a1, g2 = a2;
+        if (ev.cont) { g0 += d0; g1 += d1; g2 += d2; }
+        float* gp = A.g_albedo + (size_t)ev.texel * 3;
+        LT_COUNT(6, 3);
+        if (g0 != 0.0 && ev.rho.x > 0.f) atomicAdd(gp + 0, (float)(g0 / ev.rho.x));
+        if (g1 != 0.0 && ev.rho.y > 0.f) atomicAdd(gp + 1, (float)(g1 / ev.rho.y));
+        if (g2 != 0.0 && ev.rho.z > 0.f) atomicAdd(gp + 2, (float)(g2 / ev.rho.z));
+      }
+      if (ev.cont) beta = mul(beta, ev.rho);
+    }
+    if (ev.cont) { ++j; continue; }
+    // end of a replay
+    if (phase == 2 && (d0 != 0.0 || d1 != 0.0 || d2 != 0.0)) {
+      if (Le.x > 0.f) gl0 += d0 / Le.x;
+      if (Le.y > 0.f) gl1 += d1 / Le.y;
+      if (Le.z > 0.f) gl2 += d2 / Le.z;
+      phase = 3; j = 0;
+      continue;
+    }
+    phase = 2; j = 0; alive = false;
+  }
+  flush_le(A, gl0, gl1, gl2);
+}
+
+// ---------------------------------------------------------------- small kernels
+__global__ void k_fill_f32(float* p, size_t n, float v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_u32(unsigned int* p, size_t n, unsigned int v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_f64(double* p, size_t n, double v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_add_f64_to_f32(const double* src, float* dst, int n) {
+  int i = threadIdx.x;
+  if (i < n && dst) dst[i] += (float)src[i];
+}
+
+__global__ void __launch_bounds__(256) k_loss(const float* I, const float* T, size_t n, float* dI, double* acc) {
+  double s = 0.0;
+  const double inv = 1.0 / (double)n;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    double d = (double)I[i] - (double)T[i];
+    s += d * d;
+    dI[i] = (float)(2.0 * d * inv);
+  }
+  s = wave_sum(s);
+  __shared__ double part[16];
+  int wv = threadIdx.x >> 6;
+  if (__lane_id() == 0) part[wv] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += part[k];
+    atomicAdd(acc, t);
+  }
+}
+__global__ void k_loss_finish(const double* acc, size_t n, float* loss) { loss[0] = (float)(acc[0] / (double)n); }
+
+// Heightfield triangles from the current heights, written at their BVH slots.
+__global__ void k_hf_tris(DevScene sc, const int32_t* slot_of_prim, Tri* tris, const float* h) {
+  int nhf = 2 * (sc.hf_G - 1) * (sc.hf_G - 1);
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nhf) return;
+  f3 P[3];
+  for (int k = 0; k < 3; ++k) {
+    int gi, gj; hf_corner(sc.hf_G, q, k, gi, gj);
+    P[k] = mk(sc.hf_x0 + gi * sc.hf_dx, sc.hf_base + hget(h, sc.hf_G, gi, gj), sc.hf_z0 + gj * sc.hf_dx);
+  }
+  Tri t;
+  t.p0[0] = P[0].x; t.p0[1] = P[0].y; t.p0[2] = P[0].z; t.prim = sc.n_static + q;
+  f3 e1 = P[1] - P[0], e2 = P[2] - P[0];
+  t.e1[0] = e1.x; t.e1[1] = e1.y; t.e1[2] = e1.z; t.pad1 = 0.f;
+  t.e2[0] = e2.x; t.e2[1] = e2.y; t.e2[2] = e2.z; t.pad2 = 0.f;
+  tris[slot_of_prim[sc.n_static + q]] = t;
+}
+
+__device__ __forceinline__ void tri_box(const Tri& t, float* lo, float* hi) {
+  for (int a = 0; a < 3; ++a) {
+    float v0 = t.p0[a], v1 = t.p0[a] + t.e1[a], v2 = t.p0[a] + t.e2[a];
+    lo[a] = fminf(lo[a], fminf(v0, fminf(v1, v2)));
+    hi[a] = fmaxf(hi[a], fmaxf(v0, fmaxf(v1, v2)));
+  }
+}
+
+__device__ __forceinline__ void child_box(const Node* nodes, const Tri* tris, int child, int count, float* lo, float* hi) {
+  for (int a = 0; a < 3; ++a) { lo[a] = 3.0e38f; hi[a] = -3.0e38f; }
+  if (child < 0) return;
+  if (count > 0) {
+    for (int k = child; k < child + count; ++k) tri_box(tris[k], lo, hi);
+  } else {
+    const Node& n = nodes[child];
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fminf(n.lo0[a], n.lo1[a]);
+      hi[a] = fmaxf(n.hi0[a], n.hi1[a]);
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    float pad = 1e-5f + 1e-6f * fmaxf(fabsf(lo[a]), fabsf(hi[a]));
+    lo[a] -= pad; hi[a] += pad;
+  }
+}
+
+// Bottom-up refit of one tree level (children are always deeper).
+__global__ void k_refit_level(Node* nodes, const Tri* tris, const int32_t* level_nodes, int n) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  Node& nd = nodes[level_nodes[q]];
+  float lo[3], hi[3];
+  child_box(nodes, tris, nd.child0, nd.count0, lo, hi);
+  for (int a = 0; a < 3; ++a) { nd.lo0[a] = lo[a]; nd.hi0[a] = hi[a]; }
+  child_box(nodes, tris, nd.child1, nd.count1, lo, hi);
+  for (int a = 0; a < 3; ++a) { nd.lo1[a] = lo[a]; nd.hi1[a] = hi[a]; }
+}
+
+// ---------------------------------------------------------------- launchers
+static size_t stack_bytes(int block) { return (size_t)kStackMax * block * sizeof(int); }
+
+hipError_t read_counters(uint64_t* out, bool reset, hipStream_t s) {
+#ifdef LT_COUNTERS
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyFromSymbol(out, HIP_SYMBOL(lt_counters), 16 * sizeof(uint64_t), 0, hipMemcpyDeviceToHost);
+  if (e != hipSuccess || !reset) return e;
+  uint64_t z[16] = {0};
+  return hipMemcpyToSymbol(HIP_SYMBOL(lt_counters), z, sizeof(z), 0, hipMemcpyHostToDevice);
+#else
+  (void)out; (void)reset; (void)s;
+  return hipErrorNotSupported;
+#endif
+}
+
+hipError_t launch_trace(const PassArgs& A, bool tape, bool resv, int grid, int block, hipStream_t s) {
+  size_t sh = stack_bytes(block);
+  if (tape && resv) hipLaunchKernelGGL((k_trace<true, true>), dim3(grid), dim3(block), sh, s, A);
+  else if (tape) hipLaunchKernelGGL((k_trace<true, false>), dim3(grid), dim3(block), sh, s, A);
+  else if (resv) hipLaunchKernelGGL((k_trace<false, true>), dim3(grid), dim3(block), sh, s, A);
+  else hipLaunchKernelGGL((k_trace<false, false>), dim3(grid), dim3(block), sh, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_naive_bwd(const PassArgs& A, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_naive_bwd, dim3(grid), dim3(256), 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_reslrb_bwd(const PassArgs& A, int grid, int block, hipStream_t s) {
+  hipLaunchKernelGGL(k_reslrb_bwd, dim3(grid), dim3(block), stack_bytes(block), s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_lrb3_bwd(const PassArgs& A, int grid, int block, hipStream_t s) {
+  hipLaunchKernelGGL(k_lrb3_bwd, dim3(grid), dim3(block), stack_bytes(block), s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  int grid = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u32(unsigned int* p, size_t n, unsigned int v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  int grid = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  int grid = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_fill_f64, dim3(grid), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_add_le(const double* acc, float* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_f64_to_f32, dim3(1), dim3(64), 0, s, acc, dst, 3);
+  return hipGetLastError();
+}
+hipError_t launch_loss(const float* I, const float* T, size_t n, float* dI, double* acc, float* loss, hipStream_t s) {
+  int grid = (int)((n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048);
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_loss, dim3(grid), dim3(256), 0, s, I, T, n, dI, acc);
+  hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(1), 0, s, acc, n, loss);
+  return hipGetLastError();
+}
+hipError_t launch_hf_tris(const DevScene& sc, const int32_t* slot_of_prim, Tri* tris, const float* h, hipStream_t s) {
+  int nhf = 2 * (sc.hf_G - 1) * (sc.hf_G - 1);
+  hipLaunchKernelGGL(k_hf_tris, dim3((nhf + 255) / 256), dim3(256), 0, s, sc, slot_of_prim, tris, h);
+  return hipGetLastError();
+}
+hipError_t launch_refit_level(Node* nodes, const Tri* tris, const int32_t* level_nodes, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_refit_level, dim3((n + 127) / 128), dim3(128), 0, s, nodes, tris, level_nodes, n);
+  return hipGetLastError();
+}
+
+}  // namespace lt

@@ -1,0 +1,350 @@
+"""Python binding of the HIP light-tracing library (liblt.so).
+
+Argument marshalling only: every step of the path runs in the library's
+gfx950 kernels.  PyTorch provides device memory and the stream.  The
+binding refuses to run when the library is missing; there is no CPU
+fallback.
+
+The functions carry the C ABI's names (include/lt.h):
+  lt_create / lt_scene_upload / lt_trace / lt_loss_l2 /
+  lt_backward_naive / lt_backward_reslrb / lt_backward_lrb3
+and ``LightTrace`` wraps forward + a chosen reverse mode as a
+``torch.autograd.Function``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblt.so")
+# diagnostic build with event counters (byte model of the roofline only)
+COUNTERS_LIB_PATH = os.path.join(_HERE, "liblt_counters.so")
+
+LT_OK, LT_ERR_ARG, LT_ERR_OOM, LT_ERR_HIP, LT_ERR_STATE, LT_ERR_UNSUPPORTED = range(6)
+ATTACHED, SPLAT_SELECTED, RECORD_TAPE, RECORD_RESERVOIR = 1, 2, 4, 8
+_STATUS = {1: "LT_ERR_ARG", 2: "LT_ERR_OOM", 3: "LT_ERR_HIP", 4: "LT_ERR_STATE", 5: "LT_ERR_UNSUPPORTED"}
+
+
+class LTError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [
+        ("n_tris", C.c_int32), ("tri_v", C.POINTER(C.c_double)), ("tri_uv", C.POINTER(C.c_double)),
+        ("tri_mat", C.POINTER(C.c_int32)),
+        ("n_mats", C.c_int32), ("mat_type", C.POINTER(C.c_int32)), ("mat_tex", C.POINTER(C.c_int32)),
+        ("mat_ior", C.POINTER(C.c_double)),
+        ("n_tex", C.c_int32), ("tex_res", C.c_int32),
+        ("em_type", C.c_int32), ("em_o", C.c_double * 3), ("em_e1", C.c_double * 3), ("em_e2", C.c_double * 3),
+        ("cam_pos", C.c_double * 3), ("cam_target", C.c_double * 3), ("cam_up", C.c_double * 3),
+        ("cam_fov_deg", C.c_double), ("width", C.c_int32), ("height", C.c_int32),
+        ("hf_G", C.c_int32), ("hf_x0", C.c_double), ("hf_z0", C.c_double), ("hf_dx", C.c_double),
+        ("hf_base", C.c_double), ("hf_mat", C.c_int32),
+    ]
+
+
+class TraceArgs(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("n_paths", C.c_int64), ("max_depth", C.c_int32),
+                ("flags", C.c_uint32), ("path_mask", C.c_void_p), ("path_sig", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("albedo", C.c_void_p), ("emitter_L", C.c_void_p), ("heights", C.c_void_p)]
+
+
+class Grads(C.Structure):
+    _fields_ = [("albedo", C.c_void_p), ("emitter_L", C.c_void_p), ("heights", C.c_void_p)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32), ("lds_grad", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("guard_triggers", C.c_uint64), ("nonfinite", C.c_uint64)]
+
+
+_libs = {}
+
+
+def library(path=LIB_PATH):
+    """Load liblt.so (raises if it has not been built)."""
+    if path not in _libs:
+        if not os.path.exists(path):
+            raise RuntimeError(f"HIP library not built: {path} (run __graft_entry__.build())")
+        lib = C.CDLL(path)
+        vp = C.c_void_p
+        sig = {
+            "lt_create": ([C.c_int, vp, C.POINTER(vp)], C.c_int),
+            "lt_destroy": ([vp], None),
+            "lt_last_error": ([vp], C.c_char_p),
+            "lt_set_stream": ([vp, vp], C.c_int),
+            "lt_set_tuning": ([vp, C.POINTER(Tuning)], C.c_int),
+            "lt_get_tuning": ([vp, C.POINTER(Tuning)], C.c_int),
+            "lt_set_memory_cap": ([vp, C.c_uint64], C.c_int),
+            "lt_get_stats": ([vp, C.POINTER(Stats)], C.c_int),
+            "lt_read_counters": ([vp, C.POINTER(C.c_uint64), C.c_int], C.c_int),
+            "lt_scene_upload": ([vp, C.POINTER(SceneDesc)], C.c_int),
+            "lt_side_state_bytes": ([vp, C.POINTER(TraceArgs)], C.c_size_t),
+            "lt_workspace_bytes": ([vp, C.POINTER(TraceArgs)], C.c_size_t),
+            "lt_trace": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp, vp, C.c_size_t], C.c_int),
+            "lt_loss_l2": ([vp, vp, vp, C.c_int64, vp, vp], C.c_int),
+            "lt_backward_naive": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp, vp, C.c_size_t,
+                                   C.POINTER(Grads)], C.c_int),
+            "lt_backward_reslrb": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp, vp, C.c_size_t,
+                                    C.POINTER(Grads)], C.c_int),
+            "lt_backward_lrb3": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp, C.POINTER(Grads)], C.c_int),
+        }
+        for name, (argt, rest) in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = argt
+            fn.restype = rest
+        _libs[path] = lib
+    return _libs[path]
+
+
+def exported_symbols():
+    return ["lt_create", "lt_destroy", "lt_last_error", "lt_set_stream", "lt_set_tuning", "lt_get_tuning",
+            "lt_set_memory_cap", "lt_get_stats", "lt_read_counters", "lt_scene_upload", "lt_side_state_bytes",
+            "lt_workspace_bytes", "lt_trace", "lt_loss_l2", "lt_backward_naive", "lt_backward_reslrb",
+            "lt_backward_lrb3"]
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev_f32(x, device):
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=torch.float32).contiguous()
+    return torch.as_tensor(np.asarray(x, np.float32), device=device).contiguous()
+
+
+class Context:
+    """One library context bound to a device; calls run on torch's current
+    stream of that device."""
+
+    def __init__(self, device=0, counters=False):
+        self.lib = library(COUNTERS_LIB_PATH if counters else LIB_PATH)
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        h = C.c_void_p()
+        st = self.lib.lt_create(self.device.index or 0, None, C.byref(h))
+        if st != LT_OK:
+            raise LTError(st, "lt_create failed")
+        self.h = h
+        self.scene = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                self.lib.lt_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != LT_OK:
+            raise LTError(st, self.lib.lt_last_error(self.h).decode())
+
+    def _stream(self):
+        s = torch.cuda.current_stream(self.device)
+        self._check(self.lib.lt_set_stream(self.h, C.c_void_p(s.cuda_stream)))
+
+    def set_tuning(self, block=256, blocks_per_cu=8, lds_grad=0):
+        t = Tuning(block, blocks_per_cu, lds_grad)
+        self._check(self.lib.lt_set_tuning(self.h, C.byref(t)))
+
+    def get_tuning(self):
+        t = Tuning()
+        self._check(self.lib.lt_get_tuning(self.h, C.byref(t)))
+        return dict(block=t.block, blocks_per_cu=t.blocks_per_cu, lds_grad=t.lds_grad)
+
+    def read_counters(self, reset=True):
+        """Event counts of the LT_COUNTERS build (see lt_read_counters)."""
+        out = (C.c_uint64 * 16)()
+        self._check(self.lib.lt_read_counters(self.h, out, int(reset)))
+        names = ["rays", "shadow_rays", "nodes", "tris", "splats", "gathers", "grad_values", "paths",
+                 "tape_written", "tape_read"]
+        return {k: int(out[i]) for i, k in enumerate(names)}
+
+    def set_memory_cap(self, nbytes):
+        self._check(self.lib.lt_set_memory_cap(self.h, int(nbytes)))
+
+    def stats(self):
+        s = Stats()
+        self._check(self.lib.lt_get_stats(self.h, C.byref(s)))
+        return dict(guard_triggers=s.guard_triggers, nonfinite=s.nonfinite)
+
+    # ------------------------------------------------------------ scene
+    def scene_upload(self, sc):
+        keep = []
+
+        def f64(a):
+            a = np.ascontiguousarray(a, np.float64)
+            keep.append(a)
+            return a.ctypes.data_as(C.POINTER(C.c_double))
+
+        def i32(a):
+            a = np.ascontiguousarray(a, np.int32)
+            keep.append(a)
+            return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+        d = SceneDesc()
+        d.n_tris = int(np.asarray(sc["tri_v"]).shape[0])
+        d.tri_v, d.tri_uv, d.tri_mat = f64(sc["tri_v"]), f64(sc["tri_uv"]), i32(sc["tri_mat"])
+        d.n_mats = int(len(sc["mat_type"]))
+        d.mat_type, d.mat_tex, d.mat_ior = i32(sc["mat_type"]), i32(sc["mat_tex"]), f64(sc["mat_ior"])
+        d.n_tex, d.tex_res = int(sc["n_tex"]), int(sc["tex_res"])
+        em = sc["emitter"]
+        d.em_type = int(em["type"])
+        cam = sc["camera"]
+        for k in range(3):
+            d.em_o[k], d.em_e1[k], d.em_e2[k] = float(em["o"][k]), float(em["e1"][k]), float(em["e2"][k])
+            d.cam_pos[k], d.cam_target[k], d.cam_up[k] = (float(cam["pos"][k]), float(cam["target"][k]),
+                                                          float(cam["up"][k]))
+        d.cam_fov_deg = float(cam["fov_deg"])
+        d.width, d.height = int(cam["width"]), int(cam["height"])
+        hf = sc.get("hf")
+        if hf is not None:
+            d.hf_G, d.hf_x0, d.hf_z0 = int(hf["G"]), float(hf["x0"]), float(hf["z0"])
+            d.hf_dx, d.hf_base, d.hf_mat = float(hf["dx"]), float(hf["base"]), int(hf["mat"])
+        self._stream()
+        self._check(self.lib.lt_scene_upload(self.h, C.byref(d)))
+        self.scene = sc
+        self.W, self.H = d.width, d.height
+        return self
+
+    # ------------------------------------------------------------ passes
+    def args(self, seed, n_paths, depth, flags=0, mask=None, sig=None):
+        a = TraceArgs()
+        a.seed, a.n_paths, a.max_depth, a.flags = int(seed), int(n_paths), int(depth), int(flags)
+        a.path_mask = None if mask is None else mask.data_ptr()
+        a.path_sig = None if sig is None else sig.data_ptr()
+        return a
+
+    def params(self, albedo, Le, heights=None):
+        return Params(albedo.data_ptr(), Le.data_ptr(), None if heights is None else heights.data_ptr())
+
+    def side_state_bytes(self, a):
+        return int(self.lib.lt_side_state_bytes(self.h, C.byref(a)))
+
+    def workspace_bytes(self, a):
+        return int(self.lib.lt_workspace_bytes(self.h, C.byref(a)))
+
+    def trace(self, a, p, image, side=None):
+        self._stream()
+        nb = 0 if side is None else side.numel() * side.element_size()
+        self._check(self.lib.lt_trace(self.h, C.byref(a), C.byref(p), _ptr(image), _ptr(side), nb))
+
+    def loss_l2(self, image, target, d_image, loss):
+        self._stream()
+        self._check(self.lib.lt_loss_l2(self.h, _ptr(image), _ptr(target), image.numel(), _ptr(d_image),
+                                        _ptr(loss)))
+
+    def _grads(self, g_albedo, g_Le, g_heights):
+        return Grads(None if g_albedo is None else g_albedo.data_ptr(),
+                     None if g_Le is None else g_Le.data_ptr(),
+                     None if g_heights is None else g_heights.data_ptr())
+
+    def backward_naive(self, a, p, d_image, tape, g_albedo, g_Le, g_heights=None):
+        self._stream()
+        g = self._grads(g_albedo, g_Le, g_heights)
+        nb = tape.numel() * tape.element_size()
+        self._check(self.lib.lt_backward_naive(self.h, C.byref(a), C.byref(p), _ptr(d_image), _ptr(tape), nb,
+                                               C.byref(g)))
+
+    def backward_reslrb(self, a, p, d_image, records, g_albedo, g_Le, g_heights=None):
+        self._stream()
+        g = self._grads(g_albedo, g_Le, g_heights)
+        nb = records.numel() * records.element_size()
+        self._check(self.lib.lt_backward_reslrb(self.h, C.byref(a), C.byref(p), _ptr(d_image), _ptr(records),
+                                                nb, C.byref(g)))
+
+    def backward_lrb3(self, a, p, d_image, g_albedo, g_Le, g_heights=None):
+        self._stream()
+        g = self._grads(g_albedo, g_Le, g_heights)
+        self._check(self.lib.lt_backward_lrb3(self.h, C.byref(a), C.byref(p), _ptr(d_image), C.byref(g)))
+
+
+# C-ABI names as module-level functions -------------------------------------
+def lt_create(device=0):
+    return Context(device)
+
+
+def lt_scene_upload(ctx, scene):
+    return ctx.scene_upload(scene)
+
+
+def lt_trace(ctx, args, params, image, side=None):
+    return ctx.trace(args, params, image, side)
+
+
+def lt_loss_l2(ctx, image, target, d_image, loss):
+    return ctx.loss_l2(image, target, d_image, loss)
+
+
+def lt_backward_naive(ctx, args, params, d_image, tape, g_albedo, g_Le, g_heights=None):
+    return ctx.backward_naive(args, params, d_image, tape, g_albedo, g_Le, g_heights)
+
+
+def lt_backward_reslrb(ctx, args, params, d_image, records, g_albedo, g_Le, g_heights=None):
+    return ctx.backward_reslrb(args, params, d_image, records, g_albedo, g_Le, g_heights)
+
+
+def lt_backward_lrb3(ctx, args, params, d_image, g_albedo, g_Le, g_heights=None):
+    return ctx.backward_lrb3(args, params, d_image, g_albedo, g_Le, g_heights)
+
+
+# ------------------------------------------------------------ autograd
+MODES = ("naive", "reslrb", "lrb3")
+
+
+class LightTrace(torch.autograd.Function):
+    """image = LightTrace.apply(albedo, Le, heights, ctx, seed, n_paths, depth, mode, flags)
+
+    Forward runs lt_trace (recording the tape for "naive" or the reservoir
+    records for "reslrb"); backward runs the matching lt_backward_* with the
+    incoming image adjoint.  Seed replay is the recomputation: "lrb3" keeps
+    no side state at all.
+    """
+
+    @staticmethod
+    def forward(fctx, albedo, Le, heights, ctx, seed, n_paths, depth, mode="lrb3", flags=0):
+        if mode not in MODES:
+            raise ValueError(mode)
+        rec = RECORD_TAPE if mode == "naive" else RECORD_RESERVOIR if mode == "reslrb" else 0
+        a = ctx.args(seed, n_paths, depth, flags | rec)
+        p = ctx.params(albedo, Le, heights)
+        nb = ctx.side_state_bytes(a)
+        side = torch.empty(max(nb, 1), dtype=torch.uint8, device=albedo.device) if nb else None
+        image = torch.empty((ctx.H, ctx.W, 3), dtype=torch.float32, device=albedo.device)
+        ctx.trace(a, p, image, side)
+        fctx.lt = (ctx, seed, n_paths, depth, mode, flags | rec, side)
+        fctx.save_for_backward(albedo, Le, heights if heights is not None else torch.empty(0, device=albedo.device))
+        return image
+
+    @staticmethod
+    def backward(fctx, grad_image):
+        ctx, seed, n_paths, depth, mode, flags, side = fctx.lt
+        albedo, Le, heights = fctx.saved_tensors
+        heights = heights if heights.numel() else None
+        a = ctx.args(seed, n_paths, depth, flags)
+        p = ctx.params(albedo, Le, heights)
+        dI = grad_image.to(torch.float32).contiguous()
+        g_alb = torch.zeros_like(albedo)
+        g_le = torch.zeros_like(Le)
+        g_h = torch.zeros_like(heights) if heights is not None else None
+        if mode == "naive":
+            ctx.backward_naive(a, p, dI, side, g_alb, g_le, g_h)
+        elif mode == "reslrb":
+            ctx.backward_reslrb(a, p, dI, side, g_alb, g_le, g_h)
+        else:
+            ctx.backward_lrb3(a, p, dI, g_alb, g_le, g_h)
+        return g_alb, g_le, g_h, None, None, None, None, None, None
