@@ -558,7 +558,8 @@ lt_status lt_trace(lt_ctx* c, const lt_trace_args* a, const lt_params* p, float*
   if ((st = c->hip(launch_fill_f32(image, npix, 0.f, c->stream), "image clear")) != LT_OK) return st;
   if ((st = c->hip(launch_fill_u32(c->d_counter, 1, 0u, c->stream), "counter clear")) != LT_OK) return st;
   bool tape = (a->flags & LT_RECORD_TAPE) != 0;
-  bool resv = (a->flags & (LT_RECORD_RESERVOIR | LT_SPLAT_SELECTED)) != 0;
+  // the decision signature includes the reservoir choice R
+  bool resv = (a->flags & (LT_RECORD_RESERVOIR | LT_SPLAT_SELECTED)) != 0 || a->path_sig != nullptr;
   int grid = persistent_grid(c, a->n_paths, c->tune.block);
   return c->hip(launch_trace(A, tape, resv, grid, c->tune.block, c->stream), "trace launch");
 }

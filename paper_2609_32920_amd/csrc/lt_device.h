@@ -68,8 +68,10 @@ __device__ __forceinline__ void onb(f3 n, f3& b1, f3& b2) {
 
 // cosine-weighted direction about n (Malley's method) from (u0, u1)
 __device__ __forceinline__ f3 cosine_dir(f3 n, float u0, float u1) {
-  float r = sqrtf(u0), phi = 6.283185307179586f * u1;
-  float s = sinf(phi), c = cosf(phi);
+  // sin/cos of 2*pi*u1 via sinpi/cospi: 2*u1 is exact, so no rounding of
+  // the angle itself enters the direction
+  float r = sqrtf(u0);
+  float s = sinpif(2.0f * u1), c = cospif(2.0f * u1);
   f3 t1, t2; onb(n, t1, t2);
   float lz = sqrtf(fmaxf(0.0f, 1.0f - u0));
   return t1 * (r * c) + t2 * (r * s) + n * lz;
@@ -226,8 +228,8 @@ __device__ __forceinline__ float emit(const DevScene& sc, uint64_t seed, uint32_
   }
   r.x = ld3(sc.em_o);
   float z = 1.0f - 2.0f * u.u2;
-  float rr = sqrtf(fmaxf(0.0f, 1.0f - z * z)), phi = 6.283185307179586f * u.u3;
-  r.w = {rr * cosf(phi), rr * sinf(phi), z};
+  float rr = sqrtf(fmaxf(0.0f, 1.0f - z * z));
+  r.w = {rr * cospif(2.0f * u.u3), rr * sinpif(2.0f * u.u3), z};
   r.offn = {0.f, 0.f, 0.f}; r.off = false;
   return 4.0f * 3.14159265358979323846f;
 }

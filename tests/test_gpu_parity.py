@@ -129,8 +129,19 @@ def test_emitter_identity_full_size():
 
 def test_full_size_sampled_paths():
     # 256x256 box, depth 32, 4M paths: a seeded sample of 4096 paths is kept
-    # by the path mask at full N and compared with the oracle on those paths
+    # by the path mask at full N and compared with the oracle on those paths.
+    #
+    # Tolerance from the FP32 arithmetic: each bounce moves the FP32 vertex
+    # by up to ~c*u*L (unit roundoff u = 2^-24, scene scale L ~ 1, c ~ 4 for
+    # the hit-point and direction evaluation); over k bounces that is
+    # k*c*u*L, and the camera maps it to at most W / (2 a tan(fov/2) z_min)
+    # ~ 250 px per unit here.  The tent weight changes by the same number of
+    # pixels, so a splat may differ by ~2 * 250 * 32 * 4 * 6e-8 ~ 4e-3 of its
+    # own value at depth 32 (1e-4 at the 64x64 / depth-4 configuration).
+    # The brightest pixels come from shallow vertices, so 2e-3 of the image
+    # maximum bounds the comparison with margin.
     from tests.gpu_common import GpuRun, maxrel
+    TOL_DEEP = 2e-3
     sc = scenes.box_scene(width=256, height=256)
     g = GpuRun(sc)
     n, D, seed = 1 << 22, 32, 91
@@ -145,13 +156,16 @@ def test_full_size_sampled_paths():
     mask[keep] = 1
     gi = g.trace(seed, n, D, mask=mask)["image"]
     oi = O.render(sc, seed, n, D, path_list=keep)["image"]
-    assert maxrel(gi, oi) <= TOL
+    e = maxrel(gi, oi)
+    print(f"full-size sampled image maxrel {e:.2e}", flush=True)
+    assert e <= TOL_DEEP
     dI = _dI(gi.shape, 2)
     on = O.gradient(sc, seed, n, D, dI, path_list=keep)
     for mode in ("naive", "lrb3"):
         gg = g.backward(mode, seed, n, D, dI, mask=mask)
-        assert maxrel(gg["albedo"], on["albedo"]) <= TOL, mode
-        assert maxrel(gg["Le"], on["Le"]) <= TOL, mode
+        ea, el = maxrel(gg["albedo"], on["albedo"]), maxrel(gg["Le"], on["Le"])
+        print(f"full-size sampled {mode}: albedo {ea:.2e} Le {el:.2e}", flush=True)
+        assert ea <= TOL_DEEP and el <= TOL_DEEP, mode
 
 
 def test_memory_cap_rejects_naive_tape_before_launch():
@@ -203,8 +217,9 @@ def test_autograd_function_matches_direct_calls(box64):
 def test_loss_kernel(box64):
     sc, g = box64
     rng = np.random.default_rng(0)
-    I = rng.uniform(size=(64, 64, 3))
-    T = rng.uniform(size=(64, 64, 3))
+    # the kernel sees FP32 inputs: the reference starts from the same values
+    I = rng.uniform(size=(64, 64, 3)).astype(np.float32).astype(np.float64)
+    T = rng.uniform(size=(64, 64, 3)).astype(np.float32).astype(np.float64)
     L, dI = O.loss_and_adjoint(I, T)
     It = torch.as_tensor(I, dtype=torch.float32, device=g.dev)
     Tt = torch.as_tensor(T, dtype=torch.float32, device=g.dev)
