@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true", help="skip the per-method / per-depth sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-paths", type=int, default=1 << 15)
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for profiler byte counters)")
     return ap.parse_args()
 
 
@@ -78,6 +80,13 @@ def main():
         ctx.backward_lrb3(a, p, dI, g_alb, g_le)
         if ev: ev[3].record(stream)
 
+    if args.copy_ref:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for k in range(args.warmup):
         step(1000 + k)
     torch.cuda.synchronize()

@@ -278,8 +278,11 @@ __device__ __forceinline__ int texel_of(const DevScene& sc, const Surf& s, int t
 // Sensor connection geometry at a Lambertian vertex (Eq. 1 term i):
 // returns true with film position u and factor g (C = beta * rho * g) when
 // the camera sees x from the side the light arrived on, unoccluded.
+// visible = true: the caller already knows the shadow ray is unoccluded
+// (a replay of a connection found valid earlier); the test is skipped.
 __device__ __forceinline__ bool connect(const DevScene& sc, const Surf& s, f3 w_in, float Kfilm,
-                                        float& ux, float& uy, float& g, int* stk, int ss) {
+                                        float& ux, float& uy, float& g, int* stk, int ss,
+                                        bool visible = false) {
   f3 cpos = ld3(sc.cpos);
   f3 dv = s.x - cpos;
   float zc = dot(dv, ld3(sc.cf));
@@ -298,7 +301,7 @@ __device__ __forceinline__ bool connect(const DevScene& sc, const Surf& s, f3 w_
   f3 sd = cpos - so;
   float sl = sqrtf(dot(sd, sd));
   sd = sd * (1.0f / sl);
-  if (any_hit(sc, so, sd, kTmin, sl * (1.0f - 1e-4f), stk, ss)) return false;
+  if (!visible && any_hit(sc, so, sd, kTmin, sl * (1.0f - 1e-4f), stk, ss)) return false;
   float cosc = zc / dist;
   float cosx = fabsf(dot(s.ng, dv)) / dist;
   g = 0.31830988618379067f * Kfilm * cosx / (cosc * cosc * cosc * dist2);
@@ -335,6 +338,62 @@ __device__ __forceinline__ void splat(const DevScene& sc, float* image, float ux
     atomicAdd(p + 0, t.w[q] * C.x);
     atomicAdd(p + 1, t.w[q] * C.y);
     atomicAdd(p + 2, t.w[q] * C.z);
+  }
+}
+
+// Wave-cooperative tent splat.  Float atomics to device memory are
+// executed past the L2, so their cost scales with the number of distinct
+// cache lines an instruction touches.  The lanes holding a splat are
+// processed five at a time: lane l adds value l%12 (2 rows x 2 taps x RGB)
+// of splat l/12, so each atomic instruction covers five splats' contiguous
+// tap rows instead of 64 unrelated addresses.  Must be called by all lanes
+// of the wave (has = false for lanes without a splat).
+__device__ __forceinline__ void splat_wave(const DevScene& sc, float* image, bool has, float ux, float uy, f3 C) {
+  uint64_t m = __ballot(has);
+  if (m == 0ull) return;
+  LT_COUNT(4, has ? 1 : 0);
+  int px0 = (int)floorf(ux - 0.5f), py0 = (int)floorf(uy - 0.5f);
+  const int lane = __lane_id();
+  const int slot = lane / 12, v = lane - slot * 12;
+  const int row = v / 6, k = v - row * 6, tx = k / 3, ch = k - tx * 3;
+  while (m) {
+    uint64_t mm = m;
+    for (int i = 0; i < slot && mm; ++i) mm &= mm - 1ull;
+    int src = mm ? (__ffsll((unsigned long long)mm) - 1) : 0;
+    bool act = mm != 0ull && slot < 5;
+    int spx = __shfl(px0, src), spy = __shfl(py0, src);
+    float sux = __shfl(ux, src), suy = __shfl(uy, src);
+    float c0 = __shfl(C.x, src), c1 = __shfl(C.y, src), c2 = __shfl(C.z, src);
+    int px = spx + tx, py = spy + row;
+    if (act && px >= 0 && px < sc.W && py >= 0 && py < sc.H) {
+      float wx = 1.0f - fabsf(sux - ((float)px + 0.5f));
+      float wy = 1.0f - fabsf(suy - ((float)py + 0.5f));
+      float c = ch == 0 ? c0 : (ch == 1 ? c1 : c2);
+      atomicAdd(image + (py * sc.W + px) * 3 + ch, wx * wy * c);
+    }
+    for (int i = 0; i < 5 && m; ++i) m &= m - 1ull;
+  }
+}
+
+// Wave-cooperative add of RGB triplets: every lane with `has` adds v to
+// dst[3*idx .. 3*idx+2]; 21 triplets per atomic instruction, zero values
+// skipped.  Must be called by all lanes of the wave.
+__device__ __forceinline__ void scatter3_wave(float* dst, bool has, int idx, f3 v) {
+  uint64_t m = __ballot(has);
+  if (m == 0ull) return;
+  LT_COUNT(6, has ? 3 : 0);
+  const int lane = __lane_id();
+  const int slot = lane / 3, ch = lane - slot * 3;
+  while (m) {
+    uint64_t mm = m;
+    for (int i = 0; i < slot && mm; ++i) mm &= mm - 1ull;
+    int src = mm ? (__ffsll((unsigned long long)mm) - 1) : 0;
+    bool act = mm != 0ull && slot < 21;
+    int sidx = __shfl(idx, src);
+    float c0 = __shfl(v.x, src), c1 = __shfl(v.y, src), c2 = __shfl(v.z, src);
+    float c = ch == 0 ? c0 : (ch == 1 ? c1 : c2);
+    if (act && c != 0.0f) atomicAdd(dst + (size_t)sidx * 3 + ch, c);
+    for (int i = 0; i < 21 && m; ++i) m &= m - 1ull;
   }
 }
 

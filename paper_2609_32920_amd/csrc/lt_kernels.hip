@@ -25,7 +25,9 @@ struct Event {
   float u_res;     // reservoir uniform of this vertex
 };
 
-__device__ __forceinline__ Event bounce(const PassArgs& A, uint32_t path, int j, Ray& r, bool want_connect,
+// cmode: 0 no sensor connection, 1 full connection test (with shadow
+// ray), 2 connection geometry only (known visible from an earlier replay).
+__device__ __forceinline__ Event bounce(const PassArgs& A, uint32_t path, int j, Ray& r, int cmode,
                                         int* stk, int ss) {
   const DevScene& sc = A.sc;
   Event ev;
@@ -45,7 +47,7 @@ __device__ __forceinline__ Event bounce(const PassArgs& A, uint32_t path, int j,
     ev.kind = 1;
     ev.texel = texel_of(sc, s, sc.mat_tex[mat]);
     ev.rho = ld3(A.albedo + (size_t)ev.texel * 3);
-    if (want_connect) ev.valid = connect(sc, s, r.w, A.Kfilm, ev.ux, ev.uy, ev.g, stk, ss);
+    if (cmode) ev.valid = connect(sc, s, r.w, A.Kfilm, ev.ux, ev.uy, ev.g, stk, ss, cmode == 2);
     if (j < A.D) {
       f3 na = ev.cos_in < 0.0f ? s.ng : s.ng * -1.0f;
       r.w = cosine_dir(na, u.u0, u.u1);
@@ -112,7 +114,9 @@ __device__ __forceinline__ void flush_le(const PassArgs& A, double g0, double g1
 // Light tracing with a connection + splat at every Lambertian vertex
 // (Eq. 1-2, Eq. 20).  RESV: streams valid connections through a capacity-1
 // weighted reservoir (Eq. 8) and records/splats the selection (Eq. 9).
-// TAPE: writes the per-vertex naive-AD tape.
+// TAPE: writes the per-vertex naive-AD tape.  Each loop iteration advances
+// every live lane by one vertex; the splat is issued cooperatively by the
+// whole wave after the step.
 template <bool TAPE, bool RESV>
 __global__ void __launch_bounds__(1024) k_trace(PassArgs A) {
   extern __shared__ int lds[];
@@ -135,53 +139,59 @@ __global__ void __launch_bounds__(1024) k_trace(PassArgs A) {
       if (A.sig) A.sig[p] = 0u;
     });
     if (__ballot(alive) == 0ull) break;
-    if (!alive) continue;
-    if (j == 0) {  // new path: vertex 0 on the emitter
-      float f = emit(A.sc, A.seed, path, r);
-      beta = Le * f;
-      j = 1; nrec = 0; sig = 0x811C9DC5u;
-      Om = 0.f; omR = 0.f; R = 0;
-    }
-    Event ev = bounce(A, path, j, r, true, stk, ss);
-    if (A.sig) sig = sig_event(sig, ev);
-    if (ev.kind == 1 && ev.valid) {
-      f3 C = mul(beta, ev.rho) * ev.g;
-      if (!selected) splat(A.sc, A.image, ev.ux, ev.uy, C);
-      if (RESV) {
-        float om = 0.2126f * C.x + 0.7152f * C.y + 0.0722f * C.z;
-        if (om > 0.0f) {
-          Om += om;
-          if (ev.u_res < om / Om) { R = j; omR = om; uxR = ev.ux; uyR = ev.uy; CR = C; }
+    bool has = false;
+    float sux = 0.f, suy = 0.f;
+    f3 sC = {0.f, 0.f, 0.f};
+    if (alive) {
+      if (j == 0) {  // new path: vertex 0 on the emitter
+        float f = emit(A.sc, A.seed, path, r);
+        beta = Le * f;
+        j = 1; nrec = 0; sig = 0x811C9DC5u;
+        Om = 0.f; omR = 0.f; R = 0;
+      }
+      Event ev = bounce(A, path, j, r, 1, stk, ss);
+      if (A.sig) sig = sig_event(sig, ev);
+      if (ev.kind == 1 && ev.valid) {
+        f3 C = mul(beta, ev.rho) * ev.g;
+        if (!selected) { has = true; sux = ev.ux; suy = ev.uy; sC = C; }
+        if (RESV) {
+          float om = 0.2126f * C.x + 0.7152f * C.y + 0.0722f * C.z;
+          if (om > 0.0f) {
+            Om += om;
+            if (ev.u_res < om / Om) { R = j; omR = om; uxR = ev.ux; uyR = ev.uy; CR = C; }
+          }
         }
       }
-    }
-    if (TAPE && ev.kind != 0) {
-      TapeRec t;
-      if (ev.kind == 1) {
-        t.tf = (uint32_t)ev.texel | kTfLambert | (ev.valid ? kTfValid : 0u) | (ev.cont ? kTfScatter : 0u);
-      } else {
-        t.tf = kTfDielectric;
+      if (TAPE && ev.kind != 0) {
+        TapeRec t;
+        if (ev.kind == 1)
+          t.tf = (uint32_t)ev.texel | kTfLambert | (ev.valid ? kTfValid : 0u) | (ev.cont ? kTfScatter : 0u);
+        else
+          t.tf = kTfDielectric;
+        t.g = ev.g; t.ux = ev.ux; t.uy = ev.uy;
+        t.b[0] = beta.x; t.b[1] = beta.y; t.b[2] = beta.z; t.pad = 0.f;
+        A.tape[(size_t)(j - 1) * (size_t)A.n_paths + path] = t;
+        LT_COUNT(8, 1);
+        ++nrec;
       }
-      t.g = ev.g; t.ux = ev.ux; t.uy = ev.uy;
-      t.b[0] = beta.x; t.b[1] = beta.y; t.b[2] = beta.z; t.pad = 0.f;
-      A.tape[(size_t)(j - 1) * (size_t)A.n_paths + path] = t;
-      LT_COUNT(8, 1);
-      ++nrec;
+      if (ev.kind == 1 && ev.cont) beta = mul(beta, ev.rho);
+      if (ev.cont) {
+        ++j;
+      } else {  // path finished
+        float W = R > 0 ? Om / omR : 0.f;
+        if (RESV && selected && R > 0) { has = true; sux = uxR; suy = uyR; sC = CR * W; }
+        if (RESV && A.res) {
+          ResRec rr;
+          rr.R = R; rr.W = W; rr.ux = uxR; rr.uy = uyR;
+          rr.S[0] = CR.x * W; rr.S[1] = CR.y * W; rr.S[2] = CR.z * W; rr.pad = 0.f;
+          A.res[path] = rr;
+        }
+        if (TAPE) A.tape_len[path] = nrec;
+        if (A.sig) A.sig[path] = fnv1a(sig, (uint32_t)R);
+        alive = false; j = 0;
+      }
     }
-    if (ev.kind == 1 && ev.cont) beta = mul(beta, ev.rho);
-    if (ev.cont) { ++j; continue; }
-    // path finished
-    float W = R > 0 ? Om / omR : 0.f;
-    if (RESV && selected && R > 0) splat(A.sc, A.image, uxR, uyR, CR * W);
-    if (RESV && A.res) {
-      ResRec rr;
-      rr.R = R; rr.W = W; rr.ux = uxR; rr.uy = uyR;
-      rr.S[0] = CR.x * W; rr.S[1] = CR.y * W; rr.S[2] = CR.z * W; rr.pad = 0.f;
-      A.res[path] = rr;
-    }
-    if (TAPE) A.tape_len[path] = nrec;
-    if (A.sig) A.sig[path] = fnv1a(sig, (uint32_t)R);
-    alive = false; j = 0;
+    splat_wave(A.sc, A.image, has, sux, suy, sC);
   }
 }
 
@@ -189,41 +199,54 @@ __global__ void __launch_bounds__(1024) k_trace(PassArgs A) {
 // Reverse sweep over the tape, exact chain rule (no inverses, no division):
 //   C_j = beta_j rho_j g_j,  beta_{j+1} = beta_j rho_j (Lambertian scatter),
 //   beta_1 = L_e * emit_factor.
+// Lanes of a wave walk their tapes in lock step so that the texel
+// gradients are scattered cooperatively.
 __global__ void __launch_bounds__(256) k_naive_bwd(PassArgs A) {
   const size_t N = (size_t)A.n_paths;
   double gl0 = 0.0, gl1 = 0.0, gl2 = 0.0;
-  for (size_t path = (size_t)blockIdx.x * blockDim.x + threadIdx.x; path < N;
-       path += (size_t)gridDim.x * blockDim.x) {
-    if (A.mask && A.mask[path] == 0) continue;
-    int k = min(max(A.tape_len_in[path], 0), A.D);
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t first = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t rounds = (N + stride - 1) / stride;
+  for (size_t rd = 0; rd < rounds; ++rd) {
+    size_t path = first + rd * stride;
+    bool live = path < N && !(A.mask && A.mask[path] == 0);
+    int k = live ? min(max(A.tape_len_in[path], 0), A.D) : 0;
+    int kmax = k;
+    for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o));
     f3 bb = {0.f, 0.f, 0.f};  // adjoint of beta_{j+1}
-    for (int j = k; j >= 1; --j) {
-      TapeRec t = A.tape_in[(size_t)(j - 1) * N + path];
-      LT_COUNT(9, 1);
-      if (!(t.tf & kTfLambert)) continue;  // dielectric: weight 1, adjoint passes through
-      int texel = min((int)(t.tf & kTexMask), A.n_texels - 1);
-      f3 rho = ld3(A.albedo + (size_t)texel * 3);
-      f3 b = {t.b[0], t.b[1], t.b[2]};
-      f3 gr = {0.f, 0.f, 0.f}, bj = {0.f, 0.f, 0.f};
-      if (t.tf & kTfValid) {
-        f3 Lb = gather(A.sc, A.dI, t.ux, t.uy);
-        gr = mul(Lb, b) * t.g;
-        bj = mul(Lb, rho) * t.g;
+    for (int s = 0; s < kmax; ++s) {
+      int j = k - s;
+      bool has = false;
+      int texel = 0;
+      f3 gr = {0.f, 0.f, 0.f};
+      if (j >= 1) {
+        TapeRec t = A.tape_in[(size_t)(j - 1) * N + path];
+        LT_COUNT(9, 1);
+        if (t.tf & kTfLambert) {  // dielectric: weight 1, adjoint passes through
+          texel = min((int)(t.tf & kTexMask), A.n_texels - 1);
+          f3 rho = ld3(A.albedo + (size_t)texel * 3);
+          f3 b = {t.b[0], t.b[1], t.b[2]};
+          f3 bj = {0.f, 0.f, 0.f};
+          if (t.tf & kTfValid) {
+            f3 Lb = gather(A.sc, A.dI, t.ux, t.uy);
+            gr = mul(Lb, b) * t.g;
+            bj = mul(Lb, rho) * t.g;
+          }
+          if (t.tf & kTfScatter) {
+            gr = gr + mul(bb, b);
+            bj = bj + mul(bb, rho);
+          }
+          bb = bj;
+          has = true;
+        }
       }
-      if (t.tf & kTfScatter) {
-        gr = gr + mul(bb, b);
-        bj = bj + mul(bb, rho);
-      }
-      float* gp = A.g_albedo + (size_t)texel * 3;
-      LT_COUNT(6, 3);
-      if (gr.x != 0.f) atomicAdd(gp + 0, gr.x);
-      if (gr.y != 0.f) atomicAdd(gp + 1, gr.y);
-      if (gr.z != 0.f) atomicAdd(gp + 2, gr.z);
-      bb = bj;
+      scatter3_wave(A.g_albedo, has, texel, gr);
     }
-    gl0 += (double)bb.x * A.emit_factor;
-    gl1 += (double)bb.y * A.emit_factor;
-    gl2 += (double)bb.z * A.emit_factor;
+    if (live) {
+      gl0 += (double)bb.x * A.emit_factor;
+      gl1 += (double)bb.y * A.emit_factor;
+      gl2 += (double)bb.z * A.emit_factor;
+    }
   }
   flush_le(A, gl0, gl1, gl2);
 }
@@ -247,29 +270,36 @@ __global__ void __launch_bounds__(1024) k_reslrb_bwd(PassArgs A) {
   while (true) {
     refill(A, alive, exhausted, path, [&](uint32_t) {});
     if (__ballot(alive) == 0ull) break;
-    if (!alive) continue;
-    if (j == 0) {
+    bool has = false;
+    int texel = 0;
+    f3 gv = {0.f, 0.f, 0.f};
+    if (alive && j == 0) {
       ResRec rec = A.res_in[path];
-      if (rec.R <= 0) { alive = false; continue; }
-      R = min(rec.R, A.D);
-      f3 Lb = gather(A.sc, A.dI, rec.ux, rec.uy);
-      w = mul(Lb, mk(rec.S[0], rec.S[1], rec.S[2]));
-      if (Le.x > 0.f) gl0 += (double)w.x / Le.x;
-      if (Le.y > 0.f) gl1 += (double)w.y / Le.y;
-      if (Le.z > 0.f) gl2 += (double)w.z / Le.z;
-      emit(A.sc, A.seed, path, r);
-      j = 1;
+      if (rec.R <= 0) {
+        alive = false;
+      } else {
+        R = min(rec.R, A.D);
+        f3 Lb = gather(A.sc, A.dI, rec.ux, rec.uy);
+        w = mul(Lb, mk(rec.S[0], rec.S[1], rec.S[2]));
+        if (Le.x > 0.f) gl0 += (double)w.x / Le.x;
+        if (Le.y > 0.f) gl1 += (double)w.y / Le.y;
+        if (Le.z > 0.f) gl2 += (double)w.z / Le.z;
+        emit(A.sc, A.seed, path, r);
+        j = 1;
+      }
     }
-    Event ev = bounce(A, path, j, r, false, stk, ss);
-    if (ev.kind == 1) {
-      float* gp = A.g_albedo + (size_t)ev.texel * 3;
-      LT_COUNT(6, 3);
-      if (w.x != 0.f && ev.rho.x > 0.f) atomicAdd(gp + 0, w.x / ev.rho.x);
-      if (w.y != 0.f && ev.rho.y > 0.f) atomicAdd(gp + 1, w.y / ev.rho.y);
-      if (w.z != 0.f && ev.rho.z > 0.f) atomicAdd(gp + 2, w.z / ev.rho.z);
+    if (alive) {
+      Event ev = bounce(A, path, j, r, 0, stk, ss);
+      if (ev.kind == 1) {
+        texel = ev.texel;
+        gv = {ev.rho.x > 0.f ? w.x / ev.rho.x : 0.f, ev.rho.y > 0.f ? w.y / ev.rho.y : 0.f,
+              ev.rho.z > 0.f ? w.z / ev.rho.z : 0.f};
+        has = true;
+      }
+      if (ev.cont && j < R) ++j;
+      else { alive = false; j = 0; }
     }
-    if (ev.cont && j < R) { ++j; continue; }
-    alive = false; j = 0;
+    scatter3_wave(A.g_albedo, has, texel, gv);
   }
   flush_le(A, gl0, gl1, gl2);
 }
@@ -281,13 +311,18 @@ __global__ void __launch_bounds__(1024) k_reslrb_bwd(PassArgs A) {
 // (Eq. 15), the subtraction delta_rem -= dI(u_i) * C_i (Eq. 16) and the
 // log-derivative delta_rem / rho_i of the scatter factor (Eq. 17); the
 // emitter gets delta_total / L_e.
+// Phase 2 also keeps one bit per vertex (valid connection) and the depth of
+// the last valid connection: phase 3 then re-evaluates only the connection
+// geometry where the bit is set (no shadow rays) and stops at that depth,
+// where delta_rem is exactly zero and nothing further contributes.
 __global__ void __launch_bounds__(1024) k_lrb3_bwd(PassArgs A) {
   extern __shared__ int lds[];
   int* stk = lds + threadIdx.x;
   const int ss = blockDim.x;
   bool alive = false, exhausted = false;
   uint32_t path = 0;
-  int j = 0, phase = 2;
+  int j = 0, phase = 2, klast = 0;
+  uint64_t vmask = 0ull;
   Ray r;
   f3 beta = {0.f, 0.f, 0.f};
   double d0 = 0.0, d1 = 0.0, d2 = 0.0;  // delta_total, then delta_rem
@@ -296,45 +331,53 @@ __global__ void __launch_bounds__(1024) k_lrb3_bwd(PassArgs A) {
   while (true) {
     refill(A, alive, exhausted, path, [&](uint32_t) {});
     if (__ballot(alive) == 0ull) break;
-    if (!alive) continue;
-    if (j == 0) {
-      float f = emit(A.sc, A.seed, path, r);
-      beta = Le * f;
-      j = 1;
-      if (phase == 2) { d0 = d1 = d2 = 0.0; }
-    }
-    Event ev = bounce(A, path, j, r, true, stk, ss);
-    if (ev.kind == 1) {
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-      if (ev.valid) {
-        f3 C = mul(beta, ev.rho) * ev.g;
-        f3 Lb = gather(A.sc, A.dI, ev.ux, ev.uy);
-        a0 = (double)Lb.x * C.x; a1 = (double)Lb.y * C.y; a2 = (double)Lb.z * C.z;
+    bool has = false;
+    int texel = 0;
+    f3 gv = {0.f, 0.f, 0.f};
+    if (alive) {
+      if (j == 0) {
+        float f = emit(A.sc, A.seed, path, r);
+        beta = Le * f;
+        j = 1;
+        if (phase == 2) { d0 = d1 = d2 = 0.0; vmask = 0ull; klast = 0; }
       }
-      if (phase == 2) {
-        d0 += a0; d1 += a1; d2 += a2;
+      const int cmode = phase == 2 ? 1 : (((vmask >> (j - 1)) & 1ull) ? 2 : 0);
+      Event ev = bounce(A, path, j, r, cmode, stk, ss);
+      if (phase == 3 && j >= klast) ev.cont = false;  // nothing after the last connection
+      if (ev.kind == 1) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        if (ev.valid) {
+          f3 C = mul(beta, ev.rho) * ev.g;
+          f3 Lb = gather(A.sc, A.dI, ev.ux, ev.uy);
+          a0 = (double)Lb.x * C.x; a1 = (double)Lb.y * C.y; a2 = (double)Lb.z * C.z;
+          if (phase == 2) { vmask |= 1ull << (j - 1); klast = j; }
+        }
+        if (phase == 2) {
+          d0 += a0; d1 += a1; d2 += a2;
+        } else {
+          d0 -= a0; d1 -= a1; d2 -= a2;
+          if (j >= klast) { d0 = d1 = d2 = 0.0; }
+          double g0 = a0, g1 = a1, g2 = a2;
+          if (ev.cont) { g0 += d0; g1 += d1; g2 += d2; }
+          texel = ev.texel;
+          gv = {ev.rho.x > 0.f ? (float)(g0 / ev.rho.x) : 0.f, ev.rho.y > 0.f ? (float)(g1 / ev.rho.y) : 0.f,
+                ev.rho.z > 0.f ? (float)(g2 / ev.rho.z) : 0.f};
+          has = true;
+        }
+        if (ev.cont) beta = mul(beta, ev.rho);
+      }
+      if (ev.cont) {
+        ++j;
+      } else if (phase == 2 && klast > 0 && (d0 != 0.0 || d1 != 0.0 || d2 != 0.0)) {  // consuming replay
+        if (Le.x > 0.f) gl0 += d0 / Le.x;
+        if (Le.y > 0.f) gl1 += d1 / Le.y;
+        if (Le.z > 0.f) gl2 += d2 / Le.z;
+        phase = 3; j = 0;
       } else {
-        d0 -= a0; d1 -= a1; d2 -= a2;
-        double g0 = a0, g1 = a1, g2 = a2;
-        if (ev.cont) { g0 += d0; g1 += d1; g2 += d2; }
-        float* gp = A.g_albedo + (size_t)ev.texel * 3;
-        LT_COUNT(6, 3);
-        if (g0 != 0.0 && ev.rho.x > 0.f) atomicAdd(gp + 0, (float)(g0 / ev.rho.x));
-        if (g1 != 0.0 && ev.rho.y > 0.f) atomicAdd(gp + 1, (float)(g1 / ev.rho.y));
-        if (g2 != 0.0 && ev.rho.z > 0.f) atomicAdd(gp + 2, (float)(g2 / ev.rho.z));
+        phase = 2; j = 0; alive = false;
       }
-      if (ev.cont) beta = mul(beta, ev.rho);
     }
-    if (ev.cont) { ++j; continue; }
-    // end of a replay
-    if (phase == 2 && (d0 != 0.0 || d1 != 0.0 || d2 != 0.0)) {
-      if (Le.x > 0.f) gl0 += d0 / Le.x;
-      if (Le.y > 0.f) gl1 += d1 / Le.y;
-      if (Le.z > 0.f) gl2 += d2 / Le.z;
-      phase = 3; j = 0;
-      continue;
-    }
-    phase = 2; j = 0; alive = false;
+    scatter3_wave(A.g_albedo, has, texel, gv);
   }
   flush_le(A, gl0, gl1, gl2);
 }
