@@ -113,6 +113,9 @@ typedef struct {
   uint32_t* path_sig;       /* DEVICE [n_paths] or NULL: lt_trace writes each path's
                                decision signature (FNV-1a of hit primitive, texel,
                                connection validity, lobe and R) */
+  uint32_t* path_info;      /* DEVICE [n_paths] or NULL: attached backward passes
+                               write per-path flags (bit 0: the determinant guard
+                               zeroed a projected adjoint on this path) */
 } lt_trace_args;
 
 /* Parameters: DEVICE float arrays owned by the caller. */

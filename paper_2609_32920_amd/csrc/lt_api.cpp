@@ -233,7 +233,7 @@ lt_status check_args(lt_ctx* c, const lt_trace_args* a, const lt_params* p) {
     return c->fail(LT_ERR_ARG, "unknown flag bits%s");
   if (!p->albedo || !p->emitter_L) return c->fail(LT_ERR_ARG, "albedo and emitter_L are required%s");
   if ((a->flags & LT_ATTACHED) && c->dsc.hf_G < 2) return c->fail(LT_ERR_ARG, "LT_ATTACHED needs a heightfield%s");
-  if (a->flags & LT_ATTACHED) return c->fail(LT_ERR_UNSUPPORTED, "attached mode is not available in this build%s");
+  if ((a->flags & LT_ATTACHED) && !p->heights) return c->fail(LT_ERR_ARG, "LT_ATTACHED needs params->heights%s");
   return LT_OK;
 }
 
@@ -265,10 +265,12 @@ PassArgs base_args(lt_ctx* c, const lt_trace_args* a, const lt_params* p) {
   A.n_texels = c->dsc.n_tex * c->dsc.tex_res * c->dsc.tex_res;
   A.mask = a->path_mask;
   A.sig = a->path_sig;
+  A.info = a->path_info;
   A.albedo = p->albedo;
   A.Le = p->emitter_L;
   A.heights = p->heights;
   A.counter = c->d_counter;
+  A.stats = reinterpret_cast<unsigned long long*>(c->d_counter + 16);  // same allocation, byte 64
   return A;
 }
 
@@ -350,7 +352,12 @@ lt_status lt_set_memory_cap(lt_ctx* c, uint64_t bytes) {
 
 lt_status lt_get_stats(const lt_ctx* c, lt_stats* out) {
   if (!c || !out) return LT_ERR_ARG;
-  *out = c->stats;
+  uint64_t s[2] = {0, 0};
+  if (hipStreamSynchronize(c->stream) != hipSuccess ||
+      hipMemcpy(s, c->d_counter + 16, sizeof(s), hipMemcpyDeviceToHost) != hipSuccess)
+    return LT_ERR_HIP;
+  out->guard_triggers = s[0];
+  out->nonfinite = s[1];
   return LT_OK;
 }
 
@@ -545,6 +552,8 @@ lt_status lt_trace(lt_ctx* c, const lt_trace_args* a, const lt_params* p, float*
   lt_status st = check_args(c, a, p);
   if (st != LT_OK) return st;
   if (!image) return c->fail(LT_ERR_ARG, "null image%s");
+  if ((a->flags & LT_ATTACHED) && (a->flags & (LT_RECORD_TAPE | LT_RECORD_RESERVOIR)))
+    return c->fail(LT_ERR_UNSUPPORTED, "attached tape / reservoir records are not available in this build%s");
   SideLayout L = side_layout(a);
   if (L.total && (!side || side_bytes < L.total)) return c->fail(LT_ERR_ARG, "side state buffer too small%s");
   if ((st = check_cap(c, L.total)) != LT_OK) return st;
@@ -585,6 +594,7 @@ static lt_status backward_common(lt_ctx* c, const lt_trace_args* a, const lt_par
   A.g_Le_acc = c->d_acc;
   A.g_heights = g->heights;
   if ((st = c->hip(launch_fill_f64(c->d_acc, 3, 0.0, c->stream), "acc clear")) != LT_OK) return st;
+  if ((st = c->hip(launch_fill_u32(c->d_counter + 16, 4, 0u, c->stream), "stats clear")) != LT_OK) return st;
   return c->hip(launch_fill_u32(c->d_counter, 1, 0u, c->stream), "counter clear");
 }
 
@@ -629,8 +639,13 @@ lt_status lt_backward_lrb3(lt_ctx* c, const lt_trace_args* a, const lt_params* p
   lt_status st = backward_common(c, a, p, d_image, g, A);
   if (st != LT_OK) return st;
   if ((st = check_cap(c, 0)) != LT_OK) return st;
-  int grid = persistent_grid(c, a->n_paths, c->tune.block);
-  if ((st = c->hip(launch_lrb3_bwd(A, grid, c->tune.block, c->stream), "lrb3 backward")) != LT_OK) return st;
+  if (a->flags & LT_ATTACHED) {
+    int grid = persistent_grid(c, a->n_paths, 256);
+    if ((st = c->hip(launch_lrb3_att(A, grid, c->stream), "lrb3 attached backward")) != LT_OK) return st;
+  } else {
+    int grid = persistent_grid(c, a->n_paths, c->tune.block);
+    if ((st = c->hip(launch_lrb3_bwd(A, grid, c->tune.block, c->stream), "lrb3 backward")) != LT_OK) return st;
+  }
   return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
 }
 

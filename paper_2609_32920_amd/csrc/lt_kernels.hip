@@ -23,6 +23,8 @@ struct Event {
   int lobe, fail;  // dielectric: lobe 2 reflect / 4 refract, fail 7/8
   bool cont;       // the path continues with the updated ray
   float u_res;     // reservoir uniform of this vertex
+  int slot;        // hit triangle in BVH order
+  f3 x;            // hit point
 };
 
 // cmode: 0 no sensor connection, 1 full connection test (with shadow
@@ -33,10 +35,13 @@ __device__ __forceinline__ Event bounce(const PassArgs& A, uint32_t path, int j,
   Event ev;
   ev.prim = -1; ev.kind = 0; ev.texel = -1; ev.rho = {0.f, 0.f, 0.f}; ev.valid = false;
   ev.ux = ev.uy = ev.g = 0.f; ev.lobe = 0; ev.fail = 0; ev.cont = false; ev.u_res = 1.0f; ev.cos_in = 0.f;
+  ev.slot = -1; ev.x = {0.f, 0.f, 0.f};
   Hit h = closest_hit(sc, ray_origin(r), r.w, kTmin, 3.0e38f, stk, ss);
   if (h.tri < 0) return ev;
   Surf s = surface(sc, h.tri, r);
   ev.prim = s.prim;
+  ev.slot = h.tri;
+  ev.x = s.x;
   int mat = sc.prim_mat[s.prim];
   int mt = sc.mat_type[mat];
   if (mt == 0) return ev;
@@ -474,8 +479,15 @@ __global__ void k_refit_level(Node* nodes, const Tri* tris, const int32_t* level
   for (int a = 0; a < 3; ++a) { nd.lo1[a] = lo[a]; nd.hi1[a] = hi[a]; }
 }
 
+#include "lt_attached.inc"
+
 // ---------------------------------------------------------------- launchers
 static size_t stack_bytes(int block) { return (size_t)kStackMax * block * sizeof(int); }
+
+hipError_t launch_lrb3_att(const PassArgs& A, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_lrb3_att, dim3(grid), dim3(256), stack_bytes(256), s, A);
+  return hipGetLastError();
+}
 
 hipError_t read_counters(uint64_t* out, bool reset, hipStream_t s) {
 #ifdef LT_COUNTERS

@@ -17,6 +17,7 @@ struct PassArgs {
   int32_t n_texels;     // n_tex * tex_res^2
   const uint8_t* mask;
   uint32_t* sig;
+  uint32_t* info;
   const float* albedo;
   const float* Le;
   const float* heights;
@@ -34,12 +35,14 @@ struct PassArgs {
   float* g_albedo;
   double* g_Le_acc;
   float* g_heights;
+  unsigned long long* stats;  // [0] guard triggers, [1] non-finite drops
 };
 
 hipError_t launch_trace(const PassArgs& A, bool tape, bool resv, int grid, int block, hipStream_t s);
 hipError_t launch_naive_bwd(const PassArgs& A, int grid, hipStream_t s);
 hipError_t launch_reslrb_bwd(const PassArgs& A, int grid, int block, hipStream_t s);
 hipError_t launch_lrb3_bwd(const PassArgs& A, int grid, int block, hipStream_t s);
+hipError_t launch_lrb3_att(const PassArgs& A, int grid, hipStream_t s);
 hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t s);
 hipError_t launch_fill_u32(unsigned int* p, size_t n, unsigned int v, hipStream_t s);
 hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s);

@@ -52,7 +52,8 @@ class SceneDesc(C.Structure):
 
 class TraceArgs(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("n_paths", C.c_int64), ("max_depth", C.c_int32),
-                ("flags", C.c_uint32), ("path_mask", C.c_void_p), ("path_sig", C.c_void_p)]
+                ("flags", C.c_uint32), ("path_mask", C.c_void_p), ("path_sig", C.c_void_p),
+                ("path_info", C.c_void_p)]
 
 
 class Params(C.Structure):
@@ -222,11 +223,12 @@ class Context:
         return self
 
     # ------------------------------------------------------------ passes
-    def args(self, seed, n_paths, depth, flags=0, mask=None, sig=None):
+    def args(self, seed, n_paths, depth, flags=0, mask=None, sig=None, info=None):
         a = TraceArgs()
         a.seed, a.n_paths, a.max_depth, a.flags = int(seed), int(n_paths), int(depth), int(flags)
         a.path_mask = None if mask is None else mask.data_ptr()
         a.path_sig = None if sig is None else sig.data_ptr()
+        a.path_info = None if info is None else info.data_ptr()
         return a
 
     def params(self, albedo, Le, heights=None):

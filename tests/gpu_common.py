@@ -51,10 +51,11 @@ class GpuRun:
             out["sig"] = sig.cpu().numpy().view(np.uint32)
         return out
 
-    def backward(self, mode, seed, n, depth, dI, flags=0, mask=None, side=None):
+    def backward(self, mode, seed, n, depth, dI, flags=0, mask=None, side=None, want_info=False):
         m = None if mask is None else torch.as_tensor(np.asarray(mask, np.uint8), device=self.dev)
         rec = lt.RECORD_TAPE if mode == "naive" else lt.RECORD_RESERVOIR if mode == "reslrb" else 0
-        a = self.ctx.args(seed, n, depth, flags | rec, m)
+        info = torch.zeros(n, dtype=torch.int32, device=self.dev) if want_info else None
+        a = self.ctx.args(seed, n, depth, flags | rec, m, None, info)
         p = self.ctx.params(self.albedo, self.Le, self.heights)
         dIt = torch.as_tensor(np.asarray(dI, np.float32), device=self.dev).contiguous()
         if side is None and mode != "lrb3":
@@ -72,8 +73,12 @@ class GpuRun:
         else:
             self.ctx.backward_lrb3(a, p, dIt, g_alb, g_le, g_h)
         torch.cuda.synchronize()
-        return dict(albedo=g_alb.cpu().numpy().astype(np.float64), Le=g_le.cpu().numpy().astype(np.float64),
-                    heights=None if g_h is None else g_h.cpu().numpy().astype(np.float64))
+        out = dict(albedo=g_alb.cpu().numpy().astype(np.float64), Le=g_le.cpu().numpy().astype(np.float64),
+                   heights=None if g_h is None else g_h.cpu().numpy().astype(np.float64))
+        if want_info:
+            out["info"] = info.cpu().numpy().view(np.uint32)
+            out["stats"] = self.ctx.stats()
+        return out
 
 
 def matched_paths(sc, g, seed, n, depth, flags=0):
