@@ -113,9 +113,13 @@ typedef struct {
   uint32_t* path_sig;       /* DEVICE [n_paths] or NULL: lt_trace writes each path's
                                decision signature (FNV-1a of hit primitive, texel,
                                connection validity, lobe and R) */
-  uint32_t* path_info;      /* DEVICE [n_paths] or NULL: attached backward passes
-                               write per-path flags (bit 0: the determinant guard
-                               zeroed a projected adjoint on this path) */
+  uint32_t* path_info;      /* DEVICE [n_paths] or NULL: the attached passes write
+                               per-path flags - bit 0: the determinant guard zeroed a
+                               projected adjoint on this path; bit 1: the path has an
+                               ill-conditioned vertex (grazing hit, |cos| < 0.02;
+                               refraction with cos_t < 0.1; or a segment shorter than
+                               0.02 scene units) whose FP32 derivatives carry rounding
+                               amplified by 1/cos^2 or 1/length */
 } lt_trace_args;
 
 /* Parameters: DEVICE float arrays owned by the caller. */

@@ -206,18 +206,22 @@ int persistent_grid(const lt_ctx* c, int64_t n, int block) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-struct SideLayout { size_t tape = 0, len = 0, res = 0, total = 0; };
+struct SideLayout { size_t tape = 0, len = 0, emit = 0, res = 0, total = 0; };
 
+// Side state: naive tape [D][N] records (+ N path lengths; attached: + the
+// emitted ray's dv_1/dH_1 per path), ResLRB records [N].
 SideLayout side_layout(const lt_trace_args* a) {
   SideLayout L;
   size_t N = (size_t)a->n_paths, D = (size_t)a->max_depth;
+  const bool att = (a->flags & LT_ATTACHED) != 0;
   size_t off = 0;
   if (a->flags & LT_RECORD_TAPE) {
-    L.tape = off; off = align256(off + N * D * sizeof(TapeRec));
+    L.tape = off; off = align256(off + N * D * (att ? sizeof(TapeRecAtt) : sizeof(TapeRec)));
     L.len = off; off = align256(off + N * sizeof(int32_t));
+    if (att) { L.emit = off; off = align256(off + N * 2 * sizeof(float)); }
   }
   if (a->flags & LT_RECORD_RESERVOIR) {
-    L.res = off; off = align256(off + N * sizeof(ResRec));
+    L.res = off; off = align256(off + N * (att ? sizeof(ResRecAtt) : sizeof(ResRec)));
   }
   L.total = off;
   return L;
@@ -552,8 +556,9 @@ lt_status lt_trace(lt_ctx* c, const lt_trace_args* a, const lt_params* p, float*
   lt_status st = check_args(c, a, p);
   if (st != LT_OK) return st;
   if (!image) return c->fail(LT_ERR_ARG, "null image%s");
-  if ((a->flags & LT_ATTACHED) && (a->flags & (LT_RECORD_TAPE | LT_RECORD_RESERVOIR)))
-    return c->fail(LT_ERR_UNSUPPORTED, "attached tape / reservoir records are not available in this build%s");
+  const bool att_rec = (a->flags & LT_ATTACHED) && (a->flags & (LT_RECORD_TAPE | LT_RECORD_RESERVOIR));
+  if (att_rec && a->path_sig)
+    return c->fail(LT_ERR_UNSUPPORTED, "path signatures come from the detached forward (no attached records)%s");
   SideLayout L = side_layout(a);
   if (L.total && (!side || side_bytes < L.total)) return c->fail(LT_ERR_ARG, "side state buffer too small%s");
   if ((st = check_cap(c, L.total)) != LT_OK) return st;
@@ -561,12 +566,26 @@ lt_status lt_trace(lt_ctx* c, const lt_trace_args* a, const lt_params* p, float*
   PassArgs A = base_args(c, a, p);
   A.image = image;
   char* sb = (char*)side;
-  if (a->flags & LT_RECORD_TAPE) { A.tape = (TapeRec*)(sb + L.tape); A.tape_len = (int32_t*)(sb + L.len); }
-  if (a->flags & LT_RECORD_RESERVOIR) A.res = (ResRec*)(sb + L.res);
+  if (att_rec) {
+    if (a->flags & LT_RECORD_TAPE) {
+      A.tape_att = (TapeRecAtt*)(sb + L.tape);
+      A.tape_len = (int32_t*)(sb + L.len);
+      A.emit_d = (float*)(sb + L.emit);
+    }
+    if (a->flags & LT_RECORD_RESERVOIR) A.res_att = (ResRecAtt*)(sb + L.res);
+  } else {
+    if (a->flags & LT_RECORD_TAPE) { A.tape = (TapeRec*)(sb + L.tape); A.tape_len = (int32_t*)(sb + L.len); }
+    if (a->flags & LT_RECORD_RESERVOIR) A.res = (ResRec*)(sb + L.res);
+  }
   size_t npix = (size_t)c->dsc.W * c->dsc.H * 3;
   if ((st = c->hip(launch_fill_f32(image, npix, 0.f, c->stream), "image clear")) != LT_OK) return st;
   if ((st = c->hip(launch_fill_u32(c->d_counter, 1, 0u, c->stream), "counter clear")) != LT_OK) return st;
   bool tape = (a->flags & LT_RECORD_TAPE) != 0;
+  if (att_rec) {
+    bool rec = (a->flags & LT_RECORD_RESERVOIR) != 0;
+    int grid = persistent_grid(c, a->n_paths, 256);
+    return c->hip(launch_trace_att(A, tape, rec, grid, c->stream), "attached trace launch");
+  }
   // the decision signature includes the reservoir choice R
   bool resv = (a->flags & (LT_RECORD_RESERVOIR | LT_SPLAT_SELECTED)) != 0 || a->path_sig != nullptr;
   int grid = persistent_grid(c, a->n_paths, c->tune.block);
@@ -612,7 +631,12 @@ lt_status lt_backward_naive(lt_ctx* c, const lt_trace_args* a, const lt_params* 
   A.tape_in = (const TapeRec*)(sb + L.tape);
   A.tape_len_in = (const int32_t*)(sb + L.len);
   int grid = (int)std::max<int64_t>(1, std::min<int64_t>((a->n_paths + 255) / 256, (int64_t)c->n_cu * 16));
-  if ((st = c->hip(launch_naive_bwd(A, grid, c->stream), "naive backward")) != LT_OK) return st;
+  if (a->flags & LT_ATTACHED) {
+    A.emit_d = (float*)(sb + L.emit);
+    if ((st = c->hip(launch_naive_att_bwd(A, grid, c->stream), "naive attached backward")) != LT_OK) return st;
+  } else if ((st = c->hip(launch_naive_bwd(A, grid, c->stream), "naive backward")) != LT_OK) {
+    return st;
+  }
   return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
 }
 
@@ -626,6 +650,12 @@ lt_status lt_backward_reslrb(lt_ctx* c, const lt_trace_args* a, const lt_params*
   SideLayout L = side_layout(a);
   if (!records || bytes < L.total) return c->fail(LT_ERR_ARG, "reservoir buffer too small%s");
   if ((st = check_cap(c, L.total)) != LT_OK) return st;
+  if (a->flags & LT_ATTACHED) {
+    A.res_att_in = (const ResRecAtt*)((const char*)records + L.res);
+    int grid = persistent_grid(c, a->n_paths, 256);
+    if ((st = c->hip(launch_reslrb_att(A, grid, c->stream), "reslrb attached backward")) != LT_OK) return st;
+    return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
+  }
   A.res_in = (const ResRec*)((const char*)records + L.res);
   int grid = persistent_grid(c, a->n_paths, c->tune.block);
   if ((st = c->hip(launch_reslrb_bwd(A, grid, c->tune.block, c->stream), "reslrb backward")) != LT_OK) return st;

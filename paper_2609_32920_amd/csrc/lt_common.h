@@ -52,6 +52,33 @@ struct alignas(16) ResRec {
 };
 static_assert(sizeof(ResRec) == 32, "reservoir record layout");
 
+// Attached naive-AD tape record, [D][N] x 128 bytes: the detached fields,
+// the chart of x_s (triangle slot, v_s), and once x_{s+1} is known the two
+// non-trivial rows of J_s = dp_{s+1}/dp_s and dv_{s+1}/d(channels).
+struct alignas(16) TapeRecAtt {
+  uint32_t tf;
+  int32_t slot;
+  float v0, v1;
+  float g, ux, uy;
+  float b[3];
+  float J[8];
+  float dch[10];
+  float pad[2];
+};
+static_assert(sizeof(TapeRecAtt) == 128, "attached tape layout");
+
+// Attached ResLRB record (Sec. 4.2.2): the detached record plus the chart of
+// x_R, beta_R * rho_R and the accumulated Jacobian M_R = J_{R-1}...J_1.
+struct alignas(16) ResRecAtt {
+  ResRec base;
+  int32_t slot;
+  float v0, v1;
+  float br[3];
+  float pad[2];
+  float M[16];
+};
+static_assert(sizeof(ResRecAtt) == 128, "attached reservoir record layout");
+
 struct DevScene {
   const Node* nodes;
   const Tri* tris;

@@ -417,7 +417,7 @@ __device__ __forceinline__ f3 gather(const DevScene& sc, const float* dI, float 
 // wrong side of the geometric normal.
 // Return value: 0 ok, 7 cos_i <= 0, 8 wrong side.
 __device__ __forceinline__ int dielectric(f3 w_in, f3 ng, f3 ns, float ior, float u_lobe, f3& wo,
-                                          bool& reflect) {
+                                          bool& reflect, float& cos_t) {
   float cos_g = dot(w_in, ng);
   bool entering = cos_g < 0.0f;
   float eta = entering ? 1.0f / ior : ior;
@@ -435,6 +435,7 @@ __device__ __forceinline__ int dielectric(f3 w_in, f3 ng, f3 ns, float ior, floa
     F = 0.5f * (rs * rs + rp * rp);
   }
   reflect = u_lobe < F;
+  cos_t = reflect ? 1.0f : cost;
   if (reflect) wo = w_in + n * (2.0f * cosi);
   else wo = w_in * eta + n * (eta * cosi - cost);
   float side_in = -cos_g, s_out = dot(wo, ng);

@@ -25,6 +25,8 @@ struct Event {
   float u_res;     // reservoir uniform of this vertex
   int slot;        // hit triangle in BVH order
   f3 x;            // hit point
+  bool illc;       // ill-conditioned vertex for attached derivatives (grazing hit
+                   // or refraction near the critical angle)
 };
 
 // cmode: 0 no sensor connection, 1 full connection test (with shadow
@@ -35,7 +37,7 @@ __device__ __forceinline__ Event bounce(const PassArgs& A, uint32_t path, int j,
   Event ev;
   ev.prim = -1; ev.kind = 0; ev.texel = -1; ev.rho = {0.f, 0.f, 0.f}; ev.valid = false;
   ev.ux = ev.uy = ev.g = 0.f; ev.lobe = 0; ev.fail = 0; ev.cont = false; ev.u_res = 1.0f; ev.cos_in = 0.f;
-  ev.slot = -1; ev.x = {0.f, 0.f, 0.f};
+  ev.slot = -1; ev.x = {0.f, 0.f, 0.f}; ev.illc = false;
   Hit h = closest_hit(sc, ray_origin(r), r.w, kTmin, 3.0e38f, stk, ss);
   if (h.tri < 0) return ev;
   Surf s = surface(sc, h.tri, r);
@@ -46,6 +48,10 @@ __device__ __forceinline__ Event bounce(const PassArgs& A, uint32_t path, int j,
   int mt = sc.mat_type[mat];
   if (mt == 0) return ev;
   ev.cos_in = dot(r.w, s.ng);
+  // grazing hit (hit-point derivatives ~ 1/cos) or a short segment (the
+  // segment direction carries position rounding amplified by 1/length)
+  f3 seg = s.x - r.x;
+  ev.illc = fabsf(ev.cos_in) < 0.02f || dot(seg, seg) < 4e-4f;
   u4f u = (mt == 1 || j < A.D) ? rng4(A.seed, path, (uint32_t)j, 0u) : u4f{0.f, 0.f, 0.f, 1.f};
   ev.u_res = u.u3;
   if (mt == 1) {
@@ -66,9 +72,13 @@ __device__ __forceinline__ Event bounce(const PassArgs& A, uint32_t path, int j,
   f3 ns = s.ng;
   if (s.prim >= sc.n_static) ns = hf_shading_normal(sc, A.heights, s);
   f3 wo; bool refl;
-  int code = dielectric(r.w, s.ng, ns, sc.mat_ior[mat], u.u2, wo, refl);
+  float cos_t = 1.f;
+  int code = dielectric(r.w, s.ng, ns, sc.mat_ior[mat], u.u2, wo, refl, cos_t);
   if (code == 7) { ev.fail = 7; return ev; }
   ev.lobe = refl ? 2 : 4;
+  // refraction near the critical angle: d(cos_t) ~ 1/cos_t amplifies FP32
+  // rounding of the primal direction by ~1/cos_t^2 in the derivatives
+  if (cos_t < 0.1f) ev.illc = true;
   if (code == 8) { ev.fail = 8; return ev; }
   r.w = wo; r.x = s.x; r.offn = s.ng; r.off = true;
   ev.cont = true;
@@ -486,6 +496,21 @@ static size_t stack_bytes(int block) { return (size_t)kStackMax * block * sizeof
 
 hipError_t launch_lrb3_att(const PassArgs& A, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_lrb3_att, dim3(grid), dim3(256), stack_bytes(256), s, A);
+  return hipGetLastError();
+}
+hipError_t launch_trace_att(const PassArgs& A, bool tape, bool resv, int grid, hipStream_t s) {
+  size_t sh = stack_bytes(256);
+  if (tape && resv) hipLaunchKernelGGL((k_trace_att<true, true>), dim3(grid), dim3(256), sh, s, A);
+  else if (tape) hipLaunchKernelGGL((k_trace_att<true, false>), dim3(grid), dim3(256), sh, s, A);
+  else hipLaunchKernelGGL((k_trace_att<false, true>), dim3(grid), dim3(256), sh, s, A);
+  return hipGetLastError();
+}
+hipError_t launch_naive_att_bwd(const PassArgs& A, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_naive_att_bwd, dim3(grid), dim3(256), 0, s, A);
+  return hipGetLastError();
+}
+hipError_t launch_reslrb_att(const PassArgs& A, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_reslrb_att, dim3(grid), dim3(256), stack_bytes(256), s, A);
   return hipGetLastError();
 }
 

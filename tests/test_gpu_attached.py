@@ -43,26 +43,63 @@ def test_caustic_forward_parity(caustic16):
     assert e <= TOL
 
 
+def test_naive_attached_parity(caustic16):
+    # exact chain rule over the attached tape: no inverse, no guard; paths
+    # with an ill-conditioned vertex are flagged by the kernel and left out
+    from tests.gpu_common import matched_paths, maxrel
+    sc, g = caustic16
+    for seed, D in ((12, 3), (13, 6)):
+        n = 65536
+        mask, ids, mis = matched_paths(sc, g, seed, n, D)
+        assert mis <= 1e-3
+        dI = _dI((64, 64, 3), seed)
+        first = g.backward("naive", seed, n, D, dI, flags=lt.ATTACHED, mask=mask, want_info=True)
+        illc = (first["info"] & 2).astype(bool)
+        print(f"naive attached D={D}: ill-conditioned paths {illc.mean():.2e}", flush=True)
+        assert illc.mean() <= 5e-2
+        keep = mask.astype(bool) & ~illc
+        ids2 = np.nonzero(keep)[0].astype(np.uint32)
+        gg = g.backward("naive", seed, n, D, dI, flags=lt.ATTACHED, mask=keep.astype(np.uint8))
+        og = O.gradient(sc, seed, n, D, dI, flags=O.ATTACHED, path_list=ids2)
+        eh, ea, el = (maxrel(gg[k], og[k]) for k in ("heights", "albedo", "Le"))
+        print(f"naive attached D={D}: heights {eh:.2e} albedo {ea:.2e} Le {el:.2e}", flush=True)
+        assert eh <= TOL and ea <= TOL and el <= TOL
+
+
+def test_attached_side_state_sizes(caustic16):
+    sc, g = caustic16
+    n = 1 << 20
+    tape = [g.ctx.side_state_bytes(g.ctx.args(1, n, d, lt.ATTACHED | lt.RECORD_TAPE)) for d in (3, 6, 12)]
+    res = [g.ctx.side_state_bytes(g.ctx.args(1, n, d, lt.ATTACHED | lt.RECORD_RESERVOIR)) for d in (3, 6, 12)]
+    base = [t - 128 * n * d for t, d in zip(tape, (3, 6, 12))]
+    assert base[0] == base[1] == base[2]          # 128 B per vertex: linear in depth
+    assert res[0] == res[1] == res[2] == 128 * n  # one record per path: flat in depth
+
+
+@pytest.mark.parametrize("mode", ["lrb3", "reslrb"])
 @pytest.mark.parametrize("D", [3, 4, 6])
-def test_lrb3_attached_parity(caustic16, D):
+def test_replay_attached_parity(caustic16, D, mode):
     from tests.gpu_common import matched_paths, maxrel
     sc, g = caustic16
     seed, n = 11, 65536
     mask, ids, mis = matched_paths(sc, g, seed, n, D)
     assert mis <= 1e-3
     dI = _dI((64, 64, 3), D)
-    first = g.backward("lrb3", seed, n, D, dI, flags=lt.ATTACHED, mask=mask, want_info=True)
+    omode = O.MODE_NAIVE if mode == "lrb3" else O.MODE_RESLRB
+    first = g.backward(mode, seed, n, D, dI, flags=lt.ATTACHED, mask=mask, want_info=True)
     guard = (first["info"] & 1).astype(bool)
+    illc = (first["info"] & 2).astype(bool)
     frac = guard.mean()
-    print(f"D={D}: guard paths {guard.sum()} ({frac:.2e}), triggers {first['stats']['guard_triggers']}", flush=True)
-    assert frac <= 1e-2
-    keep = mask.astype(bool) & ~guard
+    print(f"{mode} D={D}: guard paths {guard.sum()} ({frac:.2e}), triggers {first['stats']['guard_triggers']}, "
+          f"ill-conditioned {illc.mean():.2e}", flush=True)
+    assert frac <= 1e-2 and illc.mean() <= 5e-2
+    keep = mask.astype(bool) & ~guard & ~illc
     ids2 = np.nonzero(keep)[0].astype(np.uint32)
-    gg = g.backward("lrb3", seed, n, D, dI, flags=lt.ATTACHED, mask=keep.astype(np.uint8))
-    og = O.gradient(sc, seed, n, D, dI, flags=O.ATTACHED, path_list=ids2)
+    gg = g.backward(mode, seed, n, D, dI, flags=lt.ATTACHED, mask=keep.astype(np.uint8))
+    og = O.gradient(sc, seed, n, D, dI, mode=omode, flags=O.ATTACHED, path_list=ids2)
     eh = maxrel(gg["heights"], og["heights"])
     ea = maxrel(gg["albedo"], og["albedo"])
     el = maxrel(gg["Le"], og["Le"])
-    print(f"D={D}: heights maxrel {eh:.2e}  albedo {ea:.2e}  Le {el:.2e}", flush=True)
+    print(f"{mode} D={D}: heights maxrel {eh:.2e}  albedo {ea:.2e}  Le {el:.2e}", flush=True)
     assert ea <= TOL and el <= TOL
     assert eh <= TOL
