@@ -32,6 +32,7 @@ def parse():
     ap.add_argument("--film", type=int, default=256)
     ap.add_argument("--no-sweep", action="store_true", help="skip the per-method / per-depth sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-caustic", action="store_true", help="skip the attached caustic workload")
     ap.add_argument("--cpu-paths", type=int, default=1 << 15)
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for profiler byte counters)")
@@ -120,10 +121,10 @@ def main():
     except Exception as e:  # the diagnostic build is optional
         print(f"# counters unavailable: {e}", file=sys.stderr)
 
-    def bytes_per_path(c, tape_bytes=0):
+    def bytes_per_path(c, n_sample=None):
         b = (c["nodes"] * B_NODE + c["tris"] * B_TRI + c["splats"] * B_SPLAT + c["gathers"] * B_GATHER
              + c["grad_values"] * B_GRAD + (c["tape_written"] + c["tape_read"]) * B_TAPE)
-        return b / sample
+        return b / (n_sample or sample)
 
     roofline = None
     if "lrb3" in counts:
@@ -170,6 +171,11 @@ def main():
                                          "workspace_bytes": ctx.workspace_bytes(a)}
         torch.cuda.synchronize()
 
+    # ---- attached workload: caustic heightfield slab (gradients w.r.t. heights)
+    caustic = None
+    if not args.no_caustic:
+        caustic = bench_caustic(lt, scenes, dev, stream, bytes_per_path)
+
     # ---- CPU baseline: the FP64 oracle, forward + naive backward, on a sample
     cpu = None
     if not args.no_cpu:
@@ -206,8 +212,80 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "sweep": sweep,
+        "caustic": caustic,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_caustic(lt, scenes, dev, stream, bytes_per_path_fn, G=128, film=512, N=1 << 24, D=6):
+    """Attached workload: glass heightfield slab (G x G heights), film^2,
+    depth D, N paths; forward + loss + attached backward per method."""
+    import numpy as np
+    import torch
+
+    sc = scenes.caustic_scene(G=G, width=film, height=film)
+    ctx = lt.Context(0).scene_upload(sc)
+    albedo = torch.as_tensor(sc["albedo"], dtype=torch.float32, device=dev).contiguous()
+    Le = torch.as_tensor(sc["Le"], dtype=torch.float32, device=dev)
+    h = torch.as_tensor(sc["heights"], dtype=torch.float32, device=dev).contiguous()
+    ht = torch.as_tensor(sc["heights_target"], dtype=torch.float32, device=dev).contiguous()
+    img = torch.empty((film, film, 3), dtype=torch.float32, device=dev)
+    target, dI = torch.empty_like(img), torch.empty_like(img)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    ga, gl, gh = torch.zeros_like(albedo), torch.zeros_like(Le), torch.zeros_like(h)
+    ctx.trace(ctx.args(0x7A6, N, D), ctx.params(albedo, Le, ht), target)
+    p = ctx.params(albedo, Le, h)
+    out = {"workload": f"glass heightfield slab {G}x{G} heights, film {film}x{film}, depth {D}, {N} paths, "
+                       "attached gradients w.r.t. heights"}
+    for mode in ("lrb3", "reslrb", "naive"):
+        rec = lt.RECORD_TAPE if mode == "naive" else lt.RECORD_RESERVOIR if mode == "reslrb" else 0
+        a = ctx.args(100, N, D, lt.ATTACHED | rec)
+        nb = ctx.side_state_bytes(a)
+        side = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev) if nb else None
+        ts, tb = [], []
+        for k in range(4):
+            a = ctx.args(100 + k, N, D, lt.ATTACHED | rec)
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record(stream)
+            ctx.trace(a, p, img, side)
+            ctx.loss_l2(img, target, dI, loss)
+            e[1].record(stream)
+            if mode == "naive":
+                ctx.backward_naive(a, p, dI, side, ga, gl, gh)
+            elif mode == "reslrb":
+                ctx.backward_reslrb(a, p, dI, side, ga, gl, gh)
+            else:
+                ctx.backward_lrb3(a, p, dI, ga, gl, gh)
+            e[2].record(stream)
+            e[2].synchronize()
+            if k:
+                ts.append(e[0].elapsed_time(e[2]))
+                tb.append(e[1].elapsed_time(e[2]))
+        del side
+        ms = float(np.median(ts))
+        out[mode] = {"ms": round(ms, 3), "backward_ms": round(float(np.median(tb)), 3),
+                     "paths_per_s": round(N / (ms * 1e-3)), "side_bytes_per_path": round(nb / N, 2)}
+        print(f"# caustic {mode}: step {ms:.3f} ms (backward {np.median(tb):.3f} ms)", file=sys.stderr, flush=True)
+    # byte model of the attached LRB-3 backward from the counters build
+    try:
+        sample = 1 << 18
+        cctx = lt.Context(0, counters=True).scene_upload(sc)
+        cctx.read_counters(reset=True)
+        a = cctx.args(100, sample, D, lt.ATTACHED)
+        cctx.trace(cctx.args(100, sample, D), p, img)
+        cctx.read_counters(reset=True)
+        cctx.backward_lrb3(a, p, dI, torch.zeros_like(albedo), torch.zeros_like(Le), torch.zeros_like(h))
+        c = cctx.read_counters(reset=True)
+        bpp = bytes_per_path_fn(c, sample)
+        t = out["lrb3"]["backward_ms"] * 1e-3
+        achieved = bpp * N / t / 1e9
+        out["lrb3_roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_path": round(bpp, 1),
+                                "events_per_path": {k: round(v / sample, 3) for k, v in c.items()}}
+        del cctx
+    except Exception as e:
+        print(f"# caustic counters unavailable: {e}", file=sys.stderr)
+    return out
 
 
 if __name__ == "__main__":

@@ -103,3 +103,47 @@ def test_replay_attached_parity(caustic16, D, mode):
     print(f"{mode} D={D}: heights maxrel {eh:.2e}  albedo {ea:.2e}  Le {el:.2e}", flush=True)
     assert ea <= TOL and el <= TOL
     assert eh <= TOL
+
+
+def test_full_size_caustic_sampled():
+    # 128x128 heightfield, 512x512 film, depth 6, 16M paths (the attached
+    # workload at full size, default launch shape): 2048 seeded sample paths
+    # kept by the mask and compared with the oracle on those paths.  The
+    # tolerance is the deep-path one derived for the 256x256 box (FP32
+    # vertex drift mapped to film pixels), applied to heights as well.
+    from tests.gpu_common import GpuRun, maxrel
+    TOL_FULL = 2e-3
+    sc = scenes.caustic_scene(G=128, width=512, height=512)
+    g = GpuRun(sc)
+    n, D, seed = 1 << 24, 6, 31
+    ids = np.sort(np.random.default_rng(3).choice(n, 2048, replace=False)).astype(np.uint32)
+    mask = np.zeros(n, np.uint8)
+    mask[ids] = 1
+    gs = g.trace(seed, n, D, mask=mask, want_sig=True)["sig"][ids]
+    os_ = O.render(sc, seed, n, D, path_list=ids, per_path=True)["sig"]
+    keep = ids[gs == os_]
+    assert len(keep) >= len(ids) - 4
+    mask[:] = 0
+    mask[keep] = 1
+    gi = g.trace(seed, n, D, mask=mask)["image"]
+    oi = O.render(sc, seed, n, D, path_list=keep)["image"]
+    e = maxrel(gi, oi)
+    print(f"caustic full size sampled image maxrel {e:.2e}", flush=True)
+    assert e <= TOL_FULL
+    dI = _dI(gi.shape, 9)
+    first = g.backward("lrb3", seed, n, D, dI, flags=lt.ATTACHED, mask=mask, want_info=True)
+    bad = first["info"] != 0
+    print(f"caustic full size: flagged sample paths {int(bad[keep].sum())} of {len(keep)}", flush=True)
+    mask[bad] = 0
+    keep2 = np.nonzero(mask)[0].astype(np.uint32)
+    og = O.gradient(sc, seed, n, D, dI, flags=O.ATTACHED, path_list=keep2)
+    for mode in ("lrb3", "naive", "reslrb"):
+        omode = O.MODE_RESLRB if mode == "reslrb" else O.MODE_NAIVE
+        ref = og if omode == O.MODE_NAIVE else O.gradient(sc, seed, n, D, dI, mode=omode, flags=O.ATTACHED,
+                                                          path_list=keep2)
+        # the LRB-3 flags cover the other two: ResLRB replays only up to
+        # R <= the last connection, naive vertices past it carry no adjoint
+        gg = g.backward(mode, seed, n, D, dI, flags=lt.ATTACHED, mask=mask)
+        eh = maxrel(gg["heights"], ref["heights"])
+        print(f"caustic full size sampled {mode}: heights maxrel {eh:.2e}", flush=True)
+        assert eh <= TOL_FULL, mode
