@@ -157,6 +157,7 @@ struct lt_ctx {
   uint64_t cap = 0;
   lt_stats stats{};
   int n_cu = 256;
+  int lds_max = 65536;  // dynamic LDS bytes one workgroup may use
   bool has_scene = false;
   Node* d_nodes = nullptr;
   Tri* d_tris = nullptr;
@@ -205,6 +206,15 @@ int persistent_grid(const lt_ctx* c, int64_t n, int block) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Heights gradients go to a per-workgroup LDS copy when it fits next to the
+// traversal stack (256-thread workgroups).
+int hgrad_in_lds(const lt_ctx* c, const float* g_heights, bool with_stack) {
+  if (!g_heights || c->dsc.hf_G < 2) return 0;
+  size_t need = (size_t)c->dsc.hf_G * c->dsc.hf_G * sizeof(float) +
+                (with_stack ? (size_t)c->dsc.stack_n * 256 * sizeof(int) : 0);
+  return need <= (size_t)c->lds_max ? 1 : 0;
+}
 
 struct SideLayout { size_t tape = 0, len = 0, emit = 0, res = 0, total = 0; };
 
@@ -267,6 +277,7 @@ PassArgs base_args(lt_ctx* c, const lt_trace_args* a, const lt_params* p) {
   A.Kfilm = (float)Kfilm;
   A.emit_factor = c->emit_factor;
   A.n_texels = c->dsc.n_tex * c->dsc.tex_res * c->dsc.tex_res;
+  A.hgrad_lds = 0;
   A.mask = a->path_mask;
   A.sig = a->path_sig;
   A.info = a->path_info;
@@ -306,6 +317,13 @@ lt_status lt_create(int device, void* stream, lt_ctx** out) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->n_cu = prop.multiProcessorCount;
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+    c->lds_max = lds;
+  if (set_lds_limit(c->lds_max) != hipSuccess) {
+    (void)hipGetLastError();
+    c->lds_max = 65536;
+  }
   if (hipMalloc((void**)&c->d_counter, 256) != hipSuccess || hipMalloc((void**)&c->d_acc, 256) != hipSuccess) {
     hipFree(c->d_counter); hipFree(c->d_acc);
     delete c;
@@ -337,7 +355,7 @@ lt_status lt_set_tuning(lt_ctx* c, const lt_tuning* t) {
   if (!t) { c->tune = lt_tuning{256, 4, 0}; return LT_OK; }
   if (t->block < 64 || t->block > 1024 || (t->block % 64) != 0) return c->fail(LT_ERR_ARG, "block must be 64..1024, a multiple of 64%s");
   if (t->blocks_per_cu < 1 || t->blocks_per_cu > 64) return c->fail(LT_ERR_ARG, "blocks_per_cu must be 1..64%s");
-  if ((size_t)kStackMax * t->block * sizeof(int) > 65536) return c->fail(LT_ERR_ARG, "traversal stack exceeds 64 KiB of LDS%s");
+  if ((size_t)kStackMax * t->block * sizeof(int) > (size_t)c->lds_max) return c->fail(LT_ERR_ARG, "traversal stack exceeds the LDS of a workgroup%s");
   c->tune = *t;
   return LT_OK;
 }
@@ -535,6 +553,7 @@ lt_status lt_scene_upload(lt_ctx* c, const lt_scene_desc* s) {
   d.aspect = (float)((double)s->width / (double)s->height);
   d.film_area = (float)(4.0 * ((double)s->width / s->height) * th * th);
   d.W = s->width; d.H = s->height;
+  d.stack_n = maxd + 2;
   c->has_scene = true;
   c->err.clear();
   return c->hip(hipStreamSynchronize(c->stream), "scene upload sync");
@@ -633,6 +652,7 @@ lt_status lt_backward_naive(lt_ctx* c, const lt_trace_args* a, const lt_params* 
   int grid = (int)std::max<int64_t>(1, std::min<int64_t>((a->n_paths + 255) / 256, (int64_t)c->n_cu * 16));
   if (a->flags & LT_ATTACHED) {
     A.emit_d = (float*)(sb + L.emit);
+    A.hgrad_lds = hgrad_in_lds(c, g->heights, false);
     if ((st = c->hip(launch_naive_att_bwd(A, grid, c->stream), "naive attached backward")) != LT_OK) return st;
   } else if ((st = c->hip(launch_naive_bwd(A, grid, c->stream), "naive backward")) != LT_OK) {
     return st;
@@ -653,6 +673,7 @@ lt_status lt_backward_reslrb(lt_ctx* c, const lt_trace_args* a, const lt_params*
   if (a->flags & LT_ATTACHED) {
     A.res_att_in = (const ResRecAtt*)((const char*)records + L.res);
     int grid = persistent_grid(c, a->n_paths, 256);
+    A.hgrad_lds = hgrad_in_lds(c, g->heights, true);
     if ((st = c->hip(launch_reslrb_att(A, grid, c->stream), "reslrb attached backward")) != LT_OK) return st;
     return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
   }
@@ -671,6 +692,7 @@ lt_status lt_backward_lrb3(lt_ctx* c, const lt_trace_args* a, const lt_params* p
   if ((st = check_cap(c, 0)) != LT_OK) return st;
   if (a->flags & LT_ATTACHED) {
     int grid = persistent_grid(c, a->n_paths, 256);
+    A.hgrad_lds = hgrad_in_lds(c, g->heights, true);
     if ((st = c->hip(launch_lrb3_att(A, grid, c->stream), "lrb3 attached backward")) != LT_OK) return st;
   } else {
     int grid = persistent_grid(c, a->n_paths, c->tune.block);

@@ -95,6 +95,7 @@ struct DevScene {
   float cpos[3], cf[3], cr[3], cu[3];
   float tan_half, aspect, film_area;
   int32_t W, H;
+  int32_t stack_n;  // traversal stack entries per lane (BVH depth + 2)
 };
 
 }  // namespace lt

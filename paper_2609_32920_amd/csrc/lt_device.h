@@ -383,6 +383,29 @@ __device__ __forceinline__ void scatter3_wave(float* dst, bool has, int idx, f3 
   if (m == 0ull) return;
   LT_COUNT(6, has ? 3 : 0);
   const int lane = __lane_id();
+  // Same-address atomics serialize: when many lanes target the index of
+  // the first pending lane (a small or constant texture), sum them across
+  // the wave first and let one lane commit.
+  for (int rep = 0; rep < 2 && m; ++rep) {
+    int lead = __ffsll((unsigned long long)m) - 1;
+    int li = __shfl(idx, lead);
+    bool mine = has && ((m >> lane) & 1ull) && idx == li;
+    uint64_t same = __ballot(mine);
+    if (__popcll(same) < 8) break;
+    float s0 = mine ? v.x : 0.f, s1 = mine ? v.y : 0.f, s2 = mine ? v.z : 0.f;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      s0 += __shfl_xor(s0, o); s1 += __shfl_xor(s1, o); s2 += __shfl_xor(s2, o);
+    }
+    if (lane == lead) {
+      if (s0 != 0.f) atomicAdd(dst + (size_t)li * 3 + 0, s0);
+      if (s1 != 0.f) atomicAdd(dst + (size_t)li * 3 + 1, s1);
+      if (s2 != 0.f) atomicAdd(dst + (size_t)li * 3 + 2, s2);
+    }
+    m &= ~same;
+  }
+  if (m == 0ull) return;
+  has = has && ((m >> lane) & 1ull);
   const int slot = lane / 3, ch = lane - slot * 3;
   while (m) {
     uint64_t mm = m;

@@ -492,25 +492,38 @@ __global__ void k_refit_level(Node* nodes, const Tri* tris, const int32_t* level
 #include "lt_attached.inc"
 
 // ---------------------------------------------------------------- launchers
-static size_t stack_bytes(int block) { return (size_t)kStackMax * block * sizeof(int); }
+static size_t stack_bytes(const PassArgs& A, int block) { return (size_t)A.sc.stack_n * block * sizeof(int); }
+static size_t hgrad_bytes(const PassArgs& A) {
+  return A.hgrad_lds ? (size_t)A.sc.hf_G * A.sc.hf_G * sizeof(float) : 0;
+}
+
+// allow the attached kernels the device's full LDS per workgroup
+hipError_t set_lds_limit(int bytes) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_lrb3_att, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_reslrb_att, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_naive_att_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  return e;
+}
 
 hipError_t launch_lrb3_att(const PassArgs& A, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_lrb3_att, dim3(grid), dim3(256), stack_bytes(256), s, A);
+  hipLaunchKernelGGL(k_lrb3_att, dim3(grid), dim3(256), stack_bytes(A, 256) + hgrad_bytes(A), s, A);
   return hipGetLastError();
 }
 hipError_t launch_trace_att(const PassArgs& A, bool tape, bool resv, int grid, hipStream_t s) {
-  size_t sh = stack_bytes(256);
+  size_t sh = stack_bytes(A, 256);
   if (tape && resv) hipLaunchKernelGGL((k_trace_att<true, true>), dim3(grid), dim3(256), sh, s, A);
   else if (tape) hipLaunchKernelGGL((k_trace_att<true, false>), dim3(grid), dim3(256), sh, s, A);
   else hipLaunchKernelGGL((k_trace_att<false, true>), dim3(grid), dim3(256), sh, s, A);
   return hipGetLastError();
 }
 hipError_t launch_naive_att_bwd(const PassArgs& A, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_naive_att_bwd, dim3(grid), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(k_naive_att_bwd, dim3(grid), dim3(256), hgrad_bytes(A), s, A);
   return hipGetLastError();
 }
 hipError_t launch_reslrb_att(const PassArgs& A, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_reslrb_att, dim3(grid), dim3(256), stack_bytes(256), s, A);
+  hipLaunchKernelGGL(k_reslrb_att, dim3(grid), dim3(256), stack_bytes(A, 256) + hgrad_bytes(A), s, A);
   return hipGetLastError();
 }
 
@@ -529,7 +542,7 @@ hipError_t read_counters(uint64_t* out, bool reset, hipStream_t s) {
 }
 
 hipError_t launch_trace(const PassArgs& A, bool tape, bool resv, int grid, int block, hipStream_t s) {
-  size_t sh = stack_bytes(block);
+  size_t sh = stack_bytes(A, block);
   if (tape && resv) hipLaunchKernelGGL((k_trace<true, true>), dim3(grid), dim3(block), sh, s, A);
   else if (tape) hipLaunchKernelGGL((k_trace<true, false>), dim3(grid), dim3(block), sh, s, A);
   else if (resv) hipLaunchKernelGGL((k_trace<false, true>), dim3(grid), dim3(block), sh, s, A);
@@ -543,12 +556,12 @@ hipError_t launch_naive_bwd(const PassArgs& A, int grid, hipStream_t s) {
 }
 
 hipError_t launch_reslrb_bwd(const PassArgs& A, int grid, int block, hipStream_t s) {
-  hipLaunchKernelGGL(k_reslrb_bwd, dim3(grid), dim3(block), stack_bytes(block), s, A);
+  hipLaunchKernelGGL(k_reslrb_bwd, dim3(grid), dim3(block), stack_bytes(A, block), s, A);
   return hipGetLastError();
 }
 
 hipError_t launch_lrb3_bwd(const PassArgs& A, int grid, int block, hipStream_t s) {
-  hipLaunchKernelGGL(k_lrb3_bwd, dim3(grid), dim3(block), stack_bytes(block), s, A);
+  hipLaunchKernelGGL(k_lrb3_bwd, dim3(grid), dim3(block), stack_bytes(A, block), s, A);
   return hipGetLastError();
 }
 

@@ -41,6 +41,7 @@ struct PassArgs {
   double* g_Le_acc;
   float* g_heights;
   unsigned long long* stats;  // [0] guard triggers, [1] non-finite drops
+  int32_t hgrad_lds;          // heights gradients accumulated per workgroup in LDS
 };
 
 hipError_t launch_trace(const PassArgs& A, bool tape, bool resv, int grid, int block, hipStream_t s);
@@ -59,6 +60,7 @@ hipError_t launch_loss(const float* I, const float* T, size_t n, float* dI, doub
                        hipStream_t s);
 hipError_t launch_hf_tris(const DevScene& sc, const int32_t* slot_of_prim, Tri* tris, const float* h,
                           hipStream_t s);
+hipError_t set_lds_limit(int bytes);
 hipError_t read_counters(uint64_t* out, bool reset, hipStream_t s);
 hipError_t launch_refit_level(Node* nodes, const Tri* tris, const int32_t* level_nodes, int n, hipStream_t s);
 
