@@ -179,6 +179,8 @@ typedef struct {
 typedef struct {
   uint64_t seed; int64_t n_paths; int32_t max_depth; int32_t flags; int32_t n_threads;
   const uint32_t* path_list; int64_t n_list;   // NULL: all paths [0, n_paths)
+  const double* guide_w;   // emission-guide weights [11433] or NULL (cosine emission)
+  int32_t guide_bf16;      // 1: round MLP operands to bfloat16 where the GPU does
 } ora_args;
 
 }  // extern "C"
@@ -187,6 +189,222 @@ namespace {
 
 const double kTmin = 1e-4, kEps = 1e-4, kInvPi = 0.31830988618379067154;
 const double kLumR = 0.2126, kLumG = 0.7152, kLumB = 0.0722;
+
+// ----------------------------------------------------------------- guide
+// Learned emission guide (an extension; the paper samples emission
+// cosine-weighted).  A multilayer perceptron 6 -> 64 -> 64 -> 64 -> 41 maps a
+// light vertex (position normalised to the scene box, unit normal) to a
+// mixture of 8 von Mises-Fisher lobes {mean m_k (3), log-concentration (1),
+// logit (1)} and a mixing weight logit.  The sampling density is
+//   q(w) = alpha * sum_k pi_k [v_k(w) + v_k(mirror(w))] + (1 - alpha) max(w.n, 0) / pi,
+// the lobes folded onto the emitting hemisphere by the mirror about the
+// emitter plane, with alpha = 0.9 sigmoid(o_40) so that the cosine part
+// always keeps at least a tenth of the mass (bounded weights, positive
+// density wherever emission is).  Parameter layout, row-major (out, in):
+//   W1[64][6] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[41][64] b4[41].
+// The GPU multiplies in bfloat16 with FP32 accumulation; with bf16 = true the
+// oracle rounds exactly the operands the GPU rounds (weights, layer inputs,
+// backward adjoints entering a product) and keeps everything else in FP64.
+constexpr int kGIn = 6, kGH = 64, kGOut = 41, kGLobes = 8;
+constexpr long kGW1 = 0, kGB1 = kGW1 + kGH * kGIn, kGW2 = kGB1 + kGH, kGB2 = kGW2 + kGH * kGH,
+               kGW3 = kGB2 + kGH, kGB3 = kGW3 + kGH * kGH, kGW4 = kGB3 + kGH, kGB4 = kGW4 + kGOut * kGH,
+               kGN = kGB4 + kGOut;
+const double kLogKMin = -3.0, kLogKMax = 8.0, kAlphaMax = 0.9;
+
+// Round to the nearest bfloat16 (8 significant bits), ties to even.
+double bf16r(double x) {
+  if (x == 0.0 || !std::isfinite(x)) return x;
+  int e; std::frexp(x, &e);          // |x| in [2^(e-1), 2^e)
+  double q = std::ldexp(1.0, e - 8);  // spacing of 8-bit significands there
+  return std::nearbyint(x / q) * q;
+}
+
+struct GuideAct {
+  double in[kGIn];
+  double z1[kGH], h1[kGH], z2[kGH], h2[kGH], z3[kGH], h3[kGH];
+  double o[kGOut];
+};
+
+// z[o] = sum_i W[o][i] x[i] + b[o], operands rounded when bf.
+void glayer(const double* W, const double* b, const double* x, int n_in, int n_out, bool bf, double* z) {
+  for (int o = 0; o < n_out; ++o) {
+    double s = 0.0;
+    for (int i = 0; i < n_in; ++i) s += (bf ? bf16r(W[o * n_in + i]) * bf16r(x[i]) : W[o * n_in + i] * x[i]);
+    z[o] = s + b[o];
+  }
+}
+
+void guide_forward(const double* w, const double feat[kGIn], bool bf, GuideAct& a) {
+  for (int i = 0; i < kGIn; ++i) a.in[i] = feat[i];
+  glayer(w + kGW1, w + kGB1, a.in, kGIn, kGH, bf, a.z1);
+  for (int i = 0; i < kGH; ++i) a.h1[i] = std::max(a.z1[i], 0.0);
+  glayer(w + kGW2, w + kGB2, a.h1, kGH, kGH, bf, a.z2);
+  for (int i = 0; i < kGH; ++i) a.h2[i] = std::max(a.z2[i], 0.0);
+  glayer(w + kGW3, w + kGB3, a.h2, kGH, kGH, bf, a.z3);
+  for (int i = 0; i < kGH; ++i) a.h3[i] = std::max(a.z3[i], 0.0);
+  glayer(w + kGW4, w + kGB4, a.h3, kGH, kGOut, bf, a.o);
+}
+
+// Scene box used to normalise guide positions: static triangles, the
+// heightfield footprint at its base height and the emitter's corners.
+void scene_box(const ora_scene* sc, double c[3], double h[3]) {
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  auto add = [&](double x, double y, double z) {
+    double p[3] = {x, y, z};
+    for (int k = 0; k < 3; ++k) { lo[k] = std::min(lo[k], p[k]); hi[k] = std::max(hi[k], p[k]); }
+  };
+  for (long i = 0; i < (long)sc->n_tris * 3; ++i) add(sc->tri_v[i * 3], sc->tri_v[i * 3 + 1], sc->tri_v[i * 3 + 2]);
+  if (sc->hf_G > 1) {
+    double ext = (sc->hf_G - 1) * sc->hf_dx;
+    add(sc->hf_x0, sc->hf_base, sc->hf_z0);
+    add(sc->hf_x0 + ext, sc->hf_base, sc->hf_z0 + ext);
+  }
+  const double* o = sc->em_o; const double* e1 = sc->em_e1; const double* e2 = sc->em_e2;
+  add(o[0], o[1], o[2]);
+  if (sc->em_type == ORA_EMIT_QUAD) {
+    add(o[0] + e1[0], o[1] + e1[1], o[2] + e1[2]);
+    add(o[0] + e2[0], o[1] + e2[1], o[2] + e2[2]);
+    add(o[0] + e1[0] + e2[0], o[1] + e1[1] + e2[1], o[2] + e1[2] + e2[2]);
+  }
+  for (int k = 0; k < 3; ++k) { c[k] = 0.5 * (lo[k] + hi[k]); h[k] = 0.5 * (hi[k] - lo[k]); }
+}
+
+void guide_features(const double c[3], const double h[3], D3 x, D3 n, double f[kGIn]) {
+  double p[3] = {x.x, x.y, x.z};
+  for (int k = 0; k < 3; ++k) f[k] = h[k] > 0.0 ? (p[k] - c[k]) / h[k] : 0.0;
+  f[3] = n.x; f[4] = n.y; f[5] = n.z;
+}
+
+struct Mixture {
+  D3 mu[kGLobes]; double mlen[kGLobes], kappa[kGLobes], pi[kGLobes];
+  bool kfree[kGLobes];  // log-concentration inside its clamp range
+  double alpha, sig;    // alpha = kAlphaMax * sig
+};
+
+Mixture mixture_of(const double o[kGOut]) {
+  Mixture m;
+  double lmax = -1e300;
+  for (int k = 0; k < kGLobes; ++k) lmax = std::max(lmax, o[5 * k + 4]);
+  double z = 0.0;
+  for (int k = 0; k < kGLobes; ++k) {
+    const double* q = o + 5 * k;
+    double l = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+    m.mlen[k] = l;
+    m.mu[k] = l > 0.0 ? D3{q[0] / l, q[1] / l, q[2] / l} : D3{0.0, 0.0, 1.0};
+    double lk = q[3];
+    m.kfree[k] = lk > kLogKMin && lk < kLogKMax;
+    m.kappa[k] = std::exp(std::min(std::max(lk, kLogKMin), kLogKMax));
+    m.pi[k] = std::exp(q[4] - lmax);
+    z += m.pi[k];
+  }
+  for (int k = 0; k < kGLobes; ++k) m.pi[k] /= z;
+  m.sig = 1.0 / (1.0 + std::exp(-o[40]));
+  m.alpha = kAlphaMax * m.sig;
+  return m;
+}
+
+// von Mises-Fisher density on the unit sphere.
+double vmf(D3 mu, double kappa, D3 w) {
+  return kappa / (2.0 * M_PI * -std::expm1(-2.0 * kappa)) * std::exp(kappa * (dot(mu, w) - 1.0));
+}
+
+D3 mirror(D3 w, D3 n) { return w - n * (2.0 * dot(w, n)); }
+
+double guide_pdf(const Mixture& m, D3 n, D3 w) {
+  double c = dot(w, n);
+  if (c < 0.0) return 0.0;
+  D3 wm = mirror(w, n);
+  double V = 0.0;
+  for (int k = 0; k < kGLobes; ++k) V += m.pi[k] * (vmf(m.mu[k], m.kappa[k], w) + vmf(m.mu[k], m.kappa[k], wm));
+  return m.alpha * V + (1.0 - m.alpha) * c * kInvPi;
+}
+
+// Draw a direction from the folded mixture with uniforms g0 (component),
+// g1, g2 (direction).  comp: 0 cosine part, k + 1 lobe k.
+// vMF sampling by inverting the cosine marginal (Wood 1994; Jakob 2012):
+// t = 1 + log(xi + (1 - xi) e^{-2 kappa}) / kappa with xi = 1 - g1 in (0, 1].
+D3 guide_sample(const Mixture& m, D3 n, double g0, double g1, double g2, int& comp) {
+  if (g0 >= m.alpha) {
+    comp = 0;
+    double rr = std::sqrt(g1), phi = 2.0 * M_PI * g2;
+    D3 t1, t2; onb(n, t1, t2);
+    return t1 * (rr * std::cos(phi)) + t2 * (rr * std::sin(phi)) + n * std::sqrt(std::max(0.0, 1.0 - g1));
+  }
+  double v = g0 / m.alpha, acc = 0.0;
+  int k = kGLobes - 1;
+  for (int i = 0; i < kGLobes; ++i) { acc += m.pi[i]; if (v < acc) { k = i; break; } }
+  comp = k + 1;
+  double kap = m.kappa[k], xi = 1.0 - g1;
+  double t = 1.0 + std::log(xi + (1.0 - xi) * std::exp(-2.0 * kap)) / kap;
+  t = std::min(std::max(t, -1.0), 1.0);
+  double s = std::sqrt(std::max(0.0, 1.0 - t * t)), phi = 2.0 * M_PI * g2;
+  D3 t1, t2; onb(m.mu[k], t1, t2);
+  D3 w = m.mu[k] * t + t1 * (s * std::cos(phi)) + t2 * (s * std::sin(phi));
+  if (dot(w, n) < 0.0) w = mirror(w, n);
+  return w;
+}
+
+// d(-c log q(w))/d o for one sample; returns -c log q (0 when q <= 0).
+double guide_loss_grad_o(const double o[kGOut], D3 n, D3 w, double c, double g[kGOut]) {
+  for (int i = 0; i < kGOut; ++i) g[i] = 0.0;
+  if (c == 0.0) return 0.0;
+  Mixture m = mixture_of(o);
+  double q = guide_pdf(m, n, w);
+  if (!(q > 0.0)) return 0.0;
+  double cosp = std::max(dot(w, n), 0.0) * kInvPi;
+  D3 wm = mirror(w, n);
+  D3 ws[2] = {w, wm};
+  double Vk[kGLobes], V = 0.0;
+  for (int k = 0; k < kGLobes; ++k) {
+    Vk[k] = vmf(m.mu[k], m.kappa[k], w) + vmf(m.mu[k], m.kappa[k], wm);
+    V += m.pi[k] * Vk[k];
+  }
+  double s = -c / q;  // d(-c log q)/dq
+  // alpha = kAlphaMax * sigmoid(o_40)
+  g[40] = s * (V - cosp) * kAlphaMax * m.sig * (1.0 - m.sig);
+  for (int k = 0; k < kGLobes; ++k) {
+    double wk = s * m.alpha * m.pi[k];
+    g[5 * k + 4] = s * m.alpha * m.pi[k] * (Vk[k] - V);  // softmax logits
+    double kap = m.kappa[k], dk = 0.0;
+    double gm[3] = {0.0, 0.0, 0.0};
+    for (int r = 0; r < 2; ++r) {
+      double mw = dot(m.mu[k], ws[r]);
+      double v = vmf(m.mu[k], kap, ws[r]);
+      dk += v * (1.0 / kap - 2.0 / std::expm1(2.0 * kap) + (mw - 1.0));
+      if (m.mlen[k] > 0.0) {
+        D3 t = (ws[r] - m.mu[k] * mw) * (v * kap / m.mlen[k]);
+        gm[0] += t.x; gm[1] += t.y; gm[2] += t.z;
+      }
+    }
+    g[5 * k + 3] = m.kfree[k] ? wk * dk * kap : 0.0;
+    for (int a = 0; a < 3; ++a) g[5 * k + a] = wk * gm[a];
+  }
+  return -c * std::log(q);
+}
+
+// Accumulate the parameter gradient of one sample given d(loss)/d(outputs).
+void guide_backward(const double* w, const GuideAct& a, const double go[kGOut], bool bf, double* grad) {
+  auto r = [bf](double x) { return bf ? bf16r(x) : x; };
+  double dz4[kGOut], dz3[kGH], dz2[kGH], dz1[kGH];
+  for (int o = 0; o < kGOut; ++o) dz4[o] = go[o];
+  auto back = [&](const double* W, int n_in, int n_out, const double* dz, const double* xin, long oW, long oB,
+                  const double* zprev, double* dzprev) {
+    for (int o = 0; o < n_out; ++o) {
+      grad[oB + o] += dz[o];
+      for (int i = 0; i < n_in; ++i) grad[oW + (long)o * n_in + i] += r(dz[o]) * r(xin[i]);
+    }
+    if (!dzprev) return;
+    for (int i = 0; i < n_in; ++i) {
+      double s = 0.0;
+      for (int o = 0; o < n_out; ++o) s += r(W[(long)o * n_in + i]) * r(dz[o]);
+      dzprev[i] = zprev[i] > 0.0 ? s : 0.0;
+    }
+  };
+  back(w + kGW4, kGH, kGOut, dz4, a.h3, kGW4, kGB4, a.z3, dz3);
+  back(w + kGW3, kGH, kGH, dz3, a.h2, kGW3, kGB3, a.z2, dz2);
+  back(w + kGW2, kGH, kGH, dz2, a.h1, kGW2, kGB2, a.z1, dz1);
+  back(w + kGW1, kGIn, kGH, dz1, a.in, kGW1, kGB1, nullptr, nullptr);
+}
 
 struct Scene {
   const ora_scene* s;
@@ -197,6 +415,7 @@ struct Scene {
   std::vector<D3> tv;   // [n_all][3] primal vertex positions
   // camera frame
   D3 cpos, f, r, u; double tan_half, aspect, K_area;
+  double gc[3], gh[3];  // guide position normalisation (scene box centre, half extent)
 
   int hf_corner(int tri, int k, int& gi, int& gj) const {
     // heightfield triangle -> grid corner (gi, gj); returns 1 if on heightfield
@@ -243,6 +462,7 @@ struct Scene {
     u = cross(r, f);
     tan_half = std::tan(sc->cam_fov_deg * M_PI / 360.0);
     aspect = (double)sc->width / (double)sc->height;
+    scene_box(sc, gc, gh);
   }
 
   int mat_of(int tri) const { return tri < n_static ? s->tri_mat[tri] : s->hf_mat; }
@@ -325,7 +545,18 @@ void trace_path(const Scene& S, const ora_args& A, uint32_t path, PathResult& ou
     D3 t1, t2; onb(ne, t1, t2);
     w0 = t1 * lx + t2 * ly + ne * lz;
     n_off = ne; has_off = true;
-    for (int c = 0; c < 3; ++c) beta[c] = Le[c] * V(area * M_PI);
+    double fac = area * M_PI;
+    if (A.guide_w) {  // guided emission: direction from the mixture, weight cos / q
+      double feat[kGIn]; guide_features(S.gc, S.gh, x0, ne, feat);
+      GuideAct act; guide_forward(A.guide_w, feat, A.guide_bf16 != 0, act);
+      Mixture m = mixture_of(act.o);
+      Uniform4 g = rng4(A.seed, path, 0, 1);
+      int comp;
+      w0 = guide_sample(m, ne, g.u[0], g.u[1], g.u[2], comp);
+      double q = guide_pdf(m, ne, w0);
+      fac = q > 0.0 ? area * dot(w0, ne) / q : 0.0;
+    }
+    for (int c = 0; c < 3; ++c) beta[c] = Le[c] * V(fac);
   } else {
     x0 = {sc.em_o[0], sc.em_o[1], sc.em_o[2]};
     double z = 1.0 - 2.0 * u0.u[2];
@@ -534,6 +765,7 @@ int ora_reservoir(const double* w, const double* u, int k, double* W_out) {
 int ora_render(const ora_scene* sc, const ora_args* A, const double* albedo, const double* Le,
                const double* heights, double* image, double* slices, uint32_t* sig, int32_t* Rout,
                double* Wout, double* flux) {
+  if (A->guide_w && sc->em_type != ORA_EMIT_QUAD) return -1;  // the guide steers area emission only
   Scene S; S.init(sc, albedo, Le, heights, false);
   const int W = sc->width, H = sc->height, D = A->max_depth;
   const long npix = (long)W * H * 3;
@@ -589,6 +821,7 @@ int ora_render(const ora_scene* sc, const ora_args* A, const double* albedo, con
 int ora_gradient(const ora_scene* sc, const ora_args* A, int mode, const double* albedo,
                  const double* Le, const double* heights, const double* dI, double* g_albedo,
                  double* g_Le, double* g_heights) {
+  if (A->guide_w && sc->em_type != ORA_EMIT_QUAD) return -1;
   Scene S; S.init(sc, albedo, Le, heights, (A->flags & ORA_F_ATTACHED) != 0);
   const int W = sc->width, H = sc->height;
   const int64_t n = A->path_list ? A->n_list : A->n_paths;
@@ -641,6 +874,97 @@ int ora_gradient(const ora_scene* sc, const ora_args* A, int mode, const double*
     else if (q < n_alb + 3) { if (g_Le) g_Le[q - n_alb] += s; }
     else if (g_heights) g_heights[q - n_alb - 3] += s;
   }
+  return 0;
+}
+
+// ----------------------------------------------------------------- guide API
+int ora_guide_nparams() { return (int)kGN; }
+
+// Raw network outputs [count][41] for positions x and unit normals n [count][3].
+int ora_guide_eval(const ora_scene* sc, const double* w, const double* x, const double* n, int64_t count,
+                   int bf16, double* out) {
+  double c[3], h[3]; scene_box(sc, c, h);
+  for (int64_t i = 0; i < count; ++i) {
+    double f[kGIn];
+    guide_features(c, h, {x[i * 3], x[i * 3 + 1], x[i * 3 + 2]}, {n[i * 3], n[i * 3 + 1], n[i * 3 + 2]}, f);
+    GuideAct a; guide_forward(w, f, bf16 != 0, a);
+    for (int k = 0; k < kGOut; ++k) out[i * kGOut + k] = a.o[k];
+  }
+  return 0;
+}
+
+// Folded mixture density of raw outputs o [count][41] at directions wd.
+int ora_guide_pdf(const double* o, const double* n, const double* wd, int64_t count, double* pdf) {
+  for (int64_t i = 0; i < count; ++i) {
+    Mixture m = mixture_of(o + i * kGOut);
+    pdf[i] = guide_pdf(m, {n[i * 3], n[i * 3 + 1], n[i * 3 + 2]}, {wd[i * 3], wd[i * 3 + 1], wd[i * 3 + 2]});
+  }
+  return 0;
+}
+
+// Directions drawn from raw outputs o with uniforms g [count][3].
+int ora_guide_sample(const double* o, const double* n, const double* g, int64_t count, double* wd, int32_t* comp) {
+  for (int64_t i = 0; i < count; ++i) {
+    Mixture m = mixture_of(o + i * kGOut);
+    int cp;
+    D3 w = guide_sample(m, {n[i * 3], n[i * 3 + 1], n[i * 3 + 2]}, g[i * 3], g[i * 3 + 1], g[i * 3 + 2], cp);
+    wd[i * 3] = w.x; wd[i * 3 + 1] = w.y; wd[i * 3 + 2] = w.z;
+    if (comp) comp[i] = cp;
+  }
+  return 0;
+}
+
+// Guided emission samples of the listed paths (A->path_list, else [0, n_paths)):
+// rec [n][8] = position x0 (3), direction (3), density q, emission factor
+// A cos / q (beta_1 = L_e * factor); comp [n] as in ora_guide_sample.
+int ora_guide_emit(const ora_scene* sc, const ora_args* A, double* rec, int32_t* comp) {
+  if (!A->guide_w || sc->em_type != ORA_EMIT_QUAD) return -1;
+  double c[3], h[3]; scene_box(sc, c, h);
+  D3 o = {sc->em_o[0], sc->em_o[1], sc->em_o[2]};
+  D3 e1 = {sc->em_e1[0], sc->em_e1[1], sc->em_e1[2]}, e2 = {sc->em_e2[0], sc->em_e2[1], sc->em_e2[2]};
+  D3 cr = cross(e1, e2);
+  double area = std::sqrt(dot(cr, cr));
+  D3 ne = cr * (1.0 / area);
+  const int64_t n = A->path_list ? A->n_list : A->n_paths;
+  for (int64_t k = 0; k < n; ++k) {
+    uint32_t path = A->path_list ? A->path_list[k] : (uint32_t)k;
+    Uniform4 u0 = rng4(A->seed, path, 0, 0);
+    D3 x0 = o + e1 * u0.u[0] + e2 * u0.u[1];
+    double f[kGIn]; guide_features(c, h, x0, ne, f);
+    GuideAct a; guide_forward(A->guide_w, f, A->guide_bf16 != 0, a);
+    Mixture m = mixture_of(a.o);
+    Uniform4 g = rng4(A->seed, path, 0, 1);
+    int cp;
+    D3 w = guide_sample(m, ne, g.u[0], g.u[1], g.u[2], cp);
+    double q = guide_pdf(m, ne, w);
+    double* r = rec + k * 8;
+    r[0] = x0.x; r[1] = x0.y; r[2] = x0.z; r[3] = w.x; r[4] = w.y; r[5] = w.z;
+    r[6] = q; r[7] = q > 0.0 ? area * dot(w, ne) / q : 0.0;
+    if (comp) comp[k] = cp;
+  }
+  return 0;
+}
+
+// Training loss L = -(1/count) sum_b (S_b / q_b) log q_theta(w_b | x_b, n_b) and
+// its gradient w.r.t. the parameters (added to grad [11433]).
+// samples [count][12] = x (3), n (3), w (3), q (sampling density), S, unused.
+int ora_guide_loss_grad(const ora_scene* sc, const double* w, const double* samples, int64_t count, int bf16,
+                        double* grad, double* loss) {
+  double c[3], h[3]; scene_box(sc, c, h);
+  double L = 0.0;
+  for (int64_t b = 0; b < count; ++b) {
+    const double* s = samples + b * 12;
+    double qs = s[9], S = s[10];
+    if (!(qs > 0.0) || S == 0.0) continue;
+    double f[kGIn];
+    D3 nn = {s[3], s[4], s[5]};
+    guide_features(c, h, {s[0], s[1], s[2]}, nn, f);
+    GuideAct a; guide_forward(w, f, bf16 != 0, a);
+    double go[kGOut];
+    L += guide_loss_grad_o(a.o, nn, {s[6], s[7], s[8]}, S / (qs * (double)count), go);
+    guide_backward(w, a, go, bf16 != 0, grad);
+  }
+  if (loss) *loss = L;
   return 0;
 }
 

@@ -10,6 +10,9 @@ Functions mirror the oracle's C entry points:
   loss_and_adjoint(I, T)  mean-squared error and dLoss/dI
   reservoir(w, u)       capacity-one weighted reservoir (Eq. 8)
   philox(seed, ctr)     Philox-4x32-10 block (Salmon et al. 2011)
+  guide_*               the learned emission guide (an extension: MLP to a
+                        folded vMF mixture, its sampler and density, the
+                        training loss gradient) and plain Adam
 """
 from __future__ import annotations
 
@@ -58,7 +61,12 @@ class _Scene(C.Structure):
 class _Args(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("n_paths", C.c_int64), ("max_depth", C.c_int32),
                 ("flags", C.c_int32), ("n_threads", C.c_int32),
-                ("path_list", C.POINTER(C.c_uint32)), ("n_list", C.c_int64)]
+                ("path_list", C.POINTER(C.c_uint32)), ("n_list", C.c_int64),
+                ("guide_w", C.POINTER(C.c_double)), ("guide_bf16", C.c_int32)]
+
+
+GUIDE_NPARAMS = 11433
+GUIDE_OUT = 41
 
 
 _lib = None
@@ -76,6 +84,15 @@ def _load():
         _lib.ora_reservoir.argtypes = [dp, dp, C.c_int, dp]
         _lib.ora_reservoir.restype = C.c_int
         _lib.ora_philox.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, up]
+        _lib.ora_render.restype = C.c_int
+        _lib.ora_gradient.restype = C.c_int
+        _lib.ora_guide_eval.argtypes = [C.POINTER(_Scene), dp, dp, dp, C.c_int64, C.c_int, dp]
+        _lib.ora_guide_pdf.argtypes = [dp, dp, dp, C.c_int64, dp]
+        _lib.ora_guide_sample.argtypes = [dp, dp, dp, C.c_int64, dp, ip]
+        _lib.ora_guide_emit.argtypes = [C.POINTER(_Scene), C.POINTER(_Args), dp, ip]
+        _lib.ora_guide_emit.restype = C.c_int
+        _lib.ora_guide_loss_grad.argtypes = [C.POINTER(_Scene), dp, dp, C.c_int64, C.c_int, dp, dp]
+        assert _lib.ora_guide_nparams() == GUIDE_NPARAMS
     return _lib
 
 
@@ -127,8 +144,14 @@ def _scene(sc, keep):
     return s
 
 
-def _args(seed, n_paths, depth, flags, threads, path_list, keep):
+def _args(seed, n_paths, depth, flags, threads, path_list, keep, guide_w=None, guide_bf16=True):
     a = _Args()
+    if guide_w is not None:
+        gw = keep.f64(guide_w)
+        assert gw.size == GUIDE_NPARAMS
+        a.guide_w, a.guide_bf16 = _p(gw), int(bool(guide_bf16))
+    else:
+        a.guide_w, a.guide_bf16 = None, 0
     a.seed, a.n_paths, a.max_depth, a.flags, a.n_threads = int(seed), int(n_paths), int(depth), int(flags), int(threads)
     if path_list is not None:
         pl = np.ascontiguousarray(path_list, np.uint32)
@@ -149,13 +172,14 @@ def _params(sc, albedo, Le, heights, keep):
 
 
 def render(sc, seed, n_paths, depth, albedo=None, Le=None, heights=None, flags=0,
-           path_list=None, slices=False, per_path=False, threads=0):
+           path_list=None, slices=False, per_path=False, threads=0, guide_w=None, guide_bf16=True):
     """FP64 light-tracing image [H,W,3] (plus optional per-depth slices,
-    per-path signature / reservoir index R / weight W, and total flux)."""
+    per-path signature / reservoir index R / weight W, and total flux).
+    guide_w: emission-guide weights (guided emission), else cosine emission."""
     lib = _load()
     keep = _Keep()
     s = _scene(sc, keep)
-    a = _args(seed, n_paths, depth, flags, threads, path_list, keep)
+    a = _args(seed, n_paths, depth, flags, threads, path_list, keep, guide_w, guide_bf16)
     alb, le, h = _params(sc, albedo, Le, heights, keep)
     H, W = int(sc["camera"]["height"]), int(sc["camera"]["width"])
     img = np.zeros((H, W, 3))
@@ -165,8 +189,10 @@ def render(sc, seed, n_paths, depth, albedo=None, Le=None, heights=None, flags=0
     R = np.zeros(n, np.int32) if per_path else None
     Wr = np.zeros(n) if per_path else None
     flux = np.zeros(3)
-    lib.ora_render(C.byref(s), C.byref(a), _p(alb), _p(le), _p(h), _p(img), _p(sl),
-                   _p(sig, C.c_uint32), _p(R, C.c_int32), _p(Wr), _p(flux))
+    rc = lib.ora_render(C.byref(s), C.byref(a), _p(alb), _p(le), _p(h), _p(img), _p(sl),
+                        _p(sig, C.c_uint32), _p(R, C.c_int32), _p(Wr), _p(flux))
+    if rc != 0:
+        raise ValueError("oracle render rejected its arguments")
     out = dict(image=img, flux=flux)
     if slices:
         out["slices"] = sl
@@ -176,20 +202,23 @@ def render(sc, seed, n_paths, depth, albedo=None, Le=None, heights=None, flags=0
 
 
 def gradient(sc, seed, n_paths, depth, dI, mode=MODE_NAIVE, albedo=None, Le=None, heights=None,
-             flags=0, path_list=None, threads=0):
+             flags=0, path_list=None, threads=0, guide_w=None, guide_bf16=True):
     """Gradient of <dI, I(theta)> w.r.t. albedo texels, emitter radiance and
-    (attached) heights, by taped reverse-mode AD of each light path."""
+    (attached) heights, by taped reverse-mode AD of each light path.  With
+    guide_w the emission is guided and its density is held fixed (detached)."""
     lib = _load()
     keep = _Keep()
     s = _scene(sc, keep)
-    a = _args(seed, n_paths, depth, flags, threads, path_list, keep)
+    a = _args(seed, n_paths, depth, flags, threads, path_list, keep, guide_w, guide_bf16)
     alb, le, h = _params(sc, albedo, Le, heights, keep)
     dI = keep.f64(dI)
     g_alb = np.zeros_like(alb)
     g_le = np.zeros(3)
     g_h = np.zeros_like(h) if h is not None else None
-    lib.ora_gradient(C.byref(s), C.byref(a), int(mode), _p(alb), _p(le), _p(h), _p(dI),
-                     _p(g_alb), _p(g_le), _p(g_h))
+    rc = lib.ora_gradient(C.byref(s), C.byref(a), int(mode), _p(alb), _p(le), _p(h), _p(dI),
+                          _p(g_alb), _p(g_le), _p(g_h))
+    if rc != 0:
+        raise ValueError("oracle gradient rejected its arguments")
     return dict(albedo=g_alb, Le=g_le, heights=g_h)
 
 
@@ -216,3 +245,72 @@ def philox(seed, ctr):
     out = np.zeros(4, np.uint32)
     lib.ora_philox(int(seed), *(int(c) for c in ctr), _p(out, C.c_uint32))
     return out
+
+
+# ----------------------------------------------------------------- guide
+def guide_eval(sc, w, x, n, bf16=True):
+    """Raw network outputs [count, 41] at positions x and unit normals n."""
+    lib = _load()
+    keep = _Keep()
+    s = _scene(sc, keep)
+    w, x, n = keep.f64(w), keep.f64(x), keep.f64(n)
+    out = np.zeros((x.shape[0], GUIDE_OUT))
+    lib.ora_guide_eval(C.byref(s), _p(w), _p(x), _p(n), x.shape[0], int(bool(bf16)), _p(out))
+    return out
+
+
+def guide_pdf(o, n, wd):
+    """Folded mixture density at directions wd [count, 3] for outputs o [count, 41]."""
+    lib = _load()
+    o, n, wd = (np.ascontiguousarray(a, np.float64) for a in (o, n, wd))
+    pdf = np.zeros(o.shape[0])
+    lib.ora_guide_pdf(_p(o), _p(n), _p(wd), o.shape[0], _p(pdf))
+    return pdf
+
+
+def guide_sample(o, n, g):
+    """Directions drawn from outputs o [count, 41] with uniforms g [count, 3];
+    returns (directions [count, 3], component [count]: 0 cosine, k+1 lobe k)."""
+    lib = _load()
+    o, n, g = (np.ascontiguousarray(a, np.float64) for a in (o, n, g))
+    wd = np.zeros((o.shape[0], 3))
+    comp = np.zeros(o.shape[0], np.int32)
+    lib.ora_guide_sample(_p(o), _p(n), _p(g), o.shape[0], _p(wd), _p(comp, C.c_int32))
+    return wd, comp
+
+
+def guide_emit(sc, seed, n_paths, guide_w, path_list=None, bf16=True):
+    """Guided emission of each path: dict(x, w, pdf, factor, comp)."""
+    lib = _load()
+    keep = _Keep()
+    s = _scene(sc, keep)
+    a = _args(seed, n_paths, 1, 0, 1, path_list, keep, guide_w, bf16)
+    n = len(path_list) if path_list is not None else int(n_paths)
+    rec = np.zeros((n, 8))
+    comp = np.zeros(n, np.int32)
+    if lib.ora_guide_emit(C.byref(s), C.byref(a), _p(rec), _p(comp, C.c_int32)) != 0:
+        raise ValueError("guided emission needs an area emitter and weights")
+    return dict(x=rec[:, 0:3], w=rec[:, 3:6], pdf=rec[:, 6], factor=rec[:, 7], comp=comp)
+
+
+def guide_loss_grad(sc, w, samples, bf16=True):
+    """Training loss -(1/B) sum (S/q_s) log q(w|x,n) and its parameter gradient.
+    samples [B, 12] = x (3), n (3), w (3), sampling density q_s, S, unused."""
+    lib = _load()
+    keep = _Keep()
+    s = _scene(sc, keep)
+    w, smp = keep.f64(w), keep.f64(samples)
+    grad = np.zeros(GUIDE_NPARAMS)
+    loss = C.c_double(0.0)
+    lib.ora_guide_loss_grad(C.byref(s), _p(w), _p(smp), smp.shape[0], int(bool(bf16)), _p(grad), C.byref(loss))
+    return loss.value, grad
+
+
+def adam(w, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba 2015) with bias correction; returns new (w, m, v)."""
+    w, g, m, v = (np.asarray(a, np.float64) for a in (w, g, m, v))
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mh = m / (1.0 - beta1 ** step)
+    vh = v / (1.0 - beta2 ** step)
+    return w - lr * mh / (np.sqrt(vh) + eps), m, v

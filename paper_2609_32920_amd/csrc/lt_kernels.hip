@@ -10,6 +10,12 @@
 
 namespace lt {
 
+// The instrumented build (event counters on) gives its kernels their own
+// symbol names so that profiles keep the two builds apart.
+#ifdef LT_COUNTERS
+inline namespace counted {
+#endif
+
 // One vertex of a light path: closest hit, material dispatch, sensor
 // connection geometry and the sampling of the next direction.
 struct Event {
@@ -490,6 +496,10 @@ __global__ void k_refit_level(Node* nodes, const Tri* tris, const int32_t* level
 }
 
 #include "lt_attached.inc"
+
+#ifdef LT_COUNTERS
+}  // namespace counted
+#endif
 
 // ---------------------------------------------------------------- launchers
 static size_t stack_bytes(const PassArgs& A, int block) { return (size_t)A.sc.stack_n * block * sizeof(int); }

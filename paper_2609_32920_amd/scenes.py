@@ -232,3 +232,57 @@ def batched_instances(n=48, seed=7):
         depth = int(rng.integers(4, 13))
         out.append(dict(kind=kind, G=G, film=film, n_paths=paths, depth=depth))
     return out
+
+
+GUIDE_SEED = 0x6D6C70
+GUIDE_NPARAMS = 11433   # W1[64][6] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[41][64] b4[41]
+
+
+def guide_weights(seed=GUIDE_SEED, out_scale=0.05):
+    """Initial emission-guide weights, flat float64 [11433].
+
+    Hidden layers: He-normal N(0, 2/fan_in), zero biases; output layer
+    N(0, (out_scale^2)/fan_in) so that the first mixture is broad.
+    """
+    rng = np.random.default_rng(seed)
+    parts = []
+    for n_out, n_in, s in ((64, 6, math.sqrt(2.0 / 6)), (64, 64, math.sqrt(2.0 / 64)),
+                           (64, 64, math.sqrt(2.0 / 64)), (41, 64, out_scale / math.sqrt(64))):
+        parts.append(rng.normal(0.0, s, size=n_out * n_in))
+        parts.append(np.zeros(n_out))
+    w = np.concatenate(parts)
+    assert w.size == GUIDE_NPARAMS
+    return w
+
+
+def guide_random_weights(seed, scale=1.0):
+    """Weights with every entry (biases included) drawn N(0, scale^2/fan_in):
+    a network whose mixtures are far from uniform, for parity tests."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for n_out, n_in in ((64, 6), (64, 64), (64, 64), (41, 64)):
+        s = scale * math.sqrt(2.0 / n_in)
+        parts.append(rng.normal(0.0, s, size=n_out * n_in))
+        parts.append(rng.normal(0.0, 0.3 * scale, size=n_out))
+    return np.concatenate(parts)
+
+
+def guide_sample_batch(sc, count, seed, zero_frac=0.25):
+    """Synthetic training samples [count, 12]: x uniform in the emitter quad,
+    its unit normal, a direction uniform on that hemisphere, a positive
+    sampling density, a contribution S >= 0 (a fraction exactly zero)."""
+    rng = np.random.default_rng(seed)
+    em = sc["emitter"]
+    o, e1, e2 = (np.asarray(em[k], np.float64) for k in ("o", "e1", "e2"))
+    nrm = np.cross(e1, e2)
+    nrm /= np.linalg.norm(nrm)
+    u = rng.uniform(size=(count, 2))
+    x = o + u[:, :1] * e1 + u[:, 1:2] * e2
+    d = rng.normal(size=(count, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    d = np.where((d @ nrm)[:, None] < 0.0, -d, d)
+    q = rng.uniform(0.05, 3.0, size=count)
+    S = rng.exponential(1.0, size=count) * (rng.uniform(size=count) >= zero_frac)
+    out = np.zeros((count, 12))
+    out[:, 0:3], out[:, 3:6], out[:, 6:9], out[:, 9], out[:, 10] = x, nrm, d, q, S
+    return out
