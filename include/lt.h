@@ -119,7 +119,16 @@ typedef struct {
                                ill-conditioned vertex (grazing hit, |cos| < 0.02;
                                refraction with cos_t < 0.1; or a segment shorter than
                                0.02 scene units) whose FP32 derivatives carry rounding
-                               amplified by 1/cos^2 or 1/length */
+                               amplified by 1/cos^2 or 1/length, or a connection
+                               within 1e-3 px of a kink of the tent filter (Eq. 20),
+                               where the splat-position derivative is one-sided */
+  float* path_contrib;      /* DEVICE [n_paths] or NULL: a per-path training signal S
+                               for the emission guide.  lt_trace writes the path's
+                               image contribution sum_i lum(C_i) over its connections
+                               (Rec. 709 luminance, the reservoir weight of Eq. 8);
+                               lt_backward_lrb3 writes the path's gradient magnitude:
+                               detached, sum_c |delta_total,c| (Eq. 14); attached,
+                               the L1 norm of its heights-gradient contributions */
 } lt_trace_args;
 
 /* Parameters: DEVICE float arrays owned by the caller. */
@@ -127,6 +136,8 @@ typedef struct {
   const float* albedo;    /* [n_tex][tex_res][tex_res][3] */
   const float* emitter_L; /* [3] radiance (quad) or intensity (point) */
   const float* heights;   /* [G][G] heightfield offsets, or NULL when hf_G < 2 */
+  const float* guide_w;   /* [LT_GUIDE_NPARAMS] emission-guide weights, or NULL for
+                             cosine-weighted emission (see the guide section) */
 } lt_params;
 
 /* Gradients: DEVICE float arrays, same shapes as lt_params, ACCUMULATED
@@ -191,7 +202,9 @@ lt_status lt_scene_upload(lt_ctx* ctx, const lt_scene_desc* scene);
  * (Sec. 4.2.1: selected depth R, weight Omega_k/w_R, u_R, reweighted splat).
  * 0 for neither. */
 size_t lt_side_state_bytes(const lt_ctx* ctx, const lt_trace_args* args);
-/* Library workspace bytes a call with these args uses (flat in depth). */
+/* Library workspace bytes a call with these args may use (flat in depth):
+ * the scene copy and BVH, plus the guide's packed weights and 16 bytes per
+ * path, which only guided passes use. */
 size_t lt_workspace_bytes(const lt_ctx* ctx, const lt_trace_args* args);
 
 /* Light tracing forward (Eq. 1-2, Eq. 20; Sec. 4.3.1 Pass 1).
@@ -239,6 +252,72 @@ lt_status lt_backward_reslrb(lt_ctx* ctx, const lt_trace_args* args, const lt_pa
  * LT_ERR_STATE, LT_ERR_HIP. */
 lt_status lt_backward_lrb3(lt_ctx* ctx, const lt_trace_args* args, const lt_params* params,
                            const float* d_image, lt_grads* grads);
+
+/* ------------------------------------------------------------------------
+ * Learned emission guide.  An extension of the method, not in the paper:
+ * the paper samples emitted directions cosine-weighted (Sec. 3.1).  With
+ * params->guide_w set, every pass draws the emitted direction of an area
+ * emitter from a density q learned by a small network and weights the path
+ * by A cos / q (so beta_1 = L_e A cos / q); q is held fixed in every reverse
+ * mode (a detached density), which keeps the gradients unbiased.
+ *
+ * Network: features (position normalised to the scene box, unit normal) ->
+ * 64 -> 64 -> 64 (ReLU) -> 41 outputs; products in bfloat16 on the matrix
+ * cores with FP32 accumulation.  Outputs: 8 von Mises-Fisher lobes
+ * {mean direction (3, normalised), log-concentration (1, clamped to
+ * [-3, 8]), logit (1, softmax)} and a mixing logit (alpha = 0.9 sigmoid).
+ *   q(w) = alpha sum_k pi_k [v_k(w) + v_k(mirror(w))] + (1 - alpha) max(w.n, 0) / pi
+ * where mirror reflects about the emitter plane (lobes folded onto the
+ * emitting hemisphere).  Parameter layout (FP32, row-major out x in):
+ *   W1[64][6] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[41][64] b4[41].
+ * Uniforms: Philox counter (path, 0, 1): g0 picks the component (cosine when
+ * g0 >= alpha, else the lobe whose cumulative weight first exceeds
+ * g0/alpha), (g1, g2) the direction.
+ * A guided pass uses 16 extra bytes of library workspace per path (the
+ * direction and density of each path, recomputed by every pass).
+ * Errors: LT_ERR_UNSUPPORTED for a point emitter with a guide.
+ * ------------------------------------------------------------------------ */
+#define LT_GUIDE_NPARAMS 11433
+#define LT_GUIDE_NOUT 41
+
+/* One training sample, 48 bytes: vertex position and normal, the sampled
+ * direction, its sampling density q, its contribution S, the component
+ * that drew it (0 cosine, k + 1 lobe k; informational). */
+typedef struct {
+  float x[3], n[3], w[3];
+  float pdf, S, comp;
+} lt_guide_sample;
+
+/* Raw network outputs. x, n: DEVICE [count][3] positions and unit normals;
+ * out: DEVICE [count][41].  Needs an uploaded scene (its box normalises x).
+ * Errors: LT_ERR_ARG, LT_ERR_STATE (no scene), LT_ERR_HIP. */
+lt_status lt_guide_eval(lt_ctx* ctx, const float* guide_w, const float* x, const float* n, int64_t count,
+                        float* out);
+
+/* The guided emission of paths [0, args->n_paths) exactly as the passes
+ * draw it, written as training samples out: DEVICE [n_paths]; S is taken
+ * from path_contrib (DEVICE [n_paths], e.g. lt_trace's output) or 0 when
+ * NULL.  Uses args->seed and params->guide_w only.
+ * Errors: LT_ERR_ARG, LT_ERR_STATE, LT_ERR_UNSUPPORTED (point emitter). */
+lt_status lt_guide_emit(lt_ctx* ctx, const lt_trace_args* args, const lt_params* params,
+                        const float* path_contrib, lt_guide_sample* out);
+
+/* Training loss L = -(1/count) sum_b (S_b / q_b) log q_theta(w_b | x_b, n_b)
+ * (a Monte Carlo estimate of the KL divergence from the contribution-
+ * proportional density to q_theta, up to a constant) and its gradient.
+ * samples: DEVICE [count]; grad: DEVICE [LT_GUIDE_NPARAMS], overwritten;
+ * loss: DEVICE [1] or NULL.  Samples with q <= 0 or S == 0 contribute
+ * nothing.  Deterministic (fixed reduction order).
+ * Errors: LT_ERR_ARG, LT_ERR_STATE, LT_ERR_OOM (cap), LT_ERR_HIP. */
+lt_status lt_guide_grad(lt_ctx* ctx, const float* guide_w, const lt_guide_sample* samples, int64_t count,
+                        float* grad, float* loss);
+
+/* One Adam step (Kingma & Ba 2015, bias-corrected) on the guide weights,
+ * in place.  w, m, v: DEVICE [LT_GUIDE_NPARAMS] (m, v zero before step 1);
+ * grad: DEVICE [LT_GUIDE_NPARAMS]; step: 1-based.
+ * Errors: LT_ERR_ARG (step < 1, lr <= 0, betas outside [0, 1)). */
+lt_status lt_guide_adam(lt_ctx* ctx, float* w, const float* grad, float* m, float* v, int32_t step, float lr,
+                        float beta1, float beta2, float eps);
 
 #ifdef __cplusplus
 }

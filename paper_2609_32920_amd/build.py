@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblt.so")
 LIB_COUNTERS = os.path.join(HERE, "liblt_counters.so")
-SOURCES = ["lt_kernels.hip", "lt_api.cpp"]
+SOURCES = ["lt_kernels.hip", "lt_guide.hip", "lt_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -171,9 +171,14 @@ struct lt_ctx {
   std::vector<int> level_off;  // node-level ranges into d_levels, deepest last
   DevScene dsc{};
   size_t scene_bytes = 0;
-  float emit_factor = 0.f;
   unsigned int* d_counter = nullptr;
   double* d_acc = nullptr;  // [0..2] emitter gradient, [3] loss
+  bool guide_ok = false;     // guide kernels got the LDS they need
+  void* d_gpack = nullptr;   // packed bf16 guide operands
+  float4* d_grec = nullptr;  // guided emission records [grec_n]
+  size_t grec_n = 0;
+  float* d_gpart = nullptr;  // guide gradient partial sums [gpart_n][kGN + 1]
+  size_t gpart_n = 0;
 
   lt_status fail(lt_status s, const char* fmt, const char* a = "") {
     char buf[512];
@@ -248,6 +253,66 @@ lt_status check_args(lt_ctx* c, const lt_trace_args* a, const lt_params* p) {
   if (!p->albedo || !p->emitter_L) return c->fail(LT_ERR_ARG, "albedo and emitter_L are required%s");
   if ((a->flags & LT_ATTACHED) && c->dsc.hf_G < 2) return c->fail(LT_ERR_ARG, "LT_ATTACHED needs a heightfield%s");
   if ((a->flags & LT_ATTACHED) && !p->heights) return c->fail(LT_ERR_ARG, "LT_ATTACHED needs params->heights%s");
+  if (p->guide_w && c->dsc.em_type != LT_EMIT_QUAD) return c->fail(LT_ERR_UNSUPPORTED, "the emission guide needs an area emitter%s");
+  if (p->guide_w && !c->guide_ok) return c->fail(LT_ERR_UNSUPPORTED, "guide kernels could not get their LDS%s");
+  return LT_OK;
+}
+
+size_t guide_bytes(const lt_trace_args* a, const lt_params* p) {
+  return p && p->guide_w ? (size_t)a->n_paths * sizeof(float4) : 0;
+}
+
+template <typename T>
+lt_status grow(lt_ctx* c, T** ptr, size_t& have, size_t need, const char* what) {
+  if (have >= need && *ptr) return LT_OK;
+  hipFree(*ptr);
+  *ptr = nullptr; have = 0;
+  if (hipMalloc((void**)ptr, need * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    *ptr = nullptr;
+    return c->fail(LT_ERR_OOM, "out of device memory for %s", what);
+  }
+  have = need;
+  return LT_OK;
+}
+
+lt_status guide_pack(lt_ctx* c, const float* w) {
+  if (!c->d_gpack && hipMalloc(&c->d_gpack, guide_packed_bytes()) != hipSuccess) {
+    (void)hipGetLastError();
+    c->d_gpack = nullptr;
+    return c->fail(LT_ERR_OOM, "out of device memory for the guide weights%s");
+  }
+  return c->hip(launch_guide_pack(w, c->d_gpack, c->stream), "guide pack");
+}
+
+int guide_grid(const lt_ctx* c, int64_t count) {
+  int64_t blocks = ((count + 63) / 64 + 3) / 4;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(blocks, (int64_t)c->n_cu * 4));
+}
+
+GuideArgs guide_args(lt_ctx* c, const float* w, int64_t count) {
+  GuideArgs G;
+  std::memset(&G, 0, sizeof(G));
+  G.sc = c->dsc;
+  G.count = count;
+  G.w = w;
+  G.packed = (const lt_u32x4*)c->d_gpack;
+  return G;
+}
+
+// Guided passes: the direction and density of every path's emission, drawn
+// once per pass by the guide kernel and read by the tracing kernels.
+lt_status guide_prepass(lt_ctx* c, const lt_trace_args* a, const lt_params* p, PassArgs& A) {
+  A.guide_rec = nullptr;
+  if (!p->guide_w) return LT_OK;
+  lt_status st = grow(c, &c->d_grec, c->grec_n, (size_t)a->n_paths, "guided emission records");
+  if (st != LT_OK) return st;
+  if ((st = guide_pack(c, p->guide_w)) != LT_OK) return st;
+  GuideArgs G = guide_args(c, p->guide_w, a->n_paths);
+  G.seed = a->seed;
+  G.rec = c->d_grec;
+  if ((st = c->hip(launch_guide_emit(G, guide_grid(c, a->n_paths), c->stream), "guide emit")) != LT_OK) return st;
+  A.guide_rec = c->d_grec;
   return LT_OK;
 }
 
@@ -275,7 +340,6 @@ PassArgs base_args(lt_ctx* c, const lt_trace_args* a, const lt_params* p) {
   A.flags = a->flags;
   double Kfilm = (double)c->dsc.W * c->dsc.H / ((double)c->dsc.film_area * (double)a->n_paths);
   A.Kfilm = (float)Kfilm;
-  A.emit_factor = c->emit_factor;
   A.n_texels = c->dsc.n_tex * c->dsc.tex_res * c->dsc.tex_res;
   A.hgrad_lds = 0;
   A.mask = a->path_mask;
@@ -324,6 +388,8 @@ lt_status lt_create(int device, void* stream, lt_ctx** out) {
     (void)hipGetLastError();
     c->lds_max = 65536;
   }
+  c->guide_ok = guide_init() == hipSuccess;
+  if (!c->guide_ok) (void)hipGetLastError();
   if (hipMalloc((void**)&c->d_counter, 256) != hipSuccess || hipMalloc((void**)&c->d_acc, 256) != hipSuccess) {
     hipFree(c->d_counter); hipFree(c->d_acc);
     delete c;
@@ -339,6 +405,9 @@ void lt_destroy(lt_ctx* c) {
   c->free_scene();
   hipFree(c->d_counter);
   hipFree(c->d_acc);
+  hipFree(c->d_gpack);
+  hipFree(c->d_grec);
+  hipFree(c->d_gpart);
   delete c;
 }
 
@@ -532,7 +601,31 @@ lt_status lt_scene_upload(lt_ctx* c, const lt_scene_desc* s) {
   }
   d.em_area = (float)area;
   if (s->em_type == LT_EMIT_QUAD && !(area > 0)) { c->free_scene(); return c->fail(LT_ERR_ARG, "degenerate quad emitter%s"); }
-  c->emit_factor = s->em_type == LT_EMIT_QUAD ? (float)(area * M_PI) : (float)(4.0 * M_PI);
+  {  // guide normalisation box: static triangles, heightfield footprint, emitter corners
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    auto add = [&](double x, double y, double z) {
+      double p[3] = {x, y, z};
+      for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], p[a]); hi[a] = std::max(hi[a], p[a]); }
+    };
+    for (long i = 0; i < (long)n_static * 3; ++i) add(s->tri_v[i * 3], s->tri_v[i * 3 + 1], s->tri_v[i * 3 + 2]);
+    if (G >= 2) {
+      double ext = (G - 1) * s->hf_dx;
+      add(s->hf_x0, s->hf_base, s->hf_z0);
+      add(s->hf_x0 + ext, s->hf_base, s->hf_z0 + ext);
+    }
+    const double *o = s->em_o, *e1 = s->em_e1, *e2 = s->em_e2;
+    add(o[0], o[1], o[2]);
+    if (s->em_type == LT_EMIT_QUAD) {
+      add(o[0] + e1[0], o[1] + e1[1], o[2] + e1[2]);
+      add(o[0] + e2[0], o[1] + e2[1], o[2] + e2[2]);
+      add(o[0] + e1[0] + e2[0], o[1] + e1[1] + e2[1], o[2] + e1[2] + e2[2]);
+    }
+    for (int a = 0; a < 3; ++a) {
+      double h = 0.5 * (hi[a] - lo[a]);
+      d.gb_c[a] = (float)(0.5 * (lo[a] + hi[a]));
+      d.gb_ih[a] = h > 0 ? (float)(1.0 / h) : 0.f;
+    }
+  }
   // camera frame: f = normalize(target - pos), r = normalize(f x up), u = r x f
   double f[3], r[3], u[3];
   for (int a = 0; a < 3; ++a) f[a] = s->cam_target[a] - s->cam_pos[a];
@@ -566,8 +659,9 @@ size_t lt_side_state_bytes(const lt_ctx* c, const lt_trace_args* a) {
 }
 
 size_t lt_workspace_bytes(const lt_ctx* c, const lt_trace_args* a) {
-  (void)a;
-  return c ? c->scene_bytes + 512 : 0;
+  if (!c) return 0;
+  size_t guide = guide_packed_bytes() + (a && a->n_paths > 0 ? (size_t)a->n_paths * sizeof(float4) : 0);
+  return c->scene_bytes + 512 + guide;
 }
 
 lt_status lt_trace(lt_ctx* c, const lt_trace_args* a, const lt_params* p, float* image, void* side,
@@ -580,10 +674,12 @@ lt_status lt_trace(lt_ctx* c, const lt_trace_args* a, const lt_params* p, float*
     return c->fail(LT_ERR_UNSUPPORTED, "path signatures come from the detached forward (no attached records)%s");
   SideLayout L = side_layout(a);
   if (L.total && (!side || side_bytes < L.total)) return c->fail(LT_ERR_ARG, "side state buffer too small%s");
-  if ((st = check_cap(c, L.total)) != LT_OK) return st;
+  if ((st = check_cap(c, L.total + guide_bytes(a, p))) != LT_OK) return st;
   if ((st = prepare_geometry(c, p)) != LT_OK) return st;
   PassArgs A = base_args(c, a, p);
   A.image = image;
+  A.contrib = a->path_contrib;
+  if ((st = guide_prepass(c, a, p, A)) != LT_OK) return st;
   char* sb = (char*)side;
   if (att_rec) {
     if (a->flags & LT_RECORD_TAPE) {
@@ -620,13 +716,15 @@ lt_status lt_loss_l2(lt_ctx* c, const float* image, const float* target, int64_t
 }
 
 static lt_status backward_common(lt_ctx* c, const lt_trace_args* a, const lt_params* p, const float* d_image,
-                                 lt_grads* g, PassArgs& A) {
+                                 lt_grads* g, PassArgs& A, size_t side) {
   lt_status st = check_args(c, a, p);
   if (st != LT_OK) return st;
   if (!d_image || !g) return c->fail(LT_ERR_ARG, "null d_image or grads%s");
   if (!g->albedo) return c->fail(LT_ERR_ARG, "grads->albedo is required%s");
+  if ((st = check_cap(c, side + guide_bytes(a, p))) != LT_OK) return st;
   if ((st = prepare_geometry(c, p)) != LT_OK) return st;
   A = base_args(c, a, p);
+  if ((st = guide_prepass(c, a, p, A)) != LT_OK) return st;
   A.dI = d_image;
   A.g_albedo = g->albedo;
   A.g_Le_acc = c->d_acc;
@@ -640,12 +738,11 @@ lt_status lt_backward_naive(lt_ctx* c, const lt_trace_args* a, const lt_params* 
                             const void* tape, size_t tape_bytes, lt_grads* g) {
   if (!c) return LT_ERR_ARG;
   if (a && !(a->flags & LT_RECORD_TAPE)) return c->fail(LT_ERR_ARG, "naive backward needs LT_RECORD_TAPE args%s");
+  if (a && (!tape || tape_bytes < side_layout(a).total)) return c->fail(LT_ERR_ARG, "tape buffer too small%s");
   PassArgs A;
-  lt_status st = backward_common(c, a, p, d_image, g, A);
+  lt_status st = backward_common(c, a, p, d_image, g, A, a ? side_layout(a).total : 0);
   if (st != LT_OK) return st;
   SideLayout L = side_layout(a);
-  if (!tape || tape_bytes < L.total) return c->fail(LT_ERR_ARG, "tape buffer too small%s");
-  if ((st = check_cap(c, L.total)) != LT_OK) return st;
   const char* sb = (const char*)tape;
   A.tape_in = (const TapeRec*)(sb + L.tape);
   A.tape_len_in = (const int32_t*)(sb + L.len);
@@ -664,12 +761,11 @@ lt_status lt_backward_reslrb(lt_ctx* c, const lt_trace_args* a, const lt_params*
                              const void* records, size_t bytes, lt_grads* g) {
   if (!c) return LT_ERR_ARG;
   if (a && !(a->flags & LT_RECORD_RESERVOIR)) return c->fail(LT_ERR_ARG, "ResLRB backward needs LT_RECORD_RESERVOIR args%s");
+  if (a && (!records || bytes < side_layout(a).total)) return c->fail(LT_ERR_ARG, "reservoir buffer too small%s");
   PassArgs A;
-  lt_status st = backward_common(c, a, p, d_image, g, A);
+  lt_status st = backward_common(c, a, p, d_image, g, A, a ? side_layout(a).total : 0);
   if (st != LT_OK) return st;
   SideLayout L = side_layout(a);
-  if (!records || bytes < L.total) return c->fail(LT_ERR_ARG, "reservoir buffer too small%s");
-  if ((st = check_cap(c, L.total)) != LT_OK) return st;
   if (a->flags & LT_ATTACHED) {
     A.res_att_in = (const ResRecAtt*)((const char*)records + L.res);
     int grid = persistent_grid(c, a->n_paths, 256);
@@ -687,9 +783,9 @@ lt_status lt_backward_lrb3(lt_ctx* c, const lt_trace_args* a, const lt_params* p
                            lt_grads* g) {
   if (!c) return LT_ERR_ARG;
   PassArgs A;
-  lt_status st = backward_common(c, a, p, d_image, g, A);
+  lt_status st = backward_common(c, a, p, d_image, g, A, 0);
   if (st != LT_OK) return st;
-  if ((st = check_cap(c, 0)) != LT_OK) return st;
+  A.contrib = a->path_contrib;
   if (a->flags & LT_ATTACHED) {
     int grid = persistent_grid(c, a->n_paths, 256);
     A.hgrad_lds = hgrad_in_lds(c, g->heights, true);
@@ -699,6 +795,69 @@ lt_status lt_backward_lrb3(lt_ctx* c, const lt_trace_args* a, const lt_params* p
     if ((st = c->hip(launch_lrb3_bwd(A, grid, c->tune.block, c->stream), "lrb3 backward")) != LT_OK) return st;
   }
   return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
+}
+
+lt_status lt_guide_eval(lt_ctx* c, const float* guide_w, const float* x, const float* n, int64_t count,
+                        float* out) {
+  if (!c) return LT_ERR_ARG;
+  if (!guide_w || !x || !n || !out || count < 1 || count >= ((int64_t)1 << 31))
+    return c->fail(LT_ERR_ARG, "bad guide eval arguments%s");
+  if (!c->has_scene) return c->fail(LT_ERR_STATE, "no scene uploaded%s");
+  if (!c->guide_ok) return c->fail(LT_ERR_UNSUPPORTED, "guide kernels could not get their LDS%s");
+  lt_status st = guide_pack(c, guide_w);
+  if (st != LT_OK) return st;
+  GuideArgs G = guide_args(c, guide_w, count);
+  G.x = x; G.n = n; G.out = out;
+  return c->hip(launch_guide_eval(G, guide_grid(c, count), c->stream), "guide eval");
+}
+
+lt_status lt_guide_emit(lt_ctx* c, const lt_trace_args* a, const lt_params* p, const float* path_contrib,
+                        lt_guide_sample* out) {
+  if (!c) return LT_ERR_ARG;
+  if (!a || !p || !out || !p->guide_w) return c->fail(LT_ERR_ARG, "bad guide emit arguments%s");
+  if (!c->has_scene) return c->fail(LT_ERR_STATE, "no scene uploaded%s");
+  if (a->n_paths < 1 || a->n_paths >= (int64_t)1 << 31) return c->fail(LT_ERR_ARG, "n_paths out of range [1, 2^31)%s");
+  if (c->dsc.em_type != LT_EMIT_QUAD) return c->fail(LT_ERR_UNSUPPORTED, "the emission guide needs an area emitter%s");
+  if (!c->guide_ok) return c->fail(LT_ERR_UNSUPPORTED, "guide kernels could not get their LDS%s");
+  lt_status st = guide_pack(c, p->guide_w);
+  if (st != LT_OK) return st;
+  GuideArgs G = guide_args(c, p->guide_w, a->n_paths);
+  G.seed = a->seed;
+  G.samples = reinterpret_cast<float*>(out);
+  G.contrib = path_contrib;
+  return c->hip(launch_guide_emit(G, guide_grid(c, a->n_paths), c->stream), "guide emit");
+}
+
+lt_status lt_guide_grad(lt_ctx* c, const float* guide_w, const lt_guide_sample* samples, int64_t count,
+                        float* grad, float* loss) {
+  if (!c) return LT_ERR_ARG;
+  if (!guide_w || !samples || !grad || count < 1 || count >= ((int64_t)1 << 31))
+    return c->fail(LT_ERR_ARG, "bad guide gradient arguments%s");
+  if (!c->has_scene) return c->fail(LT_ERR_STATE, "no scene uploaded%s");
+  if (!c->guide_ok) return c->fail(LT_ERR_UNSUPPORTED, "guide kernels could not get their LDS%s");
+  int grid = (int)std::min<int64_t>((count + 63) / 64, 1024);
+  lt_status st = check_cap(c, (size_t)grid * guide_partial_floats() * sizeof(float));
+  if (st != LT_OK) return st;
+  if ((st = grow(c, &c->d_gpart, c->gpart_n, (size_t)1024 * guide_partial_floats(), "guide partial sums")) != LT_OK)
+    return st;
+  if ((st = guide_pack(c, guide_w)) != LT_OK) return st;
+  GuideArgs G = guide_args(c, guide_w, count);
+  G.samples = const_cast<float*>(reinterpret_cast<const float*>(samples));
+  G.partial = c->d_gpart;
+  if ((st = c->hip(launch_guide_grad(G, grid, c->stream), "guide gradient")) != LT_OK) return st;
+  return c->hip(launch_guide_reduce(c->d_gpart, grid, grad, loss, c->stream), "guide reduce");
+}
+
+lt_status lt_guide_adam(lt_ctx* c, float* w, const float* grad, float* m, float* v, int32_t step, float lr,
+                        float beta1, float beta2, float eps) {
+  if (!c) return LT_ERR_ARG;
+  if (!w || !grad || !m || !v || step < 1 || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) ||
+      !(beta2 >= 0.f && beta2 < 1.f) || !(eps >= 0.f))
+    return c->fail(LT_ERR_ARG, "bad Adam arguments%s");
+  float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, step)));
+  float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, step)));
+  return c->hip(launch_guide_adam(w, grad, m, v, LT_GUIDE_NPARAMS, lr, beta1, beta2, eps, c1, c2, c->stream),
+                "guide adam");
 }
 
 }  // extern "C"

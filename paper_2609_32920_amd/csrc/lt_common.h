@@ -96,6 +96,9 @@ struct DevScene {
   float tan_half, aspect, film_area;
   int32_t W, H;
   int32_t stack_n;  // traversal stack entries per lane (BVH depth + 2)
+  // guide input normalisation: scene box centre and inverse half extent
+  // (static triangles, heightfield footprint at its base, emitter corners)
+  float gb_c[3], gb_ih[3];
 };
 
 }  // namespace lt

@@ -10,7 +10,9 @@ namespace lt {
 // 0 closest-hit rays, 1 shadow rays, 2 BVH node fetches, 3 triangle tests,
 // 4 film splats, 5 adjoint gathers, 6 gradient values scattered,
 // 7 paths emitted, 8 tape records written, 9 tape records read.
-#ifdef LT_COUNTERS
+// Translation units without counted events define LT_NO_EVENT_COUNTERS so
+// that the counter array has a single definition.
+#if defined(LT_COUNTERS) && !defined(LT_NO_EVENT_COUNTERS)
 __device__ unsigned long long lt_counters[16];
 #define LT_COUNT(k, v) atomicAdd(&lt_counters[k], (unsigned long long)(v))
 #else

@@ -31,9 +31,15 @@ struct Event {
   float u_res;     // reservoir uniform of this vertex
   int slot;        // hit triangle in BVH order
   f3 x;            // hit point
-  bool illc;       // ill-conditioned vertex for attached derivatives (grazing hit
-                   // or refraction near the critical angle)
+  bool illc;       // ill-conditioned vertex for attached derivatives (grazing hit,
+                   // refraction near the critical angle, short segment, or a
+                   // connection next to a tent-filter kink)
 };
+
+__device__ __forceinline__ bool near_kink(float u) {
+  float d = u - 0.5f;
+  return fabsf(d - rintf(d)) < 1e-3f;
+}
 
 // cmode: 0 no sensor connection, 1 full connection test (with shadow
 // ray), 2 connection geometry only (known visible from an earlier replay).
@@ -65,6 +71,9 @@ __device__ __forceinline__ Event bounce(const PassArgs& A, uint32_t path, int j,
     ev.texel = texel_of(sc, s, sc.mat_tex[mat]);
     ev.rho = ld3(A.albedo + (size_t)ev.texel * 3);
     if (cmode) ev.valid = connect(sc, s, r.w, A.Kfilm, ev.ux, ev.uy, ev.g, stk, ss, cmode == 2);
+    // the tent filter has kinks where u - 1/2 is an integer: within 1e-3 px
+    // of one the splat-position derivative is one-sided (rounding picks the side)
+    if (ev.valid && (near_kink(ev.ux) || near_kink(ev.uy))) ev.illc = true;
     if (j < A.D) {
       f3 na = ev.cos_in < 0.0f ? s.ng : s.ng * -1.0f;
       r.w = cosine_dir(na, u.u0, u.u1);
@@ -131,6 +140,22 @@ __device__ __forceinline__ void flush_le(const PassArgs& A, double g0, double g1
   }
 }
 
+// Vertex 0 of a path.  With a guide the emitted direction and its density q
+// come from the per-path record of the guide pass (same position draw);
+// beta_1 = L_e * A cos / q, the density held fixed in every derivative.
+__device__ __forceinline__ float emit_path(const PassArgs& A, uint32_t path, Ray& r) {
+  float f = emit(A.sc, A.seed, path, r);
+  if (A.guide_rec) {
+    float4 g = A.guide_rec[path];
+    r.w = mk(g.x, g.y, g.z);
+    float c = fmaxf(dot(r.w, ld3(A.sc.em_n)), 0.f);
+    f = g.w > 0.f ? A.sc.em_area * c / g.w : 0.f;
+  }
+  return f;
+}
+
+__device__ __forceinline__ float luminance(f3 c) { return 0.2126f * c.x + 0.7152f * c.y + 0.0722f * c.z; }
+
 // ---------------------------------------------------------------- forward
 // Light tracing with a connection + splat at every Lambertian vertex
 // (Eq. 1-2, Eq. 20).  RESV: streams valid connections through a capacity-1
@@ -152,12 +177,14 @@ __global__ void __launch_bounds__(1024) k_trace(PassArgs A) {
   float Om = 0.f, omR = 0.f, uxR = 0.f, uyR = 0.f;
   int R = 0;
   f3 CR = {0.f, 0.f, 0.f};
+  float fac = 0.f, Sl = 0.f;  // emission factor, path contribution sum_i lum(C_i)
   const f3 Le = ld3(A.Le);
   while (true) {
     refill(A, alive, exhausted, path, [&](uint32_t p) {
       if (TAPE) A.tape_len[p] = 0;
       if (RESV && A.res) { ResRec z{}; A.res[p] = z; }
       if (A.sig) A.sig[p] = 0u;
+      if (A.contrib) A.contrib[p] = 0.f;
     });
     if (__ballot(alive) == 0ull) break;
     bool has = false;
@@ -165,18 +192,19 @@ __global__ void __launch_bounds__(1024) k_trace(PassArgs A) {
     f3 sC = {0.f, 0.f, 0.f};
     if (alive) {
       if (j == 0) {  // new path: vertex 0 on the emitter
-        float f = emit(A.sc, A.seed, path, r);
-        beta = Le * f;
+        fac = emit_path(A, path, r);
+        beta = Le * fac;
         j = 1; nrec = 0; sig = 0x811C9DC5u;
-        Om = 0.f; omR = 0.f; R = 0;
+        Om = 0.f; omR = 0.f; R = 0; Sl = 0.f;
       }
       Event ev = bounce(A, path, j, r, 1, stk, ss);
       if (A.sig) sig = sig_event(sig, ev);
       if (ev.kind == 1 && ev.valid) {
         f3 C = mul(beta, ev.rho) * ev.g;
         if (!selected) { has = true; sux = ev.ux; suy = ev.uy; sC = C; }
+        Sl += luminance(C);
         if (RESV) {
-          float om = 0.2126f * C.x + 0.7152f * C.y + 0.0722f * C.z;
+          float om = luminance(C);
           if (om > 0.0f) {
             Om += om;
             if (ev.u_res < om / Om) { R = j; omR = om; uxR = ev.ux; uyR = ev.uy; CR = C; }
@@ -190,7 +218,7 @@ __global__ void __launch_bounds__(1024) k_trace(PassArgs A) {
         else
           t.tf = kTfDielectric;
         t.g = ev.g; t.ux = ev.ux; t.uy = ev.uy;
-        t.b[0] = beta.x; t.b[1] = beta.y; t.b[2] = beta.z; t.pad = 0.f;
+        t.b[0] = beta.x; t.b[1] = beta.y; t.b[2] = beta.z; t.pad = fac;
         A.tape[(size_t)(j - 1) * (size_t)A.n_paths + path] = t;
         LT_COUNT(8, 1);
         ++nrec;
@@ -209,6 +237,7 @@ __global__ void __launch_bounds__(1024) k_trace(PassArgs A) {
         }
         if (TAPE) A.tape_len[path] = nrec;
         if (A.sig) A.sig[path] = fnv1a(sig, (uint32_t)R);
+        if (A.contrib) A.contrib[path] = Sl;
         alive = false; j = 0;
       }
     }
@@ -219,7 +248,7 @@ __global__ void __launch_bounds__(1024) k_trace(PassArgs A) {
 // ---------------------------------------------------------------- naive AD
 // Reverse sweep over the tape, exact chain rule (no inverses, no division):
 //   C_j = beta_j rho_j g_j,  beta_{j+1} = beta_j rho_j (Lambertian scatter),
-//   beta_1 = L_e * emit_factor.
+//   beta_1 = L_e * f, with the path's emission factor f taped in every record.
 // Lanes of a wave walk their tapes in lock step so that the texel
 // gradients are scattered cooperatively.
 __global__ void __launch_bounds__(256) k_naive_bwd(PassArgs A) {
@@ -235,6 +264,7 @@ __global__ void __launch_bounds__(256) k_naive_bwd(PassArgs A) {
     int kmax = k;
     for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o));
     f3 bb = {0.f, 0.f, 0.f};  // adjoint of beta_{j+1}
+    float fac = 0.f;
     for (int s = 0; s < kmax; ++s) {
       int j = k - s;
       bool has = false;
@@ -243,6 +273,7 @@ __global__ void __launch_bounds__(256) k_naive_bwd(PassArgs A) {
       if (j >= 1) {
         TapeRec t = A.tape_in[(size_t)(j - 1) * N + path];
         LT_COUNT(9, 1);
+        fac = t.pad;
         if (t.tf & kTfLambert) {  // dielectric: weight 1, adjoint passes through
           texel = min((int)(t.tf & kTexMask), A.n_texels - 1);
           f3 rho = ld3(A.albedo + (size_t)texel * 3);
@@ -264,9 +295,9 @@ __global__ void __launch_bounds__(256) k_naive_bwd(PassArgs A) {
       scatter3_wave(A.g_albedo, has, texel, gr);
     }
     if (live) {
-      gl0 += (double)bb.x * A.emit_factor;
-      gl1 += (double)bb.y * A.emit_factor;
-      gl2 += (double)bb.z * A.emit_factor;
+      gl0 += (double)bb.x * fac;
+      gl1 += (double)bb.y * fac;
+      gl2 += (double)bb.z * fac;
     }
   }
   flush_le(A, gl0, gl1, gl2);
@@ -305,7 +336,7 @@ __global__ void __launch_bounds__(1024) k_reslrb_bwd(PassArgs A) {
         if (Le.x > 0.f) gl0 += (double)w.x / Le.x;
         if (Le.y > 0.f) gl1 += (double)w.y / Le.y;
         if (Le.z > 0.f) gl2 += (double)w.z / Le.z;
-        emit(A.sc, A.seed, path, r);
+        emit_path(A, path, r);
         j = 1;
       }
     }
@@ -350,14 +381,14 @@ __global__ void __launch_bounds__(1024) k_lrb3_bwd(PassArgs A) {
   const f3 Le = ld3(A.Le);
   double gl0 = 0.0, gl1 = 0.0, gl2 = 0.0;
   while (true) {
-    refill(A, alive, exhausted, path, [&](uint32_t) {});
+    refill(A, alive, exhausted, path, [&](uint32_t p) { if (A.contrib) A.contrib[p] = 0.f; });
     if (__ballot(alive) == 0ull) break;
     bool has = false;
     int texel = 0;
     f3 gv = {0.f, 0.f, 0.f};
     if (alive) {
       if (j == 0) {
-        float f = emit(A.sc, A.seed, path, r);
+        float f = emit_path(A, path, r);
         beta = Le * f;
         j = 1;
         if (phase == 2) { d0 = d1 = d2 = 0.0; vmask = 0ull; klast = 0; }
@@ -393,8 +424,11 @@ __global__ void __launch_bounds__(1024) k_lrb3_bwd(PassArgs A) {
         if (Le.x > 0.f) gl0 += d0 / Le.x;
         if (Le.y > 0.f) gl1 += d1 / Le.y;
         if (Le.z > 0.f) gl2 += d2 / Le.z;
+        // the path's adjoint-weighted contribution |delta_total|
+        if (A.contrib) A.contrib[path] = (float)(fabs(d0) + fabs(d1) + fabs(d2));
         phase = 3; j = 0;
       } else {
+        if (A.contrib && phase == 2) A.contrib[path] = 0.f;
         phase = 2; j = 0; alive = false;
       }
     }

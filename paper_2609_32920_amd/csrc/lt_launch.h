@@ -13,7 +13,6 @@ struct PassArgs {
   int32_t D;
   uint32_t flags;
   float Kfilm;          // width*height / (A_film * N)
-  float emit_factor;    // beta_0 = L_e * emit_factor
   int32_t n_texels;     // n_tex * tex_res^2
   const uint8_t* mask;
   uint32_t* sig;
@@ -42,7 +41,38 @@ struct PassArgs {
   float* g_heights;
   unsigned long long* stats;  // [0] guard triggers, [1] non-finite drops
   int32_t hgrad_lds;          // heights gradients accumulated per workgroup in LDS
+  const float4* guide_rec;    // guided emission (direction, density) per path, or null
+  float* contrib;             // per-path image contribution sum_i lum(C_i), or null
 };
+
+typedef unsigned int lt_u32x4 __attribute__((ext_vector_type(4)));
+
+// Emission-guide passes.
+struct GuideArgs {
+  DevScene sc;
+  uint64_t seed;
+  int64_t count;             // paths (emit) or samples (grad) or items (eval)
+  const float* w;            // FP32 parameters (biases read from here)
+  const lt_u32x4* packed;    // bf16 operand tiles from k_guide_pack
+  float4* rec;               // emit: per-path (direction, density)
+  float* samples;            // emit: optional [count][12] out; grad: [count][12] in
+  const float* contrib;      // emit: per-path S for the samples, or null
+  const float* x;            // eval inputs [count][3]
+  const float* n;
+  float* out;                // eval outputs [count][41]
+  float* partial;            // grad: [grid][11434] partial sums
+};
+
+size_t guide_packed_bytes();
+size_t guide_partial_floats();
+hipError_t guide_init();
+hipError_t launch_guide_pack(const float* w, void* packed, hipStream_t s);
+hipError_t launch_guide_eval(const GuideArgs& G, int grid, hipStream_t s);
+hipError_t launch_guide_emit(const GuideArgs& G, int grid, hipStream_t s);
+hipError_t launch_guide_grad(const GuideArgs& G, int grid, hipStream_t s);
+hipError_t launch_guide_reduce(const float* partial, int n_part, float* grad, float* loss, hipStream_t s);
+hipError_t launch_guide_adam(float* w, const float* grad, float* m, float* v, int n, float lr, float b1, float b2,
+                             float eps, float c1, float c2, hipStream_t s);
 
 hipError_t launch_trace(const PassArgs& A, bool tape, bool resv, int grid, int block, hipStream_t s);
 hipError_t launch_naive_bwd(const PassArgs& A, int grid, hipStream_t s);

@@ -7,7 +7,8 @@ fallback.
 
 The functions carry the C ABI's names (include/lt.h):
   lt_create / lt_scene_upload / lt_trace / lt_loss_l2 /
-  lt_backward_naive / lt_backward_reslrb / lt_backward_lrb3
+  lt_backward_naive / lt_backward_reslrb / lt_backward_lrb3 /
+  lt_guide_eval / lt_guide_emit / lt_guide_grad / lt_guide_adam
 and ``LightTrace`` wraps forward + a chosen reverse mode as a
 ``torch.autograd.Function``.
 """
@@ -53,11 +54,17 @@ class SceneDesc(C.Structure):
 class TraceArgs(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("n_paths", C.c_int64), ("max_depth", C.c_int32),
                 ("flags", C.c_uint32), ("path_mask", C.c_void_p), ("path_sig", C.c_void_p),
-                ("path_info", C.c_void_p)]
+                ("path_info", C.c_void_p), ("path_contrib", C.c_void_p)]
 
 
 class Params(C.Structure):
-    _fields_ = [("albedo", C.c_void_p), ("emitter_L", C.c_void_p), ("heights", C.c_void_p)]
+    _fields_ = [("albedo", C.c_void_p), ("emitter_L", C.c_void_p), ("heights", C.c_void_p),
+                ("guide_w", C.c_void_p)]
+
+
+GUIDE_NPARAMS = 11433
+GUIDE_NOUT = 41
+GUIDE_SAMPLE_FLOATS = 12   # lt_guide_sample: x[3] n[3] w[3] pdf S comp
 
 
 class Grads(C.Structure):
@@ -102,6 +109,10 @@ def library(path=LIB_PATH):
             "lt_backward_reslrb": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp, vp, C.c_size_t,
                                     C.POINTER(Grads)], C.c_int),
             "lt_backward_lrb3": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp, C.POINTER(Grads)], C.c_int),
+            "lt_guide_eval": ([vp, vp, vp, vp, C.c_int64, vp], C.c_int),
+            "lt_guide_emit": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp, vp], C.c_int),
+            "lt_guide_grad": ([vp, vp, vp, C.c_int64, vp, vp], C.c_int),
+            "lt_guide_adam": ([vp, vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float], C.c_int),
         }
         for name, (argt, rest) in sig.items():
             fn = getattr(lib, name)
@@ -115,7 +126,7 @@ def exported_symbols():
     return ["lt_create", "lt_destroy", "lt_last_error", "lt_set_stream", "lt_set_tuning", "lt_get_tuning",
             "lt_set_memory_cap", "lt_get_stats", "lt_read_counters", "lt_scene_upload", "lt_side_state_bytes",
             "lt_workspace_bytes", "lt_trace", "lt_loss_l2", "lt_backward_naive", "lt_backward_reslrb",
-            "lt_backward_lrb3"]
+            "lt_backward_lrb3", "lt_guide_eval", "lt_guide_emit", "lt_guide_grad", "lt_guide_adam"]
 
 
 def _ptr(t):
@@ -223,16 +234,18 @@ class Context:
         return self
 
     # ------------------------------------------------------------ passes
-    def args(self, seed, n_paths, depth, flags=0, mask=None, sig=None, info=None):
+    def args(self, seed, n_paths, depth, flags=0, mask=None, sig=None, info=None, contrib=None):
         a = TraceArgs()
         a.seed, a.n_paths, a.max_depth, a.flags = int(seed), int(n_paths), int(depth), int(flags)
         a.path_mask = None if mask is None else mask.data_ptr()
         a.path_sig = None if sig is None else sig.data_ptr()
         a.path_info = None if info is None else info.data_ptr()
+        a.path_contrib = None if contrib is None else contrib.data_ptr()
         return a
 
-    def params(self, albedo, Le, heights=None):
-        return Params(albedo.data_ptr(), Le.data_ptr(), None if heights is None else heights.data_ptr())
+    def params(self, albedo, Le, heights=None, guide_w=None):
+        return Params(albedo.data_ptr(), Le.data_ptr(), None if heights is None else heights.data_ptr(),
+                      None if guide_w is None else guide_w.data_ptr())
 
     def side_state_bytes(self, a):
         return int(self.lib.lt_side_state_bytes(self.h, C.byref(a)))
@@ -274,6 +287,28 @@ class Context:
         g = self._grads(g_albedo, g_Le, g_heights)
         self._check(self.lib.lt_backward_lrb3(self.h, C.byref(a), C.byref(p), _ptr(d_image), C.byref(g)))
 
+    # ------------------------------------------------------------ guide
+    def guide_eval(self, guide_w, x, n, out):
+        """Raw network outputs out [count, 41] at x, n [count, 3] (device float32)."""
+        self._stream()
+        self._check(self.lib.lt_guide_eval(self.h, _ptr(guide_w), _ptr(x), _ptr(n), x.shape[0], _ptr(out)))
+
+    def guide_emit(self, a, p, samples, contrib=None):
+        """Guided emission of paths [0, n_paths) as samples [n_paths, 12]."""
+        self._stream()
+        self._check(self.lib.lt_guide_emit(self.h, C.byref(a), C.byref(p), _ptr(contrib), _ptr(samples)))
+
+    def guide_grad(self, guide_w, samples, grad, loss=None):
+        """Training loss and gradient over samples [count, 12] (device float32)."""
+        self._stream()
+        self._check(self.lib.lt_guide_grad(self.h, _ptr(guide_w), _ptr(samples), samples.shape[0], _ptr(grad),
+                                           _ptr(loss)))
+
+    def guide_adam(self, w, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._stream()
+        self._check(self.lib.lt_guide_adam(self.h, _ptr(w), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr),
+                                           float(beta1), float(beta2), float(eps)))
+
 
 # C-ABI names as module-level functions -------------------------------------
 def lt_create(device=0):
@@ -302,6 +337,22 @@ def lt_backward_reslrb(ctx, args, params, d_image, records, g_albedo, g_Le, g_he
 
 def lt_backward_lrb3(ctx, args, params, d_image, g_albedo, g_Le, g_heights=None):
     return ctx.backward_lrb3(args, params, d_image, g_albedo, g_Le, g_heights)
+
+
+def lt_guide_eval(ctx, guide_w, x, n, out):
+    return ctx.guide_eval(guide_w, x, n, out)
+
+
+def lt_guide_emit(ctx, args, params, samples, contrib=None):
+    return ctx.guide_emit(args, params, samples, contrib)
+
+
+def lt_guide_grad(ctx, guide_w, samples, grad, loss=None):
+    return ctx.guide_grad(guide_w, samples, grad, loss)
+
+
+def lt_guide_adam(ctx, w, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    return ctx.guide_adam(w, grad, m, v, step, lr, beta1, beta2, eps)
 
 
 # ------------------------------------------------------------ autograd

@@ -286,3 +286,20 @@ def guide_sample_batch(sc, count, seed, zero_frac=0.25):
     out = np.zeros((count, 12))
     out[:, 0:3], out[:, 3:6], out[:, 6:9], out[:, 9], out[:, 10] = x, nrm, d, q, S
     return out
+
+
+def guide_aimed_weights(direction=(0.0, -1.0, 0.0), logk=2.0, spread=0.3, seed=GUIDE_SEED):
+    """A guide whose 8 lobes point near `direction` (mean direction plus
+    N(0, spread^2) per component), log-concentration `logk`, equal logits and
+    mixing logit 1: the shape a guide trained on a scene below the emitter
+    takes.  Hidden layers as guide_weights; only the output biases are set."""
+    w = guide_weights(seed)
+    rng = np.random.default_rng(seed + 1)
+    b4 = w[GUIDE_NPARAMS - 41:]
+    d = np.asarray(direction, np.float64)
+    for k in range(8):
+        b4[5 * k:5 * k + 3] = d + spread * rng.normal(size=3)
+        b4[5 * k + 3] = logk
+        b4[5 * k + 4] = 0.0
+    b4[40] = 1.0
+    return w

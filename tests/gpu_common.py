@@ -25,6 +25,14 @@ class GpuRun:
         h = sc.get("heights")
         self.heights = None if h is None else torch.as_tensor(np.asarray(h, np.float32), device=self.dev)
         self.H, self.W = sc["camera"]["height"], sc["camera"]["width"]
+        self.guide = None
+
+    def set_guide(self, w):
+        """Guided emission with these weights (None: cosine emission)."""
+        self.guide = None if w is None else torch.as_tensor(np.asarray(w, np.float32), device=self.dev).contiguous()
+
+    def params(self):
+        return self.ctx.params(self.albedo, self.Le, self.heights, self.guide)
 
     def set_params(self, albedo=None, Le=None, heights=None):
         if albedo is not None:
@@ -40,7 +48,7 @@ class GpuRun:
         if mask is not None:
             m = torch.as_tensor(np.asarray(mask, np.uint8), device=self.dev)
         a = self.ctx.args(seed, n, depth, flags, m, sig)
-        p = self.ctx.params(self.albedo, self.Le, self.heights)
+        p = self.params()
         nb = self.ctx.side_state_bytes(a)
         side = torch.zeros(max(nb, 1), dtype=torch.uint8, device=self.dev)
         img = torch.empty((self.H, self.W, 3), dtype=torch.float32, device=self.dev)
@@ -56,7 +64,7 @@ class GpuRun:
         rec = lt.RECORD_TAPE if mode == "naive" else lt.RECORD_RESERVOIR if mode == "reslrb" else 0
         info = torch.zeros(n, dtype=torch.int32, device=self.dev) if want_info else None
         a = self.ctx.args(seed, n, depth, flags | rec, m, None, info)
-        p = self.ctx.params(self.albedo, self.Le, self.heights)
+        p = self.params()
         dIt = torch.as_tensor(np.asarray(dI, np.float32), device=self.dev).contiguous()
         if side is None and mode != "lrb3":
             nb = self.ctx.side_state_bytes(a)
@@ -81,9 +89,31 @@ class GpuRun:
         return out
 
 
-def matched_paths(sc, g, seed, n, depth, flags=0):
-    """Per-path signatures from both sides; returns (mask, ids, mismatch fraction)."""
+def matched_paths(sc, g, seed, n, depth, flags=0, keep=None):
+    """Per-path signatures from both sides; returns (mask, ids, mismatch fraction).
+    keep: optional boolean [n] pre-selection (e.g. matching guided emission)."""
+    ow = None if g.guide is None else g.guide.cpu().numpy().astype(np.float64)
     gs = g.trace(seed, n, depth, flags, want_sig=True)["sig"]
-    os_ = O.render(sc, seed, n, depth, flags=flags, per_path=True)["sig"]
+    os_ = O.render(sc, seed, n, depth, flags=flags, per_path=True, guide_w=ow)["sig"]
     same = gs == os_
+    if keep is not None:
+        same &= keep
     return same.astype(np.uint8), np.nonzero(same)[0].astype(np.uint32), 1.0 - same.mean()
+
+
+def guide_emission_match(sc, g, seed, n, tol=2e-6, pdf_rtol=2e-5):
+    """Paths whose guided emission agrees on both sides: same mixture
+    component, directions within tol and densities within pdf_rtol.  Inside
+    the network a bfloat16 rounding can flip between FP32 and FP64
+    accumulation (one ulp of one activation); such paths leave with a
+    slightly different direction or weight and are told apart here, like
+    decision flips by their signatures."""
+    a = g.ctx.args(seed, n, 1)
+    smp = torch.zeros((n, 12), dtype=torch.float32, device=g.dev)
+    g.ctx.guide_emit(a, g.params(), smp)
+    torch.cuda.synchronize()
+    gs = smp.cpu().numpy().astype(np.float64)
+    oe = O.guide_emit(sc, seed, n, g.guide.cpu().numpy().astype(np.float64))
+    same = (gs[:, 11].astype(np.int32) == oe["comp"]) & (np.abs(gs[:, 6:9] - oe["w"]).max(axis=1) <= tol)
+    same &= np.abs(gs[:, 9] - oe["pdf"]) <= pdf_rtol * np.abs(oe["pdf"])
+    return same, gs, oe

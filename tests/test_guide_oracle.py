@@ -270,3 +270,32 @@ def test_guided_gradient_matches_finite_differences():
         Im = O.render(sc, seed, n, D, Le=lm, guide_w=w)["image"]
         fdl.append(np.sum(dI * (Ip - Im)) / 2e-5)
     np.testing.assert_allclose(g["Le"], fdl, rtol=1e-6)
+
+
+def test_guided_attached_heights_match_finite_differences():
+    # guided emission leaves the attached derivative structure alone: the
+    # emitted direction is fixed in world space and its density is held
+    # fixed, so the heights gradient of the guided estimator is the
+    # derivative of the guided image (central differences, equal signatures)
+    sc = scenes.caustic_scene(G=8, width=32, height=32)
+    w = scenes.guide_aimed_weights()
+    seed, n, D = 5, 4096, 4
+    T = O.render(sc, 99, n, D, heights=sc["heights_target"])["image"]
+    r0 = O.render(sc, seed, n, D, per_path=True, guide_w=w)
+    _, dI = O.loss_and_adjoint(r0["image"], T)
+    gh = O.gradient(sc, seed, n, D, dI, flags=O.ATTACHED, guide_w=w)["heights"]
+    assert np.count_nonzero(gh) > 20
+    h0 = sc["heights"].copy()
+    eps, checked = 1e-7, 0
+    for k in np.argsort(-np.abs(gh))[:12]:
+        hp, hm = h0.copy(), h0.copy()
+        hp[k] += eps
+        hm[k] -= eps
+        rp = O.render(sc, seed, n, D, heights=hp, per_path=True, guide_w=w)
+        rm = O.render(sc, seed, n, D, heights=hm, per_path=True, guide_w=w)
+        if not (np.array_equal(rp["sig"], r0["sig"]) and np.array_equal(rm["sig"], r0["sig"])):
+            continue
+        fd = (O.loss_and_adjoint(rp["image"], T)[0] - O.loss_and_adjoint(rm["image"], T)[0]) / (2 * eps)
+        assert abs(fd - gh[k]) <= 1e-5 * np.abs(gh).max(), (k, fd, gh[k])
+        checked += 1
+    assert checked >= 8
