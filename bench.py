@@ -33,6 +33,9 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true", help="skip the per-method / per-depth sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-caustic", action="store_true", help="skip the attached caustic workload")
+    ap.add_argument("--no-guide", action="store_true", help="skip the learned-guide workload")
+    ap.add_argument("--guide-iters", type=int, default=40, help="online training iterations of the guide")
+    ap.add_argument("--guide-seeds", type=int, default=8, help="seeds per gradient-variance estimate")
     ap.add_argument("--cpu-paths", type=int, default=1 << 15)
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for profiler byte counters)")
@@ -176,6 +179,11 @@ def main():
     if not args.no_caustic:
         caustic = bench_caustic(lt, scenes, dev, stream, bytes_per_path)
 
+    # ---- learned guide: gradient variance x time, guided vs cosine emission
+    guide = None
+    if not args.no_guide:
+        guide = bench_guide(lt, scenes, dev, stream, iters=args.guide_iters, K=args.guide_seeds)
+
     # ---- CPU baseline: the FP64 oracle, forward + naive backward, on a sample
     cpu = None
     if not args.no_cpu:
@@ -213,6 +221,7 @@ def main():
         "cpu_baseline": cpu,
         "sweep": sweep,
         "caustic": caustic,
+        "guide": guide,
     }
     print(json.dumps(out), flush=True)
 
@@ -285,6 +294,89 @@ def bench_caustic(lt, scenes, dev, stream, bytes_per_path_fn, G=128, film=512, N
         del cctx
     except Exception as e:
         print(f"# caustic counters unavailable: {e}", file=sys.stderr)
+    return out
+
+
+def bench_guide(lt, scenes, dev, stream, G=256, film=1024, N=1 << 26, D=8, iters=30, K=8, n_train=1 << 20):
+    """Learned emission guide on the caustic scene (film^2, G x G heights,
+    depth D, N paths per iteration): the guide is trained online on the
+    per-path gradient magnitudes the LRB-3 backward writes, then the heights
+    gradient's variance over K seeds (fixed image adjoint) and the time per
+    forward + backward iteration are compared with cosine emission."""
+    import numpy as np
+    import torch
+
+    sc = scenes.caustic_scene(G=G, width=film, height=film)
+    ctx = lt.Context(0).scene_upload(sc)
+    f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32), device=dev).contiguous()
+    albedo, Le, h, ht = f32(sc["albedo"]), f32(sc["Le"]), f32(sc["heights"]), f32(sc["heights_target"])
+    img = torch.empty((film, film, 3), dtype=torch.float32, device=dev)
+    target, dI = torch.empty_like(img), torch.empty_like(img)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    ctx.trace(ctx.args(0x7A6, N, D, lt.ATTACHED), ctx.params(albedo, Le, ht), target)
+    ctx.trace(ctx.args(0x7A7, N, D, lt.ATTACHED), ctx.params(albedo, Le, h), img)
+    ctx.loss_l2(img, target, dI, loss)
+    ga, gl, gh = torch.zeros_like(albedo), torch.zeros_like(Le), torch.zeros_like(h)
+
+    def iteration(seed, gw, contrib=None):
+        p = ctx.params(albedo, Le, h, gw)
+        ctx.trace(ctx.args(seed, N, D, lt.ATTACHED), p, img)
+        ga.zero_(); gl.zero_(); gh.zero_()
+        ctx.backward_lrb3(ctx.args(seed, N, D, lt.ATTACHED, contrib=contrib), p, dI, ga, gl, gh)
+
+    def estimate(gw):
+        gs, ts = [], []
+        for k in range(K):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            iteration(70000 + k, gw)
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+            gs.append(gh.double().clone())
+        gs = torch.stack(gs)
+        return gs, float(np.median(ts))
+
+    iteration(69999, None)  # warm-up
+    g0, t0 = estimate(None)
+    w = f32(scenes.guide_weights())
+    m, v, gw_grad = torch.zeros_like(w), torch.zeros_like(w), torch.zeros_like(w)
+    gloss = torch.zeros(1, dtype=torch.float32, device=dev)
+    contrib = torch.zeros(N, dtype=torch.float32, device=dev)
+    smp = torch.zeros((n_train, 12), dtype=torch.float32, device=dev)
+    tt = []
+    for it in range(1, iters + 1):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        iteration(60000 + it, w, contrib)
+        e1.record(stream)
+        p = ctx.params(albedo, Le, h, w)
+        ctx.guide_emit(ctx.args(60000 + it, n_train, D), p, smp, contrib)
+        ctx.guide_grad(w, smp, gw_grad, gloss)
+        ctx.guide_adam(w, gw_grad, m, v, it, 1e-2)
+        e2.record(stream)
+        e2.synchronize()
+        tt.append((e0.elapsed_time(e1), e1.elapsed_time(e2)))
+    g1, t1 = estimate(w)
+    dropped = ctx.stats()["nonfinite"]
+    v0, v1 = g0.var(0).sum().item(), g1.var(0).sum().item()
+    se = torch.sqrt(g0.var(0) / K + g1.var(0) / K)
+    ok = se > 0
+    z = (g1.mean(0) - g0.mean(0))[ok] / se[ok]
+    cos_share = float((smp[:, 11] == 0).float().mean().item())
+    out = {"workload": f"glass heightfield slab {G}x{G} heights, film {film}x{film}, depth {D}, {N} paths per "
+                       f"iteration, attached LRB-3-pass gradients w.r.t. heights; guide trained online for {iters} "
+                       f"iterations on {n_train} samples each (target: per-path gradient magnitude)",
+           "ms_per_iter_cosine": round(t0, 3), "ms_per_iter_guided": round(t1, 3),
+           "train_ms_per_iter": round(float(np.median([a + b for a, b in tt])), 3),
+           "guide_update_ms": round(float(np.median([b for _, b in tt])), 3),
+           "variance_cosine": v0, "variance_guided": v1, "variance_ratio": round(v1 / v0, 4),
+           "efficiency_gain": round((v0 * t0) / (v1 * t1), 4),
+           "bias_mean_z2": round(float((z * z).mean().item()), 4), "seeds": K,
+           "cosine_share_after_training": round(cos_share, 4),
+           "nonfinite_dropped_last_iteration": int(dropped)}
+    print(f"# guide: variance ratio {v1 / v0:.3f}, efficiency gain {(v0 * t0) / (v1 * t1):.3f}, "
+          f"iteration {t0:.1f} -> {t1:.1f} ms, bias z^2 {out['bias_mean_z2']}", file=sys.stderr, flush=True)
     return out
 
 

@@ -158,7 +158,8 @@ typedef struct {
 /* Counters from the last call that produced them. */
 typedef struct {
   uint64_t guard_triggers;  /* attached: singular accumulated Jacobians zeroed (Sec. 5) */
-  uint64_t nonfinite;       /* non-finite contributions dropped */
+  uint64_t nonfinite;       /* non-finite values (splats, gradient contributions) dropped
+                               before they reach the image or a gradient */
 } lt_stats;
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
@@ -302,12 +303,14 @@ lt_status lt_guide_eval(lt_ctx* ctx, const float* guide_w, const float* x, const
 lt_status lt_guide_emit(lt_ctx* ctx, const lt_trace_args* args, const lt_params* params,
                         const float* path_contrib, lt_guide_sample* out);
 
-/* Training loss L = -(1/count) sum_b (S_b / q_b) log q_theta(w_b | x_b, n_b)
- * (a Monte Carlo estimate of the KL divergence from the contribution-
- * proportional density to q_theta, up to a constant) and its gradient.
+/* Training loss L = -sum_b (S_b / q_b) log q_theta(w_b | x_b, n_b) / Z with
+ * Z = sum_b S_b / q_b (a self-normalised Monte Carlo estimate of the KL
+ * divergence from the S-proportional density to q_theta, up to a constant;
+ * invariant to the scale of S, which falls as 1/n_paths) and its gradient.
  * samples: DEVICE [count]; grad: DEVICE [LT_GUIDE_NPARAMS], overwritten;
  * loss: DEVICE [1] or NULL.  Samples with q <= 0 or S == 0 contribute
- * nothing.  Deterministic (fixed reduction order).
+ * nothing; with no contributing sample the loss and gradient are zero.
+ * Deterministic (fixed reduction order).
  * Errors: LT_ERR_ARG, LT_ERR_STATE, LT_ERR_OOM (cap), LT_ERR_HIP. */
 lt_status lt_guide_grad(lt_ctx* ctx, const float* guide_w, const lt_guide_sample* samples, int64_t count,
                         float* grad, float* loss);

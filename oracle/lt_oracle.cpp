@@ -945,23 +945,29 @@ int ora_guide_emit(const ora_scene* sc, const ora_args* A, double* rec, int32_t*
   return 0;
 }
 
-// Training loss L = -(1/count) sum_b (S_b / q_b) log q_theta(w_b | x_b, n_b) and
-// its gradient w.r.t. the parameters (added to grad [11433]).
-// samples [count][12] = x (3), n (3), w (3), q (sampling density), S, unused.
+// Training loss L = -sum_b (S_b / q_b) log q_theta(w_b | x_b, n_b) / Z, with
+// Z = sum_b S_b / q_b (self-normalised, so the scale of S does not matter),
+// and its gradient w.r.t. the parameters (added to grad [11433]); zero when
+// Z is.  samples [count][12] = x (3), n (3), w (3), q (sampling density), S, unused.
 int ora_guide_loss_grad(const ora_scene* sc, const double* w, const double* samples, int64_t count, int bf16,
                         double* grad, double* loss) {
   double c[3], h[3]; scene_box(sc, c, h);
+  double Z = 0.0;
+  for (int64_t b = 0; b < count; ++b) {
+    const double* s = samples + b * 12;
+    if (s[9] > 0.0 && s[10] != 0.0) Z += s[10] / s[9];
+  }
   double L = 0.0;
   for (int64_t b = 0; b < count; ++b) {
     const double* s = samples + b * 12;
     double qs = s[9], S = s[10];
-    if (!(qs > 0.0) || S == 0.0) continue;
+    if (!(qs > 0.0) || S == 0.0 || !(Z > 0.0)) continue;
     double f[kGIn];
     D3 nn = {s[3], s[4], s[5]};
     guide_features(c, h, {s[0], s[1], s[2]}, nn, f);
     GuideAct a; guide_forward(w, f, bf16 != 0, a);
     double go[kGOut];
-    L += guide_loss_grad_o(a.o, nn, {s[6], s[7], s[8]}, S / (qs * (double)count), go);
+    L += guide_loss_grad_o(a.o, nn, {s[6], s[7], s[8]}, S / (qs * Z), go);
     guide_backward(w, a, go, bf16 != 0, grad);
   }
   if (loss) *loss = L;

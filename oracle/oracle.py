@@ -294,8 +294,8 @@ def guide_emit(sc, seed, n_paths, guide_w, path_list=None, bf16=True):
 
 
 def guide_loss_grad(sc, w, samples, bf16=True):
-    """Training loss -(1/B) sum (S/q_s) log q(w|x,n) and its parameter gradient.
-    samples [B, 12] = x (3), n (3), w (3), sampling density q_s, S, unused."""
+    """Training loss -sum (S/q_s) log q(w|x,n) / sum (S/q_s) and its parameter
+    gradient.  samples [B, 12] = x (3), n (3), w (3), sampling density q_s, S, unused."""
     lib = _load()
     keep = _Keep()
     s = _scene(sc, keep)

@@ -695,6 +695,7 @@ lt_status lt_trace(lt_ctx* c, const lt_trace_args* a, const lt_params* p, float*
   size_t npix = (size_t)c->dsc.W * c->dsc.H * 3;
   if ((st = c->hip(launch_fill_f32(image, npix, 0.f, c->stream), "image clear")) != LT_OK) return st;
   if ((st = c->hip(launch_fill_u32(c->d_counter, 1, 0u, c->stream), "counter clear")) != LT_OK) return st;
+  if ((st = c->hip(launch_fill_u32(c->d_counter + 16, 4, 0u, c->stream), "stats clear")) != LT_OK) return st;
   bool tape = (a->flags & LT_RECORD_TAPE) != 0;
   if (att_rec) {
     bool rec = (a->flags & LT_RECORD_RESERVOIR) != 0;

@@ -483,9 +483,10 @@ __device__ __forceinline__ void bias_acc(const f32x4 (&dz)[4][4], float (&db)[4]
     for (int i = 0; i < 4; ++i) db[m][i] += dz[m][0][i] + dz[m][1][i] + dz[m][2][i] + dz[m][3][i];
 }
 
-// Loss -(1/count) sum_b (S_b / q_b) log q(w_b | x_b, n_b) and its gradient:
-// one wave per workgroup; each workgroup writes its partial gradient (and
-// loss, slot kGN) to partial[blockIdx.x][kGN + 1].
+// Unnormalised loss -sum_b (S_b / q_b) log q(w_b | x_b, n_b), its gradient and
+// Z = sum_b S_b / q_b: one wave per workgroup; each workgroup writes its
+// partial gradient, loss (slot kGN) and Z (slot kGN + 1) to
+// partial[blockIdx.x][kGN + 2]; the reduction divides by Z.
 __global__ void __launch_bounds__(64) k_guide_grad(GuideArgs G) {
   extern __shared__ float gg_lds[];
   float* stage = gg_lds;                                              // [64][kStage]
@@ -509,8 +510,7 @@ __global__ void __launch_bounds__(64) k_guide_grad(GuideArgs G) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) db1[m][i] = db2[m][i] = db3[m][i] = 0.f;
   }
-  float loss = 0.f;
-  const float inv_count = 1.0f / (float)G.count;
+  float loss = 0.f, zsum = 0.f;
   const int64_t n_tiles = (G.count + 63) / 64;
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     int64_t b = tile * 64 + lane;
@@ -518,7 +518,8 @@ __global__ void __launch_bounds__(64) k_guide_grad(GuideArgs G) {
     const float* smp = G.samples + (valid ? b : 0) * 12;
     f3 x = ld3(smp), n = ld3(smp + 3), w = ld3(smp + 6);
     float qs = smp[9], S = smp[10];
-    float c = (valid && qs > 0.f && S != 0.f) ? S / qs * inv_count : 0.f;
+    float c = (valid && qs > 0.f && S != 0.f) ? S / qs : 0.f;
+    zsum += c;
     float f[kGIn];
     features(G.sc, x, n, f);
     Fwd F;
@@ -576,7 +577,7 @@ __global__ void __launch_bounds__(64) k_guide_grad(GuideArgs G) {
     __syncthreads();
   }
   // write this workgroup's partial gradient
-  float* out = G.partial + (size_t)blockIdx.x * (kGN + 1);
+  float* out = G.partial + (size_t)blockIdx.x * (kGN + 2);
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -608,19 +609,27 @@ __global__ void __launch_bounds__(64) k_guide_grad(GuideArgs G) {
     }
   if (lane < kGOut) out[kGB4 + lane] = db4;
 #pragma unroll
-  for (int off = 1; off < 64; off <<= 1) loss += __shfl_xor(loss, off);
-  if (lane == 0) out[kGN] = loss;
+  for (int off = 1; off < 64; off <<= 1) {
+    loss += __shfl_xor(loss, off);
+    zsum += __shfl_xor(zsum, off);
+  }
+  if (lane == 0) { out[kGN] = loss; out[kGN + 1] = zsum; }
 }
 
-// grad[j] = sum over workgroups of partial[.][j] (fixed order); loss likewise.
+// grad[j] = (sum over workgroups of partial[.][j]) / Z, sums in fixed order;
+// loss likewise; everything zero when Z is.
 __global__ void k_guide_reduce(const float* __restrict__ partial, int n_part, float* __restrict__ grad,
                                float* __restrict__ loss) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j > kGN) return;
-  float s = 0.f;
-  for (int b = 0; b < n_part; ++b) s += partial[(size_t)b * (kGN + 1) + j];
-  if (j < kGN) grad[j] = s;
-  else if (loss) loss[0] = s;
+  float s = 0.f, z = 0.f;
+  for (int b = 0; b < n_part; ++b) {
+    s += partial[(size_t)b * (kGN + 2) + j];
+    z += partial[(size_t)b * (kGN + 2) + kGN + 1];
+  }
+  float r = z > 0.f ? s / z : 0.f;
+  if (j < kGN) grad[j] = r;
+  else if (loss) loss[0] = r;
 }
 
 // Adam (Kingma & Ba 2015); c1 = 1/(1-beta1^t), c2 = 1/(1-beta2^t).
@@ -642,7 +651,7 @@ __global__ void k_guide_adam(float* __restrict__ w, const float* __restrict__ gr
 
 // ------------------------------------------------------------ launchers
 size_t guide_packed_bytes() { return (size_t)kPAll * sizeof(u32x4); }
-size_t guide_partial_floats() { return (size_t)kGN + 1; }
+size_t guide_partial_floats() { return (size_t)kGN + 2; }
 static size_t emit_lds() { return (size_t)kPFwd * sizeof(u32x4) + 4 * 64 * kStage * sizeof(float); }
 static size_t grad_lds() { return 64 * kStage * sizeof(float) + (16 + 4 * 64) * kHS * sizeof(uint16_t); }
 

@@ -131,6 +131,23 @@ __device__ __forceinline__ void refill(const PassArgs& A, bool& alive, bool& exh
   }
 }
 
+// Non-finite values (a division by a vanishing cosine, length or
+// determinant on a degenerate path) never reach an atomic: they are dropped
+// and counted in stats[1].
+__device__ __forceinline__ void count_nonfinite(const PassArgs& A) {
+  if (A.stats) atomicAdd(A.stats + 1, 1ull);
+}
+__device__ __forceinline__ void keep_finite(const PassArgs& A, bool& has, f3 v) {
+  if (has && !(isfinite(v.x) && isfinite(v.y) && isfinite(v.z))) { has = false; count_nonfinite(A); }
+}
+// emitter-gradient accumulation of one path, (a0, a1, a2) in place of zeros
+// when any is non-finite
+__device__ __forceinline__ void add_le(const PassArgs& A, double& g0, double& g1, double& g2, double a0, double a1,
+                                       double a2) {
+  if (!(isfinite(a0) && isfinite(a1) && isfinite(a2))) { count_nonfinite(A); return; }
+  g0 += a0; g1 += a1; g2 += a2;
+}
+
 __device__ __forceinline__ void flush_le(const PassArgs& A, double g0, double g1, double g2) {
   g0 = wave_sum(g0); g1 = wave_sum(g1); g2 = wave_sum(g2);
   if (__lane_id() == 0 && A.g_Le_acc) {
@@ -241,6 +258,7 @@ __global__ void __launch_bounds__(1024) k_trace(PassArgs A) {
         alive = false; j = 0;
       }
     }
+    keep_finite(A, has, sC);
     splat_wave(A.sc, A.image, has, sux, suy, sC);
   }
 }
@@ -292,12 +310,11 @@ __global__ void __launch_bounds__(256) k_naive_bwd(PassArgs A) {
           has = true;
         }
       }
+      keep_finite(A, has, gr);
       scatter3_wave(A.g_albedo, has, texel, gr);
     }
     if (live) {
-      gl0 += (double)bb.x * fac;
-      gl1 += (double)bb.y * fac;
-      gl2 += (double)bb.z * fac;
+      add_le(A, gl0, gl1, gl2, (double)bb.x * fac, (double)bb.y * fac, (double)bb.z * fac);
     }
   }
   flush_le(A, gl0, gl1, gl2);
@@ -333,9 +350,8 @@ __global__ void __launch_bounds__(1024) k_reslrb_bwd(PassArgs A) {
         R = min(rec.R, A.D);
         f3 Lb = gather(A.sc, A.dI, rec.ux, rec.uy);
         w = mul(Lb, mk(rec.S[0], rec.S[1], rec.S[2]));
-        if (Le.x > 0.f) gl0 += (double)w.x / Le.x;
-        if (Le.y > 0.f) gl1 += (double)w.y / Le.y;
-        if (Le.z > 0.f) gl2 += (double)w.z / Le.z;
+        add_le(A, gl0, gl1, gl2, Le.x > 0.f ? (double)w.x / Le.x : 0.0, Le.y > 0.f ? (double)w.y / Le.y : 0.0,
+               Le.z > 0.f ? (double)w.z / Le.z : 0.0);
         emit_path(A, path, r);
         j = 1;
       }
@@ -351,6 +367,7 @@ __global__ void __launch_bounds__(1024) k_reslrb_bwd(PassArgs A) {
       if (ev.cont && j < R) ++j;
       else { alive = false; j = 0; }
     }
+    keep_finite(A, has, gv);
     scatter3_wave(A.g_albedo, has, texel, gv);
   }
   flush_le(A, gl0, gl1, gl2);
@@ -421,9 +438,8 @@ __global__ void __launch_bounds__(1024) k_lrb3_bwd(PassArgs A) {
       if (ev.cont) {
         ++j;
       } else if (phase == 2 && klast > 0 && (d0 != 0.0 || d1 != 0.0 || d2 != 0.0)) {  // consuming replay
-        if (Le.x > 0.f) gl0 += d0 / Le.x;
-        if (Le.y > 0.f) gl1 += d1 / Le.y;
-        if (Le.z > 0.f) gl2 += d2 / Le.z;
+        add_le(A, gl0, gl1, gl2, Le.x > 0.f ? d0 / Le.x : 0.0, Le.y > 0.f ? d1 / Le.y : 0.0,
+               Le.z > 0.f ? d2 / Le.z : 0.0);
         // the path's adjoint-weighted contribution |delta_total|
         if (A.contrib) A.contrib[path] = (float)(fabs(d0) + fabs(d1) + fabs(d2));
         phase = 3; j = 0;
@@ -432,6 +448,7 @@ __global__ void __launch_bounds__(1024) k_lrb3_bwd(PassArgs A) {
         phase = 2; j = 0; alive = false;
       }
     }
+    keep_finite(A, has, gv);
     scatter3_wave(A.g_albedo, has, texel, gv);
   }
   flush_le(A, gl0, gl1, gl2);

@@ -60,7 +60,7 @@ struct GuideArgs {
   const float* x;            // eval inputs [count][3]
   const float* n;
   float* out;                // eval outputs [count][41]
-  float* partial;            // grad: [grid][11434] partial sums
+  float* partial;            // grad: [grid][11435] partial sums (gradient, loss, Z)
 };
 
 size_t guide_packed_bytes();

@@ -200,3 +200,62 @@ def test_point_emitter_rejects_guide():
     with pytest.raises(lt.LTError) as e:
         g.trace(1, 1024, 2)
     assert e.value.status == lt.LT_ERR_UNSUPPORTED
+
+
+def test_trained_guide_reduces_gradient_variance():
+    """What the trained network gains: after online training on the
+    per-path gradient magnitudes of the LRB-3 backward, guided emission must
+    lower the attached heights gradient's variance x time below cosine
+    emission at equal path counts, and stay unbiased (mean z^2 ~ 1)."""
+    import time
+    from tests.gpu_common import GpuRun
+    sc = scenes.caustic_scene(G=32, width=128, height=128)
+    g = GpuRun(sc)
+    ctx, dev = g.ctx, g.dev
+    N, D, K = 1 << 20, 6, 16
+    img = torch.empty((128, 128, 3), device=dev)
+    T, dI, loss = torch.empty_like(img), torch.empty_like(img), torch.zeros(1, device=dev)
+    ctx.trace(ctx.args(999, 1 << 22, D, lt.ATTACHED),
+              ctx.params(g.albedo, g.Le, torch.as_tensor(np.asarray(sc["heights_target"], np.float32), device=dev)), T)
+    ctx.trace(ctx.args(998, 1 << 22, D, lt.ATTACHED), g.params(), img)
+    ctx.loss_l2(img, T, dI, loss)
+    ga, gl, gh = torch.zeros_like(g.albedo), torch.zeros_like(g.Le), torch.zeros_like(g.heights)
+
+    def grad(seed, contrib=None):
+        p = g.params()
+        ctx.trace(ctx.args(seed, N, D, lt.ATTACHED), p, img)
+        ga.zero_(); gl.zero_(); gh.zero_()
+        ctx.backward_lrb3(ctx.args(seed, N, D, lt.ATTACHED, contrib=contrib), p, dI, ga, gl, gh)
+        return gh
+
+    def estimate():
+        gs = []
+        grad(9999)  # warm-up outside the timed loop
+        torch.cuda.synchronize(); t0 = time.perf_counter()
+        for k in range(K):
+            gs.append(grad(10000 + k).double().clone())
+        torch.cuda.synchronize()
+        return torch.stack(gs), (time.perf_counter() - t0) / K
+
+    g.set_guide(None)
+    g0, t0 = estimate()
+    g.set_guide(scenes.guide_weights())
+    w = g.guide
+    m, v, gr = torch.zeros_like(w), torch.zeros_like(w), torch.zeros_like(w)
+    contrib = torch.zeros(N, device=dev)
+    smp = torch.zeros((1 << 18, 12), device=dev)
+    for it in range(1, 61):
+        grad(50000 + it, contrib)
+        ctx.guide_emit(ctx.args(50000 + it, 1 << 18, D), g.params(), smp, contrib)
+        ctx.guide_grad(w, smp, gr, None)
+        ctx.guide_adam(w, gr, m, v, it, 5e-3)
+    g1, t1 = estimate()
+    g.set_guide(None)
+    v0, v1 = g0.var(0).sum().item(), g1.var(0).sum().item()
+    se = torch.sqrt(g0.var(0) / K + g1.var(0) / K)
+    z = ((g1.mean(0) - g0.mean(0))[se > 0] / se[se > 0])
+    gain = (v0 * t0) / (v1 * t1)
+    print(f"trained guide: variance ratio {v1 / v0:.3f}, time {t0 * 1e3:.1f} -> {t1 * 1e3:.1f} ms, "
+          f"efficiency gain {gain:.3f}, bias mean z^2 {(z * z).mean().item():.3f}", flush=True)
+    assert v1 / v0 < 0.85 and gain > 1.1
+    assert (z * z).mean().item() < 1.5
