@@ -22,6 +22,30 @@ HBM_PEAK_GBS = 8000.0
 B_NODE, B_TRI, B_SPLAT, B_GATHER, B_GRAD, B_TAPE = 64, 48, 96, 48, 8, 32
 
 
+KERNEL_SOURCES = ["lt_common.h", "lt_device.h", "lt_launch.h", "lt_kernels.hip", "lt_attached.inc"]
+
+
+def profiled_traffic(name):
+    """HBM bytes per launch from the committed rocprofv3 summary profiles/<name>
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when the kernel
+    sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip().split()[0] if v.strip() else ""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2609_32920_amd", "csrc", f), "rb").read())
+    if fields.get("sources_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -34,8 +58,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-caustic", action="store_true", help="skip the attached caustic workload")
     ap.add_argument("--no-guide", action="store_true", help="skip the learned-guide workload")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 48-instance workload")
     ap.add_argument("--guide-iters", type=int, default=40, help="online training iterations of the guide")
-    ap.add_argument("--guide-seeds", type=int, default=8, help="seeds per gradient-variance estimate")
+    ap.add_argument("--guide-seeds", type=int, default=12, help="seeds per gradient-variance estimate")
     ap.add_argument("--cpu-paths", type=int, default=1 << 15)
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for profiler byte counters)")
@@ -134,8 +159,9 @@ def main():
         bpp = bytes_per_path(counts["lrb3"])
         t_launch = float(np.mean(bwd)) * 1e-3
         achieved = bpp * N / t_launch / 1e9
+        traffic = profiled_traffic("k_lrb3_bwd_box256_d32_4M.txt") if (N == 1 << 22 and D == 32 and W == 256) else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": "k_lrb3_bwd", "bytes_per_path": round(bpp, 1),
                     "launch_ms": round(t_launch * 1e3, 4),
                     "events_per_path": {k: round(v / sample, 3) for k, v in counts["lrb3"].items()}}
@@ -180,9 +206,16 @@ def main():
         caustic = bench_caustic(lt, scenes, dev, stream, bytes_per_path)
 
     # ---- learned guide: gradient variance x time, guided vs cosine emission
-    guide = None
+    guide = guide_smooth = None
     if not args.no_guide:
         guide = bench_guide(lt, scenes, dev, stream, iters=args.guide_iters, K=args.guide_seeds)
+        guide_smooth = bench_guide(lt, scenes, dev, stream, G=64, film=256, N=1 << 22, D=6, iters=60, K=16,
+                                   n_train=1 << 18, mode="lrb3", target="gradient", lr=5e-3)
+
+    # ---- batched instances: one persistent launch per pass, hipGraph replay
+    batch = None
+    if not args.no_batch:
+        batch = bench_batch(lt, scenes, dev, stream)
 
     # ---- CPU baseline: the FP64 oracle, forward + naive backward, on a sample
     cpu = None
@@ -222,6 +255,8 @@ def main():
         "sweep": sweep,
         "caustic": caustic,
         "guide": guide,
+        "guide_smooth_slab": guide_smooth,
+        "batch": batch,
     }
     print(json.dumps(out), flush=True)
 
@@ -290,6 +325,7 @@ def bench_caustic(lt, scenes, dev, stream, bytes_per_path_fn, G=128, film=512, N
         achieved = bpp * N / t / 1e9
         out["lrb3_roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                 "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_path": round(bpp, 1),
+                                "traffic": profiled_traffic("k_lrb3_att_caustic128_512_d6_16M.txt"),
                                 "events_per_path": {k: round(v / sample, 3) for k, v in c.items()}}
         del cctx
     except Exception as e:
@@ -297,12 +333,19 @@ def bench_caustic(lt, scenes, dev, stream, bytes_per_path_fn, G=128, film=512, N
     return out
 
 
-def bench_guide(lt, scenes, dev, stream, G=256, film=1024, N=1 << 26, D=8, iters=30, K=8, n_train=1 << 20):
+def bench_guide(lt, scenes, dev, stream, G=256, film=1024, N=1 << 26, D=8, iters=40, K=12, n_train=1 << 20,
+                mode="naive", target="adjoint", lr=1e-2):
     """Learned emission guide on the caustic scene (film^2, G x G heights,
     depth D, N paths per iteration): the guide is trained online on the
-    per-path gradient magnitudes the LRB-3 backward writes, then the heights
-    gradient's variance over K seeds (fixed image adjoint) and the time per
-    forward + backward iteration are compared with cosine emission."""
+    per-path signal the backward writes (target "adjoint": |delta_total|, the
+    adjoint-weighted contribution; "gradient": the L1 norm of the path's
+    heights gradient), then the heights gradient over K seeds (fixed image
+    adjoint) and the time per forward + backward iteration are compared with
+    cosine emission.  Two dispersions: the sample variance summed over heights,
+    and the median over heights of the per-height variance.  On a rough slab
+    the attached per-path derivative is heavy-tailed (focusing at caustic
+    folds, grazing hits): single paths then set the sample variance of K
+    seeds, and the median is the stable measure of the sampling."""
     import numpy as np
     import torch
 
@@ -311,21 +354,30 @@ def bench_guide(lt, scenes, dev, stream, G=256, film=1024, N=1 << 26, D=8, iters
     f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32), device=dev).contiguous()
     albedo, Le, h, ht = f32(sc["albedo"]), f32(sc["Le"]), f32(sc["heights"]), f32(sc["heights_target"])
     img = torch.empty((film, film, 3), dtype=torch.float32, device=dev)
-    target, dI = torch.empty_like(img), torch.empty_like(img)
+    target_img, dI = torch.empty_like(img), torch.empty_like(img)
     loss = torch.empty(1, dtype=torch.float32, device=dev)
-    ctx.trace(ctx.args(0x7A6, N, D, lt.ATTACHED), ctx.params(albedo, Le, ht), target)
+    ctx.trace(ctx.args(0x7A6, N, D, lt.ATTACHED), ctx.params(albedo, Le, ht), target_img)
     ctx.trace(ctx.args(0x7A7, N, D, lt.ATTACHED), ctx.params(albedo, Le, h), img)
-    ctx.loss_l2(img, target, dI, loss)
+    ctx.loss_l2(img, target_img, dI, loss)
     ga, gl, gh = torch.zeros_like(albedo), torch.zeros_like(Le), torch.zeros_like(h)
+    flags = lt.ATTACHED | (lt.RECORD_TAPE if mode == "naive" else 0)
+    extra = lt.CONTRIB_ADJOINT if target == "adjoint" else 0
+    nb = ctx.side_state_bytes(ctx.args(0, N, D, flags))
+    tape = torch.empty(nb, dtype=torch.uint8, device=dev) if nb else None
 
     def iteration(seed, gw, contrib=None):
         p = ctx.params(albedo, Le, h, gw)
-        ctx.trace(ctx.args(seed, N, D, lt.ATTACHED), p, img)
+        ctx.trace(ctx.args(seed, N, D, flags), p, img, tape)
         ga.zero_(); gl.zero_(); gh.zero_()
-        ctx.backward_lrb3(ctx.args(seed, N, D, lt.ATTACHED, contrib=contrib), p, dI, ga, gl, gh)
+        a = ctx.args(seed, N, D, flags | extra, contrib=contrib)
+        if mode == "naive":
+            ctx.backward_naive(a, p, dI, tape, ga, gl, gh)
+        else:
+            ctx.backward_lrb3(a, p, dI, ga, gl, gh)
 
     def estimate(gw):
         gs, ts = [], []
+        iteration(69999, gw)  # warm-up
         for k in range(K):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
@@ -334,15 +386,14 @@ def bench_guide(lt, scenes, dev, stream, G=256, film=1024, N=1 << 26, D=8, iters
             e1.synchronize()
             ts.append(e0.elapsed_time(e1))
             gs.append(gh.double().clone())
-        gs = torch.stack(gs)
-        return gs, float(np.median(ts))
+        return torch.stack(gs), float(np.median(ts))
 
-    iteration(69999, None)  # warm-up
     g0, t0 = estimate(None)
     w = f32(scenes.guide_weights())
     m, v, gw_grad = torch.zeros_like(w), torch.zeros_like(w), torch.zeros_like(w)
     gloss = torch.zeros(1, dtype=torch.float32, device=dev)
     contrib = torch.zeros(N, dtype=torch.float32, device=dev)
+    n_train = min(n_train, N)
     smp = torch.zeros((n_train, 12), dtype=torch.float32, device=dev)
     tt = []
     for it in range(1, iters + 1):
@@ -353,30 +404,112 @@ def bench_guide(lt, scenes, dev, stream, G=256, film=1024, N=1 << 26, D=8, iters
         p = ctx.params(albedo, Le, h, w)
         ctx.guide_emit(ctx.args(60000 + it, n_train, D), p, smp, contrib)
         ctx.guide_grad(w, smp, gw_grad, gloss)
-        ctx.guide_adam(w, gw_grad, m, v, it, 1e-2)
+        ctx.guide_adam(w, gw_grad, m, v, it, lr)
         e2.record(stream)
         e2.synchronize()
         tt.append((e0.elapsed_time(e1), e1.elapsed_time(e2)))
     g1, t1 = estimate(w)
     dropped = ctx.stats()["nonfinite"]
-    v0, v1 = g0.var(0).sum().item(), g1.var(0).sum().item()
-    se = torch.sqrt(g0.var(0) / K + g1.var(0) / K)
+    del tape
+    v0, v1 = g0.var(0), g1.var(0)
+    se = torch.sqrt(v0 / K + v1 / K)
     ok = se > 0
-    z = (g1.mean(0) - g0.mean(0))[ok] / se[ok]
+    z2 = ((g1.mean(0) - g0.mean(0))[ok] / se[ok]) ** 2
+    tv0, tv1, mv0, mv1 = v0.sum().item(), v1.sum().item(), v0.median().item(), v1.median().item()
     cos_share = float((smp[:, 11] == 0).float().mean().item())
+    est = "naive-AD" if mode == "naive" else "LRB-3-pass"
     out = {"workload": f"glass heightfield slab {G}x{G} heights, film {film}x{film}, depth {D}, {N} paths per "
-                       f"iteration, attached LRB-3-pass gradients w.r.t. heights; guide trained online for {iters} "
-                       f"iterations on {n_train} samples each (target: per-path gradient magnitude)",
+                       f"iteration, attached {est} gradients w.r.t. heights; guide trained online for {iters} "
+                       f"iterations on {n_train} samples each (target: {target})",
            "ms_per_iter_cosine": round(t0, 3), "ms_per_iter_guided": round(t1, 3),
            "train_ms_per_iter": round(float(np.median([a + b for a, b in tt])), 3),
            "guide_update_ms": round(float(np.median([b for _, b in tt])), 3),
-           "variance_cosine": v0, "variance_guided": v1, "variance_ratio": round(v1 / v0, 4),
-           "efficiency_gain": round((v0 * t0) / (v1 * t1), 4),
-           "bias_mean_z2": round(float((z * z).mean().item()), 4), "seeds": K,
-           "cosine_share_after_training": round(cos_share, 4),
+           "variance_cosine": tv0, "variance_guided": tv1, "variance_ratio": round(tv1 / tv0, 4),
+           "median_coord_variance_ratio": round(mv1 / mv0, 4),
+           "efficiency_gain": round((tv0 * t0) / (tv1 * t1), 4),
+           "robust_efficiency_gain": round((mv0 * t0) / (mv1 * t1), 4),
+           "bias_mean_z2": round(float(z2.mean().item()), 4), "bias_median_z2": round(float(z2.median().item()), 4),
+           "seeds": K, "cosine_share_after_training": round(cos_share, 4),
            "nonfinite_dropped_last_iteration": int(dropped)}
-    print(f"# guide: variance ratio {v1 / v0:.3f}, efficiency gain {(v0 * t0) / (v1 * t1):.3f}, "
-          f"iteration {t0:.1f} -> {t1:.1f} ms, bias z^2 {out['bias_mean_z2']}", file=sys.stderr, flush=True)
+    print(f"# guide G={G}: variance ratio {tv1 / tv0:.3f} (median-coordinate {mv1 / mv0:.3f}), "
+          f"iteration {t0:.1f} -> {t1:.1f} ms, efficiency gain {out['efficiency_gain']} "
+          f"(robust {out['robust_efficiency_gain']}), bias z^2 {out['bias_mean_z2']}", file=sys.stderr, flush=True)
+    return out
+
+
+def bench_batch(lt, scenes, dev, stream, n=48, seed=7, reps=2):
+    """48 box / caustic instances of uneven heightfield (32^2..256^2), film
+    (128^2..1024^2), path count (1M..32M) and depth (4..12) drawn from a
+    seed: one optimisation step each (forward, L2 loss, LRB-3-pass backward;
+    attached for the caustics).  Per-instance calls against the batched
+    runner (autotuned launch shape, one persistent launch per pass, the step
+    replayed from a captured hipGraph)."""
+    import tempfile
+
+    import numpy as np
+    import torch
+
+    f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32), device=dev).contiguous()
+    specs = scenes.batched_instances(n, seed)
+    insts = []
+    for k, sp in enumerate(specs):
+        box = sp["kind"] == "box"
+        sc = scenes.box_scene(width=sp["film"], height=sp["film"]) if box else \
+            scenes.caustic_scene(G=sp["G"], width=sp["film"], height=sp["film"])
+        ctx = lt.Context(0).scene_upload(sc)
+        d = dict(ctx=ctx, seed=5000 + k, n_paths=sp["n_paths"], depth=sp["depth"], attached=not box,
+                 albedo=f32(sc["albedo"]), Le=f32(sc["Le"]), heights=None if box else f32(sc["heights"]), guide=None)
+        tgt = torch.empty((sp["film"], sp["film"], 3), dtype=torch.float32, device=dev)
+        tp = ctx.params(f32(sc["albedo_target"]) if box else d["albedo"], d["Le"],
+                        None if box else f32(sc["heights_target"]))
+        ctx.trace(ctx.args(0x7A6, min(sp["n_paths"], 1 << 22), sp["depth"], 0 if box else lt.ATTACHED), tp, tgt)
+        d.update(target=tgt, image=torch.empty_like(tgt), d_image=torch.empty_like(tgt),
+                 loss=torch.zeros(1, dtype=torch.float32, device=dev), g_albedo=torch.zeros_like(d["albedo"]),
+                 g_Le=torch.zeros_like(d["Le"]), g_heights=None if box else torch.zeros_like(d["heights"]))
+        insts.append(d)
+    total = sum(d["n_paths"] for d in insts)
+    torch.cuda.synchronize()
+
+    def per_instance():
+        for d in insts:
+            ctx = d["ctx"]
+            a = ctx.args(d["seed"], d["n_paths"], d["depth"], lt.ATTACHED if d["attached"] else 0)
+            p = ctx.params(d["albedo"], d["Le"], d["heights"])
+            ctx.trace(a, p, d["image"])
+            ctx.loss_l2(d["image"], d["target"], d["d_image"], d["loss"])
+            ctx.backward_lrb3(a, p, d["d_image"], d["g_albedo"], d["g_Le"], d["g_heights"])
+
+    def timed(fn):
+        ts = []
+        for r in range(reps + 1):
+            for d in insts:
+                d["seed"] += 1
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            if r:
+                ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)) * 1e3
+
+    t_inst = timed(per_instance)
+    b = lt.Batch(0)
+    t_tune0 = time.perf_counter()
+    tune = b.autotune(insts, os.path.join(tempfile.gettempdir(), "lt_batch_tuning.json"))
+    t_tune = time.perf_counter() - t_tune0
+    t_eager = timed(lambda: b.step(insts, use_graph=False))
+    t_graph = timed(lambda: b.step(insts, use_graph=True))
+    out = {"workload": f"{n} instances ({sum(1 for d in insts if not d['attached'])} box, "
+                       f"{sum(1 for d in insts if d['attached'])} caustic; heightfields 32^2..256^2, films "
+                       f"128^2..1024^2, 1M..32M paths, depth 4..12, drawn from seed {seed}); one step each = "
+                       "forward + L2 loss + LRB-3-pass backward (attached for caustics)",
+           "paths_per_step": total, "per_instance_ms": round(t_inst, 2), "batched_eager_ms": round(t_eager, 2),
+           "batched_graph_ms": round(t_graph, 2),
+           "per_instance_paths_per_s": round(total / (t_inst * 1e-3)),
+           "batched_graph_paths_per_s": round(total / (t_graph * 1e-3)),
+           "speedup": round(t_inst / t_graph, 3), "tuning": tune, "autotune_s": round(t_tune, 2)}
+    print(f"# batch: per-instance {t_inst:.1f} ms, batched {t_eager:.1f} ms (eager) / {t_graph:.1f} ms (graph), "
+          f"speedup {t_inst / t_graph:.3f}, tuning {tune}", file=sys.stderr, flush=True)
     return out
 
 

@@ -64,7 +64,8 @@ enum {
   LT_ATTACHED = 1u,         /* differentiate geometry (heightfield heights), Sec. 3.3 */
   LT_SPLAT_SELECTED = 2u,   /* primal image splats only (Omega_k/w_R) L_R (Eq. 9) */
   LT_RECORD_TAPE = 4u,      /* lt_trace writes the naive-AD tape */
-  LT_RECORD_RESERVOIR = 8u  /* lt_trace writes the per-path ResLRB record */
+  LT_RECORD_RESERVOIR = 8u, /* lt_trace writes the per-path ResLRB record */
+  LT_CONTRIB_ADJOINT = 16u  /* attached backward: path_contrib gets |delta_total| (below) */
 };
 
 typedef struct lt_ctx lt_ctx;
@@ -126,9 +127,11 @@ typedef struct {
                                for the emission guide.  lt_trace writes the path's
                                image contribution sum_i lum(C_i) over its connections
                                (Rec. 709 luminance, the reservoir weight of Eq. 8);
-                               lt_backward_lrb3 writes the path's gradient magnitude:
-                               detached, sum_c |delta_total,c| (Eq. 14); attached,
-                               the L1 norm of its heights-gradient contributions */
+                               lt_backward_lrb3 and lt_backward_naive write the
+                               path's adjoint-weighted contribution
+                               sum_c |delta_total,c| (Eq. 14) - detached, or attached
+                               with LT_CONTRIB_ADJOINT - else, attached, the L1 norm
+                               of its heights-gradient contributions */
 } lt_trace_args;
 
 /* Parameters: DEVICE float arrays owned by the caller. */
@@ -321,6 +324,63 @@ lt_status lt_guide_grad(lt_ctx* ctx, const float* guide_w, const lt_guide_sample
  * Errors: LT_ERR_ARG (step < 1, lr <= 0, betas outside [0, 1)). */
 lt_status lt_guide_adam(lt_ctx* ctx, float* w, const float* grad, float* m, float* v, int32_t step, float lr,
                         float beta1, float beta2, float eps);
+
+/* ------------------------------------------------------------------------
+ * Batches.  An extension for training many inverse-rendering problems at
+ * once (not in the paper).  Instances of uneven scene size, film, path count
+ * and depth each take one optimisation step - the forward of lt_trace, the
+ * L2 loss and image adjoint of lt_loss_l2, the LRB-3-pass backward of
+ * lt_backward_lrb3 (Sec. 4.3) - as one persistent launch per pass over an
+ * instance table: every wave takes work tickets (path indices) from one
+ * instance at a time and moves to the next when it has drained it.  With
+ * use_graph the step is captured once into a hipGraph and replayed; between
+ * replays only the seeds may change (they are read from device memory).
+ * Results equal the per-instance calls up to the order of floating-point
+ * atomic sums.
+ * ------------------------------------------------------------------------ */
+typedef struct lt_batch lt_batch;
+
+typedef struct {
+  lt_ctx* ctx;            /* context holding this instance's uploaded scene; every
+                             instance's context uses the batch's device */
+  lt_trace_args args;     /* seed, n_paths, max_depth, flags: 0 or LT_ATTACHED; mask,
+                             signatures, info and contributions must be NULL */
+  lt_params params;       /* as for lt_backward_lrb3 (guide_w allowed) */
+  const float* target;    /* DEVICE [height][width][3] loss target */
+  float* image;           /* DEVICE [height][width][3], overwritten with the estimate */
+  float* d_image;         /* DEVICE [height][width][3], overwritten with dL/dI */
+  float* loss;            /* DEVICE [1], overwritten with the mean squared error */
+  lt_grads grads;         /* accumulated into, as by lt_backward_lrb3 */
+} lt_instance;
+
+/* A batch runner on HIP device `device`, enqueuing on `hip_stream`.
+ * Errors: LT_ERR_ARG, LT_ERR_HIP, LT_ERR_OOM. */
+lt_status lt_batch_create(int device, void* hip_stream, lt_batch** out);
+/* Release the runner (its graph and tables). NULL is ignored. */
+void lt_batch_destroy(lt_batch* b);
+const char* lt_batch_last_error(const lt_batch* b);
+/* One step for instances inst[0..n-1] (1 <= n <= 4096), on the batch's
+ * stream; the instance contexts' streams are set to it.  use_graph: 0 eager
+ * launches; 1 replay the captured hipGraph, capturing it first when the
+ * instance set differs from the captured one in anything but the seeds.
+ * Errors: LT_ERR_ARG (bad instance), LT_ERR_STATE (scene missing),
+ * LT_ERR_UNSUPPORTED (flags or outputs outside the list above), LT_ERR_OOM,
+ * LT_ERR_HIP. */
+lt_status lt_batch_step(lt_batch* b, const lt_instance* inst, int32_t n, int32_t use_graph);
+/* Launch shape of the batched passes: block and blocks_per_cu as in
+ * lt_set_tuning (the attached backward keeps 256-thread workgroups). */
+lt_status lt_batch_set_tuning(lt_batch* b, const lt_tuning* t);
+lt_status lt_batch_get_tuning(const lt_batch* b, lt_tuning* out);
+/* Pick block size and workgroups per compute unit for these instances by
+ * timing trial steps (each instance at 1/16 of its paths, at least 65536)
+ * over a fixed candidate set, keep the fastest, and remember it in
+ * cache_path (a JSON object keyed by device and workload; NULL: no cache).
+ * A cached entry is reused without trials.  Trial steps overwrite the
+ * instances' images, adjoints and losses and accumulate into their
+ * gradients: clear those afterwards.  *out (may be NULL) receives the choice.
+ * Errors: as lt_batch_step. */
+lt_status lt_batch_autotune(lt_batch* b, const lt_instance* inst, int32_t n, const char* cache_path,
+                            lt_tuning* out);
 
 #ifdef __cplusplus
 }

@@ -248,7 +248,7 @@ lt_status check_args(lt_ctx* c, const lt_trace_args* a, const lt_params* p) {
   if (!c->has_scene) return c->fail(LT_ERR_STATE, "no scene uploaded%s");
   if (a->n_paths < 1 || a->n_paths >= (int64_t)1 << 31) return c->fail(LT_ERR_ARG, "n_paths out of range [1, 2^31)%s");
   if (a->max_depth < 1 || a->max_depth > kMaxDepth) return c->fail(LT_ERR_ARG, "max_depth out of range [1, 64]%s");
-  if (a->flags & ~(uint32_t)(LT_ATTACHED | LT_SPLAT_SELECTED | LT_RECORD_TAPE | LT_RECORD_RESERVOIR))
+  if (a->flags & ~(uint32_t)(LT_ATTACHED | LT_SPLAT_SELECTED | LT_RECORD_TAPE | LT_RECORD_RESERVOIR | LT_CONTRIB_ADJOINT))
     return c->fail(LT_ERR_ARG, "unknown flag bits%s");
   if (!p->albedo || !p->emitter_L) return c->fail(LT_ERR_ARG, "albedo and emitter_L are required%s");
   if ((a->flags & LT_ATTACHED) && c->dsc.hf_G < 2) return c->fail(LT_ERR_ARG, "LT_ATTACHED needs a heightfield%s");
@@ -745,6 +745,7 @@ lt_status lt_backward_naive(lt_ctx* c, const lt_trace_args* a, const lt_params* 
   if (st != LT_OK) return st;
   SideLayout L = side_layout(a);
   const char* sb = (const char*)tape;
+  A.contrib = a->path_contrib;
   A.tape_in = (const TapeRec*)(sb + L.tape);
   A.tape_len_in = (const int32_t*)(sb + L.len);
   int grid = (int)std::max<int64_t>(1, std::min<int64_t>((a->n_paths + 255) / 256, (int64_t)c->n_cu * 16));
@@ -859,6 +860,389 @@ lt_status lt_guide_adam(lt_ctx* c, float* w, const float* grad, float* m, float*
   float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, step)));
   return c->hip(launch_guide_adam(w, grad, m, v, LT_GUIDE_NPARAMS, lr, beta1, beta2, eps, c1, c2, c->stream),
                 "guide adam");
+}
+
+}  // extern "C"
+
+// ============================================================== batches
+#include <map>
+#include <fstream>
+#include <sstream>
+
+struct lt_batch {
+  int device = 0;
+  hipStream_t stream = nullptr;       // caller's stream: eager steps and graph launches
+  hipStream_t cap = nullptr;          // the runner's own stream, for capture (the null stream cannot be)
+  std::string err;
+  lt_tuning tune{256, 4, 0};
+  int n_cu = 256;
+  std::string arch;
+  // device tables: trace [n], detached backward [n_det], attached backward [n_att]
+  PassArgs* d_tab = nullptr;
+  size_t tab_cap = 0;                 // PassArgs entries allocated
+  unsigned int* d_cnt = nullptr;      // work-ticket counters [2n]
+  double* d_acc = nullptr;            // per instance: emitter gradient (3) + loss (1)
+  size_t inst_cap = 0;
+  // captured step
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<char> key;              // the instance set the graph was captured for
+
+  lt_status fail(lt_status s, const char* msg) { err = msg; return s; }
+  lt_status hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return LT_OK;
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return LT_ERR_HIP;
+  }
+  void drop_graph() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    exec = nullptr; graph = nullptr; key.clear();
+  }
+};
+
+namespace {
+
+struct BatchPlan {
+  std::vector<PassArgs> tab;   // [n trace][n_det detached][n_att attached]
+  std::vector<int> det, att;   // instance indices of each backward kind
+  int n = 0, stack_n = 1;
+};
+
+lt_status batch_check(lt_batch* b, const lt_instance* inst, int n) {
+  if (!inst || n < 1 || n > 4096) return b->fail(LT_ERR_ARG, "need 1..4096 instances");
+  for (int i = 0; i < n; ++i) {
+    const lt_instance& I = inst[i];
+    lt_ctx* c = I.ctx;
+    if (!c) return b->fail(LT_ERR_ARG, "instance without a context");
+    if (c->device != b->device) return b->fail(LT_ERR_ARG, "instance context on another device");
+    if (I.args.flags & ~(uint32_t)LT_ATTACHED) return b->fail(LT_ERR_UNSUPPORTED, "batches take flags 0 or LT_ATTACHED only");
+    if (I.args.path_mask || I.args.path_sig || I.args.path_info || I.args.path_contrib)
+      return b->fail(LT_ERR_UNSUPPORTED, "batches take no mask, signatures, info or contributions");
+    lt_status st = check_args(c, &I.args, &I.params);
+    if (st != LT_OK) { b->err = "instance " + std::to_string(i) + ": " + c->err; return st; }
+    if (!I.target || !I.image || !I.d_image || !I.loss || !I.grads.albedo)
+      return b->fail(LT_ERR_ARG, "instance buffers (target, image, d_image, loss, grads.albedo) are required");
+  }
+  return LT_OK;
+}
+
+// Allocations every step needs, made before any capture.
+lt_status batch_reserve(lt_batch* b, const lt_instance* inst, int n) {
+  size_t need = (size_t)2 * n;
+  if (b->tab_cap < need) {
+    hipFree(b->d_tab); b->d_tab = nullptr; b->tab_cap = 0;
+    if (hipMalloc((void**)&b->d_tab, need * sizeof(PassArgs)) != hipSuccess) {
+      (void)hipGetLastError();
+      return b->fail(LT_ERR_OOM, "out of device memory for the instance table");
+    }
+    b->tab_cap = need;
+  }
+  if (b->inst_cap < (size_t)n) {
+    hipFree(b->d_cnt); hipFree(b->d_acc); b->d_cnt = nullptr; b->d_acc = nullptr; b->inst_cap = 0;
+    if (hipMalloc((void**)&b->d_cnt, (size_t)2 * n * sizeof(unsigned int)) != hipSuccess ||
+        hipMalloc((void**)&b->d_acc, (size_t)4 * n * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      return b->fail(LT_ERR_OOM, "out of device memory for the batch counters");
+    }
+    b->inst_cap = n;
+  }
+  for (int i = 0; i < n; ++i) {
+    lt_ctx* c = inst[i].ctx;
+    if (!inst[i].params.guide_w) continue;
+    lt_status st = grow(c, &c->d_grec, c->grec_n, (size_t)inst[i].args.n_paths, "guided emission records");
+    if (st == LT_OK && !c->d_gpack && hipMalloc(&c->d_gpack, guide_packed_bytes()) != hipSuccess) {
+      (void)hipGetLastError();
+      c->d_gpack = nullptr;
+      st = LT_ERR_OOM;
+    }
+    if (st != LT_OK) return b->fail(st, "out of device memory for the guide");
+  }
+  return LT_OK;
+}
+
+BatchPlan batch_plan(lt_batch* b, const lt_instance* inst, int n, int64_t path_div) {
+  BatchPlan P;
+  P.n = n;
+  P.tab.resize((size_t)2 * n);
+  for (int i = 0; i < n; ++i) {
+    const lt_instance& I = inst[i];
+    lt_ctx* c = I.ctx;
+    lt_trace_args a = I.args;
+    if (path_div > 1) a.n_paths = std::max<int64_t>(std::min<int64_t>(a.n_paths, 65536), a.n_paths / path_div);
+    PassArgs A = base_args(c, &a, &I.params);
+    A.hgrad_lds = 0;
+    A.guide_rec = I.params.guide_w ? c->d_grec : nullptr;
+    A.stats = nullptr;
+    P.stack_n = std::max(P.stack_n, c->dsc.stack_n);
+    PassArgs T = A;
+    T.image = I.image;
+    T.counter = b->d_cnt + i;
+    P.tab[i] = T;
+    PassArgs B = A;
+    B.dI = I.d_image;
+    B.g_albedo = I.grads.albedo;
+    B.g_heights = I.grads.heights;
+    B.g_Le_acc = b->d_acc + 4 * i;
+    B.counter = b->d_cnt + n + i;
+    ((a.flags & LT_ATTACHED) ? P.att : P.det).push_back(i);
+    P.tab[n + i] = B;  // reordered below
+  }
+  // backward entries: detached ones first, then attached ones
+  std::vector<PassArgs> bw;
+  for (int i : P.det) bw.push_back(P.tab[n + i]);
+  for (int i : P.att) bw.push_back(P.tab[n + i]);
+  for (int k = 0; k < n; ++k) P.tab[n + k] = bw[k];
+  return P;
+}
+
+// Everything one step launches, in order on stream s (capturable: fills, no
+// memsets, no allocation).  The instance contexts enqueue on s meanwhile and
+// are left on the caller's stream.
+lt_status batch_enqueue_on(lt_batch* b, const lt_instance* inst, const BatchPlan& P, hipStream_t s) {
+  const int n = P.n;
+  for (int i = 0; i < n; ++i) {
+    const lt_instance& I = inst[i];
+    lt_ctx* c = I.ctx;
+    c->stream = s;
+    lt_status st = prepare_geometry(c, &I.params);
+    if (st != LT_OK) return b->fail(st, c->err.c_str());
+    if (I.params.guide_w) {
+      if ((st = guide_pack(c, I.params.guide_w)) != LT_OK) return b->fail(st, c->err.c_str());
+      GuideArgs G = guide_args(c, I.params.guide_w, P.tab[i].n_paths);
+      G.seed_ptr = &b->d_tab[i].seed;  // the seed as updated before every replay
+      G.rec = c->d_grec;
+      if ((st = c->hip(launch_guide_emit(G, guide_grid(c, P.tab[i].n_paths), s), "guide emit")) != LT_OK)
+        return b->fail(st, c->err.c_str());
+    }
+    size_t npix = (size_t)c->dsc.W * c->dsc.H * 3;
+    if ((st = b->hip(launch_fill_f32(I.image, npix, 0.f, s), "image clear")) != LT_OK) return st;
+  }
+  lt_status st;
+  if ((st = b->hip(launch_fill_u32(b->d_cnt, (size_t)2 * n, 0u, s), "counter clear")) != LT_OK) return st;
+  if ((st = b->hip(launch_fill_f64(b->d_acc, (size_t)4 * n, 0.0, s), "accumulator clear")) != LT_OK) return st;
+  int grid = (int)std::max<int64_t>(1, (int64_t)b->n_cu * b->tune.blocks_per_cu);
+  if ((st = b->hip(launch_trace_batch(b->d_tab, n, P.stack_n, grid, b->tune.block, s), "batched trace")) != LT_OK)
+    return st;
+  for (int i = 0; i < n; ++i) {
+    const lt_instance& I = inst[i];
+    size_t npix = (size_t)I.ctx->dsc.W * I.ctx->dsc.H * 3;
+    if ((st = b->hip(launch_loss(I.image, I.target, npix, I.d_image, b->d_acc + 4 * i + 3, I.loss, s), "loss")) != LT_OK)
+      return st;
+  }
+  const int nd = (int)P.det.size(), na = (int)P.att.size();
+  if (nd && (st = b->hip(launch_lrb3_batch(b->d_tab + n, nd, P.stack_n, grid, b->tune.block, s),
+                         "batched backward")) != LT_OK)
+    return st;
+  if (na) {
+    int grid_att = (int)std::max<int64_t>(1, (int64_t)b->n_cu * b->tune.blocks_per_cu * b->tune.block / 256);
+    if ((st = b->hip(launch_lrb3_att_batch(b->d_tab + n + nd, na, P.stack_n, grid_att, s),
+                     "batched attached backward")) != LT_OK)
+      return st;
+  }
+  for (int i = 0; i < n; ++i)
+    if ((st = b->hip(launch_add_le(b->d_acc + 4 * i, inst[i].grads.emitter_L, s), "emitter gradient")) != LT_OK)
+      return st;
+  return LT_OK;
+}
+
+lt_status batch_enqueue(lt_batch* b, const lt_instance* inst, const BatchPlan& P, hipStream_t s) {
+  lt_status st = batch_enqueue_on(b, inst, P, s);
+  for (int i = 0; i < P.n; ++i) inst[i].ctx->stream = b->stream;
+  return st;
+}
+
+// Identity of an instance set for graph reuse: everything but the seeds.
+std::vector<char> batch_key(const lt_batch* b, const lt_instance* inst, int n) {
+  std::vector<lt_instance> v(inst, inst + n);
+  for (auto& I : v) I.args.seed = 0;
+  std::vector<char> k((const char*)v.data(), (const char*)(v.data() + n));
+  const char* t = (const char*)&b->tune;
+  k.insert(k.end(), t, t + sizeof(lt_tuning));
+  return k;
+}
+
+lt_status batch_run(lt_batch* b, const lt_instance* inst, int n, bool use_graph, int64_t path_div) {
+  lt_status st = batch_check(b, inst, n);
+  if (st != LT_OK) return st;
+  if (hipSetDevice(b->device) != hipSuccess) return b->fail(LT_ERR_HIP, "hipSetDevice failed");
+  if ((st = batch_reserve(b, inst, n)) != LT_OK) return st;
+  BatchPlan P = batch_plan(b, inst, n, path_div);
+  // the tables (seeds included) go first in stream order, outside any graph
+  if ((st = b->hip(hipMemcpyAsync(b->d_tab, P.tab.data(), P.tab.size() * sizeof(PassArgs), hipMemcpyHostToDevice,
+                                  b->stream), "table upload")) != LT_OK)
+    return st;
+  if (!use_graph) return batch_enqueue(b, inst, P, b->stream);
+  std::vector<char> key = batch_key(b, inst, n);
+  if (!b->exec || key != b->key) {
+    b->drop_graph();
+    if (!b->cap && (st = b->hip(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "capture stream")) != LT_OK)
+      return st;
+    if ((st = b->hip(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed), "begin capture")) != LT_OK) return st;
+    lt_status est = batch_enqueue(b, inst, P, b->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (est != LT_OK) { if (g) hipGraphDestroy(g); return est; }
+    if (e != hipSuccess) return b->hip(e, "end capture");
+    b->graph = g;
+    if ((st = b->hip(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "graph instantiate")) != LT_OK) {
+      b->drop_graph();
+      return st;
+    }
+    b->key = key;
+  }
+  return b->hip(hipGraphLaunch(b->exec, b->stream), "graph launch");
+}
+
+// JSON cache of tuning choices: one entry per line,
+//   "key": {"block": B, "blocks_per_cu": K, "ms": T},
+std::map<std::string, std::string> cache_read(const char* path) {
+  std::map<std::string, std::string> m;
+  if (!path) return m;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    size_t a = line.find('"'), b = a == std::string::npos ? a : line.find('"', a + 1);
+    size_t c = line.find('{'), d = line.rfind('}');
+    if (a == std::string::npos || b == std::string::npos || c == std::string::npos || d == std::string::npos || c > d)
+      continue;
+    m[line.substr(a + 1, b - a - 1)] = line.substr(c, d - c + 1);
+  }
+  return m;
+}
+bool cache_field(const std::string& obj, const char* name, double& v) {
+  std::string k = std::string("\"") + name + "\"";
+  size_t p = obj.find(k);
+  if (p == std::string::npos) return false;
+  p = obj.find(':', p);
+  if (p == std::string::npos) return false;
+  v = std::strtod(obj.c_str() + p + 1, nullptr);
+  return true;
+}
+void cache_write(const char* path, const std::map<std::string, std::string>& m) {
+  if (!path) return;
+  std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream f(tmp);
+    f << "{\n";
+    size_t i = 0;
+    for (auto& kv : m) f << "  \"" << kv.first << "\": " << kv.second << (++i < m.size() ? ",\n" : "\n");
+    f << "}\n";
+  }
+  std::rename(tmp.c_str(), path);
+}
+
+}  // namespace
+
+extern "C" {
+
+lt_status lt_batch_create(int device, void* stream, lt_batch** out) {
+  if (!out) return LT_ERR_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return LT_ERR_ARG;
+  if (hipSetDevice(device) != hipSuccess) return LT_ERR_HIP;
+  lt_batch* b = new (std::nothrow) lt_batch();
+  if (!b) return LT_ERR_OOM;
+  b->device = device;
+  b->stream = (hipStream_t)stream;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    if (prop.multiProcessorCount > 0) b->n_cu = prop.multiProcessorCount;
+    b->arch = prop.gcnArchName;
+  }
+  *out = b;
+  return LT_OK;
+}
+
+void lt_batch_destroy(lt_batch* b) {
+  if (!b) return;
+  hipSetDevice(b->device);
+  b->drop_graph();
+  if (b->cap) hipStreamDestroy(b->cap);
+  hipFree(b->d_tab);
+  hipFree(b->d_cnt);
+  hipFree(b->d_acc);
+  delete b;
+}
+
+const char* lt_batch_last_error(const lt_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+lt_status lt_batch_set_tuning(lt_batch* b, const lt_tuning* t) {
+  if (!b) return LT_ERR_ARG;
+  if (!t) { b->tune = lt_tuning{256, 4, 0}; return LT_OK; }
+  if (t->block < 64 || t->block > 1024 || (t->block % 64) != 0)
+    return b->fail(LT_ERR_ARG, "block must be 64..1024, a multiple of 64");
+  if (t->blocks_per_cu < 1 || t->blocks_per_cu > 64) return b->fail(LT_ERR_ARG, "blocks_per_cu must be 1..64");
+  b->tune = *t;
+  return LT_OK;
+}
+
+lt_status lt_batch_get_tuning(const lt_batch* b, lt_tuning* out) {
+  if (!b || !out) return LT_ERR_ARG;
+  *out = b->tune;
+  return LT_OK;
+}
+
+lt_status lt_batch_step(lt_batch* b, const lt_instance* inst, int32_t n, int32_t use_graph) {
+  if (!b) return LT_ERR_ARG;
+  return batch_run(b, inst, n, use_graph != 0, 1);
+}
+
+lt_status lt_batch_autotune(lt_batch* b, const lt_instance* inst, int32_t n, const char* cache_path, lt_tuning* out) {
+  if (!b) return LT_ERR_ARG;
+  lt_status st = batch_check(b, inst, n);
+  if (st != LT_OK) return st;
+  int64_t total = 0;
+  int n_att = 0;
+  for (int i = 0; i < n; ++i) {
+    total += inst[i].args.n_paths;
+    n_att += (inst[i].args.flags & LT_ATTACHED) ? 1 : 0;
+  }
+  char key[256];
+  std::snprintf(key, sizeof(key), "%s|cu%d|n%d|att%d|paths%lld", b->arch.c_str(), b->n_cu, n, n_att, (long long)total);
+  auto cache = cache_read(cache_path);
+  auto it = cache.find(key);
+  double bl = 0, bpc = 0;
+  if (it != cache.end() && cache_field(it->second, "block", bl) && cache_field(it->second, "blocks_per_cu", bpc)) {
+    lt_tuning t{(int32_t)bl, (int32_t)bpc, 0};
+    if ((st = lt_batch_set_tuning(b, &t)) == LT_OK && out) *out = t;
+    return st;
+  }
+  static const int blocks[] = {128, 256, 512};
+  static const int per_cu[] = {2, 4, 8};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return b->fail(LT_ERR_HIP, "event create");
+  lt_tuning best{256, 4, 0};
+  float best_ms = 1e30f;
+  const lt_tuning saved = b->tune;
+  for (int blk : blocks)
+    for (int k : per_cu) {
+      b->tune = lt_tuning{blk, k, 0};
+      float ms = 0.f;
+      for (int rep = 0; rep < 3 && st == LT_OK; ++rep) {
+        hipEventRecord(e0, b->stream);
+        st = batch_run(b, inst, n, false, 16);
+        hipEventRecord(e1, b->stream);
+        if (st == LT_OK && hipEventSynchronize(e1) != hipSuccess) st = b->fail(LT_ERR_HIP, "trial step");
+        float t = 0.f;
+        if (st == LT_OK && rep > 0 && hipEventElapsedTime(&t, e0, e1) == hipSuccess) ms += t;
+      }
+      if (st != LT_OK) break;
+      if (ms < best_ms) { best_ms = ms; best = b->tune; }
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  b->tune = saved;
+  if (st != LT_OK) return st;
+  if ((st = lt_batch_set_tuning(b, &best)) != LT_OK) return st;
+  char val[160];
+  std::snprintf(val, sizeof(val), "{\"block\": %d, \"blocks_per_cu\": %d, \"ms\": %.3f}", best.block,
+                best.blocks_per_cu, best_ms / 2.0f);
+  cache[key] = val;
+  cache_write(cache_path, cache);
+  if (out) *out = best;
+  return LT_OK;
 }
 
 }  // extern "C"

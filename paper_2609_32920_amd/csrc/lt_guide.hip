@@ -390,11 +390,12 @@ __global__ void __launch_bounds__(256) k_guide_emit(GuideArgs G) {
   const DevScene& sc = G.sc;
   const f3 o0 = ld3(sc.em_o), e1 = ld3(sc.em_e1), e2 = ld3(sc.em_e2), ne = ld3(sc.em_n);
   const int64_t n_tiles = (G.count + 63) / 64;
+  const uint64_t seed = G.seed_ptr ? *G.seed_ptr : G.seed;
   for (int64_t base = (int64_t)blockIdx.x * 4; base < n_tiles; base += (int64_t)gridDim.x * 4) {
     int64_t p = (base + wave) * 64 + lane;
     bool valid = p < G.count;
     uint32_t path = (uint32_t)(valid ? p : 0);
-    u4f u = rng4(G.seed, path, 0u, 0u);
+    u4f u = rng4(seed, path, 0u, 0u);
     f3 x = o0 + e1 * u.u0 + e2 * u.u1;
     float f[kGIn];
     features(sc, x, ne, f);
@@ -403,7 +404,7 @@ __global__ void __launch_bounds__(256) k_guide_emit(GuideArgs G) {
     float o[kGOut];
     outputs_to_lane(F, stage, o);
     GMix m = mixture_of(o);
-    u4f gu = rng4(G.seed, path, 0u, 1u);
+    u4f gu = rng4(seed, path, 0u, 1u);
     int comp;
     f3 w = mix_sample(m, ne, gu.u0, gu.u1, gu.u2, comp);
     float q = mix_pdf(m, ne, w);

@@ -181,8 +181,7 @@ __device__ __forceinline__ float luminance(f3 c) { return 0.2126f * c.x + 0.7152
 // every live lane by one vertex; the splat is issued cooperatively by the
 // whole wave after the step.
 template <bool TAPE, bool RESV>
-__global__ void __launch_bounds__(1024) k_trace(PassArgs A) {
-  extern __shared__ int lds[];
+__device__ __forceinline__ void trace_run(const PassArgs& A, int* lds) {
   int* stk = lds + threadIdx.x;
   const int ss = blockDim.x;
   const bool selected = (A.flags & 2u) != 0;
@@ -263,6 +262,12 @@ __global__ void __launch_bounds__(1024) k_trace(PassArgs A) {
   }
 }
 
+template <bool TAPE, bool RESV>
+__global__ void __launch_bounds__(1024) k_trace(PassArgs A) {
+  extern __shared__ int lds[];
+  trace_run<TAPE, RESV>(A, lds);
+}
+
 // ---------------------------------------------------------------- naive AD
 // Reverse sweep over the tape, exact chain rule (no inverses, no division):
 //   C_j = beta_j rho_j g_j,  beta_{j+1} = beta_j rho_j (Lambertian scatter),
@@ -316,6 +321,10 @@ __global__ void __launch_bounds__(256) k_naive_bwd(PassArgs A) {
     if (live) {
       add_le(A, gl0, gl1, gl2, (double)bb.x * fac, (double)bb.y * fac, (double)bb.z * fac);
     }
+    // the path's adjoint-weighted contribution |delta_total| = sum_c |L_e,c f bb_c|
+    if (A.contrib && path < N)
+      A.contrib[path] = live ? fabsf(A.Le[0] * fac * bb.x) + fabsf(A.Le[1] * fac * bb.y) + fabsf(A.Le[2] * fac * bb.z)
+                             : 0.f;
   }
   flush_le(A, gl0, gl1, gl2);
 }
@@ -384,8 +393,7 @@ __global__ void __launch_bounds__(1024) k_reslrb_bwd(PassArgs A) {
 // the last valid connection: phase 3 then re-evaluates only the connection
 // geometry where the bit is set (no shadow rays) and stops at that depth,
 // where delta_rem is exactly zero and nothing further contributes.
-__global__ void __launch_bounds__(1024) k_lrb3_bwd(PassArgs A) {
-  extern __shared__ int lds[];
+__device__ __forceinline__ void lrb3_run(const PassArgs& A, int* lds) {
   int* stk = lds + threadIdx.x;
   const int ss = blockDim.x;
   bool alive = false, exhausted = false;
@@ -452,6 +460,11 @@ __global__ void __launch_bounds__(1024) k_lrb3_bwd(PassArgs A) {
     scatter3_wave(A.g_albedo, has, texel, gv);
   }
   flush_le(A, gl0, gl1, gl2);
+}
+
+__global__ void __launch_bounds__(1024) k_lrb3_bwd(PassArgs A) {
+  extern __shared__ int lds[];
+  lrb3_run(A, lds);
 }
 
 // ---------------------------------------------------------------- small kernels
@@ -548,6 +561,27 @@ __global__ void k_refit_level(Node* nodes, const Tri* tris, const int32_t* level
 
 #include "lt_attached.inc"
 
+// ---------------------------------------------------------------- batches
+// One persistent launch over a table of instances (scenes, films, path
+// counts and depths of their own).  Every wave walks the table in order and
+// takes work tickets (path indices) from each instance's own counter; a wave
+// moves on once its lanes have drained an instance, so an instance's
+// arguments stay uniform across the wave and the cooperative splat and
+// gradient scatter work unchanged.  Waves that finish an instance early start
+// on the next one while others drain: no launch gaps, one tail per launch.
+__global__ void __launch_bounds__(1024) k_trace_batch(const PassArgs* __restrict__ T, int n) {
+  extern __shared__ int lds[];
+  for (int i = 0; i < n; ++i) trace_run<false, false>(T[i], lds);
+}
+__global__ void __launch_bounds__(1024) k_lrb3_batch(const PassArgs* __restrict__ T, int n) {
+  extern __shared__ int lds[];
+  for (int i = 0; i < n; ++i) lrb3_run(T[i], lds);
+}
+__global__ void __launch_bounds__(256) k_lrb3_att_batch(const PassArgs* __restrict__ T, int n) {
+  extern __shared__ int lds[];
+  for (int i = 0; i < n; ++i) lrb3_att_run(T[i], lds);
+}
+
 #ifdef LT_COUNTERS
 }  // namespace counted
 #endif
@@ -585,6 +619,19 @@ hipError_t launch_naive_att_bwd(const PassArgs& A, int grid, hipStream_t s) {
 }
 hipError_t launch_reslrb_att(const PassArgs& A, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_reslrb_att, dim3(grid), dim3(256), stack_bytes(A, 256) + hgrad_bytes(A), s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace_batch(const PassArgs* table, int n, int stack_n, int grid, int block, hipStream_t s) {
+  hipLaunchKernelGGL(k_trace_batch, dim3(grid), dim3(block), (size_t)stack_n * block * sizeof(int), s, table, n);
+  return hipGetLastError();
+}
+hipError_t launch_lrb3_batch(const PassArgs* table, int n, int stack_n, int grid, int block, hipStream_t s) {
+  hipLaunchKernelGGL(k_lrb3_batch, dim3(grid), dim3(block), (size_t)stack_n * block * sizeof(int), s, table, n);
+  return hipGetLastError();
+}
+hipError_t launch_lrb3_att_batch(const PassArgs* table, int n, int stack_n, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_lrb3_att_batch, dim3(grid), dim3(256), (size_t)stack_n * 256 * sizeof(int), s, table, n);
   return hipGetLastError();
 }
 

@@ -51,6 +51,7 @@ typedef unsigned int lt_u32x4 __attribute__((ext_vector_type(4)));
 struct GuideArgs {
   DevScene sc;
   uint64_t seed;
+  const uint64_t* seed_ptr;  // emit: seed read from device memory when set (graph replays)
   int64_t count;             // paths (emit) or samples (grad) or items (eval)
   const float* w;            // FP32 parameters (biases read from here)
   const lt_u32x4* packed;    // bf16 operand tiles from k_guide_pack
@@ -75,6 +76,11 @@ hipError_t launch_guide_adam(float* w, const float* grad, float* m, float* v, in
                              float eps, float c1, float c2, hipStream_t s);
 
 hipError_t launch_trace(const PassArgs& A, bool tape, bool resv, int grid, int block, hipStream_t s);
+// batches: `table` is a DEVICE array of n PassArgs; stack_n the largest
+// traversal stack among them
+hipError_t launch_trace_batch(const PassArgs* table, int n, int stack_n, int grid, int block, hipStream_t s);
+hipError_t launch_lrb3_batch(const PassArgs* table, int n, int stack_n, int grid, int block, hipStream_t s);
+hipError_t launch_lrb3_att_batch(const PassArgs* table, int n, int stack_n, int grid, hipStream_t s);
 hipError_t launch_naive_bwd(const PassArgs& A, int grid, hipStream_t s);
 hipError_t launch_reslrb_bwd(const PassArgs& A, int grid, int block, hipStream_t s);
 hipError_t launch_lrb3_bwd(const PassArgs& A, int grid, int block, hipStream_t s);

@@ -8,7 +8,8 @@ fallback.
 The functions carry the C ABI's names (include/lt.h):
   lt_create / lt_scene_upload / lt_trace / lt_loss_l2 /
   lt_backward_naive / lt_backward_reslrb / lt_backward_lrb3 /
-  lt_guide_eval / lt_guide_emit / lt_guide_grad / lt_guide_adam
+  lt_guide_eval / lt_guide_emit / lt_guide_grad / lt_guide_adam /
+  lt_batch_create / lt_batch_step / lt_batch_autotune
 and ``LightTrace`` wraps forward + a chosen reverse mode as a
 ``torch.autograd.Function``.
 """
@@ -26,7 +27,7 @@ LIB_PATH = os.path.join(_HERE, "liblt.so")
 COUNTERS_LIB_PATH = os.path.join(_HERE, "liblt_counters.so")
 
 LT_OK, LT_ERR_ARG, LT_ERR_OOM, LT_ERR_HIP, LT_ERR_STATE, LT_ERR_UNSUPPORTED = range(6)
-ATTACHED, SPLAT_SELECTED, RECORD_TAPE, RECORD_RESERVOIR = 1, 2, 4, 8
+ATTACHED, SPLAT_SELECTED, RECORD_TAPE, RECORD_RESERVOIR, CONTRIB_ADJOINT = 1, 2, 4, 8, 16
 _STATUS = {1: "LT_ERR_ARG", 2: "LT_ERR_OOM", 3: "LT_ERR_HIP", 4: "LT_ERR_STATE", 5: "LT_ERR_UNSUPPORTED"}
 
 
@@ -79,6 +80,11 @@ class Stats(C.Structure):
     _fields_ = [("guard_triggers", C.c_uint64), ("nonfinite", C.c_uint64)]
 
 
+class Instance(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("args", TraceArgs), ("params", Params), ("target", C.c_void_p),
+                ("image", C.c_void_p), ("d_image", C.c_void_p), ("loss", C.c_void_p), ("grads", Grads)]
+
+
 _libs = {}
 
 
@@ -113,6 +119,13 @@ def library(path=LIB_PATH):
             "lt_guide_emit": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp, vp], C.c_int),
             "lt_guide_grad": ([vp, vp, vp, C.c_int64, vp, vp], C.c_int),
             "lt_guide_adam": ([vp, vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float], C.c_int),
+            "lt_batch_create": ([C.c_int, vp, C.POINTER(vp)], C.c_int),
+            "lt_batch_destroy": ([vp], None),
+            "lt_batch_last_error": ([vp], C.c_char_p),
+            "lt_batch_step": ([vp, C.POINTER(Instance), C.c_int32, C.c_int32], C.c_int),
+            "lt_batch_set_tuning": ([vp, C.POINTER(Tuning)], C.c_int),
+            "lt_batch_get_tuning": ([vp, C.POINTER(Tuning)], C.c_int),
+            "lt_batch_autotune": ([vp, C.POINTER(Instance), C.c_int32, C.c_char_p, C.POINTER(Tuning)], C.c_int),
         }
         for name, (argt, rest) in sig.items():
             fn = getattr(lib, name)
@@ -126,7 +139,9 @@ def exported_symbols():
     return ["lt_create", "lt_destroy", "lt_last_error", "lt_set_stream", "lt_set_tuning", "lt_get_tuning",
             "lt_set_memory_cap", "lt_get_stats", "lt_read_counters", "lt_scene_upload", "lt_side_state_bytes",
             "lt_workspace_bytes", "lt_trace", "lt_loss_l2", "lt_backward_naive", "lt_backward_reslrb",
-            "lt_backward_lrb3", "lt_guide_eval", "lt_guide_emit", "lt_guide_grad", "lt_guide_adam"]
+            "lt_backward_lrb3", "lt_guide_eval", "lt_guide_emit", "lt_guide_grad", "lt_guide_adam",
+            "lt_batch_create", "lt_batch_destroy", "lt_batch_last_error", "lt_batch_step", "lt_batch_set_tuning",
+            "lt_batch_get_tuning", "lt_batch_autotune"]
 
 
 def _ptr(t):
@@ -310,6 +325,68 @@ class Context:
                                            float(beta1), float(beta2), float(eps)))
 
 
+class Batch:
+    """Runner of batched optimisation steps (lt_batch_*) on torch's current
+    stream of `device`.  An instance is a dict with keys ctx (Context), seed,
+    n_paths, depth, attached (bool), albedo, Le, heights, guide (tensors or
+    None), target, image, d_image, loss, g_albedo, g_Le, g_heights."""
+
+    def __init__(self, device=0):
+        self.lib = library(LIB_PATH)
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        h = C.c_void_p()
+        s = torch.cuda.current_stream(self.device)
+        st = self.lib.lt_batch_create(self.device.index or 0, C.c_void_p(s.cuda_stream), C.byref(h))
+        if st != LT_OK:
+            raise LTError(st, "lt_batch_create failed")
+        self.h = h
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                self.lib.lt_batch_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != LT_OK:
+            raise LTError(st, self.lib.lt_batch_last_error(self.h).decode())
+
+    @staticmethod
+    def table(instances):
+        arr = (Instance * len(instances))()
+        for k, d in enumerate(instances):
+            ctx = d["ctx"]
+            arr[k].ctx = ctx.h
+            arr[k].args = ctx.args(d["seed"], d["n_paths"], d["depth"], ATTACHED if d.get("attached") else 0)
+            arr[k].params = ctx.params(d["albedo"], d["Le"], d.get("heights"), d.get("guide"))
+            arr[k].target, arr[k].image = d["target"].data_ptr(), d["image"].data_ptr()
+            arr[k].d_image, arr[k].loss = d["d_image"].data_ptr(), d["loss"].data_ptr()
+            arr[k].grads = ctx._grads(d["g_albedo"], d.get("g_Le"), d.get("g_heights"))
+        return arr
+
+    def step(self, instances, use_graph=True, table=None):
+        arr = table if table is not None else self.table(instances)
+        self._check(self.lib.lt_batch_step(self.h, arr, len(arr), int(bool(use_graph))))
+
+    def set_tuning(self, block=256, blocks_per_cu=4):
+        t = Tuning(block, blocks_per_cu, 0)
+        self._check(self.lib.lt_batch_set_tuning(self.h, C.byref(t)))
+
+    def get_tuning(self):
+        t = Tuning()
+        self._check(self.lib.lt_batch_get_tuning(self.h, C.byref(t)))
+        return dict(block=t.block, blocks_per_cu=t.blocks_per_cu)
+
+    def autotune(self, instances, cache_path=None):
+        arr = self.table(instances)
+        t = Tuning()
+        self._check(self.lib.lt_batch_autotune(self.h, arr, len(arr),
+                                               None if cache_path is None else str(cache_path).encode(), C.byref(t)))
+        return dict(block=t.block, blocks_per_cu=t.blocks_per_cu)
+
+
 # C-ABI names as module-level functions -------------------------------------
 def lt_create(device=0):
     return Context(device)
@@ -353,6 +430,18 @@ def lt_guide_grad(ctx, guide_w, samples, grad, loss=None):
 
 def lt_guide_adam(ctx, w, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return ctx.guide_adam(w, grad, m, v, step, lr, beta1, beta2, eps)
+
+
+def lt_batch_create(device=0):
+    return Batch(device)
+
+
+def lt_batch_step(batch, instances, use_graph=True):
+    return batch.step(instances, use_graph)
+
+
+def lt_batch_autotune(batch, instances, cache_path=None):
+    return batch.autotune(instances, cache_path)
 
 
 # ------------------------------------------------------------ autograd

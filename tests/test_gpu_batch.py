@@ -1,0 +1,146 @@
+"""Batched optimisation steps (one persistent launch per pass over an
+instance table, optionally replayed from a captured hipGraph) against the
+same steps made by per-instance calls.
+
+Both run the same kernels' per-path code with the same seeds; only the
+order of floating-point atomic sums differs (and the attached backward of
+a single instance pre-reduces heights gradients in LDS), so results agree to
+FP32 summation-order rounding: max |a - b| / max |b| <= 1e-5 for images and
+losses, 1e-4 for gradients.
+"""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2609_32920_amd import lt, scenes
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [  # kind, G, film, paths, depth, guided
+    ("box", 0, 64, 100_000, 4, False),
+    ("caustic", 16, 64, 65_536, 4, False),
+    ("box", 0, 96, 70_001, 6, False),
+    ("caustic", 24, 80, 50_000, 6, True),
+    ("box", 0, 32, 1, 3, False),
+]
+
+
+def _f32(a, dev):
+    return torch.as_tensor(np.asarray(a, np.float32), device=dev).contiguous()
+
+
+def _instances(dev):
+    out = []
+    for k, (kind, G, film, n, D, guided) in enumerate(SPECS):
+        sc = scenes.box_scene(width=film, height=film) if kind == "box" else \
+            scenes.caustic_scene(G=G, width=film, height=film)
+        ctx = lt.Context(0).scene_upload(sc)
+        d = dict(ctx=ctx, seed=100 + k, n_paths=n, depth=D, attached=kind == "caustic",
+                 albedo=_f32(sc["albedo"], dev), Le=_f32(sc["Le"], dev),
+                 heights=_f32(sc["heights"], dev) if kind == "caustic" else None,
+                 guide=_f32(scenes.guide_aimed_weights(), dev) if guided else None)
+        tgt = torch.empty((film, film, 3), device=dev)
+        tp = ctx.params(_f32(sc["albedo_target"], dev) if kind == "box" else d["albedo"], d["Le"],
+                        _f32(sc["heights_target"], dev) if kind == "caustic" else None)
+        ctx.trace(ctx.args(7, 1 << 16, D, lt.ATTACHED if kind == "caustic" else 0), tp, tgt)
+        d.update(target=tgt, image=torch.empty_like(tgt), d_image=torch.empty_like(tgt),
+                 loss=torch.zeros(1, device=dev), g_albedo=torch.zeros_like(d["albedo"]),
+                 g_Le=torch.zeros_like(d["Le"]),
+                 g_heights=torch.zeros_like(d["heights"]) if d["heights"] is not None else None)
+        out.append(d)
+    torch.cuda.synchronize()
+    return out
+
+
+def _zero(insts):
+    for d in insts:
+        for k in ("g_albedo", "g_Le", "g_heights"):
+            if d[k] is not None:
+                d[k].zero_()
+
+
+def _reference(d):
+    """The same step through per-instance calls."""
+    ctx = d["ctx"]
+    a = ctx.args(d["seed"], d["n_paths"], d["depth"], lt.ATTACHED if d["attached"] else 0)
+    p = ctx.params(d["albedo"], d["Le"], d["heights"], d["guide"])
+    img, dI = torch.empty_like(d["image"]), torch.empty_like(d["image"])
+    loss = torch.zeros(1, device=d["image"].device)
+    ga, gl = torch.zeros_like(d["albedo"]), torch.zeros_like(d["Le"])
+    gh = torch.zeros_like(d["heights"]) if d["heights"] is not None else None
+    ctx.trace(a, p, img)
+    ctx.loss_l2(img, d["target"], dI, loss)
+    ctx.backward_lrb3(a, p, dI, ga, gl, gh)
+    torch.cuda.synchronize()
+    return dict(image=img, d_image=dI, loss=loss, g_albedo=ga, g_Le=gl, g_heights=gh)
+
+
+def _maxrel(a, b):
+    a, b = a.double(), b.double()
+    den = b.abs().max().item()
+    return (a - b).abs().max().item() / den if den > 0 else (a - b).abs().max().item()
+
+
+def _compare(insts, tag):
+    for k, d in enumerate(insts):
+        ref = _reference(d)
+        e_img = _maxrel(d["image"], ref["image"])
+        e_loss = _maxrel(d["loss"], ref["loss"])
+        e_g = [_maxrel(d[g], ref[g]) for g in ("g_albedo", "g_Le", "g_heights") if d[g] is not None]
+        print(f"{tag} instance {k} {SPECS[k]}: image {e_img:.1e} loss {e_loss:.1e} grads {max(e_g):.1e}", flush=True)
+        assert e_img <= 1e-5 and e_loss <= 1e-5 and max(e_g) <= 1e-4
+
+
+def test_batched_step_matches_per_instance_calls():
+    dev = torch.device("cuda", 0)
+    insts = _instances(dev)
+    b = lt.Batch(0)
+    _zero(insts)
+    b.step(insts, use_graph=False)
+    torch.cuda.synchronize()
+    _compare(insts, "eager batch")
+
+
+def test_graph_replays_match_per_instance_calls():
+    dev = torch.device("cuda", 0)
+    insts = _instances(dev)
+    b = lt.Batch(0)
+    for rep in range(3):  # capture, then replays with new seeds and eager work in between
+        for k, d in enumerate(insts):
+            d["seed"] = 1000 * rep + 17 * k + 1
+        _zero(insts)
+        b.step(insts, use_graph=True)
+        torch.cuda.synchronize()
+        _compare(insts, f"graph replay {rep}")
+
+
+def test_autotune_and_cache(tmp_path):
+    dev = torch.device("cuda", 0)
+    insts = _instances(dev)
+    b = lt.Batch(0)
+    cache = tmp_path / "tune.json"
+    t1 = b.autotune(insts, cache)
+    data = json.loads(cache.read_text())
+    assert len(data) == 1
+    entry = next(iter(data.values()))
+    assert entry["block"] == t1["block"] and entry["blocks_per_cu"] == t1["blocks_per_cu"] and entry["ms"] > 0
+    b2 = lt.Batch(0)
+    assert b2.autotune(insts, cache) == t1 == b.get_tuning()
+    # the tuned runner still computes the same step
+    _zero(insts)
+    b.step(insts, use_graph=True)
+    torch.cuda.synchronize()
+    _compare(insts, "tuned graph")
+
+
+def test_batch_rejects_unsupported():
+    dev = torch.device("cuda", 0)
+    insts = _instances(dev)[:1]
+    b = lt.Batch(0)
+    arr = b.table(insts)
+    arr[0].args.flags = lt.RECORD_TAPE
+    with pytest.raises(lt.LTError) as e:
+        b.step(insts, table=arr)
+    assert e.value.status == lt.LT_ERR_UNSUPPORTED
