@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 48-instance workload")
     ap.add_argument("--guide-iters", type=int, default=40, help="online training iterations of the guide")
     ap.add_argument("--guide-seeds", type=int, default=12, help="seeds per gradient-variance estimate")
-    ap.add_argument("--cpu-paths", type=int, default=1 << 15)
+    ap.add_argument("--cpu-paths", type=int, default=1 << 22, help="paths in the CPU-oracle sample")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for profiler byte counters)")
     return ap.parse_args()
@@ -213,9 +213,10 @@ def main():
                                    n_train=1 << 18, mode="lrb3", target="gradient", lr=5e-3)
 
     # ---- batched instances: one persistent launch per pass, hipGraph replay
-    batch = None
+    batch = batch_small = None
     if not args.no_batch:
         batch = bench_batch(lt, scenes, dev, stream)
+        batch_small = bench_batch(lt, scenes, dev, stream, path_scale=1.0 / 64, reps=4)
 
     # ---- CPU baseline: the FP64 oracle, forward + naive backward, on a sample
     cpu = None
@@ -257,6 +258,7 @@ def main():
         "guide": guide,
         "guide_smooth_slab": guide_smooth,
         "batch": batch,
+        "batch_small_instances": batch_small,
     }
     print(json.dumps(out), flush=True)
 
@@ -437,7 +439,7 @@ def bench_guide(lt, scenes, dev, stream, G=256, film=1024, N=1 << 26, D=8, iters
     return out
 
 
-def bench_batch(lt, scenes, dev, stream, n=48, seed=7, reps=2):
+def bench_batch(lt, scenes, dev, stream, n=48, seed=7, reps=2, path_scale=1.0):
     """48 box / caustic instances of uneven heightfield (32^2..256^2), film
     (128^2..1024^2), path count (1M..32M) and depth (4..12) drawn from a
     seed: one optimisation step each (forward, L2 loss, LRB-3-pass backward;
@@ -457,12 +459,13 @@ def bench_batch(lt, scenes, dev, stream, n=48, seed=7, reps=2):
         sc = scenes.box_scene(width=sp["film"], height=sp["film"]) if box else \
             scenes.caustic_scene(G=sp["G"], width=sp["film"], height=sp["film"])
         ctx = lt.Context(0).scene_upload(sc)
-        d = dict(ctx=ctx, seed=5000 + k, n_paths=sp["n_paths"], depth=sp["depth"], attached=not box,
+        npaths = max(1, int(sp["n_paths"] * path_scale))
+        d = dict(ctx=ctx, seed=5000 + k, n_paths=npaths, depth=sp["depth"], attached=not box,
                  albedo=f32(sc["albedo"]), Le=f32(sc["Le"]), heights=None if box else f32(sc["heights"]), guide=None)
         tgt = torch.empty((sp["film"], sp["film"], 3), dtype=torch.float32, device=dev)
         tp = ctx.params(f32(sc["albedo_target"]) if box else d["albedo"], d["Le"],
                         None if box else f32(sc["heights_target"]))
-        ctx.trace(ctx.args(0x7A6, min(sp["n_paths"], 1 << 22), sp["depth"], 0 if box else lt.ATTACHED), tp, tgt)
+        ctx.trace(ctx.args(0x7A6, min(npaths, 1 << 22), sp["depth"], 0 if box else lt.ATTACHED), tp, tgt)
         d.update(target=tgt, image=torch.empty_like(tgt), d_image=torch.empty_like(tgt),
                  loss=torch.zeros(1, dtype=torch.float32, device=dev), g_albedo=torch.zeros_like(d["albedo"]),
                  g_Le=torch.zeros_like(d["Le"]), g_heights=None if box else torch.zeros_like(d["heights"]))
@@ -499,9 +502,10 @@ def bench_batch(lt, scenes, dev, stream, n=48, seed=7, reps=2):
     t_tune = time.perf_counter() - t_tune0
     t_eager = timed(lambda: b.step(insts, use_graph=False))
     t_graph = timed(lambda: b.step(insts, use_graph=True))
+    lo, hi = min(d["n_paths"] for d in insts), max(d["n_paths"] for d in insts)
     out = {"workload": f"{n} instances ({sum(1 for d in insts if not d['attached'])} box, "
                        f"{sum(1 for d in insts if d['attached'])} caustic; heightfields 32^2..256^2, films "
-                       f"128^2..1024^2, 1M..32M paths, depth 4..12, drawn from seed {seed}); one step each = "
+                       f"128^2..1024^2, {lo}..{hi} paths, depth 4..12, drawn from seed {seed}); one step each = "
                        "forward + L2 loss + LRB-3-pass backward (attached for caustics)",
            "paths_per_step": total, "per_instance_ms": round(t_inst, 2), "batched_eager_ms": round(t_eager, 2),
            "batched_graph_ms": round(t_graph, 2),
