@@ -25,10 +25,11 @@ B_NODE, B_TRI, B_SPLAT, B_GATHER, B_GRAD, B_TAPE = 64, 48, 96, 48, 8, 32
 KERNEL_SOURCES = ["lt_common.h", "lt_device.h", "lt_launch.h", "lt_kernels.hip", "lt_attached.inc"]
 
 
-def profiled_traffic(name):
-    """HBM bytes per launch from the committed rocprofv3 summary profiles/<name>
-    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when the kernel
-    sources changed since the counters were taken."""
+def profiled_traffic(name, field="traffic_bytes_per_launch"):
+    """A figure from the committed rocprofv3 summary profiles/<name>: HBM bytes
+    per launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy) or a VALU
+    issue fraction; None when the kernel sources changed since the counters
+    were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
@@ -41,9 +42,9 @@ def profiled_traffic(name):
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, "paper_2609_32920_amd", "csrc", f), "rb").read())
-    if fields.get("sources_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in fields:
+    if fields.get("sources_sha256") != h.hexdigest() or field not in fields:
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    return float(fields[field])
 
 
 def parse():
@@ -163,6 +164,8 @@ def main():
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": "k_lrb3_bwd", "bytes_per_path": round(bpp, 1),
+                    "valu_issue_frac_profiled": profiled_traffic("k_lrb3_caustic128_box256_valu.txt",
+                                                                 "valu_issue_frac_k_lrb3_bwd"),
                     "launch_ms": round(t_launch * 1e3, 4),
                     "events_per_path": {k: round(v / sample, 3) for k, v in counts["lrb3"].items()}}
         print(f"# lrb3 algorithmic bytes/path {bpp:.0f}  achieved {achieved:.0f} GB/s", file=sys.stderr)
@@ -328,6 +331,8 @@ def bench_caustic(lt, scenes, dev, stream, bytes_per_path_fn, G=128, film=512, N
         out["lrb3_roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                 "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_path": round(bpp, 1),
                                 "traffic": profiled_traffic("k_lrb3_att_caustic128_512_d6_16M.txt"),
+                                "valu_issue_frac_profiled": profiled_traffic("k_lrb3_caustic128_box256_valu.txt",
+                                                                             "valu_issue_frac_k_lrb3_att"),
                                 "events_per_path": {k: round(v / sample, 3) for k, v in c.items()}}
         del cctx
     except Exception as e:

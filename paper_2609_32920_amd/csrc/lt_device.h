@@ -134,8 +134,11 @@ __device__ __forceinline__ Hit closest_hit(const DevScene& sc, f3 o, f3 d, float
   f3 inv = safe_inv(d);
   int sp = 0, node = 0;
   while (true) {
-    float4 a, b, c; int4 e;
-    load_node(sc.nodes, node, a, b, c, e);
+    float4 a, b, c; int4 e4;
+    load_node(sc.nodes, node, a, b, c, e4);
+    // plain scalars: a select over the vector's fields would be lowered
+    // to an indexed private-memory access
+    const struct { int x, y, z, w; } e = {e4.x, e4.y, e4.z, e4.w};
     LT_COUNT(2, 1);
     float tn0, tn1;
     bool h0 = e.x >= 0 && slab(a.x, a.y, a.z, a.w, b.x, b.y, o, inv, tmin, h.t, tn0);
@@ -178,8 +181,11 @@ __device__ __forceinline__ bool any_hit(const DevScene& sc, f3 o, f3 d, float tm
   f3 inv = safe_inv(d);
   int sp = 0, node = 0;
   while (true) {
-    float4 a, b, c; int4 e;
-    load_node(sc.nodes, node, a, b, c, e);
+    float4 a, b, c; int4 e4;
+    load_node(sc.nodes, node, a, b, c, e4);
+    // plain scalars: a select over the vector's fields would be lowered
+    // to an indexed private-memory access
+    const struct { int x, y, z, w; } e = {e4.x, e4.y, e4.z, e4.w};
     LT_COUNT(2, 1);
     float tn0, tn1;
     bool h0 = e.x >= 0 && slab(a.x, a.y, a.z, a.w, b.x, b.y, o, inv, tmin, tmax, tn0);
