@@ -213,7 +213,7 @@ def main():
     if not args.no_guide:
         guide = bench_guide(lt, scenes, dev, stream, iters=args.guide_iters, K=args.guide_seeds)
         guide_smooth = bench_guide(lt, scenes, dev, stream, G=64, film=256, N=1 << 22, D=6, iters=60, K=16,
-                                   n_train=1 << 18, mode="lrb3", target="gradient", lr=5e-3)
+                                   n_train=1 << 18, mode="lrb3", target="gradient", lr=2e-3)
 
     # ---- batched instances: one persistent launch per pass, hipGraph replay
     batch = batch_small = None

@@ -155,7 +155,10 @@ typedef struct {
 typedef struct {
   int32_t block;           /* threads per workgroup: 64..1024, multiple of 64 */
   int32_t blocks_per_cu;   /* persistent workgroups per compute unit, 1..64 */
-  int32_t lds_grad;        /* 1: pre-reduce albedo gradients in LDS when they fit */
+  int32_t lds_grad;        /* 1 (default): each workgroup pre-reduces albedo gradients in LDS
+                              when the texture set takes at most 48 KB and the copy costs
+                              the kernel no resident workgroups; 0: never (waves then
+                              write-combine them into the gradient array) */
 } lt_tuning;
 
 /* Counters from the last call that produced them. */
@@ -368,7 +371,12 @@ const char* lt_batch_last_error(const lt_batch* b);
  * LT_ERR_HIP. */
 lt_status lt_batch_step(lt_batch* b, const lt_instance* inst, int32_t n, int32_t use_graph);
 /* Launch shape of the batched passes: block and blocks_per_cu as in
- * lt_set_tuning (the attached backward keeps 256-thread workgroups). */
+ * lt_set_tuning (the attached backward keeps 256-thread workgroups).
+ * Default {256, 4, 1}.  The backward passes keep per-workgroup LDS copies of
+ * the gradient arrays (heights always, albedo with lds_grad = 1) for the
+ * instances whose arrays fit one budget per pass: the largest requested size
+ * that costs the pass no resident workgroups per compute unit.  The other
+ * instances accumulate into their gradient arrays directly. */
 lt_status lt_batch_set_tuning(lt_batch* b, const lt_tuning* t);
 lt_status lt_batch_get_tuning(const lt_batch* b, lt_tuning* out);
 /* Pick block size and workgroups per compute unit for these instances by

@@ -153,7 +153,7 @@ struct lt_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
-  lt_tuning tune{256, 4, 0};
+  lt_tuning tune{256, 4, 1};
   uint64_t cap = 0;
   lt_stats stats{};
   int n_cu = 256;
@@ -220,6 +220,20 @@ int hgrad_in_lds(const lt_ctx* c, const float* g_heights, bool with_stack) {
                 (with_stack ? (size_t)c->dsc.stack_n * 256 * sizeof(int) : 0);
   return need <= (size_t)c->lds_max ? 1 : 0;
 }
+
+// Albedo gradients go to a per-workgroup LDS copy (lt_tuning.lds_grad) when
+// the texture set takes at most 48 KB, fits next to the other LDS users and
+// costs the kernel no resident workgroups per CU; otherwise each wave
+// write-combines them into the caller's array.
+int agrad_in_lds(const lt_ctx* c, BwdKernel k, int block, size_t used) {
+  if (!c->tune.lds_grad) return 0;
+  size_t need = (size_t)c->dsc.n_tex * c->dsc.tex_res * c->dsc.tex_res * 3 * sizeof(float);
+  if (need > 48 * 1024 || used + need > (size_t)c->lds_max) return 0;
+  int with = resident_groups(k, block, used + need);
+  return with > 0 && with >= resident_groups(k, block, used) ? 1 : 0;
+}
+size_t stack_lds(const lt_ctx* c, int block) { return (size_t)c->dsc.stack_n * block * sizeof(int); }
+size_t hgrad_lds_bytes(const lt_ctx* c, int on) { return on ? (size_t)c->dsc.hf_G * c->dsc.hf_G * sizeof(float) : 0; }
 
 struct SideLayout { size_t tape = 0, len = 0, emit = 0, res = 0, total = 0; };
 
@@ -342,6 +356,7 @@ PassArgs base_args(lt_ctx* c, const lt_trace_args* a, const lt_params* p) {
   A.Kfilm = (float)Kfilm;
   A.n_texels = c->dsc.n_tex * c->dsc.tex_res * c->dsc.tex_res;
   A.hgrad_lds = 0;
+  A.agrad_lds = 0;
   A.mask = a->path_mask;
   A.sig = a->path_sig;
   A.info = a->path_info;
@@ -421,7 +436,7 @@ lt_status lt_set_stream(lt_ctx* c, void* stream) {
 
 lt_status lt_set_tuning(lt_ctx* c, const lt_tuning* t) {
   if (!c) return LT_ERR_ARG;
-  if (!t) { c->tune = lt_tuning{256, 4, 0}; return LT_OK; }
+  if (!t) { c->tune = lt_tuning{256, 4, 1}; return LT_OK; }
   if (t->block < 64 || t->block > 1024 || (t->block % 64) != 0) return c->fail(LT_ERR_ARG, "block must be 64..1024, a multiple of 64%s");
   if (t->blocks_per_cu < 1 || t->blocks_per_cu > 64) return c->fail(LT_ERR_ARG, "blocks_per_cu must be 1..64%s");
   if ((size_t)kStackMax * t->block * sizeof(int) > (size_t)c->lds_max) return c->fail(LT_ERR_ARG, "traversal stack exceeds the LDS of a workgroup%s");
@@ -752,9 +767,11 @@ lt_status lt_backward_naive(lt_ctx* c, const lt_trace_args* a, const lt_params* 
   if (a->flags & LT_ATTACHED) {
     A.emit_d = (float*)(sb + L.emit);
     A.hgrad_lds = hgrad_in_lds(c, g->heights, false);
+    A.agrad_lds = agrad_in_lds(c, BwdKernel::naive_att, 256, hgrad_lds_bytes(c, A.hgrad_lds));
     if ((st = c->hip(launch_naive_att_bwd(A, grid, c->stream), "naive attached backward")) != LT_OK) return st;
-  } else if ((st = c->hip(launch_naive_bwd(A, grid, c->stream), "naive backward")) != LT_OK) {
-    return st;
+  } else {
+    A.agrad_lds = agrad_in_lds(c, BwdKernel::naive, 256, 0);
+    if ((st = c->hip(launch_naive_bwd(A, grid, c->stream), "naive backward")) != LT_OK) return st;
   }
   return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
 }
@@ -772,11 +789,13 @@ lt_status lt_backward_reslrb(lt_ctx* c, const lt_trace_args* a, const lt_params*
     A.res_att_in = (const ResRecAtt*)((const char*)records + L.res);
     int grid = persistent_grid(c, a->n_paths, 256);
     A.hgrad_lds = hgrad_in_lds(c, g->heights, true);
+    A.agrad_lds = agrad_in_lds(c, BwdKernel::reslrb_att, 256, stack_lds(c, 256) + hgrad_lds_bytes(c, A.hgrad_lds));
     if ((st = c->hip(launch_reslrb_att(A, grid, c->stream), "reslrb attached backward")) != LT_OK) return st;
     return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
   }
   A.res_in = (const ResRec*)((const char*)records + L.res);
   int grid = persistent_grid(c, a->n_paths, c->tune.block);
+  A.agrad_lds = agrad_in_lds(c, BwdKernel::reslrb, c->tune.block, stack_lds(c, c->tune.block));
   if ((st = c->hip(launch_reslrb_bwd(A, grid, c->tune.block, c->stream), "reslrb backward")) != LT_OK) return st;
   return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
 }
@@ -791,9 +810,11 @@ lt_status lt_backward_lrb3(lt_ctx* c, const lt_trace_args* a, const lt_params* p
   if (a->flags & LT_ATTACHED) {
     int grid = persistent_grid(c, a->n_paths, 256);
     A.hgrad_lds = hgrad_in_lds(c, g->heights, true);
+    A.agrad_lds = agrad_in_lds(c, BwdKernel::lrb3_att, 256, stack_lds(c, 256) + hgrad_lds_bytes(c, A.hgrad_lds));
     if ((st = c->hip(launch_lrb3_att(A, grid, c->stream), "lrb3 attached backward")) != LT_OK) return st;
   } else {
     int grid = persistent_grid(c, a->n_paths, c->tune.block);
+    A.agrad_lds = agrad_in_lds(c, BwdKernel::lrb3, c->tune.block, stack_lds(c, c->tune.block));
     if ((st = c->hip(launch_lrb3_bwd(A, grid, c->tune.block, c->stream), "lrb3 backward")) != LT_OK) return st;
   }
   return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
@@ -874,7 +895,7 @@ struct lt_batch {
   hipStream_t stream = nullptr;       // caller's stream: eager steps and graph launches
   hipStream_t cap = nullptr;          // the runner's own stream, for capture (the null stream cannot be)
   std::string err;
-  lt_tuning tune{256, 4, 0};
+  lt_tuning tune{256, 4, 1};
   int n_cu = 256;
   std::string arch;
   // device tables: trace [n], detached backward [n_det], attached backward [n_att]
@@ -906,8 +927,25 @@ namespace {
 struct BatchPlan {
   std::vector<PassArgs> tab;   // [n trace][n_det detached][n_att attached]
   std::vector<int> det, att;   // instance indices of each backward kind
-  int n = 0, stack_n = 1;
+  int n = 0, stack_n = 1;      // traversal stack entries per lane, the same for every entry
+  size_t det_lds = 0, att_lds = 0;  // LDS bytes past the stacks for gradient copies, per launch
 };
+
+// Largest of the sizes the instances ask for that fits next to the traversal
+// stacks and costs the batched kernel no resident workgroups per CU (0 if
+// none does).  Residency only falls as the size grows, so the first fit from
+// the top is the answer.
+size_t batch_lds_budget(BwdKernel k, int block, size_t stack, size_t lds_max, std::vector<size_t> sizes) {
+  std::sort(sizes.begin(), sizes.end());
+  sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+  const int base = resident_groups(k, block, stack);
+  for (auto it = sizes.rbegin(); it != sizes.rend() && *it > 0; ++it) {
+    if (stack + *it > lds_max) continue;
+    int r = resident_groups(k, block, stack + *it);
+    if (r > 0 && r >= base) return *it;
+  }
+  return 0;
+}
 
 lt_status batch_check(lt_batch* b, const lt_instance* inst, int n) {
   if (!inst || n < 1 || n > 4096) return b->fail(LT_ERR_ARG, "need 1..4096 instances");
@@ -988,6 +1026,44 @@ BatchPlan batch_plan(lt_batch* b, const lt_instance* inst, int n, int64_t path_d
     ((a.flags & LT_ATTACHED) ? P.att : P.det).push_back(i);
     P.tab[n + i] = B;  // reordered below
   }
+  // Gradient copies in LDS.  Every entry lays its LDS out past stacks of the
+  // batch's common depth, so no instance's copies overlap the stacks of waves
+  // still on another instance; the copies of one instance are flushed
+  // (workgroup barrier) before its waves move on.
+  auto tex_bytes = [&](const lt_ctx* c) -> size_t {
+    size_t t = (size_t)c->dsc.n_tex * c->dsc.tex_res * c->dsc.tex_res * 3 * sizeof(float);
+    return b->tune.lds_grad && t <= 48 * 1024 ? t : 0;
+  };
+  auto hf_bytes = [&](const lt_instance& I) -> size_t {
+    int G = I.ctx->dsc.hf_G;
+    return I.grads.heights && G >= 2 ? (size_t)G * G * sizeof(float) : 0;
+  };
+  std::vector<size_t> dsz, asz;
+  for (int i = 0; i < n; ++i) {
+    size_t t = tex_bytes(inst[i].ctx);
+    if (!(inst[i].args.flags & LT_ATTACHED)) { dsz.push_back(t); continue; }
+    size_t h = hf_bytes(inst[i]);
+    asz.push_back(h); asz.push_back(t);
+    if (h && t) asz.push_back(h + t);
+  }
+  const size_t lds_max = (size_t)inst[0].ctx->lds_max;
+  if (!P.det.empty())
+    P.det_lds = batch_lds_budget(BwdKernel::lrb3_batch, b->tune.block, (size_t)P.stack_n * b->tune.block * sizeof(int),
+                                 lds_max, dsz);
+  if (!P.att.empty())
+    P.att_lds = batch_lds_budget(BwdKernel::lrb3_att_batch, 256, (size_t)P.stack_n * 256 * sizeof(int), lds_max, asz);
+  for (auto& e : P.tab) e.sc.stack_n = P.stack_n;
+  for (int i = 0; i < n; ++i) {
+    PassArgs& B = P.tab[n + i];
+    size_t t = tex_bytes(inst[i].ctx);
+    if (!(inst[i].args.flags & LT_ATTACHED)) {
+      B.agrad_lds = t && t <= P.det_lds;
+      continue;
+    }
+    size_t h = hf_bytes(inst[i]);
+    B.hgrad_lds = h && h <= P.att_lds;
+    B.agrad_lds = t && t + (B.hgrad_lds ? h : 0) <= P.att_lds;
+  }
   // backward entries: detached ones first, then attached ones
   std::vector<PassArgs> bw;
   for (int i : P.det) bw.push_back(P.tab[n + i]);
@@ -1031,12 +1107,12 @@ lt_status batch_enqueue_on(lt_batch* b, const lt_instance* inst, const BatchPlan
       return st;
   }
   const int nd = (int)P.det.size(), na = (int)P.att.size();
-  if (nd && (st = b->hip(launch_lrb3_batch(b->d_tab + n, nd, P.stack_n, grid, b->tune.block, s),
+  if (nd && (st = b->hip(launch_lrb3_batch(b->d_tab + n, nd, P.stack_n, P.det_lds, grid, b->tune.block, s),
                          "batched backward")) != LT_OK)
     return st;
   if (na) {
     int grid_att = (int)std::max<int64_t>(1, (int64_t)b->n_cu * b->tune.blocks_per_cu * b->tune.block / 256);
-    if ((st = b->hip(launch_lrb3_att_batch(b->d_tab + n + nd, na, P.stack_n, grid_att, s),
+    if ((st = b->hip(launch_lrb3_att_batch(b->d_tab + n + nd, na, P.stack_n, P.att_lds, grid_att, s),
                      "batched attached backward")) != LT_OK)
       return st;
   }
@@ -1052,13 +1128,17 @@ lt_status batch_enqueue(lt_batch* b, const lt_instance* inst, const BatchPlan& P
   return st;
 }
 
-// Identity of an instance set for graph reuse: everything but the seeds.
-std::vector<char> batch_key(const lt_batch* b, const lt_instance* inst, int n) {
+// Identity of a step for graph reuse: the instances (all but the seeds), the
+// tuning and the plan's LDS sizes (a scene uploaded again into an instance's
+// context may change them).
+std::vector<char> batch_key(const lt_batch* b, const lt_instance* inst, int n, const BatchPlan& P) {
   std::vector<lt_instance> v(inst, inst + n);
   for (auto& I : v) I.args.seed = 0;
   std::vector<char> k((const char*)v.data(), (const char*)(v.data() + n));
   const char* t = (const char*)&b->tune;
   k.insert(k.end(), t, t + sizeof(lt_tuning));
+  const size_t sz[3] = {(size_t)P.stack_n, P.det_lds, P.att_lds};
+  k.insert(k.end(), (const char*)sz, (const char*)(sz + 3));
   return k;
 }
 
@@ -1073,7 +1153,7 @@ lt_status batch_run(lt_batch* b, const lt_instance* inst, int n, bool use_graph,
                                   b->stream), "table upload")) != LT_OK)
     return st;
   if (!use_graph) return batch_enqueue(b, inst, P, b->stream);
-  std::vector<char> key = batch_key(b, inst, n);
+  std::vector<char> key = batch_key(b, inst, n, P);
   if (!b->exec || key != b->key) {
     b->drop_graph();
     if (!b->cap && (st = b->hip(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "capture stream")) != LT_OK)
@@ -1200,12 +1280,14 @@ lt_status lt_batch_autotune(lt_batch* b, const lt_instance* inst, int32_t n, con
     n_att += (inst[i].args.flags & LT_ATTACHED) ? 1 : 0;
   }
   char key[256];
-  std::snprintf(key, sizeof(key), "%s|cu%d|n%d|att%d|paths%lld", b->arch.c_str(), b->n_cu, n, n_att, (long long)total);
+  const int32_t lg = b->tune.lds_grad;  // kept: the trials choose the launch shape only
+  std::snprintf(key, sizeof(key), "%s|cu%d|n%d|att%d|paths%lld|lds%d", b->arch.c_str(), b->n_cu, n, n_att,
+                (long long)total, (int)lg);
   auto cache = cache_read(cache_path);
   auto it = cache.find(key);
   double bl = 0, bpc = 0;
   if (it != cache.end() && cache_field(it->second, "block", bl) && cache_field(it->second, "blocks_per_cu", bpc)) {
-    lt_tuning t{(int32_t)bl, (int32_t)bpc, 0};
+    lt_tuning t{(int32_t)bl, (int32_t)bpc, lg};
     if ((st = lt_batch_set_tuning(b, &t)) == LT_OK && out) *out = t;
     return st;
   }
@@ -1213,12 +1295,12 @@ lt_status lt_batch_autotune(lt_batch* b, const lt_instance* inst, int32_t n, con
   static const int per_cu[] = {2, 4, 8};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return b->fail(LT_ERR_HIP, "event create");
-  lt_tuning best{256, 4, 0};
+  lt_tuning best{256, 4, lg};
   float best_ms = 1e30f;
   const lt_tuning saved = b->tune;
   for (int blk : blocks)
     for (int k : per_cu) {
-      b->tune = lt_tuning{blk, k, 0};
+      b->tune = lt_tuning{blk, k, lg};
       float ms = 0.f;
       for (int rep = 0; rep < 3 && st == LT_OK; ++rep) {
         hipEventRecord(e0, b->stream);

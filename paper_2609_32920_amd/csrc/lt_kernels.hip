@@ -148,6 +148,88 @@ __device__ __forceinline__ void add_le(const PassArgs& A, double& g0, double& g1
   g0 += a0; g1 += a1; g2 += a2;
 }
 
+// Albedo gradients.  With A.agrad_lds each workgroup pre-reduces them in an
+// LDS copy of the texture set and adds that to the caller's array once, at
+// its end.  Without it (the set is large, or the copy would cost resident
+// workgroups) they go to the caller's array through a one-entry
+// write-combining cache per wave: sums for the texel most of the wave hits
+// stay in registers while later scatters hit the same texel, so a constant
+// or small texture takes one atomic per wave and texel change, not one per
+// scatter.  Every thread of the workgroup calls begin and end, and every
+// lane of a wave calls scatter.
+// The LDS copy is addressed through a pointer derived only from the
+// workgroup's LDS array, and the choice between it and the caller's array is
+// a branch on the uniform flag, not a pointer select: each side then compiles
+// to LDS or global atomics rather than flat ones.
+struct AGrad {
+  float* lds;
+  int idx;  // cached texel (wave-uniform), -1 when empty
+  float s0, s1, s2;
+};
+__device__ __forceinline__ AGrad agrad_begin(const PassArgs& A, int* lds) {
+  AGrad g{reinterpret_cast<float*>(lds), -1, 0.f, 0.f, 0.f};
+  if (!A.agrad_lds) return g;
+  const int n = A.n_texels * 3;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) g.lds[i] = 0.f;
+  __syncthreads();
+  return g;
+}
+__device__ __forceinline__ void agrad_flush(const PassArgs& A, AGrad& g) {
+  if (g.idx >= 0 && __lane_id() == 0) {
+    float* d = A.g_albedo + (size_t)g.idx * 3;
+    if (g.s0 != 0.f) atomicAdd(d + 0, g.s0);
+    if (g.s1 != 0.f) atomicAdd(d + 1, g.s1);
+    if (g.s2 != 0.f) atomicAdd(d + 2, g.s2);
+  }
+}
+__device__ __forceinline__ void scatter_albedo(const PassArgs& A, AGrad& g, bool has, int texel, f3 v) {
+  if (A.agrad_lds) {
+    scatter3_wave(g.lds, has, texel, v);
+    return;
+  }
+  uint64_t m = __ballot(has);
+  if (m == 0ull) return;
+  const int lane = __lane_id();
+  int lead = __ffsll((unsigned long long)m) - 1;
+  int li = __shfl(texel, lead);
+  bool mine = has && texel == li;
+  uint64_t same = __ballot(mine);
+  if (li == g.idx || __popcll(same) >= 8) {
+    LT_COUNT(6, mine ? 3 : 0);
+    float s0 = mine ? v.x : 0.f, s1 = mine ? v.y : 0.f, s2 = mine ? v.z : 0.f;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {  // xor butterfly: every lane ends with the same sums
+      s0 += __shfl_xor(s0, o); s1 += __shfl_xor(s1, o); s2 += __shfl_xor(s2, o);
+    }
+    if (li != g.idx) {
+      agrad_flush(A, g);
+      g.idx = li; g.s0 = 0.f; g.s1 = 0.f; g.s2 = 0.f;
+    }
+    g.s0 += s0; g.s1 += s1; g.s2 += s2;
+    has = has && !mine;
+    if (m == same) return;
+  }
+  scatter3_wave(A.g_albedo, has, texel, v);
+}
+__device__ __forceinline__ void agrad_end(const PassArgs& A, AGrad& g) {
+  if (!A.agrad_lds) {
+    agrad_flush(A, g);
+    return;
+  }
+  __syncthreads();
+  const int n = A.n_texels * 3;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    float v = g.lds[i];
+    if (v != 0.f) atomicAdd(A.g_albedo + i, v);
+  }
+}
+
+// The workgroup's next instance of a batch reuses the LDS past the traversal
+// stacks: no wave may start on it before every wave has flushed the copies.
+__device__ __forceinline__ void lds_grads_done(const PassArgs& A) {
+  if (A.hgrad_lds || A.agrad_lds) __syncthreads();
+}
+
 __device__ __forceinline__ void flush_le(const PassArgs& A, double g0, double g1, double g2) {
   g0 = wave_sum(g0); g1 = wave_sum(g1); g2 = wave_sum(g2);
   if (__lane_id() == 0 && A.g_Le_acc) {
@@ -275,6 +357,8 @@ __global__ void __launch_bounds__(1024) k_trace(PassArgs A) {
 // Lanes of a wave walk their tapes in lock step so that the texel
 // gradients are scattered cooperatively.
 __global__ void __launch_bounds__(256) k_naive_bwd(PassArgs A) {
+  extern __shared__ int lds[];
+  AGrad ga = agrad_begin(A, lds);
   const size_t N = (size_t)A.n_paths;
   double gl0 = 0.0, gl1 = 0.0, gl2 = 0.0;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -316,7 +400,7 @@ __global__ void __launch_bounds__(256) k_naive_bwd(PassArgs A) {
         }
       }
       keep_finite(A, has, gr);
-      scatter3_wave(A.g_albedo, has, texel, gr);
+      scatter_albedo(A, ga, has, texel, gr);
     }
     if (live) {
       add_le(A, gl0, gl1, gl2, (double)bb.x * fac, (double)bb.y * fac, (double)bb.z * fac);
@@ -327,6 +411,7 @@ __global__ void __launch_bounds__(256) k_naive_bwd(PassArgs A) {
                              : 0.f;
   }
   flush_le(A, gl0, gl1, gl2);
+  agrad_end(A, ga);
 }
 
 // ---------------------------------------------------------------- ResLRB
@@ -338,6 +423,7 @@ __global__ void __launch_bounds__(1024) k_reslrb_bwd(PassArgs A) {
   extern __shared__ int lds[];
   int* stk = lds + threadIdx.x;
   const int ss = blockDim.x;
+  AGrad ga = agrad_begin(A, lds + A.sc.stack_n * blockDim.x);
   bool alive = false, exhausted = false;
   uint32_t path = 0;
   int j = 0, R = 0;
@@ -377,9 +463,10 @@ __global__ void __launch_bounds__(1024) k_reslrb_bwd(PassArgs A) {
       else { alive = false; j = 0; }
     }
     keep_finite(A, has, gv);
-    scatter3_wave(A.g_albedo, has, texel, gv);
+    scatter_albedo(A, ga, has, texel, gv);
   }
   flush_le(A, gl0, gl1, gl2);
+  agrad_end(A, ga);
 }
 
 // ---------------------------------------------------------------- LRB-3
@@ -396,6 +483,7 @@ __global__ void __launch_bounds__(1024) k_reslrb_bwd(PassArgs A) {
 __device__ __forceinline__ void lrb3_run(const PassArgs& A, int* lds) {
   int* stk = lds + threadIdx.x;
   const int ss = blockDim.x;
+  AGrad ga = agrad_begin(A, lds + A.sc.stack_n * blockDim.x);
   bool alive = false, exhausted = false;
   uint32_t path = 0;
   int j = 0, phase = 2, klast = 0;
@@ -457,9 +545,11 @@ __device__ __forceinline__ void lrb3_run(const PassArgs& A, int* lds) {
       }
     }
     keep_finite(A, has, gv);
-    scatter3_wave(A.g_albedo, has, texel, gv);
+    scatter_albedo(A, ga, has, texel, gv);
   }
   flush_le(A, gl0, gl1, gl2);
+  agrad_end(A, ga);
+  lds_grads_done(A);
 }
 
 __global__ void __launch_bounds__(1024) k_lrb3_bwd(PassArgs A) {
@@ -569,17 +659,31 @@ __global__ void k_refit_level(Node* nodes, const Tri* tris, const int32_t* level
 // arguments stay uniform across the wave and the cooperative splat and
 // gradient scatter work unchanged.  Waves that finish an instance early start
 // on the next one while others drain: no launch gaps, one tail per launch.
+// Pointers read from ordinary memory are generic to the compiler, so every
+// access through them would be a flat instruction (address-space check,
+// counted on both the vector-memory and LDS counters).  The table is
+// read-only during a launch and is read through the constant address space,
+// as kernel arguments are; pointers loaded from there are taken to be global
+// memory, and loads, stores and atomics through them compile to global ones.
+__device__ __forceinline__ PassArgs table_entry(const PassArgs* T, int i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return ((const __attribute__((address_space(4))) PassArgs*)T)[i];
+#else
+  return T[i];  // host pass of the device function: never executed
+#endif
+}
+
 __global__ void __launch_bounds__(1024) k_trace_batch(const PassArgs* __restrict__ T, int n) {
   extern __shared__ int lds[];
-  for (int i = 0; i < n; ++i) trace_run<false, false>(T[i], lds);
+  for (int i = 0; i < n; ++i) trace_run<false, false>(table_entry(T, i), lds);
 }
 __global__ void __launch_bounds__(1024) k_lrb3_batch(const PassArgs* __restrict__ T, int n) {
   extern __shared__ int lds[];
-  for (int i = 0; i < n; ++i) lrb3_run(T[i], lds);
+  for (int i = 0; i < n; ++i) lrb3_run(table_entry(T, i), lds);
 }
-__global__ void __launch_bounds__(256) k_lrb3_att_batch(const PassArgs* __restrict__ T, int n) {
+__global__ void __launch_bounds__(256, 2) k_lrb3_att_batch(const PassArgs* __restrict__ T, int n) {
   extern __shared__ int lds[];
-  for (int i = 0; i < n; ++i) lrb3_att_run(T[i], lds);
+  for (int i = 0; i < n; ++i) lrb3_att_run(table_entry(T, i), lds);
 }
 
 #ifdef LT_COUNTERS
@@ -591,19 +695,46 @@ static size_t stack_bytes(const PassArgs& A, int block) { return (size_t)A.sc.st
 static size_t hgrad_bytes(const PassArgs& A) {
   return A.hgrad_lds ? (size_t)A.sc.hf_G * A.sc.hf_G * sizeof(float) : 0;
 }
+static size_t agrad_bytes(const PassArgs& A) { return A.agrad_lds ? (size_t)A.n_texels * 3 * sizeof(float) : 0; }
 
-// allow the attached kernels the device's full LDS per workgroup
+// allow the backward kernels the device's full LDS per workgroup
 hipError_t set_lds_limit(int bytes) {
   hipError_t e = hipFuncSetAttribute((const void*)k_lrb3_att, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_reslrb_att, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_naive_att_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_lrb3_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_reslrb_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_naive_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_lrb3_batch, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_lrb3_att_batch, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   return e;
 }
 
+int resident_groups(BwdKernel k, int block, size_t lds) {
+  const void* f = nullptr;
+  switch (k) {
+    case BwdKernel::naive: f = (const void*)k_naive_bwd; break;
+    case BwdKernel::reslrb: f = (const void*)k_reslrb_bwd; break;
+    case BwdKernel::lrb3: f = (const void*)k_lrb3_bwd; break;
+    case BwdKernel::naive_att: f = (const void*)k_naive_att_bwd; break;
+    case BwdKernel::reslrb_att: f = (const void*)k_reslrb_att; break;
+    case BwdKernel::lrb3_att: f = (const void*)k_lrb3_att; break;
+    case BwdKernel::lrb3_batch: f = (const void*)k_lrb3_batch; break;
+    case BwdKernel::lrb3_att_batch: f = (const void*)k_lrb3_att_batch; break;
+  }
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, block, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
+}
+
 hipError_t launch_lrb3_att(const PassArgs& A, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_lrb3_att, dim3(grid), dim3(256), stack_bytes(A, 256) + hgrad_bytes(A), s, A);
+  hipLaunchKernelGGL(k_lrb3_att, dim3(grid), dim3(256), stack_bytes(A, 256) + hgrad_bytes(A) + agrad_bytes(A), s, A);
   return hipGetLastError();
 }
 hipError_t launch_trace_att(const PassArgs& A, bool tape, bool resv, int grid, hipStream_t s) {
@@ -614,11 +745,11 @@ hipError_t launch_trace_att(const PassArgs& A, bool tape, bool resv, int grid, h
   return hipGetLastError();
 }
 hipError_t launch_naive_att_bwd(const PassArgs& A, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_naive_att_bwd, dim3(grid), dim3(256), hgrad_bytes(A), s, A);
+  hipLaunchKernelGGL(k_naive_att_bwd, dim3(grid), dim3(256), hgrad_bytes(A) + agrad_bytes(A), s, A);
   return hipGetLastError();
 }
 hipError_t launch_reslrb_att(const PassArgs& A, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_reslrb_att, dim3(grid), dim3(256), stack_bytes(A, 256) + hgrad_bytes(A), s, A);
+  hipLaunchKernelGGL(k_reslrb_att, dim3(grid), dim3(256), stack_bytes(A, 256) + hgrad_bytes(A) + agrad_bytes(A), s, A);
   return hipGetLastError();
 }
 
@@ -626,12 +757,15 @@ hipError_t launch_trace_batch(const PassArgs* table, int n, int stack_n, int gri
   hipLaunchKernelGGL(k_trace_batch, dim3(grid), dim3(block), (size_t)stack_n * block * sizeof(int), s, table, n);
   return hipGetLastError();
 }
-hipError_t launch_lrb3_batch(const PassArgs* table, int n, int stack_n, int grid, int block, hipStream_t s) {
-  hipLaunchKernelGGL(k_lrb3_batch, dim3(grid), dim3(block), (size_t)stack_n * block * sizeof(int), s, table, n);
+hipError_t launch_lrb3_batch(const PassArgs* table, int n, int stack_n, size_t grad_lds, int grid, int block,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_lrb3_batch, dim3(grid), dim3(block), (size_t)stack_n * block * sizeof(int) + grad_lds, s, table,
+                     n);
   return hipGetLastError();
 }
-hipError_t launch_lrb3_att_batch(const PassArgs* table, int n, int stack_n, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_lrb3_att_batch, dim3(grid), dim3(256), (size_t)stack_n * 256 * sizeof(int), s, table, n);
+hipError_t launch_lrb3_att_batch(const PassArgs* table, int n, int stack_n, size_t grad_lds, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_lrb3_att_batch, dim3(grid), dim3(256), (size_t)stack_n * 256 * sizeof(int) + grad_lds, s, table,
+                     n);
   return hipGetLastError();
 }
 
@@ -659,17 +793,17 @@ hipError_t launch_trace(const PassArgs& A, bool tape, bool resv, int grid, int b
 }
 
 hipError_t launch_naive_bwd(const PassArgs& A, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_naive_bwd, dim3(grid), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(k_naive_bwd, dim3(grid), dim3(256), agrad_bytes(A), s, A);
   return hipGetLastError();
 }
 
 hipError_t launch_reslrb_bwd(const PassArgs& A, int grid, int block, hipStream_t s) {
-  hipLaunchKernelGGL(k_reslrb_bwd, dim3(grid), dim3(block), stack_bytes(A, block), s, A);
+  hipLaunchKernelGGL(k_reslrb_bwd, dim3(grid), dim3(block), stack_bytes(A, block) + agrad_bytes(A), s, A);
   return hipGetLastError();
 }
 
 hipError_t launch_lrb3_bwd(const PassArgs& A, int grid, int block, hipStream_t s) {
-  hipLaunchKernelGGL(k_lrb3_bwd, dim3(grid), dim3(block), stack_bytes(A, block), s, A);
+  hipLaunchKernelGGL(k_lrb3_bwd, dim3(grid), dim3(block), stack_bytes(A, block) + agrad_bytes(A), s, A);
   return hipGetLastError();
 }
 

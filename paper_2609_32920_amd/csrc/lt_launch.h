@@ -41,6 +41,7 @@ struct PassArgs {
   float* g_heights;
   unsigned long long* stats;  // [0] guard triggers, [1] non-finite drops
   int32_t hgrad_lds;          // heights gradients accumulated per workgroup in LDS
+  int32_t agrad_lds;          // albedo gradients accumulated per workgroup in LDS
   const float4* guide_rec;    // guided emission (direction, density) per path, or null
   float* contrib;             // per-path image contribution sum_i lum(C_i), or null
 };
@@ -79,8 +80,10 @@ hipError_t launch_trace(const PassArgs& A, bool tape, bool resv, int grid, int b
 // batches: `table` is a DEVICE array of n PassArgs; stack_n the largest
 // traversal stack among them
 hipError_t launch_trace_batch(const PassArgs* table, int n, int stack_n, int grid, int block, hipStream_t s);
-hipError_t launch_lrb3_batch(const PassArgs* table, int n, int stack_n, int grid, int block, hipStream_t s);
-hipError_t launch_lrb3_att_batch(const PassArgs* table, int n, int stack_n, int grid, hipStream_t s);
+// grad_lds: LDS bytes past the traversal stacks for per-workgroup gradient copies
+hipError_t launch_lrb3_batch(const PassArgs* table, int n, int stack_n, size_t grad_lds, int grid, int block,
+                             hipStream_t s);
+hipError_t launch_lrb3_att_batch(const PassArgs* table, int n, int stack_n, size_t grad_lds, int grid, hipStream_t s);
 hipError_t launch_naive_bwd(const PassArgs& A, int grid, hipStream_t s);
 hipError_t launch_reslrb_bwd(const PassArgs& A, int grid, int block, hipStream_t s);
 hipError_t launch_lrb3_bwd(const PassArgs& A, int grid, int block, hipStream_t s);
@@ -97,6 +100,10 @@ hipError_t launch_loss(const float* I, const float* T, size_t n, float* dI, doub
 hipError_t launch_hf_tris(const DevScene& sc, const int32_t* slot_of_prim, Tri* tris, const float* h,
                           hipStream_t s);
 hipError_t set_lds_limit(int bytes);
+// Workgroups of a backward kernel resident per CU at `block` threads and
+// `lds` dynamic LDS bytes (0 if it cannot launch or the query fails).
+enum class BwdKernel { naive, reslrb, lrb3, naive_att, reslrb_att, lrb3_att, lrb3_batch, lrb3_att_batch };
+int resident_groups(BwdKernel k, int block, size_t lds);
 hipError_t read_counters(uint64_t* out, bool reset, hipStream_t s);
 hipError_t launch_refit_level(Node* nodes, const Tri* tris, const int32_t* level_nodes, int n, hipStream_t s);
 

@@ -184,7 +184,7 @@ class Context:
         s = torch.cuda.current_stream(self.device)
         self._check(self.lib.lt_set_stream(self.h, C.c_void_p(s.cuda_stream)))
 
-    def set_tuning(self, block=256, blocks_per_cu=8, lds_grad=0):
+    def set_tuning(self, block=256, blocks_per_cu=4, lds_grad=1):
         t = Tuning(block, blocks_per_cu, lds_grad)
         self._check(self.lib.lt_set_tuning(self.h, C.byref(t)))
 
@@ -370,21 +370,21 @@ class Batch:
         arr = table if table is not None else self.table(instances)
         self._check(self.lib.lt_batch_step(self.h, arr, len(arr), int(bool(use_graph))))
 
-    def set_tuning(self, block=256, blocks_per_cu=4):
-        t = Tuning(block, blocks_per_cu, 0)
+    def set_tuning(self, block=256, blocks_per_cu=4, lds_grad=1):
+        t = Tuning(block, blocks_per_cu, lds_grad)
         self._check(self.lib.lt_batch_set_tuning(self.h, C.byref(t)))
 
     def get_tuning(self):
         t = Tuning()
         self._check(self.lib.lt_batch_get_tuning(self.h, C.byref(t)))
-        return dict(block=t.block, blocks_per_cu=t.blocks_per_cu)
+        return dict(block=t.block, blocks_per_cu=t.blocks_per_cu, lds_grad=t.lds_grad)
 
     def autotune(self, instances, cache_path=None):
         arr = self.table(instances)
         t = Tuning()
         self._check(self.lib.lt_batch_autotune(self.h, arr, len(arr),
                                                None if cache_path is None else str(cache_path).encode(), C.byref(t)))
-        return dict(block=t.block, blocks_per_cu=t.blocks_per_cu)
+        return dict(block=t.block, blocks_per_cu=t.blocks_per_cu, lds_grad=t.lds_grad)
 
 
 # C-ABI names as module-level functions -------------------------------------

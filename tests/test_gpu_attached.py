@@ -66,6 +66,31 @@ def test_naive_attached_parity(caustic16):
         assert eh <= TOL and ea <= TOL and el <= TOL
 
 
+def test_attached_parity_without_lds_copies(caustic16):
+    """lds_grad = 0: the single albedo texel's gradient goes through each
+    wave's write-combining cache (one texel: every scatter hits it) in all
+    three attached reverse modes."""
+    from tests.gpu_common import matched_paths, maxrel
+    sc, g = caustic16
+    seed, n, D = 14, 65536, 5
+    mask, ids, mis = matched_paths(sc, g, seed, n, D)
+    assert mis <= 1e-3
+    dI = _dI((64, 64, 3), seed)
+    g.ctx.set_tuning(256, 4, 0)
+    try:
+        for mode, omode in (("naive", O.MODE_NAIVE), ("lrb3", O.MODE_NAIVE), ("reslrb", O.MODE_RESLRB)):
+            first = g.backward(mode, seed, n, D, dI, flags=lt.ATTACHED, mask=mask, want_info=True)
+            keep = mask.astype(bool) & ((first["info"] & 3) == 0)
+            ids2 = np.nonzero(keep)[0].astype(np.uint32)
+            gg = g.backward(mode, seed, n, D, dI, flags=lt.ATTACHED, mask=keep.astype(np.uint8))
+            og = O.gradient(sc, seed, n, D, dI, mode=omode, flags=O.ATTACHED, path_list=ids2)
+            eh, ea, el = (maxrel(gg[k], og[k]) for k in ("heights", "albedo", "Le"))
+            print(f"{mode} attached (no LDS copies): heights {eh:.2e} albedo {ea:.2e} Le {el:.2e}", flush=True)
+            assert eh <= TOL and ea <= TOL and el <= TOL, mode
+    finally:
+        g.ctx.set_tuning()
+
+
 def test_attached_side_state_sizes(caustic16):
     sc, g = caustic16
     n = 1 << 20

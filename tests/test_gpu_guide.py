@@ -230,7 +230,8 @@ def test_trained_guide_reduces_gradient_variance():
 
     def estimate():
         gs = []
-        grad(9999)  # warm-up outside the timed loop
+        for k in range(4):  # warm-up (clocks, first launches) outside the timed loop
+            grad(9990 + k)
         torch.cuda.synchronize(); t0 = time.perf_counter()
         for k in range(K):
             gs.append(grad(10000 + k).double().clone())
@@ -248,7 +249,9 @@ def test_trained_guide_reduces_gradient_variance():
         grad(50000 + it, contrib)
         ctx.guide_emit(ctx.args(50000 + it, 1 << 18, D), g.params(), smp, contrib)
         ctx.guide_grad(w, smp, gr, None)
-        ctx.guide_adam(w, gr, m, v, it, 5e-3)
+        # Adam step 2e-3: at 5e-3 a quarter of the training runs overshoot
+        # into lobes worse than cosine emission
+        ctx.guide_adam(w, gr, m, v, it, 2e-3)
     g1, t1 = estimate()
     g.set_guide(None)
     v0, v1 = g0.var(0).sum().item(), g1.var(0).sum().item()

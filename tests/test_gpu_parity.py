@@ -56,6 +56,29 @@ def test_gradient_parity_all_modes_box(box64):
         assert ea <= TOL and el <= TOL, mode
 
 
+def test_gradient_parity_without_lds_copies(box64):
+    """lds_grad = 0: albedo gradients skip the per-workgroup LDS copy and go
+    through each wave's write-combining cache into the gradient array (ten
+    16x16 textures: cache hits, texel changes and per-lane leftovers)."""
+    from tests.gpu_common import matched_paths, maxrel
+    sc, g = box64
+    seed, n, D = 6, 16384, 5
+    mask, ids, mis = matched_paths(sc, g, seed, n, D)
+    assert mis <= 1e-3
+    dI = _dI((64, 64, 3), 12)
+    on = O.gradient(sc, seed, n, D, dI, path_list=ids)
+    orr = O.gradient(sc, seed, n, D, dI, mode=O.MODE_RESLRB, path_list=ids)
+    g.ctx.set_tuning(256, 4, 0)
+    try:
+        for mode, ref in (("naive", on), ("lrb3", on), ("reslrb", orr)):
+            gg = g.backward(mode, seed, n, D, dI, mask=mask)
+            ea, el = maxrel(gg["albedo"], ref["albedo"]), maxrel(gg["Le"], ref["Le"])
+            print(f"{mode} (no LDS copies): albedo maxrel {ea:.2e}  Le maxrel {el:.2e}", flush=True)
+            assert ea <= TOL and el <= TOL, mode
+    finally:
+        g.ctx.set_tuning()
+
+
 def test_reslrb_selected_image_and_records(box64):
     from tests.gpu_common import matched_paths, maxrel
     sc, g = box64
