@@ -22,7 +22,7 @@ HBM_PEAK_GBS = 8000.0
 B_NODE, B_TRI, B_SPLAT, B_GATHER, B_GRAD, B_TAPE = 64, 48, 96, 48, 8, 32
 
 
-KERNEL_SOURCES = ["lt_common.h", "lt_device.h", "lt_launch.h", "lt_kernels.hip", "lt_attached.inc"]
+KERNEL_SOURCES = ["lt_common.h", "lt_device.h", "lt_launch.h", "lt_kernels.hip", "lt_attached.inc", "lt_api.cpp"]
 
 
 def profiled_traffic(name, field="traffic_bytes_per_launch"):

@@ -17,9 +17,10 @@ using namespace lt;
 namespace {
 
 // ------------------------------------------------------------ BVH builder
-// Binned SAH over triangle bounds (16 bins per axis), leaves of at most 4
-// triangles, median split below a depth that keeps the traversal stack
-// within kStackMax.
+// Binned SAH over triangle bounds (16 bins per axis); a node of at most 4
+// triangles becomes a leaf when the SAH cost of its best split is no lower;
+// median split below a depth that keeps the traversal stack within
+// kStackMax.
 struct BPrim { float lo[3], hi[3], c[3]; int id; };
 struct BNode { float lo[3], hi[3]; int left = -1, right = -1, first = 0, count = 0; };
 
@@ -49,7 +50,7 @@ struct Builder {
     }
     max_depth = std::max(max_depth, depth);
     int n = e - b;
-    if (n <= 4) { nd.first = b; nd.count = n; bn[idx] = nd; return idx; }
+    if (n <= 1) { nd.first = b; nd.count = n; bn[idx] = nd; return idx; }
     int mid = -1;
     if (depth < kStackMax - 8) {
       const int NB = 16;
@@ -75,6 +76,12 @@ struct Builder {
           float cost = area(llo, lhi) * nl + area(rlo, rhi) * nr;
           if (cost < best) { best = cost; best_axis = a; best_bin = s; }
         }
+      }
+      // SAH termination: a leaf of up to 4 costs n intersection tests; a
+      // split costs one node visit (two box tests) plus the area-weighted
+      // tests below it
+      if (n <= 4 && (best_axis < 0 || 1.0f + best / std::max(area(nd.lo, nd.hi), 1e-30f) >= (float)n)) {
+        nd.first = b; nd.count = n; bn[idx] = nd; return idx;
       }
       if (best_axis >= 0) {
         float ext = chi[best_axis] - clo[best_axis];
@@ -213,12 +220,17 @@ int persistent_grid(const lt_ctx* c, int64_t n, int block) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Heights gradients go to a per-workgroup LDS copy when it fits next to the
-// traversal stack (256-thread workgroups).
-int hgrad_in_lds(const lt_ctx* c, const float* g_heights, bool with_stack) {
+// traversal stacks (256-thread workgroups).  The replay kernels (arithmetic-
+// heavy, latency-bound at two waves per SIMD) take it only when it costs no
+// resident workgroups per CU; the tape walk (little arithmetic per scatter,
+// bound by the atomics) takes it whenever it fits.
+int hgrad_in_lds(const lt_ctx* c, const float* g_heights, BwdKernel k, size_t stack, bool keep_residency) {
   if (!g_heights || c->dsc.hf_G < 2) return 0;
-  size_t need = (size_t)c->dsc.hf_G * c->dsc.hf_G * sizeof(float) +
-                (with_stack ? (size_t)c->dsc.stack_n * 256 * sizeof(int) : 0);
-  return need <= (size_t)c->lds_max ? 1 : 0;
+  size_t need = (size_t)c->dsc.hf_G * c->dsc.hf_G * sizeof(float);
+  if (stack + need > (size_t)c->lds_max) return 0;
+  if (!keep_residency) return 1;
+  int with = resident_groups(k, 256, stack + need);
+  return with > 0 && with >= resident_groups(k, 256, stack) ? 1 : 0;
 }
 
 // Albedo gradients go to a per-workgroup LDS copy (lt_tuning.lds_grad) when
@@ -766,7 +778,7 @@ lt_status lt_backward_naive(lt_ctx* c, const lt_trace_args* a, const lt_params* 
   int grid = (int)std::max<int64_t>(1, std::min<int64_t>((a->n_paths + 255) / 256, (int64_t)c->n_cu * 16));
   if (a->flags & LT_ATTACHED) {
     A.emit_d = (float*)(sb + L.emit);
-    A.hgrad_lds = hgrad_in_lds(c, g->heights, false);
+    A.hgrad_lds = hgrad_in_lds(c, g->heights, BwdKernel::naive_att, 0, false);
     A.agrad_lds = agrad_in_lds(c, BwdKernel::naive_att, 256, hgrad_lds_bytes(c, A.hgrad_lds));
     if ((st = c->hip(launch_naive_att_bwd(A, grid, c->stream), "naive attached backward")) != LT_OK) return st;
   } else {
@@ -788,7 +800,7 @@ lt_status lt_backward_reslrb(lt_ctx* c, const lt_trace_args* a, const lt_params*
   if (a->flags & LT_ATTACHED) {
     A.res_att_in = (const ResRecAtt*)((const char*)records + L.res);
     int grid = persistent_grid(c, a->n_paths, 256);
-    A.hgrad_lds = hgrad_in_lds(c, g->heights, true);
+    A.hgrad_lds = hgrad_in_lds(c, g->heights, BwdKernel::reslrb_att, stack_lds(c, 256), true);
     A.agrad_lds = agrad_in_lds(c, BwdKernel::reslrb_att, 256, stack_lds(c, 256) + hgrad_lds_bytes(c, A.hgrad_lds));
     if ((st = c->hip(launch_reslrb_att(A, grid, c->stream), "reslrb attached backward")) != LT_OK) return st;
     return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
@@ -809,7 +821,7 @@ lt_status lt_backward_lrb3(lt_ctx* c, const lt_trace_args* a, const lt_params* p
   A.contrib = a->path_contrib;
   if (a->flags & LT_ATTACHED) {
     int grid = persistent_grid(c, a->n_paths, 256);
-    A.hgrad_lds = hgrad_in_lds(c, g->heights, true);
+    A.hgrad_lds = hgrad_in_lds(c, g->heights, BwdKernel::lrb3_att, stack_lds(c, 256), true);
     A.agrad_lds = agrad_in_lds(c, BwdKernel::lrb3_att, 256, stack_lds(c, 256) + hgrad_lds_bytes(c, A.hgrad_lds));
     if ((st = c->hip(launch_lrb3_att(A, grid, c->stream), "lrb3 attached backward")) != LT_OK) return st;
   } else {
