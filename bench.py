@@ -222,6 +222,11 @@ def main():
         batch = bench_batch(lt, scenes, dev, stream)
         batch_small = bench_batch(lt, scenes, dev, stream, path_scale=1.0 / 64, reps=4)
 
+    # ---- guided + batched against the plain GPU tracer
+    guided_batch = None
+    if not (args.no_batch or args.no_guide):
+        guided_batch = bench_guided_batch(lt, scenes, dev, stream)
+
     # ---- CPU baseline: the FP64 oracle, forward + naive backward, on a sample
     cpu = None
     if not args.no_cpu:
@@ -266,6 +271,7 @@ def main():
         "guide_smooth_slab": guide_smooth,
         "batch": batch,
         "batch_small_instances": batch_small,
+        "guided_batch": guided_batch,
     }
     print(json.dumps(out), flush=True)
 
@@ -523,6 +529,143 @@ def bench_batch(lt, scenes, dev, stream, n=48, seed=7, reps=2, path_scale=1.0):
            "speedup": round(t_inst / t_graph, 3), "tuning": tune, "autotune_s": round(t_tune, 2)}
     print(f"# batch: per-instance {t_inst:.1f} ms, batched {t_eager:.1f} ms (eager) / {t_graph:.1f} ms (graph), "
           f"speedup {t_inst / t_graph:.3f}, tuning {tune}", file=sys.stderr, flush=True)
+    return out
+
+
+def bench_guided_batch(lt, scenes, dev, stream, n=12, seed=11, iters=50, K=16, n_train=1 << 18, lr=2e-3):
+    """Guided + batched against the plain GPU tracer.  n smooth-slab caustic
+    instances (sizes and scenes from a seed) take optimisation steps
+    (forward, L2 loss and image adjoint, attached LRB-3 backward).  Plain:
+    per-instance calls with cosine emission.  Guided + batched: every
+    instance's guide is first trained online on its own per-path gradient
+    magnitudes (per-instance calls, `iters` steps; reported apart, as a cost
+    an optimisation pays once), then the steps run as one batched hipGraph
+    replay with guided emission.  Per instance: the heights-gradient variance
+    over K seeds (each step with its own image and adjoint); per step: the
+    time of all instances.  Gain = geometric mean over instances of
+    (variance x time) plain / guided-batched; the robust gain uses the median
+    per-height variance instead of the sum."""
+    import tempfile
+
+    import numpy as np
+    import torch
+
+    f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32), device=dev).contiguous()
+    specs = scenes.guided_batch_instances(n, seed)
+    insts = []
+    for sp in specs:
+        sc = scenes.caustic_scene(G=sp["G"], width=sp["film"], height=sp["film"], seed=sp["scene_seed"],
+                                  target_seed=sp["target_seed"])
+        ctx = lt.Context(0).scene_upload(sc)
+        d = dict(ctx=ctx, seed=0, n_paths=sp["n_paths"], depth=sp["depth"], attached=True, albedo=f32(sc["albedo"]),
+                 Le=f32(sc["Le"]), heights=f32(sc["heights"]), guide=None)
+        tgt = torch.empty((sp["film"], sp["film"], 3), dtype=torch.float32, device=dev)
+        ctx.trace(ctx.args(0x7A6, 1 << 22, sp["depth"], lt.ATTACHED), ctx.params(d["albedo"], d["Le"],
+                  f32(sc["heights_target"])), tgt)
+        d.update(target=tgt, image=torch.empty_like(tgt), d_image=torch.empty_like(tgt),
+                 loss=torch.zeros(1, dtype=torch.float32, device=dev), g_albedo=torch.zeros_like(d["albedo"]),
+                 g_Le=torch.zeros_like(d["Le"]), g_heights=torch.zeros_like(d["heights"]))
+        insts.append(d)
+    torch.cuda.synchronize()
+    seed_of = lambda s, k: s + 7919 * k
+
+    def zero():
+        for d in insts:
+            d["g_albedo"].zero_(); d["g_Le"].zero_(); d["g_heights"].zero_()
+
+    def per_instance(s, contrib=None):
+        zero()
+        for k, d in enumerate(insts):
+            ctx = d["ctx"]
+            a = ctx.args(seed_of(s, k), d["n_paths"], d["depth"], lt.ATTACHED,
+                         contrib=None if contrib is None else contrib[k])
+            p = ctx.params(d["albedo"], d["Le"], d["heights"], d["guide"])
+            ctx.trace(a, p, d["image"])
+            ctx.loss_l2(d["image"], d["target"], d["d_image"], d["loss"])
+            ctx.backward_lrb3(a, p, d["d_image"], d["g_albedo"], d["g_Le"], d["g_heights"])
+
+    b = lt.Batch(0)
+
+    def batched(s):
+        zero()
+        for k, d in enumerate(insts):
+            d["seed"] = seed_of(s, k)
+        b.step(insts, use_graph=True)
+
+    def timed(fn, reps=4):
+        fn(80000)
+        ts = []
+        for r in range(reps):
+            torch.cuda.synchronize(); t0 = time.perf_counter()
+            fn(81000 + 1000 * r)
+            torch.cuda.synchronize(); ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)) * 1e3
+
+    def measure(fn):
+        gs, ts = [[] for _ in insts], []
+        fn(90000)
+        for r in range(K):
+            torch.cuda.synchronize(); t0 = time.perf_counter()
+            fn(100000 + 1000 * r)
+            torch.cuda.synchronize(); ts.append(time.perf_counter() - t0)
+            for k, d in enumerate(insts):
+                gs[k].append(d["g_heights"].double().clone())
+        return [torch.stack(g) for g in gs], float(np.median(ts)) * 1e3
+
+    g0, t0 = measure(per_instance)            # plain: cosine emission, per-instance calls
+    b.autotune(insts, os.path.join(tempfile.gettempdir(), "lt_guided_batch_tuning.json"))
+    t_cos_batched = timed(batched)
+    # train every instance's guide on its own gradient-magnitude signal
+    contrib = [torch.zeros(d["n_paths"], dtype=torch.float32, device=dev) for d in insts]
+    opt = []
+    for d in insts:
+        d["guide"] = f32(scenes.guide_weights())
+        w = d["guide"]
+        opt.append(dict(m=torch.zeros_like(w), v=torch.zeros_like(w), g=torch.zeros_like(w),
+                        smp=torch.zeros((min(n_train, d["n_paths"]), 12), dtype=torch.float32, device=dev)))
+    torch.cuda.synchronize(); tt0 = time.perf_counter()
+    for it in range(1, iters + 1):
+        s = 60000 + 1000 * it
+        per_instance(s, contrib)
+        for k, d in enumerate(insts):
+            ctx, o = d["ctx"], opt[k]
+            p = ctx.params(d["albedo"], d["Le"], d["heights"], d["guide"])
+            ctx.guide_emit(ctx.args(seed_of(s, k), o["smp"].shape[0], d["depth"]), p, o["smp"], contrib[k])
+            ctx.guide_grad(d["guide"], o["smp"], o["g"], None)
+            ctx.guide_adam(d["guide"], o["g"], o["m"], o["v"], it, lr)
+    torch.cuda.synchronize(); train_s = time.perf_counter() - tt0
+    t_guided_inst = timed(per_instance)
+    g1, t1 = measure(batched)                 # guided + batched (graph replays)
+    for d in insts:
+        d["guide"] = None
+    ratios, robust, z2 = [], [], []
+    for a, c in zip(g0, g1):
+        v0, v1 = a.var(0), c.var(0)
+        ratios.append(v1.sum().item() / v0.sum().item())
+        robust.append(v1.median().item() / max(v0.median().item(), 1e-300))
+        se = torch.sqrt(v0 / K + v1 / K)
+        ok = se > 0
+        z = (c.mean(0) - a.mean(0))[ok] / se[ok]
+        z2.append((z * z).mean().item())
+    gm = lambda xs: float(np.exp(np.mean(np.log(np.asarray(xs)))))
+    gain = gm([1.0 / r for r in ratios]) * t0 / t1
+    rgain = gm([1.0 / r for r in robust]) * t0 / t1
+    total = sum(d["n_paths"] for d in insts)
+    out = {"workload": f"{n} glass-slab caustic instances (heightfields 32^2..96^2, films 128^2..384^2, "
+                       f"{min(d['n_paths'] for d in insts)}..{max(d['n_paths'] for d in insts)} paths, depth 6, "
+                       f"scenes and sizes from seed {seed}); one step each = forward + L2 loss + attached LRB-3 "
+                       f"backward; heights-gradient variance over {K} seeds",
+           "paths_per_step": total, "plain_per_instance_cosine_ms": round(t0, 2),
+           "batched_cosine_ms": round(t_cos_batched, 2), "per_instance_guided_ms": round(t_guided_inst, 2),
+           "batched_guided_ms": round(t1, 2), "guide_training_s": round(train_s, 2), "training_steps": iters,
+           "variance_ratio_geomean": round(gm(ratios), 4), "median_coord_variance_ratio_geomean": round(gm(robust), 4),
+           "variance_ratio_per_instance": [round(r, 3) for r in ratios],
+           "efficiency_gain": round(gain, 3), "robust_efficiency_gain": round(rgain, 3),
+           "bias_mean_z2": round(float(np.mean(z2)), 3)}
+    print(f"# guided+batched ({n} slabs): plain {t0:.1f} ms/step, batched cosine {t_cos_batched:.1f}, "
+          f"guided per-instance {t_guided_inst:.1f}, guided batched {t1:.1f}; variance ratio (geomean) "
+          f"{gm(ratios):.3f}, median-coordinate {gm(robust):.3f}; gain {gain:.2f}x (robust {rgain:.2f}x); "
+          f"bias z^2 {np.mean(z2):.3f}; training {train_s:.1f} s", file=sys.stderr, flush=True)
     return out
 
 

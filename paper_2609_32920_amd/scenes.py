@@ -234,6 +234,22 @@ def batched_instances(n=48, seed=7):
     return out
 
 
+def guided_batch_instances(n=12, seed=11):
+    """Size table of a batch of smooth-slab caustic instances for the guided
+    batch: heightfield side G log-uniform in [32, 96], film side log-uniform
+    in [128, 384] rounded to a multiple of 16, path count log-uniform in
+    [1M, 4M], depth 6; each instance has its own scene and target seeds."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        G = int(round(math.exp(rng.uniform(math.log(32), math.log(96)))))
+        film = int(round(math.exp(rng.uniform(math.log(128), math.log(384))) / 16.0)) * 16
+        paths = int(round(math.exp(rng.uniform(math.log(1 << 20), math.log(4 << 20)))))
+        out.append(dict(G=G, film=film, n_paths=paths, depth=6, scene_seed=SCENE_SEED + 101 * (k + 1),
+                        target_seed=TARGET_SEED + 7 * (k + 1)))
+    return out
+
+
 GUIDE_SEED = 0x6D6C70
 GUIDE_NPARAMS = 11433   # W1[64][6] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[41][64] b4[41]
 
