@@ -239,6 +239,14 @@ __device__ __forceinline__ void flush_le(const PassArgs& A, double g0, double g1
   }
 }
 
+// Reciprocal emitter radiance, zero where a channel is zero: the emitter
+// gradient of a path is its adjoint sum times this (computed once, not a
+// double division per path).
+struct D3R { double x, y, z; };
+__device__ __forceinline__ D3R recip_le(f3 Le) {
+  return {Le.x > 0.f ? 1.0 / Le.x : 0.0, Le.y > 0.f ? 1.0 / Le.y : 0.0, Le.z > 0.f ? 1.0 / Le.z : 0.0};
+}
+
 // Vertex 0 of a path.  With a guide the emitted direction and its density q
 // come from the per-path record of the guide pass (same position draw);
 // beta_1 = L_e * A cos / q, the density held fixed in every derivative.
@@ -430,6 +438,7 @@ __global__ void __launch_bounds__(1024) k_reslrb_bwd(PassArgs A) {
   Ray r;
   f3 w = {0.f, 0.f, 0.f};
   const f3 Le = ld3(A.Le);
+  const D3R iLe = recip_le(Le);
   double gl0 = 0.0, gl1 = 0.0, gl2 = 0.0;
   while (true) {
     refill(A, alive, exhausted, path, [&](uint32_t) {});
@@ -445,8 +454,7 @@ __global__ void __launch_bounds__(1024) k_reslrb_bwd(PassArgs A) {
         R = min(rec.R, A.D);
         f3 Lb = gather(A.sc, A.dI, rec.ux, rec.uy);
         w = mul(Lb, mk(rec.S[0], rec.S[1], rec.S[2]));
-        add_le(A, gl0, gl1, gl2, Le.x > 0.f ? (double)w.x / Le.x : 0.0, Le.y > 0.f ? (double)w.y / Le.y : 0.0,
-               Le.z > 0.f ? (double)w.z / Le.z : 0.0);
+        add_le(A, gl0, gl1, gl2, (double)w.x * iLe.x, (double)w.y * iLe.y, (double)w.z * iLe.z);
         emit_path(A, path, r);
         j = 1;
       }
@@ -492,6 +500,7 @@ __device__ __forceinline__ void lrb3_run(const PassArgs& A, int* lds) {
   f3 beta = {0.f, 0.f, 0.f};
   double d0 = 0.0, d1 = 0.0, d2 = 0.0;  // delta_total, then delta_rem
   const f3 Le = ld3(A.Le);
+  const D3R iLe = recip_le(Le);
   double gl0 = 0.0, gl1 = 0.0, gl2 = 0.0;
   while (true) {
     refill(A, alive, exhausted, path, [&](uint32_t p) { if (A.contrib) A.contrib[p] = 0.f; });
@@ -525,8 +534,8 @@ __device__ __forceinline__ void lrb3_run(const PassArgs& A, int* lds) {
           double g0 = a0, g1 = a1, g2 = a2;
           if (ev.cont) { g0 += d0; g1 += d1; g2 += d2; }
           texel = ev.texel;
-          gv = {ev.rho.x > 0.f ? (float)(g0 / ev.rho.x) : 0.f, ev.rho.y > 0.f ? (float)(g1 / ev.rho.y) : 0.f,
-                ev.rho.z > 0.f ? (float)(g2 / ev.rho.z) : 0.f};
+          gv = {ev.rho.x > 0.f ? (float)g0 / ev.rho.x : 0.f, ev.rho.y > 0.f ? (float)g1 / ev.rho.y : 0.f,
+                ev.rho.z > 0.f ? (float)g2 / ev.rho.z : 0.f};
           has = true;
         }
         if (ev.cont) beta = mul(beta, ev.rho);
@@ -534,8 +543,7 @@ __device__ __forceinline__ void lrb3_run(const PassArgs& A, int* lds) {
       if (ev.cont) {
         ++j;
       } else if (phase == 2 && klast > 0 && (d0 != 0.0 || d1 != 0.0 || d2 != 0.0)) {  // consuming replay
-        add_le(A, gl0, gl1, gl2, Le.x > 0.f ? d0 / Le.x : 0.0, Le.y > 0.f ? d1 / Le.y : 0.0,
-               Le.z > 0.f ? d2 / Le.z : 0.0);
+        add_le(A, gl0, gl1, gl2, d0 * iLe.x, d1 * iLe.y, d2 * iLe.z);
         // the path's adjoint-weighted contribution |delta_total|
         if (A.contrib) A.contrib[path] = (float)(fabs(d0) + fabs(d1) + fabs(d2));
         phase = 3; j = 0;
