@@ -27,9 +27,9 @@ KERNEL_SOURCES = ["lt_common.h", "lt_device.h", "lt_launch.h", "lt_kernels.hip",
 
 def profiled_traffic(name, field="traffic_bytes_per_launch"):
     """A figure from the committed rocprofv3 summary profiles/<name>: HBM bytes
-    per launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy) or a VALU
-    issue fraction; None when the kernel sources changed since the counters
-    were taken."""
+    per launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), a VALU
+    issue fraction, an L2 hit rate or the resident waves per SIMD; None when
+    the kernel sources changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
@@ -167,6 +167,10 @@ def main():
                     "kernel": "k_lrb3_bwd", "bytes_per_path": round(bpp, 1),
                     "valu_issue_frac_profiled": profiled_traffic("k_lrb3_caustic128_box256_valu.txt",
                                                                  "valu_issue_frac_k_lrb3_bwd"),
+                    "l2_hit_rate_profiled": profiled_traffic("k_lrb3_caustic128_box256_valu.txt",
+                                                             "l2_hit_rate_k_lrb3_bwd"),
+                    "waves_per_simd_profiled": profiled_traffic("k_lrb3_caustic128_box256_valu.txt",
+                                                                "waves_per_simd_k_lrb3_bwd"),
                     "launch_ms": round(t_launch * 1e3, 4),
                     "events_per_path": {k: round(v / sample, 3) for k, v in counts["lrb3"].items()}}
         print(f"# lrb3 algorithmic bytes/path {bpp:.0f}  achieved {achieved:.0f} GB/s", file=sys.stderr)
@@ -343,6 +347,10 @@ def bench_caustic(lt, scenes, dev, stream, bytes_per_path_fn, G=128, film=512, N
                                 "traffic": profiled_traffic("k_lrb3_att_caustic128_512_d6_16M.txt"),
                                 "valu_issue_frac_profiled": profiled_traffic("k_lrb3_caustic128_box256_valu.txt",
                                                                              "valu_issue_frac_k_lrb3_att"),
+                                "l2_hit_rate_profiled": profiled_traffic("k_lrb3_caustic128_box256_valu.txt",
+                                                                         "l2_hit_rate_k_lrb3_att"),
+                                "waves_per_simd_profiled": profiled_traffic("k_lrb3_caustic128_box256_valu.txt",
+                                                                            "waves_per_simd_k_lrb3_att"),
                                 "events_per_path": {k: round(v / sample, 3) for k, v in c.items()}}
         del cctx
     except Exception as e:
