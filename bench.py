@@ -61,7 +61,10 @@ def parse():
     ap.add_argument("--no-guide", action="store_true", help="skip the learned-guide workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 48-instance workload")
     ap.add_argument("--guide-iters", type=int, default=40, help="online training iterations of the guide")
-    ap.add_argument("--guide-seeds", type=int, default=12, help="seeds per gradient-variance estimate")
+    ap.add_argument("--guide-seeds", type=int, default=32, help="seeds per gradient-variance estimate")
+    ap.add_argument("--ee-seeds", type=int, default=16, help="seeds per equal-error variance estimate")
+    ap.add_argument("--no-inverse", action="store_true", help="skip the heightfield inverse-rendering loop")
+    ap.add_argument("--inverse-iters", type=int, default=200, help="Adam iterations of the inverse-rendering loop")
     ap.add_argument("--cpu-paths", type=int, default=1 << 22, help="paths in the CPU-oracle sample")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="least CPU-oracle time (whole steps)")
     ap.add_argument("--copy-ref", action="store_true",
@@ -208,15 +211,55 @@ def main():
                                          "workspace_bytes": ctx.workspace_bytes(a)}
         torch.cuda.synchronize()
 
+    # ---- equal-error throughput: paths/s x (naive-AD variance / the method's
+    # variance), the gradient variance summed over parameters across seeds
+    # with one fixed image adjoint (only the estimators differ)
+    equal = None
+    if not args.no_sweep and f"naive_d{D}" in sweep:
+        equal = {}
+        dI_fix = dI.clone()
+        for mode in ("naive", "reslrb", "lrb3"):
+            rec = lt.RECORD_TAPE if mode == "naive" else lt.RECORD_RESERVOIR if mode == "reslrb" else 0
+            nb = ctx.side_state_bytes(ctx.args(4000, N, D, rec))
+            side = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev) if nb else None
+            gs = []
+            for k in range(args.ee_seeds):
+                a = ctx.args(4000 + k, N, D, rec)
+                ctx.trace(a, p, img, side)
+                g_alb.zero_(); g_le.zero_()
+                if mode == "naive":
+                    ctx.backward_naive(a, p, dI_fix, side, g_alb, g_le)
+                elif mode == "reslrb":
+                    ctx.backward_reslrb(a, p, dI_fix, side, g_alb, g_le)
+                else:
+                    ctx.backward_lrb3(a, p, dI_fix, g_alb, g_le)
+                gs.append(torch.cat([g_alb.flatten(), g_le.flatten()]).double())
+            del side
+            equal[mode] = {"variance": torch.stack(gs).var(0).sum().item()}
+        for mode in equal:
+            ms = sweep[f"{mode}_d{D}"]["ms"]
+            r = equal["naive"]["variance"] / equal[mode]["variance"]
+            equal[mode].update(paths_per_s=round(N / (ms * 1e-3)), variance_ratio_naive_over_method=round(r, 4),
+                               equal_error_paths_per_s=round(N / (ms * 1e-3) * r))
+        print("# equal-error paths/s (D=%d): " % D + ", ".join(
+            f"{m} {v['equal_error_paths_per_s'] / 1e6:.0f}M (variance ratio {v['variance_ratio_naive_over_method']:.3f})"
+            for m, v in equal.items()), file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+
     # ---- attached workload: caustic heightfield slab (gradients w.r.t. heights)
     caustic = None
     if not args.no_caustic:
         caustic = bench_caustic(lt, scenes, dev, stream, bytes_per_path)
 
+    # ---- heightfield inverse rendering: loss against time per reverse mode
+    inverse = None
+    if not (args.no_caustic or args.no_inverse):
+        inverse = bench_inverse(lt, scenes, dev, stream, iters=args.inverse_iters)
+
     # ---- learned guide: gradient variance x time, guided vs cosine emission
     guide = guide_smooth = None
     if not args.no_guide:
-        guide = bench_guide(lt, scenes, dev, stream, iters=args.guide_iters, K=args.guide_seeds)
+        guide = bench_guide(lt, scenes, dev, stream, iters=args.guide_iters, K=args.guide_seeds, lr=2e-3)
         guide_smooth = bench_guide(lt, scenes, dev, stream, G=64, film=256, N=1 << 22, D=6, iters=60, K=16,
                                    n_train=1 << 18, mode="lrb3", target="gradient", lr=2e-3)
 
@@ -232,7 +275,7 @@ def main():
         guided_batch = bench_guided_batch(lt, scenes, dev, stream)
 
     # ---- CPU baseline: the FP64 oracle, forward + naive backward, on a sample
-    cpu = None
+    cpu = cpu1 = None
     if not args.no_cpu:
         from oracle import oracle as O
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
@@ -248,6 +291,14 @@ def main():
         cpu = {"value": round(reps * args.cpu_paths / tc, 1), "unit": "paths/s", "cores": threads, "kind": "oracle",
                "sample": f"first {args.cpu_paths} of the {N} paths (same scene, depth {D}) for {reps} seeds; "
                          f"forward + taped naive-AD backward in FP64, {tc:.2f} s"}
+        n1 = min(args.cpu_paths, 1 << 16)
+        ids1 = np.arange(n1, dtype=np.uint32)
+        t1 = time.perf_counter()
+        O.render(sc, 2000, N, D, path_list=ids1, threads=1)
+        O.gradient(sc, 2000, N, D, dIh, path_list=ids1, threads=1)
+        t1 = time.perf_counter() - t1
+        cpu1 = {"value": round(n1 / t1, 1), "unit": "paths/s", "cores": 1, "kind": "oracle",
+                "sample": f"first {n1} paths, one thread, {t1:.2f} s"}
 
     out = {
         "metric": "differentiated light paths/s (fwd+bwd)",
@@ -269,8 +320,11 @@ def main():
                     "backward": round(float(np.median(bwd)), 4)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_baseline_1thread": cpu1,
         "sweep": sweep,
+        "equal_error": equal,
         "caustic": caustic,
+        "inverse_rendering": inverse,
         "guide": guide,
         "guide_smooth_slab": guide_smooth,
         "batch": batch,
@@ -326,8 +380,10 @@ def bench_caustic(lt, scenes, dev, stream, bytes_per_path_fn, G=128, film=512, N
                 tb.append(e[1].elapsed_time(e[2]))
         del side
         ms = float(np.median(ts))
+        guards = ctx.stats()["guard_triggers"]  # of the last backward
         out[mode] = {"ms": round(ms, 3), "backward_ms": round(float(np.median(tb)), 3),
-                     "paths_per_s": round(N / (ms * 1e-3)), "side_bytes_per_path": round(nb / N, 2)}
+                     "paths_per_s": round(N / (ms * 1e-3)), "side_bytes_per_path": round(nb / N, 2),
+                     "guard_triggers_per_path": round(guards / N, 6)}
         print(f"# caustic {mode}: step {ms:.3f} ms (backward {np.median(tb):.3f} ms)", file=sys.stderr, flush=True)
     # byte model of the attached LRB-3 backward from the counters build
     try:
@@ -441,6 +497,16 @@ def bench_guide(lt, scenes, dev, stream, G=256, film=1024, N=1 << 26, D=8, iters
     ok = se > 0
     z2 = ((g1.mean(0) - g0.mean(0))[ok] / se[ok]) ** 2
     tv0, tv1, mv0, mv1 = v0.sum().item(), v1.sum().item(), v0.median().item(), v1.median().item()
+    # bootstrap over seeds (both sides resampled): how far single heavy-tailed
+    # paths move the summed-variance ratio
+    gen = torch.Generator(device=g0.device)
+    gen.manual_seed(12345)
+    boot = []
+    for _ in range(200):
+        i0 = torch.randint(K, (K,), device=g0.device, generator=gen)
+        i1 = torch.randint(K, (K,), device=g0.device, generator=gen)
+        boot.append(g1[i1].var(0).sum().item() / max(g0[i0].var(0).sum().item(), 1e-300))
+    ci = [round(float(x), 4) for x in np.percentile(boot, [5, 95])]
     cos_share = float((smp[:, 11] == 0).float().mean().item())
     est = "naive-AD" if mode == "naive" else "LRB-3-pass"
     out = {"workload": f"glass heightfield slab {G}x{G} heights, film {film}x{film}, depth {D}, {N} paths per "
@@ -450,15 +516,81 @@ def bench_guide(lt, scenes, dev, stream, G=256, film=1024, N=1 << 26, D=8, iters
            "train_ms_per_iter": round(float(np.median([a + b for a, b in tt])), 3),
            "guide_update_ms": round(float(np.median([b for _, b in tt])), 3),
            "variance_cosine": tv0, "variance_guided": tv1, "variance_ratio": round(tv1 / tv0, 4),
+           "variance_ratio_bootstrap_90": ci,
            "median_coord_variance_ratio": round(mv1 / mv0, 4),
            "efficiency_gain": round((tv0 * t0) / (tv1 * t1), 4),
            "robust_efficiency_gain": round((mv0 * t0) / (mv1 * t1), 4),
            "bias_mean_z2": round(float(z2.mean().item()), 4), "bias_median_z2": round(float(z2.median().item()), 4),
            "seeds": K, "cosine_share_after_training": round(cos_share, 4),
            "nonfinite_dropped_last_iteration": int(dropped)}
-    print(f"# guide G={G}: variance ratio {tv1 / tv0:.3f} (median-coordinate {mv1 / mv0:.3f}), "
+    print(f"# guide G={G}: variance ratio {tv1 / tv0:.3f} (bootstrap 90% {ci[0]:.3f}-{ci[1]:.3f}; "
+          f"median-coordinate {mv1 / mv0:.3f}), "
           f"iteration {t0:.1f} -> {t1:.1f} ms, efficiency gain {out['efficiency_gain']} "
           f"(robust {out['robust_efficiency_gain']}), bias z^2 {out['bias_mean_z2']}", file=sys.stderr, flush=True)
+    return out
+
+
+def bench_inverse(lt, scenes, dev, stream, G=128, film=512, N=1 << 24, D=6, iters=200, lr=1e-4, log_every=20):
+    """Heightfield inverse rendering: Adam on the slab's free heights (the
+    boundary ring stays at zero) toward the image of the seeded sinusoid
+    target heights, one attached backward per iteration, per reverse mode.
+    Loss against time; the Monte Carlo floor is the loss of the target
+    heights themselves rendered with N paths."""
+    import numpy as np
+    import torch
+
+    f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32), device=dev).contiguous()
+    sc = scenes.caustic_scene(G=G, width=film, height=film)
+    ctx = lt.Context(0).scene_upload(sc)
+    albedo, Le, ht = f32(sc["albedo"]), f32(sc["Le"]), f32(sc["heights_target"])
+    free = torch.zeros((G, G), device=dev)
+    free[1:-1, 1:-1] = 1.0
+    free = free.reshape(-1)
+    T = torch.empty((film, film, 3), dtype=torch.float32, device=dev)
+    ctx.trace(ctx.args(0x7A6, 1 << 26, D, lt.ATTACHED), ctx.params(albedo, Le, ht), T)
+    img, dI, loss = torch.empty_like(T), torch.empty_like(T), torch.zeros(1, dtype=torch.float32, device=dev)
+    ctx.trace(ctx.args(4242, N, D, lt.ATTACHED), ctx.params(albedo, Le, ht), img)
+    floor = (img - T).pow(2).mean().item()
+    ga, gl = torch.zeros_like(albedo), torch.zeros_like(Le)
+    out = {"workload": f"glass heightfield slab {G}x{G} heights, film {film}x{film}, depth {D}, {N} paths per "
+                       f"iteration; Adam (lr {lr}) on the free heights toward the image of the sinusoid target "
+                       f"heights (rendered with 2^26 paths), {iters} iterations",
+           "loss_floor": floor}
+    for mode in ("lrb3", "reslrb", "naive"):
+        rec = lt.RECORD_TAPE if mode == "naive" else lt.RECORD_RESERVOIR if mode == "reslrb" else 0
+        nb = ctx.side_state_bytes(ctx.args(0, N, D, lt.ATTACHED | rec))
+        side = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev) if nb else None
+        h = torch.nn.Parameter(f32(sc["heights"]))
+        opt = torch.optim.Adam([h], lr=lr)
+        gh = torch.zeros_like(ht)
+        curve = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for it in range(iters):
+            a = ctx.args(5000 + it, N, D, lt.ATTACHED | rec)
+            p = ctx.params(albedo, Le, h.detach())
+            ctx.trace(a, p, img, side)
+            ctx.loss_l2(img, T, dI, loss)
+            gh.zero_(); ga.zero_(); gl.zero_()
+            if mode == "naive":
+                ctx.backward_naive(a, p, dI, side, ga, gl, gh)
+            elif mode == "reslrb":
+                ctx.backward_reslrb(a, p, dI, side, ga, gl, gh)
+            else:
+                ctx.backward_lrb3(a, p, dI, ga, gl, gh)
+            h.grad = gh * free
+            opt.step()
+            if it % log_every == 0 or it == iters - 1:
+                torch.cuda.synchronize()
+                curve.append([it, round(time.perf_counter() - t0, 3), loss.item()])
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        del side
+        first = next((t for _, t, l in curve if l <= 2.0 * floor), None)
+        out[mode] = {"ms_per_iter": round(total * 1e3 / iters, 3), "loss_first": curve[0][2],
+                     "loss_last": curve[-1][2], "time_to_2x_floor_s": first, "curve": curve}
+        print(f"# inverse {mode}: {total * 1e3 / iters:.1f} ms/iter, loss {curve[0][2]:.3e} -> {curve[-1][2]:.3e} "
+              f"(floor {floor:.3e}), 2x floor after {first} s", file=sys.stderr, flush=True)
     return out
 
 
