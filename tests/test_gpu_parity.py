@@ -219,6 +219,30 @@ def test_memory_cap_rejects_naive_tape_before_launch():
     g.ctx.set_memory_cap(0)
 
 
+def test_out_of_range_arguments_are_rejected_before_launch(box64):
+    """Path counts outside [1, 2^31), depths outside [1, 64], a ResLRB
+    backward without reservoir records and an undersized reservoir buffer
+    are argument errors, reported before anything is enqueued."""
+    sc, g = box64
+    p = g.ctx.params(g.albedo, g.Le)
+    img = torch.full((64, 64, 3), 7.0, device=g.dev)
+    for n, D in ((0, 4), (-5, 4), (1 << 31, 4), (1024, 0), (1024, 65)):
+        with pytest.raises(lt.LTError) as e:
+            g.ctx.trace(g.ctx.args(1, n, D), p, img)
+        assert e.value.status == lt.LT_ERR_ARG, (n, D)
+    dI = torch.zeros_like(img)
+    ga, gl = torch.zeros_like(g.albedo), torch.zeros_like(g.Le)
+    side = torch.zeros(64, dtype=torch.uint8, device=g.dev)
+    with pytest.raises(lt.LTError) as e:  # args without LT_RECORD_RESERVOIR
+        g.ctx.backward_reslrb(g.ctx.args(1, 1024, 4), p, dI, side, ga, gl)
+    assert e.value.status == lt.LT_ERR_ARG
+    with pytest.raises(lt.LTError) as e:  # 64 bytes for 1024 records
+        g.ctx.backward_reslrb(g.ctx.args(1, 1024, 4, lt.RECORD_RESERVOIR), p, dI, side, ga, gl)
+    assert e.value.status == lt.LT_ERR_ARG
+    torch.cuda.synchronize()
+    assert torch.all(img == 7.0) and torch.all(ga == 0) and torch.all(gl == 0)
+
+
 def test_autograd_function_matches_direct_calls(box64):
     sc, g = box64
     alb = g.albedo.clone().requires_grad_(True)
