@@ -5,6 +5,11 @@
 // their path, so paths of uneven length do not idle the SIMD.  All path
 // state lives in registers; the BVH traversal stack lives in LDS.
 #include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "lt_device.h"
 #include "lt_launch.h"
 
@@ -722,6 +727,17 @@ hipError_t set_lds_limit(int bytes) {
 }
 
 int resident_groups(BwdKernel k, int block, size_t lds) {
+  // the answer depends only on the arguments and the device: cache it
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, size_t>, int> memo;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) (void)hipGetLastError();
+  const auto key = std::make_tuple(dev, (int)k, block, lds);
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = memo.find(key);
+    if (it != memo.end()) return it->second;
+  }
   const void* f = nullptr;
   switch (k) {
     case BwdKernel::naive: f = (const void*)k_naive_bwd; break;
@@ -738,6 +754,8 @@ int resident_groups(BwdKernel k, int block, size_t lds) {
     (void)hipGetLastError();
     return 0;
   }
+  std::lock_guard<std::mutex> g(mu);
+  memo[key] = n;
   return n;
 }
 
