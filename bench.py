@@ -334,7 +334,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def bench_caustic(lt, scenes, dev, stream, bytes_per_path_fn, G=128, film=512, N=1 << 24, D=6):
+def bench_caustic(lt, scenes, dev, stream, bytes_per_path_fn, G=128, film=512, N=1 << 24, D=6, ee_seeds=8):
     """Attached workload: glass heightfield slab (G x G heights), film^2,
     depth D, N paths; forward + loss + attached backward per method."""
     import numpy as np
@@ -385,6 +385,36 @@ def bench_caustic(lt, scenes, dev, stream, bytes_per_path_fn, G=128, film=512, N
                      "paths_per_s": round(N / (ms * 1e-3)), "side_bytes_per_path": round(nb / N, 2),
                      "guard_triggers_per_path": round(guards / N, 6)}
         print(f"# caustic {mode}: step {ms:.3f} ms (backward {np.median(tb):.3f} ms)", file=sys.stderr, flush=True)
+    # equal-error form: heights-gradient variance over seeds with one fixed
+    # image adjoint, per method (the paper expects ResLRB close to LRB-3
+    # here: a caustic path has about one sensor connection)
+    dI_fix = dI.clone()
+    var = {}
+    for mode in ("naive", "reslrb", "lrb3"):
+        rec = lt.RECORD_TAPE if mode == "naive" else lt.RECORD_RESERVOIR if mode == "reslrb" else 0
+        nb = ctx.side_state_bytes(ctx.args(0, N, D, lt.ATTACHED | rec))
+        side = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev) if nb else None
+        gs = []
+        for k in range(ee_seeds):
+            a = ctx.args(7000 + k, N, D, lt.ATTACHED | rec)
+            ctx.trace(a, p, img, side)
+            ga.zero_(); gl.zero_(); gh.zero_()
+            if mode == "naive":
+                ctx.backward_naive(a, p, dI_fix, side, ga, gl, gh)
+            elif mode == "reslrb":
+                ctx.backward_reslrb(a, p, dI_fix, side, ga, gl, gh)
+            else:
+                ctx.backward_lrb3(a, p, dI_fix, ga, gl, gh)
+            gs.append(gh.double().clone())
+        del side
+        var[mode] = torch.stack(gs).var(0).sum().item()
+    for mode in var:
+        r = var["naive"] / var[mode]
+        out[mode].update(heights_variance=var[mode], variance_ratio_naive_over_method=round(r, 4),
+                         equal_error_paths_per_s=round(out[mode]["paths_per_s"] * r))
+    print("# caustic equal-error paths/s: " + ", ".join(
+        f"{m} {out[m]['equal_error_paths_per_s'] / 1e6:.0f}M (variance ratio {out[m]['variance_ratio_naive_over_method']:.3f})"
+        for m in var), file=sys.stderr, flush=True)
     # byte model of the attached LRB-3 backward from the counters build
     try:
         sample = 1 << 18
