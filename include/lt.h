@@ -116,7 +116,9 @@ typedef struct {
                                connection validity, lobe and R) */
   uint32_t* path_info;      /* DEVICE [n_paths] or NULL: the attached passes write
                                per-path flags - bit 0: the determinant guard zeroed a
-                               projected adjoint on this path; bit 1: the path has an
+                               projected adjoint on this path (it then zeroes every later
+                               one: the later accumulated Jacobians are singular too);
+                               bit 1: the path has an
                                ill-conditioned vertex (grazing hit, |cos| < 0.02;
                                refraction with cos_t < 0.1; or a segment shorter than
                                0.02 scene units) whose FP32 derivatives carry rounding
@@ -163,7 +165,9 @@ typedef struct {
 
 /* Counters from the last call that produced them. */
 typedef struct {
-  uint64_t guard_triggers;  /* attached: singular accumulated Jacobians zeroed (Sec. 5) */
+  uint64_t guard_triggers;  /* attached: projections through singular accumulated
+                               Jacobians zeroed (Sec. 5), counting the later vertices of a
+                               path once the guard has fired on it */
   uint64_t nonfinite;       /* non-finite values (splats, gradient contributions) dropped
                                before they reach the image or a gradient */
 } lt_stats;
