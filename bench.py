@@ -75,8 +75,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by "
-              "path index across GPUs but multi-GPU runs are not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU execution is not "
+              "implemented (paths would shard by index across GPUs)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
