@@ -301,7 +301,7 @@ def main():
                 "sample": f"first {n1} paths, one thread, {t1:.2f} s"}
 
     out = {
-        "metric": "differentiated light paths/s (fwd+bwd)",
+        "metric": "differentiated light paths/s (fwd+bwd) at fixed gradient error; bytes/path vs depth",
         "value": round(value, 1),
         "unit": "paths/s",
         "n_gpus": 1,
