@@ -33,6 +33,9 @@
  *     counter = (path, vertex, block)), so the same (seed, n_paths,
  *     max_depth, flags, params) gives the same paths and decisions on every
  *     call; only the order of floating-point atomic sums may differ.
+ *   - A context (and a batch runner) is used by one host thread at a time:
+ *     calls on the same handle must not overlap.  Distinct contexts may be
+ *     driven concurrently; each has its own stream, workspace and scene.
  *   - No exception crosses this boundary.
  */
 #ifndef LT_H
