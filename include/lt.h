@@ -336,6 +336,19 @@ lt_status lt_guide_grad(lt_ctx* ctx, const float* guide_w, const lt_guide_sample
 lt_status lt_guide_adam(lt_ctx* ctx, float* w, const float* grad, float* m, float* v, int32_t step, float lr,
                         float beta1, float beta2, float eps);
 
+/* One online training step of the guide, after a pass made with `args` and
+ * guide_w: the guided emission of paths [0, min(args->n_paths, n_samples))
+ * paired with path_contrib (as lt_guide_emit, into samples: DEVICE
+ * [n_samples]), the loss gradient over those samples (as lt_guide_grad,
+ * into grad: DEVICE [LT_GUIDE_NPARAMS]; loss: DEVICE [1] or NULL) and an
+ * Adam step on guide_w in place (as lt_guide_adam; m, v: DEVICE
+ * [LT_GUIDE_NPARAMS], zero before step 1).  All arguments are checked
+ * before anything is enqueued.
+ * Errors: as those three calls. */
+lt_status lt_guide_train_step(lt_ctx* ctx, const lt_trace_args* args, float* guide_w, const float* path_contrib,
+                              lt_guide_sample* samples, int64_t n_samples, float* grad, float* m, float* v,
+                              float* loss, int32_t step, float lr, float beta1, float beta2, float eps);
+
 /* ------------------------------------------------------------------------
  * Batches.  An extension for training many inverse-rendering problems at
  * once (not in the paper).  Instances of uneven scene size, film, path count

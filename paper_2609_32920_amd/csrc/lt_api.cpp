@@ -895,6 +895,30 @@ lt_status lt_guide_adam(lt_ctx* c, float* w, const float* grad, float* m, float*
                 "guide adam");
 }
 
+lt_status lt_guide_train_step(lt_ctx* c, const lt_trace_args* a, float* guide_w, const float* path_contrib,
+                              lt_guide_sample* samples, int64_t n_samples, float* grad, float* m, float* v,
+                              float* loss, int32_t step, float lr, float beta1, float beta2, float eps) {
+  if (!c) return LT_ERR_ARG;
+  // everything the three steps check, before any of them enqueues
+  if (!a || !guide_w || !samples || !grad || !m || !v || n_samples < 1 || step < 1 || !(lr > 0.f) ||
+      !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps >= 0.f))
+    return c->fail(LT_ERR_ARG, "bad guide training-step arguments%s");
+  if (!c->has_scene) return c->fail(LT_ERR_STATE, "no scene uploaded%s");
+  if (a->n_paths < 1 || a->n_paths >= (int64_t)1 << 31) return c->fail(LT_ERR_ARG, "n_paths out of range [1, 2^31)%s");
+  if (c->dsc.em_type != LT_EMIT_QUAD) return c->fail(LT_ERR_UNSUPPORTED, "the emission guide needs an area emitter%s");
+  if (!c->guide_ok) return c->fail(LT_ERR_UNSUPPORTED, "guide kernels could not get their LDS%s");
+  lt_trace_args e = *a;
+  e.n_paths = std::min<int64_t>(a->n_paths, n_samples);
+  int grid = (int)std::min<int64_t>((e.n_paths + 63) / 64, 1024);
+  lt_status st = check_cap(c, (size_t)grid * guide_partial_floats() * sizeof(float));
+  if (st != LT_OK) return st;
+  lt_params p{};
+  p.guide_w = guide_w;
+  if ((st = lt_guide_emit(c, &e, &p, path_contrib, samples)) != LT_OK) return st;
+  if ((st = lt_guide_grad(c, guide_w, samples, e.n_paths, grad, loss)) != LT_OK) return st;
+  return lt_guide_adam(c, guide_w, grad, m, v, step, lr, beta1, beta2, eps);
+}
+
 }  // extern "C"
 
 // ============================================================== batches

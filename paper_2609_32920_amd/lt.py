@@ -9,6 +9,7 @@ The functions carry the C ABI's names (include/lt.h):
   lt_create / lt_scene_upload / lt_trace / lt_loss_l2 /
   lt_backward_naive / lt_backward_reslrb / lt_backward_lrb3 /
   lt_guide_eval / lt_guide_emit / lt_guide_grad / lt_guide_adam /
+  lt_guide_train_step /
   lt_batch_create / lt_batch_step / lt_batch_autotune
 and ``LightTrace`` wraps forward + a chosen reverse mode as a
 ``torch.autograd.Function``.
@@ -119,6 +120,8 @@ def library(path=LIB_PATH):
             "lt_guide_emit": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp, vp], C.c_int),
             "lt_guide_grad": ([vp, vp, vp, C.c_int64, vp, vp], C.c_int),
             "lt_guide_adam": ([vp, vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float], C.c_int),
+            "lt_guide_train_step": ([vp, C.POINTER(TraceArgs), vp, vp, vp, C.c_int64, vp, vp, vp, vp, C.c_int32,
+                                     C.c_float, C.c_float, C.c_float, C.c_float], C.c_int),
             "lt_batch_create": ([C.c_int, vp, C.POINTER(vp)], C.c_int),
             "lt_batch_destroy": ([vp], None),
             "lt_batch_last_error": ([vp], C.c_char_p),
@@ -140,6 +143,7 @@ def exported_symbols():
             "lt_set_memory_cap", "lt_get_stats", "lt_read_counters", "lt_scene_upload", "lt_side_state_bytes",
             "lt_workspace_bytes", "lt_trace", "lt_loss_l2", "lt_backward_naive", "lt_backward_reslrb",
             "lt_backward_lrb3", "lt_guide_eval", "lt_guide_emit", "lt_guide_grad", "lt_guide_adam",
+            "lt_guide_train_step",
             "lt_batch_create", "lt_batch_destroy", "lt_batch_last_error", "lt_batch_step", "lt_batch_set_tuning",
             "lt_batch_get_tuning", "lt_batch_autotune"]
 
@@ -324,6 +328,15 @@ class Context:
         self._check(self.lib.lt_guide_adam(self.h, _ptr(w), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr),
                                            float(beta1), float(beta2), float(eps)))
 
+    def guide_train_step(self, a, guide_w, contrib, samples, grad, m, v, step, lr, loss=None, beta1=0.9,
+                         beta2=0.999, eps=1e-8):
+        """Emission samples paired with contrib, loss gradient and one Adam
+        step on guide_w in place (samples: [n_samples, 12] device float32)."""
+        self._stream()
+        self._check(self.lib.lt_guide_train_step(self.h, C.byref(a), _ptr(guide_w), _ptr(contrib), _ptr(samples),
+                                                 samples.shape[0], _ptr(grad), _ptr(m), _ptr(v), _ptr(loss),
+                                                 int(step), float(lr), float(beta1), float(beta2), float(eps)))
+
 
 class Batch:
     """Runner of batched optimisation steps (lt_batch_*) on torch's current
@@ -430,6 +443,11 @@ def lt_guide_grad(ctx, guide_w, samples, grad, loss=None):
 
 def lt_guide_adam(ctx, w, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return ctx.guide_adam(w, grad, m, v, step, lr, beta1, beta2, eps)
+
+
+def lt_guide_train_step(ctx, a, guide_w, contrib, samples, grad, m, v, step, lr, loss=None, beta1=0.9,
+                        beta2=0.999, eps=1e-8):
+    return ctx.guide_train_step(a, guide_w, contrib, samples, grad, m, v, step, lr, loss, beta1, beta2, eps)
 
 
 def lt_batch_create(device=0):

@@ -192,6 +192,41 @@ def test_adam_step(box):
     np.testing.assert_allclose(tv.cpu().numpy(), ov, rtol=1e-6, atol=1e-7)
 
 
+def test_train_step_equals_its_three_calls():
+    """lt_guide_train_step = lt_guide_emit + lt_guide_grad + lt_guide_adam
+    (all three deterministic: bitwise equal results), and a rejected step
+    writes nothing."""
+    from tests.gpu_common import GpuRun
+    sc = scenes.caustic_scene(G=16, width=64, height=64)
+    g = GpuRun(sc)
+    g.set_guide(scenes.guide_weights())
+    dev = g.dev
+    N, D, n_s = 1 << 16, 4, 20_000
+    contrib = torch.zeros(N, device=dev)
+    img = torch.empty((64, 64, 3), device=dev)
+    g.ctx.trace(g.ctx.args(77, N, D, lt.ATTACHED, contrib=contrib), g.params(), img)
+    a = g.ctx.args(77, N, D)
+    w1, w2 = g.guide.clone(), g.guide.clone()
+    st = [dict(m=torch.zeros_like(w1), v=torch.zeros_like(w1), g=torch.zeros_like(w1),
+               loss=torch.zeros(1, device=dev), smp=torch.zeros((n_s, 12), device=dev)) for _ in range(2)]
+    for step in (1, 2):
+        s0, s1 = st
+        g.ctx.guide_emit(g.ctx.args(77, n_s, D), g.ctx.params(g.albedo, g.Le, g.heights, w1), s0["smp"], contrib)
+        g.ctx.guide_grad(w1, s0["smp"], s0["g"], s0["loss"])
+        g.ctx.guide_adam(w1, s0["g"], s0["m"], s0["v"], step, 2e-3)
+        g.ctx.guide_train_step(a, w2, contrib, s1["smp"], s1["g"], s1["m"], s1["v"], step, 2e-3, loss=s1["loss"])
+    torch.cuda.synchronize()
+    for k in ("smp", "g", "m", "v", "loss"):
+        assert torch.equal(st[0][k], st[1][k]), k
+    assert torch.equal(w1, w2) and not torch.equal(w1, g.guide)
+    before = w2.clone()
+    with pytest.raises(lt.LTError) as e:
+        g.ctx.guide_train_step(a, w2, contrib, st[1]["smp"], st[1]["g"], st[1]["m"], st[1]["v"], 0, 2e-3)
+    assert e.value.status == lt.LT_ERR_ARG
+    torch.cuda.synchronize()
+    assert torch.equal(w2, before)
+
+
 def test_point_emitter_rejects_guide():
     from tests.gpu_common import GpuRun
     sc = scenes.plane_point_light_scene()
