@@ -185,7 +185,7 @@ void lt_destroy(lt_ctx* ctx);
 const char* lt_last_error(const lt_ctx* ctx);
 /* Switch the stream later calls enqueue on. */
 lt_status lt_set_stream(lt_ctx* ctx, void* hip_stream);
-/* Launch shape: NULL restores the defaults {128, 8, 1} (the attached kernels
+/* Launch shape: NULL restores the defaults {128, 10, 1} (the attached kernels
  * keep 256-thread workgroups and take blocks_per_cu only). Errors: LT_ERR_ARG. */
 lt_status lt_set_tuning(lt_ctx* ctx, const lt_tuning* tuning);
 lt_status lt_get_tuning(const lt_ctx* ctx, lt_tuning* out);

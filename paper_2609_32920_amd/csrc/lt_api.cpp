@@ -160,7 +160,7 @@ struct lt_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
-  lt_tuning tune{128, 8, 1};
+  lt_tuning tune{128, 10, 1};
   uint64_t cap = 0;
   lt_stats stats{};
   int n_cu = 256;
@@ -448,7 +448,7 @@ lt_status lt_set_stream(lt_ctx* c, void* stream) {
 
 lt_status lt_set_tuning(lt_ctx* c, const lt_tuning* t) {
   if (!c) return LT_ERR_ARG;
-  if (!t) { c->tune = lt_tuning{128, 8, 1}; return LT_OK; }
+  if (!t) { c->tune = lt_tuning{128, 10, 1}; return LT_OK; }
   if (t->block < 64 || t->block > 1024 || (t->block % 64) != 0) return c->fail(LT_ERR_ARG, "block must be 64..1024, a multiple of 64%s");
   if (t->blocks_per_cu < 1 || t->blocks_per_cu > 64) return c->fail(LT_ERR_ARG, "blocks_per_cu must be 1..64%s");
   if ((size_t)kStackMax * t->block * sizeof(int) > (size_t)c->lds_max) return c->fail(LT_ERR_ARG, "traversal stack exceeds the LDS of a workgroup%s");

@@ -188,7 +188,7 @@ class Context:
         s = torch.cuda.current_stream(self.device)
         self._check(self.lib.lt_set_stream(self.h, C.c_void_p(s.cuda_stream)))
 
-    def set_tuning(self, block=128, blocks_per_cu=8, lds_grad=1):
+    def set_tuning(self, block=128, blocks_per_cu=10, lds_grad=1):
         t = Tuning(block, blocks_per_cu, lds_grad)
         self._check(self.lib.lt_set_tuning(self.h, C.byref(t)))
 
