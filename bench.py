@@ -318,6 +318,7 @@ def main():
                    "paths": N, "depth": D, "film": [W, H], "method": "lrb3", "scene": "box"},
         "step_ms": {"forward": round(float(np.median(fwd)), 4), "loss": round(float(np.median(lss)), 4),
                     "backward": round(float(np.median(bwd)), 4)},
+        "forward_paths_per_s": round(N / (float(np.median(fwd)) * 1e-3), 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "cpu_baseline_1thread": cpu1,
