@@ -110,12 +110,18 @@ def test_batched_step_matches_per_instance_calls(lds_grad):
 
 
 def test_graph_replays_match_per_instance_calls():
+    """Capture, then replays with new seeds, new guide weights (written in
+    place, as a training step does) and eager work in between."""
     dev = torch.device("cuda", 0)
     insts = _instances(dev)
     b = lt.Batch(0)
-    for rep in range(3):  # capture, then replays with new seeds and eager work in between
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    for rep in range(3):
         for k, d in enumerate(insts):
             d["seed"] = 1000 * rep + 17 * k + 1
+            if d["guide"] is not None and rep:
+                d["guide"].add_(0.02 * torch.randn(d["guide"].shape, device=dev, generator=gen))
         _zero(insts)
         b.step(insts, use_graph=True)
         torch.cuda.synchronize()
