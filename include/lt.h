@@ -356,7 +356,9 @@ lt_status lt_guide_train_step(lt_ctx* ctx, const lt_trace_args* args, float* gui
  * L2 loss and image adjoint of lt_loss_l2, the LRB-3-pass backward of
  * lt_backward_lrb3 (Sec. 4.3) - as one persistent launch per pass over an
  * instance table: every wave takes work tickets (path indices) from one
- * instance at a time and moves to the next when it has drained it.  With
+ * instance at a time and moves to the next when it has drained it.
+ * Attached instances of 2^20 paths or more take a backward launch each (a
+ * kernel with more waves resident than the multi-instance one).  With
  * use_graph the step is captured once into a hipGraph and replayed; between
  * replays only the seeds may change (they are read from device memory).
  * Results equal the per-instance calls up to the order of floating-point

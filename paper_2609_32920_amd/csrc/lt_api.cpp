@@ -221,9 +221,9 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Heights gradients go to a per-workgroup LDS copy when it fits next to the
 // traversal stacks (256-thread workgroups).  The replay kernels (arithmetic-
-// heavy, latency-bound at two waves per SIMD) take it only when it costs no
-// resident workgroups per CU; the tape walk (little arithmetic per scatter,
-// bound by the atomics) takes it whenever it fits.
+// heavy, latency-bound at two or three waves per SIMD) take it only when it
+// costs no resident workgroups per CU; the tape walk (little arithmetic per
+// scatter, bound by the atomics) takes it whenever it fits.
 int hgrad_in_lds(const lt_ctx* c, const float* g_heights, BwdKernel k, size_t stack, bool keep_residency) {
   if (!g_heights || c->dsc.hf_G < 2) return 0;
   size_t need = (size_t)c->dsc.hf_G * c->dsc.hf_G * sizeof(float);
@@ -960,11 +960,18 @@ struct lt_batch {
 
 namespace {
 
+// Attached instances of at least this many paths run their backward as a
+// launch of their own (the one-entry kernel, three waves per SIMD against the
+// multi-entry kernel's two); at that size a launch's tail and gap are small
+// against its work.
+constexpr int64_t kSoloPaths = (int64_t)1 << 20;
+
 struct BatchPlan {
-  std::vector<PassArgs> tab;   // [n trace][n_det detached][n_att attached]
-  std::vector<int> det, att;   // instance indices of each backward kind
+  std::vector<PassArgs> tab;   // [n trace][n_det detached][n_att attached][n_solo attached, own launch each]
+  std::vector<int> det, att, solo;  // instance indices of each backward kind
   int n = 0, stack_n = 1;      // traversal stack entries per lane, the same for every entry
   size_t det_lds = 0, att_lds = 0;  // LDS bytes past the stacks for gradient copies, per launch
+  std::vector<size_t> solo_lds;     // the same for each solo launch
 };
 
 // Largest of the sizes the instances ask for that fits next to the traversal
@@ -1059,7 +1066,7 @@ BatchPlan batch_plan(lt_batch* b, const lt_instance* inst, int n, int64_t path_d
     B.g_heights = I.grads.heights;
     B.g_Le_acc = b->d_acc + 4 * i;
     B.counter = b->d_cnt + n + i;
-    ((a.flags & LT_ATTACHED) ? P.att : P.det).push_back(i);
+    ((a.flags & LT_ATTACHED) ? (a.n_paths >= kSoloPaths ? P.solo : P.att) : P.det).push_back(i);
     P.tab[n + i] = B;  // reordered below
   }
   // Gradient copies in LDS.  Every entry lays its LDS out past stacks of the
@@ -1075,9 +1082,9 @@ BatchPlan batch_plan(lt_batch* b, const lt_instance* inst, int n, int64_t path_d
     return I.grads.heights && G >= 2 ? (size_t)G * G * sizeof(float) : 0;
   };
   std::vector<size_t> dsz, asz;
-  for (int i = 0; i < n; ++i) {
+  for (int i : P.det) dsz.push_back(tex_bytes(inst[i].ctx));
+  for (int i : P.att) {
     size_t t = tex_bytes(inst[i].ctx);
-    if (!(inst[i].args.flags & LT_ATTACHED)) { dsz.push_back(t); continue; }
     size_t h = hf_bytes(inst[i]);
     asz.push_back(h); asz.push_back(t);
     if (h && t) asz.push_back(h + t);
@@ -1089,21 +1096,36 @@ BatchPlan batch_plan(lt_batch* b, const lt_instance* inst, int n, int64_t path_d
   if (!P.att.empty())
     P.att_lds = batch_lds_budget(BwdKernel::lrb3_att_batch, 256, (size_t)P.stack_n * 256 * sizeof(int), lds_max, asz);
   for (auto& e : P.tab) e.sc.stack_n = P.stack_n;
-  for (int i = 0; i < n; ++i) {
-    PassArgs& B = P.tab[n + i];
+  for (int i : P.det) {
     size_t t = tex_bytes(inst[i].ctx);
-    if (!(inst[i].args.flags & LT_ATTACHED)) {
-      B.agrad_lds = t && t <= P.det_lds;
-      continue;
-    }
-    size_t h = hf_bytes(inst[i]);
+    P.tab[n + i].agrad_lds = t && t <= P.det_lds;
+  }
+  for (int i : P.att) {
+    PassArgs& B = P.tab[n + i];
+    size_t h = hf_bytes(inst[i]), t = tex_bytes(inst[i].ctx);
     B.hgrad_lds = h && h <= P.att_lds;
     B.agrad_lds = t && t + (B.hgrad_lds ? h : 0) <= P.att_lds;
   }
-  // backward entries: detached ones first, then attached ones
+  // a solo launch takes each copy that fits and costs it no resident workgroups
+  const size_t stack_att = (size_t)P.stack_n * 256 * sizeof(int);
+  auto free_of_cost = [&](size_t extra) {
+    if (stack_att + extra > lds_max) return false;
+    int r = resident_groups(BwdKernel::lrb3_att_entry, 256, stack_att + extra);
+    return r > 0 && r >= resident_groups(BwdKernel::lrb3_att_entry, 256, stack_att);
+  };
+  for (int i : P.solo) {
+    PassArgs& B = P.tab[n + i];
+    size_t h = hf_bytes(inst[i]), t = tex_bytes(inst[i].ctx);
+    B.hgrad_lds = h && free_of_cost(h);
+    size_t hb = B.hgrad_lds ? h : 0;
+    B.agrad_lds = t && free_of_cost(hb + t);
+    P.solo_lds.push_back(hb + (B.agrad_lds ? t : 0));
+  }
+  // backward entries: detached ones first, then attached ones, then solo ones
   std::vector<PassArgs> bw;
   for (int i : P.det) bw.push_back(P.tab[n + i]);
   for (int i : P.att) bw.push_back(P.tab[n + i]);
+  for (int i : P.solo) bw.push_back(P.tab[n + i]);
   for (int k = 0; k < n; ++k) P.tab[n + k] = bw[k];
   return P;
 }
@@ -1152,6 +1174,13 @@ lt_status batch_enqueue_on(lt_batch* b, const lt_instance* inst, const BatchPlan
                      "batched attached backward")) != LT_OK)
       return st;
   }
+  for (size_t k = 0; k < P.solo.size(); ++k) {
+    const int e = n + nd + na + (int)k;
+    const int grid_one = persistent_grid(inst[P.solo[k]].ctx, P.tab[e].n_paths, 256);
+    if ((st = b->hip(launch_lrb3_att_entry(b->d_tab + e, P.stack_n, P.solo_lds[k], grid_one, s),
+                     "attached backward")) != LT_OK)
+      return st;
+  }
   for (int i = 0; i < n; ++i)
     if ((st = b->hip(launch_add_le(b->d_acc + 4 * i, inst[i].grads.emitter_L, s), "emitter gradient")) != LT_OK)
       return st;
@@ -1165,16 +1194,18 @@ lt_status batch_enqueue(lt_batch* b, const lt_instance* inst, const BatchPlan& P
 }
 
 // Identity of a step for graph reuse: the instances (all but the seeds), the
-// tuning and the plan's LDS sizes (a scene uploaded again into an instance's
-// context may change them).
+// tuning, the plan's solo launches and its LDS sizes (a scene uploaded again
+// into an instance's context may change them).
 std::vector<char> batch_key(const lt_batch* b, const lt_instance* inst, int n, const BatchPlan& P) {
   std::vector<lt_instance> v(inst, inst + n);
   for (auto& I : v) I.args.seed = 0;
   std::vector<char> k((const char*)v.data(), (const char*)(v.data() + n));
   const char* t = (const char*)&b->tune;
   k.insert(k.end(), t, t + sizeof(lt_tuning));
-  const size_t sz[3] = {(size_t)P.stack_n, P.det_lds, P.att_lds};
-  k.insert(k.end(), (const char*)sz, (const char*)(sz + 3));
+  const size_t sz[4] = {(size_t)P.stack_n, P.det_lds, P.att_lds, P.solo.size()};
+  k.insert(k.end(), (const char*)sz, (const char*)(sz + 4));
+  k.insert(k.end(), (const char*)P.solo.data(), (const char*)(P.solo.data() + P.solo.size()));
+  k.insert(k.end(), (const char*)P.solo_lds.data(), (const char*)(P.solo_lds.data() + P.solo_lds.size()));
   return k;
 }
 

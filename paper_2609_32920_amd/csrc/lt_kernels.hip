@@ -701,6 +701,15 @@ __global__ void __launch_bounds__(256, 2) k_lrb3_att_batch(const PassArgs* __res
   extern __shared__ int lds[];
   for (int i = 0; i < n; ++i) lrb3_att_run(table_entry(T, i), lds);
 }
+// One attached entry of the table, at the single-instance kernel's three
+// waves per SIMD (the loop over entries above costs registers enough to hold
+// that kernel to two).  Batches run their large attached instances through
+// it, one launch each; the arguments stay in the table, so a replayed graph
+// reads each step's seeds.
+__global__ void __launch_bounds__(256, 3) k_lrb3_att_entry(const PassArgs* __restrict__ T) {
+  extern __shared__ int lds[];
+  lrb3_att_run(table_entry(T, 0), lds);
+}
 
 #ifdef LT_COUNTERS
 }  // namespace counted
@@ -726,6 +735,8 @@ hipError_t set_lds_limit(int bytes) {
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_lrb3_batch, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_lrb3_att_batch, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_lrb3_att_entry, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   return e;
 }
 
@@ -751,6 +762,7 @@ int resident_groups(BwdKernel k, int block, size_t lds) {
     case BwdKernel::lrb3_att: f = (const void*)k_lrb3_att; break;
     case BwdKernel::lrb3_batch: f = (const void*)k_lrb3_batch; break;
     case BwdKernel::lrb3_att_batch: f = (const void*)k_lrb3_att_batch; break;
+    case BwdKernel::lrb3_att_entry: f = (const void*)k_lrb3_att_entry; break;
   }
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, block, lds) != hipSuccess) {
@@ -795,6 +807,10 @@ hipError_t launch_lrb3_batch(const PassArgs* table, int n, int stack_n, size_t g
 hipError_t launch_lrb3_att_batch(const PassArgs* table, int n, int stack_n, size_t grad_lds, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_lrb3_att_batch, dim3(grid), dim3(256), (size_t)stack_n * 256 * sizeof(int) + grad_lds, s, table,
                      n);
+  return hipGetLastError();
+}
+hipError_t launch_lrb3_att_entry(const PassArgs* entry, int stack_n, size_t grad_lds, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_lrb3_att_entry, dim3(grid), dim3(256), (size_t)stack_n * 256 * sizeof(int) + grad_lds, s, entry);
   return hipGetLastError();
 }
 

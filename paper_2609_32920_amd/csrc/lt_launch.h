@@ -84,6 +84,8 @@ hipError_t launch_trace_batch(const PassArgs* table, int n, int stack_n, int gri
 hipError_t launch_lrb3_batch(const PassArgs* table, int n, int stack_n, size_t grad_lds, int grid, int block,
                              hipStream_t s);
 hipError_t launch_lrb3_att_batch(const PassArgs* table, int n, int stack_n, size_t grad_lds, int grid, hipStream_t s);
+// one attached table entry (the table pointer already offset to it)
+hipError_t launch_lrb3_att_entry(const PassArgs* entry, int stack_n, size_t grad_lds, int grid, hipStream_t s);
 hipError_t launch_naive_bwd(const PassArgs& A, int grid, hipStream_t s);
 hipError_t launch_reslrb_bwd(const PassArgs& A, int grid, int block, hipStream_t s);
 hipError_t launch_lrb3_bwd(const PassArgs& A, int grid, int block, hipStream_t s);
@@ -102,7 +104,7 @@ hipError_t launch_hf_tris(const DevScene& sc, const int32_t* slot_of_prim, Tri* 
 hipError_t set_lds_limit(int bytes);
 // Workgroups of a backward kernel resident per CU at `block` threads and
 // `lds` dynamic LDS bytes (0 if it cannot launch or the query fails).
-enum class BwdKernel { naive, reslrb, lrb3, naive_att, reslrb_att, lrb3_att, lrb3_batch, lrb3_att_batch };
+enum class BwdKernel { naive, reslrb, lrb3, naive_att, reslrb_att, lrb3_att, lrb3_batch, lrb3_att_batch, lrb3_att_entry };
 int resident_groups(BwdKernel k, int block, size_t lds);
 hipError_t read_counters(uint64_t* out, bool reset, hipStream_t s);
 hipError_t launch_refit_level(Node* nodes, const Tri* tris, const int32_t* level_nodes, int n, hipStream_t s);

@@ -1,6 +1,8 @@
 """Batched optimisation steps (one persistent launch per pass over an
 instance table, optionally replayed from a captured hipGraph) against the
-same steps made by per-instance calls.
+same steps made by per-instance calls.  The two attached instances of 2^20
+paths or more take the backward launch of their own (the one-entry kernel,
+reading its arguments and seed from the table).
 
 Both run the same kernels' per-path code with the same seeds; only the
 order of floating-point atomic sums differs (gradients pre-reduced in LDS
@@ -24,6 +26,8 @@ SPECS = [  # kind, G, film, paths, depth, guided
     ("box", 0, 96, 70_001, 6, False),
     ("caustic", 24, 80, 50_000, 6, True),
     ("box", 0, 32, 1, 3, False),
+    ("caustic", 32, 64, 1 << 20, 4, True),
+    ("caustic", 40, 48, 1_100_000, 5, False),
 ]
 
 
