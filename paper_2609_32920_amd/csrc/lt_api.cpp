@@ -1066,7 +1066,8 @@ BatchPlan batch_plan(lt_batch* b, const lt_instance* inst, int n, int64_t path_d
     B.g_heights = I.grads.heights;
     B.g_Le_acc = b->d_acc + 4 * i;
     B.counter = b->d_cnt + n + i;
-    ((a.flags & LT_ATTACHED) ? (a.n_paths >= kSoloPaths ? P.solo : P.att) : P.det).push_back(i);
+    // by the caller's path count, so the autotuner's shortened steps keep the plan's shape
+    ((a.flags & LT_ATTACHED) ? (I.args.n_paths >= kSoloPaths ? P.solo : P.att) : P.det).push_back(i);
     P.tab[n + i] = B;  // reordered below
   }
   // Gradient copies in LDS.  Every entry lays its LDS out past stacks of the
