@@ -2,13 +2,16 @@
 instance table, optionally replayed from a captured hipGraph) against the
 same steps made by per-instance calls.  The two attached instances of 2^20
 paths or more take the backward launch of their own (the one-entry kernel,
-reading its arguments and seed from the table).
+reading its arguments and seed from the table); the 128x128 heightfield's
+heights copy does not fit the LDS of its workgroups, so its heights
+gradients go straight to memory.
 
 Both run the same kernels' per-path code with the same seeds; only the
 order of floating-point atomic sums differs (gradients pre-reduced in LDS
 or write-combined per wave, on either side), so results agree to
 FP32 summation-order rounding: max |a - b| / max |b| <= 1e-5 for images and
-losses, 1e-4 for gradients.
+losses, 1e-4 for gradients (the backward fed the batch's own image adjoint
+on both sides).
 """
 import json
 
@@ -27,7 +30,7 @@ SPECS = [  # kind, G, film, paths, depth, guided
     ("caustic", 24, 80, 50_000, 6, True),
     ("box", 0, 32, 1, 3, False),
     ("caustic", 32, 64, 1 << 20, 4, True),
-    ("caustic", 40, 48, 1_100_000, 5, False),
+    ("caustic", 128, 48, 1_100_000, 5, False),
 ]
 
 
@@ -66,7 +69,12 @@ def _zero(insts):
 
 
 def _reference(d):
-    """The same step through per-instance calls."""
+    """The same step through per-instance calls.  The backward takes the
+    batch's own image adjoint: an adjoint recomputed from the per-instance
+    image inherits that image's FP32 splat-order rounding (about 1e-6), and
+    the global gradient sums (a caustic slab's single albedo texel, the
+    emitter) cancel enough to amplify it past 1e-4 (1.3e-4 and 3.2e-5
+    measured on the 128x128 instance while its heights agreed to 2e-7)."""
     ctx = d["ctx"]
     a = ctx.args(d["seed"], d["n_paths"], d["depth"], lt.ATTACHED if d["attached"] else 0)
     p = ctx.params(d["albedo"], d["Le"], d["heights"], d["guide"])
@@ -76,7 +84,7 @@ def _reference(d):
     gh = torch.zeros_like(d["heights"]) if d["heights"] is not None else None
     ctx.trace(a, p, img)
     ctx.loss_l2(img, d["target"], dI, loss)
-    ctx.backward_lrb3(a, p, dI, ga, gl, gh)
+    ctx.backward_lrb3(a, p, d["d_image"], ga, gl, gh)
     torch.cuda.synchronize()
     return dict(image=img, d_image=dI, loss=loss, g_albedo=ga, g_Le=gl, g_heights=gh)
 
@@ -93,7 +101,8 @@ def _compare(insts, tag):
         e_img = _maxrel(d["image"], ref["image"])
         e_loss = _maxrel(d["loss"], ref["loss"])
         e_g = [_maxrel(d[g], ref[g]) for g in ("g_albedo", "g_Le", "g_heights") if d[g] is not None]
-        print(f"{tag} instance {k} {SPECS[k]}: image {e_img:.1e} loss {e_loss:.1e} grads {max(e_g):.1e}", flush=True)
+        print(f"{tag} instance {k} {SPECS[k]}: image {e_img:.1e} loss {e_loss:.1e} grads "
+              f"(albedo, Le[, heights]) {' '.join(f'{x:.1e}' for x in e_g)}", flush=True)
         assert e_img <= 1e-5 and e_loss <= 1e-5 and max(e_g) <= 1e-4
 
 
