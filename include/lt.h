@@ -186,7 +186,8 @@ const char* lt_last_error(const lt_ctx* ctx);
 /* Switch the stream later calls enqueue on. */
 lt_status lt_set_stream(lt_ctx* ctx, void* hip_stream);
 /* Launch shape: NULL restores the defaults {128, 10, 1} (the attached kernels
- * keep 256-thread workgroups and take blocks_per_cu only). Errors: LT_ERR_ARG. */
+ * choose their own workgroup size, 256 or 768 threads, and take blocks_per_cu
+ * only). Errors: LT_ERR_ARG. */
 lt_status lt_set_tuning(lt_ctx* ctx, const lt_tuning* tuning);
 lt_status lt_get_tuning(const lt_ctx* ctx, lt_tuning* out);
 /* Cap, in bytes, on side state plus library workspace a call may use
@@ -394,7 +395,7 @@ const char* lt_batch_last_error(const lt_batch* b);
  * LT_ERR_HIP. */
 lt_status lt_batch_step(lt_batch* b, const lt_instance* inst, int32_t n, int32_t use_graph);
 /* Launch shape of the batched passes: block and blocks_per_cu as in
- * lt_set_tuning (the attached backward keeps 256-thread workgroups).
+ * lt_set_tuning (the attached backward chooses its own workgroup size).
  * Default {256, 4, 1}.  The backward passes keep per-workgroup LDS copies of
  * the gradient arrays (heights always, albedo with lds_grad = 1) for the
  * instances whose arrays fit one budget per pass: the largest requested size

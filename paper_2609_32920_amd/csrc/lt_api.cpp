@@ -220,17 +220,36 @@ int persistent_grid(const lt_ctx* c, int64_t n, int block) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Heights gradients go to a per-workgroup LDS copy when it fits next to the
-// traversal stacks (256-thread workgroups).  The replay kernels (arithmetic-
+// traversal stacks of a `block`-thread workgroup.  The replay kernels (arithmetic-
 // heavy, latency-bound at two or three waves per SIMD) take it only when it
 // costs no resident workgroups per CU; the tape walk (little arithmetic per
 // scatter, bound by the atomics) takes it whenever it fits.
-int hgrad_in_lds(const lt_ctx* c, const float* g_heights, BwdKernel k, size_t stack, bool keep_residency) {
+int hgrad_in_lds(const lt_ctx* c, const float* g_heights, BwdKernel k, int block, size_t stack, bool keep_residency) {
   if (!g_heights || c->dsc.hf_G < 2) return 0;
   size_t need = (size_t)c->dsc.hf_G * c->dsc.hf_G * sizeof(float);
   if (stack + need > (size_t)c->lds_max) return 0;
   if (!keep_residency) return 1;
-  int with = resident_groups(k, 256, stack + need);
-  return with > 0 && with >= resident_groups(k, 256, stack) ? 1 : 0;
+  int with = resident_groups(k, block, stack + need);
+  return with > 0 && with >= resident_groups(k, block, stack) ? 1 : 0;
+}
+
+// Workgroup size of the attached LRB-3 backward.  It holds three waves per
+// SIMD, so one 768-thread workgroup fills a CU and has the CU's whole LDS:
+// the traversal stacks plus a heights-gradient copy that three 256-thread
+// workgroups could not hold without losing residency (128² heights: caustic
+// backward 51.1 -> 48.8 ms).  256 where the copy fits those three anyway
+// (small heightfields run 1-2% faster so) or does not fit beside 768 lanes'
+// stacks either.
+int lrb3_att_block(const lt_ctx* c, const float* g_heights, int stack_n) {
+  if (!g_heights || c->dsc.hf_G < 2) return 256;
+  const size_t need = (size_t)c->dsc.hf_G * c->dsc.hf_G * sizeof(float);
+  auto copy_free = [&](int block) {
+    const size_t stack = (size_t)stack_n * block * sizeof(int);
+    if (stack + need > (size_t)c->lds_max) return false;
+    int with = resident_groups(BwdKernel::lrb3_att, block, stack + need);
+    return with > 0 && with >= resident_groups(BwdKernel::lrb3_att, block, stack);
+  };
+  return !copy_free(256) && copy_free(768) ? 768 : 256;
 }
 
 // Albedo gradients go to a per-workgroup LDS copy (lt_tuning.lds_grad) when
@@ -778,7 +797,7 @@ lt_status lt_backward_naive(lt_ctx* c, const lt_trace_args* a, const lt_params* 
   int grid = (int)std::max<int64_t>(1, std::min<int64_t>((a->n_paths + 255) / 256, (int64_t)c->n_cu * 16));
   if (a->flags & LT_ATTACHED) {
     A.emit_d = (float*)(sb + L.emit);
-    A.hgrad_lds = hgrad_in_lds(c, g->heights, BwdKernel::naive_att, 0, false);
+    A.hgrad_lds = hgrad_in_lds(c, g->heights, BwdKernel::naive_att, 256, 0, false);
     A.agrad_lds = agrad_in_lds(c, BwdKernel::naive_att, 256, hgrad_lds_bytes(c, A.hgrad_lds));
     if ((st = c->hip(launch_naive_att_bwd(A, grid, c->stream), "naive attached backward")) != LT_OK) return st;
   } else {
@@ -800,7 +819,7 @@ lt_status lt_backward_reslrb(lt_ctx* c, const lt_trace_args* a, const lt_params*
   if (a->flags & LT_ATTACHED) {
     A.res_att_in = (const ResRecAtt*)((const char*)records + L.res);
     int grid = persistent_grid(c, a->n_paths, 256);
-    A.hgrad_lds = hgrad_in_lds(c, g->heights, BwdKernel::reslrb_att, stack_lds(c, 256), true);
+    A.hgrad_lds = hgrad_in_lds(c, g->heights, BwdKernel::reslrb_att, 256, stack_lds(c, 256), true);
     A.agrad_lds = agrad_in_lds(c, BwdKernel::reslrb_att, 256, stack_lds(c, 256) + hgrad_lds_bytes(c, A.hgrad_lds));
     if ((st = c->hip(launch_reslrb_att(A, grid, c->stream), "reslrb attached backward")) != LT_OK) return st;
     return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
@@ -820,10 +839,11 @@ lt_status lt_backward_lrb3(lt_ctx* c, const lt_trace_args* a, const lt_params* p
   if (st != LT_OK) return st;
   A.contrib = a->path_contrib;
   if (a->flags & LT_ATTACHED) {
-    int grid = persistent_grid(c, a->n_paths, 256);
-    A.hgrad_lds = hgrad_in_lds(c, g->heights, BwdKernel::lrb3_att, stack_lds(c, 256), true);
-    A.agrad_lds = agrad_in_lds(c, BwdKernel::lrb3_att, 256, stack_lds(c, 256) + hgrad_lds_bytes(c, A.hgrad_lds));
-    if ((st = c->hip(launch_lrb3_att(A, grid, c->stream), "lrb3 attached backward")) != LT_OK) return st;
+    const int blk = lrb3_att_block(c, g->heights, c->dsc.stack_n);
+    int grid = persistent_grid(c, a->n_paths, blk);
+    A.hgrad_lds = hgrad_in_lds(c, g->heights, BwdKernel::lrb3_att, blk, stack_lds(c, blk), true);
+    A.agrad_lds = agrad_in_lds(c, BwdKernel::lrb3_att, blk, stack_lds(c, blk) + hgrad_lds_bytes(c, A.hgrad_lds));
+    if ((st = c->hip(launch_lrb3_att(A, grid, blk, c->stream), "lrb3 attached backward")) != LT_OK) return st;
   } else {
     int grid = persistent_grid(c, a->n_paths, c->tune.block);
     A.agrad_lds = agrad_in_lds(c, BwdKernel::lrb3, c->tune.block, stack_lds(c, c->tune.block));
@@ -972,6 +992,7 @@ struct BatchPlan {
   int n = 0, stack_n = 1;      // traversal stack entries per lane, the same for every entry
   size_t det_lds = 0, att_lds = 0;  // LDS bytes past the stacks for gradient copies, per launch
   std::vector<size_t> solo_lds;     // the same for each solo launch
+  std::vector<int> solo_block;      // workgroup size of each solo launch
 };
 
 // Largest of the sizes the instances ask for that fits next to the traversal
@@ -1107,20 +1128,23 @@ BatchPlan batch_plan(lt_batch* b, const lt_instance* inst, int n, int64_t path_d
     B.hgrad_lds = h && h <= P.att_lds;
     B.agrad_lds = t && t + (B.hgrad_lds ? h : 0) <= P.att_lds;
   }
-  // a solo launch takes each copy that fits and costs it no resident workgroups
-  const size_t stack_att = (size_t)P.stack_n * 256 * sizeof(int);
-  auto free_of_cost = [&](size_t extra) {
-    if (stack_att + extra > lds_max) return false;
-    int r = resident_groups(BwdKernel::lrb3_att_entry, 256, stack_att + extra);
-    return r > 0 && r >= resident_groups(BwdKernel::lrb3_att_entry, 256, stack_att);
-  };
+  // a solo launch takes the single-instance call's workgroup size and each
+  // copy that fits and costs it no resident workgroups
   for (int i : P.solo) {
     PassArgs& B = P.tab[n + i];
+    const int blk = lrb3_att_block(inst[i].ctx, inst[i].grads.heights, P.stack_n);
+    const size_t stack = (size_t)P.stack_n * blk * sizeof(int);
+    auto free_of_cost = [&](size_t extra) {
+      if (stack + extra > lds_max) return false;
+      int r = resident_groups(BwdKernel::lrb3_att_entry, blk, stack + extra);
+      return r > 0 && r >= resident_groups(BwdKernel::lrb3_att_entry, blk, stack);
+    };
     size_t h = hf_bytes(inst[i]), t = tex_bytes(inst[i].ctx);
     B.hgrad_lds = h && free_of_cost(h);
     size_t hb = B.hgrad_lds ? h : 0;
     B.agrad_lds = t && free_of_cost(hb + t);
     P.solo_lds.push_back(hb + (B.agrad_lds ? t : 0));
+    P.solo_block.push_back(blk);
   }
   // backward entries: detached ones first, then attached ones, then solo ones
   std::vector<PassArgs> bw;
@@ -1177,8 +1201,8 @@ lt_status batch_enqueue_on(lt_batch* b, const lt_instance* inst, const BatchPlan
   }
   for (size_t k = 0; k < P.solo.size(); ++k) {
     const int e = n + nd + na + (int)k;
-    const int grid_one = persistent_grid(inst[P.solo[k]].ctx, P.tab[e].n_paths, 256);
-    if ((st = b->hip(launch_lrb3_att_entry(b->d_tab + e, P.stack_n, P.solo_lds[k], grid_one, s),
+    const int grid_one = persistent_grid(inst[P.solo[k]].ctx, P.tab[e].n_paths, P.solo_block[k]);
+    if ((st = b->hip(launch_lrb3_att_entry(b->d_tab + e, P.stack_n, P.solo_lds[k], grid_one, P.solo_block[k], s),
                      "attached backward")) != LT_OK)
       return st;
   }
@@ -1207,6 +1231,7 @@ std::vector<char> batch_key(const lt_batch* b, const lt_instance* inst, int n, c
   k.insert(k.end(), (const char*)sz, (const char*)(sz + 4));
   k.insert(k.end(), (const char*)P.solo.data(), (const char*)(P.solo.data() + P.solo.size()));
   k.insert(k.end(), (const char*)P.solo_lds.data(), (const char*)(P.solo_lds.data() + P.solo_lds.size()));
+  k.insert(k.end(), (const char*)P.solo_block.data(), (const char*)(P.solo_block.data() + P.solo_block.size()));
   return k;
 }
 

@@ -702,11 +702,11 @@ __global__ void __launch_bounds__(256, 2) k_lrb3_att_batch(const PassArgs* __res
   for (int i = 0; i < n; ++i) lrb3_att_run(table_entry(T, i), lds);
 }
 // One attached entry of the table, at the single-instance kernel's three
-// waves per SIMD (the loop over entries above costs registers enough to hold
-// that kernel to two).  Batches run their large attached instances through
-// it, one launch each; the arguments stay in the table, so a replayed graph
-// reads each step's seeds.
-__global__ void __launch_bounds__(256, 3) k_lrb3_att_entry(const PassArgs* __restrict__ T) {
+// waves per SIMD and workgroup sizes (the loop over entries above costs
+// registers enough to hold that kernel to two).  Batches run their large
+// attached instances through it, one launch each; the arguments stay in the
+// table, so a replayed graph reads each step's seeds.
+__global__ void __launch_bounds__(768, 3) k_lrb3_att_entry(const PassArgs* __restrict__ T) {
   extern __shared__ int lds[];
   lrb3_att_run(table_entry(T, 0), lds);
 }
@@ -774,8 +774,9 @@ int resident_groups(BwdKernel k, int block, size_t lds) {
   return n;
 }
 
-hipError_t launch_lrb3_att(const PassArgs& A, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_lrb3_att, dim3(grid), dim3(256), stack_bytes(A, 256) + hgrad_bytes(A) + agrad_bytes(A), s, A);
+hipError_t launch_lrb3_att(const PassArgs& A, int grid, int block, hipStream_t s) {
+  hipLaunchKernelGGL(k_lrb3_att, dim3(grid), dim3(block), stack_bytes(A, block) + hgrad_bytes(A) + agrad_bytes(A), s,
+                     A);
   return hipGetLastError();
 }
 hipError_t launch_trace_att(const PassArgs& A, bool tape, bool resv, int grid, hipStream_t s) {
@@ -809,8 +810,10 @@ hipError_t launch_lrb3_att_batch(const PassArgs* table, int n, int stack_n, size
                      n);
   return hipGetLastError();
 }
-hipError_t launch_lrb3_att_entry(const PassArgs* entry, int stack_n, size_t grad_lds, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_lrb3_att_entry, dim3(grid), dim3(256), (size_t)stack_n * 256 * sizeof(int) + grad_lds, s, entry);
+hipError_t launch_lrb3_att_entry(const PassArgs* entry, int stack_n, size_t grad_lds, int grid, int block,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_lrb3_att_entry, dim3(grid), dim3(block), (size_t)stack_n * block * sizeof(int) + grad_lds, s,
+                     entry);
   return hipGetLastError();
 }
 

@@ -85,11 +85,12 @@ hipError_t launch_lrb3_batch(const PassArgs* table, int n, int stack_n, size_t g
                              hipStream_t s);
 hipError_t launch_lrb3_att_batch(const PassArgs* table, int n, int stack_n, size_t grad_lds, int grid, hipStream_t s);
 // one attached table entry (the table pointer already offset to it)
-hipError_t launch_lrb3_att_entry(const PassArgs* entry, int stack_n, size_t grad_lds, int grid, hipStream_t s);
+hipError_t launch_lrb3_att_entry(const PassArgs* entry, int stack_n, size_t grad_lds, int grid, int block,
+                                 hipStream_t s);
 hipError_t launch_naive_bwd(const PassArgs& A, int grid, hipStream_t s);
 hipError_t launch_reslrb_bwd(const PassArgs& A, int grid, int block, hipStream_t s);
 hipError_t launch_lrb3_bwd(const PassArgs& A, int grid, int block, hipStream_t s);
-hipError_t launch_lrb3_att(const PassArgs& A, int grid, hipStream_t s);
+hipError_t launch_lrb3_att(const PassArgs& A, int grid, int block, hipStream_t s);
 hipError_t launch_trace_att(const PassArgs& A, bool tape, bool resv, int grid, hipStream_t s);
 hipError_t launch_naive_att_bwd(const PassArgs& A, int grid, hipStream_t s);
 hipError_t launch_reslrb_att(const PassArgs& A, int grid, hipStream_t s);

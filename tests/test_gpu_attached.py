@@ -134,9 +134,10 @@ def test_replay_attached_parity(caustic16, D, mode):
                          ids=["G128_full_size", "G224_heights_beyond_lds"])
 def test_full_size_caustic_sampled(G, film, n, nsamp):
     # 128x128 heightfield, 512x512 film, depth 6, 16M paths (the attached
-    # workload at full size, default launch shape), and a 224x224
-    # heightfield whose heights (196 KB) exceed LDS, so no heights copy is
-    # kept in any backward kernel: seeded sample paths
+    # workload at full size, default launch shape; the LRB-3 backward runs
+    # 768-thread workgroups with the heights copy in LDS), and a 224x224
+    # heightfield whose heights (196 KB) exceed LDS, so the LRB-3 backward
+    # keeps 256-thread workgroups and scatters to memory: seeded sample paths
     # kept by the mask and compared with the oracle on those paths.  The
     # tolerance is the deep-path one derived for the 256x256 box (FP32
     # vertex drift mapped to film pixels), applied to heights as well, and

@@ -2,9 +2,9 @@
 instance table, optionally replayed from a captured hipGraph) against the
 same steps made by per-instance calls.  The two attached instances of 2^20
 paths or more take the backward launch of their own (the one-entry kernel,
-reading its arguments and seed from the table); the 128x128 heightfield's
-heights copy does not fit the LDS of its workgroups, so its heights
-gradients go straight to memory.
+reading its arguments and seed from the table), with 256-thread workgroups
+for the 32x32 heightfield and 768-thread ones, holding the heights copy in
+LDS, for the 128x128 one.
 
 Both run the same kernels' per-path code with the same seeds; only the
 order of floating-point atomic sums differs (gradients pre-reduced in LDS
