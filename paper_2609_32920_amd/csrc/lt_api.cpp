@@ -233,23 +233,24 @@ int hgrad_in_lds(const lt_ctx* c, const float* g_heights, BwdKernel k, int block
   return with > 0 && with >= resident_groups(k, block, stack) ? 1 : 0;
 }
 
-// Workgroup size of the attached LRB-3 backward.  It holds three waves per
-// SIMD, so one 768-thread workgroup fills a CU and has the CU's whole LDS:
-// the traversal stacks plus a heights-gradient copy that three 256-thread
-// workgroups could not hold without losing residency (128² heights: caustic
-// backward 51.1 -> 48.8 ms).  256 where the copy fits those three anyway
-// (small heightfields run 1-2% faster so) or does not fit beside 768 lanes'
+// Workgroup size of the attached replay backwards.  The LRB-3 kernel holds
+// three waves per SIMD and the ResLRB kernel two, so one workgroup of `big`
+// threads (768, 512) fills a CU and has the CU's whole LDS: the traversal
+// stacks plus a heights-gradient copy that 256-thread workgroups could not
+// hold without losing residency (128² heights: caustic LRB-3 backward
+// 51.1 -> 48.8 ms).  256 where the copy fits those anyway (small
+// heightfields run 1-2% faster so) or does not fit beside `big` lanes'
 // stacks either.
-int lrb3_att_block(const lt_ctx* c, const float* g_heights, int stack_n) {
+int att_replay_block(const lt_ctx* c, const float* g_heights, int stack_n, BwdKernel k, int big) {
   if (!g_heights || c->dsc.hf_G < 2) return 256;
   const size_t need = (size_t)c->dsc.hf_G * c->dsc.hf_G * sizeof(float);
   auto copy_free = [&](int block) {
     const size_t stack = (size_t)stack_n * block * sizeof(int);
     if (stack + need > (size_t)c->lds_max) return false;
-    int with = resident_groups(BwdKernel::lrb3_att, block, stack + need);
-    return with > 0 && with >= resident_groups(BwdKernel::lrb3_att, block, stack);
+    int with = resident_groups(k, block, stack + need);
+    return with > 0 && with >= resident_groups(k, block, stack);
   };
-  return !copy_free(256) && copy_free(768) ? 768 : 256;
+  return !copy_free(256) && copy_free(big) ? big : 256;
 }
 
 // Albedo gradients go to a per-workgroup LDS copy (lt_tuning.lds_grad) when
@@ -818,10 +819,11 @@ lt_status lt_backward_reslrb(lt_ctx* c, const lt_trace_args* a, const lt_params*
   SideLayout L = side_layout(a);
   if (a->flags & LT_ATTACHED) {
     A.res_att_in = (const ResRecAtt*)((const char*)records + L.res);
-    int grid = persistent_grid(c, a->n_paths, 256);
-    A.hgrad_lds = hgrad_in_lds(c, g->heights, BwdKernel::reslrb_att, 256, stack_lds(c, 256), true);
-    A.agrad_lds = agrad_in_lds(c, BwdKernel::reslrb_att, 256, stack_lds(c, 256) + hgrad_lds_bytes(c, A.hgrad_lds));
-    if ((st = c->hip(launch_reslrb_att(A, grid, c->stream), "reslrb attached backward")) != LT_OK) return st;
+    const int blk = att_replay_block(c, g->heights, c->dsc.stack_n, BwdKernel::reslrb_att, 512);
+    int grid = persistent_grid(c, a->n_paths, blk);
+    A.hgrad_lds = hgrad_in_lds(c, g->heights, BwdKernel::reslrb_att, blk, stack_lds(c, blk), true);
+    A.agrad_lds = agrad_in_lds(c, BwdKernel::reslrb_att, blk, stack_lds(c, blk) + hgrad_lds_bytes(c, A.hgrad_lds));
+    if ((st = c->hip(launch_reslrb_att(A, grid, blk, c->stream), "reslrb attached backward")) != LT_OK) return st;
     return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
   }
   A.res_in = (const ResRec*)((const char*)records + L.res);
@@ -839,7 +841,7 @@ lt_status lt_backward_lrb3(lt_ctx* c, const lt_trace_args* a, const lt_params* p
   if (st != LT_OK) return st;
   A.contrib = a->path_contrib;
   if (a->flags & LT_ATTACHED) {
-    const int blk = lrb3_att_block(c, g->heights, c->dsc.stack_n);
+    const int blk = att_replay_block(c, g->heights, c->dsc.stack_n, BwdKernel::lrb3_att, 768);
     int grid = persistent_grid(c, a->n_paths, blk);
     A.hgrad_lds = hgrad_in_lds(c, g->heights, BwdKernel::lrb3_att, blk, stack_lds(c, blk), true);
     A.agrad_lds = agrad_in_lds(c, BwdKernel::lrb3_att, blk, stack_lds(c, blk) + hgrad_lds_bytes(c, A.hgrad_lds));
@@ -1132,7 +1134,7 @@ BatchPlan batch_plan(lt_batch* b, const lt_instance* inst, int n, int64_t path_d
   // copy that fits and costs it no resident workgroups
   for (int i : P.solo) {
     PassArgs& B = P.tab[n + i];
-    const int blk = lrb3_att_block(inst[i].ctx, inst[i].grads.heights, P.stack_n);
+    const int blk = att_replay_block(inst[i].ctx, inst[i].grads.heights, P.stack_n, BwdKernel::lrb3_att_entry, 768);
     const size_t stack = (size_t)P.stack_n * blk * sizeof(int);
     auto free_of_cost = [&](size_t extra) {
       if (stack + extra > lds_max) return false;

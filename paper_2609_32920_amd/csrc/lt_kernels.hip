@@ -790,8 +790,9 @@ hipError_t launch_naive_att_bwd(const PassArgs& A, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_naive_att_bwd, dim3(grid), dim3(256), hgrad_bytes(A) + agrad_bytes(A), s, A);
   return hipGetLastError();
 }
-hipError_t launch_reslrb_att(const PassArgs& A, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_reslrb_att, dim3(grid), dim3(256), stack_bytes(A, 256) + hgrad_bytes(A) + agrad_bytes(A), s, A);
+hipError_t launch_reslrb_att(const PassArgs& A, int grid, int block, hipStream_t s) {
+  hipLaunchKernelGGL(k_reslrb_att, dim3(grid), dim3(block), stack_bytes(A, block) + hgrad_bytes(A) + agrad_bytes(A), s,
+                     A);
   return hipGetLastError();
 }
 

@@ -93,7 +93,7 @@ hipError_t launch_lrb3_bwd(const PassArgs& A, int grid, int block, hipStream_t s
 hipError_t launch_lrb3_att(const PassArgs& A, int grid, int block, hipStream_t s);
 hipError_t launch_trace_att(const PassArgs& A, bool tape, bool resv, int grid, hipStream_t s);
 hipError_t launch_naive_att_bwd(const PassArgs& A, int grid, hipStream_t s);
-hipError_t launch_reslrb_att(const PassArgs& A, int grid, hipStream_t s);
+hipError_t launch_reslrb_att(const PassArgs& A, int grid, int block, hipStream_t s);
 hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t s);
 hipError_t launch_fill_u32(unsigned int* p, size_t n, unsigned int v, hipStream_t s);
 hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s);
