@@ -513,6 +513,48 @@ struct Scene {
   }
 };
 
+// Scattering at a smooth dielectric interface (the Glass Slab / caustic
+// material of Sec. 6), as an AD expression of the incoming direction w_in and
+// the unit shading normal ns (same side as the unit geometric normal ng).
+// The lobe is chosen with the unpolarized Fresnel reflectance F (textbook
+// s/p amplitudes, relative index eta = n_from / n_to): reflect iff
+// u_lobe < F, else refract by Snell's law; either lobe has weight 1, so the
+// throughput is unchanged.  Returns 7 (and no direction) when w_in arrives
+// from behind the shading normal, 8 when the new direction falls on the wrong
+// side of the geometric normal (the path ends), else 0.
+int dielectric_event(const V3& w_in, const V3& ns, D3 ng, double ior, double u_lobe, V3& wo, bool& reflect,
+                     double& F) {
+  const double cos_g = dot(val(w_in), ng);
+  const bool entering = cos_g < 0.0;
+  const double eta = entering ? 1.0 / ior : ior;
+  const V3 n = entering ? ns : ns * V(-1.0);
+  const V cosi = -dot(w_in, n);
+  reflect = false;
+  F = 0.0;
+  if (cosi.v <= 0.0) return 7;
+  const double sin2t = eta * eta * (1.0 - cosi.v * cosi.v);
+  if (sin2t >= 1.0) {
+    F = 1.0;  // total internal reflection
+  } else {
+    const double cost_d = std::sqrt(1.0 - sin2t);
+    const double ei = entering ? 1.0 : ior, et = entering ? ior : 1.0;
+    const double rs = (ei * cosi.v - et * cost_d) / (ei * cosi.v + et * cost_d);
+    const double rp = (et * cosi.v - ei * cost_d) / (et * cosi.v + ei * cost_d);
+    F = 0.5 * (rs * rs + rp * rp);
+  }
+  reflect = u_lobe < F;
+  if (reflect) {
+    wo = w_in + n * (V(2.0) * cosi);
+  } else {
+    const V cost = vsqrt(V(1.0) - V(eta * eta) * (V(1.0) - cosi * cosi));
+    wo = w_in * V(eta) + n * (V(eta) * cosi - cost);
+  }
+  const double side_in = -cos_g;  // > 0 when the ray arrived on the +ng side
+  const double s_out = dot(val(wo), ng);
+  if (reflect ? (s_out * side_in <= 0.0) : (s_out * side_in >= 0.0)) return 8;
+  return 0;
+}
+
 struct Conn { V C[3]; V ux, uy; int depth; };
 
 struct PathResult {
@@ -679,36 +721,13 @@ void trace_path(const Scene& S, const ora_args& A, uint32_t path, PathResult& ou
         ns = normalize(V3{-Sx, V(1.0), -Sz});
       }
       if (j == A.max_depth) break;
-      bool entering = cos_in < 0.0;
-      double ior = sc.mat_ior[mat];
-      double eta = entering ? 1.0 / ior : ior;
-      V3 n = entering ? ns : ns * V(-1.0);
-      V cosi = -dot(wcur, n);
-      if (cosi.v <= 0.0) { out.sig = fnv1a(out.sig, 7u); break; }
-      double sin2t = eta * eta * (1.0 - cosi.v * cosi.v);
-      double F;
-      double cost_d = 0.0;
-      if (sin2t >= 1.0) F = 1.0;
-      else {
-        cost_d = std::sqrt(1.0 - sin2t);
-        double ei = entering ? 1.0 : ior, et = entering ? ior : 1.0;
-        double rs = (ei * cosi.v - et * cost_d) / (ei * cosi.v + et * cost_d);
-        double rp = (et * cosi.v - ei * cost_d) / (et * cosi.v + ei * cost_d);
-        F = 0.5 * (rs * rs + rp * rp);
-      }
-      bool reflect = uj.u[2] < F;
-      out.sig = fnv1a(out.sig, reflect ? 2u : 4u);
       V3 wo;
-      if (reflect) wo = wcur + n * (V(2.0) * cosi);
-      else {
-        V cost = vsqrt(V(1.0) - V(eta * eta) * (V(1.0) - cosi * cosi));
-        wo = wcur * V(eta) + n * (V(eta) * cosi - cost);
-      }
-      double side_in = -cos_in;  // > 0 when the ray arrived on the +ng side
-      double s_out = dot(val(wo), ngd);
-      if (reflect ? (s_out * side_in <= 0.0) : (s_out * side_in >= 0.0)) {
-        out.sig = fnv1a(out.sig, 8u); break;
-      }
+      bool reflect = false;
+      double F = 0.0;
+      int code = dielectric_event(wcur, ns, ngd, sc.mat_ior[mat], uj.u[2], wo, reflect, F);
+      if (code == 7) { out.sig = fnv1a(out.sig, 7u); break; }
+      out.sig = fnv1a(out.sig, reflect ? 2u : 4u);
+      if (code == 8) { out.sig = fnv1a(out.sig, 8u); break; }
       xprev = x; wcur = wo;
       offn = ngd; off = true;
     }
@@ -757,6 +776,23 @@ int ora_reservoir(const double* w, const double* u, int k, double* W_out) {
   }
   if (W_out) *W_out = R ? Om / wr : 0.0;
   return R;
+}
+
+// One dielectric scattering event with constant inputs (w_in, ng, ns unit
+// 3-vectors; ns on the side of ng): writes the new direction wo (when the
+// return value is 0 or 8), whether the reflection lobe was taken and the
+// Fresnel reflectance F.  Returns the event code of dielectric_event.
+int ora_dielectric(const double* w_in, const double* ng, const double* ns, double ior, double u_lobe, double* wo,
+                   int32_t* reflect, double* F) {
+  V3 w = cst({w_in[0], w_in[1], w_in[2]}), n = cst({ns[0], ns[1], ns[2]});
+  V3 o;
+  bool refl = false;
+  double f = 0.0;
+  int code = dielectric_event(w, n, {ng[0], ng[1], ng[2]}, ior, u_lobe, o, refl, f);
+  if (code != 7) { wo[0] = o.x.v; wo[1] = o.y.v; wo[2] = o.z.v; }
+  if (reflect) *reflect = refl ? 1 : 0;
+  if (F) *F = f;
+  return code;
 }
 
 // Forward render.  image: [H][W][3] (overwritten).  Optional outputs:

@@ -9,6 +9,8 @@ Functions mirror the oracle's C entry points:
                         (naive) or of the ResLRB estimator (Eq. 11)
   loss_and_adjoint(I, T)  mean-squared error and dLoss/dI
   reservoir(w, u)       capacity-one weighted reservoir (Eq. 8)
+  dielectric(...)       one smooth-dielectric scattering event (Fresnel
+                        lobe choice, Snell refraction, mirror reflection)
   philox(seed, ctr)     Philox-4x32-10 block (Salmon et al. 2011)
   guide_*               the learned emission guide (an extension: MLP to a
                         folded vMF mixture, its sampler and density, the
@@ -92,6 +94,8 @@ def _load():
         _lib.ora_guide_emit.argtypes = [C.POINTER(_Scene), C.POINTER(_Args), dp, ip]
         _lib.ora_guide_emit.restype = C.c_int
         _lib.ora_guide_loss_grad.argtypes = [C.POINTER(_Scene), dp, dp, C.c_int64, C.c_int, dp, dp]
+        _lib.ora_dielectric.argtypes = [dp, dp, dp, C.c_double, C.c_double, dp, ip, dp]
+        _lib.ora_dielectric.restype = C.c_int
         assert _lib.ora_guide_nparams() == GUIDE_NPARAMS
     return _lib
 
@@ -238,6 +242,21 @@ def reservoir(w, u):
     Wr = C.c_double(0.0)
     R = lib.ora_reservoir(_p(w), _p(u), len(w), C.byref(Wr))
     return R, Wr.value
+
+
+def dielectric(w_in, ng, ns, ior, u_lobe):
+    """One smooth-dielectric scattering event (the oracle's own step):
+    returns (code, wo, reflect, F) with code 0 ok, 7 arrival behind the
+    shading normal, 8 new direction on the wrong side of the geometric
+    normal; wo the outgoing unit direction, F the Fresnel reflectance."""
+    lib = _load()
+    w_in, ng, ns = (np.ascontiguousarray(a, np.float64) for a in (w_in, ng, ns))
+    wo = np.zeros(3)
+    refl = C.c_int32(0)
+    F = C.c_double(0.0)
+    code = lib.ora_dielectric(_p(w_in), _p(ng), _p(ns), float(ior), float(u_lobe), _p(wo), C.byref(refl),
+                              C.byref(F))
+    return int(code), wo, bool(refl.value), F.value
 
 
 def philox(seed, ctr):

@@ -215,6 +215,42 @@ def plane_point_light_scene(width=32, height=32, rho=0.6, I0=5.0, light_h=0.8,
     )
 
 
+def two_plane_point_light_scene(width=8, height=8, rho_floor=0.7, rho_wall=0.5, I0=5.0,
+                                light=(-0.3, 0.8, 0.1), fov_deg=30.0):
+    """Point light, a Lambertian floor and a Lambertian wall, seen by a
+    pinhole camera that sees only the wall.
+
+    Floor: y = 0, x,z in [-1, 1], albedo rho_floor (texture 0), normal +y.
+    Wall: x = 1, y in [0, 2], z in [-1, 1], albedo rho_wall (texture 1),
+    normal -x.  Isotropic point light of intensity I0 at `light`.  Camera at
+    (-0.5, 1, 0) looking along +x (up +y) with a narrow field of view: its
+    view cone meets only the wall, and no floor point projects onto the film.
+    The light paths light -> floor -> wall put their second vertex on the
+    visible wall, so the depth-2 part of the image has a closed form (a
+    pixel-filtered integral over the floor of the once-scattered radiance).
+    """
+    b = _Builder()
+    b.quad((-1, 0, -1), (0, 0, 2), (2, 0, 0), 0)   # floor, normal +y
+    b.quad((1, 0, -1), (0, 0, 2), (0, 2, 0), 1)    # wall, normal -x
+    tri_v, tri_uv, tri_mat = b.arrays()
+    albedo = np.zeros((2, 1, 1, 3))
+    albedo[0] = rho_floor
+    albedo[1] = rho_wall
+    return dict(
+        name="two_plane_point",
+        tri_v=tri_v, tri_uv=tri_uv, tri_mat=tri_mat,
+        mat_type=np.array([MAT_LAMBERT, MAT_LAMBERT], np.int32), mat_tex=np.array([0, 1], np.int32),
+        mat_ior=np.array([1.0, 1.0]),
+        n_tex=2, tex_res=1,
+        emitter=dict(type=EMIT_POINT, o=np.array(light, float), e1=np.zeros(3), e2=np.zeros(3)),
+        camera=dict(pos=np.array([-0.5, 1.0, 0.0]), target=np.array([1.0, 1.0, 0.0]),
+                    up=np.array([0.0, 1.0, 0.0]), fov_deg=fov_deg, width=width, height=height),
+        hf=None,
+        albedo=albedo, Le=np.full(3, float(I0)), heights=None,
+        albedo_target=None, heights_target=None,
+    )
+
+
 def batched_instances(n=48, seed=7):
     """Size table of a batch of uneven inverse-rendering instances.
 
