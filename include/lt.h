@@ -370,8 +370,9 @@ typedef struct lt_batch lt_batch;
 typedef struct {
   lt_ctx* ctx;            /* context holding this instance's uploaded scene; every
                              instance's context uses the batch's device */
-  lt_trace_args args;     /* seed, n_paths, max_depth, flags: 0 or LT_ATTACHED; mask,
-                             signatures, info and contributions must be NULL */
+  lt_trace_args args;     /* seed, n_paths, max_depth, flags: 0 or LT_ATTACHED; path_mask
+                             as for lt_trace (DEVICE [n_paths] or NULL); signatures,
+                             info and contributions must be NULL */
   lt_params params;       /* as for lt_backward_lrb3 (guide_w allowed) */
   const float* target;    /* DEVICE [height][width][3] loss target */
   float* image;           /* DEVICE [height][width][3], overwritten with the estimate */

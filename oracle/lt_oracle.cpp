@@ -560,12 +560,25 @@ struct Conn { V C[3]; V ux, uy; int depth; };
 struct PathResult {
   std::vector<Conn> conns;
   uint32_t sig; int R; double W;
+  // An ill-conditioned vertex lies at or before the path's last sensor
+  // connection: a grazing hit (|cos| < 0.02), a segment shorter than 0.02
+  // scene units, a refraction with cos_t < 0.1, or a connection within
+  // 1e-3 px of a kink of the tent filter.  Test bookkeeping only (the
+  // derivatives of such paths amplify rounding by 1/cos^2, 1/length or a
+  // one-sided filter slope); it changes nothing the oracle computes.
+  bool illc;
 };
+
+inline bool near_tent_kink(double u) {
+  double d = u - 0.5;
+  return std::fabs(d - std::nearbyint(d)) < 1e-3;
+}
 
 // Trace one light path as an AD expression of the parameters.
 void trace_path(const Scene& S, const ora_args& A, uint32_t path, PathResult& out) {
   const ora_scene& sc = *S.s;
-  out.conns.clear(); out.sig = 0x811C9DC5u; out.R = 0; out.W = 0.0;
+  out.conns.clear(); out.sig = 0x811C9DC5u; out.R = 0; out.W = 0.0; out.illc = false;
+  bool ill = false;  // ill-conditioned vertex so far
   const int W = sc.width, H = sc.height;
   const double Kfilm = (double)W * H / (4.0 * S.aspect * S.tan_half * S.tan_half * (double)A.n_paths);
 
@@ -638,6 +651,10 @@ void trace_path(const Scene& S, const ora_args& A, uint32_t path, PathResult& ou
     D3 ngd = val(ng), wd_in = val(wcur);
     double cos_in = dot(wd_in, ngd);
     Uniform4 uj = rng4(A.seed, path, (uint32_t)j, 0);
+    {
+      D3 seg = val(x) - val(xprev);
+      if (std::fabs(cos_in) < 0.02 || dot(seg, seg) < 4e-4) ill = true;
+    }
 
     if (mtype == ORA_LAMBERT) {
       // texel (nearest), from primal chart coordinates
@@ -691,6 +708,8 @@ void trace_path(const Scene& S, const ora_args& A, uint32_t path, PathResult& ou
                 if (uj.u[3] < om / Omega) { out.R = j; omegaR = om; }
               }
               out.conns.push_back(cn);
+              if (near_tent_kink(ux.v) || near_tent_kink(uy.v)) ill = true;
+              out.illc = ill;
             }
           }
         }
@@ -726,6 +745,7 @@ void trace_path(const Scene& S, const ora_args& A, uint32_t path, PathResult& ou
       double F = 0.0;
       int code = dielectric_event(wcur, ns, ngd, sc.mat_ior[mat], uj.u[2], wo, reflect, F);
       if (code == 7) { out.sig = fnv1a(out.sig, 7u); break; }
+      if (!reflect && std::fabs(dot(val(wo), val(ns))) < 0.1) ill = true;  // refraction near the critical angle
       out.sig = fnv1a(out.sig, reflect ? 2u : 4u);
       if (code == 8) { out.sig = fnv1a(out.sig, 8u); break; }
       xprev = x; wcur = wo;
@@ -797,10 +817,12 @@ int ora_dielectric(const double* w_in, const double* ng, const double* ns, doubl
 
 // Forward render.  image: [H][W][3] (overwritten).  Optional outputs:
 // slices [D][H][W][3] (connections of vertex i land in slice i-1),
-// sig/R/Wres per listed path, flux = sum over connections of C (3 doubles).
+// sig/R/Wres per listed path, flux = sum over connections of C (3 doubles),
+// info per listed path (bit 1: an ill-conditioned vertex at or before the
+// last sensor connection, see PathResult).
 int ora_render(const ora_scene* sc, const ora_args* A, const double* albedo, const double* Le,
                const double* heights, double* image, double* slices, uint32_t* sig, int32_t* Rout,
-               double* Wout, double* flux) {
+               double* Wout, double* flux, uint32_t* info) {
   if (A->guide_w && sc->em_type != ORA_EMIT_QUAD) return -1;  // the guide steers area emission only
   Scene S; S.init(sc, albedo, Le, heights, false);
   const int W = sc->width, H = sc->height, D = A->max_depth;
@@ -824,6 +846,7 @@ int ora_render(const ora_scene* sc, const ora_args* A, const double* albedo, con
       if (sig) sig[k] = pr.sig;
       if (Rout) Rout[k] = pr.R;
       if (Wout) Wout[k] = pr.W;
+      if (info) info[k] = pr.illc ? 2u : 0u;
       for (size_t ci = 0; ci < pr.conns.size(); ++ci) {
         const Conn& cn = pr.conns[ci];
         double scale = 1.0;

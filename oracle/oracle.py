@@ -81,7 +81,7 @@ def _load():
             build()
         _lib = C.CDLL(_LIB)
         dp, ip, up = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_uint32)
-        _lib.ora_render.argtypes = [C.POINTER(_Scene), C.POINTER(_Args), dp, dp, dp, dp, dp, up, ip, dp, dp]
+        _lib.ora_render.argtypes = [C.POINTER(_Scene), C.POINTER(_Args), dp, dp, dp, dp, dp, up, ip, dp, dp, up]
         _lib.ora_gradient.argtypes = [C.POINTER(_Scene), C.POINTER(_Args), C.c_int, dp, dp, dp, dp, dp, dp, dp]
         _lib.ora_reservoir.argtypes = [dp, dp, C.c_int, dp]
         _lib.ora_reservoir.restype = C.c_int
@@ -178,7 +178,8 @@ def _params(sc, albedo, Le, heights, keep):
 def render(sc, seed, n_paths, depth, albedo=None, Le=None, heights=None, flags=0,
            path_list=None, slices=False, per_path=False, threads=0, guide_w=None, guide_bf16=True):
     """FP64 light-tracing image [H,W,3] (plus optional per-depth slices,
-    per-path signature / reservoir index R / weight W, and total flux).
+    per-path signature / reservoir index R / weight W / ill-conditioning
+    flag, and total flux).
     guide_w: emission-guide weights (guided emission), else cosine emission."""
     lib = _load()
     keep = _Keep()
@@ -192,16 +193,17 @@ def render(sc, seed, n_paths, depth, albedo=None, Le=None, heights=None, flags=0
     sig = np.zeros(n, np.uint32) if per_path else None
     R = np.zeros(n, np.int32) if per_path else None
     Wr = np.zeros(n) if per_path else None
+    info = np.zeros(n, np.uint32) if per_path else None
     flux = np.zeros(3)
     rc = lib.ora_render(C.byref(s), C.byref(a), _p(alb), _p(le), _p(h), _p(img), _p(sl),
-                        _p(sig, C.c_uint32), _p(R, C.c_int32), _p(Wr), _p(flux))
+                        _p(sig, C.c_uint32), _p(R, C.c_int32), _p(Wr), _p(flux), _p(info, C.c_uint32))
     if rc != 0:
         raise ValueError("oracle render rejected its arguments")
     out = dict(image=img, flux=flux)
     if slices:
         out["slices"] = sl
     if per_path:
-        out.update(sig=sig, R=R, W=Wr)
+        out.update(sig=sig, R=R, W=Wr, illc=(info & 2) != 0)
     return out
 
 

@@ -1021,8 +1021,8 @@ lt_status batch_check(lt_batch* b, const lt_instance* inst, int n) {
     if (!c) return b->fail(LT_ERR_ARG, "instance without a context");
     if (c->device != b->device) return b->fail(LT_ERR_ARG, "instance context on another device");
     if (I.args.flags & ~(uint32_t)LT_ATTACHED) return b->fail(LT_ERR_UNSUPPORTED, "batches take flags 0 or LT_ATTACHED only");
-    if (I.args.path_mask || I.args.path_sig || I.args.path_info || I.args.path_contrib)
-      return b->fail(LT_ERR_UNSUPPORTED, "batches take no mask, signatures, info or contributions");
+    if (I.args.path_sig || I.args.path_info || I.args.path_contrib)
+      return b->fail(LT_ERR_UNSUPPORTED, "batches take no signatures, info or contributions");
     lt_status st = check_args(c, &I.args, &I.params);
     if (st != LT_OK) { b->err = "instance " + std::to_string(i) + ": " + c->err; return st; }
     if (!I.target || !I.image || !I.d_image || !I.loss || !I.grads.albedo)

@@ -610,20 +610,28 @@ __global__ void __launch_bounds__(256) k_loss(const float* I, const float* T, si
 __global__ void k_loss_finish(const double* acc, size_t n, float* loss) { loss[0] = (float)(acc[0] / (double)n); }
 
 // Heightfield triangles from the current heights, written at their BVH slots.
+// The edges are built from height differences and whole grid steps, not by
+// subtracting rounded corner positions: base + h rounds to about 6e-8 at
+// base 0.6, which on a 1/127 grid spacing would put ~1e-5 of error on every
+// facet slope, whereas h_k - h_0 and (i_k - i_0) dx are exact or nearly so.
 __global__ void k_hf_tris(DevScene sc, const int32_t* slot_of_prim, Tri* tris, const float* h) {
   int nhf = 2 * (sc.hf_G - 1) * (sc.hf_G - 1);
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nhf) return;
-  f3 P[3];
+  int gi[3], gj[3];
+  float hv[3];
   for (int k = 0; k < 3; ++k) {
-    int gi, gj; hf_corner(sc.hf_G, q, k, gi, gj);
-    P[k] = mk(sc.hf_x0 + gi * sc.hf_dx, sc.hf_base + hget(h, sc.hf_G, gi, gj), sc.hf_z0 + gj * sc.hf_dx);
+    hf_corner(sc.hf_G, q, k, gi[k], gj[k]);
+    hv[k] = hget(h, sc.hf_G, gi[k], gj[k]);
   }
   Tri t;
-  t.p0[0] = P[0].x; t.p0[1] = P[0].y; t.p0[2] = P[0].z; t.prim = sc.n_static + q;
-  f3 e1 = P[1] - P[0], e2 = P[2] - P[0];
-  t.e1[0] = e1.x; t.e1[1] = e1.y; t.e1[2] = e1.z; t.pad1 = 0.f;
-  t.e2[0] = e2.x; t.e2[1] = e2.y; t.e2[2] = e2.z; t.pad2 = 0.f;
+  t.p0[0] = sc.hf_x0 + gi[0] * sc.hf_dx;
+  t.p0[1] = sc.hf_base + hv[0];
+  t.p0[2] = sc.hf_z0 + gj[0] * sc.hf_dx;
+  t.prim = sc.n_static + q;
+  t.e1[0] = (float)(gi[1] - gi[0]) * sc.hf_dx; t.e1[1] = hv[1] - hv[0]; t.e1[2] = (float)(gj[1] - gj[0]) * sc.hf_dx;
+  t.e2[0] = (float)(gi[2] - gi[0]) * sc.hf_dx; t.e2[1] = hv[2] - hv[0]; t.e2[2] = (float)(gj[2] - gj[0]) * sc.hf_dx;
+  t.pad1 = 0.f; t.pad2 = 0.f;
   tris[slot_of_prim[sc.n_static + q]] = t;
 }
 

@@ -180,37 +180,37 @@ class Context:
         except Exception:
             pass
 
-    def _check(self, st):
+    def _status(self, st):
         if st != LT_OK:
             raise LTError(st, self.lib.lt_last_error(self.h).decode())
 
     def _stream(self):
         s = torch.cuda.current_stream(self.device)
-        self._check(self.lib.lt_set_stream(self.h, C.c_void_p(s.cuda_stream)))
+        self._status(self.lib.lt_set_stream(self.h, C.c_void_p(s.cuda_stream)))
 
     def set_tuning(self, block=128, blocks_per_cu=10, lds_grad=1):
         t = Tuning(block, blocks_per_cu, lds_grad)
-        self._check(self.lib.lt_set_tuning(self.h, C.byref(t)))
+        self._status(self.lib.lt_set_tuning(self.h, C.byref(t)))
 
     def get_tuning(self):
         t = Tuning()
-        self._check(self.lib.lt_get_tuning(self.h, C.byref(t)))
+        self._status(self.lib.lt_get_tuning(self.h, C.byref(t)))
         return dict(block=t.block, blocks_per_cu=t.blocks_per_cu, lds_grad=t.lds_grad)
 
     def read_counters(self, reset=True):
         """Event counts of the LT_COUNTERS build (see lt_read_counters)."""
         out = (C.c_uint64 * 16)()
-        self._check(self.lib.lt_read_counters(self.h, out, int(reset)))
+        self._status(self.lib.lt_read_counters(self.h, out, int(reset)))
         names = ["rays", "shadow_rays", "nodes", "tris", "splats", "gathers", "grad_values", "paths",
                  "tape_written", "tape_read"]
         return {k: int(out[i]) for i, k in enumerate(names)}
 
     def set_memory_cap(self, nbytes):
-        self._check(self.lib.lt_set_memory_cap(self.h, int(nbytes)))
+        self._status(self.lib.lt_set_memory_cap(self.h, int(nbytes)))
 
     def stats(self):
         s = Stats()
-        self._check(self.lib.lt_get_stats(self.h, C.byref(s)))
+        self._status(self.lib.lt_get_stats(self.h, C.byref(s)))
         return dict(guard_triggers=s.guard_triggers, nonfinite=s.nonfinite)
 
     # ------------------------------------------------------------ scene
@@ -247,7 +247,7 @@ class Context:
             d.hf_G, d.hf_x0, d.hf_z0 = int(hf["G"]), float(hf["x0"]), float(hf["z0"])
             d.hf_dx, d.hf_base, d.hf_mat = float(hf["dx"]), float(hf["base"]), int(hf["mat"])
         self._stream()
-        self._check(self.lib.lt_scene_upload(self.h, C.byref(d)))
+        self._status(self.lib.lt_scene_upload(self.h, C.byref(d)))
         self.scene = sc
         self.W, self.H = d.width, d.height
         return self
@@ -262,7 +262,38 @@ class Context:
         a.path_contrib = None if contrib is None else contrib.data_ptr()
         return a
 
+    def _sizes(self):
+        sc = self.scene
+        if sc is None:
+            raise LTError(LT_ERR_STATE, "no scene uploaded")
+        hf = sc.get("hf")
+        G = int(hf["G"]) if hf is not None else 0
+        return int(sc["n_tex"]) * int(sc["tex_res"]) ** 2 * 3, G * G
+
+    def _check(self, t, name, numel):
+        """A parameter or gradient array the kernels read or write through a
+        raw pointer: float32, contiguous, on this context's device, with the
+        element count the uploaded scene implies."""
+        if t is None:
+            return
+        if not isinstance(t, torch.Tensor):
+            raise ValueError(f"{name} must be a torch tensor")
+        if t.dtype != torch.float32:
+            raise ValueError(f"{name} must be float32, got {t.dtype}")
+        if t.device.type != "cuda" or (t.device.index or 0) != (self.device.index or 0):
+            raise ValueError(f"{name} must live on {self.device}, got {t.device}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.numel() != numel:
+            raise ValueError(f"{name} has {t.numel()} elements, the scene needs {numel}")
+
     def params(self, albedo, Le, heights=None, guide_w=None):
+        n_alb, n_h = self._sizes()
+        self._check(albedo, "albedo", n_alb)
+        self._check(Le, "Le", 3)
+        if heights is not None:
+            self._check(heights, "heights", n_h)
+        self._check(guide_w, "guide_w", GUIDE_NPARAMS)
         return Params(albedo.data_ptr(), Le.data_ptr(), None if heights is None else heights.data_ptr(),
                       None if guide_w is None else guide_w.data_ptr())
 
@@ -275,14 +306,18 @@ class Context:
     def trace(self, a, p, image, side=None):
         self._stream()
         nb = 0 if side is None else side.numel() * side.element_size()
-        self._check(self.lib.lt_trace(self.h, C.byref(a), C.byref(p), _ptr(image), _ptr(side), nb))
+        self._status(self.lib.lt_trace(self.h, C.byref(a), C.byref(p), _ptr(image), _ptr(side), nb))
 
     def loss_l2(self, image, target, d_image, loss):
         self._stream()
-        self._check(self.lib.lt_loss_l2(self.h, _ptr(image), _ptr(target), image.numel(), _ptr(d_image),
+        self._status(self.lib.lt_loss_l2(self.h, _ptr(image), _ptr(target), image.numel(), _ptr(d_image),
                                         _ptr(loss)))
 
     def _grads(self, g_albedo, g_Le, g_heights):
+        n_alb, n_h = self._sizes()
+        self._check(g_albedo, "g_albedo", n_alb)
+        self._check(g_Le, "g_Le", 3)
+        self._check(g_heights, "g_heights", n_h)
         return Grads(None if g_albedo is None else g_albedo.data_ptr(),
                      None if g_Le is None else g_Le.data_ptr(),
                      None if g_heights is None else g_heights.data_ptr())
@@ -291,41 +326,41 @@ class Context:
         self._stream()
         g = self._grads(g_albedo, g_Le, g_heights)
         nb = tape.numel() * tape.element_size()
-        self._check(self.lib.lt_backward_naive(self.h, C.byref(a), C.byref(p), _ptr(d_image), _ptr(tape), nb,
+        self._status(self.lib.lt_backward_naive(self.h, C.byref(a), C.byref(p), _ptr(d_image), _ptr(tape), nb,
                                                C.byref(g)))
 
     def backward_reslrb(self, a, p, d_image, records, g_albedo, g_Le, g_heights=None):
         self._stream()
         g = self._grads(g_albedo, g_Le, g_heights)
         nb = records.numel() * records.element_size()
-        self._check(self.lib.lt_backward_reslrb(self.h, C.byref(a), C.byref(p), _ptr(d_image), _ptr(records),
+        self._status(self.lib.lt_backward_reslrb(self.h, C.byref(a), C.byref(p), _ptr(d_image), _ptr(records),
                                                 nb, C.byref(g)))
 
     def backward_lrb3(self, a, p, d_image, g_albedo, g_Le, g_heights=None):
         self._stream()
         g = self._grads(g_albedo, g_Le, g_heights)
-        self._check(self.lib.lt_backward_lrb3(self.h, C.byref(a), C.byref(p), _ptr(d_image), C.byref(g)))
+        self._status(self.lib.lt_backward_lrb3(self.h, C.byref(a), C.byref(p), _ptr(d_image), C.byref(g)))
 
     # ------------------------------------------------------------ guide
     def guide_eval(self, guide_w, x, n, out):
         """Raw network outputs out [count, 41] at x, n [count, 3] (device float32)."""
         self._stream()
-        self._check(self.lib.lt_guide_eval(self.h, _ptr(guide_w), _ptr(x), _ptr(n), x.shape[0], _ptr(out)))
+        self._status(self.lib.lt_guide_eval(self.h, _ptr(guide_w), _ptr(x), _ptr(n), x.shape[0], _ptr(out)))
 
     def guide_emit(self, a, p, samples, contrib=None):
         """Guided emission of paths [0, n_paths) as samples [n_paths, 12]."""
         self._stream()
-        self._check(self.lib.lt_guide_emit(self.h, C.byref(a), C.byref(p), _ptr(contrib), _ptr(samples)))
+        self._status(self.lib.lt_guide_emit(self.h, C.byref(a), C.byref(p), _ptr(contrib), _ptr(samples)))
 
     def guide_grad(self, guide_w, samples, grad, loss=None):
         """Training loss and gradient over samples [count, 12] (device float32)."""
         self._stream()
-        self._check(self.lib.lt_guide_grad(self.h, _ptr(guide_w), _ptr(samples), samples.shape[0], _ptr(grad),
+        self._status(self.lib.lt_guide_grad(self.h, _ptr(guide_w), _ptr(samples), samples.shape[0], _ptr(grad),
                                            _ptr(loss)))
 
     def guide_adam(self, w, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         self._stream()
-        self._check(self.lib.lt_guide_adam(self.h, _ptr(w), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr),
+        self._status(self.lib.lt_guide_adam(self.h, _ptr(w), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr),
                                            float(beta1), float(beta2), float(eps)))
 
     def guide_train_step(self, a, guide_w, contrib, samples, grad, m, v, step, lr, loss=None, beta1=0.9,
@@ -333,7 +368,7 @@ class Context:
         """Emission samples paired with contrib, loss gradient and one Adam
         step on guide_w in place (samples: [n_samples, 12] device float32)."""
         self._stream()
-        self._check(self.lib.lt_guide_train_step(self.h, C.byref(a), _ptr(guide_w), _ptr(contrib), _ptr(samples),
+        self._status(self.lib.lt_guide_train_step(self.h, C.byref(a), _ptr(guide_w), _ptr(contrib), _ptr(samples),
                                                  samples.shape[0], _ptr(grad), _ptr(m), _ptr(v), _ptr(loss),
                                                  int(step), float(lr), float(beta1), float(beta2), float(eps)))
 
@@ -342,7 +377,8 @@ class Batch:
     """Runner of batched optimisation steps (lt_batch_*) on torch's current
     stream of `device`.  An instance is a dict with keys ctx (Context), seed,
     n_paths, depth, attached (bool), albedo, Le, heights, guide (tensors or
-    None), target, image, d_image, loss, g_albedo, g_Le, g_heights."""
+    None), target, image, d_image, loss, g_albedo, g_Le, g_heights, and
+    optionally mask (uint8 [n_paths] on the device, as lt_trace's path mask)."""
 
     def __init__(self, device=0):
         self.lib = library(LIB_PATH)
@@ -372,7 +408,8 @@ class Batch:
         for k, d in enumerate(instances):
             ctx = d["ctx"]
             arr[k].ctx = ctx.h
-            arr[k].args = ctx.args(d["seed"], d["n_paths"], d["depth"], ATTACHED if d.get("attached") else 0)
+            arr[k].args = ctx.args(d["seed"], d["n_paths"], d["depth"], ATTACHED if d.get("attached") else 0,
+                                   d.get("mask"))
             arr[k].params = ctx.params(d["albedo"], d["Le"], d.get("heights"), d.get("guide"))
             arr[k].target, arr[k].image = d["target"].data_ptr(), d["image"].data_ptr()
             arr[k].d_image, arr[k].loss = d["d_image"].data_ptr(), d["loss"].data_ptr()
@@ -467,35 +504,38 @@ MODES = ("naive", "reslrb", "lrb3")
 
 
 class LightTrace(torch.autograd.Function):
-    """image = LightTrace.apply(albedo, Le, heights, ctx, seed, n_paths, depth, mode, flags)
+    """image = LightTrace.apply(albedo, Le, heights, ctx, seed, n_paths, depth, mode, flags, mask)
 
     Forward runs lt_trace (recording the tape for "naive" or the reservoir
     records for "reslrb"); backward runs the matching lt_backward_* with the
     incoming image adjoint.  Seed replay is the recomputation: "lrb3" keeps
-    no side state at all.
+    no side state at all.  mask (optional, uint8 [n_paths] on the device):
+    paths whose byte is 0 contribute nothing to the image or the gradients.
     """
 
     @staticmethod
-    def forward(fctx, albedo, Le, heights, ctx, seed, n_paths, depth, mode="lrb3", flags=0):
+    def forward(fctx, albedo, Le, heights, ctx, seed, n_paths, depth, mode="lrb3", flags=0, mask=None):
         if mode not in MODES:
             raise ValueError(mode)
+        if mask is not None and (mask.dtype != torch.uint8 or mask.numel() != n_paths or not mask.is_contiguous()):
+            raise ValueError("mask must be a contiguous uint8 tensor with one byte per path")
         rec = RECORD_TAPE if mode == "naive" else RECORD_RESERVOIR if mode == "reslrb" else 0
-        a = ctx.args(seed, n_paths, depth, flags | rec)
+        a = ctx.args(seed, n_paths, depth, flags | rec, mask)
         p = ctx.params(albedo, Le, heights)
         nb = ctx.side_state_bytes(a)
         side = torch.empty(max(nb, 1), dtype=torch.uint8, device=albedo.device) if nb else None
         image = torch.empty((ctx.H, ctx.W, 3), dtype=torch.float32, device=albedo.device)
         ctx.trace(a, p, image, side)
-        fctx.lt = (ctx, seed, n_paths, depth, mode, flags | rec, side)
+        fctx.lt = (ctx, seed, n_paths, depth, mode, flags | rec, side, mask)
         fctx.save_for_backward(albedo, Le, heights if heights is not None else torch.empty(0, device=albedo.device))
         return image
 
     @staticmethod
     def backward(fctx, grad_image):
-        ctx, seed, n_paths, depth, mode, flags, side = fctx.lt
+        ctx, seed, n_paths, depth, mode, flags, side, mask = fctx.lt
         albedo, Le, heights = fctx.saved_tensors
         heights = heights if heights.numel() else None
-        a = ctx.args(seed, n_paths, depth, flags)
+        a = ctx.args(seed, n_paths, depth, flags, mask)
         p = ctx.params(albedo, Le, heights)
         dI = grad_image.to(torch.float32).contiguous()
         g_alb = torch.zeros_like(albedo)
@@ -507,4 +547,4 @@ class LightTrace(torch.autograd.Function):
             ctx.backward_reslrb(a, p, dI, side, g_alb, g_le, g_h)
         else:
             ctx.backward_lrb3(a, p, dI, g_alb, g_le, g_h)
-        return g_alb, g_le, g_h, None, None, None, None, None, None
+        return g_alb, g_le, g_h, None, None, None, None, None, None, None

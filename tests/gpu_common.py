@@ -89,16 +89,57 @@ class GpuRun:
         return out
 
 
-def matched_paths(sc, g, seed, n, depth, flags=0, keep=None):
-    """Per-path signatures from both sides; returns (mask, ids, mismatch fraction).
+def matched_paths(sc, g, seed, n, depth, flags=0, keep=None, want_illc=False):
+    """Per-path signatures from both sides; returns (mask, ids, mismatch fraction)
+    and, with want_illc, the oracle's own per-path ill-conditioning flag
+    (bool [n]: a grazing hit, short segment, near-critical refraction or a
+    connection next to a tent kink at or before the last connection).
     keep: optional boolean [n] pre-selection (e.g. matching guided emission)."""
     ow = None if g.guide is None else g.guide.cpu().numpy().astype(np.float64)
     gs = g.trace(seed, n, depth, flags, want_sig=True)["sig"]
-    os_ = O.render(sc, seed, n, depth, flags=flags, per_path=True, guide_w=ow)["sig"]
-    same = gs == os_
+    r = O.render(sc, seed, n, depth, flags=flags, per_path=True, guide_w=ow)
+    same = gs == r["sig"]
     if keep is not None:
         same &= keep
-    return same.astype(np.uint8), np.nonzero(same)[0].astype(np.uint32), 1.0 - same.mean()
+    out = (same.astype(np.uint8), np.nonzero(same)[0].astype(np.uint32), 1.0 - same.mean())
+    return out + (r["illc"],) if want_illc else out
+
+
+def matched_sample(sc, g, seed, n, depth, ids, flags=0):
+    """A seeded sample `ids` of the n paths: those whose signatures agree on
+    both sides (the GPU runs at full n with the sample kept by the path mask)
+    and, with a guide, whose guided emission agrees too; plus the oracle's
+    ill-conditioning flag of each kept path.
+    Returns (kept ids, illc of the kept ids)."""
+    ids = np.asarray(ids, np.uint32)
+    mask = np.zeros(n, np.uint8)
+    mask[ids] = 1
+    ow = None if g.guide is None else g.guide.cpu().numpy().astype(np.float64)
+    gs = g.trace(seed, n, depth, flags, mask=mask, want_sig=True)["sig"][ids]
+    r = O.render(sc, seed, n, depth, flags=flags, path_list=ids, per_path=True, guide_w=ow)
+    same = gs == r["sig"]
+    if ow is not None:
+        same &= guide_sample_match(sc, g, seed, n, ids)
+    return ids[same], r["illc"][same]
+
+
+def guide_sample_match(sc, g, seed, n, ids, tol=2e-6, pdf_rtol=2e-5):
+    """guide_emission_match on a sample of the paths (boolean per id)."""
+    a = g.ctx.args(seed, n, 1)
+    smp = torch.zeros((n, 12), dtype=torch.float32, device=g.dev)
+    g.ctx.guide_emit(a, g.params(), smp)
+    torch.cuda.synchronize()
+    gs = smp.cpu().numpy().astype(np.float64)[np.asarray(ids, np.int64)]
+    oe = O.guide_emit(sc, seed, n, g.guide.cpu().numpy().astype(np.float64), path_list=ids)
+    same = (gs[:, 11].astype(np.int32) == oe["comp"]) & (np.abs(gs[:, 6:9] - oe["w"]).max(axis=1) <= tol)
+    same &= np.abs(gs[:, 9] - oe["pdf"]) <= pdf_rtol * np.abs(oe["pdf"])
+    return same
+
+
+def mask_of(n, ids):
+    m = np.zeros(n, np.uint8)
+    m[np.asarray(ids, np.int64)] = 1
+    return m
 
 
 def guide_emission_match(sc, g, seed, n, tol=2e-6, pdf_rtol=2e-5):

@@ -169,3 +169,61 @@ def test_batch_rejects_unsupported():
     with pytest.raises(lt.LTError) as e:
         b.step(insts, table=arr)
     assert e.value.status == lt.LT_ERR_UNSUPPORTED
+
+
+def test_batched_step_against_oracle():
+    from oracle import oracle as O
+    from tests.gpu_common import GpuRun, mask_of, matched_sample, maxrel
+    dev = torch.device("cuda", 0)
+    insts, refs = [], []
+    for k, (kind, G, film, n, D, guided) in enumerate(SPECS):
+        sc = scenes.box_scene(width=film, height=film) if kind == "box" else \
+            scenes.caustic_scene(G=G, width=film, height=film)
+        g = GpuRun(sc)
+        if guided:
+            g.set_guide(scenes.guide_aimed_weights())
+        seed = 300 + k
+        att = kind == "caustic"
+        ids = np.sort(np.random.default_rng(k).choice(n, min(n, 768), replace=False)).astype(np.uint32)
+        keep, illc = matched_sample(sc, g, seed, n, D, ids, flags=lt.ATTACHED if att else 0)
+        keep = keep[~illc]
+        if att:
+            first = g.backward("lrb3", seed, n, D, np.ones((film, film, 3)), flags=lt.ATTACHED,
+                               mask=mask_of(n, keep), want_info=True)
+            keep = keep[(first["info"][keep] & 1) == 0]
+        assert len(keep) >= 0.8 * len(ids) - 4, (k, len(keep))
+        ow = None if g.guide is None else g.guide.cpu().numpy().astype(np.float64)
+        T = O.render(sc, 7, 4096, D, albedo=sc["albedo_target"] if kind == "box" else None,
+                     heights=sc["heights_target"] if att else None)["image"]
+        Io = O.render(sc, seed, n, D, path_list=keep, guide_w=ow)["image"]
+        Lo, dIo = O.loss_and_adjoint(Io, T)
+        go = O.gradient(sc, seed, n, D, dIo, flags=O.ATTACHED if att else 0, path_list=keep, guide_w=ow)
+        refs.append((Io, Lo, go, len(keep)))
+        tgt = torch.as_tensor(T, dtype=torch.float32, device=dev).contiguous()
+        d = dict(ctx=g.ctx, seed=seed, n_paths=n, depth=D, attached=att, albedo=g.albedo, Le=g.Le,
+                 heights=g.heights if att else None, guide=g.guide, target=tgt, image=torch.empty_like(tgt),
+                 d_image=torch.empty_like(tgt), loss=torch.zeros(1, device=dev),
+                 g_albedo=torch.zeros_like(g.albedo), g_Le=torch.zeros_like(g.Le),
+                 g_heights=torch.zeros_like(g.heights) if att else None,
+                 mask=torch.as_tensor(mask_of(n, keep), device=dev), keep_run=g)
+        insts.append(d)
+    def rel(a, ref):
+        if np.max(np.abs(ref)) == 0:
+            return float(np.max(np.abs(a)))
+        return maxrel(a, ref)
+
+    b = lt.Batch(0)
+    for use_graph in (False, True):
+        _zero(insts)
+        b.step(insts, use_graph=use_graph)
+        torch.cuda.synchronize()
+        for k, d in enumerate(insts):
+            Io, Lo, go, nk = refs[k]
+            ei = rel(d["image"].cpu().numpy(), Io)
+            el = abs(d["loss"].item() - Lo) / Lo
+            eg = [rel(d["g_albedo"].cpu().numpy(), go["albedo"]), rel(d["g_Le"].cpu().numpy(), go["Le"])]
+            if d["attached"]:
+                eg.append(rel(d["g_heights"].cpu().numpy(), go["heights"]))
+            print(f"batch vs oracle ({'graph' if use_graph else 'eager'}) instance {k} {SPECS[k]} on {nk} paths: "
+                  f"image {ei:.1e} loss {el:.1e} grads {' '.join(f'{x:.1e}' for x in eg)}", flush=True)
+            assert ei <= 1e-4 and el <= 1e-4 and max(eg) <= 1e-4, k

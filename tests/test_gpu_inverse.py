@@ -61,3 +61,54 @@ def test_adam_on_heights_reaches_the_noise_floor(mode):
     assert losses[1] <= 0.25 * losses[0]
     assert losses[1] <= 3.0 * floor
     assert ring[0].abs().max() == 0 and ring[-1].abs().max() == 0  # the boundary ring stayed fixed
+
+
+def test_parity_at_heights_moved_by_adam():
+    """The forward and the attached gradient (naive AD, LRB-3, ResLRB) at
+    heights far from the flat start, against the oracle.  The heights come
+    from Adam steps driven by the oracle's own FP64 gradient of the image
+    loss toward the sinusoid target (so no input of the comparison comes from
+    the HIP path); after them the slab's steepest slope is about three times
+    that of the start, the BVH refit moves every heightfield box, and the parity bar
+    is the same as on the flat slab."""
+    from oracle import oracle as O
+    from tests.gpu_common import GpuRun, mask_of, matched_paths, maxrel
+    G, film, D = 16, 64, 4
+    sc = scenes.caustic_scene(G=G, width=film, height=film)
+    free = np.zeros((G, G))
+    free[1:-1, 1:-1] = 1.0
+    free = free.reshape(-1)
+    T = O.render(sc, 0x7A6, 1 << 16, D, heights=sc["heights_target"])["image"]
+    h = sc["heights"].copy()
+    m = np.zeros_like(h)
+    v = np.zeros_like(h)
+    for k in range(12):
+        I = O.render(sc, 900 + k, 16384, D, heights=h)["image"]
+        _, dI = O.loss_and_adjoint(I, T)
+        gh = O.gradient(sc, 900 + k, 16384, D, dI, flags=O.ATTACHED, heights=h)["heights"] * free
+        h, m, v = O.adam(h, gh, m, v, k + 1, lr=2e-3)
+    moved = np.abs(h - sc["heights"]).max()
+    slope0 = np.abs(np.diff(sc["heights"].reshape(G, G), axis=1)).max() * (G - 1)
+    slope = np.abs(np.diff(h.reshape(G, G), axis=1)).max() * (G - 1)
+    print(f"heights moved by up to {moved:.3e}; max x-slope {slope0:.3f} -> {slope:.3f}", flush=True)
+    assert moved > 0.01
+    sc_m = dict(sc, heights=h)
+    g = GpuRun(sc_m)
+    seed, n = 41, 65536
+    mask, ids, mis, illc = matched_paths(sc_m, g, seed, n, D, want_illc=True)
+    assert mis <= 1e-3 and illc.mean() <= 5e-2
+    e = maxrel(g.trace(seed, n, D, mask=mask)["image"], O.render(sc_m, seed, n, D, path_list=ids)["image"])
+    print(f"moved heights: image maxrel {e:.2e}", flush=True)
+    assert e <= 1e-4
+    dI = np.random.default_rng(5).normal(size=(film, film, 3))
+    clean = mask.astype(bool) & ~illc
+    first = g.backward("lrb3", seed, n, D, dI, flags=lt.ATTACHED, mask=clean.astype(np.uint8), want_info=True)
+    guard = (first["info"] & 1) != 0
+    assert guard.mean() <= 1e-2
+    for mode, omode in (("naive", O.MODE_NAIVE), ("lrb3", O.MODE_NAIVE), ("reslrb", O.MODE_RESLRB)):
+        sel = np.nonzero(clean if mode == "naive" else clean & ~guard)[0].astype(np.uint32)
+        ref = O.gradient(sc_m, seed, n, D, dI, mode=omode, flags=O.ATTACHED, path_list=sel)
+        gg = g.backward(mode, seed, n, D, dI, flags=lt.ATTACHED, mask=mask_of(n, sel))
+        eh = maxrel(gg["heights"], ref["heights"])
+        print(f"moved heights {mode}: heights maxrel {eh:.2e}", flush=True)
+        assert eh <= 1e-4, mode

@@ -243,22 +243,66 @@ def test_out_of_range_arguments_are_rejected_before_launch(box64):
     assert torch.all(img == 7.0) and torch.all(ga == 0) and torch.all(gl == 0)
 
 
-def test_autograd_function_matches_direct_calls(box64):
+def test_autograd_function_against_oracle(box64):
+    """LightTrace under torch autograd with a scaled L2 loss, against the
+    oracle's gradient of the same loss on the same (signature-matched)
+    paths: the backward must take the incoming image adjoint, whatever its
+    scale, in every reverse mode."""
+    from tests.gpu_common import matched_paths, maxrel
     sc, g = box64
-    alb = g.albedo.clone().requires_grad_(True)
-    le = g.Le.clone().requires_grad_(True)
-    T = torch.zeros((64, 64, 3), device=g.dev)
-    grads = {}
+    seed, n, D, scale = 5, 16384, 4, 2.5
+    mask, ids, mis = matched_paths(sc, g, seed, n, D)
+    assert mis <= 1e-3
+    T = O.render(sc, 99, 4096, D, albedo=sc["albedo_target"])["image"]
+    Tt = torch.as_tensor(T, dtype=torch.float32, device=g.dev)
+    Io = O.render(sc, seed, n, D, path_list=ids)["image"]
+    Lo, dIo = O.loss_and_adjoint(Io, T)
+    ref = {"naive": O.gradient(sc, seed, n, D, scale * dIo, path_list=ids)}
+    ref["lrb3"] = ref["naive"]
+    ref["reslrb"] = O.gradient(sc, seed, n, D, scale * dIo, mode=O.MODE_RESLRB, path_list=ids)
+    m = torch.as_tensor(mask, device=g.dev)
     for mode in ("naive", "reslrb", "lrb3"):
-        alb.grad = None
-        le.grad = None
-        img = lt.LightTrace.apply(alb, le, None, g.ctx, 5, 16384, 4, mode, 0)
-        loss = ((img - T) ** 2).mean()
+        alb = g.albedo.clone().requires_grad_(True)
+        le = g.Le.clone().requires_grad_(True)
+        img = lt.LightTrace.apply(alb, le, None, g.ctx, seed, n, D, mode, 0, m)
+        loss = scale * ((img - Tt) ** 2).mean()
         loss.backward()
-        grads[mode] = (alb.grad.cpu().numpy(), le.grad.cpu().numpy())
-    from tests.gpu_common import maxrel
-    assert maxrel(grads["lrb3"][0], grads["naive"][0]) <= TOL
-    assert maxrel(grads["lrb3"][1], grads["naive"][1]) <= TOL
+        el = abs(loss.item() - scale * Lo) / (scale * Lo)
+        ea, ee = maxrel(alb.grad.cpu().numpy(), ref[mode]["albedo"]), maxrel(le.grad.cpu().numpy(), ref[mode]["Le"])
+        print(f"autograd {mode}: loss {el:.2e} albedo {ea:.2e} Le {ee:.2e}", flush=True)
+        assert el <= TOL and ea <= TOL and ee <= TOL, mode
+
+
+def test_autograd_function_attached_against_oracle():
+    """The same through the attached LRB-3 backward on a small caustic: the
+    heights gradient of a scaled L2 loss against the oracle's, on paths whose
+    decisions agree, that the oracle does not flag as ill-conditioned and
+    where the determinant guard did not fire."""
+    from tests.gpu_common import GpuRun, matched_paths, maxrel
+    sc = scenes.caustic_scene(G=16, width=64, height=64)
+    g = GpuRun(sc)
+    seed, n, D, scale = 17, 65536, 4, 3.0
+    mask, ids, mis, illc = matched_paths(sc, g, seed, n, D, want_illc=True)
+    assert mis <= 1e-3
+    T = O.render(sc, 99, 16384, D, heights=sc["heights_target"])["image"]
+    first = g.backward("lrb3", seed, n, D, np.ones((64, 64, 3)), flags=lt.ATTACHED, mask=mask, want_info=True)
+    keep = mask.astype(bool) & ~illc & ((first["info"] & 1) == 0)
+    ids2 = np.nonzero(keep)[0].astype(np.uint32)
+    Io = O.render(sc, seed, n, D, path_list=ids2)["image"]
+    Lo, dIo = O.loss_and_adjoint(Io, T)
+    ref = O.gradient(sc, seed, n, D, scale * dIo, flags=O.ATTACHED, path_list=ids2)
+    h = g.heights.clone().requires_grad_(True)
+    le = g.Le.clone().requires_grad_(True)
+    alb = g.albedo.clone().requires_grad_(True)
+    m = torch.as_tensor(keep.astype(np.uint8), device=g.dev)
+    img = lt.LightTrace.apply(alb, le, h, g.ctx, seed, n, D, "lrb3", lt.ATTACHED, m)
+    loss = scale * ((img - torch.as_tensor(T, dtype=torch.float32, device=g.dev)) ** 2).mean()
+    loss.backward()
+    eh = maxrel(h.grad.cpu().numpy(), ref["heights"])
+    ee = maxrel(le.grad.cpu().numpy(), ref["Le"])
+    print(f"autograd attached lrb3: loss {abs(loss.item() / (scale * Lo) - 1):.2e} heights {eh:.2e} Le {ee:.2e}",
+          flush=True)
+    assert abs(loss.item() / (scale * Lo) - 1) <= TOL and eh <= TOL and ee <= TOL
 
 
 def test_loss_kernel(box64):

@@ -22,6 +22,12 @@ from paper_2609_32920_amd import lt, scenes
 pytestmark = pytest.mark.gpu
 
 SEEDS = 256
+# Ceiling on the relative all-path bias of the attached replay modes that the
+# determinant guard causes on the 16x16 caustic at depth 4 (0.15% of paths):
+# measured at zero within the noise of the 64-seed estimate (whose floor is
+# about 0.05); the bias shows only as a mean z^2 near 3, i.e. it sits in the
+# few heights that the guard paths cross.
+BIAS_CEILING = 0.02
 
 
 def _zstats(d):
@@ -47,6 +53,28 @@ def _run(sc, n, D, flags, params_of, modes=("naive", "reslrb", "lrb3")):
     return {m: np.array(v) for m, v in out.items()}, stats
 
 
+def _unweighted_reslrb(g, seed, n, D, dI):
+    """ResLRB with the reservoir reweight taken out: the records written by the
+    forward get S_hat = C_R (not (Omega/w_R) C_R) and W = 1 before the
+    adjoint pass, so the estimator scales the selected connection by one
+    instead of by the inverse selection probability (Eq. 9-10).  A biased
+    estimator the seed-mean criterion must reject."""
+    out = g.trace(seed, n, D, lt.RECORD_RESERVOIR)
+    side = out["side"]
+    f = side.view(torch.float32).view(-1, 8)[:n]
+    R = side.view(torch.int32).view(-1, 8)[:n, 0]
+    sel = R > 0
+    W = f[:, 1].clone()
+    f[sel, 4:7] /= W[sel, None]
+    f[sel, 1] = 1.0
+    return g.backward("reslrb", seed, n, D, dI, side=side)
+
+
+def _criterion(z):
+    frac3 = float(np.mean(np.abs(z) > 3))
+    return frac3 <= 0.01 and np.abs(z).max() < 5.5 and abs(np.mean(z * z) - 1.0) < 0.25, frac3
+
+
 def test_detached_box_seed_means():
     sc = scenes.box_scene(width=64, height=64)
     res, _ = _run(sc, 16_384, 4, 0, lambda r: np.concatenate([r["albedo"].ravel(), r["Le"]]))
@@ -56,12 +84,33 @@ def test_detached_box_seed_means():
     assert np.abs(res["lrb3"] - naive).max() <= 1e-4 * scale
     # (its per-seed differences are rounding only, so a z-test would measure
     # rounding offsets against rounding noise; the equality above is the test)
-    z, k = _zstats(res["reslrb"] - naive)
-    frac3 = float(np.mean(np.abs(z) > 3))
+    d = res["reslrb"] - naive
+    z, k = _zstats(d)
+    ok, frac3 = _criterion(z)
     print(f"box reslrb: {k} params, mean z^2 {np.mean(z * z):.3f}, |z|>3 {frac3:.4f}, max |z| {np.abs(z).max():.2f}",
           flush=True)
     assert frac3 <= 0.01 and np.abs(z).max() < 5.5
     assert abs(np.mean(z * z) - 1.0) < 0.15
+    # eight fixed random projections of the parameter vector: |z| <= 3 each
+    P = np.random.default_rng(2609).normal(size=(8, d.shape[1]))
+    zp = (d @ P.T).mean(0) / ((d @ P.T).std(0, ddof=1) / np.sqrt(d.shape[0]))
+    print(f"box reslrb projections: z {np.array2string(zp, precision=2)}", flush=True)
+    assert np.all(np.abs(zp) <= 3.0)
+    # power: the same criterion rejects ResLRB without the Omega/w_R reweight
+    from tests.gpu_common import GpuRun
+    g = GpuRun(sc)
+    dI = np.random.default_rng(11).normal(size=(64, 64, 3)) * 1e-2
+    du = []
+    for s in range(64):
+        seed = 10_000 + s
+        ru = _unweighted_reslrb(g, seed, 16_384, 4, dI)
+        rn = g.backward("naive", seed, 16_384, 4, dI)
+        du.append(np.concatenate([ru["albedo"].ravel(), ru["Le"]]) - np.concatenate([rn["albedo"].ravel(), rn["Le"]]))
+    zu, _ = _zstats(np.array(du))
+    oku, frac3u = _criterion(zu)
+    print(f"box unweighted reslrb (64 seeds): mean z^2 {np.mean(zu * zu):.3f}, |z|>3 {frac3u:.4f} - must fail",
+          flush=True)
+    assert not oku
 
 
 def test_attached_caustic_seed_means():
@@ -76,7 +125,7 @@ def test_attached_caustic_seed_means():
     n, D = 65_536, 4
     dI = np.random.default_rng(11).normal(size=(64, 64, 3)) * 1e-2
     res = {m: [] for m in ("naive", "reslrb", "lrb3")}
-    full = {m: [] for m in ("naive", "reslrb")}
+    full = {m: [] for m in ("naive", "reslrb", "lrb3")}
     guard = []
     for s in range(SEEDS):
         seed = 20_000 + s
@@ -99,8 +148,22 @@ def test_attached_caustic_seed_means():
     e = np.abs(m_l - m_n).max() / np.abs(m_n).max()
     print(f"caustic lrb3 vs naive seed means (guard-free paths): max rel {e:.2e}", flush=True)
     assert e <= 1e-3
-    zf, _ = _zstats(np.array(full["reslrb"]) - np.array(full["naive"]))
-    print(f"caustic reslrb on all paths (64 seeds): mean z^2 {np.mean(zf * zf):.3f} (guard drops)", flush=True)
+    # Over all paths the guard's dropped terms bias both replay modes (Sec. 5).
+    # The bias is measured as the norm of the seed-mean difference from naive
+    # AD, with the sampling noise of that mean taken out, relative to the
+    # norm of naive AD's seed-mean gradient, and held below a ceiling.
+    gn = np.array(full["naive"])
+    for m in ("reslrb", "lrb3"):
+        dm = np.array(full[m]) - gn
+        S = dm.shape[0]
+        noise2 = np.sum(dm.var(0, ddof=1)) / S
+        b2 = np.sum(dm.mean(0) ** 2) - noise2
+        gnorm = np.linalg.norm(gn.mean(0))
+        rel = np.sqrt(max(b2, 0.0)) / gnorm
+        zf, _ = _zstats(dm)
+        print(f"caustic {m} on all paths ({S} seeds): relative bias {rel:.4f} (noise floor of the estimate "
+              f"{np.sqrt(noise2) / gnorm:.4f}), mean z^2 {np.mean(zf * zf):.3f} (guard drops)", flush=True)
+        assert rel <= BIAS_CEILING, m
 
 
 def test_attached_replay_variance_matches_naive_on_all_paths():
