@@ -164,6 +164,13 @@ typedef struct {
                               when the texture set takes at most 48 KB and the copy costs
                               the kernel no resident workgroups; 0: never (waves then
                               write-combine them into the gradient array) */
+  int32_t lrb3_split;      /* how lt_backward_lrb3 runs its two replays.  Split: pass 2 and
+                              pass 3 as two kernels, each connected path's state (delta_total,
+                              validity bits, last connection depth; attached also A) handed
+                              over in library workspace, 40 or 64 bytes per path, flat in
+                              depth.  Fused: one kernel runs both passes per path, state in
+                              registers.  0: fused always; 1: split always; 2 (default):
+                              split for LT_ATTACHED calls, fused for detached ones */
 } lt_tuning;
 
 /* Counters from the last call that produced them. */
@@ -185,7 +192,7 @@ void lt_destroy(lt_ctx* ctx);
 const char* lt_last_error(const lt_ctx* ctx);
 /* Switch the stream later calls enqueue on. */
 lt_status lt_set_stream(lt_ctx* ctx, void* hip_stream);
-/* Launch shape: NULL restores the defaults {128, 10, 1} (the attached kernels
+/* Launch shape: NULL restores the defaults {128, 10, 1, 2} (the attached kernels
  * choose their own workgroup size, 256 or 768 threads, and take blocks_per_cu
  * only). Errors: LT_ERR_ARG. */
 lt_status lt_set_tuning(lt_ctx* ctx, const lt_tuning* tuning);
@@ -219,8 +226,10 @@ lt_status lt_scene_upload(lt_ctx* ctx, const lt_scene_desc* scene);
  * 0 for neither. */
 size_t lt_side_state_bytes(const lt_ctx* ctx, const lt_trace_args* args);
 /* Library workspace bytes a call with these args may use (flat in depth):
- * the scene copy and BVH, plus the guide's packed weights and 16 bytes per
- * path, which only guided passes use. */
+ * the scene copy and BVH, the guide's packed weights and 16 bytes per path
+ * (guided passes only), and the LRB-3 backward's per-path hand-off between
+ * its two kernels when they are split (lt_tuning.lrb3_split): 40 bytes per
+ * path, 64 with LT_ATTACHED. */
 size_t lt_workspace_bytes(const lt_ctx* ctx, const lt_trace_args* args);
 
 /* Light tracing forward (Eq. 1-2, Eq. 20; Sec. 4.3.1 Pass 1).
@@ -396,8 +405,9 @@ const char* lt_batch_last_error(const lt_batch* b);
  * LT_ERR_HIP. */
 lt_status lt_batch_step(lt_batch* b, const lt_instance* inst, int32_t n, int32_t use_graph);
 /* Launch shape of the batched passes: block and blocks_per_cu as in
- * lt_set_tuning (the attached backward chooses its own workgroup size).
- * Default {256, 4, 1}.  The backward passes keep per-workgroup LDS copies of
+ * lt_set_tuning (the attached backward chooses its own workgroup size;
+ * lrb3_split is ignored: batches run both LRB-3 passes in one kernel).
+ * Default {256, 4, 1, 0}.  The backward passes keep per-workgroup LDS copies of
  * the gradient arrays (heights always, albedo with lds_grad = 1) for the
  * instances whose arrays fit one budget per pass: the largest requested size
  * that costs the pass no resident workgroups per compute unit.  The other

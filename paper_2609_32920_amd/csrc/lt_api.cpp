@@ -160,7 +160,7 @@ struct lt_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
-  lt_tuning tune{128, 10, 1};
+  lt_tuning tune{128, 10, 1, 2};
   uint64_t cap = 0;
   lt_stats stats{};
   int n_cu = 256;
@@ -186,6 +186,8 @@ struct lt_ctx {
   size_t grec_n = 0;
   float* d_gpart = nullptr;  // guide gradient partial sums [gpart_n][kGN + 1]
   size_t gpart_n = 0;
+  char* d_hand = nullptr;    // LRB-3 hand-off between its two kernels [hand_n bytes]
+  size_t hand_n = 0;
 
   lt_status fail(lt_status s, const char* fmt, const char* a = "") {
     char buf[512];
@@ -306,6 +308,20 @@ lt_status check_args(lt_ctx* c, const lt_trace_args* a, const lt_params* p) {
 
 size_t guide_bytes(const lt_trace_args* a, const lt_params* p) {
   return p && p->guide_w ? (size_t)a->n_paths * sizeof(float4) : 0;
+}
+
+// LRB-3 hand-off between the pass-2 and pass-3 kernels: one entry per path
+// at most (flat in depth).
+// Whether lt_backward_lrb3 runs its passes as two kernels for these args:
+// measured on the 256x256 box at depth 32 the fused kernel is faster (8.4
+// against 13.5 ms), on the 128x128 caustic (attached) the split pair (40.3
+// against 49.8 ms), hence the default 2.
+bool lrb3_split(const lt_ctx* c, const lt_trace_args* a) {
+  return c->tune.lrb3_split == 1 || (c->tune.lrb3_split == 2 && (a->flags & LT_ATTACHED));
+}
+size_t hand_bytes(const lt_ctx* c, const lt_trace_args* a) {
+  if (!lrb3_split(c, a) || a->n_paths < 1) return 0;
+  return (size_t)a->n_paths * ((a->flags & LT_ATTACHED) ? sizeof(Lrb3HandAtt) : sizeof(Lrb3Hand));
 }
 
 template <typename T>
@@ -455,6 +471,7 @@ void lt_destroy(lt_ctx* c) {
   hipFree(c->d_gpack);
   hipFree(c->d_grec);
   hipFree(c->d_gpart);
+  hipFree(c->d_hand);
   delete c;
 }
 
@@ -468,10 +485,12 @@ lt_status lt_set_stream(lt_ctx* c, void* stream) {
 
 lt_status lt_set_tuning(lt_ctx* c, const lt_tuning* t) {
   if (!c) return LT_ERR_ARG;
-  if (!t) { c->tune = lt_tuning{128, 10, 1}; return LT_OK; }
+  if (!t) { c->tune = lt_tuning{128, 10, 1, 2}; return LT_OK; }
   if (t->block < 64 || t->block > 1024 || (t->block % 64) != 0) return c->fail(LT_ERR_ARG, "block must be 64..1024, a multiple of 64%s");
   if (t->blocks_per_cu < 1 || t->blocks_per_cu > 64) return c->fail(LT_ERR_ARG, "blocks_per_cu must be 1..64%s");
   if ((size_t)kStackMax * t->block * sizeof(int) > (size_t)c->lds_max) return c->fail(LT_ERR_ARG, "traversal stack exceeds the LDS of a workgroup%s");
+  if (t->lds_grad != 0 && t->lds_grad != 1) return c->fail(LT_ERR_ARG, "lds_grad must be 0 or 1%s");
+  if (t->lrb3_split < 0 || t->lrb3_split > 2) return c->fail(LT_ERR_ARG, "lrb3_split must be 0, 1 or 2%s");
   c->tune = *t;
   return LT_OK;
 }
@@ -708,7 +727,7 @@ size_t lt_side_state_bytes(const lt_ctx* c, const lt_trace_args* a) {
 size_t lt_workspace_bytes(const lt_ctx* c, const lt_trace_args* a) {
   if (!c) return 0;
   size_t guide = guide_packed_bytes() + (a && a->n_paths > 0 ? (size_t)a->n_paths * sizeof(float4) : 0);
-  return c->scene_bytes + 512 + guide;
+  return c->scene_bytes + 512 + guide + (a ? hand_bytes(c, a) : 0);
 }
 
 lt_status lt_trace(lt_ctx* c, const lt_trace_args* a, const lt_params* p, float* image, void* side,
@@ -837,10 +856,37 @@ lt_status lt_backward_lrb3(lt_ctx* c, const lt_trace_args* a, const lt_params* p
                            lt_grads* g) {
   if (!c) return LT_ERR_ARG;
   PassArgs A;
-  lt_status st = backward_common(c, a, p, d_image, g, A, 0);
+  lt_status st = backward_common(c, a, p, d_image, g, A, a ? hand_bytes(c, a) : 0);
   if (st != LT_OK) return st;
   A.contrib = a->path_contrib;
-  if (a->flags & LT_ATTACHED) {
+  const bool att = (a->flags & LT_ATTACHED) != 0;
+  if (lrb3_split(c, a)) {
+    // pass 2 appends one hand-off entry per connected path; pass 3 replays those
+    const size_t need = hand_bytes(c, a);
+    if ((st = grow(c, &c->d_hand, c->hand_n, need, "the LRB-3 hand-off")) != LT_OK) return st;
+    A.hand = reinterpret_cast<Lrb3Hand*>(c->d_hand);
+    A.hand_att = reinterpret_cast<Lrb3HandAtt*>(c->d_hand);
+    A.hand_n = c->d_counter + 1;
+    A.hand_ticket = c->d_counter + 2;
+    if ((st = c->hip(launch_fill_u32(c->d_counter + 1, 2, 0u, c->stream), "hand-off clear")) != LT_OK) return st;
+    if (att) {
+      const int blk2 = 256;
+      if ((st = c->hip(launch_lrb3_att_p2(A, persistent_grid(c, a->n_paths, blk2), blk2, c->stream),
+                       "lrb3 attached pass 2")) != LT_OK)
+        return st;
+      const int blk = att_replay_block(c, g->heights, c->dsc.stack_n, BwdKernel::lrb3_att_p3, 768);
+      A.hgrad_lds = hgrad_in_lds(c, g->heights, BwdKernel::lrb3_att_p3, blk, stack_lds(c, blk), true);
+      A.agrad_lds = agrad_in_lds(c, BwdKernel::lrb3_att_p3, blk, stack_lds(c, blk) + hgrad_lds_bytes(c, A.hgrad_lds));
+      if ((st = c->hip(launch_lrb3_att_p3(A, persistent_grid(c, a->n_paths, blk), blk, c->stream),
+                       "lrb3 attached pass 3")) != LT_OK)
+        return st;
+    } else {
+      const int blk = c->tune.block, grid = persistent_grid(c, a->n_paths, blk);
+      if ((st = c->hip(launch_lrb3_p2(A, grid, blk, c->stream), "lrb3 pass 2")) != LT_OK) return st;
+      A.agrad_lds = agrad_in_lds(c, BwdKernel::lrb3_p3, blk, stack_lds(c, blk));
+      if ((st = c->hip(launch_lrb3_p3(A, grid, blk, c->stream), "lrb3 pass 3")) != LT_OK) return st;
+    }
+  } else if (att) {
     const int blk = att_replay_block(c, g->heights, c->dsc.stack_n, BwdKernel::lrb3_att, 768);
     int grid = persistent_grid(c, a->n_paths, blk);
     A.hgrad_lds = hgrad_in_lds(c, g->heights, BwdKernel::lrb3_att, blk, stack_lds(c, blk), true);
@@ -953,7 +999,7 @@ struct lt_batch {
   hipStream_t stream = nullptr;       // caller's stream: eager steps and graph launches
   hipStream_t cap = nullptr;          // the runner's own stream, for capture (the null stream cannot be)
   std::string err;
-  lt_tuning tune{256, 4, 1};
+  lt_tuning tune{256, 4, 1, 0};
   int n_cu = 256;
   std::string arch;
   // device tables: trace [n], detached backward [n_det], attached backward [n_att]
@@ -1345,7 +1391,7 @@ const char* lt_batch_last_error(const lt_batch* b) { return b ? b->err.c_str() :
 
 lt_status lt_batch_set_tuning(lt_batch* b, const lt_tuning* t) {
   if (!b) return LT_ERR_ARG;
-  if (!t) { b->tune = lt_tuning{256, 4, 1}; return LT_OK; }
+  if (!t) { b->tune = lt_tuning{256, 4, 1, 0}; return LT_OK; }
   if (t->block < 64 || t->block > 1024 || (t->block % 64) != 0)
     return b->fail(LT_ERR_ARG, "block must be 64..1024, a multiple of 64");
   if (t->blocks_per_cu < 1 || t->blocks_per_cu > 64) return b->fail(LT_ERR_ARG, "blocks_per_cu must be 1..64");
@@ -1382,7 +1428,7 @@ lt_status lt_batch_autotune(lt_batch* b, const lt_instance* inst, int32_t n, con
   auto it = cache.find(key);
   double bl = 0, bpc = 0;
   if (it != cache.end() && cache_field(it->second, "block", bl) && cache_field(it->second, "blocks_per_cu", bpc)) {
-    lt_tuning t{(int32_t)bl, (int32_t)bpc, lg};
+    lt_tuning t{(int32_t)bl, (int32_t)bpc, lg, 0};
     if ((st = lt_batch_set_tuning(b, &t)) == LT_OK && out) *out = t;
     return st;
   }
@@ -1390,12 +1436,12 @@ lt_status lt_batch_autotune(lt_batch* b, const lt_instance* inst, int32_t n, con
   static const int per_cu[] = {2, 4, 8};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return b->fail(LT_ERR_HIP, "event create");
-  lt_tuning best{256, 4, lg};
+  lt_tuning best{256, 4, lg, 0};
   float best_ms = 1e30f;
   const lt_tuning saved = b->tune;
   for (int blk : blocks)
     for (int k : per_cu) {
-      b->tune = lt_tuning{blk, k, lg};
+      b->tune = lt_tuning{blk, k, lg, 0};
       float ms = 0.f;
       for (int rep = 0; rep < 3 && st == LT_OK; ++rep) {
         hipEventRecord(e0, b->stream);

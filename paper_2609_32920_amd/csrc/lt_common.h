@@ -79,6 +79,28 @@ struct alignas(16) ResRecAtt {
 };
 static_assert(sizeof(ResRecAtt) == 128, "attached reservoir record layout");
 
+// LRB-3 hand-off between the two replays (Sec. 4.3: the per-sample state of
+// the method), one entry per path that has a sensor connection, appended by
+// the pass-2 kernel and consumed by the pass-3 kernel: the path, the depth of
+// its last connection, one bit per vertex for a valid connection and
+// delta_total (FP64, Eq. 14); attached also A = sum_i a_i M_i (Eq. 18).
+struct alignas(8) Lrb3Hand {
+  uint32_t path;
+  int32_t klast;
+  uint64_t vmask;
+  double d[3];
+};
+static_assert(sizeof(Lrb3Hand) == 40, "hand-off layout");
+struct alignas(16) Lrb3HandAtt {
+  uint32_t path;
+  int32_t klast;
+  uint64_t vmask;
+  double d[3];
+  float A[4];
+  float pad[2];
+};
+static_assert(sizeof(Lrb3HandAtt) == 64, "attached hand-off layout");
+
 struct DevScene {
   const Node* nodes;
   const Tri* tris;

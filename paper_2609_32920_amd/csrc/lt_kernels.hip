@@ -573,6 +573,152 @@ __global__ void __launch_bounds__(1024) k_lrb3_bwd(PassArgs A) {
   lrb3_run(A, lds);
 }
 
+// ---------------------------------------------------------------- LRB-3, two kernels
+// The same two replays as k_lrb3_bwd, each a kernel of its own with the
+// method's per-path state handed over in memory (Lrb3Hand, 40 bytes per
+// connected path, flat in depth).  Every wave then runs one phase: pass 2's
+// shadow rays and pass 3's gradient scatters never share a wave, and pass 3
+// visits only the paths with a sensor connection, compacted by the append.
+
+// Next work item for every lane that needs one: tickets below n_items.
+__device__ __forceinline__ void fetch_items(unsigned int* ticket, uint32_t n_items, bool& alive, bool& exhausted,
+                                            uint32_t& item) {
+  while (true) {
+    bool need = !alive && !exhausted;
+    if (__ballot(need) == 0ull) break;
+    uint32_t t = fetch_paths(ticket, need);
+    if (need) {
+      if (t >= n_items) exhausted = true;
+      else { alive = true; item = t; }
+    }
+  }
+}
+
+// Pass 2 (Eq. 14): replay with the sensor connections (shadow rays
+// included), delta_total = sum_i dI(u_i) C_i in FP64, one bit per vertex for
+// a valid connection, the depth of the last one.  A path whose delta_total is
+// nonzero gets its emitter gradient delta_total / L_e here and a hand-off
+// entry (wave-aggregated append).
+__device__ __forceinline__ void lrb3_p2_run(const PassArgs& A, int* lds) {
+  int* stk = lds + threadIdx.x;
+  const int ss = blockDim.x;
+  bool alive = false, exhausted = false;
+  uint32_t path = 0;
+  int j = 0, klast = 0;
+  uint64_t vmask = 0ull;
+  Ray r;
+  f3 beta = {0.f, 0.f, 0.f};
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+  const f3 Le = ld3(A.Le);
+  const D3R iLe = recip_le(Le);
+  double gl0 = 0.0, gl1 = 0.0, gl2 = 0.0;
+  while (true) {
+    refill(A, alive, exhausted, path, [&](uint32_t p) { if (A.contrib) A.contrib[p] = 0.f; });
+    if (__ballot(alive) == 0ull) break;
+    bool put = false;
+    if (alive) {
+      if (j == 0) {
+        beta = Le * emit_path(A, path, r);
+        j = 1;
+        d0 = d1 = d2 = 0.0; vmask = 0ull; klast = 0;
+      }
+      Event ev = bounce(A, path, j, r, 1, stk, ss);
+      if (ev.kind == 1) {
+        if (ev.valid) {
+          f3 C = mul(beta, ev.rho) * ev.g;
+          f3 Lb = gather(A.sc, A.dI, ev.ux, ev.uy);
+          d0 += (double)Lb.x * C.x; d1 += (double)Lb.y * C.y; d2 += (double)Lb.z * C.z;
+          vmask |= 1ull << (j - 1); klast = j;
+        }
+        if (ev.cont) beta = mul(beta, ev.rho);
+      }
+      if (ev.cont) {
+        ++j;
+      } else {
+        put = klast > 0 && (d0 != 0.0 || d1 != 0.0 || d2 != 0.0);
+        if (put) add_le(A, gl0, gl1, gl2, d0 * iLe.x, d1 * iLe.y, d2 * iLe.z);
+        // the path's adjoint-weighted contribution |delta_total|
+        if (A.contrib) A.contrib[path] = put ? (float)(fabs(d0) + fabs(d1) + fabs(d2)) : 0.f;
+        alive = false; j = 0;
+      }
+    }
+    const uint32_t slot = fetch_paths(A.hand_n, put);
+    if (put) {
+      Lrb3Hand h;
+      h.path = path; h.klast = klast; h.vmask = vmask; h.d[0] = d0; h.d[1] = d1; h.d[2] = d2;
+      A.hand[slot] = h;
+    }
+  }
+  flush_le(A, gl0, gl1, gl2);
+}
+
+// Pass 3 (Eq. 15-17) over the handed-over paths: replay to the last
+// connection re-evaluating only the connection geometry where the bit is
+// set (no shadow rays), the splat term dI(u_i) C_i / rho_i, the subtraction
+// from delta_rem and the scatter term delta_rem / rho_i.
+__device__ __forceinline__ void lrb3_p3_run(const PassArgs& A, int* lds) {
+  int* stk = lds + threadIdx.x;
+  const int ss = blockDim.x;
+  AGrad ga = agrad_begin(A, lds + A.sc.stack_n * blockDim.x);
+  const uint32_t n_items = *A.hand_n;
+  bool alive = false, exhausted = false;
+  uint32_t item = 0, path = 0;
+  int j = 0, klast = 0;
+  uint64_t vmask = 0ull;
+  Ray r;
+  f3 beta = {0.f, 0.f, 0.f};
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+  const f3 Le = ld3(A.Le);
+  while (true) {
+    fetch_items(A.hand_ticket, n_items, alive, exhausted, item);
+    if (__ballot(alive) == 0ull) break;
+    bool has = false;
+    int texel = 0;
+    f3 gv = {0.f, 0.f, 0.f};
+    if (alive) {
+      if (j == 0) {
+        const Lrb3Hand h = A.hand[item];
+        path = h.path; klast = h.klast; vmask = h.vmask; d0 = h.d[0]; d1 = h.d[1]; d2 = h.d[2];
+        beta = Le * emit_path(A, path, r);
+        j = 1;
+      }
+      Event ev = bounce(A, path, j, r, ((vmask >> (j - 1)) & 1ull) ? 2 : 0, stk, ss);
+      if (j >= klast) ev.cont = false;  // nothing after the last connection
+      if (ev.kind == 1) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        if (ev.valid) {
+          f3 C = mul(beta, ev.rho) * ev.g;
+          f3 Lb = gather(A.sc, A.dI, ev.ux, ev.uy);
+          a0 = (double)Lb.x * C.x; a1 = (double)Lb.y * C.y; a2 = (double)Lb.z * C.z;
+        }
+        d0 -= a0; d1 -= a1; d2 -= a2;
+        if (j >= klast) { d0 = d1 = d2 = 0.0; }
+        double g0 = a0, g1 = a1, g2 = a2;
+        if (ev.cont) { g0 += d0; g1 += d1; g2 += d2; }
+        texel = ev.texel;
+        gv = {ev.rho.x > 0.f ? (float)g0 / ev.rho.x : 0.f, ev.rho.y > 0.f ? (float)g1 / ev.rho.y : 0.f,
+              ev.rho.z > 0.f ? (float)g2 / ev.rho.z : 0.f};
+        has = true;
+        if (ev.cont) beta = mul(beta, ev.rho);
+      }
+      if (ev.cont) ++j;
+      else { alive = false; j = 0; }
+    }
+    keep_finite(A, has, gv);
+    scatter_albedo(A, ga, has, texel, gv);
+  }
+  agrad_end(A, ga);
+}
+
+__global__ void __launch_bounds__(1024) k_lrb3_p2(PassArgs A) {
+  extern __shared__ int lds[];
+  lrb3_p2_run(A, lds);
+}
+__global__ void __launch_bounds__(1024) k_lrb3_p3(PassArgs A) {
+  extern __shared__ int lds[];
+  lrb3_p3_run(A, lds);
+}
+
 // ---------------------------------------------------------------- small kernels
 __global__ void k_fill_f32(float* p, size_t n, float v) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
@@ -745,6 +891,9 @@ hipError_t set_lds_limit(int bytes) {
     e = hipFuncSetAttribute((const void*)k_lrb3_att_batch, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_lrb3_att_entry, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  for (const void* f : {(const void*)k_lrb3_p2, (const void*)k_lrb3_p3, (const void*)k_lrb3_att_p2,
+                        (const void*)k_lrb3_att_p3})
+    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   return e;
 }
 
@@ -771,6 +920,10 @@ int resident_groups(BwdKernel k, int block, size_t lds) {
     case BwdKernel::lrb3_batch: f = (const void*)k_lrb3_batch; break;
     case BwdKernel::lrb3_att_batch: f = (const void*)k_lrb3_att_batch; break;
     case BwdKernel::lrb3_att_entry: f = (const void*)k_lrb3_att_entry; break;
+    case BwdKernel::lrb3_p2: f = (const void*)k_lrb3_p2; break;
+    case BwdKernel::lrb3_p3: f = (const void*)k_lrb3_p3; break;
+    case BwdKernel::lrb3_att_p2: f = (const void*)k_lrb3_att_p2; break;
+    case BwdKernel::lrb3_att_p3: f = (const void*)k_lrb3_att_p3; break;
   }
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, block, lds) != hipSuccess) {
@@ -861,6 +1014,24 @@ hipError_t launch_reslrb_bwd(const PassArgs& A, int grid, int block, hipStream_t
 
 hipError_t launch_lrb3_bwd(const PassArgs& A, int grid, int block, hipStream_t s) {
   hipLaunchKernelGGL(k_lrb3_bwd, dim3(grid), dim3(block), stack_bytes(A, block) + agrad_bytes(A), s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_lrb3_p2(const PassArgs& A, int grid, int block, hipStream_t s) {
+  hipLaunchKernelGGL(k_lrb3_p2, dim3(grid), dim3(block), stack_bytes(A, block), s, A);
+  return hipGetLastError();
+}
+hipError_t launch_lrb3_p3(const PassArgs& A, int grid, int block, hipStream_t s) {
+  hipLaunchKernelGGL(k_lrb3_p3, dim3(grid), dim3(block), stack_bytes(A, block) + agrad_bytes(A), s, A);
+  return hipGetLastError();
+}
+hipError_t launch_lrb3_att_p2(const PassArgs& A, int grid, int block, hipStream_t s) {
+  hipLaunchKernelGGL(k_lrb3_att_p2, dim3(grid), dim3(block), stack_bytes(A, block), s, A);
+  return hipGetLastError();
+}
+hipError_t launch_lrb3_att_p3(const PassArgs& A, int grid, int block, hipStream_t s) {
+  hipLaunchKernelGGL(k_lrb3_att_p3, dim3(grid), dim3(block), stack_bytes(A, block) + hgrad_bytes(A) + agrad_bytes(A),
+                     s, A);
   return hipGetLastError();
 }
 

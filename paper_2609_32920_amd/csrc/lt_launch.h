@@ -44,6 +44,12 @@ struct PassArgs {
   int32_t agrad_lds;          // albedo gradients accumulated per workgroup in LDS
   const float4* guide_rec;    // guided emission (direction, density) per path, or null
   float* contrib;             // per-path image contribution sum_i lum(C_i), or null
+  // LRB-3 as two kernels: pass 2 appends a hand-off entry per connected path,
+  // pass 3 replays the queued paths
+  Lrb3Hand* hand;             // detached entries [n_paths]
+  Lrb3HandAtt* hand_att;      // attached entries [n_paths]
+  unsigned int* hand_n;       // entries appended (pass 2) / available (pass 3)
+  unsigned int* hand_ticket;  // pass-3 work tickets
 };
 
 typedef unsigned int lt_u32x4 __attribute__((ext_vector_type(4)));
@@ -90,6 +96,11 @@ hipError_t launch_lrb3_att_entry(const PassArgs* entry, int stack_n, size_t grad
 hipError_t launch_naive_bwd(const PassArgs& A, int grid, hipStream_t s);
 hipError_t launch_reslrb_bwd(const PassArgs& A, int grid, int block, hipStream_t s);
 hipError_t launch_lrb3_bwd(const PassArgs& A, int grid, int block, hipStream_t s);
+// LRB-3 as two kernels with the per-path hand-off of Lrb3Hand / Lrb3HandAtt
+hipError_t launch_lrb3_p2(const PassArgs& A, int grid, int block, hipStream_t s);
+hipError_t launch_lrb3_p3(const PassArgs& A, int grid, int block, hipStream_t s);
+hipError_t launch_lrb3_att_p2(const PassArgs& A, int grid, int block, hipStream_t s);
+hipError_t launch_lrb3_att_p3(const PassArgs& A, int grid, int block, hipStream_t s);
 hipError_t launch_lrb3_att(const PassArgs& A, int grid, int block, hipStream_t s);
 hipError_t launch_trace_att(const PassArgs& A, bool tape, bool resv, int grid, hipStream_t s);
 hipError_t launch_naive_att_bwd(const PassArgs& A, int grid, hipStream_t s);
@@ -105,7 +116,8 @@ hipError_t launch_hf_tris(const DevScene& sc, const int32_t* slot_of_prim, Tri* 
 hipError_t set_lds_limit(int bytes);
 // Workgroups of a backward kernel resident per CU at `block` threads and
 // `lds` dynamic LDS bytes (0 if it cannot launch or the query fails).
-enum class BwdKernel { naive, reslrb, lrb3, naive_att, reslrb_att, lrb3_att, lrb3_batch, lrb3_att_batch, lrb3_att_entry };
+enum class BwdKernel { naive, reslrb, lrb3, naive_att, reslrb_att, lrb3_att, lrb3_batch, lrb3_att_batch, lrb3_att_entry,
+                       lrb3_p2, lrb3_p3, lrb3_att_p2, lrb3_att_p3 };
 int resident_groups(BwdKernel k, int block, size_t lds);
 hipError_t read_counters(uint64_t* out, bool reset, hipStream_t s);
 hipError_t launch_refit_level(Node* nodes, const Tri* tris, const int32_t* level_nodes, int n, hipStream_t s);

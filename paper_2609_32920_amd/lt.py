@@ -74,7 +74,8 @@ class Grads(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32), ("lds_grad", C.c_int32)]
+    _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32), ("lds_grad", C.c_int32),
+                ("lrb3_split", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -188,14 +189,14 @@ class Context:
         s = torch.cuda.current_stream(self.device)
         self._status(self.lib.lt_set_stream(self.h, C.c_void_p(s.cuda_stream)))
 
-    def set_tuning(self, block=128, blocks_per_cu=10, lds_grad=1):
-        t = Tuning(block, blocks_per_cu, lds_grad)
+    def set_tuning(self, block=128, blocks_per_cu=10, lds_grad=1, lrb3_split=2):
+        t = Tuning(block, blocks_per_cu, lds_grad, lrb3_split)
         self._status(self.lib.lt_set_tuning(self.h, C.byref(t)))
 
     def get_tuning(self):
         t = Tuning()
         self._status(self.lib.lt_get_tuning(self.h, C.byref(t)))
-        return dict(block=t.block, blocks_per_cu=t.blocks_per_cu, lds_grad=t.lds_grad)
+        return dict(block=t.block, blocks_per_cu=t.blocks_per_cu, lds_grad=t.lds_grad, lrb3_split=t.lrb3_split)
 
     def read_counters(self, reset=True):
         """Event counts of the LT_COUNTERS build (see lt_read_counters)."""
@@ -421,7 +422,7 @@ class Batch:
         self._check(self.lib.lt_batch_step(self.h, arr, len(arr), int(bool(use_graph))))
 
     def set_tuning(self, block=256, blocks_per_cu=4, lds_grad=1):
-        t = Tuning(block, blocks_per_cu, lds_grad)
+        t = Tuning(block, blocks_per_cu, lds_grad, 0)
         self._check(self.lib.lt_batch_set_tuning(self.h, C.byref(t)))
 
     def get_tuning(self):

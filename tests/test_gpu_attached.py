@@ -104,11 +104,24 @@ def test_attached_side_state_sizes(caustic16):
     assert res[0] == res[1] == res[2] == 128 * n  # one record per path: flat in depth
 
 
-@pytest.mark.parametrize("mode", ["lrb3", "reslrb"])
+@pytest.mark.parametrize("mode", ["lrb3", "reslrb", "lrb3_fused"])
 @pytest.mark.parametrize("D", [3, 4, 6])
 def test_replay_attached_parity(caustic16, D, mode):
-    from tests.gpu_common import matched_paths, maxrel
+    """lrb3: the two-kernel LRB-3 with its per-path hand-off (default);
+    lrb3_fused: both passes in one kernel (lrb3_split = 0)."""
     sc, g = caustic16
+    if mode == "lrb3_fused":
+        g.ctx.set_tuning(lrb3_split=0)
+        try:
+            _replay_attached_parity(sc, g, D, "lrb3")
+        finally:
+            g.ctx.set_tuning()
+    else:
+        _replay_attached_parity(sc, g, D, mode)
+
+
+def _replay_attached_parity(sc, g, D, mode):
+    from tests.gpu_common import matched_paths, maxrel
     seed, n = 11, 65536
     mask, ids, mis, illc = matched_paths(sc, g, seed, n, D, want_illc=True)
     assert mis <= 1e-3

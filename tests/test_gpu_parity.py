@@ -56,6 +56,27 @@ def test_gradient_parity_all_modes_box(box64):
         assert ea <= TOL and el <= TOL, mode
 
 
+def test_lrb3_split_kernels_parity(box64):
+    """lrb3_split = 1: the detached LRB-3 passes as two kernels with the
+    per-path hand-off (the default form runs them fused), against the
+    oracle."""
+    from tests.gpu_common import matched_paths, maxrel
+    sc, g = box64
+    seed, n, D = 7, 16384, 6
+    mask, ids, mis = matched_paths(sc, g, seed, n, D)
+    assert mis <= 1e-3
+    dI = _dI((64, 64, 3), 13)
+    on = O.gradient(sc, seed, n, D, dI, path_list=ids)
+    g.ctx.set_tuning(lrb3_split=1)
+    try:
+        gg = g.backward("lrb3", seed, n, D, dI, mask=mask)
+    finally:
+        g.ctx.set_tuning()
+    ea, el = maxrel(gg["albedo"], on["albedo"]), maxrel(gg["Le"], on["Le"])
+    print(f"lrb3 split: albedo maxrel {ea:.2e}  Le maxrel {el:.2e}", flush=True)
+    assert ea <= TOL and el <= TOL
+
+
 def test_gradient_parity_without_lds_copies(box64):
     """lds_grad = 0: albedo gradients skip the per-workgroup LDS copy and go
     through each wave's write-combining cache into the gradient array (ten
