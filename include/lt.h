@@ -68,7 +68,8 @@ enum {
   LT_SPLAT_SELECTED = 2u,   /* primal image splats only (Omega_k/w_R) L_R (Eq. 9) */
   LT_RECORD_TAPE = 4u,      /* lt_trace writes the naive-AD tape */
   LT_RECORD_RESERVOIR = 8u, /* lt_trace writes the per-path ResLRB record */
-  LT_CONTRIB_ADJOINT = 16u  /* attached backward: path_contrib gets |delta_total| (below) */
+  LT_CONTRIB_ADJOINT = 16u, /* attached backward: path_contrib gets |delta_total| (below) */
+  LT_RECORD_SPLATS = 32u    /* lt_trace writes the buffered two-pass splat records (detached) */
 };
 
 typedef struct lt_ctx lt_ctx;
@@ -222,8 +223,11 @@ lt_status lt_scene_upload(lt_ctx* ctx, const lt_scene_desc* scene);
 /* Bytes of caller-provided side state lt_trace writes for these args:
  * LT_RECORD_TAPE: the naive-AD tape, N*D records (linear in depth) plus one
  * path length per path; LT_RECORD_RESERVOIR: one ResLRB record per path
- * (Sec. 4.2.1: selected depth R, weight Omega_k/w_R, u_R, reweighted splat).
- * 0 for neither. */
+ * (Sec. 4.2.1: selected depth R, weight Omega_k/w_R, u_R, reweighted splat);
+ * LT_RECORD_SPLATS: the buffered two-pass buffer, a 16-byte header per path
+ * (last connection depth, one validity bit per vertex) and a 20-byte record
+ * (u_i, C_i) for every vertex up to max_depth, preallocated (linear in
+ * depth).  The flags' buffers are laid out one after the other.  0 for none. */
 size_t lt_side_state_bytes(const lt_ctx* ctx, const lt_trace_args* args);
 /* Library workspace bytes a call with these args may use (flat in depth):
  * the scene copy and BVH, the guide's packed weights and 16 bytes per path
@@ -268,6 +272,19 @@ lt_status lt_backward_naive(lt_ctx* ctx, const lt_trace_args* args, const lt_par
 lt_status lt_backward_reslrb(lt_ctx* ctx, const lt_trace_args* args, const lt_params* params,
                              const float* d_image, const void* records, size_t records_bytes,
                              lt_grads* grads);
+
+/* Buffered two-pass backward (the lrb_2pass variant of Sec. 6; Sec. 4.1
+ * explains why its memory stays linear in depth): delta_total = sum_i
+ * dI(u_i) C_i (Eq. 14) is read back from the splat records lt_trace wrote
+ * with LT_RECORD_SPLATS (same args and params), then one replay per path
+ * consumes it as LRB-3's Pass 3 does (Eq. 15-17), taking u_i and C_i from the
+ * records (no shadow rays, no connection geometry).  The gradient equals
+ * naive AD's per path.  Detached only.
+ * Errors: LT_ERR_ARG (records too small / flags), LT_ERR_UNSUPPORTED
+ * (LT_ATTACHED), LT_ERR_STATE, LT_ERR_HIP. */
+lt_status lt_backward_lrb2(lt_ctx* ctx, const lt_trace_args* args, const lt_params* params,
+                           const float* d_image, const void* records, size_t records_bytes,
+                           lt_grads* grads);
 
 /* LRB-3-pass backward (Sec. 4.3): Pass 2 replays each path and accumulates
  * delta_total = sum_i dI(u_i) * L_i (Eq. 14; attached also A_pos, Eq. 18);

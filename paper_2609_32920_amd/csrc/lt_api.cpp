@@ -269,7 +269,7 @@ int agrad_in_lds(const lt_ctx* c, BwdKernel k, int block, size_t used) {
 size_t stack_lds(const lt_ctx* c, int block) { return (size_t)c->dsc.stack_n * block * sizeof(int); }
 size_t hgrad_lds_bytes(const lt_ctx* c, int on) { return on ? (size_t)c->dsc.hf_G * c->dsc.hf_G * sizeof(float) : 0; }
 
-struct SideLayout { size_t tape = 0, len = 0, emit = 0, res = 0, total = 0; };
+struct SideLayout { size_t tape = 0, len = 0, emit = 0, res = 0, spl_hdr = 0, spl = 0, total = 0; };
 
 // Side state: naive tape [D][N] records (+ N path lengths; attached: + the
 // emitted ray's dv_1/dH_1 per path), ResLRB records [N].
@@ -286,6 +286,10 @@ SideLayout side_layout(const lt_trace_args* a) {
   if (a->flags & LT_RECORD_RESERVOIR) {
     L.res = off; off = align256(off + N * (att ? sizeof(ResRecAtt) : sizeof(ResRec)));
   }
+  if (a->flags & LT_RECORD_SPLATS) {
+    L.spl_hdr = off; off = align256(off + N * sizeof(SplatHdr));
+    L.spl = off; off = align256(off + N * D * sizeof(SplatRec));
+  }
   L.total = off;
   return L;
 }
@@ -296,8 +300,11 @@ lt_status check_args(lt_ctx* c, const lt_trace_args* a, const lt_params* p) {
   if (!c->has_scene) return c->fail(LT_ERR_STATE, "no scene uploaded%s");
   if (a->n_paths < 1 || a->n_paths >= (int64_t)1 << 31) return c->fail(LT_ERR_ARG, "n_paths out of range [1, 2^31)%s");
   if (a->max_depth < 1 || a->max_depth > kMaxDepth) return c->fail(LT_ERR_ARG, "max_depth out of range [1, 64]%s");
-  if (a->flags & ~(uint32_t)(LT_ATTACHED | LT_SPLAT_SELECTED | LT_RECORD_TAPE | LT_RECORD_RESERVOIR | LT_CONTRIB_ADJOINT))
+  if (a->flags & ~(uint32_t)(LT_ATTACHED | LT_SPLAT_SELECTED | LT_RECORD_TAPE | LT_RECORD_RESERVOIR | LT_CONTRIB_ADJOINT |
+                             LT_RECORD_SPLATS))
     return c->fail(LT_ERR_ARG, "unknown flag bits%s");
+  if ((a->flags & LT_RECORD_SPLATS) && (a->flags & (LT_ATTACHED | LT_RECORD_TAPE)))
+    return c->fail(LT_ERR_UNSUPPORTED, "LT_RECORD_SPLATS is detached and not combined with LT_RECORD_TAPE%s");
   if (!p->albedo || !p->emitter_L) return c->fail(LT_ERR_ARG, "albedo and emitter_L are required%s");
   if ((a->flags & LT_ATTACHED) && c->dsc.hf_G < 2) return c->fail(LT_ERR_ARG, "LT_ATTACHED needs a heightfield%s");
   if ((a->flags & LT_ATTACHED) && !p->heights) return c->fail(LT_ERR_ARG, "LT_ATTACHED needs params->heights%s");
@@ -757,6 +764,7 @@ lt_status lt_trace(lt_ctx* c, const lt_trace_args* a, const lt_params* p, float*
   } else {
     if (a->flags & LT_RECORD_TAPE) { A.tape = (TapeRec*)(sb + L.tape); A.tape_len = (int32_t*)(sb + L.len); }
     if (a->flags & LT_RECORD_RESERVOIR) A.res = (ResRec*)(sb + L.res);
+    if (a->flags & LT_RECORD_SPLATS) { A.spl_hdr = (SplatHdr*)(sb + L.spl_hdr); A.spl = (SplatRec*)(sb + L.spl); }
   }
   size_t npix = (size_t)c->dsc.W * c->dsc.H * 3;
   if ((st = c->hip(launch_fill_f32(image, npix, 0.f, c->stream), "image clear")) != LT_OK) return st;
@@ -771,6 +779,8 @@ lt_status lt_trace(lt_ctx* c, const lt_trace_args* a, const lt_params* p, float*
   // the decision signature includes the reservoir choice R
   bool resv = (a->flags & (LT_RECORD_RESERVOIR | LT_SPLAT_SELECTED)) != 0 || a->path_sig != nullptr;
   int grid = persistent_grid(c, a->n_paths, c->tune.block);
+  if (a->flags & LT_RECORD_SPLATS)
+    return c->hip(launch_trace_splats(A, resv, grid, c->tune.block, c->stream), "trace launch");
   return c->hip(launch_trace(A, tape, resv, grid, c->tune.block, c->stream), "trace launch");
 }
 
@@ -782,8 +792,21 @@ lt_status lt_loss_l2(lt_ctx* c, const float* image, const float* target, int64_t
   return c->hip(launch_loss(image, target, (size_t)n, d_image, c->d_acc + 3, loss, c->stream), "loss launch");
 }
 
+// Where a backward call keeps its working memory: u32 counters ([0] work
+// tickets, [1] LRB-3 hand-off entries, [2] pass-3 tickets, [16..19] two u64
+// statistics), the FP64 emitter-gradient accumulators and the LRB-3 hand-off.
+// The entry points use the context's buffers and grow the hand-off on
+// demand.
+struct Work {
+  unsigned int* counter;
+  double* acc;
+  char* hand;       // null: the context's hand-off, grown as needed
+  size_t hand_cap;  // bytes at hand when it is set
+};
+Work ctx_work(lt_ctx* c) { return Work{c->d_counter, c->d_acc, nullptr, 0}; }
+
 static lt_status backward_common(lt_ctx* c, const lt_trace_args* a, const lt_params* p, const float* d_image,
-                                 lt_grads* g, PassArgs& A, size_t side) {
+                                 lt_grads* g, PassArgs& A, size_t side, const Work& w) {
   lt_status st = check_args(c, a, p);
   if (st != LT_OK) return st;
   if (!d_image || !g) return c->fail(LT_ERR_ARG, "null d_image or grads%s");
@@ -791,14 +814,20 @@ static lt_status backward_common(lt_ctx* c, const lt_trace_args* a, const lt_par
   if ((st = check_cap(c, side + guide_bytes(a, p))) != LT_OK) return st;
   if ((st = prepare_geometry(c, p)) != LT_OK) return st;
   A = base_args(c, a, p);
+  A.counter = w.counter;
+  A.stats = reinterpret_cast<unsigned long long*>(w.counter + 16);
   if ((st = guide_prepass(c, a, p, A)) != LT_OK) return st;
   A.dI = d_image;
   A.g_albedo = g->albedo;
-  A.g_Le_acc = c->d_acc;
+  A.g_Le_acc = w.acc;
   A.g_heights = g->heights;
-  if ((st = c->hip(launch_fill_f64(c->d_acc, 3, 0.0, c->stream), "acc clear")) != LT_OK) return st;
-  if ((st = c->hip(launch_fill_u32(c->d_counter + 16, 4, 0u, c->stream), "stats clear")) != LT_OK) return st;
-  return c->hip(launch_fill_u32(c->d_counter, 1, 0u, c->stream), "counter clear");
+  if ((st = c->hip(launch_fill_f64(w.acc, 3, 0.0, c->stream), "acc clear")) != LT_OK) return st;
+  if ((st = c->hip(launch_fill_u32(w.counter + 16, 4, 0u, c->stream), "stats clear")) != LT_OK) return st;
+  return c->hip(launch_fill_u32(w.counter, 1, 0u, c->stream), "counter clear");
+}
+static lt_status backward_common(lt_ctx* c, const lt_trace_args* a, const lt_params* p, const float* d_image,
+                                 lt_grads* g, PassArgs& A, size_t side) {
+  return backward_common(c, a, p, d_image, g, A, side, ctx_work(c));
 }
 
 lt_status lt_backward_naive(lt_ctx* c, const lt_trace_args* a, const lt_params* p, const float* d_image,
@@ -852,23 +881,45 @@ lt_status lt_backward_reslrb(lt_ctx* c, const lt_trace_args* a, const lt_params*
   return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
 }
 
-lt_status lt_backward_lrb3(lt_ctx* c, const lt_trace_args* a, const lt_params* p, const float* d_image,
-                           lt_grads* g) {
+lt_status lt_backward_lrb2(lt_ctx* c, const lt_trace_args* a, const lt_params* p, const float* d_image,
+                           const void* records, size_t bytes, lt_grads* g) {
   if (!c) return LT_ERR_ARG;
+  if (a && (a->flags & LT_ATTACHED)) return c->fail(LT_ERR_UNSUPPORTED, "the buffered two-pass backward is detached%s");
+  if (a && !(a->flags & LT_RECORD_SPLATS)) return c->fail(LT_ERR_ARG, "two-pass backward needs LT_RECORD_SPLATS args%s");
+  if (a && (!records || bytes < side_layout(a).total)) return c->fail(LT_ERR_ARG, "splat record buffer too small%s");
   PassArgs A;
-  lt_status st = backward_common(c, a, p, d_image, g, A, a ? hand_bytes(c, a) : 0);
+  lt_status st = backward_common(c, a, p, d_image, g, A, a ? side_layout(a).total : 0);
+  if (st != LT_OK) return st;
+  SideLayout L = side_layout(a);
+  A.contrib = a->path_contrib;
+  A.spl_hdr_in = (const SplatHdr*)((const char*)records + L.spl_hdr);
+  A.spl_in = (const SplatRec*)((const char*)records + L.spl);
+  const int blk = c->tune.block, grid = persistent_grid(c, a->n_paths, blk);
+  A.agrad_lds = agrad_in_lds(c, BwdKernel::lrb2, blk, stack_lds(c, blk));
+  if ((st = c->hip(launch_lrb2_bwd(A, grid, blk, c->stream), "two-pass backward")) != LT_OK) return st;
+  return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
+}
+
+// The LRB-3 backward on the working memory w (see Work).
+static lt_status lrb3_enqueue(lt_ctx* c, const lt_trace_args* a, const lt_params* p, const float* d_image,
+                              lt_grads* g, const Work& w) {
+  PassArgs A;
+  lt_status st = backward_common(c, a, p, d_image, g, A, w.hand ? 0 : hand_bytes(c, a), w);
   if (st != LT_OK) return st;
   A.contrib = a->path_contrib;
   const bool att = (a->flags & LT_ATTACHED) != 0;
   if (lrb3_split(c, a)) {
     // pass 2 appends one hand-off entry per connected path; pass 3 replays those
-    const size_t need = hand_bytes(c, a);
-    if ((st = grow(c, &c->d_hand, c->hand_n, need, "the LRB-3 hand-off")) != LT_OK) return st;
-    A.hand = reinterpret_cast<Lrb3Hand*>(c->d_hand);
-    A.hand_att = reinterpret_cast<Lrb3HandAtt*>(c->d_hand);
-    A.hand_n = c->d_counter + 1;
-    A.hand_ticket = c->d_counter + 2;
-    if ((st = c->hip(launch_fill_u32(c->d_counter + 1, 2, 0u, c->stream), "hand-off clear")) != LT_OK) return st;
+    char* hand = w.hand;
+    if (!hand) {
+      if ((st = grow(c, &c->d_hand, c->hand_n, hand_bytes(c, a), "the LRB-3 hand-off")) != LT_OK) return st;
+      hand = c->d_hand;
+    }
+    A.hand = reinterpret_cast<Lrb3Hand*>(hand);
+    A.hand_att = reinterpret_cast<Lrb3HandAtt*>(hand);
+    A.hand_n = w.counter + 1;
+    A.hand_ticket = w.counter + 2;
+    if ((st = c->hip(launch_fill_u32(w.counter + 1, 2, 0u, c->stream), "hand-off clear")) != LT_OK) return st;
     if (att) {
       const int blk2 = 256;
       if ((st = c->hip(launch_lrb3_att_p2(A, persistent_grid(c, a->n_paths, blk2), blk2, c->stream),
@@ -897,7 +948,13 @@ lt_status lt_backward_lrb3(lt_ctx* c, const lt_trace_args* a, const lt_params* p
     A.agrad_lds = agrad_in_lds(c, BwdKernel::lrb3, c->tune.block, stack_lds(c, c->tune.block));
     if ((st = c->hip(launch_lrb3_bwd(A, grid, c->tune.block, c->stream), "lrb3 backward")) != LT_OK) return st;
   }
-  return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
+  return c->hip(launch_add_le(w.acc, g->emitter_L, c->stream), "emitter gradient");
+}
+
+lt_status lt_backward_lrb3(lt_ctx* c, const lt_trace_args* a, const lt_params* p, const float* d_image,
+                           lt_grads* g) {
+  if (!c) return LT_ERR_ARG;
+  return lrb3_enqueue(c, a, p, d_image, g, ctx_work(c));
 }
 
 lt_status lt_guide_eval(lt_ctx* c, const float* guide_w, const float* x, const float* n, int64_t count,

@@ -52,6 +52,23 @@ struct alignas(16) ResRec {
 };
 static_assert(sizeof(ResRec) == 32, "reservoir record layout");
 
+// Buffered two-pass (lrb_2pass) side state: a header per path (the depth of
+// its last sensor connection, one bit per vertex for a valid connection) and
+// a splat record per (vertex, path), vertex-major [D][N], preallocated for
+// every vertex up to the maximum depth and written where a connection is
+// valid: the film position u_i and the contribution C_i.
+struct alignas(16) SplatHdr {
+  int32_t klast;
+  int32_t pad;
+  uint64_t vmask;
+};
+static_assert(sizeof(SplatHdr) == 16, "splat header layout");
+struct SplatRec {
+  float ux, uy;
+  float C[3];
+};
+static_assert(sizeof(SplatRec) == 20, "splat record layout");
+
 // Attached naive-AD tape record, [D][N] x 128 bytes: the detached fields,
 // the chart of x_s (triangle slot, v_s), and once x_{s+1} is known the two
 // non-trivial rows of J_s = dp_{s+1}/dp_s and dv_{s+1}/d(channels).

@@ -272,10 +272,11 @@ __device__ __forceinline__ float luminance(f3 c) { return 0.2126f * c.x + 0.7152
 // Light tracing with a connection + splat at every Lambertian vertex
 // (Eq. 1-2, Eq. 20).  RESV: streams valid connections through a capacity-1
 // weighted reservoir (Eq. 8) and records/splats the selection (Eq. 9).
-// TAPE: writes the per-vertex naive-AD tape.  Each loop iteration advances
-// every live lane by one vertex; the splat is issued cooperatively by the
-// whole wave after the step.
-template <bool TAPE, bool RESV>
+// TAPE: writes the per-vertex naive-AD tape.  SPL: writes the buffered
+// two-pass splat records (u_i, C_i of every valid connection, a per-path
+// header).  Each loop iteration advances every live lane by one vertex; the
+// splat is issued cooperatively by the whole wave after the step.
+template <bool TAPE, bool RESV, bool SPL = false>
 __device__ __forceinline__ void trace_run(const PassArgs& A, int* lds) {
   int* stk = lds + threadIdx.x;
   const int ss = blockDim.x;
@@ -289,9 +290,12 @@ __device__ __forceinline__ void trace_run(const PassArgs& A, int* lds) {
   int R = 0;
   f3 CR = {0.f, 0.f, 0.f};
   float fac = 0.f, Sl = 0.f;  // emission factor, path contribution sum_i lum(C_i)
+  int klast = 0;              // SPL: last connection depth and validity bits
+  uint64_t vmask = 0ull;
   const f3 Le = ld3(A.Le);
   while (true) {
     refill(A, alive, exhausted, path, [&](uint32_t p) {
+      if (SPL) { SplatHdr z{}; A.spl_hdr[p] = z; }
       if (TAPE) A.tape_len[p] = 0;
       if (RESV && A.res) { ResRec z{}; A.res[p] = z; }
       if (A.sig) A.sig[p] = 0u;
@@ -307,11 +311,17 @@ __device__ __forceinline__ void trace_run(const PassArgs& A, int* lds) {
         beta = Le * fac;
         j = 1; nrec = 0; sig = 0x811C9DC5u;
         Om = 0.f; omR = 0.f; R = 0; Sl = 0.f;
+        klast = 0; vmask = 0ull;
       }
       Event ev = bounce(A, path, j, r, 1, stk, ss);
       if (A.sig) sig = sig_event(sig, ev);
       if (ev.kind == 1 && ev.valid) {
         f3 C = mul(beta, ev.rho) * ev.g;
+        if (SPL) {
+          SplatRec* o = A.spl + (size_t)(j - 1) * (size_t)A.n_paths + path;
+          o->ux = ev.ux; o->uy = ev.uy; o->C[0] = C.x; o->C[1] = C.y; o->C[2] = C.z;
+          klast = j; vmask |= 1ull << (j - 1);
+        }
         if (!selected) { has = true; sux = ev.ux; suy = ev.uy; sC = C; }
         Sl += luminance(C);
         if (RESV) {
@@ -347,6 +357,11 @@ __device__ __forceinline__ void trace_run(const PassArgs& A, int* lds) {
           A.res[path] = rr;
         }
         if (TAPE) A.tape_len[path] = nrec;
+        if (SPL) {
+          SplatHdr hd;
+          hd.klast = klast; hd.pad = 0; hd.vmask = vmask;
+          A.spl_hdr[path] = hd;
+        }
         if (A.sig) A.sig[path] = fnv1a(sig, (uint32_t)R);
         if (A.contrib) A.contrib[path] = Sl;
         alive = false; j = 0;
@@ -360,10 +375,10 @@ __device__ __forceinline__ void trace_run(const PassArgs& A, int* lds) {
 // At most 96 VGPRs (five waves per SIMD, with the default 10 x 128-thread
 // workgroups per CU): a few registers spill and the caustic forward runs 5%
 // faster than at four waves; the box forward is unchanged.
-template <bool TAPE, bool RESV>
+template <bool TAPE, bool RESV, bool SPL = false>
 __global__ void __launch_bounds__(1024, 5) k_trace(PassArgs A) {
   extern __shared__ int lds[];
-  trace_run<TAPE, RESV>(A, lds);
+  trace_run<TAPE, RESV, SPL>(A, lds);
 }
 
 // ---------------------------------------------------------------- naive AD
@@ -571,6 +586,92 @@ __device__ __forceinline__ void lrb3_run(const PassArgs& A, int* lds) {
 __global__ void __launch_bounds__(1024) k_lrb3_bwd(PassArgs A) {
   extern __shared__ int lds[];
   lrb3_run(A, lds);
+}
+
+// ---------------------------------------------------------------- buffered two-pass
+// The buffered two-pass variant (lrb_2pass, Sec. 4.1 and Sec. 6): the forward
+// stored every connection's film position and contribution in a buffer
+// preallocated to the maximum depth, so delta_total = sum_i dI(u_i) C_i
+// (Eq. 14) is read back without a traversal, and one replay (no shadow rays,
+// no connection geometry: u_i and C_i come from the buffer) consumes it as
+// LRB-3's pass 3 does (Eq. 15-17).  Memory is linear in depth, traversals
+// two (forward and replay), the gradient naive AD's.
+__device__ __forceinline__ void lrb2_run(const PassArgs& A, int* lds) {
+  int* stk = lds + threadIdx.x;
+  const int ss = blockDim.x;
+  AGrad ga = agrad_begin(A, lds + A.sc.stack_n * blockDim.x);
+  const size_t N = (size_t)A.n_paths;
+  bool alive = false, exhausted = false;
+  uint32_t path = 0;
+  int j = 0, klast = 0;
+  uint64_t vmask = 0ull;
+  Ray r;
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+  const f3 Le = ld3(A.Le);
+  const D3R iLe = recip_le(Le);
+  double gl0 = 0.0, gl1 = 0.0, gl2 = 0.0;
+  while (true) {
+    refill(A, alive, exhausted, path, [&](uint32_t p) { if (A.contrib) A.contrib[p] = 0.f; });
+    if (__ballot(alive) == 0ull) break;
+    bool has = false;
+    int texel = 0;
+    f3 gv = {0.f, 0.f, 0.f};
+    if (alive && j == 0) {
+      const SplatHdr hd = A.spl_hdr_in[path];
+      klast = min(hd.klast, A.D);
+      vmask = hd.vmask;
+      d0 = d1 = d2 = 0.0;
+      for (uint64_t m = vmask; m; m &= m - 1ull) {
+        const int i = __ffsll((unsigned long long)m);  // 1-based vertex
+        if (i > klast) break;
+        const SplatRec rec = A.spl_in[(size_t)(i - 1) * N + path];
+        LT_COUNT(9, 1);
+        f3 Lb = gather(A.sc, A.dI, rec.ux, rec.uy);
+        d0 += (double)Lb.x * rec.C[0]; d1 += (double)Lb.y * rec.C[1]; d2 += (double)Lb.z * rec.C[2];
+      }
+      if (klast > 0 && (d0 != 0.0 || d1 != 0.0 || d2 != 0.0)) {
+        add_le(A, gl0, gl1, gl2, d0 * iLe.x, d1 * iLe.y, d2 * iLe.z);
+        if (A.contrib) A.contrib[path] = (float)(fabs(d0) + fabs(d1) + fabs(d2));
+        emit_path(A, path, r);
+        j = 1;
+      } else {
+        if (A.contrib) A.contrib[path] = 0.f;
+        alive = false;
+      }
+    }
+    if (alive) {
+      Event ev = bounce(A, path, j, r, 0, stk, ss);
+      const bool last = j >= klast;
+      if (ev.kind == 1) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        if ((vmask >> (j - 1)) & 1ull) {
+          const SplatRec rec = A.spl_in[(size_t)(j - 1) * N + path];
+          LT_COUNT(9, 1);
+          f3 Lb = gather(A.sc, A.dI, rec.ux, rec.uy);
+          a0 = (double)Lb.x * rec.C[0]; a1 = (double)Lb.y * rec.C[1]; a2 = (double)Lb.z * rec.C[2];
+        }
+        d0 -= a0; d1 -= a1; d2 -= a2;
+        if (last) { d0 = d1 = d2 = 0.0; }
+        double g0 = a0, g1 = a1, g2 = a2;
+        if (!last) { g0 += d0; g1 += d1; g2 += d2; }
+        texel = ev.texel;
+        gv = {ev.rho.x > 0.f ? (float)g0 / ev.rho.x : 0.f, ev.rho.y > 0.f ? (float)g1 / ev.rho.y : 0.f,
+              ev.rho.z > 0.f ? (float)g2 / ev.rho.z : 0.f};
+        has = true;
+      }
+      if (ev.cont && !last) ++j;
+      else { alive = false; j = 0; }
+    }
+    keep_finite(A, has, gv);
+    scatter_albedo(A, ga, has, texel, gv);
+  }
+  flush_le(A, gl0, gl1, gl2);
+  agrad_end(A, ga);
+}
+
+__global__ void __launch_bounds__(1024) k_lrb2_bwd(PassArgs A) {
+  extern __shared__ int lds[];
+  lrb2_run(A, lds);
 }
 
 // ---------------------------------------------------------------- LRB-3, two kernels
@@ -892,7 +993,7 @@ hipError_t set_lds_limit(int bytes) {
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_lrb3_att_entry, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   for (const void* f : {(const void*)k_lrb3_p2, (const void*)k_lrb3_p3, (const void*)k_lrb3_att_p2,
-                        (const void*)k_lrb3_att_p3})
+                        (const void*)k_lrb3_att_p3, (const void*)k_lrb2_bwd})
     if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   return e;
 }
@@ -924,6 +1025,7 @@ int resident_groups(BwdKernel k, int block, size_t lds) {
     case BwdKernel::lrb3_p3: f = (const void*)k_lrb3_p3; break;
     case BwdKernel::lrb3_att_p2: f = (const void*)k_lrb3_att_p2; break;
     case BwdKernel::lrb3_att_p3: f = (const void*)k_lrb3_att_p3; break;
+    case BwdKernel::lrb2: f = (const void*)k_lrb2_bwd; break;
   }
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, block, lds) != hipSuccess) {
@@ -1014,6 +1116,17 @@ hipError_t launch_reslrb_bwd(const PassArgs& A, int grid, int block, hipStream_t
 
 hipError_t launch_lrb3_bwd(const PassArgs& A, int grid, int block, hipStream_t s) {
   hipLaunchKernelGGL(k_lrb3_bwd, dim3(grid), dim3(block), stack_bytes(A, block) + agrad_bytes(A), s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace_splats(const PassArgs& A, bool resv, int grid, int block, hipStream_t s) {
+  size_t sh = stack_bytes(A, block);
+  if (resv) hipLaunchKernelGGL((k_trace<false, true, true>), dim3(grid), dim3(block), sh, s, A);
+  else hipLaunchKernelGGL((k_trace<false, false, true>), dim3(grid), dim3(block), sh, s, A);
+  return hipGetLastError();
+}
+hipError_t launch_lrb2_bwd(const PassArgs& A, int grid, int block, hipStream_t s) {
+  hipLaunchKernelGGL(k_lrb2_bwd, dim3(grid), dim3(block), stack_bytes(A, block) + agrad_bytes(A), s, A);
   return hipGetLastError();
 }
 

@@ -46,6 +46,10 @@ struct PassArgs {
   float* contrib;             // per-path image contribution sum_i lum(C_i), or null
   // LRB-3 as two kernels: pass 2 appends a hand-off entry per connected path,
   // pass 3 replays the queued paths
+  SplatHdr* spl_hdr;          // buffered two-pass: per-path header [n_paths] (forward writes)
+  SplatRec* spl;              // and splat records [D][n_paths]
+  const SplatHdr* spl_hdr_in; // (backward reads)
+  const SplatRec* spl_in;
   Lrb3Hand* hand;             // detached entries [n_paths]
   Lrb3HandAtt* hand_att;      // attached entries [n_paths]
   unsigned int* hand_n;       // entries appended (pass 2) / available (pass 3)
@@ -83,6 +87,10 @@ hipError_t launch_guide_adam(float* w, const float* grad, float* m, float* v, in
                              float eps, float c1, float c2, hipStream_t s);
 
 hipError_t launch_trace(const PassArgs& A, bool tape, bool resv, int grid, int block, hipStream_t s);
+// forward that also writes the buffered two-pass splat records
+hipError_t launch_trace_splats(const PassArgs& A, bool resv, int grid, int block, hipStream_t s);
+// buffered two-pass backward: delta_total from the records, one replay
+hipError_t launch_lrb2_bwd(const PassArgs& A, int grid, int block, hipStream_t s);
 // batches: `table` is a DEVICE array of n PassArgs; stack_n the largest
 // traversal stack among them
 hipError_t launch_trace_batch(const PassArgs* table, int n, int stack_n, int grid, int block, hipStream_t s);
@@ -117,7 +125,7 @@ hipError_t set_lds_limit(int bytes);
 // Workgroups of a backward kernel resident per CU at `block` threads and
 // `lds` dynamic LDS bytes (0 if it cannot launch or the query fails).
 enum class BwdKernel { naive, reslrb, lrb3, naive_att, reslrb_att, lrb3_att, lrb3_batch, lrb3_att_batch, lrb3_att_entry,
-                       lrb3_p2, lrb3_p3, lrb3_att_p2, lrb3_att_p3 };
+                       lrb3_p2, lrb3_p3, lrb3_att_p2, lrb3_att_p3, lrb2 };
 int resident_groups(BwdKernel k, int block, size_t lds);
 hipError_t read_counters(uint64_t* out, bool reset, hipStream_t s);
 hipError_t launch_refit_level(Node* nodes, const Tri* tris, const int32_t* level_nodes, int n, hipStream_t s);

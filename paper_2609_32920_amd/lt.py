@@ -7,7 +7,7 @@ fallback.
 
 The functions carry the C ABI's names (include/lt.h):
   lt_create / lt_scene_upload / lt_trace / lt_loss_l2 /
-  lt_backward_naive / lt_backward_reslrb / lt_backward_lrb3 /
+  lt_backward_naive / lt_backward_reslrb / lt_backward_lrb3 / lt_backward_lrb2 /
   lt_guide_eval / lt_guide_emit / lt_guide_grad / lt_guide_adam /
   lt_guide_train_step /
   lt_batch_create / lt_batch_step / lt_batch_autotune
@@ -28,7 +28,7 @@ LIB_PATH = os.path.join(_HERE, "liblt.so")
 COUNTERS_LIB_PATH = os.path.join(_HERE, "liblt_counters.so")
 
 LT_OK, LT_ERR_ARG, LT_ERR_OOM, LT_ERR_HIP, LT_ERR_STATE, LT_ERR_UNSUPPORTED = range(6)
-ATTACHED, SPLAT_SELECTED, RECORD_TAPE, RECORD_RESERVOIR, CONTRIB_ADJOINT = 1, 2, 4, 8, 16
+ATTACHED, SPLAT_SELECTED, RECORD_TAPE, RECORD_RESERVOIR, CONTRIB_ADJOINT, RECORD_SPLATS = 1, 2, 4, 8, 16, 32
 _STATUS = {1: "LT_ERR_ARG", 2: "LT_ERR_OOM", 3: "LT_ERR_HIP", 4: "LT_ERR_STATE", 5: "LT_ERR_UNSUPPORTED"}
 
 
@@ -117,6 +117,8 @@ def library(path=LIB_PATH):
             "lt_backward_reslrb": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp, vp, C.c_size_t,
                                     C.POINTER(Grads)], C.c_int),
             "lt_backward_lrb3": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp, C.POINTER(Grads)], C.c_int),
+            "lt_backward_lrb2": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp, vp, C.c_size_t,
+                                  C.POINTER(Grads)], C.c_int),
             "lt_guide_eval": ([vp, vp, vp, vp, C.c_int64, vp], C.c_int),
             "lt_guide_emit": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp, vp], C.c_int),
             "lt_guide_grad": ([vp, vp, vp, C.c_int64, vp, vp], C.c_int),
@@ -143,7 +145,7 @@ def exported_symbols():
     return ["lt_create", "lt_destroy", "lt_last_error", "lt_set_stream", "lt_set_tuning", "lt_get_tuning",
             "lt_set_memory_cap", "lt_get_stats", "lt_read_counters", "lt_scene_upload", "lt_side_state_bytes",
             "lt_workspace_bytes", "lt_trace", "lt_loss_l2", "lt_backward_naive", "lt_backward_reslrb",
-            "lt_backward_lrb3", "lt_guide_eval", "lt_guide_emit", "lt_guide_grad", "lt_guide_adam",
+            "lt_backward_lrb3", "lt_backward_lrb2", "lt_guide_eval", "lt_guide_emit", "lt_guide_grad", "lt_guide_adam",
             "lt_guide_train_step",
             "lt_batch_create", "lt_batch_destroy", "lt_batch_last_error", "lt_batch_step", "lt_batch_set_tuning",
             "lt_batch_get_tuning", "lt_batch_autotune"]
@@ -337,6 +339,13 @@ class Context:
         self._status(self.lib.lt_backward_reslrb(self.h, C.byref(a), C.byref(p), _ptr(d_image), _ptr(records),
                                                 nb, C.byref(g)))
 
+    def backward_lrb2(self, a, p, d_image, records, g_albedo, g_Le):
+        self._stream()
+        g = self._grads(g_albedo, g_Le, None)
+        nb = records.numel() * records.element_size()
+        self._status(self.lib.lt_backward_lrb2(self.h, C.byref(a), C.byref(p), _ptr(d_image), _ptr(records), nb,
+                                               C.byref(g)))
+
     def backward_lrb3(self, a, p, d_image, g_albedo, g_Le, g_heights=None):
         self._stream()
         g = self._grads(g_albedo, g_Le, g_heights)
@@ -463,6 +472,10 @@ def lt_backward_reslrb(ctx, args, params, d_image, records, g_albedo, g_Le, g_he
     return ctx.backward_reslrb(args, params, d_image, records, g_albedo, g_Le, g_heights)
 
 
+def lt_backward_lrb2(ctx, args, params, d_image, records, g_albedo, g_Le):
+    return ctx.backward_lrb2(args, params, d_image, records, g_albedo, g_Le)
+
+
 def lt_backward_lrb3(ctx, args, params, d_image, g_albedo, g_Le, g_heights=None):
     return ctx.backward_lrb3(args, params, d_image, g_albedo, g_Le, g_heights)
 
@@ -501,14 +514,15 @@ def lt_batch_autotune(batch, instances, cache_path=None):
 
 
 # ------------------------------------------------------------ autograd
-MODES = ("naive", "reslrb", "lrb3")
+MODES = ("naive", "reslrb", "lrb3", "lrb2")
 
 
 class LightTrace(torch.autograd.Function):
     """image = LightTrace.apply(albedo, Le, heights, ctx, seed, n_paths, depth, mode, flags, mask)
 
-    Forward runs lt_trace (recording the tape for "naive" or the reservoir
-    records for "reslrb"); backward runs the matching lt_backward_* with the
+    Forward runs lt_trace (recording the tape for "naive", the reservoir
+    records for "reslrb" or the splat records for "lrb2", the buffered
+    two-pass variant); backward runs the matching lt_backward_* with the
     incoming image adjoint.  Seed replay is the recomputation: "lrb3" keeps
     no side state at all.  mask (optional, uint8 [n_paths] on the device):
     paths whose byte is 0 contribute nothing to the image or the gradients.
@@ -520,7 +534,7 @@ class LightTrace(torch.autograd.Function):
             raise ValueError(mode)
         if mask is not None and (mask.dtype != torch.uint8 or mask.numel() != n_paths or not mask.is_contiguous()):
             raise ValueError("mask must be a contiguous uint8 tensor with one byte per path")
-        rec = RECORD_TAPE if mode == "naive" else RECORD_RESERVOIR if mode == "reslrb" else 0
+        rec = {"naive": RECORD_TAPE, "reslrb": RECORD_RESERVOIR, "lrb2": RECORD_SPLATS}.get(mode, 0)
         a = ctx.args(seed, n_paths, depth, flags | rec, mask)
         p = ctx.params(albedo, Le, heights)
         nb = ctx.side_state_bytes(a)
@@ -546,6 +560,8 @@ class LightTrace(torch.autograd.Function):
             ctx.backward_naive(a, p, dI, side, g_alb, g_le, g_h)
         elif mode == "reslrb":
             ctx.backward_reslrb(a, p, dI, side, g_alb, g_le, g_h)
+        elif mode == "lrb2":
+            ctx.backward_lrb2(a, p, dI, side, g_alb, g_le)
         else:
             ctx.backward_lrb3(a, p, dI, g_alb, g_le, g_h)
         return g_alb, g_le, g_h, None, None, None, None, None, None, None

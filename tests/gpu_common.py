@@ -61,7 +61,7 @@ class GpuRun:
 
     def backward(self, mode, seed, n, depth, dI, flags=0, mask=None, side=None, want_info=False):
         m = None if mask is None else torch.as_tensor(np.asarray(mask, np.uint8), device=self.dev)
-        rec = lt.RECORD_TAPE if mode == "naive" else lt.RECORD_RESERVOIR if mode == "reslrb" else 0
+        rec = {"naive": lt.RECORD_TAPE, "reslrb": lt.RECORD_RESERVOIR, "lrb2": lt.RECORD_SPLATS}.get(mode, 0)
         info = torch.zeros(n, dtype=torch.int32, device=self.dev) if want_info else None
         a = self.ctx.args(seed, n, depth, flags | rec, m, None, info)
         p = self.params()
@@ -78,6 +78,8 @@ class GpuRun:
             self.ctx.backward_naive(a, p, dIt, side, g_alb, g_le, g_h)
         elif mode == "reslrb":
             self.ctx.backward_reslrb(a, p, dIt, side, g_alb, g_le, g_h)
+        elif mode == "lrb2":
+            self.ctx.backward_lrb2(a, p, dIt, side, g_alb, g_le)
         else:
             self.ctx.backward_lrb3(a, p, dIt, g_alb, g_le, g_h)
         torch.cuda.synchronize()

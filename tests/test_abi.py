@@ -27,7 +27,8 @@ def declared_functions():
 
 def test_header_declares_the_paper_entry_points():
     names = declared_functions()
-    for n in ("lt_scene_upload", "lt_trace", "lt_backward_naive", "lt_backward_reslrb", "lt_backward_lrb3"):
+    for n in ("lt_scene_upload", "lt_trace", "lt_backward_naive", "lt_backward_reslrb", "lt_backward_lrb3",
+              "lt_backward_lrb2"):
         assert n in names
 
 
@@ -57,6 +58,10 @@ def test_side_state_linear_for_tape_flat_for_replay(lib):
     assert res[0] == res[1] == res[2] == 32 * n
     # LRB-3: nothing
     assert none == [0, 0, 0]
+    # buffered two-pass: a 16-byte header per path and a 20-byte splat record
+    # preallocated for every (vertex, path): linear in depth, 20/32 of the tape
+    spl = [lib.lt_side_state_bytes(None, C.byref(_args(n, d, lt.RECORD_SPLATS))) for d in (8, 16, 32)]
+    assert all(s == 16 * n + 20 * n * d for s, d in zip(spl, (8, 16, 32)))
     # the paper's card (16 GiB) cannot hold the depth-32 tape at 4M paths
     # plus its own working set while the replay records stay tiny
     assert tape[2] > 4 << 30 and res[2] < 256 << 20

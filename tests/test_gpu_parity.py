@@ -49,7 +49,7 @@ def test_gradient_parity_all_modes_box(box64):
     dI = _dI((64, 64, 3))
     on = O.gradient(sc, seed, n, D, dI, path_list=ids)
     orr = O.gradient(sc, seed, n, D, dI, mode=O.MODE_RESLRB, path_list=ids)
-    for mode, ref in (("naive", on), ("lrb3", on), ("reslrb", orr)):
+    for mode, ref in (("naive", on), ("lrb3", on), ("reslrb", orr), ("lrb2", on)):
         gg = g.backward(mode, seed, n, D, dI, mask=mask)
         ea, el = maxrel(gg["albedo"], ref["albedo"]), maxrel(gg["Le"], ref["Le"])
         print(f"{mode}: albedo maxrel {ea:.2e}  Le maxrel {el:.2e}", flush=True)
@@ -127,7 +127,7 @@ def test_deeper_paths_and_ragged_sizes(box64):
         assert maxrel(gi, oi) <= TOL, (n, D)
         dI = _dI((64, 64, 3), seed)
         on = O.gradient(sc, seed, n, D, dI, path_list=ids)
-        for mode in ("naive", "lrb3"):
+        for mode in ("naive", "lrb3", "lrb2"):
             gg = g.backward(mode, seed, n, D, dI, mask=mask)
             assert maxrel(gg["albedo"], on["albedo"]) <= TOL, (mode, n, D)
             assert maxrel(gg["Le"], on["Le"]) <= TOL, (mode, n, D)
@@ -139,7 +139,7 @@ def test_empty_mask_gives_zero(box64):
     mask = np.zeros(n, np.uint8)
     img = g.trace(1, n, 4, mask=mask)["image"]
     assert np.all(img == 0)
-    for mode in ("naive", "reslrb", "lrb3"):
+    for mode in ("naive", "reslrb", "lrb3", "lrb2"):
         gg = g.backward(mode, 1, n, 4, _dI((64, 64, 3)), mask=mask)
         assert np.all(gg["albedo"] == 0) and np.all(gg["Le"] == 0)
 
@@ -164,7 +164,7 @@ def test_emitter_identity_full_size():
     img = g.trace(seed, n, D)["image"]
     dI = _dI(img.shape, 3)
     rhs = np.einsum("hwc,hwc->c", dI, img)
-    for mode in ("naive", "lrb3"):
+    for mode in ("naive", "lrb3", "lrb2"):
         gg = g.backward(mode, seed, n, D, dI)
         lhs = np.asarray(sc["Le"]) * gg["Le"]
         print(mode, lhs, rhs, flush=True)
@@ -205,7 +205,7 @@ def test_full_size_sampled_paths():
     assert e <= TOL_DEEP
     dI = _dI(gi.shape, 2)
     on = O.gradient(sc, seed, n, D, dI, path_list=keep)
-    for mode in ("naive", "lrb3"):
+    for mode in ("naive", "lrb3", "lrb2"):
         gg = g.backward(mode, seed, n, D, dI, mask=mask)
         ea, el = maxrel(gg["albedo"], on["albedo"]), maxrel(gg["Le"], on["Le"])
         print(f"full-size sampled {mode}: albedo {ea:.2e} Le {el:.2e}", flush=True)
@@ -279,10 +279,10 @@ def test_autograd_function_against_oracle(box64):
     Io = O.render(sc, seed, n, D, path_list=ids)["image"]
     Lo, dIo = O.loss_and_adjoint(Io, T)
     ref = {"naive": O.gradient(sc, seed, n, D, scale * dIo, path_list=ids)}
-    ref["lrb3"] = ref["naive"]
+    ref["lrb3"] = ref["lrb2"] = ref["naive"]
     ref["reslrb"] = O.gradient(sc, seed, n, D, scale * dIo, mode=O.MODE_RESLRB, path_list=ids)
     m = torch.as_tensor(mask, device=g.dev)
-    for mode in ("naive", "reslrb", "lrb3"):
+    for mode in ("naive", "reslrb", "lrb3", "lrb2"):
         alb = g.albedo.clone().requires_grad_(True)
         le = g.Le.clone().requires_grad_(True)
         img = lt.LightTrace.apply(alb, le, None, g.ctx, seed, n, D, mode, 0, m)
