@@ -295,6 +295,26 @@ lt_status lt_backward_lrb2(lt_ctx* ctx, const lt_trace_args* args, const lt_para
 lt_status lt_backward_lrb3(lt_ctx* ctx, const lt_trace_args* args, const lt_params* params,
                            const float* d_image, lt_grads* grads);
 
+/* lt_backward_lrb3 for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with every piece of working
+ * memory (work counters, statistics, the FP64 emitter-gradient accumulators,
+ * the pass-2 -> pass-3 hand-off) in a static device array of 32 MiB that the
+ * library holds on each GPU it runs on until the process ends.  The call
+ * allocates nothing; the caller still passes inputs and outputs.
+ * Limits: with the two-kernel form (lt_tuning.lrb3_split) n_paths is at most
+ * 524,280 attached (64-byte hand-off entries) or 838,848 detached (40-byte
+ * entries); the fused form has no limit.  No emission guide (its per-path
+ * records are allocated).  lt_get_stats does not report its counters.
+ * Every call on a GPU shares that GPU's array (all contexts on it included)
+ * and clears what must start at zero, so calls that overlap on one GPU race
+ * and must be ordered by the caller.
+ * Errors: as lt_backward_lrb3, plus LT_ERR_ARG (n_paths above the limit),
+ * LT_ERR_UNSUPPORTED (guide weights set, or no scratch address on this
+ * device). */
+lt_status lt_backward_lrb3_noalloc(lt_ctx* ctx, const lt_trace_args* args, const lt_params* params,
+                                   const float* d_image, lt_grads* grads);
+
 /* ------------------------------------------------------------------------
  * Learned emission guide.  An extension of the method, not in the paper:
  * the paper samples emitted directions cosine-weighted (Sec. 3.1).  With

@@ -156,6 +156,15 @@ hipError_t upload(T** dst, const T* src, size_t n) {
 
 }  // namespace
 
+// Device scratch of the no-allocation entry point (lt_backward_lrb3_noalloc):
+// work counters and statistics, the FP64 emitter-gradient accumulators and
+// the LRB-3 hand-off.  One copy per GPU, held from module load to process
+// end; host code reaches it only through the address hipGetSymbolAddress
+// returns for the current device (the array's name is a host-side stand-in).
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+constexpr size_t kScratchCounters = 0, kScratchAcc = 256, kScratchHand = 512;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 struct lt_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -188,6 +197,7 @@ struct lt_ctx {
   size_t gpart_n = 0;
   char* d_hand = nullptr;    // LRB-3 hand-off between its two kernels [hand_n bytes]
   size_t hand_n = 0;
+  char* d_scratch = nullptr; // this device's copy of the static scratch (null: unavailable)
 
   lt_status fail(lt_status s, const char* fmt, const char* a = "") {
     char buf[512];
@@ -464,6 +474,14 @@ lt_status lt_create(int device, void* stream, lt_ctx** out) {
     hipFree(c->d_counter); hipFree(c->d_acc);
     delete c;
     return LT_ERR_OOM;
+  }
+  // the static scratch's address on this device (the device is current)
+  void* sp = nullptr;
+  if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) == hipSuccess && sp) {
+    c->d_scratch = static_cast<char*>(sp);
+  } else {
+    (void)hipGetLastError();
+    c->d_scratch = nullptr;
   }
   *out = c;
   return LT_OK;
@@ -795,8 +813,9 @@ lt_status lt_loss_l2(lt_ctx* c, const float* image, const float* target, int64_t
 // Where a backward call keeps its working memory: u32 counters ([0] work
 // tickets, [1] LRB-3 hand-off entries, [2] pass-3 tickets, [16..19] two u64
 // statistics), the FP64 emitter-gradient accumulators and the LRB-3 hand-off.
-// The entry points use the context's buffers and grow the hand-off on
-// demand.
+// The ordinary entry points use the context's buffers and grow the hand-off
+// on demand; the no-allocation entry point points all three into the static
+// scratch.
 struct Work {
   unsigned int* counter;
   double* acc;
@@ -955,6 +974,26 @@ lt_status lt_backward_lrb3(lt_ctx* c, const lt_trace_args* a, const lt_params* p
                            lt_grads* g) {
   if (!c) return LT_ERR_ARG;
   return lrb3_enqueue(c, a, p, d_image, g, ctx_work(c));
+}
+
+lt_status lt_backward_lrb3_noalloc(lt_ctx* c, const lt_trace_args* a, const lt_params* p, const float* d_image,
+                                   lt_grads* g) {
+  if (!c) return LT_ERR_ARG;
+  if (!c->d_scratch) return c->fail(LT_ERR_UNSUPPORTED, "the static scratch has no address on this device%s");
+  if (!a || !p) return c->fail(LT_ERR_ARG, "null args or params%s");
+  if (p->guide_w) return c->fail(LT_ERR_UNSUPPORTED, "the no-allocation backward takes no guide (its records are allocated)%s");
+  const size_t cap = kScratchBytes - kScratchHand;
+  if (a->n_paths >= 1 && hand_bytes(c, a) > cap) {
+    char buf[256];
+    const size_t entry = (a->flags & LT_ATTACHED) ? sizeof(Lrb3HandAtt) : sizeof(Lrb3Hand);
+    std::snprintf(buf, sizeof(buf), "n_paths %lld exceeds the static scratch: at most %zu paths in this form",
+                  (long long)a->n_paths, cap / entry);
+    c->err = buf;
+    return LT_ERR_ARG;
+  }
+  Work w{reinterpret_cast<unsigned int*>(c->d_scratch + kScratchCounters),
+         reinterpret_cast<double*>(c->d_scratch + kScratchAcc), c->d_scratch + kScratchHand, cap};
+  return lrb3_enqueue(c, a, p, d_image, g, w);
 }
 
 lt_status lt_guide_eval(lt_ctx* c, const float* guide_w, const float* x, const float* n, int64_t count,

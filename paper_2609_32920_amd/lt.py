@@ -119,6 +119,8 @@ def library(path=LIB_PATH):
             "lt_backward_lrb3": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp, C.POINTER(Grads)], C.c_int),
             "lt_backward_lrb2": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp, vp, C.c_size_t,
                                   C.POINTER(Grads)], C.c_int),
+            "lt_backward_lrb3_noalloc": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp, C.POINTER(Grads)],
+                                         C.c_int),
             "lt_guide_eval": ([vp, vp, vp, vp, C.c_int64, vp], C.c_int),
             "lt_guide_emit": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp, vp], C.c_int),
             "lt_guide_grad": ([vp, vp, vp, C.c_int64, vp, vp], C.c_int),
@@ -145,7 +147,7 @@ def exported_symbols():
     return ["lt_create", "lt_destroy", "lt_last_error", "lt_set_stream", "lt_set_tuning", "lt_get_tuning",
             "lt_set_memory_cap", "lt_get_stats", "lt_read_counters", "lt_scene_upload", "lt_side_state_bytes",
             "lt_workspace_bytes", "lt_trace", "lt_loss_l2", "lt_backward_naive", "lt_backward_reslrb",
-            "lt_backward_lrb3", "lt_backward_lrb2", "lt_guide_eval", "lt_guide_emit", "lt_guide_grad", "lt_guide_adam",
+            "lt_backward_lrb3", "lt_backward_lrb2", "lt_backward_lrb3_noalloc", "lt_guide_eval", "lt_guide_emit", "lt_guide_grad", "lt_guide_adam",
             "lt_guide_train_step",
             "lt_batch_create", "lt_batch_destroy", "lt_batch_last_error", "lt_batch_step", "lt_batch_set_tuning",
             "lt_batch_get_tuning", "lt_batch_autotune"]
@@ -350,6 +352,13 @@ class Context:
         self._stream()
         g = self._grads(g_albedo, g_Le, g_heights)
         self._status(self.lib.lt_backward_lrb3(self.h, C.byref(a), C.byref(p), _ptr(d_image), C.byref(g)))
+
+    def backward_lrb3_noalloc(self, a, p, d_image, g_albedo, g_Le, g_heights=None):
+        """lt_backward_lrb3_noalloc: the LRB-3 backward with its working memory
+        in the library's static device scratch (no allocation)."""
+        self._stream()
+        g = self._grads(g_albedo, g_Le, g_heights)
+        self._status(self.lib.lt_backward_lrb3_noalloc(self.h, C.byref(a), C.byref(p), _ptr(d_image), C.byref(g)))
 
     # ------------------------------------------------------------ guide
     def guide_eval(self, guide_w, x, n, out):
