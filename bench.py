@@ -167,6 +167,10 @@ def main():
         traffic = profiled_traffic("k_lrb3_bwd_box256_d32_4M.txt") if (N == 1 << 22 and D == 32 and W == 256) else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    # the same launch's measured DRAM bytes (rocprofv3) over its time: the
+                    # share of the HBM peak the kernel actually moves, beside the
+                    # algorithmic-byte fraction above
+                    "traffic_frac": None if traffic is None else round(traffic / t_launch / 1e9 / HBM_PEAK_GBS, 4),
                     "kernel": "k_lrb3_bwd", "bytes_per_path": round(bpp, 1),
                     "valu_issue_frac_profiled": profiled_traffic("k_lrb3_caustic128_box256_valu.txt",
                                                                  "valu_issue_frac_k_lrb3_bwd"),
@@ -178,38 +182,57 @@ def main():
                     "events_per_path": {k: round(v / sample, 3) for k, v in counts["lrb3"].items()}}
         print(f"# lrb3 algorithmic bytes/path {bpp:.0f}  achieved {achieved:.0f} GB/s", file=sys.stderr)
 
-    # ---- per-method / per-depth sweep: differentiated paths/s, bytes/path
+    # ---- per-method / per-depth sweep: differentiated paths/s, bytes/path.
+    # Side state is what the call's API sizes (lt_side_state_bytes); the
+    # measured figure is the device memory the step holds beyond the inputs
+    # (the side-state tensor, the library workspace it grows: hand-off,
+    # guide records), from hipMemGetInfo before and after, with a fresh
+    # context per entry so that nothing is left over from the last one.
     sweep = {}
     if not args.no_sweep:
+        recs = {"naive": lt.RECORD_TAPE, "reslrb": lt.RECORD_RESERVOIR, "lrb3": 0, "lrb2": lt.RECORD_SPLATS}
         for d in (8, 16, 32):
-            for mode in ("naive", "reslrb", "lrb3"):
-                rec = lt.RECORD_TAPE if mode == "naive" else lt.RECORD_RESERVOIR if mode == "reslrb" else 0
-                a = ctx.args(3000, N, d, rec)
-                nb = ctx.side_state_bytes(a)
+            for mode in ("naive", "reslrb", "lrb3", "lrb2"):
+                rec = recs[mode]
+                torch.cuda.synchronize()
+                torch.cuda.empty_cache()
+                free0 = torch.cuda.mem_get_info(dev)[0]
+                mctx = lt.Context(0).scene_upload(sc)
+                a = mctx.args(3000, N, d, rec)
+                nb = mctx.side_state_bytes(a)
                 side = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev) if nb else None
                 ts = []
                 for k in range(4):
-                    a = ctx.args(3000 + k, N, d, rec)
+                    a = mctx.args(3000 + k, N, d, rec)
                     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                     e0.record(stream)
-                    ctx.trace(a, p, img, side)
-                    ctx.loss_l2(img, target, dI, loss)
+                    mctx.trace(a, p, img, side)
+                    mctx.loss_l2(img, target, dI, loss)
                     if mode == "naive":
-                        ctx.backward_naive(a, p, dI, side, g_alb, g_le)
+                        mctx.backward_naive(a, p, dI, side, g_alb, g_le)
                     elif mode == "reslrb":
-                        ctx.backward_reslrb(a, p, dI, side, g_alb, g_le)
+                        mctx.backward_reslrb(a, p, dI, side, g_alb, g_le)
+                    elif mode == "lrb2":
+                        mctx.backward_lrb2(a, p, dI, side, g_alb, g_le)
                     else:
-                        ctx.backward_lrb3(a, p, dI, g_alb, g_le)
+                        mctx.backward_lrb3(a, p, dI, g_alb, g_le)
                     e1.record(stream)
                     e1.synchronize()
                     if k:
                         ts.append(e0.elapsed_time(e1))
-                del side
+                held = free0 - torch.cuda.mem_get_info(dev)[0]
+                ws = mctx.workspace_bytes(a)
+                del side, mctx
                 ms = float(np.median(ts))
                 sweep[f"{mode}_d{d}"] = {"ms": round(ms, 3), "paths_per_s": round(N / (ms * 1e-3)),
                                          "side_bytes_per_path": round(nb / N, 2),
-                                         "workspace_bytes": ctx.workspace_bytes(a)}
+                                         "workspace_bytes": ws,
+                                         "measured_device_bytes_per_path": round(held / N, 2)}
         torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        print("# memory per path (measured, D 8/16/32): " + "; ".join(
+            f"{m} " + "/".join(f"{sweep[f'{m}_d{d}']['measured_device_bytes_per_path']:.0f}" for d in (8, 16, 32))
+            for m in ("naive", "reslrb", "lrb3", "lrb2")), file=sys.stderr, flush=True)
 
     # ---- equal-error throughput: paths/s x (naive-AD variance / the method's
     # variance), the gradient variance summed over parameters across seeds
@@ -275,7 +298,7 @@ def main():
         guided_batch = bench_guided_batch(lt, scenes, dev, stream)
 
     # ---- CPU baseline: the FP64 oracle, forward + naive backward, on a sample
-    cpu = cpu1 = None
+    cpu = cpu1 = cpu_more = None
     if not args.no_cpu:
         from oracle import oracle as O
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
@@ -299,6 +322,7 @@ def main():
         t1 = time.perf_counter() - t1
         cpu1 = {"value": round(n1 / t1, 1), "unit": "paths/s", "cores": 1, "kind": "oracle",
                 "sample": f"first {n1} paths, one thread, {t1:.2f} s"}
+        cpu_more = cpu_baselines(O, scenes, threads, sc, dIh, N)
 
     out = {
         "metric": "differentiated light paths/s (fwd+bwd) at fixed gradient error; bytes/path vs depth",
@@ -322,6 +346,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "cpu_baseline_1thread": cpu1,
+        "cpu_baseline_workloads": cpu_more,
         "sweep": sweep,
         "equal_error": equal,
         "caustic": caustic,
@@ -333,6 +358,39 @@ def main():
         "guided_batch": guided_batch,
     }
     print(json.dumps(out), flush=True)
+
+
+def cpu_baselines(O, scenes, threads, box, dI_box, N_box, n_box=1 << 18, n_caustic=1 << 15):
+    """The FP64 oracle (forward + taped naive backward) on the other
+    workloads, each on a bounded sample of its paths whose rate stands for
+    the whole job (paths are independent; the rate is per path): the box at
+    depth 8 and 16 (2^18 of 4,194,304 paths) and the attached caustic (128^2
+    heights, 512^2 film, depth 6; 2^15 of 16,777,216 paths: the oracle finds
+    hits by testing every triangle, 33k here)."""
+    import numpy as np
+    out = {}
+    ids = np.arange(n_box, dtype=np.uint32)
+    for d in (8, 16):
+        t0 = time.perf_counter()
+        O.render(box, 2100, N_box, d, path_list=ids, threads=threads)
+        O.gradient(box, 2100, N_box, d, dI_box, path_list=ids, threads=threads)
+        t = time.perf_counter() - t0
+        out[f"box_d{d}"] = {"value": round(n_box / t, 1), "unit": "paths/s", "cores": threads, "kind": "oracle",
+                            "sample": f"first {n_box} of {N_box} paths, 256x256 box, depth {d}, {t:.2f} s; "
+                                      f"rate per path stands for the whole job"}
+    sc = scenes.caustic_scene(G=128, width=512, height=512)
+    dI = np.random.default_rng(9).normal(size=(512, 512, 3)) * 1e-3
+    ids = np.arange(n_caustic, dtype=np.uint32)
+    t0 = time.perf_counter()
+    O.render(sc, 2200, 1 << 24, 6, path_list=ids, threads=threads)
+    O.gradient(sc, 2200, 1 << 24, 6, dI, flags=O.ATTACHED, path_list=ids, threads=threads)
+    t = time.perf_counter() - t0
+    out["caustic"] = {"value": round(n_caustic / t, 1), "unit": "paths/s", "cores": threads, "kind": "oracle",
+                      "sample": f"first {n_caustic} of 16777216 paths, caustic 128^2 heights, 512^2 film, depth 6, "
+                                f"attached, {t:.2f} s; rate per path stands for the whole job"}
+    print("# oracle paths/s: " + ", ".join(f"{k} {v['value']:.0f}" for k, v in out.items()), file=sys.stderr,
+          flush=True)
+    return out
 
 
 def bench_caustic(lt, scenes, dev, stream, bytes_per_path_fn, G=128, film=512, N=1 << 24, D=6, ee_seeds=8):
