@@ -147,14 +147,22 @@ typedef struct {
   const float* heights;   /* [G][G] heightfield offsets, or NULL when hf_G < 2 */
   const float* guide_w;   /* [LT_GUIDE_NPARAMS] emission-guide weights, or NULL for
                              cosine-weighted emission (see the guide section) */
+  const float* normal_map; /* [G][G][2] or NULL: a normal map on the heightfield (the
+                             normal-mapped dielectric panel of Sec. 6.1): the shading
+                             slopes (Sx, Sz) at each grid vertex, blended
+                             barycentrically, shading normal normalize(-Sx, 1, -Sz);
+                             NULL: the slopes are central differences of the heights.
+                             The geometry always comes from the heights. */
 } lt_params;
 
 /* Gradients: DEVICE float arrays, same shapes as lt_params, ACCUMULATED
- * into (the caller zeroes them).  A NULL member is not written. */
+ * into (the caller zeroes them).  A NULL member is not written.
+ * heights and normal_map are written by LT_ATTACHED backward passes. */
 typedef struct {
   float* albedo;
   float* emitter_L;
   float* heights;
+  float* normal_map;
 } lt_grads;
 
 /* Launch shape and strategy knobs (see lt_set_tuning). */

@@ -410,8 +410,9 @@ struct Scene {
   const ora_scene* s;
   int n_static, n_hf, n_all;
   const double* albedo; const double* Le; const double* heights;
+  const double* nmap;   // [G][G][2] normal-map slopes (Sx, Sz), or null: slopes from the heights
   bool attached;
-  long slot_Le, slot_h;
+  long slot_Le, slot_h, slot_n;
   std::vector<D3> tv;   // [n_all][3] primal vertex positions
   // camera frame
   D3 cpos, f, r, u; double tan_half, aspect, K_area;
@@ -436,13 +437,15 @@ struct Scene {
     return V(v);
   }
 
-  void init(const ora_scene* sc, const double* alb, const double* le, const double* h, bool att) {
+  void init(const ora_scene* sc, const double* alb, const double* le, const double* h, const double* nm, bool att) {
     s = sc; albedo = alb; Le = le; heights = h; attached = att && sc->hf_G > 1 && h;
+    nmap = sc->hf_G > 1 ? nm : nullptr;
     n_static = sc->n_tris;
     n_hf = sc->hf_G > 1 ? 2 * (sc->hf_G - 1) * (sc->hf_G - 1) : 0;
     n_all = n_static + n_hf;
     slot_Le = (long)sc->n_tex * sc->tex_res * sc->tex_res * 3;
     slot_h = slot_Le + 3;
+    slot_n = slot_h + (sc->hf_G > 1 ? (long)sc->hf_G * sc->hf_G : 0);
     tv.resize((size_t)n_all * 3);
     for (int t = 0; t < n_static; ++t)
       for (int k = 0; k < 3; ++k)
@@ -502,10 +505,17 @@ struct Scene {
     }
   }
 
-  // Central-difference slope of the heightfield at grid vertex (gi, gj),
-  // one-sided on the border.
+  // Shading slopes at grid vertex (gi, gj): the normal-map parameters when
+  // the surface is normal-mapped, else the central-difference slope of the
+  // heightfield, one-sided on the border.
   void slope(int gi, int gj, V& sx, V& sz) const {
     int G = s->hf_G; double dx = s->hf_dx;
+    if (nmap) {
+      long k = 2 * ((long)gj * G + gi);
+      sx = attached ? leaf(nmap[k], slot_n + k) : V(nmap[k]);
+      sz = attached ? leaf(nmap[k + 1], slot_n + k + 1) : V(nmap[k + 1]);
+      return;
+    }
     int a = std::max(gi - 1, 0), b = std::min(gi + 1, G - 1);
     sx = (hvar(b, gj) - hvar(a, gj)) / V((b - a) * dx);
     int c = std::max(gj - 1, 0), d = std::min(gj + 1, G - 1);
@@ -821,10 +831,10 @@ int ora_dielectric(const double* w_in, const double* ng, const double* ns, doubl
 // info per listed path (bit 1: an ill-conditioned vertex at or before the
 // last sensor connection, see PathResult).
 int ora_render(const ora_scene* sc, const ora_args* A, const double* albedo, const double* Le,
-               const double* heights, double* image, double* slices, uint32_t* sig, int32_t* Rout,
-               double* Wout, double* flux, uint32_t* info) {
+               const double* heights, const double* nmap, double* image, double* slices, uint32_t* sig,
+               int32_t* Rout, double* Wout, double* flux, uint32_t* info) {
   if (A->guide_w && sc->em_type != ORA_EMIT_QUAD) return -1;  // the guide steers area emission only
-  Scene S; S.init(sc, albedo, Le, heights, false);
+  Scene S; S.init(sc, albedo, Le, heights, nmap, false);
   const int W = sc->width, H = sc->height, D = A->max_depth;
   const long npix = (long)W * H * 3;
   const int64_t n = A->path_list ? A->n_list : A->n_paths;
@@ -878,14 +888,15 @@ int ora_render(const ora_scene* sc, const ora_args* A, const double* albedo, con
 // weight Omega_k/omega_R (Eq. 11).  Gradients are accumulated into g_*
 // (g_heights only when ORA_F_ATTACHED and the scene has a heightfield).
 int ora_gradient(const ora_scene* sc, const ora_args* A, int mode, const double* albedo,
-                 const double* Le, const double* heights, const double* dI, double* g_albedo,
-                 double* g_Le, double* g_heights) {
+                 const double* Le, const double* heights, const double* nmap, const double* dI, double* g_albedo,
+                 double* g_Le, double* g_heights, double* g_nmap) {
   if (A->guide_w && sc->em_type != ORA_EMIT_QUAD) return -1;
-  Scene S; S.init(sc, albedo, Le, heights, (A->flags & ORA_F_ATTACHED) != 0);
+  Scene S; S.init(sc, albedo, Le, heights, nmap, (A->flags & ORA_F_ATTACHED) != 0);
   const int W = sc->width, H = sc->height;
   const int64_t n = A->path_list ? A->n_list : A->n_paths;
   const long n_alb = S.slot_Le, n_h = sc->hf_G > 1 ? (long)sc->hf_G * sc->hf_G : 0;
-  const long nslot = n_alb + 3 + n_h;
+  const long n_n = S.nmap ? 2 * n_h : 0;
+  const long nslot = n_alb + 3 + n_h + n_n;
   int nt = A->n_threads > 0 ? A->n_threads : omp_get_max_threads();
   std::vector<std::vector<double>> gr(nt, std::vector<double>(nslot, 0.0));
 #pragma omp parallel num_threads(nt)
@@ -931,7 +942,8 @@ int ora_gradient(const ora_scene* sc, const ora_args* A, int mode, const double*
     double s = 0; for (int t = 0; t < nt; ++t) s += gr[t][q];
     if (q < n_alb) { if (g_albedo) g_albedo[q] += s; }
     else if (q < n_alb + 3) { if (g_Le) g_Le[q - n_alb] += s; }
-    else if (g_heights) g_heights[q - n_alb - 3] += s;
+    else if (q < n_alb + 3 + n_h) { if (g_heights) g_heights[q - n_alb - 3] += s; }
+    else if (g_nmap) g_nmap[q - n_alb - 3 - n_h] += s;
   }
   return 0;
 }

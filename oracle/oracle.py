@@ -81,8 +81,8 @@ def _load():
             build()
         _lib = C.CDLL(_LIB)
         dp, ip, up = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_uint32)
-        _lib.ora_render.argtypes = [C.POINTER(_Scene), C.POINTER(_Args), dp, dp, dp, dp, dp, up, ip, dp, dp, up]
-        _lib.ora_gradient.argtypes = [C.POINTER(_Scene), C.POINTER(_Args), C.c_int, dp, dp, dp, dp, dp, dp, dp]
+        _lib.ora_render.argtypes = [C.POINTER(_Scene), C.POINTER(_Args), dp, dp, dp, dp, dp, dp, up, ip, dp, dp, up]
+        _lib.ora_gradient.argtypes = [C.POINTER(_Scene), C.POINTER(_Args), C.c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp]
         _lib.ora_reservoir.argtypes = [dp, dp, C.c_int, dp]
         _lib.ora_reservoir.restype = C.c_int
         _lib.ora_philox.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, up]
@@ -166,26 +166,32 @@ def _args(seed, n_paths, depth, flags, threads, path_list, keep, guide_w=None, g
     return a
 
 
-def _params(sc, albedo, Le, heights, keep):
+def _params(sc, albedo, Le, heights, keep, normal_map=None):
     albedo = keep.f64(sc["albedo"] if albedo is None else albedo)
     Le = keep.f64(sc["Le"] if Le is None else Le)
     if heights is None:
         heights = sc.get("heights")
     heights = None if heights is None else keep.f64(heights)
-    return albedo, Le, heights
+    if normal_map is None:
+        normal_map = sc.get("normal_map")
+    normal_map = None if normal_map is None else keep.f64(normal_map)
+    return albedo, Le, heights, normal_map
 
 
 def render(sc, seed, n_paths, depth, albedo=None, Le=None, heights=None, flags=0,
-           path_list=None, slices=False, per_path=False, threads=0, guide_w=None, guide_bf16=True):
+           path_list=None, slices=False, per_path=False, threads=0, guide_w=None, guide_bf16=True,
+           normal_map=None):
     """FP64 light-tracing image [H,W,3] (plus optional per-depth slices,
     per-path signature / reservoir index R / weight W / ill-conditioning
     flag, and total flux).
-    guide_w: emission-guide weights (guided emission), else cosine emission."""
+    guide_w: emission-guide weights (guided emission), else cosine emission.
+    normal_map: [G*G*2] shading slopes of a normal-mapped heightfield
+    (default: the scene's, if any; else slopes from the heights)."""
     lib = _load()
     keep = _Keep()
     s = _scene(sc, keep)
     a = _args(seed, n_paths, depth, flags, threads, path_list, keep, guide_w, guide_bf16)
-    alb, le, h = _params(sc, albedo, Le, heights, keep)
+    alb, le, h, nm = _params(sc, albedo, Le, heights, keep, normal_map)
     H, W = int(sc["camera"]["height"]), int(sc["camera"]["width"])
     img = np.zeros((H, W, 3))
     sl = np.zeros((depth, H, W, 3)) if slices else None
@@ -195,7 +201,7 @@ def render(sc, seed, n_paths, depth, albedo=None, Le=None, heights=None, flags=0
     Wr = np.zeros(n) if per_path else None
     info = np.zeros(n, np.uint32) if per_path else None
     flux = np.zeros(3)
-    rc = lib.ora_render(C.byref(s), C.byref(a), _p(alb), _p(le), _p(h), _p(img), _p(sl),
+    rc = lib.ora_render(C.byref(s), C.byref(a), _p(alb), _p(le), _p(h), _p(nm), _p(img), _p(sl),
                         _p(sig, C.c_uint32), _p(R, C.c_int32), _p(Wr), _p(flux), _p(info, C.c_uint32))
     if rc != 0:
         raise ValueError("oracle render rejected its arguments")
@@ -208,24 +214,26 @@ def render(sc, seed, n_paths, depth, albedo=None, Le=None, heights=None, flags=0
 
 
 def gradient(sc, seed, n_paths, depth, dI, mode=MODE_NAIVE, albedo=None, Le=None, heights=None,
-             flags=0, path_list=None, threads=0, guide_w=None, guide_bf16=True):
+             flags=0, path_list=None, threads=0, guide_w=None, guide_bf16=True, normal_map=None):
     """Gradient of <dI, I(theta)> w.r.t. albedo texels, emitter radiance and
-    (attached) heights, by taped reverse-mode AD of each light path.  With
-    guide_w the emission is guided and its density is held fixed (detached)."""
+    (attached) heights and normal-map slopes, by taped reverse-mode AD of
+    each light path.  With guide_w the emission is guided and its density is
+    held fixed (detached)."""
     lib = _load()
     keep = _Keep()
     s = _scene(sc, keep)
     a = _args(seed, n_paths, depth, flags, threads, path_list, keep, guide_w, guide_bf16)
-    alb, le, h = _params(sc, albedo, Le, heights, keep)
+    alb, le, h, nm = _params(sc, albedo, Le, heights, keep, normal_map)
     dI = keep.f64(dI)
     g_alb = np.zeros_like(alb)
     g_le = np.zeros(3)
     g_h = np.zeros_like(h) if h is not None else None
-    rc = lib.ora_gradient(C.byref(s), C.byref(a), int(mode), _p(alb), _p(le), _p(h), _p(dI),
-                          _p(g_alb), _p(g_le), _p(g_h))
+    g_n = np.zeros_like(nm) if nm is not None else None
+    rc = lib.ora_gradient(C.byref(s), C.byref(a), int(mode), _p(alb), _p(le), _p(h), _p(nm), _p(dI),
+                          _p(g_alb), _p(g_le), _p(g_h), _p(g_n))
     if rc != 0:
         raise ValueError("oracle gradient rejected its arguments")
-    return dict(albedo=g_alb, Le=g_le, heights=g_h)
+    return dict(albedo=g_alb, Le=g_le, heights=g_h, normal_map=g_n)
 
 
 def loss_and_adjoint(image, target):

@@ -318,6 +318,8 @@ lt_status check_args(lt_ctx* c, const lt_trace_args* a, const lt_params* p) {
   if (!p->albedo || !p->emitter_L) return c->fail(LT_ERR_ARG, "albedo and emitter_L are required%s");
   if ((a->flags & LT_ATTACHED) && c->dsc.hf_G < 2) return c->fail(LT_ERR_ARG, "LT_ATTACHED needs a heightfield%s");
   if ((a->flags & LT_ATTACHED) && !p->heights) return c->fail(LT_ERR_ARG, "LT_ATTACHED needs params->heights%s");
+  if (p->normal_map && (c->dsc.hf_G < 2 || !p->heights))
+    return c->fail(LT_ERR_ARG, "a normal map needs a heightfield and params->heights%s");
   if (p->guide_w && c->dsc.em_type != LT_EMIT_QUAD) return c->fail(LT_ERR_UNSUPPORTED, "the emission guide needs an area emitter%s");
   if (p->guide_w && !c->guide_ok) return c->fail(LT_ERR_UNSUPPORTED, "guide kernels could not get their LDS%s");
   return LT_OK;
@@ -428,6 +430,7 @@ PassArgs base_args(lt_ctx* c, const lt_trace_args* a, const lt_params* p) {
   A.albedo = p->albedo;
   A.Le = p->emitter_L;
   A.heights = p->heights;
+  A.nmap = p->normal_map;
   A.counter = c->d_counter;
   A.stats = reinterpret_cast<unsigned long long*>(c->d_counter + 16);  // same allocation, byte 64
   return A;
@@ -840,6 +843,7 @@ static lt_status backward_common(lt_ctx* c, const lt_trace_args* a, const lt_par
   A.g_albedo = g->albedo;
   A.g_Le_acc = w.acc;
   A.g_heights = g->heights;
+  A.g_nmap = (a->flags & LT_ATTACHED) ? g->normal_map : nullptr;
   if ((st = c->hip(launch_fill_f64(w.acc, 3, 0.0, c->stream), "acc clear")) != LT_OK) return st;
   if ((st = c->hip(launch_fill_u32(w.counter + 16, 4, 0u, c->stream), "stats clear")) != LT_OK) return st;
   return c->hip(launch_fill_u32(w.counter, 1, 0u, c->stream), "counter clear");
@@ -1229,6 +1233,7 @@ BatchPlan batch_plan(lt_batch* b, const lt_instance* inst, int n, int64_t path_d
     B.dI = I.d_image;
     B.g_albedo = I.grads.albedo;
     B.g_heights = I.grads.heights;
+    B.g_nmap = (I.args.flags & LT_ATTACHED) ? I.grads.normal_map : nullptr;
     B.g_Le_acc = b->d_acc + 4 * i;
     B.counter = b->d_cnt + n + i;
     // by the caller's path count, so the autotuner's shortened steps keep the plan's shape

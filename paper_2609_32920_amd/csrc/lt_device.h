@@ -494,14 +494,27 @@ __device__ __forceinline__ void hf_slope(const float* h, int G, float dx, int i,
   sz = (hget(h, G, i, d) - hget(h, G, i, c)) / ((float)(d - c) * dx);
 }
 
-__device__ __forceinline__ f3 hf_shading_normal(const DevScene& sc, const float* h, const Surf& s) {
+// Shading slopes at grid vertex (i, j): the normal-map parameters (Sx, Sz)
+// of a normal-mapped surface when nmap is given, else the central
+// differences of the heights.
+__device__ __forceinline__ void hf_slopes(const float* h, const float* nmap, int G, float dx, int i, int j, float& sx,
+                                          float& sz) {
+  if (nmap) {
+    const float* q = nmap + 2 * (j * G + i);
+    sx = q[0]; sz = q[1];
+    return;
+  }
+  hf_slope(h, G, dx, i, j, sx, sz);
+}
+
+__device__ __forceinline__ f3 hf_shading_normal(const DevScene& sc, const float* h, const float* nmap, const Surf& s) {
   int local = s.prim - sc.n_static;
   float Sx = 0.f, Sz = 0.f;
   float wts[3] = {1.0f - s.b1 - s.b2, s.b1, s.b2};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     int gi, gj; hf_corner(sc.hf_G, local, k, gi, gj);
-    float sx, sz; hf_slope(h, sc.hf_G, sc.hf_dx, gi, gj, sx, sz);
+    float sx, sz; hf_slopes(h, nmap, sc.hf_G, sc.hf_dx, gi, gj, sx, sz);
     Sx += wts[k] * sx; Sz += wts[k] * sz;
   }
   return normalize(mk(-Sx, 1.0f, -Sz));

@@ -90,7 +90,7 @@ __device__ __forceinline__ Event bounce(const PassArgs& A, uint32_t path, int j,
   ev.kind = 2;
   if (j >= A.D) return ev;
   f3 ns = s.ng;
-  if (s.prim >= sc.n_static) ns = hf_shading_normal(sc, A.heights, s);
+  if (s.prim >= sc.n_static) ns = hf_shading_normal(sc, A.heights, A.nmap, s);
   f3 wo; bool refl;
   float cos_t = 1.f;
   int code = dielectric(r.w, s.ng, ns, sc.mat_ior[mat], u.u2, wo, refl, cos_t);

@@ -20,6 +20,7 @@ struct PassArgs {
   const float* albedo;
   const float* Le;
   const float* heights;
+  const float* nmap;          // normal-map slopes [G][G][2] of the heightfield, or null
   unsigned int* counter;
   // forward outputs
   float* image;
@@ -39,6 +40,7 @@ struct PassArgs {
   float* g_albedo;
   double* g_Le_acc;
   float* g_heights;
+  float* g_nmap;              // normal-map gradients [G][G][2], or null
   unsigned long long* stats;  // [0] guard triggers, [1] non-finite drops
   int32_t hgrad_lds;          // heights gradients accumulated per workgroup in LDS
   int32_t agrad_lds;          // albedo gradients accumulated per workgroup in LDS

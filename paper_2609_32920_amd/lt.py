@@ -61,7 +61,7 @@ class TraceArgs(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("albedo", C.c_void_p), ("emitter_L", C.c_void_p), ("heights", C.c_void_p),
-                ("guide_w", C.c_void_p)]
+                ("guide_w", C.c_void_p), ("normal_map", C.c_void_p)]
 
 
 GUIDE_NPARAMS = 11433
@@ -70,7 +70,8 @@ GUIDE_SAMPLE_FLOATS = 12   # lt_guide_sample: x[3] n[3] w[3] pdf S comp
 
 
 class Grads(C.Structure):
-    _fields_ = [("albedo", C.c_void_p), ("emitter_L", C.c_void_p), ("heights", C.c_void_p)]
+    _fields_ = [("albedo", C.c_void_p), ("emitter_L", C.c_void_p), ("heights", C.c_void_p),
+                ("normal_map", C.c_void_p)]
 
 
 class Tuning(C.Structure):
@@ -292,15 +293,17 @@ class Context:
         if t.numel() != numel:
             raise ValueError(f"{name} has {t.numel()} elements, the scene needs {numel}")
 
-    def params(self, albedo, Le, heights=None, guide_w=None):
+    def params(self, albedo, Le, heights=None, guide_w=None, normal_map=None):
         n_alb, n_h = self._sizes()
         self._check(albedo, "albedo", n_alb)
         self._check(Le, "Le", 3)
         if heights is not None:
             self._check(heights, "heights", n_h)
         self._check(guide_w, "guide_w", GUIDE_NPARAMS)
+        self._check(normal_map, "normal_map", 2 * n_h)
         return Params(albedo.data_ptr(), Le.data_ptr(), None if heights is None else heights.data_ptr(),
-                      None if guide_w is None else guide_w.data_ptr())
+                      None if guide_w is None else guide_w.data_ptr(),
+                      None if normal_map is None else normal_map.data_ptr())
 
     def side_state_bytes(self, a):
         return int(self.lib.lt_side_state_bytes(self.h, C.byref(a)))
@@ -318,25 +321,29 @@ class Context:
         self._status(self.lib.lt_loss_l2(self.h, _ptr(image), _ptr(target), image.numel(), _ptr(d_image),
                                         _ptr(loss)))
 
-    def _grads(self, g_albedo, g_Le, g_heights):
+    def _grads(self, g_albedo, g_Le, g_heights, g_normal_map=None):
         n_alb, n_h = self._sizes()
         self._check(g_albedo, "g_albedo", n_alb)
         self._check(g_Le, "g_Le", 3)
         self._check(g_heights, "g_heights", n_h)
+        self._check(g_normal_map, "g_normal_map", 2 * n_h)
         return Grads(None if g_albedo is None else g_albedo.data_ptr(),
                      None if g_Le is None else g_Le.data_ptr(),
-                     None if g_heights is None else g_heights.data_ptr())
+                     None if g_heights is None else g_heights.data_ptr(),
+                     None if g_normal_map is None else g_normal_map.data_ptr())
 
-    def backward_naive(self, a, p, d_image, tape, g_albedo, g_Le, g_heights=None):
+    def backward_naive(self, a, p, d_image, tape, g_albedo, g_Le, g_heights=None,
+                     g_normal_map=None):
         self._stream()
-        g = self._grads(g_albedo, g_Le, g_heights)
+        g = self._grads(g_albedo, g_Le, g_heights, g_normal_map)
         nb = tape.numel() * tape.element_size()
         self._status(self.lib.lt_backward_naive(self.h, C.byref(a), C.byref(p), _ptr(d_image), _ptr(tape), nb,
                                                C.byref(g)))
 
-    def backward_reslrb(self, a, p, d_image, records, g_albedo, g_Le, g_heights=None):
+    def backward_reslrb(self, a, p, d_image, records, g_albedo, g_Le, g_heights=None,
+                     g_normal_map=None):
         self._stream()
-        g = self._grads(g_albedo, g_Le, g_heights)
+        g = self._grads(g_albedo, g_Le, g_heights, g_normal_map)
         nb = records.numel() * records.element_size()
         self._status(self.lib.lt_backward_reslrb(self.h, C.byref(a), C.byref(p), _ptr(d_image), _ptr(records),
                                                 nb, C.byref(g)))
@@ -348,16 +355,16 @@ class Context:
         self._status(self.lib.lt_backward_lrb2(self.h, C.byref(a), C.byref(p), _ptr(d_image), _ptr(records), nb,
                                                C.byref(g)))
 
-    def backward_lrb3(self, a, p, d_image, g_albedo, g_Le, g_heights=None):
+    def backward_lrb3(self, a, p, d_image, g_albedo, g_Le, g_heights=None, g_normal_map=None):
         self._stream()
-        g = self._grads(g_albedo, g_Le, g_heights)
+        g = self._grads(g_albedo, g_Le, g_heights, g_normal_map)
         self._status(self.lib.lt_backward_lrb3(self.h, C.byref(a), C.byref(p), _ptr(d_image), C.byref(g)))
 
-    def backward_lrb3_noalloc(self, a, p, d_image, g_albedo, g_Le, g_heights=None):
+    def backward_lrb3_noalloc(self, a, p, d_image, g_albedo, g_Le, g_heights=None, g_normal_map=None):
         """lt_backward_lrb3_noalloc: the LRB-3 backward with its working memory
         in the library's static device scratch (no allocation)."""
         self._stream()
-        g = self._grads(g_albedo, g_Le, g_heights)
+        g = self._grads(g_albedo, g_Le, g_heights, g_normal_map)
         self._status(self.lib.lt_backward_lrb3_noalloc(self.h, C.byref(a), C.byref(p), _ptr(d_image), C.byref(g)))
 
     # ------------------------------------------------------------ guide
@@ -429,10 +436,10 @@ class Batch:
             arr[k].ctx = ctx.h
             arr[k].args = ctx.args(d["seed"], d["n_paths"], d["depth"], ATTACHED if d.get("attached") else 0,
                                    d.get("mask"))
-            arr[k].params = ctx.params(d["albedo"], d["Le"], d.get("heights"), d.get("guide"))
+            arr[k].params = ctx.params(d["albedo"], d["Le"], d.get("heights"), d.get("guide"), d.get("normal_map"))
             arr[k].target, arr[k].image = d["target"].data_ptr(), d["image"].data_ptr()
             arr[k].d_image, arr[k].loss = d["d_image"].data_ptr(), d["loss"].data_ptr()
-            arr[k].grads = ctx._grads(d["g_albedo"], d.get("g_Le"), d.get("g_heights"))
+            arr[k].grads = ctx._grads(d["g_albedo"], d.get("g_Le"), d.get("g_heights"), d.get("g_normal_map"))
         return arr
 
     def step(self, instances, use_graph=True, table=None):

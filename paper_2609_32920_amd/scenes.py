@@ -19,7 +19,8 @@ Scene dictionary layout (all arrays numpy, float64 unless noted):
   hf       dict(G, x0, z0, dx, base, mat) or None: heightfield top surface
            with vertex (i, j) at (x0 + i*dx, base + h[j*G+i], z0 + j*dx)
   albedo, Le, heights   initial parameters
-  albedo_target, heights_target   parameters that generate the loss target
+  normal_map        optional [G*G*2] shading slopes (Sx, Sz) of a normal-mapped heightfield
+  albedo_target, heights_target, normal_map_target   parameters that generate the loss target
 """
 from __future__ import annotations
 
@@ -184,6 +185,31 @@ def caustic_scene(G=128, width=512, height=512, seed=SCENE_SEED, target_seed=TAR
         heights=h.reshape(-1).copy(),
         albedo_target=None, heights_target=ht.reshape(-1).copy(),
     )
+
+
+def glass_panel_scene(G=16, width=64, height=64, seed=SCENE_SEED, target_seed=TARGET_SEED, slope_sigma=0.05):
+    """Normal-mapped glass panel over a diffuse receiver (attached workload
+    with a normal map, the Glass Panel validation of the paper).
+
+    The caustic scene's slab with a flat top (all heights zero) whose shading
+    comes from a G x G normal map: per-vertex slopes (Sx, Sz), blended
+    barycentrically, shading normal normalize(-Sx, 1, -Sz).  The map starts
+    N(0, slope_sigma) per slope; the target map is a seeded smooth pattern
+    (products of sines and cosines of amplitude ~0.1).
+    """
+    sc = caustic_scene(G=G, width=width, height=height, seed=seed, target_seed=target_seed)
+    rng = np.random.default_rng(seed + 17)
+    nm = rng.normal(0.0, slope_sigma, size=(G, G, 2))
+    trng = np.random.default_rng(target_seed + 17)
+    a, b = trng.uniform(0.05, 0.15, size=2)
+    kx, kz = trng.integers(1, 4, size=2)
+    xs = np.linspace(-0.5, 0.5, G)
+    X, Z = np.meshgrid(xs, xs, indexing="xy")   # X[j, i] = x_i, Z[j, i] = z_j
+    nt = np.stack([a * np.cos(math.pi * kx * (X + 0.5)) * np.sin(math.pi * kz * (Z + 0.5)),
+                   b * np.sin(math.pi * kx * (X + 0.5)) * np.cos(math.pi * kz * (Z + 0.5))], axis=-1)
+    sc.update(name=f"panel{G}_{width}x{height}", heights=np.zeros(G * G), heights_target=None,
+              normal_map=nm.reshape(-1).copy(), normal_map_target=nt.reshape(-1).copy())
+    return sc
 
 
 def plane_point_light_scene(width=32, height=32, rho=0.6, I0=5.0, light_h=0.8,

@@ -24,6 +24,8 @@ class GpuRun:
         self.Le = torch.as_tensor(np.asarray(sc["Le"], np.float32), device=self.dev).contiguous()
         h = sc.get("heights")
         self.heights = None if h is None else torch.as_tensor(np.asarray(h, np.float32), device=self.dev)
+        nm = sc.get("normal_map")
+        self.nmap = None if nm is None else torch.as_tensor(np.asarray(nm, np.float32), device=self.dev).contiguous()
         self.H, self.W = sc["camera"]["height"], sc["camera"]["width"]
         self.guide = None
 
@@ -32,7 +34,7 @@ class GpuRun:
         self.guide = None if w is None else torch.as_tensor(np.asarray(w, np.float32), device=self.dev).contiguous()
 
     def params(self):
-        return self.ctx.params(self.albedo, self.Le, self.heights, self.guide)
+        return self.ctx.params(self.albedo, self.Le, self.heights, self.guide, self.nmap)
 
     def set_params(self, albedo=None, Le=None, heights=None):
         if albedo is not None:
@@ -74,17 +76,19 @@ class GpuRun:
         g_alb = torch.zeros_like(self.albedo)
         g_le = torch.zeros_like(self.Le)
         g_h = torch.zeros_like(self.heights) if self.heights is not None else None
+        g_n = torch.zeros_like(self.nmap) if self.nmap is not None else None
         if mode == "naive":
-            self.ctx.backward_naive(a, p, dIt, side, g_alb, g_le, g_h)
+            self.ctx.backward_naive(a, p, dIt, side, g_alb, g_le, g_h, g_n)
         elif mode == "reslrb":
-            self.ctx.backward_reslrb(a, p, dIt, side, g_alb, g_le, g_h)
+            self.ctx.backward_reslrb(a, p, dIt, side, g_alb, g_le, g_h, g_n)
         elif mode == "lrb2":
             self.ctx.backward_lrb2(a, p, dIt, side, g_alb, g_le)
         else:
-            self.ctx.backward_lrb3(a, p, dIt, g_alb, g_le, g_h)
+            self.ctx.backward_lrb3(a, p, dIt, g_alb, g_le, g_h, g_n)
         torch.cuda.synchronize()
         out = dict(albedo=g_alb.cpu().numpy().astype(np.float64), Le=g_le.cpu().numpy().astype(np.float64),
-                   heights=None if g_h is None else g_h.cpu().numpy().astype(np.float64))
+                   heights=None if g_h is None else g_h.cpu().numpy().astype(np.float64),
+                   normal_map=None if g_n is None else g_n.cpu().numpy().astype(np.float64))
         if want_info:
             out["info"] = info.cpu().numpy().view(np.uint32)
             out["stats"] = self.ctx.stats()

@@ -241,3 +241,35 @@ def test_full_size_caustic_sampled(G, film, n, nsamp, guard_max):
         eh = maxrel(gg["heights"], ref["heights"])
         print(f"caustic G={G} sampled {mode}: heights maxrel {eh:.2e} over {len(sel)} paths", flush=True)
         assert eh <= TOL_FULL, mode
+
+
+@pytest.mark.parametrize("mode", ["naive", "lrb3", "reslrb"])
+def test_normal_mapped_panel_parity(mode):
+    """A flat glass panel whose shading comes from a normal map (Sec. 6.1,
+    Glass Panel): the forward and the attached gradients with respect to the
+    normal-map slopes (through the Jacobians at each refraction) and the
+    heights (through the geometry), against the oracle."""
+    from tests.gpu_common import GpuRun, matched_paths, maxrel
+    sc = scenes.glass_panel_scene(G=16, width=64, height=64)
+    g = GpuRun(sc)
+    seed, n, D = 23, 65536, 5
+    mask, ids, mis, illc = matched_paths(sc, g, seed, n, D, want_illc=True)
+    assert mis <= 1e-3 and illc.mean() <= 5e-2
+    if mode == "naive":
+        e = maxrel(g.trace(seed, n, D, mask=mask)["image"], O.render(sc, seed, n, D, path_list=ids)["image"])
+        print(f"panel image maxrel {e:.2e}", flush=True)
+        assert e <= TOL
+    dI = _dI((64, 64, 3), 5)
+    keep = mask.astype(bool) & ~illc
+    if mode != "naive":
+        first = g.backward(mode, seed, n, D, dI, flags=lt.ATTACHED, mask=mask, want_info=True)
+        guard = (first["info"] & 1) != 0
+        assert guard.mean() <= 1e-2
+        keep &= ~guard
+    sel = np.nonzero(keep)[0].astype(np.uint32)
+    omode = O.MODE_RESLRB if mode == "reslrb" else O.MODE_NAIVE
+    gg = g.backward(mode, seed, n, D, dI, flags=lt.ATTACHED, mask=keep.astype(np.uint8))
+    og = O.gradient(sc, seed, n, D, dI, mode=omode, flags=O.ATTACHED, path_list=sel)
+    en, eh, ea = (maxrel(gg[k], og[k]) for k in ("normal_map", "heights", "albedo"))
+    print(f"panel {mode}: normal map maxrel {en:.2e} heights {eh:.2e} albedo {ea:.2e}", flush=True)
+    assert en <= TOL and eh <= TOL and ea <= TOL
