@@ -59,8 +59,11 @@ typedef enum {
 
 /* material types (lt_scene_desc.mat_type) */
 enum { LT_MAT_ABSORBER = 0, LT_MAT_LAMBERT = 1, LT_MAT_DIELECTRIC = 2 };
-/* emitter types (lt_scene_desc.em_type) */
-enum { LT_EMIT_QUAD = 0, LT_EMIT_POINT = 1 };
+/* emitter types (lt_scene_desc.em_type): an area quad with cosine-weighted
+ * emission, an isotropic point, or a directional quad (a collimated beam
+ * leaving the quad along its normal, as the directional emitter of the
+ * paper's Tumbler scene, Sec. 6.1) */
+enum { LT_EMIT_QUAD = 0, LT_EMIT_POINT = 1, LT_EMIT_DIRECTIONAL = 2 };
 
 /* lt_trace_args.flags */
 enum {
@@ -81,7 +84,12 @@ typedef struct lt_ctx lt_ctx;
  *  mat_type/mat_tex/mat_ior [n_mats]: type, texture index (Lambertian),
  *                         refractive index (dielectric)
  *  n_tex, tex_res         albedo parameters are [n_tex][tex_res][tex_res][3]
- *  emitter: quad (o, e1, e2; one-sided, normal normalize(e1 x e2)) or point (o)
+ *  emitter: quad (o, e1, e2; one-sided, normal normalize(e1 x e2)), point (o) or
+ *          directional quad (o, e1, e2; the beam leaves along the normal, radiance
+ *          = irradiance across the quad, beta_1 = L_e * area); em_tex_res > 0 (quad
+ *          and directional): L_e is an em_tex_res^2 RGB texture over the quad, the
+ *          emission point's texel (floor(u0 R), floor(u1 R)) of its quad coordinates
+ *          u0 along e1, u1 along e2; 0: one RGB radiance
  *  camera: pinhole at cam_pos looking at cam_target, vertical FOV, film
  *          width x height pixels; image row 0 is the top row
  *  heightfield (hf_G >= 2, else none): vertex (i, j) at
@@ -105,6 +113,7 @@ typedef struct {
   int32_t hf_G;
   double hf_x0, hf_z0, hf_dx, hf_base;
   int32_t hf_mat;
+  int32_t em_tex_res;   /* 0 or the emitter texture's side (see emitter above) */
 } lt_scene_desc;
 
 /* Per-call trace arguments. */
@@ -143,7 +152,9 @@ typedef struct {
 /* Parameters: DEVICE float arrays owned by the caller. */
 typedef struct {
   const float* albedo;    /* [n_tex][tex_res][tex_res][3] */
-  const float* emitter_L; /* [3] radiance (quad) or intensity (point) */
+  const float* emitter_L; /* [3] radiance (quad, directional) or intensity (point), or
+                             [em_tex_res][em_tex_res][3] for a textured emitter (detached
+                             passes only: LT_ATTACHED rejects a textured emitter) */
   const float* heights;   /* [G][G] heightfield offsets, or NULL when hf_G < 2 */
   const float* guide_w;   /* [LT_GUIDE_NPARAMS] emission-guide weights, or NULL for
                              cosine-weighted emission (see the guide section) */

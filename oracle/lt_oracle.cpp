@@ -163,7 +163,7 @@ void onbv(const V3& n, V3& b1, V3& b2) {
 extern "C" {
 
 enum { ORA_ABSORBER = 0, ORA_LAMBERT = 1, ORA_DIELECTRIC = 2 };
-enum { ORA_EMIT_QUAD = 0, ORA_EMIT_POINT = 1 };
+enum { ORA_EMIT_QUAD = 0, ORA_EMIT_POINT = 1, ORA_EMIT_DIRECTIONAL = 2 };
 enum { ORA_F_ATTACHED = 1, ORA_F_SPLAT_SELECTED = 2 };
 enum { ORA_MODE_NAIVE = 0, ORA_MODE_RESLRB = 1 };
 
@@ -174,6 +174,7 @@ typedef struct {
   int32_t em_type; double em_o[3], em_e1[3], em_e2[3];
   double cam_pos[3], cam_target[3], cam_up[3], cam_fov_deg; int32_t width, height;
   int32_t hf_G; double hf_x0, hf_z0, hf_dx, hf_base; int32_t hf_mat;
+  int32_t em_tex_res;   // > 0: the emitter's radiance is an em_tex_res^2 RGB texture over its quad
 } ora_scene;
 
 typedef struct {
@@ -261,7 +262,7 @@ void scene_box(const ora_scene* sc, double c[3], double h[3]) {
   }
   const double* o = sc->em_o; const double* e1 = sc->em_e1; const double* e2 = sc->em_e2;
   add(o[0], o[1], o[2]);
-  if (sc->em_type == ORA_EMIT_QUAD) {
+  if (sc->em_type != ORA_EMIT_POINT) {
     add(o[0] + e1[0], o[1] + e1[1], o[2] + e1[2]);
     add(o[0] + e2[0], o[1] + e2[1], o[2] + e2[2]);
     add(o[0] + e1[0] + e2[0], o[1] + e1[1] + e2[1], o[2] + e1[2] + e2[2]);
@@ -413,6 +414,7 @@ struct Scene {
   const double* nmap;   // [G][G][2] normal-map slopes (Sx, Sz), or null: slopes from the heights
   bool attached;
   long slot_Le, slot_h, slot_n;
+  long n_le;            // emitter radiance parameters: 3, or 3 per texel of a textured emitter
   std::vector<D3> tv;   // [n_all][3] primal vertex positions
   // camera frame
   D3 cpos, f, r, u; double tan_half, aspect, K_area;
@@ -444,7 +446,8 @@ struct Scene {
     n_hf = sc->hf_G > 1 ? 2 * (sc->hf_G - 1) * (sc->hf_G - 1) : 0;
     n_all = n_static + n_hf;
     slot_Le = (long)sc->n_tex * sc->tex_res * sc->tex_res * 3;
-    slot_h = slot_Le + 3;
+    n_le = 3L * (sc->em_tex_res > 0 ? (long)sc->em_tex_res * sc->em_tex_res : 1);
+    slot_h = slot_Le + n_le;
     slot_n = slot_h + (sc->hf_G > 1 ? (long)sc->hf_G * sc->hf_G : 0);
     tv.resize((size_t)n_all * 3);
     for (int t = 0; t < n_static; ++t)
@@ -594,11 +597,31 @@ void trace_path(const Scene& S, const ora_args& A, uint32_t path, PathResult& ou
 
   // --- emission (vertex 0)
   Uniform4 u0 = rng4(A.seed, path, 0, 0);
+  // radiance of the emission point: the texel of its quad coordinates (u0
+  // along e1, u1 along e2; nearest texel) when the emitter is textured
+  long le = 0;
+  if (sc.em_tex_res > 0) {
+    const int R = sc.em_tex_res;
+    int tx = std::min((int)std::floor(u0.u[0] * R), R - 1), ty = std::min((int)std::floor(u0.u[1] * R), R - 1);
+    le = 3L * ((long)ty * R + tx);
+  }
   V Le[3];
-  for (int c = 0; c < 3; ++c) Le[c] = leaf(S.Le[c], S.slot_Le + c);
+  for (int c = 0; c < 3; ++c) Le[c] = leaf(S.Le[le + c], S.slot_Le + le + c);
   D3 x0, w0, n_off; bool has_off;
   V beta[3];
-  if (sc.em_type == ORA_EMIT_QUAD) {
+  if (sc.em_type == ORA_EMIT_DIRECTIONAL) {
+    // a collimated beam leaving the quad along its normal: irradiance Le
+    // across the quad, uniform position, beta_1 = Le * area
+    D3 o = {sc.em_o[0], sc.em_o[1], sc.em_o[2]};
+    D3 e1 = {sc.em_e1[0], sc.em_e1[1], sc.em_e1[2]}, e2 = {sc.em_e2[0], sc.em_e2[1], sc.em_e2[2]};
+    D3 cr = cross(e1, e2);
+    double area = std::sqrt(dot(cr, cr));
+    D3 ne = cr * (1.0 / area);
+    x0 = o + e1 * u0.u[0] + e2 * u0.u[1];
+    w0 = ne;
+    n_off = ne; has_off = true;
+    for (int c = 0; c < 3; ++c) beta[c] = Le[c] * V(area);
+  } else if (sc.em_type == ORA_EMIT_QUAD) {
     D3 o = {sc.em_o[0], sc.em_o[1], sc.em_o[2]};
     D3 e1 = {sc.em_e1[0], sc.em_e1[1], sc.em_e1[2]}, e2 = {sc.em_e2[0], sc.em_e2[1], sc.em_e2[2]};
     D3 cr = cross(e1, e2);
@@ -834,6 +857,7 @@ int ora_render(const ora_scene* sc, const ora_args* A, const double* albedo, con
                const double* heights, const double* nmap, double* image, double* slices, uint32_t* sig,
                int32_t* Rout, double* Wout, double* flux, uint32_t* info) {
   if (A->guide_w && sc->em_type != ORA_EMIT_QUAD) return -1;  // the guide steers area emission only
+  if (sc->em_tex_res > 0 && sc->em_type == ORA_EMIT_POINT) return -1;
   Scene S; S.init(sc, albedo, Le, heights, nmap, false);
   const int W = sc->width, H = sc->height, D = A->max_depth;
   const long npix = (long)W * H * 3;
@@ -891,12 +915,13 @@ int ora_gradient(const ora_scene* sc, const ora_args* A, int mode, const double*
                  const double* Le, const double* heights, const double* nmap, const double* dI, double* g_albedo,
                  double* g_Le, double* g_heights, double* g_nmap) {
   if (A->guide_w && sc->em_type != ORA_EMIT_QUAD) return -1;
+  if (sc->em_tex_res > 0 && sc->em_type == ORA_EMIT_POINT) return -1;
   Scene S; S.init(sc, albedo, Le, heights, nmap, (A->flags & ORA_F_ATTACHED) != 0);
   const int W = sc->width, H = sc->height;
   const int64_t n = A->path_list ? A->n_list : A->n_paths;
   const long n_alb = S.slot_Le, n_h = sc->hf_G > 1 ? (long)sc->hf_G * sc->hf_G : 0;
-  const long n_n = S.nmap ? 2 * n_h : 0;
-  const long nslot = n_alb + 3 + n_h + n_n;
+  const long n_n = S.nmap ? 2 * n_h : 0, n_le = S.n_le;
+  const long nslot = n_alb + n_le + n_h + n_n;
   int nt = A->n_threads > 0 ? A->n_threads : omp_get_max_threads();
   std::vector<std::vector<double>> gr(nt, std::vector<double>(nslot, 0.0));
 #pragma omp parallel num_threads(nt)
@@ -941,9 +966,9 @@ int ora_gradient(const ora_scene* sc, const ora_args* A, int mode, const double*
   for (long q = 0; q < nslot; ++q) {
     double s = 0; for (int t = 0; t < nt; ++t) s += gr[t][q];
     if (q < n_alb) { if (g_albedo) g_albedo[q] += s; }
-    else if (q < n_alb + 3) { if (g_Le) g_Le[q - n_alb] += s; }
-    else if (q < n_alb + 3 + n_h) { if (g_heights) g_heights[q - n_alb - 3] += s; }
-    else if (g_nmap) g_nmap[q - n_alb - 3 - n_h] += s;
+    else if (q < n_alb + n_le) { if (g_Le) g_Le[q - n_alb] += s; }
+    else if (q < n_alb + n_le + n_h) { if (g_heights) g_heights[q - n_alb - n_le] += s; }
+    else if (g_nmap) g_nmap[q - n_alb - n_le - n_h] += s;
   }
   return 0;
 }

@@ -57,6 +57,7 @@ class _Scene(C.Structure):
         ("cam_fov_deg", C.c_double), ("width", C.c_int32), ("height", C.c_int32),
         ("hf_G", C.c_int32), ("hf_x0", C.c_double), ("hf_z0", C.c_double), ("hf_dx", C.c_double),
         ("hf_base", C.c_double), ("hf_mat", C.c_int32),
+        ("em_tex_res", C.c_int32),
     ]
 
 
@@ -132,6 +133,7 @@ def _scene(sc, keep):
     s.n_tex, s.tex_res = int(sc["n_tex"]), int(sc["tex_res"])
     em = sc["emitter"]
     s.em_type = int(em["type"])
+    s.em_tex_res = int(em.get("tex_res", 0))
     for k in range(3):
         s.em_o[k], s.em_e1[k], s.em_e2[k] = em["o"][k], em["e1"][k], em["e2"][k]
     cam = sc["camera"]
@@ -226,7 +228,7 @@ def gradient(sc, seed, n_paths, depth, dI, mode=MODE_NAIVE, albedo=None, Le=None
     alb, le, h, nm = _params(sc, albedo, Le, heights, keep, normal_map)
     dI = keep.f64(dI)
     g_alb = np.zeros_like(alb)
-    g_le = np.zeros(3)
+    g_le = np.zeros_like(le)
     g_h = np.zeros_like(h) if h is not None else None
     g_n = np.zeros_like(nm) if nm is not None else None
     rc = lib.ora_gradient(C.byref(s), C.byref(a), int(mode), _p(alb), _p(le), _p(h), _p(nm), _p(dI),

@@ -321,6 +321,10 @@ lt_status check_args(lt_ctx* c, const lt_trace_args* a, const lt_params* p) {
   if (p->normal_map && (c->dsc.hf_G < 2 || !p->heights))
     return c->fail(LT_ERR_ARG, "a normal map needs a heightfield and params->heights%s");
   if (p->guide_w && c->dsc.em_type != LT_EMIT_QUAD) return c->fail(LT_ERR_UNSUPPORTED, "the emission guide needs an area emitter%s");
+  if (c->dsc.em_tex_res > 0 && (a->flags & LT_ATTACHED))
+    return c->fail(LT_ERR_UNSUPPORTED, "a textured emitter is supported by detached passes only%s");
+  if (c->dsc.em_tex_res > 0 && p->guide_w)
+    return c->fail(LT_ERR_UNSUPPORTED, "the emission guide takes an untextured emitter%s");
   if (p->guide_w && !c->guide_ok) return c->fail(LT_ERR_UNSUPPORTED, "guide kernels could not get their LDS%s");
   return LT_OK;
 }
@@ -563,7 +567,10 @@ lt_status lt_scene_upload(lt_ctx* c, const lt_scene_desc* s) {
     return c->fail(LT_ERR_ARG, "bad texture shape%s");
   if (s->width < 1 || s->height < 1 || s->width > 16384 || s->height > 16384) return c->fail(LT_ERR_ARG, "bad film size%s");
   if (!(s->cam_fov_deg > 0.0 && s->cam_fov_deg < 180.0)) return c->fail(LT_ERR_ARG, "bad field of view%s");
-  if (s->em_type != LT_EMIT_QUAD && s->em_type != LT_EMIT_POINT) return c->fail(LT_ERR_ARG, "bad emitter type%s");
+  if (s->em_type != LT_EMIT_QUAD && s->em_type != LT_EMIT_POINT && s->em_type != LT_EMIT_DIRECTIONAL)
+    return c->fail(LT_ERR_ARG, "bad emitter type%s");
+  if (s->em_tex_res < 0 || s->em_tex_res > 4096 || (s->em_tex_res > 0 && s->em_type == LT_EMIT_POINT))
+    return c->fail(LT_ERR_ARG, "bad emitter texture size (0, or 1..4096 on a quad or directional emitter)%s");
   if (s->hf_G == 1 || s->hf_G < 0 || s->hf_G > 4096) return c->fail(LT_ERR_ARG, "bad heightfield size%s");
   for (int m = 0; m < s->n_mats; ++m) {
     if (s->mat_type[m] < 0 || s->mat_type[m] > 2) return c->fail(LT_ERR_ARG, "bad material type%s");
@@ -685,6 +692,7 @@ lt_status lt_scene_upload(lt_ctx* c, const lt_scene_desc* s) {
   d.hf_mat = s->hf_mat;
   d.n_tex = s->n_tex; d.tex_res = s->tex_res;
   d.em_type = s->em_type;
+  d.em_tex_res = s->em_tex_res;
   double cr[3] = {s->em_e1[1] * s->em_e2[2] - s->em_e1[2] * s->em_e2[1],
                   s->em_e1[2] * s->em_e2[0] - s->em_e1[0] * s->em_e2[2],
                   s->em_e1[0] * s->em_e2[1] - s->em_e1[1] * s->em_e2[0]};
@@ -694,7 +702,7 @@ lt_status lt_scene_upload(lt_ctx* c, const lt_scene_desc* s) {
     d.em_n[a] = area > 0 ? (float)(cr[a] / area) : 0.f;
   }
   d.em_area = (float)area;
-  if (s->em_type == LT_EMIT_QUAD && !(area > 0)) { c->free_scene(); return c->fail(LT_ERR_ARG, "degenerate quad emitter%s"); }
+  if (s->em_type != LT_EMIT_POINT && !(area > 0)) { c->free_scene(); return c->fail(LT_ERR_ARG, "degenerate quad emitter%s"); }
   {  // guide normalisation box: static triangles, heightfield footprint, emitter corners
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     auto add = [&](double x, double y, double z) {
@@ -709,7 +717,7 @@ lt_status lt_scene_upload(lt_ctx* c, const lt_scene_desc* s) {
     }
     const double *o = s->em_o, *e1 = s->em_e1, *e2 = s->em_e2;
     add(o[0], o[1], o[2]);
-    if (s->em_type == LT_EMIT_QUAD) {
+    if (s->em_type != LT_EMIT_POINT) {
       add(o[0] + e1[0], o[1] + e1[1], o[2] + e1[2]);
       add(o[0] + e2[0], o[1] + e2[1], o[2] + e2[2]);
       add(o[0] + e1[0] + e2[0], o[1] + e1[1] + e2[1], o[2] + e1[2] + e2[2]);
@@ -842,6 +850,7 @@ static lt_status backward_common(lt_ctx* c, const lt_trace_args* a, const lt_par
   A.dI = d_image;
   A.g_albedo = g->albedo;
   A.g_Le_acc = w.acc;
+  A.g_le_tex = c->dsc.em_tex_res > 0 ? g->emitter_L : nullptr;
   A.g_heights = g->heights;
   A.g_nmap = (a->flags & LT_ATTACHED) ? g->normal_map : nullptr;
   if ((st = c->hip(launch_fill_f64(w.acc, 3, 0.0, c->stream), "acc clear")) != LT_OK) return st;
@@ -1235,6 +1244,7 @@ BatchPlan batch_plan(lt_batch* b, const lt_instance* inst, int n, int64_t path_d
     B.g_heights = I.grads.heights;
     B.g_nmap = (I.args.flags & LT_ATTACHED) ? I.grads.normal_map : nullptr;
     B.g_Le_acc = b->d_acc + 4 * i;
+    B.g_le_tex = c->dsc.em_tex_res > 0 ? I.grads.emitter_L : nullptr;
     B.counter = b->d_cnt + n + i;
     // by the caller's path count, so the autotuner's shortened steps keep the plan's shape
     ((a.flags & LT_ATTACHED) ? (I.args.n_paths >= kSoloPaths ? P.solo : P.att) : P.det).push_back(i);

@@ -129,7 +129,8 @@ struct DevScene {
   int32_t n_nodes, n_tris, n_static;
   int32_t hf_G; float hf_x0, hf_z0, hf_dx, hf_base; int32_t hf_mat;
   int32_t n_tex, tex_res;
-  int32_t em_type;
+  int32_t em_type;          // 0 area quad, 1 point, 2 directional quad
+  int32_t em_tex_res;       // > 0: L_e is an em_tex_res^2 RGB texture over the quad
   float em_o[3], em_e1[3], em_e2[3], em_n[3], em_area;
   float cpos[3], cf[3], cr[3], cu[3];
   float tan_half, aspect, film_area;

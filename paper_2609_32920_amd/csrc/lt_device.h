@@ -227,6 +227,13 @@ struct Ray { f3 x, w, offn; bool off; };
 __device__ __forceinline__ float emit(const DevScene& sc, uint64_t seed, uint32_t path, Ray& r) {
   LT_COUNT(7, 1);
   u4f u = rng4(seed, path, 0u, 0u);
+  if (sc.em_type == 2) {  // directional: a collimated beam along the quad's normal
+    f3 o = ld3(sc.em_o), e1 = ld3(sc.em_e1), e2 = ld3(sc.em_e2), ne = ld3(sc.em_n);
+    r.x = o + e1 * u.u0 + e2 * u.u1;
+    r.w = ne;
+    r.offn = ne; r.off = true;
+    return sc.em_area;
+  }
   if (sc.em_type == 0) {
     f3 o = ld3(sc.em_o), e1 = ld3(sc.em_e1), e2 = ld3(sc.em_e2), ne = ld3(sc.em_n);
     r.x = o + e1 * u.u0 + e2 * u.u1;

@@ -146,10 +146,19 @@ __device__ __forceinline__ void keep_finite(const PassArgs& A, bool& has, f3 v) 
   if (has && !(isfinite(v.x) && isfinite(v.y) && isfinite(v.z))) { has = false; count_nonfinite(A); }
 }
 // emitter-gradient accumulation of one path, (a0, a1, a2) in place of zeros
-// when any is non-finite
+// when any is non-finite: into the lane's FP64 sums (one radiance), or onto
+// the path's texel of a textured emitter (texel >= 0)
 __device__ __forceinline__ void add_le(const PassArgs& A, double& g0, double& g1, double& g2, double a0, double a1,
-                                       double a2) {
+                                       double a2, int texel = -1) {
   if (!(isfinite(a0) && isfinite(a1) && isfinite(a2))) { count_nonfinite(A); return; }
+  if (texel >= 0) {
+    if (!A.g_le_tex) return;
+    float* d = A.g_le_tex + 3 * texel;
+    if (a0 != 0.0) atomicAdd(d + 0, (float)a0);
+    if (a1 != 0.0) atomicAdd(d + 1, (float)a1);
+    if (a2 != 0.0) atomicAdd(d + 2, (float)a2);
+    return;
+  }
   g0 += a0; g1 += a1; g2 += a2;
 }
 
@@ -252,6 +261,22 @@ __device__ __forceinline__ D3R recip_le(f3 Le) {
   return {Le.x > 0.f ? 1.0 / Le.x : 0.0, Le.y > 0.f ? 1.0 / Le.y : 0.0, Le.z > 0.f ? 1.0 / Le.z : 0.0};
 }
 
+// Emitter radiance of a path.  One radiance: Le, iLe as set once per kernel,
+// texel -1.  A textured emitter: the texel of the path's emission point
+// (quad coordinates u0 along e1, u1 along e2, nearest texel; computed on the
+// 24-bit integers of the uniforms, so exactly floor(u R)), its radiance and
+// reciprocal.
+__device__ __forceinline__ void path_emitter(const PassArgs& A, uint32_t path, f3& Le, D3R& iLe, int& texel) {
+  const int R = A.sc.em_tex_res;
+  if (R <= 0) return;
+  u4f u = rng4(A.seed, path, 0u, 0u);
+  const uint64_t k0 = (uint64_t)(u.u0 * 16777216.0f), k1 = (uint64_t)(u.u1 * 16777216.0f);
+  const int tx = (int)((k0 * (uint64_t)R) >> 24), ty = (int)((k1 * (uint64_t)R) >> 24);
+  texel = ty * R + tx;
+  Le = ld3(A.Le + 3 * texel);
+  iLe = recip_le(Le);
+}
+
 // Vertex 0 of a path.  With a guide the emitted direction and its density q
 // come from the per-path record of the guide pass (same position draw);
 // beta_1 = L_e * A cos / q, the density held fixed in every derivative.
@@ -292,7 +317,9 @@ __device__ __forceinline__ void trace_run(const PassArgs& A, int* lds) {
   float fac = 0.f, Sl = 0.f;  // emission factor, path contribution sum_i lum(C_i)
   int klast = 0;              // SPL: last connection depth and validity bits
   uint64_t vmask = 0ull;
-  const f3 Le = ld3(A.Le);
+  f3 Le = ld3(A.Le);
+  D3R iLe = {0.0, 0.0, 0.0};
+  int etex = -1;
   while (true) {
     refill(A, alive, exhausted, path, [&](uint32_t p) {
       if (SPL) { SplatHdr z{}; A.spl_hdr[p] = z; }
@@ -308,6 +335,7 @@ __device__ __forceinline__ void trace_run(const PassArgs& A, int* lds) {
     if (alive) {
       if (j == 0) {  // new path: vertex 0 on the emitter
         fac = emit_path(A, path, r);
+        path_emitter(A, path, Le, iLe, etex);
         beta = Le * fac;
         j = 1; nrec = 0; sig = 0x811C9DC5u;
         Om = 0.f; omR = 0.f; R = 0; Sl = 0.f;
@@ -433,13 +461,16 @@ __global__ void __launch_bounds__(256) k_naive_bwd(PassArgs A) {
       keep_finite(A, has, gr);
       scatter_albedo(A, ga, has, texel, gr);
     }
+    f3 Lp = ld3(A.Le);
     if (live) {
-      add_le(A, gl0, gl1, gl2, (double)bb.x * fac, (double)bb.y * fac, (double)bb.z * fac);
+      D3R iLp = {0.0, 0.0, 0.0};
+      int etex = -1;
+      path_emitter(A, (uint32_t)path, Lp, iLp, etex);
+      add_le(A, gl0, gl1, gl2, (double)bb.x * fac, (double)bb.y * fac, (double)bb.z * fac, etex);
     }
     // the path's adjoint-weighted contribution |delta_total| = sum_c |L_e,c f bb_c|
     if (A.contrib && path < N)
-      A.contrib[path] = live ? fabsf(A.Le[0] * fac * bb.x) + fabsf(A.Le[1] * fac * bb.y) + fabsf(A.Le[2] * fac * bb.z)
-                             : 0.f;
+      A.contrib[path] = live ? fabsf(Lp.x * fac * bb.x) + fabsf(Lp.y * fac * bb.y) + fabsf(Lp.z * fac * bb.z) : 0.f;
   }
   flush_le(A, gl0, gl1, gl2);
   agrad_end(A, ga);
@@ -460,8 +491,9 @@ __global__ void __launch_bounds__(1024) k_reslrb_bwd(PassArgs A) {
   int j = 0, R = 0;
   Ray r;
   f3 w = {0.f, 0.f, 0.f};
-  const f3 Le = ld3(A.Le);
-  const D3R iLe = recip_le(Le);
+  f3 Le = ld3(A.Le);
+  D3R iLe = recip_le(Le);
+  int etex = -1;
   double gl0 = 0.0, gl1 = 0.0, gl2 = 0.0;
   while (true) {
     refill(A, alive, exhausted, path, [&](uint32_t) {});
@@ -477,7 +509,8 @@ __global__ void __launch_bounds__(1024) k_reslrb_bwd(PassArgs A) {
         R = min(rec.R, A.D);
         f3 Lb = gather(A.sc, A.dI, rec.ux, rec.uy);
         w = mul(Lb, mk(rec.S[0], rec.S[1], rec.S[2]));
-        add_le(A, gl0, gl1, gl2, (double)w.x * iLe.x, (double)w.y * iLe.y, (double)w.z * iLe.z);
+        path_emitter(A, path, Le, iLe, etex);
+        add_le(A, gl0, gl1, gl2, (double)w.x * iLe.x, (double)w.y * iLe.y, (double)w.z * iLe.z, etex);
         emit_path(A, path, r);
         j = 1;
       }
@@ -522,8 +555,9 @@ __device__ __forceinline__ void lrb3_run(const PassArgs& A, int* lds) {
   Ray r;
   f3 beta = {0.f, 0.f, 0.f};
   double d0 = 0.0, d1 = 0.0, d2 = 0.0;  // delta_total, then delta_rem
-  const f3 Le = ld3(A.Le);
-  const D3R iLe = recip_le(Le);
+  f3 Le = ld3(A.Le);
+  D3R iLe = recip_le(Le);
+  int etex = -1;
   double gl0 = 0.0, gl1 = 0.0, gl2 = 0.0;
   while (true) {
     refill(A, alive, exhausted, path, [&](uint32_t p) { if (A.contrib) A.contrib[p] = 0.f; });
@@ -534,6 +568,7 @@ __device__ __forceinline__ void lrb3_run(const PassArgs& A, int* lds) {
     if (alive) {
       if (j == 0) {
         float f = emit_path(A, path, r);
+        path_emitter(A, path, Le, iLe, etex);
         beta = Le * f;
         j = 1;
         if (phase == 2) { d0 = d1 = d2 = 0.0; vmask = 0ull; klast = 0; }
@@ -566,7 +601,7 @@ __device__ __forceinline__ void lrb3_run(const PassArgs& A, int* lds) {
       if (ev.cont) {
         ++j;
       } else if (phase == 2 && klast > 0 && (d0 != 0.0 || d1 != 0.0 || d2 != 0.0)) {  // consuming replay
-        add_le(A, gl0, gl1, gl2, d0 * iLe.x, d1 * iLe.y, d2 * iLe.z);
+        add_le(A, gl0, gl1, gl2, d0 * iLe.x, d1 * iLe.y, d2 * iLe.z, etex);
         // the path's adjoint-weighted contribution |delta_total|
         if (A.contrib) A.contrib[path] = (float)(fabs(d0) + fabs(d1) + fabs(d2));
         phase = 3; j = 0;
@@ -607,8 +642,9 @@ __device__ __forceinline__ void lrb2_run(const PassArgs& A, int* lds) {
   uint64_t vmask = 0ull;
   Ray r;
   double d0 = 0.0, d1 = 0.0, d2 = 0.0;
-  const f3 Le = ld3(A.Le);
-  const D3R iLe = recip_le(Le);
+  f3 Le = ld3(A.Le);
+  D3R iLe = recip_le(Le);
+  int etex = -1;
   double gl0 = 0.0, gl1 = 0.0, gl2 = 0.0;
   while (true) {
     refill(A, alive, exhausted, path, [&](uint32_t p) { if (A.contrib) A.contrib[p] = 0.f; });
@@ -630,7 +666,8 @@ __device__ __forceinline__ void lrb2_run(const PassArgs& A, int* lds) {
         d0 += (double)Lb.x * rec.C[0]; d1 += (double)Lb.y * rec.C[1]; d2 += (double)Lb.z * rec.C[2];
       }
       if (klast > 0 && (d0 != 0.0 || d1 != 0.0 || d2 != 0.0)) {
-        add_le(A, gl0, gl1, gl2, d0 * iLe.x, d1 * iLe.y, d2 * iLe.z);
+        path_emitter(A, path, Le, iLe, etex);
+        add_le(A, gl0, gl1, gl2, d0 * iLe.x, d1 * iLe.y, d2 * iLe.z, etex);
         if (A.contrib) A.contrib[path] = (float)(fabs(d0) + fabs(d1) + fabs(d2));
         emit_path(A, path, r);
         j = 1;
@@ -710,8 +747,9 @@ __device__ __forceinline__ void lrb3_p2_run(const PassArgs& A, int* lds) {
   Ray r;
   f3 beta = {0.f, 0.f, 0.f};
   double d0 = 0.0, d1 = 0.0, d2 = 0.0;
-  const f3 Le = ld3(A.Le);
-  const D3R iLe = recip_le(Le);
+  f3 Le = ld3(A.Le);
+  D3R iLe = recip_le(Le);
+  int etex = -1;
   double gl0 = 0.0, gl1 = 0.0, gl2 = 0.0;
   while (true) {
     refill(A, alive, exhausted, path, [&](uint32_t p) { if (A.contrib) A.contrib[p] = 0.f; });
@@ -719,7 +757,9 @@ __device__ __forceinline__ void lrb3_p2_run(const PassArgs& A, int* lds) {
     bool put = false;
     if (alive) {
       if (j == 0) {
-        beta = Le * emit_path(A, path, r);
+        const float f = emit_path(A, path, r);
+        path_emitter(A, path, Le, iLe, etex);
+        beta = Le * f;
         j = 1;
         d0 = d1 = d2 = 0.0; vmask = 0ull; klast = 0;
       }
@@ -737,7 +777,7 @@ __device__ __forceinline__ void lrb3_p2_run(const PassArgs& A, int* lds) {
         ++j;
       } else {
         put = klast > 0 && (d0 != 0.0 || d1 != 0.0 || d2 != 0.0);
-        if (put) add_le(A, gl0, gl1, gl2, d0 * iLe.x, d1 * iLe.y, d2 * iLe.z);
+        if (put) add_le(A, gl0, gl1, gl2, d0 * iLe.x, d1 * iLe.y, d2 * iLe.z, etex);
         // the path's adjoint-weighted contribution |delta_total|
         if (A.contrib) A.contrib[path] = put ? (float)(fabs(d0) + fabs(d1) + fabs(d2)) : 0.f;
         alive = false; j = 0;
@@ -769,7 +809,9 @@ __device__ __forceinline__ void lrb3_p3_run(const PassArgs& A, int* lds) {
   Ray r;
   f3 beta = {0.f, 0.f, 0.f};
   double d0 = 0.0, d1 = 0.0, d2 = 0.0;
-  const f3 Le = ld3(A.Le);
+  f3 Le = ld3(A.Le);
+  D3R iLe = {0.0, 0.0, 0.0};
+  int etex = -1;
   while (true) {
     fetch_items(A.hand_ticket, n_items, alive, exhausted, item);
     if (__ballot(alive) == 0ull) break;
@@ -780,7 +822,9 @@ __device__ __forceinline__ void lrb3_p3_run(const PassArgs& A, int* lds) {
       if (j == 0) {
         const Lrb3Hand h = A.hand[item];
         path = h.path; klast = h.klast; vmask = h.vmask; d0 = h.d[0]; d1 = h.d[1]; d2 = h.d[2];
-        beta = Le * emit_path(A, path, r);
+        const float f = emit_path(A, path, r);
+        path_emitter(A, path, Le, iLe, etex);
+        beta = Le * f;
         j = 1;
       }
       Event ev = bounce(A, path, j, r, ((vmask >> (j - 1)) & 1ull) ? 2 : 0, stk, ss);

@@ -39,6 +39,7 @@ struct PassArgs {
   const ResRec* res_in;
   float* g_albedo;
   double* g_Le_acc;
+  float* g_le_tex;            // textured emitter: the caller's [R][R][3] gradient, or null
   float* g_heights;
   float* g_nmap;              // normal-map gradients [G][G][2], or null
   unsigned long long* stats;  // [0] guard triggers, [1] non-finite drops

@@ -49,7 +49,7 @@ class SceneDesc(C.Structure):
         ("cam_pos", C.c_double * 3), ("cam_target", C.c_double * 3), ("cam_up", C.c_double * 3),
         ("cam_fov_deg", C.c_double), ("width", C.c_int32), ("height", C.c_int32),
         ("hf_G", C.c_int32), ("hf_x0", C.c_double), ("hf_z0", C.c_double), ("hf_dx", C.c_double),
-        ("hf_base", C.c_double), ("hf_mat", C.c_int32),
+        ("hf_base", C.c_double), ("hf_mat", C.c_int32), ("em_tex_res", C.c_int32),
     ]
 
 
@@ -241,6 +241,7 @@ class Context:
         d.n_tex, d.tex_res = int(sc["n_tex"]), int(sc["tex_res"])
         em = sc["emitter"]
         d.em_type = int(em["type"])
+        d.em_tex_res = int(em.get("tex_res", 0))
         cam = sc["camera"]
         for k in range(3):
             d.em_o[k], d.em_e1[k], d.em_e2[k] = float(em["o"][k]), float(em["e1"][k]), float(em["e2"][k])
@@ -274,6 +275,8 @@ class Context:
             raise LTError(LT_ERR_STATE, "no scene uploaded")
         hf = sc.get("hf")
         G = int(hf["G"]) if hf is not None else 0
+        R = int(sc["emitter"].get("tex_res", 0))
+        self.n_le = 3 * (R * R if R > 0 else 1)
         return int(sc["n_tex"]) * int(sc["tex_res"]) ** 2 * 3, G * G
 
     def _check(self, t, name, numel):
@@ -296,7 +299,7 @@ class Context:
     def params(self, albedo, Le, heights=None, guide_w=None, normal_map=None):
         n_alb, n_h = self._sizes()
         self._check(albedo, "albedo", n_alb)
-        self._check(Le, "Le", 3)
+        self._check(Le, "Le", self.n_le)
         if heights is not None:
             self._check(heights, "heights", n_h)
         self._check(guide_w, "guide_w", GUIDE_NPARAMS)
@@ -324,7 +327,7 @@ class Context:
     def _grads(self, g_albedo, g_Le, g_heights, g_normal_map=None):
         n_alb, n_h = self._sizes()
         self._check(g_albedo, "g_albedo", n_alb)
-        self._check(g_Le, "g_Le", 3)
+        self._check(g_Le, "g_Le", self.n_le)
         self._check(g_heights, "g_heights", n_h)
         self._check(g_normal_map, "g_normal_map", 2 * n_h)
         return Grads(None if g_albedo is None else g_albedo.data_ptr(),

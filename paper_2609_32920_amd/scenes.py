@@ -14,7 +14,11 @@ Scene dictionary layout (all arrays numpy, float64 unless noted):
   mat_tex  [M]      int32 texture index of a Lambertian material (-1 otherwise)
   mat_ior  [M]      refractive index of a dielectric material
   n_tex, tex_res    albedo textures are [n_tex, tex_res, tex_res, 3]
-  emitter  dict(type=EMIT_QUAD|EMIT_POINT, o, e1, e2)  (point: o = position)
+  emitter  dict(type=EMIT_QUAD|EMIT_POINT|EMIT_DIRECTIONAL, o, e1, e2[, tex_res])
+           (point: o = position; directional: a collimated beam leaving the
+           quad along normalize(e1 x e2); tex_res > 0: the radiance Le is a
+           tex_res^2 RGB texture over the quad, texel (floor(u0 R), floor(u1 R))
+           of the quad coordinates u0 along e1, u1 along e2)
   camera   dict(pos, target, up, fov_deg, width, height)
   hf       dict(G, x0, z0, dx, base, mat) or None: heightfield top surface
            with vertex (i, j) at (x0 + i*dx, base + h[j*G+i], z0 + j*dx)
@@ -34,6 +38,7 @@ MAT_DIELECTRIC = 2
 
 EMIT_QUAD = 0
 EMIT_POINT = 1
+EMIT_DIRECTIONAL = 2
 
 SCENE_SEED = 2609
 TARGET_SEED = 0x7A6
@@ -209,6 +214,64 @@ def glass_panel_scene(G=16, width=64, height=64, seed=SCENE_SEED, target_seed=TA
                    b * np.sin(math.pi * kx * (X + 0.5)) * np.cos(math.pi * kz * (Z + 0.5))], axis=-1)
     sc.update(name=f"panel{G}_{width}x{height}", heights=np.zeros(G * G), heights_target=None,
               normal_map=nm.reshape(-1).copy(), normal_map_target=nt.reshape(-1).copy())
+    return sc
+
+
+def directional_plane_scene(width=16, height=16, rho=0.6, tex_res=4, seed=SCENE_SEED, cam_h=2.0, fov_deg=60.0):
+    """A textured directional emitter over a Lambertian plane, seen by a
+    pinhole camera looking straight down (closed-form pin only).
+
+    Plane y = 0, x,z in [-4, 4], albedo rho.  The emitter: a 0.9 x 0.7 quad
+    at y = 1 from (-0.5, 1, -0.3), e1 along +x, e2 along +z, emitting a
+    collimated beam straight down with a tex_res^2 RGB irradiance texture
+    U(0.5, 1.5).  The emitter is not geometry (nothing occludes the camera).
+    Camera at (0, cam_h, 0), up +z.  The beam lights the quad's footprint at
+    normal incidence, so the expected image is a sum over texels of
+    rho E_t / pi times the tent-filtered film area of the texel's footprint.
+    """
+    b = _Builder()
+    b.quad((-4, 0, -4), (0, 0, 8), (8, 0, 0), 0)   # normal +y
+    tri_v, tri_uv, tri_mat = b.arrays()
+    rng = np.random.default_rng(seed + 29)
+    Le = rng.uniform(0.5, 1.5, size=(tex_res, tex_res, 3))
+    return dict(
+        name="directional_plane",
+        tri_v=tri_v, tri_uv=tri_uv, tri_mat=tri_mat,
+        mat_type=np.array([MAT_LAMBERT], np.int32), mat_tex=np.array([0], np.int32),
+        mat_ior=np.array([1.0]),
+        n_tex=1, tex_res=1,
+        emitter=dict(type=EMIT_DIRECTIONAL, o=np.array([-0.5, 1.0, -0.3]), e1=np.array([0.9, 0.0, 0.0]),
+                     e2=np.array([0.0, 0.0, 0.7]), tex_res=tex_res),
+        camera=dict(pos=np.array([0.0, cam_h, 0.0]), target=np.array([0.0, 0.0, 0.0]),
+                    up=np.array([0.0, 0.0, 1.0]), fov_deg=fov_deg, width=width, height=height),
+        hf=None,
+        albedo=np.full((1, 1, 1, 3), rho), Le=Le.reshape(-1).copy(), heights=None,
+        albedo_target=None, heights_target=None,
+    )
+
+
+def tumbler_scene(G=16, width=64, height=64, tex_res=8, seed=SCENE_SEED, target_seed=TARGET_SEED, ior=1.5):
+    """Glass under a textured directional emitter (the Tumbler validation of
+    the paper: differentiate the radiance texture of a directional emitter).
+
+    The caustic scene's receiver and glass heightfield slab (heights
+    N(0, 0.002) inside a zero ring), lit by a collimated beam from a 0.6 x 0.6
+    quad at y = 1 pointing down, whose irradiance is a tex_res^2 RGB texture
+    U(10, 30); the target texture is the same plus a seeded smooth pattern.
+    Detached: the parameters are the emitter texture and the receiver albedo.
+    """
+    sc = caustic_scene(G=G, width=width, height=height, seed=seed, target_seed=target_seed, ior=ior)
+    # drop the small area emitter's absorber quad: the beam source is not geometry
+    sc["tri_v"], sc["tri_uv"], sc["tri_mat"] = sc["tri_v"][:-2], sc["tri_uv"][:-2], sc["tri_mat"][:-2]
+    rng = np.random.default_rng(seed + 31)
+    Le = rng.uniform(10.0, 30.0, size=(tex_res, tex_res, 3))
+    xs = np.linspace(0.0, 1.0, tex_res)
+    X, Z = np.meshgrid(xs, xs, indexing="xy")
+    bump = 5.0 * np.sin(2 * math.pi * X)[..., None] * np.cos(math.pi * Z)[..., None] * np.array([1.0, 0.8, 0.6])
+    sc.update(name=f"tumbler{G}_{width}x{height}",
+              emitter=dict(type=EMIT_DIRECTIONAL, o=np.array([-0.3, 1.0, -0.3]), e1=np.array([0.6, 0.0, 0.0]),
+                           e2=np.array([0.0, 0.0, 0.6]), tex_res=tex_res),
+              Le=Le.reshape(-1).copy(), Le_target=(Le + bump).reshape(-1).copy())
     return sc
 
 
