@@ -182,6 +182,8 @@ typedef struct {
   const uint32_t* path_list; int64_t n_list;   // NULL: all paths [0, n_paths)
   const double* guide_w;   // emission-guide weights [11433] or NULL (cosine emission)
   int32_t guide_bf16;      // 1: round MLP operands to bfloat16 where the GPU does
+  int32_t guide_diffuse;   // 1 (with guide_w): Lambertian vertices scatter from the
+                           // guide table of their texel (see GuideTable)
 } ora_args;
 
 }  // extern "C"
@@ -419,6 +421,9 @@ struct Scene {
   // camera frame
   D3 cpos, f, r, u; double tan_half, aspect, K_area;
   double gc[3], gh[3];  // guide position normalisation (scene box centre, half extent)
+  // guide table of the Lambertian texels (built by build_guide_table)
+  std::vector<Mixture> gtab;
+  std::vector<uint8_t> gok;
 
   int hf_corner(int tri, int k, int& gi, int& gj) const {
     // heightfield triangle -> grid corner (gi, gj); returns 1 if on heightfield
@@ -526,6 +531,70 @@ struct Scene {
   }
 };
 
+// Centre of every albedo texel on the scene surface, for the diffuse guide
+// table.  Texel (t, tx, ty) has chart centre ((tx + 1/2)/R, (ty + 1/2)/R);
+// its position and unit normal come from the lowest-index static triangle
+// whose material is Lambertian with texture t and whose chart triangle
+// contains the centre (barycentrics >= -1e-9): the barycentric blend of its
+// corners and normalize((v1 - v0) x (v2 - v0)).  ok[texel] = 0 when no
+// triangle covers the centre.  x, n: [n_tex R R][3].
+void texel_centres(const ora_scene* sc, std::vector<double>& x, std::vector<double>& n, std::vector<uint8_t>& ok) {
+  const int R = sc->tex_res;
+  const long T = (long)sc->n_tex * R * R;
+  x.assign(T * 3, 0.0); n.assign(T * 3, 0.0); ok.assign(T, 0);
+  for (int t = 0; t < sc->n_tris; ++t) {
+    int mat = sc->tri_mat[t];
+    if (sc->mat_type[mat] != ORA_LAMBERT) continue;
+    int tex = sc->mat_tex[mat];
+    const double* uv = sc->tri_uv + (size_t)t * 6;
+    const double* v = sc->tri_v + (size_t)t * 9;
+    double a0 = uv[2] - uv[0], a1 = uv[3] - uv[1], b0 = uv[4] - uv[0], b1 = uv[5] - uv[1];
+    double det = a0 * b1 - a1 * b0;
+    if (std::fabs(det) < 1e-300) continue;
+    D3 p0 = {v[0], v[1], v[2]}, p1 = {v[3], v[4], v[5]}, p2 = {v[6], v[7], v[8]};
+    D3 nrm = normalize(cross(p1 - p0, p2 - p0));
+    for (int ty = 0; ty < R; ++ty)
+      for (int tx = 0; tx < R; ++tx) {
+        long k = ((long)tex * R + ty) * R + tx;
+        if (ok[k]) continue;
+        double cx = (tx + 0.5) / R - uv[0], cy = (ty + 0.5) / R - uv[1];
+        double l1 = (cx * b1 - cy * b0) / det, l2 = (a0 * cy - a1 * cx) / det, l0 = 1.0 - l1 - l2;
+        if (l0 < -1e-9 || l1 < -1e-9 || l2 < -1e-9) continue;
+        D3 c = p0 * l0 + p1 * l1 + p2 * l2;
+        x[k * 3] = c.x; x[k * 3 + 1] = c.y; x[k * 3 + 2] = c.z;
+        n[k * 3] = nrm.x; n[k * 3 + 1] = nrm.y; n[k * 3 + 2] = nrm.z;
+        ok[k] = 1;
+      }
+  }
+}
+
+// Guide table (an extension, like the emission guide): the mixture of the
+// network at each texel centre, entry 2 texel + side with the network's
+// normal input +n (side 0) or -n (side 1).  A Lambertian vertex that the
+// ray reaches against its triangle's geometric normal (cos_in < 0) uses
+// side 0, else side 1; a vertex of an uncovered texel samples the cosine
+// density.  Raw outputs of every entry go to `raw` when given.
+void build_guide_table(Scene& S, const ora_args& A, std::vector<double>* raw) {
+  std::vector<double> x, n; std::vector<uint8_t> ok;
+  texel_centres(S.s, x, n, ok);
+  const long T = (long)ok.size();
+  S.gtab.assign(2 * T, Mixture{});
+  S.gok.assign(2 * T, 0);
+  if (raw) raw->assign(2 * T * kGOut, 0.0);
+  for (long k = 0; k < T; ++k) {
+    if (!ok[k]) continue;
+    for (int side = 0; side < 2; ++side) {
+      double sg = side ? -1.0 : 1.0;
+      D3 xc = {x[k * 3], x[k * 3 + 1], x[k * 3 + 2]}, nc = {sg * n[k * 3], sg * n[k * 3 + 1], sg * n[k * 3 + 2]};
+      double f[kGIn]; guide_features(S.gc, S.gh, xc, nc, f);
+      GuideAct act; guide_forward(A.guide_w, f, A.guide_bf16 != 0, act);
+      S.gtab[2 * k + side] = mixture_of(act.o);
+      S.gok[2 * k + side] = 1;
+      if (raw) for (int q = 0; q < kGOut; ++q) (*raw)[(2 * k + side) * kGOut + q] = act.o[q];
+    }
+  }
+}
+
 // Scattering at a smooth dielectric interface (the Glass Slab / caustic
 // material of Sec. 6), as an AD expression of the incoming direction w_in and
 // the unit shading normal ns (same side as the unit geometric normal ng).
@@ -580,6 +649,10 @@ struct PathResult {
   // derivatives of such paths amplify rounding by 1/cos^2, 1/length or a
   // one-sided filter slope); it changes nothing the oracle computes.
   bool illc;
+  // first guided Lambertian scatter of the path (guide training sample):
+  // vertex depth (0: none), position, arrival-side normal, direction,
+  // density, component
+  int gdepth; double gx[3], gn[3], gwd[3], gq; int gcomp;
 };
 
 inline bool near_tent_kink(double u) {
@@ -590,7 +663,7 @@ inline bool near_tent_kink(double u) {
 // Trace one light path as an AD expression of the parameters.
 void trace_path(const Scene& S, const ora_args& A, uint32_t path, PathResult& out) {
   const ora_scene& sc = *S.s;
-  out.conns.clear(); out.sig = 0x811C9DC5u; out.R = 0; out.W = 0.0; out.illc = false;
+  out.conns.clear(); out.sig = 0x811C9DC5u; out.R = 0; out.W = 0.0; out.illc = false; out.gdepth = 0;
   bool ill = false;  // ill-conditioned vertex so far
   const int W = sc.width, H = sc.height;
   const double Kfilm = (double)W * H / (4.0 * S.aspect * S.tan_half * S.tan_half * (double)A.n_paths);
@@ -753,12 +826,37 @@ void trace_path(const Scene& S, const ora_args& A, uint32_t path, PathResult& ou
       // --- cosine-weighted scatter on the arrival side
       double rr = std::sqrt(uj.u[0]), phi = 2.0 * M_PI * uj.u[1];
       double lx = rr * std::cos(phi), ly = rr * std::sin(phi), lz = std::sqrt(std::max(0.0, 1.0 - uj.u[0]));
+      V3 nav = cos_in < 0 ? ng : ng * V(-1.0);
+      double gwf = 1.0;  // f cos / p over rho: 1 for cosine sampling
+      const long ge = 2 * texel + (cos_in < 0 ? 0 : 1);
+      if (A.guide_w && A.guide_diffuse && S.gok[ge]) {
+        // guided scatter: direction from the texel's mixture folded about
+        // the arrival-side normal (component by u2, direction by u0, u1),
+        // weight cos / (pi q) with the density held fixed; the direction
+        // enters the derivatives through its local coordinates, like the
+        // cosine sample
+        D3 nd = val(nav);
+        int comp;
+        D3 w = guide_sample(S.gtab[ge], nd, uj.u[2], uj.u[0], uj.u[1], comp);
+        double q = guide_pdf(S.gtab[ge], nd, w), c = dot(w, nd);
+        if (!(q > 0.0 && c > 0.0)) break;
+        gwf = c / (M_PI * q);
+        D3 b1p, b2p; onb(nd, b1p, b2p);
+        lx = dot(w, b1p); ly = dot(w, b2p); lz = c;
+        if (out.gdepth == 0) {
+          D3 xp = val(x);
+          out.gdepth = j;
+          out.gx[0] = xp.x; out.gx[1] = xp.y; out.gx[2] = xp.z;
+          out.gn[0] = nd.x; out.gn[1] = nd.y; out.gn[2] = nd.z;
+          out.gwd[0] = w.x; out.gwd[1] = w.y; out.gwd[2] = w.z;
+          out.gq = q; out.gcomp = comp;
+        }
+      }
       // the sampled direction is held fixed in the local frame of the
       // arrival-side normal, so the frame moves with the surface
-      V3 nav = cos_in < 0 ? ng : ng * V(-1.0);
       V3 t1, t2; onbv(nav, t1, t2);
       V3 wo = t1 * V(lx) + t2 * V(ly) + nav * V(lz);
-      for (int c = 0; c < 3; ++c) beta[c] = beta[c] * rho[c];
+      for (int c = 0; c < 3; ++c) beta[c] = beta[c] * rho[c] * V(gwf);
       xprev = x; wcur = wo;
       offn = ngd; off = true;
     } else {  // dielectric: Fresnel-sampled reflect / refract, weight 1
@@ -859,6 +957,7 @@ int ora_render(const ora_scene* sc, const ora_args* A, const double* albedo, con
   if (A->guide_w && sc->em_type != ORA_EMIT_QUAD) return -1;  // the guide steers area emission only
   if (sc->em_tex_res > 0 && sc->em_type == ORA_EMIT_POINT) return -1;
   Scene S; S.init(sc, albedo, Le, heights, nmap, false);
+  if (A->guide_w && A->guide_diffuse) build_guide_table(S, *A, nullptr);
   const int W = sc->width, H = sc->height, D = A->max_depth;
   const long npix = (long)W * H * 3;
   const int64_t n = A->path_list ? A->n_list : A->n_paths;
@@ -917,6 +1016,7 @@ int ora_gradient(const ora_scene* sc, const ora_args* A, int mode, const double*
   if (A->guide_w && sc->em_type != ORA_EMIT_QUAD) return -1;
   if (sc->em_tex_res > 0 && sc->em_type == ORA_EMIT_POINT) return -1;
   Scene S; S.init(sc, albedo, Le, heights, nmap, (A->flags & ORA_F_ATTACHED) != 0);
+  if (A->guide_w && A->guide_diffuse) build_guide_table(S, *A, nullptr);
   const int W = sc->width, H = sc->height;
   const int64_t n = A->path_list ? A->n_list : A->n_paths;
   const long n_alb = S.slot_Le, n_h = sc->hf_G > 1 ? (long)sc->hf_G * sc->hf_G : 0;
@@ -1006,6 +1106,59 @@ int ora_guide_sample(const double* o, const double* n, const double* g, int64_t 
     D3 w = guide_sample(m, {n[i * 3], n[i * 3 + 1], n[i * 3 + 2]}, g[i * 3], g[i * 3 + 1], g[i * 3 + 2], cp);
     wd[i * 3] = w.x; wd[i * 3 + 1] = w.y; wd[i * 3 + 2] = w.z;
     if (comp) comp[i] = cp;
+  }
+  return 0;
+}
+
+// Guide table (see build_guide_table): raw network outputs per entry
+// raw [2 T][41], texel centres x, n [T][3] and coverage ok [T], T the number
+// of albedo texels.  Returns T, or -1 without guide weights.
+int64_t ora_guide_table(const ora_scene* sc, const ora_args* A, double* raw, double* x, double* n, uint8_t* ok) {
+  if (!A->guide_w) return -1;
+  Scene S; S.init(sc, nullptr, nullptr, nullptr, nullptr, false);
+  std::vector<double> r, xv, nv; std::vector<uint8_t> okv;
+  texel_centres(sc, xv, nv, okv);
+  build_guide_table(S, *A, &r);
+  const int64_t T = (int64_t)okv.size();
+  if (raw) std::copy(r.begin(), r.end(), raw);
+  if (x) std::copy(xv.begin(), xv.end(), x);
+  if (n) std::copy(nv.begin(), nv.end(), n);
+  if (ok) std::copy(okv.begin(), okv.end(), ok);
+  return T;
+}
+
+// Training samples of the diffuse guide, one per listed path: the path's
+// first guided Lambertian scatter (position, arrival-side normal, sampled
+// direction, density q, component) with S = sum of lum(C_i) over the path's
+// connections after that vertex (the contribution the direction carried),
+// in the 12-double layout of ora_guide_emit's samples; all zero for a path
+// with no guided scatter.  Needs guide_w and guide_diffuse.
+int ora_guide_vertex_samples(const ora_scene* sc, const ora_args* A, const double* albedo, const double* Le,
+                             const double* heights, const double* nmap, double* out) {
+  if (!A->guide_w || !A->guide_diffuse || sc->em_type != ORA_EMIT_QUAD) return -1;
+  Scene S; S.init(sc, albedo, Le, heights, nmap, false);
+  build_guide_table(S, *A, nullptr);
+  const int64_t n = A->path_list ? A->n_list : A->n_paths;
+  int nt = A->n_threads > 0 ? A->n_threads : omp_get_max_threads();
+#pragma omp parallel num_threads(nt)
+  {
+    Tape tape; g_tape = &tape;
+    PathResult pr;
+#pragma omp for schedule(dynamic, 256)
+    for (int64_t k = 0; k < n; ++k) {
+      uint32_t path = A->path_list ? A->path_list[k] : (uint32_t)k;
+      tape.clear();
+      trace_path(S, *A, path, pr);
+      double* o = out + k * 12;
+      for (int q = 0; q < 12; ++q) o[q] = 0.0;
+      if (!pr.gdepth) continue;
+      double Sd = 0.0;
+      for (const Conn& cn : pr.conns)
+        if (cn.depth > pr.gdepth) Sd += kLumR * cn.C[0].v + kLumG * cn.C[1].v + kLumB * cn.C[2].v;
+      for (int q = 0; q < 3; ++q) { o[q] = pr.gx[q]; o[3 + q] = pr.gn[q]; o[6 + q] = pr.gwd[q]; }
+      o[9] = pr.gq; o[10] = Sd; o[11] = pr.gcomp;
+    }
+    g_tape = nullptr;
   }
   return 0;
 }

@@ -65,7 +65,8 @@ class _Args(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("n_paths", C.c_int64), ("max_depth", C.c_int32),
                 ("flags", C.c_int32), ("n_threads", C.c_int32),
                 ("path_list", C.POINTER(C.c_uint32)), ("n_list", C.c_int64),
-                ("guide_w", C.POINTER(C.c_double)), ("guide_bf16", C.c_int32)]
+                ("guide_w", C.POINTER(C.c_double)), ("guide_bf16", C.c_int32),
+                ("guide_diffuse", C.c_int32)]
 
 
 GUIDE_NPARAMS = 11433
@@ -95,6 +96,10 @@ def _load():
         _lib.ora_guide_emit.argtypes = [C.POINTER(_Scene), C.POINTER(_Args), dp, ip]
         _lib.ora_guide_emit.restype = C.c_int
         _lib.ora_guide_loss_grad.argtypes = [C.POINTER(_Scene), dp, dp, C.c_int64, C.c_int, dp, dp]
+        _lib.ora_guide_table.argtypes = [C.POINTER(_Scene), C.POINTER(_Args), dp, dp, dp, C.POINTER(C.c_uint8)]
+        _lib.ora_guide_table.restype = C.c_int64
+        _lib.ora_guide_vertex_samples.argtypes = [C.POINTER(_Scene), C.POINTER(_Args), dp, dp, dp, dp, dp]
+        _lib.ora_guide_vertex_samples.restype = C.c_int
         _lib.ora_dielectric.argtypes = [dp, dp, dp, C.c_double, C.c_double, dp, ip, dp]
         _lib.ora_dielectric.restype = C.c_int
         assert _lib.ora_guide_nparams() == GUIDE_NPARAMS
@@ -150,7 +155,8 @@ def _scene(sc, keep):
     return s
 
 
-def _args(seed, n_paths, depth, flags, threads, path_list, keep, guide_w=None, guide_bf16=True):
+def _args(seed, n_paths, depth, flags, threads, path_list, keep, guide_w=None, guide_bf16=True,
+          guide_diffuse=False):
     a = _Args()
     if guide_w is not None:
         gw = keep.f64(guide_w)
@@ -158,6 +164,7 @@ def _args(seed, n_paths, depth, flags, threads, path_list, keep, guide_w=None, g
         a.guide_w, a.guide_bf16 = _p(gw), int(bool(guide_bf16))
     else:
         a.guide_w, a.guide_bf16 = None, 0
+    a.guide_diffuse = int(bool(guide_diffuse) and guide_w is not None)
     a.seed, a.n_paths, a.max_depth, a.flags, a.n_threads = int(seed), int(n_paths), int(depth), int(flags), int(threads)
     if path_list is not None:
         pl = np.ascontiguousarray(path_list, np.uint32)
@@ -182,17 +189,18 @@ def _params(sc, albedo, Le, heights, keep, normal_map=None):
 
 def render(sc, seed, n_paths, depth, albedo=None, Le=None, heights=None, flags=0,
            path_list=None, slices=False, per_path=False, threads=0, guide_w=None, guide_bf16=True,
-           normal_map=None):
+           normal_map=None, guide_diffuse=False):
     """FP64 light-tracing image [H,W,3] (plus optional per-depth slices,
     per-path signature / reservoir index R / weight W / ill-conditioning
     flag, and total flux).
-    guide_w: emission-guide weights (guided emission), else cosine emission.
+    guide_w: emission-guide weights (guided emission), else cosine emission;
+    guide_diffuse: Lambertian vertices scatter from the guide table too.
     normal_map: [G*G*2] shading slopes of a normal-mapped heightfield
     (default: the scene's, if any; else slopes from the heights)."""
     lib = _load()
     keep = _Keep()
     s = _scene(sc, keep)
-    a = _args(seed, n_paths, depth, flags, threads, path_list, keep, guide_w, guide_bf16)
+    a = _args(seed, n_paths, depth, flags, threads, path_list, keep, guide_w, guide_bf16, guide_diffuse)
     alb, le, h, nm = _params(sc, albedo, Le, heights, keep, normal_map)
     H, W = int(sc["camera"]["height"]), int(sc["camera"]["width"])
     img = np.zeros((H, W, 3))
@@ -216,15 +224,16 @@ def render(sc, seed, n_paths, depth, albedo=None, Le=None, heights=None, flags=0
 
 
 def gradient(sc, seed, n_paths, depth, dI, mode=MODE_NAIVE, albedo=None, Le=None, heights=None,
-             flags=0, path_list=None, threads=0, guide_w=None, guide_bf16=True, normal_map=None):
+             flags=0, path_list=None, threads=0, guide_w=None, guide_bf16=True, normal_map=None,
+             guide_diffuse=False):
     """Gradient of <dI, I(theta)> w.r.t. albedo texels, emitter radiance and
     (attached) heights and normal-map slopes, by taped reverse-mode AD of
-    each light path.  With guide_w the emission is guided and its density is
-    held fixed (detached)."""
+    each light path.  With guide_w the emission (and with guide_diffuse the
+    Lambertian scatter) is guided and its density is held fixed (detached)."""
     lib = _load()
     keep = _Keep()
     s = _scene(sc, keep)
-    a = _args(seed, n_paths, depth, flags, threads, path_list, keep, guide_w, guide_bf16)
+    a = _args(seed, n_paths, depth, flags, threads, path_list, keep, guide_w, guide_bf16, guide_diffuse)
     alb, le, h, nm = _params(sc, albedo, Le, heights, keep, normal_map)
     dI = keep.f64(dI)
     g_alb = np.zeros_like(alb)
@@ -322,6 +331,37 @@ def guide_emit(sc, seed, n_paths, guide_w, path_list=None, bf16=True):
     if lib.ora_guide_emit(C.byref(s), C.byref(a), _p(rec), _p(comp, C.c_int32)) != 0:
         raise ValueError("guided emission needs an area emitter and weights")
     return dict(x=rec[:, 0:3], w=rec[:, 3:6], pdf=rec[:, 6], factor=rec[:, 7], comp=comp)
+
+
+def guide_table(sc, guide_w, bf16=True):
+    """The diffuse guide table: raw network outputs per entry [2T, 41]
+    (entry 2 texel + side), texel centres x, n [T, 3] and coverage ok [T]."""
+    lib = _load()
+    keep = _Keep()
+    s = _scene(sc, keep)
+    a = _args(1, 1, 1, 0, 1, None, keep, guide_w, bf16)
+    T = int(sc["n_tex"]) * int(sc["tex_res"]) ** 2
+    raw, x, n = np.zeros((2 * T, GUIDE_OUT)), np.zeros((T, 3)), np.zeros((T, 3))
+    ok = np.zeros(T, np.uint8)
+    rc = lib.ora_guide_table(C.byref(s), C.byref(a), _p(raw), _p(x), _p(n), _p(ok, C.c_uint8))
+    assert rc == T
+    return dict(raw=raw, x=x, n=n, ok=ok.astype(bool))
+
+
+def guide_vertex_samples(sc, seed, n_paths, depth, guide_w, path_list=None, bf16=True, threads=0,
+                         albedo=None, Le=None):
+    """Diffuse-guide training samples [n, 12] (x, n, w, q, S, comp) of each
+    path's first guided Lambertian scatter; zero rows for paths without one."""
+    lib = _load()
+    keep = _Keep()
+    s = _scene(sc, keep)
+    a = _args(seed, n_paths, depth, 0, threads, path_list, keep, guide_w, bf16, True)
+    alb, le, h, nm = _params(sc, albedo, Le, None, keep)
+    n = len(path_list) if path_list is not None else int(n_paths)
+    out = np.zeros((n, 12))
+    if lib.ora_guide_vertex_samples(C.byref(s), C.byref(a), _p(alb), _p(le), _p(h), _p(nm), _p(out)) != 0:
+        raise ValueError("diffuse guide samples need an area emitter and weights")
+    return out
 
 
 def guide_loss_grad(sc, w, samples, bf16=True):

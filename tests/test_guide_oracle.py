@@ -11,7 +11,13 @@
   * Adam equals torch.optim.Adam;
   * the guided light tracer is unbiased: its mean image over seeds matches
     the cosine-emission tracer's within sampling error, and its albedo
-    gradient equals finite differences of the guided image.
+    gradient equals finite differences of the guided image;
+  * the diffuse guide table: texel centres lie where an independent affine
+    fit of each quad's chart puts them, entries are the network at both
+    sides, alpha = 0 reduces it to cosine sampling, the guided tracer
+    (emission and diffuse vertices) stays unbiased, its albedo and attached
+    heights gradients equal finite differences, and the training samples'
+    S add up to the flux of the later connections.
 """
 import math
 
@@ -299,3 +305,164 @@ def test_guided_attached_heights_match_finite_differences():
         assert abs(fd - gh[k]) <= 1e-5 * np.abs(gh).max(), (k, fd, gh[k])
         checked += 1
     assert checked >= 8
+
+
+# ----------------------------------------------------------------- diffuse guide
+def _quad_affine(sc, tex):
+    """Least-squares affine map chart (u, v, 1) -> position over the
+    triangles of texture `tex` (a planar quad), and their unit normal."""
+    rows, pos = [], []
+    for t in range(sc["tri_v"].shape[0]):
+        m = sc["tri_mat"][t]
+        if sc["mat_type"][m] != scenes.MAT_LAMBERT or sc["mat_tex"][m] != tex:
+            continue
+        for k in range(3):
+            rows.append([*sc["tri_uv"][t, k], 1.0])
+            pos.append(sc["tri_v"][t, k])
+        e1 = sc["tri_v"][t, 1] - sc["tri_v"][t, 0]
+        e2 = sc["tri_v"][t, 2] - sc["tri_v"][t, 0]
+        nrm = np.cross(e1, e2)
+    M, *_ = np.linalg.lstsq(np.array(rows), np.array(pos), rcond=None)
+    return M, nrm / np.linalg.norm(nrm)
+
+
+def test_texel_centres_on_the_quads():
+    sc = scenes.box_scene(width=16, height=16, tex_res=4)
+    t = O.guide_table(sc, scenes.guide_random_weights(2))
+    R = sc["tex_res"]
+    assert t["ok"].all()
+    for tex in range(sc["n_tex"]):
+        M, nrm = _quad_affine(sc, tex)
+        for ty in range(R):
+            for tx in range(R):
+                k = (tex * R + ty) * R + tx
+                want = np.array([(tx + 0.5) / R, (ty + 0.5) / R, 1.0]) @ M
+                np.testing.assert_allclose(t["x"][k], want, atol=1e-12)
+                np.testing.assert_allclose(t["n"][k], nrm, atol=1e-12)
+
+
+def test_guide_table_entries_are_the_network_at_both_sides():
+    sc = scenes.box_scene(width=16, height=16, tex_res=4)
+    w = scenes.guide_random_weights(3)
+    t = O.guide_table(sc, w)
+    raw0 = O.guide_eval(sc, w, t["x"], t["n"])
+    raw1 = O.guide_eval(sc, w, t["x"], -t["n"])
+    np.testing.assert_array_equal(t["raw"][0::2], raw0)
+    np.testing.assert_array_equal(t["raw"][1::2], raw1)
+    assert np.abs(raw0 - raw1).max() > 1e-3   # the normal input matters
+
+
+def _cosine_only(w):
+    w = np.array(w, np.float64)
+    w[-1] = -1e3          # mixing logit: alpha = 0.9 sigmoid(-1000) = 0
+    return w
+
+
+def test_diffuse_guide_with_zero_alpha_is_cosine_sampling():
+    # alpha = 0 leaves only the cosine component: the same directions (from
+    # the same two uniforms) and weight cos / (pi cos / pi) = 1
+    sc = scenes.box_scene(width=16, height=16, tex_res=4)
+    w = _cosine_only(scenes.guide_random_weights(4))
+    a = O.render(sc, 5, 4000, 5, per_path=True)
+    b = O.render(sc, 5, 4000, 5, per_path=True, guide_w=w, guide_diffuse=True)
+    c = O.render(sc, 5, 4000, 5, per_path=True, guide_w=w)
+    np.testing.assert_array_equal(b["sig"], c["sig"])
+    np.testing.assert_allclose(b["image"], c["image"], rtol=1e-12, atol=1e-12 * c["image"].max())
+    assert np.abs(a["image"] - c["image"]).max() > 0   # the emission guide itself is on
+
+
+def _aimed_up(logk=2.5):
+    return scenes.guide_aimed_weights(direction=(0.0, 1.0, 0.3), logk=logk, spread=0.2)
+
+
+def test_diffuse_guided_tracer_unbiased():
+    sc = scenes.box_scene(width=32, height=32)
+    w = _aimed_up()
+    seeds, n = 24, 6000
+    gs = np.array([_blocks(O.render(sc, 1000 + s, n, 4, guide_w=w, guide_diffuse=True)["image"])
+                   for s in range(seeds)])
+    us = np.array([_blocks(O.render(sc, 5000 + s, n, 4)["image"]) for s in range(seeds)])
+    diff = gs.mean(0) - us.mean(0)
+    se = np.sqrt(gs.var(0, ddof=1) / seeds + us.var(0, ddof=1) / seeds)
+    z = diff / se
+    assert np.max(np.abs(z)) < 4.5, np.max(np.abs(z))
+    # the diffuse guide really changes the estimator: its samples are not
+    # cosine distributed (q differs from cos / pi)
+    smp = O.guide_vertex_samples(sc, 3, 2000, 4, w)
+    on = smp[:, 9] > 0
+    assert on.mean() > 0.3
+    cosq = np.einsum("ij,ij->i", smp[on, 3:6], smp[on, 6:9]) / math.pi
+    assert np.std(cosq / smp[on, 9]) > 0.1 * np.mean(cosq / smp[on, 9])
+
+
+def test_diffuse_guided_gradient_matches_finite_differences():
+    sc = scenes.box_scene(width=16, height=16, tex_res=4)
+    w = _aimed_up()
+    seed, n, D = 3, 3000, 4
+    T = O.render(sc, 99, 20000, D, albedo=sc["albedo_target"])["image"]
+    I = O.render(sc, seed, n, D, guide_w=w, guide_diffuse=True)["image"]
+    _, dI = O.loss_and_adjoint(I, T)
+    g = O.gradient(sc, seed, n, D, dI, guide_w=w, guide_diffuse=True)
+    rng = np.random.default_rng(1)
+    alb = sc["albedo"]
+    flat = alb.reshape(-1)
+    for i in rng.choice(flat.size, 6, replace=False):
+        h = 1e-5
+        ap, am = flat.copy(), flat.copy()
+        ap[i] += h; am[i] -= h
+        Ip = O.render(sc, seed, n, D, albedo=ap.reshape(alb.shape), guide_w=w, guide_diffuse=True)["image"]
+        Im = O.render(sc, seed, n, D, albedo=am.reshape(alb.shape), guide_w=w, guide_diffuse=True)["image"]
+        fd = np.sum(dI * (Ip - Im)) / (2 * h)
+        assert abs(fd - g["albedo"].reshape(-1)[i]) <= 1e-6 * max(1e-3, abs(fd)), (i, fd, g["albedo"].reshape(-1)[i])
+
+
+def test_diffuse_guided_attached_heights_match_finite_differences():
+    # the caustic's diffuse vertices lie on the static receiver: the guided
+    # direction there does not move with the heights, so the attached
+    # gradient is the derivative of the guided image
+    sc = scenes.caustic_scene(G=8, width=32, height=32)
+    w = scenes.guide_aimed_weights()
+    seed, n, D = 5, 4096, 4
+    T = O.render(sc, 99, n, D, heights=sc["heights_target"])["image"]
+    kw = dict(guide_w=w, guide_diffuse=True)
+    r0 = O.render(sc, seed, n, D, per_path=True, **kw)
+    _, dI = O.loss_and_adjoint(r0["image"], T)
+    gh = O.gradient(sc, seed, n, D, dI, flags=O.ATTACHED, **kw)["heights"]
+    assert np.count_nonzero(gh) > 20
+    h0 = sc["heights"].copy()
+    eps, checked = 1e-7, 0
+    for k in np.argsort(-np.abs(gh))[:12]:
+        hp, hm = h0.copy(), h0.copy()
+        hp[k] += eps
+        hm[k] -= eps
+        rp = O.render(sc, seed, n, D, heights=hp, per_path=True, **kw)
+        rm = O.render(sc, seed, n, D, heights=hm, per_path=True, **kw)
+        if not (np.array_equal(rp["sig"], r0["sig"]) and np.array_equal(rm["sig"], r0["sig"])):
+            continue
+        fd = (O.loss_and_adjoint(rp["image"], T)[0] - O.loss_and_adjoint(rm["image"], T)[0]) / (2 * eps)
+        assert abs(fd - gh[k]) <= 1e-5 * np.abs(gh).max(), (k, fd, gh[k])
+        checked += 1
+    assert checked >= 6
+
+
+def test_diffuse_vertex_samples_follow_the_paths():
+    # the sample's S is the luminance of the path's connections after the
+    # sampled vertex: summed over paths it is the flux of the depth >= 2
+    # slices of paths whose first scatter is guided (every box path is)
+    sc = scenes.box_scene(width=16, height=16, tex_res=4)
+    w = _aimed_up()
+    seed, n, D = 8, 3000, 4
+    smp = O.guide_vertex_samples(sc, seed, n, D, w)
+    kw = dict(guide_w=w, guide_diffuse=True)
+    lum = np.array([0.2126, 0.7152, 0.0722])
+    on = smp[:, 9] > 0
+    assert on.mean() > 0.5
+    # every box path that scatters does so first at x_1 (a Lambertian wall),
+    # so the samples' S add up to the flux of the connections at depth >= 2:
+    # the flux at depth D minus the flux at depth 1 of the same paths
+    f_all = O.render(sc, seed, n, D, **kw)["flux"]
+    f_one = O.render(sc, seed, n, 1, **kw)["flux"]
+    np.testing.assert_allclose(smp[:, 10].sum(), lum @ (f_all - f_one), rtol=1e-9)
+    np.testing.assert_allclose(np.linalg.norm(smp[on, 3:6], axis=1), 1.0, atol=1e-12)
+    np.testing.assert_allclose(np.linalg.norm(smp[on, 6:9], axis=1), 1.0, atol=1e-12)
+    assert (np.einsum("ij,ij->i", smp[on, 3:6], smp[on, 6:9]) > 0).all()
