@@ -72,7 +72,9 @@ enum {
   LT_RECORD_TAPE = 4u,      /* lt_trace writes the naive-AD tape */
   LT_RECORD_RESERVOIR = 8u, /* lt_trace writes the per-path ResLRB record */
   LT_CONTRIB_ADJOINT = 16u, /* attached backward: path_contrib gets |delta_total| (below) */
-  LT_RECORD_SPLATS = 32u    /* lt_trace writes the buffered two-pass splat records (detached) */
+  LT_RECORD_SPLATS = 32u,   /* lt_trace writes the buffered two-pass splat records (detached) */
+  LT_GUIDE_DIFFUSE = 64u    /* with params->guide_w: Lambertian vertices scatter from the
+                               learned guide too (diffuse guide table, see the guide section) */
 };
 
 typedef struct lt_ctx lt_ctx;
@@ -358,6 +360,23 @@ lt_status lt_backward_lrb3_noalloc(lt_ctx* ctx, const lt_trace_args* args, const
  * direction and density of each path, recomputed by every pass).
  * Errors: LT_ERR_UNSUPPORTED for a point emitter with a guide.
  * ------------------------------------------------------------------------ */
+/* Diffuse vertices (LT_GUIDE_DIFFUSE).  The same network also guides the
+ * scattered direction at Lambertian vertices, queried per albedo texel: once
+ * per pass the library evaluates it at every texel centre - the chart centre
+ * ((tx + 1/2)/R, (ty + 1/2)/R) placed on the lowest-index static Lambertian
+ * triangle of the texel's texture whose chart triangle holds it - with the
+ * triangle's unit normal +n (side 0) and -n (side 1), and keeps the folded
+ * mixtures in a table (2 x 16 float4 per texel, L2-resident).  A vertex
+ * reached against its triangle's geometric normal uses side 0, else side 1;
+ * it draws from the mixture folded about its arrival-side normal, the
+ * component by the third uniform of its vertex counter (path, j, 0), the
+ * direction by the first two, and weights the path by rho cos / (pi q) in
+ * place of rho, q held fixed in every reverse mode.  Attached passes keep
+ * the drawn direction fixed in the vertex's local frame, as for a cosine
+ * sample.  A texel that no triangle holds samples the cosine density.
+ * Workspace: + 512 bytes per texel; a detached naive tape: + 4 bytes per
+ * vertex record (the scatter weight).
+ * ------------------------------------------------------------------------ */
 #define LT_GUIDE_NPARAMS 11433
 #define LT_GUIDE_NOUT 41
 
@@ -382,6 +401,18 @@ lt_status lt_guide_eval(lt_ctx* ctx, const float* guide_w, const float* x, const
  * Errors: LT_ERR_ARG, LT_ERR_STATE, LT_ERR_UNSUPPORTED (point emitter). */
 lt_status lt_guide_emit(lt_ctx* ctx, const lt_trace_args* args, const lt_params* params,
                         const float* path_contrib, lt_guide_sample* out);
+
+/* Training samples of the diffuse guide, one per path of
+ * [0, args->n_paths): the path's first guided Lambertian scatter (position,
+ * arrival-side normal, direction, density q, component) with S = the sum
+ * of lum(C_i) over the path's later connections (Rec. 709 luminance), as
+ * the guided pass with args draws it; an all-zero sample (S = 0) for a path
+ * with none.  out: DEVICE [n_paths].  args->flags: 0 or LT_GUIDE_DIFFUSE
+ * (the pass is guided at diffuse vertices either way); params->guide_w set.
+ * Writes no image.
+ * Errors: as lt_trace, LT_ERR_ARG (other flags, null out or guide_w). */
+lt_status lt_guide_vertex_samples(lt_ctx* ctx, const lt_trace_args* args, const lt_params* params,
+                                  lt_guide_sample* out);
 
 /* Training loss L = -sum_b (S_b / q_b) log q_theta(w_b | x_b, n_b) / Z with
  * Z = sum_b S_b / q_b (a self-normalised Monte Carlo estimate of the KL

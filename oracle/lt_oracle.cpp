@@ -183,7 +183,10 @@ typedef struct {
   const double* guide_w;   // emission-guide weights [11433] or NULL (cosine emission)
   int32_t guide_bf16;      // 1: round MLP operands to bfloat16 where the GPU does
   int32_t guide_diffuse;   // 1 (with guide_w): Lambertian vertices scatter from the
-                           // guide table of their texel (see GuideTable)
+                           // guide table of their texel (see build_guide_table)
+  const uint8_t* guide_flag;  // test bookkeeping, or NULL: per guide-table entry, 1 marks
+                              // it; ora_render's info bit 2 reports a path that scatters
+                              // from a marked entry (changes nothing computed)
 } ora_args;
 
 }  // extern "C"
@@ -653,6 +656,7 @@ struct PathResult {
   // vertex depth (0: none), position, arrival-side normal, direction,
   // density, component
   int gdepth; double gx[3], gn[3], gwd[3], gq; int gcomp;
+  bool gflag;  // scattered from a guide-table entry marked in ora_args.guide_flag
 };
 
 inline bool near_tent_kink(double u) {
@@ -663,7 +667,7 @@ inline bool near_tent_kink(double u) {
 // Trace one light path as an AD expression of the parameters.
 void trace_path(const Scene& S, const ora_args& A, uint32_t path, PathResult& out) {
   const ora_scene& sc = *S.s;
-  out.conns.clear(); out.sig = 0x811C9DC5u; out.R = 0; out.W = 0.0; out.illc = false; out.gdepth = 0;
+  out.conns.clear(); out.sig = 0x811C9DC5u; out.R = 0; out.W = 0.0; out.illc = false; out.gdepth = 0; out.gflag = false;
   bool ill = false;  // ill-conditioned vertex so far
   const int W = sc.width, H = sc.height;
   const double Kfilm = (double)W * H / (4.0 * S.aspect * S.tan_half * S.tan_half * (double)A.n_paths);
@@ -836,6 +840,7 @@ void trace_path(const Scene& S, const ora_args& A, uint32_t path, PathResult& ou
         // enters the derivatives through its local coordinates, like the
         // cosine sample
         D3 nd = val(nav);
+        if (A.guide_flag && A.guide_flag[ge]) out.gflag = true;
         int comp;
         D3 w = guide_sample(S.gtab[ge], nd, uj.u[2], uj.u[0], uj.u[1], comp);
         double q = guide_pdf(S.gtab[ge], nd, w), c = dot(w, nd);
@@ -950,7 +955,8 @@ int ora_dielectric(const double* w_in, const double* ng, const double* ns, doubl
 // slices [D][H][W][3] (connections of vertex i land in slice i-1),
 // sig/R/Wres per listed path, flux = sum over connections of C (3 doubles),
 // info per listed path (bit 1: an ill-conditioned vertex at or before the
-// last sensor connection, see PathResult).
+// last sensor connection, see PathResult; bit 2: a guided scatter from an
+// entry marked in guide_flag).
 int ora_render(const ora_scene* sc, const ora_args* A, const double* albedo, const double* Le,
                const double* heights, const double* nmap, double* image, double* slices, uint32_t* sig,
                int32_t* Rout, double* Wout, double* flux, uint32_t* info) {
@@ -979,7 +985,7 @@ int ora_render(const ora_scene* sc, const ora_args* A, const double* albedo, con
       if (sig) sig[k] = pr.sig;
       if (Rout) Rout[k] = pr.R;
       if (Wout) Wout[k] = pr.W;
-      if (info) info[k] = pr.illc ? 2u : 0u;
+      if (info) info[k] = (pr.illc ? 2u : 0u) | (pr.gflag ? 4u : 0u);
       for (size_t ci = 0; ci < pr.conns.size(); ++ci) {
         const Conn& cn = pr.conns[ci];
         double scale = 1.0;

@@ -66,7 +66,7 @@ class _Args(C.Structure):
                 ("flags", C.c_int32), ("n_threads", C.c_int32),
                 ("path_list", C.POINTER(C.c_uint32)), ("n_list", C.c_int64),
                 ("guide_w", C.POINTER(C.c_double)), ("guide_bf16", C.c_int32),
-                ("guide_diffuse", C.c_int32)]
+                ("guide_diffuse", C.c_int32), ("guide_flag", C.POINTER(C.c_uint8))]
 
 
 GUIDE_NPARAMS = 11433
@@ -165,6 +165,7 @@ def _args(seed, n_paths, depth, flags, threads, path_list, keep, guide_w=None, g
     else:
         a.guide_w, a.guide_bf16 = None, 0
     a.guide_diffuse = int(bool(guide_diffuse) and guide_w is not None)
+    a.guide_flag = None
     a.seed, a.n_paths, a.max_depth, a.flags, a.n_threads = int(seed), int(n_paths), int(depth), int(flags), int(threads)
     if path_list is not None:
         pl = np.ascontiguousarray(path_list, np.uint32)
@@ -189,12 +190,14 @@ def _params(sc, albedo, Le, heights, keep, normal_map=None):
 
 def render(sc, seed, n_paths, depth, albedo=None, Le=None, heights=None, flags=0,
            path_list=None, slices=False, per_path=False, threads=0, guide_w=None, guide_bf16=True,
-           normal_map=None, guide_diffuse=False):
+           normal_map=None, guide_diffuse=False, guide_flag=None):
     """FP64 light-tracing image [H,W,3] (plus optional per-depth slices,
     per-path signature / reservoir index R / weight W / ill-conditioning
     flag, and total flux).
     guide_w: emission-guide weights (guided emission), else cosine emission;
-    guide_diffuse: Lambertian vertices scatter from the guide table too.
+    guide_diffuse: Lambertian vertices scatter from the guide table too;
+    guide_flag: optional bool per guide-table entry (test bookkeeping):
+    per_path's "gflag" marks the paths that scatter from a marked entry.
     normal_map: [G*G*2] shading slopes of a normal-mapped heightfield
     (default: the scene's, if any; else slopes from the heights)."""
     lib = _load()
@@ -202,6 +205,10 @@ def render(sc, seed, n_paths, depth, albedo=None, Le=None, heights=None, flags=0
     s = _scene(sc, keep)
     a = _args(seed, n_paths, depth, flags, threads, path_list, keep, guide_w, guide_bf16, guide_diffuse)
     alb, le, h, nm = _params(sc, albedo, Le, heights, keep, normal_map)
+    if guide_flag is not None:
+        gf = np.ascontiguousarray(guide_flag, np.uint8)
+        keep.refs.append(gf)
+        a.guide_flag = _p(gf, C.c_uint8)
     H, W = int(sc["camera"]["height"]), int(sc["camera"]["width"])
     img = np.zeros((H, W, 3))
     sl = np.zeros((depth, H, W, 3)) if slices else None
@@ -219,7 +226,7 @@ def render(sc, seed, n_paths, depth, albedo=None, Le=None, heights=None, flags=0
     if slices:
         out["slices"] = sl
     if per_path:
-        out.update(sig=sig, R=R, W=Wr, illc=(info & 2) != 0)
+        out.update(sig=sig, R=R, W=Wr, illc=(info & 2) != 0, gflag=(info & 4) != 0)
     return out
 
 

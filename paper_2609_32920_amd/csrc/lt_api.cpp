@@ -195,6 +195,9 @@ struct lt_ctx {
   size_t grec_n = 0;
   float* d_gpart = nullptr;  // guide gradient partial sums [gpart_n][kGN + 1]
   size_t gpart_n = 0;
+  float* d_tcx = nullptr;    // albedo texel centres [n_texels][3] (diffuse guide inputs)
+  float* d_tcn = nullptr;    // and their normals (0: no triangle covers the centre)
+  float4* d_gtab = nullptr;  // diffuse guide table [2 n_texels][16], built per guided pass
   char* d_hand = nullptr;    // LRB-3 hand-off between its two kernels [hand_n bytes]
   size_t hand_n = 0;
   char* d_scratch = nullptr; // this device's copy of the static scratch (null: unavailable)
@@ -215,8 +218,10 @@ struct lt_ctx {
   void free_scene() {
     hipFree(d_nodes); hipFree(d_tris); hipFree(d_prim_mat); hipFree(d_prim_uv);
     hipFree(d_mat_type); hipFree(d_mat_tex); hipFree(d_mat_ior); hipFree(d_slot_of_prim); hipFree(d_levels);
+    hipFree(d_tcx); hipFree(d_tcn); hipFree(d_gtab);
     d_nodes = nullptr; d_tris = nullptr; d_prim_mat = nullptr; d_prim_uv = nullptr; d_mat_type = nullptr;
     d_mat_tex = nullptr; d_mat_ior = nullptr; d_slot_of_prim = nullptr; d_levels = nullptr;
+    d_tcx = nullptr; d_tcn = nullptr; d_gtab = nullptr;
     has_scene = false; scene_bytes = 0;
   }
 };
@@ -279,10 +284,11 @@ int agrad_in_lds(const lt_ctx* c, BwdKernel k, int block, size_t used) {
 size_t stack_lds(const lt_ctx* c, int block) { return (size_t)c->dsc.stack_n * block * sizeof(int); }
 size_t hgrad_lds_bytes(const lt_ctx* c, int on) { return on ? (size_t)c->dsc.hf_G * c->dsc.hf_G * sizeof(float) : 0; }
 
-struct SideLayout { size_t tape = 0, len = 0, emit = 0, res = 0, spl_hdr = 0, spl = 0, total = 0; };
+struct SideLayout { size_t tape = 0, len = 0, emit = 0, gw = 0, res = 0, spl_hdr = 0, spl = 0, total = 0; };
 
 // Side state: naive tape [D][N] records (+ N path lengths; attached: + the
-// emitted ray's dv_1/dH_1 per path), ResLRB records [N].
+// emitted ray's dv_1/dH_1 per path; detached with a diffuse guide: + [D][N]
+// scatter weights), ResLRB records [N].
 SideLayout side_layout(const lt_trace_args* a) {
   SideLayout L;
   size_t N = (size_t)a->n_paths, D = (size_t)a->max_depth;
@@ -292,6 +298,9 @@ SideLayout side_layout(const lt_trace_args* a) {
     L.tape = off; off = align256(off + N * D * (att ? sizeof(TapeRecAtt) : sizeof(TapeRec)));
     L.len = off; off = align256(off + N * sizeof(int32_t));
     if (att) { L.emit = off; off = align256(off + N * 2 * sizeof(float)); }
+    // detached tape with a diffuse guide: the scatter weight cos / (pi q) of
+    // every vertex (the attached record has room for it)
+    if (!att && (a->flags & LT_GUIDE_DIFFUSE)) { L.gw = off; off = align256(off + N * D * sizeof(float)); }
   }
   if (a->flags & LT_RECORD_RESERVOIR) {
     L.res = off; off = align256(off + N * (att ? sizeof(ResRecAtt) : sizeof(ResRec)));
@@ -311,8 +320,10 @@ lt_status check_args(lt_ctx* c, const lt_trace_args* a, const lt_params* p) {
   if (a->n_paths < 1 || a->n_paths >= (int64_t)1 << 31) return c->fail(LT_ERR_ARG, "n_paths out of range [1, 2^31)%s");
   if (a->max_depth < 1 || a->max_depth > kMaxDepth) return c->fail(LT_ERR_ARG, "max_depth out of range [1, 64]%s");
   if (a->flags & ~(uint32_t)(LT_ATTACHED | LT_SPLAT_SELECTED | LT_RECORD_TAPE | LT_RECORD_RESERVOIR | LT_CONTRIB_ADJOINT |
-                             LT_RECORD_SPLATS))
+                             LT_RECORD_SPLATS | LT_GUIDE_DIFFUSE))
     return c->fail(LT_ERR_ARG, "unknown flag bits%s");
+  if ((a->flags & LT_GUIDE_DIFFUSE) && !p->guide_w)
+    return c->fail(LT_ERR_ARG, "LT_GUIDE_DIFFUSE needs params->guide_w%s");
   if ((a->flags & LT_RECORD_SPLATS) && (a->flags & (LT_ATTACHED | LT_RECORD_TAPE)))
     return c->fail(LT_ERR_UNSUPPORTED, "LT_RECORD_SPLATS is detached and not combined with LT_RECORD_TAPE%s");
   if (!p->albedo || !p->emitter_L) return c->fail(LT_ERR_ARG, "albedo and emitter_L are required%s");
@@ -398,6 +409,19 @@ lt_status guide_prepass(lt_ctx* c, const lt_trace_args* a, const lt_params* p, P
   G.rec = c->d_grec;
   if ((st = c->hip(launch_guide_emit(G, guide_grid(c, a->n_paths), c->stream), "guide emit")) != LT_OK) return st;
   A.guide_rec = c->d_grec;
+  A.gtab = nullptr;
+  if (a->flags & LT_GUIDE_DIFFUSE) {
+    const int64_t ne = 2 * (int64_t)c->dsc.n_tex * c->dsc.tex_res * c->dsc.tex_res;
+    if (!c->d_gtab && hipMalloc((void**)&c->d_gtab, (size_t)ne * kGTabF4 * sizeof(float4)) != hipSuccess) {
+      (void)hipGetLastError();
+      c->d_gtab = nullptr;
+      return c->fail(LT_ERR_OOM, "out of device memory for the diffuse guide table%s");
+    }
+    GuideArgs T = guide_args(c, p->guide_w, ne);
+    T.x = c->d_tcx; T.n = c->d_tcn; T.table = c->d_gtab;
+    if ((st = c->hip(launch_guide_table(T, guide_grid(c, ne), c->stream), "guide table")) != LT_OK) return st;
+    A.gtab = c->d_gtab;
+  }
   return LT_OK;
 }
 
@@ -680,7 +704,8 @@ lt_status lt_scene_upload(lt_ctx* c, const lt_scene_desc* s) {
   if (e != hipSuccess) { c->free_scene(); return c->hip(e, "scene upload"); }
   c->level_off = loff;
   c->scene_bytes = F.nodes.size() * sizeof(Node) + ordered.size() * sizeof(Tri) + pmat.size() * 4 +
-                   puv.size() * 4 + slot.size() * 4 + levels.size() * 4 + 512;
+                   puv.size() * 4 + slot.size() * 4 + levels.size() * 4 +
+                   (size_t)s->n_tex * s->tex_res * s->tex_res * 6 * sizeof(float) + 512;
 
   DevScene& d = c->dsc;
   std::memset(&d, 0, sizeof(d));
@@ -728,6 +753,47 @@ lt_status lt_scene_upload(lt_ctx* c, const lt_scene_desc* s) {
       d.gb_ih[a] = h > 0 ? (float)(1.0 / h) : 0.f;
     }
   }
+  {  // albedo texel centres for the diffuse guide table: the chart centre
+     // ((tx + 1/2)/R, (ty + 1/2)/R) of each texel on the lowest-index static
+     // Lambertian triangle of its texture whose chart triangle holds it
+     // (barycentrics >= -1e-9); position by barycentric blend, unit normal
+     // of (v1 - v0) x (v2 - v0); normal 0 where no triangle holds it
+    const int R = s->tex_res;
+    const size_t T = (size_t)s->n_tex * R * R;
+    std::vector<float> tcx(T * 3, 0.f), tcn(T * 3, 0.f);
+    std::vector<char> done(T, 0);
+    for (int t = 0; t < n_static; ++t) {
+      const int m = s->tri_mat[t];
+      if (s->mat_type[m] != LT_MAT_LAMBERT) continue;
+      const int tex = s->mat_tex[m];
+      const double* uv = s->tri_uv + (size_t)t * 6;
+      const double* v = s->tri_v + (size_t)t * 9;
+      const double a0 = uv[2] - uv[0], a1 = uv[3] - uv[1], b0 = uv[4] - uv[0], b1 = uv[5] - uv[1];
+      const double det = a0 * b1 - a1 * b0;
+      if (!(std::fabs(det) > 0.0)) continue;
+      double e1[3], e2[3], nr[3];
+      for (int q = 0; q < 3; ++q) { e1[q] = v[3 + q] - v[q]; e2[q] = v[6 + q] - v[q]; }
+      nr[0] = e1[1] * e2[2] - e1[2] * e2[1]; nr[1] = e1[2] * e2[0] - e1[0] * e2[2]; nr[2] = e1[0] * e2[1] - e1[1] * e2[0];
+      const double nl = std::sqrt(nr[0] * nr[0] + nr[1] * nr[1] + nr[2] * nr[2]);
+      if (!(nl > 0.0)) continue;
+      for (int ty = 0; ty < R; ++ty)
+        for (int tx = 0; tx < R; ++tx) {
+          const size_t k = ((size_t)tex * R + ty) * R + tx;
+          if (done[k]) continue;
+          const double px = (tx + 0.5) / R - uv[0], py = (ty + 0.5) / R - uv[1];
+          const double w1 = (px * b1 - py * b0) / det, w2 = (a0 * py - a1 * px) / det, w0 = 1.0 - w1 - w2;
+          if (w0 < -1e-9 || w1 < -1e-9 || w2 < -1e-9) continue;
+          for (int q = 0; q < 3; ++q) {
+            tcx[k * 3 + q] = (float)(w0 * v[q] + w1 * v[3 + q] + w2 * v[6 + q]);
+            tcn[k * 3 + q] = (float)(nr[q] / nl);
+          }
+          done[k] = 1;
+        }
+    }
+    hipError_t e2 = upload(&c->d_tcx, tcx.data(), tcx.size());
+    if (e2 == hipSuccess) e2 = upload(&c->d_tcn, tcn.data(), tcn.size());
+    if (e2 != hipSuccess) { c->free_scene(); return c->hip(e2, "texel centre upload"); }
+  }
   // camera frame: f = normalize(target - pos), r = normalize(f x up), u = r x f
   double f[3], r[3], u[3];
   for (int a = 0; a < 3; ++a) f[a] = s->cam_target[a] - s->cam_pos[a];
@@ -763,6 +829,8 @@ size_t lt_side_state_bytes(const lt_ctx* c, const lt_trace_args* a) {
 size_t lt_workspace_bytes(const lt_ctx* c, const lt_trace_args* a) {
   if (!c) return 0;
   size_t guide = guide_packed_bytes() + (a && a->n_paths > 0 ? (size_t)a->n_paths * sizeof(float4) : 0);
+  if (a && (a->flags & LT_GUIDE_DIFFUSE))
+    guide += 2 * (size_t)c->dsc.n_tex * c->dsc.tex_res * c->dsc.tex_res * kGTabF4 * sizeof(float4);
   return c->scene_bytes + 512 + guide + (a ? hand_bytes(c, a) : 0);
 }
 
@@ -791,7 +859,10 @@ lt_status lt_trace(lt_ctx* c, const lt_trace_args* a, const lt_params* p, float*
     }
     if (a->flags & LT_RECORD_RESERVOIR) A.res_att = (ResRecAtt*)(sb + L.res);
   } else {
-    if (a->flags & LT_RECORD_TAPE) { A.tape = (TapeRec*)(sb + L.tape); A.tape_len = (int32_t*)(sb + L.len); }
+    if (a->flags & LT_RECORD_TAPE) {
+      A.tape = (TapeRec*)(sb + L.tape); A.tape_len = (int32_t*)(sb + L.len);
+      if (L.gw) A.tape_gw = (float*)(sb + L.gw);
+    }
     if (a->flags & LT_RECORD_RESERVOIR) A.res = (ResRec*)(sb + L.res);
     if (a->flags & LT_RECORD_SPLATS) { A.spl_hdr = (SplatHdr*)(sb + L.spl_hdr); A.spl = (SplatRec*)(sb + L.spl); }
   }
@@ -875,6 +946,7 @@ lt_status lt_backward_naive(lt_ctx* c, const lt_trace_args* a, const lt_params* 
   A.contrib = a->path_contrib;
   A.tape_in = (const TapeRec*)(sb + L.tape);
   A.tape_len_in = (const int32_t*)(sb + L.len);
+  if (L.gw) A.tape_gw_in = (const float*)(sb + L.gw);
   int grid = (int)std::max<int64_t>(1, std::min<int64_t>((a->n_paths + 255) / 256, (int64_t)c->n_cu * 16));
   if (a->flags & LT_ATTACHED) {
     A.emit_d = (float*)(sb + L.emit);
@@ -1038,6 +1110,24 @@ lt_status lt_guide_emit(lt_ctx* c, const lt_trace_args* a, const lt_params* p, c
   G.samples = reinterpret_cast<float*>(out);
   G.contrib = path_contrib;
   return c->hip(launch_guide_emit(G, guide_grid(c, a->n_paths), c->stream), "guide emit");
+}
+
+lt_status lt_guide_vertex_samples(lt_ctx* c, const lt_trace_args* a, const lt_params* p, lt_guide_sample* out) {
+  lt_status st = check_args(c, a, p);
+  if (st != LT_OK) return st;
+  if (!out || !p->guide_w) return c->fail(LT_ERR_ARG, "bad diffuse guide sample arguments%s");
+  if (a->flags & (LT_ATTACHED | LT_RECORD_TAPE | LT_RECORD_RESERVOIR | LT_RECORD_SPLATS | LT_SPLAT_SELECTED))
+    return c->fail(LT_ERR_ARG, "diffuse guide samples take a plain detached pass (flags LT_GUIDE_DIFFUSE only)%s");
+  lt_trace_args e = *a;
+  e.flags = LT_GUIDE_DIFFUSE;
+  if ((st = check_cap(c, guide_bytes(&e, p))) != LT_OK) return st;
+  if ((st = prepare_geometry(c, p)) != LT_OK) return st;
+  PassArgs A = base_args(c, &e, p);
+  A.gsamp = reinterpret_cast<float*>(out);
+  if ((st = guide_prepass(c, &e, p, A)) != LT_OK) return st;
+  if ((st = c->hip(launch_fill_u32(c->d_counter, 1, 0u, c->stream), "counter clear")) != LT_OK) return st;
+  int grid = persistent_grid(c, a->n_paths, c->tune.block);
+  return c->hip(launch_trace_gsamples(A, grid, c->tune.block, c->stream), "diffuse guide samples");
 }
 
 lt_status lt_guide_grad(lt_ctx* c, const float* guide_w, const lt_guide_sample* samples, int64_t count,

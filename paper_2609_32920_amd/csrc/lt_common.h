@@ -118,6 +118,9 @@ struct alignas(16) Lrb3HandAtt {
 };
 static_assert(sizeof(Lrb3HandAtt) == 64, "attached hand-off layout");
 
+// float4 slots of one diffuse guide-table entry (8 lobes x 2)
+constexpr int kGTabF4 = 16;
+
 struct DevScene {
   const Node* nodes;
   const Tri* tris;

@@ -79,6 +79,75 @@ __device__ __forceinline__ f3 cosine_dir(f3 n, float u0, float u1) {
   return t1 * (r * c) + t2 * (r * s) + n * lz;
 }
 
+// von Mises-Fisher direction about the unit mean mu (concentration kap,
+// em = 1 - e^{-2 kap}) from (g1, g2): the cosine t to mu by inverting its
+// marginal (Wood 1994; Jakob 2012), 1 - t = -log(1 - g1 em) / kap, and
+// sin^2 = (1 - t)(1 + t), so there is no cancellation near the mean.
+__device__ __forceinline__ f3 vmf_dir(f3 mu, float kap, float em, float g1, float g2) {
+  float u = -log1pf(-g1 * em) / kap;
+  u = fminf(fmaxf(u, 0.0f), 2.0f);
+  float t = 1.0f - u;
+  float s = sqrtf(u * (2.0f - u));
+  float sp = sinpif(2.0f * g2), cp = cospif(2.0f * g2);
+  f3 t1, t2; onb(mu, t1, t2);
+  return mu * t + t1 * (s * cp) + t2 * (s * sp);
+}
+
+// ------------------------------------------------------------ diffuse guide
+// A guide-table entry: the folded vMF mixture of the learned guide at one
+// side of one albedo texel, 16 float4.  Lobe k: [2k] = (mean direction,
+// kappa), [2k+1] = (mixture weight, vMF normaliser kappa / (2 pi em),
+// em = 1 - e^{-2 kappa}, the mixing weight alpha for k = 0).  alpha < 0
+// marks an entry without a guide: the vertex samples the cosine density.
+// Density about the unit arrival-side normal n:
+//   q(w) = alpha sum_k pi_k [v_k(w) + v_k(mirror(w))] + (1 - alpha) max(w.n, 0) / pi.
+constexpr int kGTabLobes = 8;
+
+__device__ __forceinline__ float gtab_pdf(const float4* e, f3 n, f3 w) {
+  float c = dot(w, n);
+  if (c < 0.f) return 0.f;
+  f3 wm = w - n * (2.0f * c);
+  float V = 0.f;
+#pragma unroll
+  for (int k = 0; k < kGTabLobes; ++k) {
+    float4 a = e[2 * k], b = e[2 * k + 1];
+    f3 mu = {a.x, a.y, a.z};
+    V += b.x * b.y * (expf(a.w * (dot(mu, w) - 1.0f)) + expf(a.w * (dot(mu, wm) - 1.0f)));
+  }
+  float al = e[1].w;
+  return al * V + (1.0f - al) * c * 0.318309886183790672f;
+}
+
+// Draw from entry e about n: the component by g0 (cosine when g0 >= alpha,
+// else the lobe whose cumulative weight first exceeds g0 / alpha), the
+// direction by (g1, g2), a lobe direction below the surface mirrored
+// about it.  Returns the direction, its density q and the component
+// (0 cosine, k + 1 lobe k).
+__device__ __forceinline__ f3 gtab_sample(const float4* e, f3 n, float g0, float g1, float g2, float& q,
+                                           int& comp) {
+  const float al = e[1].w;
+  f3 w;
+  comp = 0;
+  if (g0 >= al) {
+    w = cosine_dir(n, g1, g2);
+  } else {
+    float v = g0 / al, acc = 0.f;
+    int k = kGTabLobes - 1;
+#pragma unroll
+    for (int i = 0; i < kGTabLobes; ++i) {
+      acc += e[2 * i + 1].x;
+      if (v < acc) { k = i; break; }
+    }
+    comp = k + 1;
+    float4 a = e[2 * k], b = e[2 * k + 1];
+    w = vmf_dir(mk(a.x, a.y, a.z), a.w, b.z, g1, g2);
+    float c = dot(w, n);
+    if (c < 0.f) w = w - n * (2.0f * c);
+  }
+  q = gtab_pdf(e, n, w);
+  return w;
+}
+
 // ------------------------------------------------------------ BVH traversal
 struct Hit { int tri; float t; };
 

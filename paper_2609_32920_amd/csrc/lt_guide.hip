@@ -304,14 +304,8 @@ __device__ __forceinline__ f3 mix_sample(const GMix& m, f3 n, float g0, float g1
   for (int i = 1; i < kGLobes; ++i)
     if (i == k) { mu = m.mu[i]; kap = m.kap[i]; }
   // 1 - t = -log(xi + (1 - xi) e^{-2 kappa}) / kappa = -log1p(-g1 (1 - e^{-2 kappa})) / kappa
-  // (1 - xi = g1 exactly), and sin^2 = (1 - t)(1 + t): no cancellation near the mean
-  float u = -log1pf(-g1 * -expm1f(-2.0f * kap)) / kap;
-  u = fminf(fmaxf(u, 0.0f), 2.0f);
-  float t = 1.0f - u;
-  float s = sqrtf(u * (2.0f - u));
-  float sp = sinpif(2.0f * g2), cp = cospif(2.0f * g2);
-  f3 t1, t2; onb(mu, t1, t2);
-  f3 w = mu * t + t1 * (s * cp) + t2 * (s * sp);
+  // (1 - xi = g1 exactly)
+  f3 w = vmf_dir(mu, kap, -expm1f(-2.0f * kap), g1, g2);
   if (dot(w, n) < 0.f) w = mirror(w, n);
   return w;
 }
@@ -376,6 +370,46 @@ __global__ void __launch_bounds__(256) k_guide_eval(GuideArgs G) {
     outputs_to_lane(F, stage, o);
     if (valid)
       for (int k = 0; k < kGOut; ++k) G.out[item * kGOut + k] = o[k];
+  }
+}
+
+// Guide table of the Lambertian texels: item i = 2 texel + side evaluates
+// the network at the texel centre x[texel] with normal +n[texel] (side 0)
+// or -n[texel] (side 1) and stores the folded mixture as a 16-float4 entry
+// (layout of gtab_sample); a texel with n = 0 (no covering triangle) gets
+// alpha = -1 (cosine sampling).
+__global__ void __launch_bounds__(256) k_guide_table(GuideArgs G) {
+  extern __shared__ u32x4 gl_lds[];
+  for (int i = threadIdx.x; i < kPFwd; i += blockDim.x) gl_lds[i] = G.packed[i];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = __lane_id();
+  float* stage = reinterpret_cast<float*>(gl_lds + kPFwd) + wave * 64 * kStage;
+  const int64_t n_tiles = (G.count + 63) / 64;
+  for (int64_t base = (int64_t)blockIdx.x * 4; base < n_tiles; base += (int64_t)gridDim.x * 4) {
+    int64_t item = (base + wave) * 64 + lane;
+    bool valid = item < G.count;
+    int64_t it = valid ? item : G.count - 1, tx = it >> 1;
+    f3 x = ld3(G.x + tx * 3), n = ld3(G.n + tx * 3);
+    if (it & 1) n = n * -1.0f;
+    float f[kGIn];
+    features(G.sc, x, n, f);
+    Fwd F;
+    mlp_forward<false>(gl_lds, G.w, f, F, nullptr, nullptr, nullptr, nullptr);
+    float o[kGOut];
+    outputs_to_lane(F, stage, o);
+    if (!valid) continue;
+    float4* e = G.table + item * kGTabF4;
+    if (dot(n, n) == 0.f) {
+      for (int k = 0; k < kGTabF4; ++k) e[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      e[1].w = -1.0f;
+      continue;
+    }
+    GMix m = mixture_of(o);
+    for (int k = 0; k < kGLobes; ++k) {
+      float kap = m.kap[k], em = -expm1f(-2.0f * kap);
+      e[2 * k] = make_float4(m.mu[k].x, m.mu[k].y, m.mu[k].z, kap);
+      e[2 * k + 1] = make_float4(m.pi[k], kap / (2.0f * kPiF * em), em, k == 0 ? m.alpha : 0.f);
+    }
   }
 }
 
@@ -661,6 +695,8 @@ hipError_t guide_init() {
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_guide_eval, hipFuncAttributeMaxDynamicSharedMemorySize, (int)emit_lds());
   if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_guide_table, hipFuncAttributeMaxDynamicSharedMemorySize, (int)emit_lds());
+  if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_guide_grad, hipFuncAttributeMaxDynamicSharedMemorySize, (int)grad_lds());
   return e;
 }
@@ -671,6 +707,10 @@ hipError_t launch_guide_pack(const float* w, void* packed, hipStream_t s) {
 }
 hipError_t launch_guide_eval(const GuideArgs& G, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_guide_eval, dim3(grid), dim3(256), emit_lds(), s, G);
+  return hipGetLastError();
+}
+hipError_t launch_guide_table(const GuideArgs& G, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_guide_table, dim3(grid), dim3(256), emit_lds(), s, G);
   return hipGetLastError();
 }
 hipError_t launch_guide_emit(const GuideArgs& G, int grid, hipStream_t s) {

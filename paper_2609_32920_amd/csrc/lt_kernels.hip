@@ -36,6 +36,9 @@ struct Event {
   float u_res;     // reservoir uniform of this vertex
   int slot;        // hit triangle in BVH order
   f3 x;            // hit point
+  float gw, gq;    // Lambertian scatter weight over rho (cos / (pi q) when guided, else 1)
+                   // and the guided density q (0: cosine sampling)
+  int gcomp;       // guided component (0 cosine, k + 1 lobe k)
   bool illc;       // ill-conditioned vertex for attached derivatives (grazing hit,
                    // refraction near the critical angle, short segment, or a
                    // connection next to a tent-filter kink)
@@ -54,7 +57,7 @@ __device__ __forceinline__ Event bounce(const PassArgs& A, uint32_t path, int j,
   Event ev;
   ev.prim = -1; ev.kind = 0; ev.texel = -1; ev.rho = {0.f, 0.f, 0.f}; ev.valid = false;
   ev.ux = ev.uy = ev.g = 0.f; ev.lobe = 0; ev.fail = 0; ev.cont = false; ev.u_res = 1.0f; ev.cos_in = 0.f;
-  ev.slot = -1; ev.x = {0.f, 0.f, 0.f}; ev.illc = false;
+  ev.slot = -1; ev.x = {0.f, 0.f, 0.f}; ev.illc = false; ev.gw = 1.0f; ev.gq = 0.f; ev.gcomp = 0;
   Hit h = closest_hit(sc, ray_origin(r), r.w, kTmin, 3.0e38f, stk, ss);
   if (h.tri < 0) return ev;
   Surf s = surface(sc, h.tri, r);
@@ -81,7 +84,22 @@ __device__ __forceinline__ Event bounce(const PassArgs& A, uint32_t path, int j,
     if (ev.valid && (near_kink(ev.ux) || near_kink(ev.uy))) ev.illc = true;
     if (j < A.D) {
       f3 na = ev.cos_in < 0.0f ? s.ng : s.ng * -1.0f;
-      r.w = cosine_dir(na, u.u0, u.u1);
+      const float4* ge = A.gtab ? A.gtab + (size_t)(2 * ev.texel + (ev.cos_in < 0.0f ? 0 : 1)) * kGTabF4 : nullptr;
+      if (ge && ge[1].w >= 0.f) {
+        // guided scatter (component by u2, direction by u0, u1), weight
+        // f cos / q = rho cos / (pi q) with q held fixed
+        float q;
+        int comp;
+        f3 w = gtab_sample(ge, na, u.u2, u.u0, u.u1, q, comp);
+        ev.gcomp = comp;
+        float c = dot(w, na);
+        if (!(q > 0.f && c > 0.f)) return ev;
+        ev.gw = c / (3.14159265358979323846f * q);
+        ev.gq = q;
+        r.w = w;
+      } else {
+        r.w = cosine_dir(na, u.u0, u.u1);
+      }
       r.x = s.x; r.offn = s.ng; r.off = true;
       ev.cont = true;
     }
@@ -299,9 +317,12 @@ __device__ __forceinline__ float luminance(f3 c) { return 0.2126f * c.x + 0.7152
 // weighted reservoir (Eq. 8) and records/splats the selection (Eq. 9).
 // TAPE: writes the per-vertex naive-AD tape.  SPL: writes the buffered
 // two-pass splat records (u_i, C_i of every valid connection, a per-path
-// header).  Each loop iteration advances every live lane by one vertex; the
-// splat is issued cooperatively by the whole wave after the step.
-template <bool TAPE, bool RESV, bool SPL = false>
+// header).  GS: writes each path's diffuse-guide training sample (its first
+// guided Lambertian scatter: position, arrival-side normal, direction,
+// density, S = sum of lum(C_i) over the later connections, component).
+// Each loop iteration advances every live lane by one vertex; the splat is
+// issued cooperatively by the whole wave after the step.
+template <bool TAPE, bool RESV, bool SPL = false, bool GS = false>
 __device__ __forceinline__ void trace_run(const PassArgs& A, int* lds) {
   int* stk = lds + threadIdx.x;
   const int ss = blockDim.x;
@@ -320,8 +341,12 @@ __device__ __forceinline__ void trace_run(const PassArgs& A, int* lds) {
   f3 Le = ld3(A.Le);
   D3R iLe = {0.0, 0.0, 0.0};
   int etex = -1;
+  float gs[12];  // GS: the sample being built (gs[10] accumulates S)
+  bool gs_on = false;
   while (true) {
     refill(A, alive, exhausted, path, [&](uint32_t p) {
+      if (GS)
+        for (int q = 0; q < 12; ++q) A.gsamp[(size_t)p * 12 + q] = 0.f;
       if (SPL) { SplatHdr z{}; A.spl_hdr[p] = z; }
       if (TAPE) A.tape_len[p] = 0;
       if (RESV && A.res) { ResRec z{}; A.res[p] = z; }
@@ -340,11 +365,17 @@ __device__ __forceinline__ void trace_run(const PassArgs& A, int* lds) {
         j = 1; nrec = 0; sig = 0x811C9DC5u;
         Om = 0.f; omR = 0.f; R = 0; Sl = 0.f;
         klast = 0; vmask = 0ull;
+        if (GS) {
+          gs_on = false;
+#pragma unroll
+          for (int q = 0; q < 12; ++q) gs[q] = 0.f;
+        }
       }
       Event ev = bounce(A, path, j, r, 1, stk, ss);
       if (A.sig) sig = sig_event(sig, ev);
       if (ev.kind == 1 && ev.valid) {
         f3 C = mul(beta, ev.rho) * ev.g;
+        if (GS && gs_on) gs[10] += luminance(C);
         if (SPL) {
           SplatRec* o = A.spl + (size_t)(j - 1) * (size_t)A.n_paths + path;
           o->ux = ev.ux; o->uy = ev.uy; o->C[0] = C.x; o->C[1] = C.y; o->C[2] = C.z;
@@ -369,13 +400,24 @@ __device__ __forceinline__ void trace_run(const PassArgs& A, int* lds) {
         t.g = ev.g; t.ux = ev.ux; t.uy = ev.uy;
         t.b[0] = beta.x; t.b[1] = beta.y; t.b[2] = beta.z; t.pad = fac;
         A.tape[(size_t)(j - 1) * (size_t)A.n_paths + path] = t;
+        if (A.tape_gw) A.tape_gw[(size_t)(j - 1) * (size_t)A.n_paths + path] = ev.gw;
         LT_COUNT(8, 1);
         ++nrec;
       }
-      if (ev.kind == 1 && ev.cont) beta = mul(beta, ev.rho);
+      if (ev.kind == 1 && ev.cont) beta = mul(beta, ev.rho) * ev.gw;
+      if (GS && !gs_on && ev.kind == 1 && ev.cont && ev.gq > 0.f) {
+        f3 na = ev.cos_in < 0.0f ? r.offn : r.offn * -1.0f;
+        gs[0] = ev.x.x; gs[1] = ev.x.y; gs[2] = ev.x.z;
+        gs[3] = na.x; gs[4] = na.y; gs[5] = na.z;
+        gs[6] = r.w.x; gs[7] = r.w.y; gs[8] = r.w.z;
+        gs[9] = ev.gq; gs[11] = (float)ev.gcomp;
+        gs_on = true;
+      }
       if (ev.cont) {
         ++j;
       } else {  // path finished
+        if (GS)
+          for (int q = 0; q < 12; ++q) A.gsamp[(size_t)path * 12 + q] = gs[q];
         float W = R > 0 ? Om / omR : 0.f;
         if (RESV && selected && R > 0) { has = true; sux = uxR; suy = uyR; sC = CR * W; }
         if (RESV && A.res) {
@@ -395,23 +437,26 @@ __device__ __forceinline__ void trace_run(const PassArgs& A, int* lds) {
         alive = false; j = 0;
       }
     }
-    keep_finite(A, has, sC);
-    splat_wave(A.sc, A.image, has, sux, suy, sC);
+    if (!GS) {  // the sample pass writes no image
+      keep_finite(A, has, sC);
+      splat_wave(A.sc, A.image, has, sux, suy, sC);
+    }
   }
 }
 
 // At most 96 VGPRs (five waves per SIMD, with the default 10 x 128-thread
 // workgroups per CU): a few registers spill and the caustic forward runs 5%
 // faster than at four waves; the box forward is unchanged.
-template <bool TAPE, bool RESV, bool SPL = false>
+template <bool TAPE, bool RESV, bool SPL = false, bool GS = false>
 __global__ void __launch_bounds__(1024, 5) k_trace(PassArgs A) {
   extern __shared__ int lds[];
-  trace_run<TAPE, RESV, SPL>(A, lds);
+  trace_run<TAPE, RESV, SPL, GS>(A, lds);
 }
 
 // ---------------------------------------------------------------- naive AD
 // Reverse sweep over the tape, exact chain rule (no inverses, no division):
-//   C_j = beta_j rho_j g_j,  beta_{j+1} = beta_j rho_j (Lambertian scatter),
+//   C_j = beta_j rho_j g_j,  beta_{j+1} = beta_j rho_j s_j (Lambertian scatter,
+//   s_j = 1, or cos / (pi q) from the tape's weight array when guided),
 //   beta_1 = L_e * f, with the path's emission factor f taped in every record.
 // Lanes of a wave walk their tapes in lock step so that the texel
 // gradients are scattered cooperatively.
@@ -451,8 +496,9 @@ __global__ void __launch_bounds__(256) k_naive_bwd(PassArgs A) {
             bj = mul(Lb, rho) * t.g;
           }
           if (t.tf & kTfScatter) {
-            gr = gr + mul(bb, b);
-            bj = bj + mul(bb, rho);
+            const float sw = A.tape_gw_in ? A.tape_gw_in[(size_t)(j - 1) * N + path] : 1.0f;
+            gr = gr + mul(bb, b) * sw;
+            bj = bj + mul(bb, rho) * sw;
           }
           bb = bj;
           has = true;
@@ -596,7 +642,7 @@ __device__ __forceinline__ void lrb3_run(const PassArgs& A, int* lds) {
                 ev.rho.z > 0.f ? (float)g2 / ev.rho.z : 0.f};
           has = true;
         }
-        if (ev.cont) beta = mul(beta, ev.rho);
+        if (ev.cont) beta = mul(beta, ev.rho) * ev.gw;
       }
       if (ev.cont) {
         ++j;
@@ -771,7 +817,7 @@ __device__ __forceinline__ void lrb3_p2_run(const PassArgs& A, int* lds) {
           d0 += (double)Lb.x * C.x; d1 += (double)Lb.y * C.y; d2 += (double)Lb.z * C.z;
           vmask |= 1ull << (j - 1); klast = j;
         }
-        if (ev.cont) beta = mul(beta, ev.rho);
+        if (ev.cont) beta = mul(beta, ev.rho) * ev.gw;
       }
       if (ev.cont) {
         ++j;
@@ -844,7 +890,7 @@ __device__ __forceinline__ void lrb3_p3_run(const PassArgs& A, int* lds) {
         gv = {ev.rho.x > 0.f ? (float)g0 / ev.rho.x : 0.f, ev.rho.y > 0.f ? (float)g1 / ev.rho.y : 0.f,
               ev.rho.z > 0.f ? (float)g2 / ev.rho.z : 0.f};
         has = true;
-        if (ev.cont) beta = mul(beta, ev.rho);
+        if (ev.cont) beta = mul(beta, ev.rho) * ev.gw;
       }
       if (ev.cont) ++j;
       else { alive = false; j = 0; }
@@ -1167,6 +1213,10 @@ hipError_t launch_trace_splats(const PassArgs& A, bool resv, int grid, int block
   size_t sh = stack_bytes(A, block);
   if (resv) hipLaunchKernelGGL((k_trace<false, true, true>), dim3(grid), dim3(block), sh, s, A);
   else hipLaunchKernelGGL((k_trace<false, false, true>), dim3(grid), dim3(block), sh, s, A);
+  return hipGetLastError();
+}
+hipError_t launch_trace_gsamples(const PassArgs& A, int grid, int block, hipStream_t s) {
+  hipLaunchKernelGGL((k_trace<false, false, false, true>), dim3(grid), dim3(block), stack_bytes(A, block), s, A);
   return hipGetLastError();
 }
 hipError_t launch_lrb2_bwd(const PassArgs& A, int grid, int block, hipStream_t s) {

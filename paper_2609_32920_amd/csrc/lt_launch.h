@@ -46,6 +46,10 @@ struct PassArgs {
   int32_t hgrad_lds;          // heights gradients accumulated per workgroup in LDS
   int32_t agrad_lds;          // albedo gradients accumulated per workgroup in LDS
   const float4* guide_rec;    // guided emission (direction, density) per path, or null
+  const float4* gtab;         // diffuse guide table [2 n_texels][16], or null (cosine scatter)
+  float* tape_gw;             // naive tape with a diffuse guide: scatter weight [D][n_paths]
+  const float* tape_gw_in;
+  float* gsamp;               // diffuse guide training samples [n_paths][12], or null
   float* contrib;             // per-path image contribution sum_i lum(C_i), or null
   // LRB-3 as two kernels: pass 2 appends a hand-off entry per connected path,
   // pass 3 replays the queued paths
@@ -76,6 +80,7 @@ struct GuideArgs {
   const float* n;
   float* out;                // eval outputs [count][41]
   float* partial;            // grad: [grid][11435] partial sums (gradient, loss, Z)
+  float4* table;             // table: [count][16] guide-table entries out
 };
 
 size_t guide_packed_bytes();
@@ -84,6 +89,8 @@ hipError_t guide_init();
 hipError_t launch_guide_pack(const float* w, void* packed, hipStream_t s);
 hipError_t launch_guide_eval(const GuideArgs& G, int grid, hipStream_t s);
 hipError_t launch_guide_emit(const GuideArgs& G, int grid, hipStream_t s);
+// diffuse guide table: count = 2 x texels, x / n the texel centres and normals
+hipError_t launch_guide_table(const GuideArgs& G, int grid, hipStream_t s);
 hipError_t launch_guide_grad(const GuideArgs& G, int grid, hipStream_t s);
 hipError_t launch_guide_reduce(const float* partial, int n_part, float* grad, float* loss, hipStream_t s);
 hipError_t launch_guide_adam(float* w, const float* grad, float* m, float* v, int n, float lr, float b1, float b2,
@@ -92,6 +99,8 @@ hipError_t launch_guide_adam(float* w, const float* grad, float* m, float* v, in
 hipError_t launch_trace(const PassArgs& A, bool tape, bool resv, int grid, int block, hipStream_t s);
 // forward that also writes the buffered two-pass splat records
 hipError_t launch_trace_splats(const PassArgs& A, bool resv, int grid, int block, hipStream_t s);
+// forward that also writes each path's diffuse-guide training sample (A.gsamp)
+hipError_t launch_trace_gsamples(const PassArgs& A, int grid, int block, hipStream_t s);
 // buffered two-pass backward: delta_total from the records, one replay
 hipError_t launch_lrb2_bwd(const PassArgs& A, int grid, int block, hipStream_t s);
 // batches: `table` is a DEVICE array of n PassArgs; stack_n the largest

@@ -8,7 +8,7 @@ fallback.
 The functions carry the C ABI's names (include/lt.h):
   lt_create / lt_scene_upload / lt_trace / lt_loss_l2 /
   lt_backward_naive / lt_backward_reslrb / lt_backward_lrb3 / lt_backward_lrb2 /
-  lt_guide_eval / lt_guide_emit / lt_guide_grad / lt_guide_adam /
+  lt_guide_eval / lt_guide_emit / lt_guide_vertex_samples / lt_guide_grad / lt_guide_adam /
   lt_guide_train_step /
   lt_batch_create / lt_batch_step / lt_batch_autotune
 and ``LightTrace`` wraps forward + a chosen reverse mode as a
@@ -29,6 +29,7 @@ COUNTERS_LIB_PATH = os.path.join(_HERE, "liblt_counters.so")
 
 LT_OK, LT_ERR_ARG, LT_ERR_OOM, LT_ERR_HIP, LT_ERR_STATE, LT_ERR_UNSUPPORTED = range(6)
 ATTACHED, SPLAT_SELECTED, RECORD_TAPE, RECORD_RESERVOIR, CONTRIB_ADJOINT, RECORD_SPLATS = 1, 2, 4, 8, 16, 32
+GUIDE_DIFFUSE = 64
 _STATUS = {1: "LT_ERR_ARG", 2: "LT_ERR_OOM", 3: "LT_ERR_HIP", 4: "LT_ERR_STATE", 5: "LT_ERR_UNSUPPORTED"}
 
 
@@ -124,6 +125,7 @@ def library(path=LIB_PATH):
                                          C.c_int),
             "lt_guide_eval": ([vp, vp, vp, vp, C.c_int64, vp], C.c_int),
             "lt_guide_emit": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp, vp], C.c_int),
+            "lt_guide_vertex_samples": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp], C.c_int),
             "lt_guide_grad": ([vp, vp, vp, C.c_int64, vp, vp], C.c_int),
             "lt_guide_adam": ([vp, vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float], C.c_int),
             "lt_guide_train_step": ([vp, C.POINTER(TraceArgs), vp, vp, vp, C.c_int64, vp, vp, vp, vp, C.c_int32,
@@ -149,7 +151,7 @@ def exported_symbols():
             "lt_set_memory_cap", "lt_get_stats", "lt_read_counters", "lt_scene_upload", "lt_side_state_bytes",
             "lt_workspace_bytes", "lt_trace", "lt_loss_l2", "lt_backward_naive", "lt_backward_reslrb",
             "lt_backward_lrb3", "lt_backward_lrb2", "lt_backward_lrb3_noalloc", "lt_guide_eval", "lt_guide_emit", "lt_guide_grad", "lt_guide_adam",
-            "lt_guide_train_step",
+            "lt_guide_train_step", "lt_guide_vertex_samples",
             "lt_batch_create", "lt_batch_destroy", "lt_batch_last_error", "lt_batch_step", "lt_batch_set_tuning",
             "lt_batch_get_tuning", "lt_batch_autotune"]
 
@@ -381,6 +383,12 @@ class Context:
         self._stream()
         self._status(self.lib.lt_guide_emit(self.h, C.byref(a), C.byref(p), _ptr(contrib), _ptr(samples)))
 
+    def guide_vertex_samples(self, a, p, samples):
+        """Diffuse-guide training samples [n_paths, 12]: each path's first
+        guided Lambertian scatter with the luminance of its later connections."""
+        self._stream()
+        self._status(self.lib.lt_guide_vertex_samples(self.h, C.byref(a), C.byref(p), _ptr(samples)))
+
     def guide_grad(self, guide_w, samples, grad, loss=None):
         """Training loss and gradient over samples [count, 12] (device float32)."""
         self._stream()
@@ -505,6 +513,10 @@ def lt_guide_eval(ctx, guide_w, x, n, out):
 
 def lt_guide_emit(ctx, args, params, samples, contrib=None):
     return ctx.guide_emit(args, params, samples, contrib)
+
+
+def lt_guide_vertex_samples(ctx, args, params, samples):
+    return ctx.guide_vertex_samples(args, params, samples)
 
 
 def lt_guide_grad(ctx, guide_w, samples, grad, loss=None):

@@ -28,10 +28,18 @@ class GpuRun:
         self.nmap = None if nm is None else torch.as_tensor(np.asarray(nm, np.float32), device=self.dev).contiguous()
         self.H, self.W = sc["camera"]["height"], sc["camera"]["width"]
         self.guide = None
+        self.gflags = 0
 
-    def set_guide(self, w):
-        """Guided emission with these weights (None: cosine emission)."""
+    def set_guide(self, w, diffuse=False):
+        """Guided emission with these weights (None: cosine emission); with
+        diffuse, Lambertian vertices are guided too (LT_GUIDE_DIFFUSE on
+        every pass)."""
         self.guide = None if w is None else torch.as_tensor(np.asarray(w, np.float32), device=self.dev).contiguous()
+        self.gflags = lt.GUIDE_DIFFUSE if (diffuse and w is not None) else 0
+
+    @property
+    def gdiff(self):
+        return self.gflags != 0
 
     def params(self):
         return self.ctx.params(self.albedo, self.Le, self.heights, self.guide, self.nmap)
@@ -49,7 +57,7 @@ class GpuRun:
         m = None
         if mask is not None:
             m = torch.as_tensor(np.asarray(mask, np.uint8), device=self.dev)
-        a = self.ctx.args(seed, n, depth, flags, m, sig)
+        a = self.ctx.args(seed, n, depth, flags | self.gflags, m, sig)
         p = self.params()
         nb = self.ctx.side_state_bytes(a)
         side = torch.zeros(max(nb, 1), dtype=torch.uint8, device=self.dev)
@@ -65,7 +73,7 @@ class GpuRun:
         m = None if mask is None else torch.as_tensor(np.asarray(mask, np.uint8), device=self.dev)
         rec = {"naive": lt.RECORD_TAPE, "reslrb": lt.RECORD_RESERVOIR, "lrb2": lt.RECORD_SPLATS}.get(mode, 0)
         info = torch.zeros(n, dtype=torch.int32, device=self.dev) if want_info else None
-        a = self.ctx.args(seed, n, depth, flags | rec, m, None, info)
+        a = self.ctx.args(seed, n, depth, flags | rec | self.gflags, m, None, info)
         p = self.params()
         dIt = torch.as_tensor(np.asarray(dI, np.float32), device=self.dev).contiguous()
         if side is None and mode != "lrb3":
@@ -95,16 +103,42 @@ class GpuRun:
         return out
 
 
-def matched_paths(sc, g, seed, n, depth, flags=0, keep=None, want_illc=False):
+def diffuse_table_flags(sc, g, rel=1e-5):
+    """Entries of the diffuse guide table whose network outputs differ on the
+    two sides beyond FP32 rounding (a bfloat16 rounding that flipped between
+    FP32 and FP64 accumulation): the GPU network evaluated at the oracle's
+    texel centres and sides against the oracle's table.  Returns bool [2T]."""
+    w = g.guide.cpu().numpy().astype(np.float64)
+    t = O.guide_table(sc, w)
+    x = np.repeat(t["x"], 2, axis=0)
+    nn = np.repeat(t["n"], 2, axis=0)
+    nn[1::2] *= -1.0
+    dev = lambda a: torch.as_tensor(a, dtype=torch.float32, device=g.dev).contiguous()
+    out = torch.zeros((x.shape[0], 41), dtype=torch.float32, device=g.dev)
+    g.ctx.guide_eval(g.guide, dev(x), dev(nn), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    ref = t["raw"]
+    err = np.abs(got - ref).max(axis=1) / np.maximum(np.abs(ref).max(axis=1), 1e-30)
+    flag = (err > rel) & np.repeat(t["ok"], 2)
+    return flag
+
+
+def matched_paths(sc, g, seed, n, depth, flags=0, keep=None, want_illc=False, gflag=None):
     """Per-path signatures from both sides; returns (mask, ids, mismatch fraction)
     and, with want_illc, the oracle's own per-path ill-conditioning flag
     (bool [n]: a grazing hit, short segment, near-critical refraction or a
     connection next to a tent kink at or before the last connection).
-    keep: optional boolean [n] pre-selection (e.g. matching guided emission)."""
+    keep: optional boolean [n] pre-selection (e.g. matching guided emission).
+    gflag: optional bool per diffuse guide-table entry: paths that scatter
+    from a marked entry are excluded too (see diffuse_table_flags)."""
     ow = None if g.guide is None else g.guide.cpu().numpy().astype(np.float64)
     gs = g.trace(seed, n, depth, flags, want_sig=True)["sig"]
-    r = O.render(sc, seed, n, depth, flags=flags, per_path=True, guide_w=ow)
+    r = O.render(sc, seed, n, depth, flags=flags, per_path=True, guide_w=ow, guide_diffuse=g.gdiff,
+                 guide_flag=gflag)
     same = gs == r["sig"]
+    if gflag is not None:
+        same &= ~r["gflag"]
     if keep is not None:
         same &= keep
     out = (same.astype(np.uint8), np.nonzero(same)[0].astype(np.uint32), 1.0 - same.mean())
@@ -122,7 +156,7 @@ def matched_sample(sc, g, seed, n, depth, ids, flags=0):
     mask[ids] = 1
     ow = None if g.guide is None else g.guide.cpu().numpy().astype(np.float64)
     gs = g.trace(seed, n, depth, flags, mask=mask, want_sig=True)["sig"][ids]
-    r = O.render(sc, seed, n, depth, flags=flags, path_list=ids, per_path=True, guide_w=ow)
+    r = O.render(sc, seed, n, depth, flags=flags, path_list=ids, per_path=True, guide_w=ow, guide_diffuse=g.gdiff)
     same = gs == r["sig"]
     if ow is not None:
         same &= guide_sample_match(sc, g, seed, n, ids)
