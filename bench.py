@@ -292,6 +292,11 @@ def main():
         batch = bench_batch(lt, scenes, dev, stream)
         batch_small = bench_batch(lt, scenes, dev, stream, path_scale=1.0 / 64, reps=4)
 
+    # ---- learned guide at diffuse vertices (detail-view box)
+    guide_diffuse = None
+    if not args.no_guide:
+        guide_diffuse = bench_guide_diffuse(lt, scenes, dev, stream)
+
     # ---- guided + batched against the plain GPU tracer
     guided_batch = None
     if not (args.no_batch or args.no_guide):
@@ -356,6 +361,7 @@ def main():
         "batch": batch,
         "batch_small_instances": batch_small,
         "guided_batch": guided_batch,
+        "guide_diffuse_detail_box": guide_diffuse,
     }
     print(json.dumps(out), flush=True)
 
@@ -619,6 +625,109 @@ def bench_guide(lt, scenes, dev, stream, G=256, film=1024, N=1 << 26, D=8, iters
     return out
 
 
+def _boot_ratio(g0, g1, stat, n=200, seed=12345):
+    """Bootstrap (both sides' seeds resampled) 5th-95th percentiles of
+    stat(var of g1) / stat(var of g0) over the per-seed gradients g [K, P]."""
+    import numpy as np
+    import torch
+    gen = torch.Generator(device=g0.device)
+    gen.manual_seed(seed)
+    K0, K1 = g0.shape[0], g1.shape[0]
+    out = []
+    for _ in range(n):
+        i0 = torch.randint(K0, (K0,), device=g0.device, generator=gen)
+        i1 = torch.randint(K1, (K1,), device=g0.device, generator=gen)
+        out.append(stat(g1[i1].var(0)) / max(stat(g0[i0].var(0)), 1e-300))
+    return [round(float(x), 4) for x in np.percentile(out, [5, 95])]
+
+
+def bench_guide_diffuse(lt, scenes, dev, stream, film=256, N=1 << 22, D=8, iters=40, K=24, n_train=1 << 18,
+                        lr=2e-3):
+    """Learned guide at diffuse vertices on the box seen through a narrow
+    window (film^2, depth D, N paths per iteration, detached LRB-3-pass
+    albedo gradients): cosine sampling against a guide trained online on
+    emission samples only (used at vertex 0) and one trained on emission plus
+    diffuse-vertex samples (used at vertex 0 and every Lambertian vertex).
+    Variance over K seeds (summed and median over texels, with bootstrap 90%
+    intervals of the ratios), time per backward, efficiency gain =
+    (variance x time) cosine / guided."""
+    import numpy as np
+    import torch
+
+    sc = scenes.box_detail_scene(width=film, height=film)
+    ctx = lt.Context(0).scene_upload(sc)
+    f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32), device=dev).contiguous()
+    alb, Le = f32(sc["albedo"]), f32(sc["Le"])
+    img = torch.empty((film, film, 3), dtype=torch.float32, device=dev)
+    T, dI, loss = torch.empty_like(img), torch.empty_like(img), torch.zeros(1, dtype=torch.float32, device=dev)
+    ctx.trace(ctx.args(1, 1 << 24, D), ctx.params(f32(sc["albedo_target"]), Le), T)
+    ctx.trace(ctx.args(2, 1 << 24, D), ctx.params(alb, Le), img)
+    ctx.loss_l2(img, T, dI, loss)
+    ga, gl = torch.zeros_like(alb), torch.zeros_like(Le)
+
+    def step(seed, w, flags, contrib=None):
+        ga.zero_(); gl.zero_()
+        ctx.backward_lrb3(ctx.args(seed, N, D, flags | lt.CONTRIB_ADJOINT, contrib=contrib),
+                          ctx.params(alb, Le, None, w), dI, ga, gl)
+
+    def estimate(w, flags):
+        step(69999, w, flags)
+        gs, ts = [], []
+        for k in range(K):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            step(70000 + k, w, flags)
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+            gs.append(ga.double().clone())
+        return torch.stack(gs), float(np.median(ts))
+
+    def train(diffuse):
+        w = f32(scenes.guide_weights())
+        m, v, g1, g2 = (torch.zeros_like(w) for _ in range(4))
+        contrib = torch.zeros(N, dtype=torch.float32, device=dev)
+        se = torch.zeros((n_train, 12), dtype=torch.float32, device=dev)
+        sd = torch.zeros_like(se)
+        flags = lt.GUIDE_DIFFUSE if diffuse else 0
+        for i in range(1, iters + 1):
+            step(60000 + i, w, flags, contrib)
+            p = ctx.params(alb, Le, None, w)
+            ctx.guide_emit(ctx.args(60000 + i, n_train, D), p, se, contrib)
+            ctx.guide_grad(w, se, g1, None)
+            if diffuse:
+                ctx.guide_vertex_samples(ctx.args(60000 + i, n_train, D, lt.GUIDE_DIFFUSE), p, sd)
+                ctx.guide_grad(w, sd, g2, None)
+                g1 += g2
+            ctx.guide_adam(w, g1, m, v, i, lr)
+        return w
+
+    g0, t0 = estimate(None, 0)
+    out = {"workload": f"diffuse box seen through a 12-degree window, film {film}x{film}, depth {D}, {N} paths, "
+                       f"detached LRB-3-pass albedo gradients over {K} seeds; guides trained online for {iters} "
+                       f"iterations on {n_train} samples of each kind",
+           "ms_per_backward_cosine": round(t0, 3)}
+    for name, diffuse in (("emission_only", False), ("emission_and_diffuse", True)):
+        w = train(diffuse)
+        g1, t1 = estimate(w, lt.GUIDE_DIFFUSE if diffuse else 0)
+        v0, v1 = g0.var(0), g1.var(0)
+        se = torch.sqrt(v0 / K + v1 / K)
+        ok = se > 0
+        z2 = ((g1.mean(0) - g0.mean(0))[ok] / se[ok]) ** 2
+        vr, mr = v1.sum().item() / v0.sum().item(), v1.median().item() / v0.median().item()
+        out[name] = {"ms_per_backward": round(t1, 3), "variance_ratio": round(vr, 4),
+                     "variance_ratio_bootstrap_90": _boot_ratio(g0, g1, lambda v: v.sum().item()),
+                     "median_texel_variance_ratio": round(mr, 4),
+                     "median_texel_ratio_bootstrap_90": _boot_ratio(g0, g1, lambda v: v.median().item()),
+                     "efficiency_gain": round(t0 / (vr * t1), 4), "robust_efficiency_gain": round(t0 / (mr * t1), 4),
+                     "bias_mean_z2": round(float(z2.mean().item()), 4)}
+        print(f"# diffuse guide ({name}): variance ratio {vr:.3f} {out[name]['variance_ratio_bootstrap_90']}, "
+              f"median-texel {mr:.3f} {out[name]['median_texel_ratio_bootstrap_90']}, {t0:.2f} -> {t1:.2f} ms, "
+              f"gain {out[name]['efficiency_gain']} (robust {out[name]['robust_efficiency_gain']}), "
+              f"z^2 {out[name]['bias_mean_z2']}", file=sys.stderr, flush=True)
+    return out
+
+
 def bench_inverse(lt, scenes, dev, stream, G=128, film=512, N=1 << 24, D=6, iters=200, lr=1e-4, log_every=20):
     """Heightfield inverse rendering: Adam on the slab's free heights (the
     boundary ring stays at zero) toward the image of the seeded sinusoid
@@ -761,7 +870,7 @@ def bench_batch(lt, scenes, dev, stream, n=48, seed=7, reps=2, path_scale=1.0):
     return out
 
 
-def bench_guided_batch(lt, scenes, dev, stream, n=12, seed=11, iters=50, K=16, n_train=1 << 18, lr=2e-3):
+def bench_guided_batch(lt, scenes, dev, stream, n=12, seed=11, iters=50, K=32, n_train=1 << 18, lr=2e-3):
     """Guided + batched against the plain GPU tracer.  n smooth-slab caustic
     instances (sizes and scenes from a seed) take optimisation steps
     (forward, L2 loss and image adjoint, attached LRB-3 backward).  Plain:
@@ -879,6 +988,30 @@ def bench_guided_batch(lt, scenes, dev, stream, n=12, seed=11, iters=50, K=16, n
     gm = lambda xs: float(np.exp(np.mean(np.log(np.asarray(xs)))))
     gain = gm([1.0 / r for r in ratios]) * t0 / t1
     rgain = gm([1.0 / r for r in robust]) * t0 / t1
+    # bootstrap over seeds (each instance's K seeds resampled on both sides):
+    # 90% intervals of both gains; the robust (median-coordinate) gain is the
+    # estimator fixed in advance for the conclusion
+    gen = torch.Generator(device=g0[0].device)
+    gen.manual_seed(12345)
+    bg, brg = [], []
+    for _ in range(200):
+        rr, rb = [], []
+        for a, c in zip(g0, g1):
+            i0 = torch.randint(K, (K,), device=a.device, generator=gen)
+            i1 = torch.randint(K, (K,), device=a.device, generator=gen)
+            v0, v1 = a[i0].var(0), c[i1].var(0)
+            rr.append(v1.sum().item() / max(v0.sum().item(), 1e-300))
+            rb.append(v1.median().item() / max(v0.median().item(), 1e-300))
+        bg.append(gm([1.0 / max(r, 1e-300) for r in rr]) * t0 / t1)
+        brg.append(gm([1.0 / max(r, 1e-300) for r in rb]) * t0 / t1)
+    gain_ci = [round(float(x), 3) for x in np.percentile(bg, [5, 95])]
+    rgain_ci = [round(float(x), 3) for x in np.percentile(brg, [5, 95])]
+    if rgain_ci[0] > 1.0:
+        verdict = "guided+batched beats the plain tracer at equal gradient error (robust gain interval above 1)"
+    elif rgain_ci[1] < 1.0:
+        verdict = "no gain: the plain tracer is more efficient (robust gain interval below 1)"
+    else:
+        verdict = "no resolved gain: the robust gain interval contains 1"
     total = sum(d["n_paths"] for d in insts)
     out = {"workload": f"{n} glass-slab caustic instances (heightfields 32^2..96^2, films 128^2..384^2, "
                        f"{min(d['n_paths'] for d in insts)}..{max(d['n_paths'] for d in insts)} paths, depth 6, "
@@ -890,10 +1023,13 @@ def bench_guided_batch(lt, scenes, dev, stream, n=12, seed=11, iters=50, K=16, n
            "variance_ratio_geomean": round(gm(ratios), 4), "median_coord_variance_ratio_geomean": round(gm(robust), 4),
            "variance_ratio_per_instance": [round(r, 3) for r in ratios],
            "efficiency_gain": round(gain, 3), "robust_efficiency_gain": round(rgain, 3),
+           "efficiency_gain_bootstrap_90": gain_ci, "robust_efficiency_gain_bootstrap_90": rgain_ci,
+           "conclusion": verdict,
            "bias_mean_z2": round(float(np.mean(z2)), 3)}
     print(f"# guided+batched ({n} slabs): plain {t0:.1f} ms/step, batched cosine {t_cos_batched:.1f}, "
           f"guided per-instance {t_guided_inst:.1f}, guided batched {t1:.1f}; variance ratio (geomean) "
-          f"{gm(ratios):.3f}, median-coordinate {gm(robust):.3f}; gain {gain:.2f}x (robust {rgain:.2f}x); "
+          f"{gm(ratios):.3f}, median-coordinate {gm(robust):.3f}; gain {gain:.2f}x {gain_ci} "
+          f"(robust {rgain:.2f}x {rgain_ci}: {verdict}); "
           f"bias z^2 {np.mean(z2):.3f}; training {train_s:.1f} s", file=sys.stderr, flush=True)
     return out
 

@@ -137,6 +137,17 @@ def box_scene(width=64, height=64, tex_res=16, seed=SCENE_SEED,
     )
 
 
+def box_detail_scene(width=128, height=128, tex_res=16, seed=SCENE_SEED, target_seed=TARGET_SEED, Le=10.0):
+    """The diffuse box seen through a narrow window: the same camera position
+    with a 12 degree vertical FOV aimed at (0.75, 0.3, 1.0), the lower right
+    of the back wall.  Most light vertices connect outside the film, so the
+    directions that reach the seen region carry the gradient: a scene where
+    guiding diffuse vertices pays."""
+    sc = box_scene(width, height, tex_res, seed, target_seed, Le)
+    sc["camera"] = dict(sc["camera"], fov_deg=12.0, target=np.array([0.75, 0.3, 1.0]))
+    return sc
+
+
 def caustic_scene(G=128, width=512, height=512, seed=SCENE_SEED, target_seed=TARGET_SEED,
                   Le=1000.0, ior=1.5, h_sigma=0.002):
     """Glass heightfield slab over a diffuse receiver (attached workload).

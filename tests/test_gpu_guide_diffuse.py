@@ -150,3 +150,69 @@ def test_diffuse_guide_flag_needs_weights(box):
     with pytest.raises(lt.LTError) as e:
         g.ctx.trace(a, g.params(), img, None)
     assert e.value.status == lt.LT_ERR_ARG
+
+
+def test_trained_diffuse_guide_gain():
+    """What guiding diffuse vertices gains: on the box seen through a narrow
+    window, a guide trained online on emission samples (|delta_total|
+    targets) and diffuse-vertex samples (luminance of the later connections)
+    lowers the detached LRB-3 albedo gradient's variance below cosine
+    sampling - summed and median over texels - more than the same training
+    without diffuse samples, and stays unbiased (mean z^2 ~ 1)."""
+    film, N, D, K = 128, 1 << 20, 8, 16
+    sc = scenes.box_detail_scene(width=film, height=film)
+    ctx = lt.Context(0).scene_upload(sc)
+    dev = torch.device("cuda", 0)
+    f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32), device=dev).contiguous()
+    alb, Le = f32(sc["albedo"]), f32(sc["Le"])
+    img = torch.empty((film, film, 3), device=dev)
+    T, dI, loss = torch.empty_like(img), torch.empty_like(img), torch.zeros(1, device=dev)
+    ctx.trace(ctx.args(1, 1 << 22, D), ctx.params(f32(sc["albedo_target"]), Le), T)
+    ctx.trace(ctx.args(2, 1 << 22, D), ctx.params(alb, Le), img)
+    ctx.loss_l2(img, T, dI, loss)
+    ga, gl = torch.zeros_like(alb), torch.zeros_like(Le)
+
+    def step(seed, w, flags, contrib=None):
+        ga.zero_(); gl.zero_()
+        ctx.backward_lrb3(ctx.args(seed, N, D, flags | lt.CONTRIB_ADJOINT, contrib=contrib),
+                          ctx.params(alb, Le, None, w), dI, ga, gl)
+
+    def estimate(w, flags):
+        gs = []
+        for k in range(K):
+            step(7000 + k, w, flags)
+            gs.append(ga.double().clone())
+        return torch.stack(gs)
+
+    def train(diffuse, iters=40, lr=2e-3, n_train=1 << 18):
+        w = f32(scenes.guide_weights())
+        m, v, g1, g2 = (torch.zeros_like(w) for _ in range(4))
+        contrib = torch.zeros(N, device=dev)
+        se, sd = torch.zeros((n_train, 12), device=dev), torch.zeros((n_train, 12), device=dev)
+        flags = lt.GUIDE_DIFFUSE if diffuse else 0
+        for i in range(1, iters + 1):
+            step(5000 + i, w, flags, contrib)
+            p = ctx.params(alb, Le, None, w)
+            ctx.guide_emit(ctx.args(5000 + i, n_train, D), p, se, contrib)
+            ctx.guide_grad(w, se, g1, None)
+            if diffuse:   # each population self-normalised, the two gradients added
+                ctx.guide_vertex_samples(ctx.args(5000 + i, n_train, D, lt.GUIDE_DIFFUSE), p, sd)
+                ctx.guide_grad(w, sd, g2, None)
+                g1 += g2
+            ctx.guide_adam(w, g1, m, v, i, lr)
+        return w
+
+    g0 = estimate(None, 0)
+    ge = estimate(train(False), 0)
+    gd = estimate(train(True), lt.GUIDE_DIFFUSE)
+    v0 = g0.var(0)
+    res = {}
+    for name, g in (("emission", ge), ("emission+diffuse", gd)):
+        v = g.var(0)
+        z = (g.mean(0) - g0.mean(0)) / torch.sqrt(v0 / K + v / K).clamp_min(1e-30)
+        res[name] = (v.sum().item() / v0.sum().item(), v.median().item() / v0.median().item(), (z * z).mean().item())
+        print(f"detail box, {name} guide: variance ratio {res[name][0]:.3f}, median-texel {res[name][1]:.3f}, "
+              f"bias mean z^2 {res[name][2]:.3f}", flush=True)
+    vr, mr, z2 = res["emission+diffuse"]
+    assert vr < 0.6 and mr < 0.75 and z2 < 1.5
+    assert vr < res["emission"][0] and mr < res["emission"][1]
