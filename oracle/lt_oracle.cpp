@@ -162,7 +162,7 @@ void onbv(const V3& n, V3& b1, V3& b2) {
 // ----------------------------------------------------------------- C API
 extern "C" {
 
-enum { ORA_ABSORBER = 0, ORA_LAMBERT = 1, ORA_DIELECTRIC = 2 };
+enum { ORA_ABSORBER = 0, ORA_LAMBERT = 1, ORA_DIELECTRIC = 2, ORA_CONDUCTOR = 3 };
 enum { ORA_EMIT_QUAD = 0, ORA_EMIT_POINT = 1, ORA_EMIT_DIRECTIONAL = 2 };
 enum { ORA_F_ATTACHED = 1, ORA_F_SPLAT_SELECTED = 2 };
 enum { ORA_MODE_NAIVE = 0, ORA_MODE_RESLRB = 1 };
@@ -640,6 +640,63 @@ int dielectric_event(const V3& w_in, const V3& ns, D3 ng, double ior, double u_l
   return 0;
 }
 
+// Rough conductor (an extension for the Mirror validation of Sec. 6.1: the
+// paper names a roughened conductor without fixing its model).  GGX /
+// Trowbridge-Reitz microfacets of roughness a about the unit shading normal
+// n, Smith's separable masking, and a reflectance F0 (the material's albedo
+// texel) that does not vary with angle:
+//   D(m) = a^2 / (pi ((m.n)^2 (a^2 - 1) + 1)^2),
+//   G1(v) = 2 (v.n) / ((v.n) + sqrt(a^2 + (1 - a^2)(v.n)^2)),
+//   f(wi, wo) = F0 D(h) G1(wi) G1(wo) / (4 (wi.n)(wo.n)),  h = normalize(wi + wo).
+// Sampling draws m with density D(m)(m.n) (tan^2 theta_m = a^2 u0 / (1 - u0),
+// phi = 2 pi u1) and reflects wi about it; the weight f (wo.n) / p is then
+// F0 G1(wi) G1(wo) (wi.m) / ((wi.n)(m.n)).
+V ggx_D(const V& cm, double a2) {
+  V d = cm * cm * V(a2 - 1.0) + V(1.0);
+  return V(a2 * kInvPi) / (d * d);
+}
+V ggx_G1(const V& cv, double a2) { return V(2.0) * cv / (cv + vsqrt(V(a2) + V(1.0 - a2) * cv * cv)); }
+
+// local microfacet normal (x, y, z) of the uniforms (u0, u1)
+void ggx_local(double a, double u0, double u1, double& lx, double& ly, double& lz) {
+  double t2 = a * a * u0 / (1.0 - u0);
+  lz = 1.0 / std::sqrt(1.0 + t2);
+  double st = std::sqrt(std::max(0.0, 1.0 - lz * lz)), phi = 2.0 * M_PI * u1;
+  lx = st * std::cos(phi); ly = st * std::sin(phi);
+}
+
+// The conductor's part of a sensor connection from the vertex, f (wc.n) / F0
+// = D(h) G1(wi) G1(wc) / (4 wi.n), for unit wi, wc on the side of n.
+V conductor_conn(const V3& wi, const V3& wc, const V3& n, double a) {
+  const double a2 = a * a;
+  V3 h = normalize(wi + wc);
+  V cosi = dot(wi, n);
+  return ggx_D(dot(h, n), a2) * ggx_G1(cosi, a2) * ggx_G1(dot(wc, n), a2) / (V(4.0) * cosi);
+}
+
+// Microfacet reflection of unit wi (pointing away from the surface, on the
+// side of the unit shading normal n) with the microfacet normal of (u0, u1)
+// held fixed in the local frame of n: writes wo and the weight f (wo.n) / p
+// over F0.  Returns 7 when wi does not see the drawn microfacet, 8 when wo
+// leaves below n or on the far side of the geometric normal ng (side_in =
+// +1 when the ray arrived on the +ng side), else 0.
+int conductor_event(const V3& wi, const V3& n, D3 ng, double side_in, double a, double u0, double u1, V3& wo,
+                    V& wgt) {
+  const double a2 = a * a;
+  double lx, ly, lz;
+  ggx_local(a, u0, u1, lx, ly, lz);
+  V3 t1, t2; onbv(n, t1, t2);
+  V3 m = t1 * V(lx) + t2 * V(ly) + n * V(lz);
+  V cwm = dot(wi, m);
+  if (cwm.v <= 0.0) return 7;
+  wo = m * (V(2.0) * cwm) - wi;
+  V coso = dot(wo, n);
+  if (coso.v <= 0.0 || dot(val(wo), ng) * side_in <= 0.0) return 8;
+  V cosi = dot(wi, n);
+  wgt = ggx_G1(cosi, a2) * ggx_G1(coso, a2) * cwm / (cosi * V(lz));
+  return 0;
+}
+
 struct Conn { V C[3]; V ux, uy; int depth; };
 
 struct PathResult {
@@ -766,7 +823,24 @@ void trace_path(const Scene& S, const ora_args& A, uint32_t path, PathResult& ou
       if (std::fabs(cos_in) < 0.02 || dot(seg, seg) < 4e-4) ill = true;
     }
 
-    if (mtype == ORA_LAMBERT) {
+    // shading normal: the geometric one, or on the heightfield the
+    // normalised (-S_x, 1, -S_z) of the barycentric blend of the vertex
+    // slopes (central differences of the heights, or a normal map)
+    auto shading_normal = [&]() {
+      V3 ns = ng;
+      if (tri >= S.n_static) {
+        V sx[3], sz[3];
+        for (int k = 0; k < 3; ++k) { int gi, gj; S.hf_corner(tri, k, gi, gj); S.slope(gi, gj, sx[k], sz[k]); }
+        V c0 = V(1.0) - b1 - b2;
+        V Sx = c0 * sx[0] + b1 * sx[1] + b2 * sx[2];
+        V Sz = c0 * sz[0] + b1 * sz[1] + b2 * sz[2];
+        ns = normalize(V3{-Sx, V(1.0), -Sz});
+      }
+      return ns;
+    };
+
+    if (mtype == ORA_LAMBERT || mtype == ORA_CONDUCTOR) {
+      const bool cond = mtype == ORA_CONDUCTOR;
       // texel (nearest), from primal chart coordinates
       int tex = sc.mat_tex[mat], R = sc.tex_res;
       double uvx, uvy;
@@ -782,6 +856,17 @@ void trace_path(const Scene& S, const ora_args& A, uint32_t path, PathResult& ou
       out.sig = fnv1a(out.sig, (uint32_t)texel + 1u);
       V rho[3];
       for (int c = 0; c < 3; ++c) rho[c] = leaf(S.albedo[texel * 3 + c], texel * 3 + c);
+      // conductor: arrival-side shading normal n_a and wi = -w; a ray
+      // arriving from behind n_a ends the path (no connection)
+      V3 n_a = ng, wi = wcur * V(-1.0);
+      V cosi(0.0);
+      const double a_r = cond ? sc.mat_ior[mat] : 0.0;
+      if (cond) {
+        V3 ns = shading_normal();
+        n_a = cos_in < 0 ? ns : ns * V(-1.0);
+        cosi = dot(wi, n_a);
+        if (cosi.v <= 0.0) { out.sig = fnv1a(out.sig, 7u); break; }
+      }
 
       // --- sensor connection (Eq. 1 term i)
       uint32_t valid = 0;
@@ -796,7 +881,8 @@ void trace_path(const Scene& S, const ora_args& A, uint32_t path, PathResult& ou
           double dist = std::sqrt(dot(dvd, dvd));
           D3 wc = dvd * (-1.0 / dist);
           double cg = dot(ngd, wc);
-          if (cg * (-cos_in) > 0.0) {
+          const bool side_ok = cg * (-cos_in) > 0.0 && (!cond || dot(val(n_a), wc) > 0.0);
+          if (side_ok) {
             D3 so = val(x) + ngd * (cg >= 0 ? kEps : -kEps);
             D3 sd = S.cpos - so;
             double sl = std::sqrt(dot(sd, sd));
@@ -806,8 +892,14 @@ void trace_path(const Scene& S, const ora_args& A, uint32_t path, PathResult& ou
               V dist2 = dot(dv, dv);
               V distv = vsqrt(dist2);
               V cosc = zc / distv;
-              V cosx = vabs(dot(ng, dv)) / distv;
-              V g = V(kInvPi * Kfilm) * cosx / (cosc * cosc * cosc * dist2);
+              V g;
+              if (!cond) {
+                V cosx = vabs(dot(ng, dv)) / distv;
+                g = V(kInvPi * Kfilm) * cosx / (cosc * cosc * cosc * dist2);
+              } else {
+                V bc = conductor_conn(wi, dv * (V(-1.0) / distv), n_a, a_r);
+                g = V(Kfilm) * bc / (cosc * cosc * cosc * dist2);
+              }
               Conn cn;
               for (int c = 0; c < 3; ++c) cn.C[c] = beta[c] * rho[c] * g;
               cn.ux = ux; cn.uy = uy; cn.depth = j;
@@ -827,6 +919,17 @@ void trace_path(const Scene& S, const ora_args& A, uint32_t path, PathResult& ou
       out.sig = fnv1a(out.sig, valid);
       if (j == A.max_depth) break;
 
+      if (cond) {
+        // --- microfacet reflection (the microfacet normal held fixed in the
+        // local frame of n_a, so the frame moves with the surface)
+        V3 wo; V wgt;
+        int code = conductor_event(wi, n_a, ngd, cos_in < 0 ? 1.0 : -1.0, a_r, uj.u[0], uj.u[1], wo, wgt);
+        if (code) { out.sig = fnv1a(out.sig, (uint32_t)code); break; }
+        for (int c = 0; c < 3; ++c) beta[c] = beta[c] * rho[c] * wgt;
+        xprev = x; wcur = wo;
+        offn = ngd; off = true;
+        continue;
+      }
       // --- cosine-weighted scatter on the arrival side
       double rr = std::sqrt(uj.u[0]), phi = 2.0 * M_PI * uj.u[1];
       double lx = rr * std::cos(phi), ly = rr * std::sin(phi), lz = std::sqrt(std::max(0.0, 1.0 - uj.u[0]));
@@ -865,16 +968,7 @@ void trace_path(const Scene& S, const ora_args& A, uint32_t path, PathResult& ou
       xprev = x; wcur = wo;
       offn = ngd; off = true;
     } else {  // dielectric: Fresnel-sampled reflect / refract, weight 1
-      V3 ns = ng;
-      if (tri >= S.n_static) {
-        // interpolated central-difference slope -> shading normal
-        V sx[3], sz[3];
-        for (int k = 0; k < 3; ++k) { int gi, gj; S.hf_corner(tri, k, gi, gj); S.slope(gi, gj, sx[k], sz[k]); }
-        V c0 = V(1.0) - b1 - b2;
-        V Sx = c0 * sx[0] + b1 * sx[1] + b2 * sx[2];
-        V Sz = c0 * sz[0] + b1 * sz[1] + b2 * sz[2];
-        ns = normalize(V3{-Sx, V(1.0), -Sz});
-      }
+      V3 ns = shading_normal();
       if (j == A.max_depth) break;
       V3 wo;
       bool reflect = false;
@@ -932,6 +1026,30 @@ int ora_reservoir(const double* w, const double* u, int k, double* W_out) {
   }
   if (W_out) *W_out = R ? Om / wr : 0.0;
   return R;
+}
+
+// GGX terms at roughness a: D(m) for m.n = cm and G1 for v.n = cv.
+void ora_ggx_terms(double a, double cm, double cv, double* D, double* G1) {
+  *D = ggx_D(V(cm), a * a).v;
+  *G1 = ggx_G1(V(cv), a * a).v;
+}
+
+// One rough-conductor reflection with constant inputs (wi, n unit, wi on the
+// side of n; ng = n): writes wo and the weight f (wo.n) / p over F0.  Returns
+// the event code of conductor_event.
+int ora_conductor(const double* wi, const double* n, double a, double u0, double u1, double* wo, double* wgt) {
+  V3 w = cst({wi[0], wi[1], wi[2]}), nn = cst({n[0], n[1], n[2]});
+  V3 o{V(0.0), V(0.0), V(0.0)};
+  V g(0.0);
+  int code = conductor_event(w, nn, {n[0], n[1], n[2]}, 1.0, a, u0, u1, o, g);
+  wo[0] = o.x.v; wo[1] = o.y.v; wo[2] = o.z.v;
+  *wgt = g.v;
+  return code;
+}
+
+// The conductor's connection factor f (wc.n) / F0 for constant unit wi, wc, n.
+double ora_conductor_conn(const double* wi, const double* wc, const double* n, double a) {
+  return conductor_conn(cst({wi[0], wi[1], wi[2]}), cst({wc[0], wc[1], wc[2]}), cst({n[0], n[1], n[2]}), a).v;
 }
 
 // One dielectric scattering event with constant inputs (w_in, ng, ns unit

@@ -100,6 +100,11 @@ def _load():
         _lib.ora_guide_table.restype = C.c_int64
         _lib.ora_guide_vertex_samples.argtypes = [C.POINTER(_Scene), C.POINTER(_Args), dp, dp, dp, dp, dp]
         _lib.ora_guide_vertex_samples.restype = C.c_int
+        _lib.ora_ggx_terms.argtypes = [C.c_double, C.c_double, C.c_double, dp, dp]
+        _lib.ora_conductor.argtypes = [dp, dp, C.c_double, C.c_double, C.c_double, dp, dp]
+        _lib.ora_conductor.restype = C.c_int
+        _lib.ora_conductor_conn.argtypes = [dp, dp, dp, C.c_double]
+        _lib.ora_conductor_conn.restype = C.c_double
         _lib.ora_dielectric.argtypes = [dp, dp, dp, C.c_double, C.c_double, dp, ip, dp]
         _lib.ora_dielectric.restype = C.c_int
         assert _lib.ora_guide_nparams() == GUIDE_NPARAMS
@@ -285,6 +290,34 @@ def dielectric(w_in, ng, ns, ior, u_lobe):
     code = lib.ora_dielectric(_p(w_in), _p(ng), _p(ns), float(ior), float(u_lobe), _p(wo), C.byref(refl),
                               C.byref(F))
     return int(code), wo, bool(refl.value), F.value
+
+
+def ggx_terms(a, cm, cv):
+    """GGX D(m) at m.n = cm and Smith G1 at v.n = cv for roughness a."""
+    lib = _load()
+    D, G1 = C.c_double(), C.c_double()
+    lib.ora_ggx_terms(float(a), float(cm), float(cv), C.byref(D), C.byref(G1))
+    return D.value, G1.value
+
+
+def conductor(w_in, n, a, u0, u1):
+    """One rough-conductor reflection of wi (unit, pointing away from the
+    surface on the side of n): (code, wo, weight f (wo.n)/p over F0); code 7
+    (wi misses the drawn microfacet), 8 (wo below the surface), else 0."""
+    lib = _load()
+    wi = np.ascontiguousarray(w_in, np.float64)
+    nn = np.ascontiguousarray(n, np.float64)
+    wo = np.zeros(3)
+    wgt = C.c_double()
+    code = lib.ora_conductor(_p(wi), _p(nn), float(a), float(u0), float(u1), _p(wo), C.byref(wgt))
+    return code, wo, wgt.value
+
+
+def conductor_conn(w_in, wc, n, a):
+    """The conductor's connection factor f (wc.n)/F0 = D(h) G1(wi) G1(wc)/(4 wi.n)."""
+    lib = _load()
+    wi, c, nn = (np.ascontiguousarray(v, np.float64) for v in (w_in, wc, n))
+    return lib.ora_conductor_conn(_p(wi), _p(c), _p(nn), float(a))
 
 
 def philox(seed, ctr):

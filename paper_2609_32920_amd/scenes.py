@@ -10,9 +10,10 @@ Scene dictionary layout (all arrays numpy, float64 unless noted):
   tri_v    [T,3,3]  world-space triangle vertices (static geometry)
   tri_uv   [T,3,2]  per-vertex chart/texture coordinates
   tri_mat  [T]      int32 material index
-  mat_type [M]      int32: MAT_ABSORBER, MAT_LAMBERT, MAT_DIELECTRIC
-  mat_tex  [M]      int32 texture index of a Lambertian material (-1 otherwise)
-  mat_ior  [M]      refractive index of a dielectric material
+  mat_type [M]      int32: MAT_ABSORBER, MAT_LAMBERT, MAT_DIELECTRIC, MAT_CONDUCTOR
+  mat_tex  [M]      int32 texture index of a Lambertian material (its albedo) or a
+                    conductor (its reflectance F0); -1 otherwise
+  mat_ior  [M]      refractive index of a dielectric, GGX roughness of a conductor
   n_tex, tex_res    albedo textures are [n_tex, tex_res, tex_res, 3]
   emitter  dict(type=EMIT_QUAD|EMIT_POINT|EMIT_DIRECTIONAL, o, e1, e2[, tex_res])
            (point: o = position; directional: a collimated beam leaving the
@@ -35,6 +36,7 @@ import numpy as np
 MAT_ABSORBER = 0
 MAT_LAMBERT = 1
 MAT_DIELECTRIC = 2
+MAT_CONDUCTOR = 3
 
 EMIT_QUAD = 0
 EMIT_POINT = 1
@@ -203,6 +205,60 @@ def caustic_scene(G=128, width=512, height=512, seed=SCENE_SEED, target_seed=TAR
     )
 
 
+def mirror_scene(G=16, width=64, height=64, seed=SCENE_SEED, target_seed=TARGET_SEED, roughness=0.15,
+                 Le=200.0, h_sigma=0.002):
+    """Rough-conductor heightfield throwing a caustic onto a diffuse wall
+    (the Mirror validation of the paper: attached gradients w.r.t. the
+    vertex positions - here the heights - of a roughened conductor).
+
+    Mirror: G x G heightfield over x,z in [-0.5, 0.5] at y = h (boundary
+    ring at 0, inside N(0, h_sigma)), GGX roughness `roughness`, reflectance
+    F0 (0.9, 0.85, 0.8) (texture 1).  Emitter: 0.1 x 0.1 quad centred at
+    (-0.8, 0.8, 0) facing the mirror's centre (45 degrees).  Receiver: the
+    wall x = 0.9 facing -x (y in [-0.2, 1.6], z in [-1, 1]), grey albedo 0.8
+    (texture 0).  Camera at (-0.3, 0.7, -1.8) looking at (0.6, 0.55, 0), 50
+    degree FOV: it sees the lit wall and the mirror.  Target heights: a
+    seeded product of sines vanishing on the ring.
+    """
+    b = _Builder()
+    # materials: 0 receiver (Lambert, tex 0), 1 mirror (conductor, tex 1), 2 absorber (emitter)
+    mat_type = np.array([MAT_LAMBERT, MAT_CONDUCTOR, MAT_ABSORBER], np.int32)
+    mat_tex = np.array([0, 1, -1], np.int32)
+    mat_ior = np.array([1.0, float(roughness), 1.0])
+    b.quad((0.9, -0.2, -1.0), (0, 0, 2), (0, 1.8, 0), 0)    # wall, normal -x
+    s2 = 0.1 / math.sqrt(2.0)
+    e1, e2 = np.array([s2, s2, 0.0]), np.array([0.0, 0.0, 0.1])   # e1 x e2 along (1, -1, 0)
+    em_o = np.array([-0.8, 0.8, 0.0]) - 0.5 * e1 - 0.5 * e2
+    b.quad(em_o, e1, e2, 2)
+    tri_v, tri_uv, tri_mat = b.arrays()
+    rng = np.random.default_rng(seed)
+    h = rng.normal(0.0, h_sigma, size=(G, G))
+    h[0, :] = h[-1, :] = h[:, 0] = h[:, -1] = 0.0
+    trng = np.random.default_rng(target_seed)
+    amp = trng.uniform(0.005, 0.015)
+    kx, kz = trng.integers(1, 4, size=2)
+    xs = np.linspace(-0.5, 0.5, G)
+    X, Z = np.meshgrid(xs, xs, indexing="xy")
+    ht = amp * np.sin(math.pi * kx * (X + 0.5)) * np.sin(math.pi * kz * (Z + 0.5))
+    ht[0, :] = ht[-1, :] = ht[:, 0] = ht[:, -1] = 0.0
+    albedo = np.zeros((2, 1, 1, 3))
+    albedo[0, 0, 0] = 0.8
+    albedo[1, 0, 0] = (0.9, 0.85, 0.8)
+    return dict(
+        name=f"mirror{G}_{width}x{height}",
+        tri_v=tri_v, tri_uv=tri_uv, tri_mat=tri_mat,
+        mat_type=mat_type, mat_tex=mat_tex, mat_ior=mat_ior,
+        n_tex=2, tex_res=1,
+        emitter=dict(type=EMIT_QUAD, o=em_o, e1=e1, e2=e2),
+        camera=dict(pos=np.array([-0.3, 0.7, -1.8]), target=np.array([0.6, 0.55, 0.0]),
+                    up=np.array([0.0, 1.0, 0.0]), fov_deg=50.0, width=width, height=height),
+        hf=dict(G=G, x0=-0.5, z0=-0.5, dx=1.0 / (G - 1), base=0.0, mat=1),
+        albedo=albedo, Le=np.full(3, float(Le)),
+        heights=h.reshape(-1).copy(),
+        albedo_target=None, heights_target=ht.reshape(-1).copy(),
+    )
+
+
 def glass_panel_scene(G=16, width=64, height=64, seed=SCENE_SEED, target_seed=TARGET_SEED, slope_sigma=0.05):
     """Normal-mapped glass panel over a diffuse receiver (attached workload
     with a normal map, the Glass Panel validation of the paper).
@@ -287,23 +343,25 @@ def tumbler_scene(G=16, width=64, height=64, tex_res=8, seed=SCENE_SEED, target_
 
 
 def plane_point_light_scene(width=32, height=32, rho=0.6, I0=5.0, light_h=0.8,
-                            cam_h=2.0, fov_deg=60.0):
+                            cam_h=2.0, fov_deg=60.0, roughness=None):
     """Point light over a large Lambertian plane seen by a pinhole camera.
 
     Plane y = 0 spanning x,z in [-4, 4] with one constant albedo rho (a 1x1
     texture); isotropic point light of intensity I0 at (0.3, light_h, -0.2);
     camera at (0, cam_h, 0) looking straight down with up = +z.  With one
     scattering vertex the expected image has a closed form (a pixel-filtered
-    integral of rho/pi * I0 cos(theta_l) / r^2).
+    integral of rho/pi * I0 cos(theta_l) / r^2).  With a roughness the
+    plane is a rough conductor of reflectance rho instead.
     """
     b = _Builder()
     b.quad((-4, 0, -4), (0, 0, 8), (8, 0, 0), 0)   # normal +y
     tri_v, tri_uv, tri_mat = b.arrays()
+    cond = roughness is not None
     return dict(
         name="plane_point",
         tri_v=tri_v, tri_uv=tri_uv, tri_mat=tri_mat,
-        mat_type=np.array([MAT_LAMBERT], np.int32), mat_tex=np.array([0], np.int32),
-        mat_ior=np.array([1.0]),
+        mat_type=np.array([MAT_CONDUCTOR if cond else MAT_LAMBERT], np.int32), mat_tex=np.array([0], np.int32),
+        mat_ior=np.array([float(roughness) if cond else 1.0]),
         n_tex=1, tex_res=1,
         emitter=dict(type=EMIT_POINT, o=np.array([0.3, light_h, -0.2]),
                      e1=np.zeros(3), e2=np.zeros(3)),
