@@ -58,7 +58,7 @@ typedef enum {
 } lt_status;
 
 /* material types (lt_scene_desc.mat_type) */
-enum { LT_MAT_ABSORBER = 0, LT_MAT_LAMBERT = 1, LT_MAT_DIELECTRIC = 2 };
+enum { LT_MAT_ABSORBER = 0, LT_MAT_LAMBERT = 1, LT_MAT_DIELECTRIC = 2, LT_MAT_CONDUCTOR = 3 };
 /* emitter types (lt_scene_desc.em_type): an area quad with cosine-weighted
  * emission, an isotropic point, or a directional quad (a collimated beam
  * leaving the quad along its normal, as the directional emitter of the
@@ -83,8 +83,19 @@ typedef struct lt_ctx lt_ctx;
  *  tri_v  [n_tris][3][3]  static triangle vertices (world space)
  *  tri_uv [n_tris][3][2]  per-vertex texture coordinates in [0,1]
  *  tri_mat[n_tris]        material index in [0, n_mats)
- *  mat_type/mat_tex/mat_ior [n_mats]: type, texture index (Lambertian),
- *                         refractive index (dielectric)
+ *  mat_type/mat_tex/mat_ior [n_mats]: type, texture index (Lambertian: its
+ *                         albedo; rough conductor: its reflectance F0), and
+ *                         refractive index (dielectric) or GGX roughness in
+ *                         [1e-3, 1] (conductor).  The rough conductor (the
+ *                         roughened mirror of the attached validation, Sec. 6.1):
+ *                         f = F0 D(h) G1(wi) G1(wo) / (4 (wi.n)(wo.n)) with GGX D,
+ *                         Smith's separable G1 and n the shading normal (on the
+ *                         heightfield the blended slopes, as for glass); its
+ *                         vertices connect to the sensor, and scatter by
+ *                         reflecting about a microfacet normal drawn with density
+ *                         D(m)(m.n) from the vertex's first two uniforms, weight
+ *                         F0 G1(wi) G1(wo) (wi.m) / ((wi.n)(m.n)).  Detached
+ *                         passes only (LT_ATTACHED returns LT_ERR_UNSUPPORTED).
  *  n_tex, tex_res         albedo parameters are [n_tex][tex_res][tex_res][3]
  *  emitter: quad (o, e1, e2; one-sided, normal normalize(e1 x e2)), point (o) or
  *          directional quad (o, e1, e2; the beam leaves along the normal, radiance

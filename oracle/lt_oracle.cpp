@@ -857,7 +857,7 @@ void trace_path(const Scene& S, const ora_args& A, uint32_t path, PathResult& ou
       V rho[3];
       for (int c = 0; c < 3; ++c) rho[c] = leaf(S.albedo[texel * 3 + c], texel * 3 + c);
       // conductor: arrival-side shading normal n_a and wi = -w; a ray
-      // arriving from behind n_a ends the path (no connection)
+      // arriving from behind n_a ends the path (no connection; code 9)
       V3 n_a = ng, wi = wcur * V(-1.0);
       V cosi(0.0);
       const double a_r = cond ? sc.mat_ior[mat] : 0.0;
@@ -865,7 +865,7 @@ void trace_path(const Scene& S, const ora_args& A, uint32_t path, PathResult& ou
         V3 ns = shading_normal();
         n_a = cos_in < 0 ? ns : ns * V(-1.0);
         cosi = dot(wi, n_a);
-        if (cosi.v <= 0.0) { out.sig = fnv1a(out.sig, 7u); break; }
+        if (cosi.v <= 0.0) { out.sig = fnv1a(out.sig, 9u); break; }
       }
 
       // --- sensor connection (Eq. 1 term i)

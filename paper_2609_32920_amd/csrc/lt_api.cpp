@@ -201,6 +201,7 @@ struct lt_ctx {
   char* d_hand = nullptr;    // LRB-3 hand-off between its two kernels [hand_n bytes]
   size_t hand_n = 0;
   char* d_scratch = nullptr; // this device's copy of the static scratch (null: unavailable)
+  bool has_conductor = false; // the uploaded scene has rough-conductor surfaces
 
   lt_status fail(lt_status s, const char* fmt, const char* a = "") {
     char buf[512];
@@ -287,9 +288,9 @@ size_t hgrad_lds_bytes(const lt_ctx* c, int on) { return on ? (size_t)c->dsc.hf_
 struct SideLayout { size_t tape = 0, len = 0, emit = 0, gw = 0, res = 0, spl_hdr = 0, spl = 0, total = 0; };
 
 // Side state: naive tape [D][N] records (+ N path lengths; attached: + the
-// emitted ray's dv_1/dH_1 per path; detached with a diffuse guide: + [D][N]
-// scatter weights), ResLRB records [N].
-SideLayout side_layout(const lt_trace_args* a) {
+// emitted ray's dv_1/dH_1 per path; detached with a diffuse guide or rough
+// conductors in the scene: + [D][N] scatter weights), ResLRB records [N].
+SideLayout side_layout(const lt_ctx* c, const lt_trace_args* a) {
   SideLayout L;
   size_t N = (size_t)a->n_paths, D = (size_t)a->max_depth;
   const bool att = (a->flags & LT_ATTACHED) != 0;
@@ -298,9 +299,11 @@ SideLayout side_layout(const lt_trace_args* a) {
     L.tape = off; off = align256(off + N * D * (att ? sizeof(TapeRecAtt) : sizeof(TapeRec)));
     L.len = off; off = align256(off + N * sizeof(int32_t));
     if (att) { L.emit = off; off = align256(off + N * 2 * sizeof(float)); }
-    // detached tape with a diffuse guide: the scatter weight cos / (pi q) of
-    // every vertex (the attached record has room for it)
-    if (!att && (a->flags & LT_GUIDE_DIFFUSE)) { L.gw = off; off = align256(off + N * D * sizeof(float)); }
+    // detached tape with a diffuse guide or rough conductors: the scatter
+    // weight over rho of every vertex (the attached record has room for it)
+    if (!att && ((a->flags & LT_GUIDE_DIFFUSE) || (c && c->has_conductor))) {
+      L.gw = off; off = align256(off + N * D * sizeof(float));
+    }
   }
   if (a->flags & LT_RECORD_RESERVOIR) {
     L.res = off; off = align256(off + N * (att ? sizeof(ResRecAtt) : sizeof(ResRec)));
@@ -332,6 +335,8 @@ lt_status check_args(lt_ctx* c, const lt_trace_args* a, const lt_params* p) {
   if (p->normal_map && (c->dsc.hf_G < 2 || !p->heights))
     return c->fail(LT_ERR_ARG, "a normal map needs a heightfield and params->heights%s");
   if (p->guide_w && c->dsc.em_type != LT_EMIT_QUAD) return c->fail(LT_ERR_UNSUPPORTED, "the emission guide needs an area emitter%s");
+  if (c->has_conductor && (a->flags & LT_ATTACHED))
+    return c->fail(LT_ERR_UNSUPPORTED, "rough conductors are supported by detached passes only%s");
   if (c->dsc.em_tex_res > 0 && (a->flags & LT_ATTACHED))
     return c->fail(LT_ERR_UNSUPPORTED, "a textured emitter is supported by detached passes only%s");
   if (c->dsc.em_tex_res > 0 && p->guide_w)
@@ -597,9 +602,12 @@ lt_status lt_scene_upload(lt_ctx* c, const lt_scene_desc* s) {
     return c->fail(LT_ERR_ARG, "bad emitter texture size (0, or 1..4096 on a quad or directional emitter)%s");
   if (s->hf_G == 1 || s->hf_G < 0 || s->hf_G > 4096) return c->fail(LT_ERR_ARG, "bad heightfield size%s");
   for (int m = 0; m < s->n_mats; ++m) {
-    if (s->mat_type[m] < 0 || s->mat_type[m] > 2) return c->fail(LT_ERR_ARG, "bad material type%s");
-    if (s->mat_type[m] == LT_MAT_LAMBERT && (s->mat_tex[m] < 0 || s->mat_tex[m] >= s->n_tex))
-      return c->fail(LT_ERR_ARG, "Lambertian material without a valid texture%s");
+    if (s->mat_type[m] < 0 || s->mat_type[m] > 3) return c->fail(LT_ERR_ARG, "bad material type%s");
+    if ((s->mat_type[m] == LT_MAT_LAMBERT || s->mat_type[m] == LT_MAT_CONDUCTOR) &&
+        (s->mat_tex[m] < 0 || s->mat_tex[m] >= s->n_tex))
+      return c->fail(LT_ERR_ARG, "Lambertian or conductor material without a valid texture%s");
+    if (s->mat_type[m] == LT_MAT_CONDUCTOR && !(s->mat_ior[m] >= 1e-3 && s->mat_ior[m] <= 1.0))
+      return c->fail(LT_ERR_ARG, "conductor roughness outside [1e-3, 1]%s");
     if (s->mat_type[m] == LT_MAT_DIELECTRIC && !(s->mat_ior[m] > 0.0)) return c->fail(LT_ERR_ARG, "bad IOR%s");
   }
   for (int t = 0; t < s->n_tris; ++t)
@@ -703,6 +711,9 @@ lt_status lt_scene_upload(lt_ctx* c, const lt_scene_desc* s) {
   if (e == hipSuccess) e = upload(&c->d_levels, levels.data(), levels.size());
   if (e != hipSuccess) { c->free_scene(); return c->hip(e, "scene upload"); }
   c->level_off = loff;
+  c->has_conductor = false;
+  for (int t = 0; t < s->n_tris; ++t) c->has_conductor |= s->mat_type[s->tri_mat[t]] == LT_MAT_CONDUCTOR;
+  if (G >= 2) c->has_conductor |= s->mat_type[s->hf_mat] == LT_MAT_CONDUCTOR;
   c->scene_bytes = F.nodes.size() * sizeof(Node) + ordered.size() * sizeof(Tri) + pmat.size() * 4 +
                    puv.size() * 4 + slot.size() * 4 + levels.size() * 4 +
                    (size_t)s->n_tex * s->tex_res * s->tex_res * 6 * sizeof(float) + 512;
@@ -821,9 +832,8 @@ lt_status lt_scene_upload(lt_ctx* c, const lt_scene_desc* s) {
 }
 
 size_t lt_side_state_bytes(const lt_ctx* c, const lt_trace_args* a) {
-  (void)c;
   if (!a || a->n_paths < 1 || a->max_depth < 1) return 0;
-  return side_layout(a).total;
+  return side_layout(c, a).total;
 }
 
 size_t lt_workspace_bytes(const lt_ctx* c, const lt_trace_args* a) {
@@ -842,7 +852,7 @@ lt_status lt_trace(lt_ctx* c, const lt_trace_args* a, const lt_params* p, float*
   const bool att_rec = (a->flags & LT_ATTACHED) && (a->flags & (LT_RECORD_TAPE | LT_RECORD_RESERVOIR));
   if (att_rec && a->path_sig)
     return c->fail(LT_ERR_UNSUPPORTED, "path signatures come from the detached forward (no attached records)%s");
-  SideLayout L = side_layout(a);
+  SideLayout L = side_layout(c, a);
   if (L.total && (!side || side_bytes < L.total)) return c->fail(LT_ERR_ARG, "side state buffer too small%s");
   if ((st = check_cap(c, L.total + guide_bytes(a, p))) != LT_OK) return st;
   if ((st = prepare_geometry(c, p)) != LT_OK) return st;
@@ -937,11 +947,11 @@ lt_status lt_backward_naive(lt_ctx* c, const lt_trace_args* a, const lt_params* 
                             const void* tape, size_t tape_bytes, lt_grads* g) {
   if (!c) return LT_ERR_ARG;
   if (a && !(a->flags & LT_RECORD_TAPE)) return c->fail(LT_ERR_ARG, "naive backward needs LT_RECORD_TAPE args%s");
-  if (a && (!tape || tape_bytes < side_layout(a).total)) return c->fail(LT_ERR_ARG, "tape buffer too small%s");
+  if (a && (!tape || tape_bytes < side_layout(c, a).total)) return c->fail(LT_ERR_ARG, "tape buffer too small%s");
   PassArgs A;
-  lt_status st = backward_common(c, a, p, d_image, g, A, a ? side_layout(a).total : 0);
+  lt_status st = backward_common(c, a, p, d_image, g, A, a ? side_layout(c, a).total : 0);
   if (st != LT_OK) return st;
-  SideLayout L = side_layout(a);
+  SideLayout L = side_layout(c, a);
   const char* sb = (const char*)tape;
   A.contrib = a->path_contrib;
   A.tape_in = (const TapeRec*)(sb + L.tape);
@@ -964,11 +974,11 @@ lt_status lt_backward_reslrb(lt_ctx* c, const lt_trace_args* a, const lt_params*
                              const void* records, size_t bytes, lt_grads* g) {
   if (!c) return LT_ERR_ARG;
   if (a && !(a->flags & LT_RECORD_RESERVOIR)) return c->fail(LT_ERR_ARG, "ResLRB backward needs LT_RECORD_RESERVOIR args%s");
-  if (a && (!records || bytes < side_layout(a).total)) return c->fail(LT_ERR_ARG, "reservoir buffer too small%s");
+  if (a && (!records || bytes < side_layout(c, a).total)) return c->fail(LT_ERR_ARG, "reservoir buffer too small%s");
   PassArgs A;
-  lt_status st = backward_common(c, a, p, d_image, g, A, a ? side_layout(a).total : 0);
+  lt_status st = backward_common(c, a, p, d_image, g, A, a ? side_layout(c, a).total : 0);
   if (st != LT_OK) return st;
-  SideLayout L = side_layout(a);
+  SideLayout L = side_layout(c, a);
   if (a->flags & LT_ATTACHED) {
     A.res_att_in = (const ResRecAtt*)((const char*)records + L.res);
     const int blk = att_replay_block(c, g->heights, c->dsc.stack_n, BwdKernel::reslrb_att, 512);
@@ -990,11 +1000,11 @@ lt_status lt_backward_lrb2(lt_ctx* c, const lt_trace_args* a, const lt_params* p
   if (!c) return LT_ERR_ARG;
   if (a && (a->flags & LT_ATTACHED)) return c->fail(LT_ERR_UNSUPPORTED, "the buffered two-pass backward is detached%s");
   if (a && !(a->flags & LT_RECORD_SPLATS)) return c->fail(LT_ERR_ARG, "two-pass backward needs LT_RECORD_SPLATS args%s");
-  if (a && (!records || bytes < side_layout(a).total)) return c->fail(LT_ERR_ARG, "splat record buffer too small%s");
+  if (a && (!records || bytes < side_layout(c, a).total)) return c->fail(LT_ERR_ARG, "splat record buffer too small%s");
   PassArgs A;
-  lt_status st = backward_common(c, a, p, d_image, g, A, a ? side_layout(a).total : 0);
+  lt_status st = backward_common(c, a, p, d_image, g, A, a ? side_layout(c, a).total : 0);
   if (st != LT_OK) return st;
-  SideLayout L = side_layout(a);
+  SideLayout L = side_layout(c, a);
   A.contrib = a->path_contrib;
   A.spl_hdr_in = (const SplatHdr*)((const char*)records + L.spl_hdr);
   A.spl_in = (const SplatRec*)((const char*)records + L.spl);

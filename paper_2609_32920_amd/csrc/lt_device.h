@@ -93,6 +93,58 @@ __device__ __forceinline__ f3 vmf_dir(f3 mu, float kap, float em, float g1, floa
   return mu * t + t1 * (s * cp) + t2 * (s * sp);
 }
 
+// ------------------------------------------------------------ rough conductor
+// GGX (Trowbridge-Reitz) microfacets of roughness a about the unit normal n,
+// Smith's separable masking, reflectance F0 (the material's texel, constant
+// in angle):  D(m) = a^2 / (pi ((m.n)^2 (a^2 - 1) + 1)^2),
+// G1(v) = 2 (v.n) / ((v.n) + sqrt(a^2 + (1 - a^2)(v.n)^2)),
+// f = F0 D(h) G1(wi) G1(wo) / (4 (wi.n)(wo.n)).
+__device__ __forceinline__ float ggx_D(float cm, float a2) {
+  float d = cm * cm * (a2 - 1.0f) + 1.0f;
+  return a2 * 0.318309886183790672f / (d * d);
+}
+__device__ __forceinline__ float ggx_G1(float cv, float a2) { return 2.0f * cv / (cv + sqrtf(a2 + (1.0f - a2) * cv * cv)); }
+
+// f (wc.n) / F0 = D(h) G1(wi) G1(wc) / (4 wi.n) of a sensor connection
+__device__ __forceinline__ float ggx_conn(f3 wi, f3 wc, f3 n, float a) {
+  const float a2 = a * a;
+  f3 h = normalize(wi + wc);
+  float ci = dot(wi, n);
+  return ggx_D(dot(h, n), a2) * ggx_G1(ci, a2) * ggx_G1(dot(wc, n), a2) / (4.0f * ci);
+}
+
+// Local microfacet normal drawn with density D(m)(m.n) from (u0, u1):
+// tan^2 theta = a^2 u0 / (1 - u0), phi = 2 pi u1.
+__device__ __forceinline__ void ggx_local(float a, float u0, float u1, float& lx, float& ly, float& lz) {
+  float t2 = a * a * u0 / (1.0f - u0);
+  lz = 1.0f / sqrtf(1.0f + t2);
+  float st = sqrtf(t2) * lz;
+  lx = st * cospif(2.0f * u1);
+  ly = st * sinpif(2.0f * u1);
+}
+
+// Reflection of wi (unit, away from the surface, wi.n > 0) about the drawn
+// microfacet normal held in the local frame of n: wo and the weight
+// f (wo.n) / p over F0 = G1(wi) G1(wo) (wi.m) / ((wi.n)(m.n)).  Returns 7
+// when wi does not see the microfacet, 8 when wo leaves below n or on the
+// far side of the geometric normal ng (side_in = +1: arrived on the +ng
+// side), else 0.
+__device__ __forceinline__ int conductor_scatter(f3 wi, f3 n, f3 ng, float side_in, float a, float u0, float u1,
+                                                 f3& wo, float& wgt) {
+  float lx, ly, lz;
+  ggx_local(a, u0, u1, lx, ly, lz);
+  f3 t1, t2; onb(n, t1, t2);
+  f3 m = t1 * lx + t2 * ly + n * lz;
+  float cwm = dot(wi, m);
+  if (!(cwm > 0.0f)) return 7;
+  wo = m * (2.0f * cwm) - wi;
+  float co = dot(wo, n);
+  if (!(co > 0.0f) || !(dot(wo, ng) * side_in > 0.0f)) return 8;
+  const float a2 = a * a, ci = dot(wi, n);
+  wgt = ggx_G1(ci, a2) * ggx_G1(co, a2) * cwm / (ci * lz);
+  return 0;
+}
+
 // ------------------------------------------------------------ diffuse guide
 // A guide-table entry: the folded vMF mixture of the learned guide at one
 // side of one albedo texel, 16 float4.  Lobe k: [2k] = (mean direction,
@@ -364,9 +416,12 @@ __device__ __forceinline__ int texel_of(const DevScene& sc, const Surf& s, int t
 // the camera sees x from the side the light arrived on, unoccluded.
 // visible = true: the caller already knows the shadow ray is unoccluded
 // (a replay of a connection found valid earlier); the test is skipped.
+// A conductor vertex passes its arrival-side shading normal na and
+// roughness a: the camera must lie on na's side too, and g carries the
+// microfacet factor instead of the Lambertian cos / pi.
 __device__ __forceinline__ bool connect(const DevScene& sc, const Surf& s, f3 w_in, float Kfilm,
                                         float& ux, float& uy, float& g, int* stk, int ss,
-                                        bool visible = false) {
+                                        bool visible = false, const f3* na = nullptr, float a = 0.f) {
   f3 cpos = ld3(sc.cpos);
   f3 dv = s.x - cpos;
   float zc = dot(dv, ld3(sc.cf));
@@ -381,14 +436,19 @@ __device__ __forceinline__ bool connect(const DevScene& sc, const Surf& s, f3 w_
   float cg = dot(s.ng, wc);
   float cos_in = dot(w_in, s.ng);
   if (!(cg * (-cos_in) > 0.0f)) return false;
+  if (na && !(dot(*na, wc) > 0.0f)) return false;
   f3 so = s.x + s.ng * (cg >= 0.0f ? kEps : -kEps);
   f3 sd = cpos - so;
   float sl = sqrtf(dot(sd, sd));
   sd = sd * (1.0f / sl);
   if (!visible && any_hit(sc, so, sd, kTmin, sl * (1.0f - 1e-4f), stk, ss)) return false;
   float cosc = zc / dist;
-  float cosx = fabsf(dot(s.ng, dv)) / dist;
-  g = 0.31830988618379067f * Kfilm * cosx / (cosc * cosc * cosc * dist2);
+  if (na) {
+    g = Kfilm * ggx_conn(w_in * -1.0f, wc, *na, a) / (cosc * cosc * cosc * dist2);
+  } else {
+    float cosx = fabsf(dot(s.ng, dv)) / dist;
+    g = 0.31830988618379067f * Kfilm * cosx / (cosc * cosc * cosc * dist2);
+  }
   return true;
 }
 

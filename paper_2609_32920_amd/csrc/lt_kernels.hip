@@ -25,13 +25,16 @@ inline namespace counted {
 // connection geometry and the sampling of the next direction.
 struct Event {
   int prim;        // hit primitive, -1 on a miss
-  int kind;        // 0 path ended at this hit (miss/absorber), 1 Lambertian, 2 dielectric
+  int kind;        // 0 path ended at this hit (miss/absorber), 1 Lambertian or rough
+                   // conductor (a texel, a connection, a scatter linear in rho), 2 dielectric
+  bool cond;       // kind 1 on a rough conductor
   int texel;       // Lambertian texel
   f3 rho;          // Lambertian albedo
   bool valid;      // sensor connection exists
   float ux, uy, g; // film position and connection factor (C = beta rho g)
   float cos_in;
-  int lobe, fail;  // dielectric: lobe 2 reflect / 4 refract, fail 7/8
+  int lobe, fail;  // dielectric: lobe 2 reflect / 4 refract, fail 7/8; conductor: fail 9
+                   // (arrived behind its shading normal), 7/8 (no reflection)
   bool cont;       // the path continues with the updated ray
   float u_res;     // reservoir uniform of this vertex
   int slot;        // hit triangle in BVH order
@@ -55,7 +58,7 @@ __device__ __forceinline__ Event bounce(const PassArgs& A, uint32_t path, int j,
                                         int* stk, int ss) {
   const DevScene& sc = A.sc;
   Event ev;
-  ev.prim = -1; ev.kind = 0; ev.texel = -1; ev.rho = {0.f, 0.f, 0.f}; ev.valid = false;
+  ev.prim = -1; ev.kind = 0; ev.cond = false; ev.texel = -1; ev.rho = {0.f, 0.f, 0.f}; ev.valid = false;
   ev.ux = ev.uy = ev.g = 0.f; ev.lobe = 0; ev.fail = 0; ev.cont = false; ev.u_res = 1.0f; ev.cos_in = 0.f;
   ev.slot = -1; ev.x = {0.f, 0.f, 0.f}; ev.illc = false; ev.gw = 1.0f; ev.gq = 0.f; ev.gcomp = 0;
   Hit h = closest_hit(sc, ray_origin(r), r.w, kTmin, 3.0e38f, stk, ss);
@@ -72,16 +75,36 @@ __device__ __forceinline__ Event bounce(const PassArgs& A, uint32_t path, int j,
   // segment direction carries position rounding amplified by 1/length)
   f3 seg = s.x - r.x;
   ev.illc = fabsf(ev.cos_in) < 0.02f || dot(seg, seg) < 4e-4f;
-  u4f u = (mt == 1 || j < A.D) ? rng4(A.seed, path, (uint32_t)j, 0u) : u4f{0.f, 0.f, 0.f, 1.f};
+  u4f u = (mt != 2 || j < A.D) ? rng4(A.seed, path, (uint32_t)j, 0u) : u4f{0.f, 0.f, 0.f, 1.f};
   ev.u_res = u.u3;
-  if (mt == 1) {
+  if (mt == 1 || mt == 3) {
     ev.kind = 1;
+    ev.cond = mt == 3;
     ev.texel = texel_of(sc, s, sc.mat_tex[mat]);
     ev.rho = ld3(A.albedo + (size_t)ev.texel * 3);
-    if (cmode) ev.valid = connect(sc, s, r.w, A.Kfilm, ev.ux, ev.uy, ev.g, stk, ss, cmode == 2);
+    f3 nc = s.ng;  // conductor: arrival-side shading normal
+    float rough = 0.f;
+    if (ev.cond) {
+      rough = sc.mat_ior[mat];
+      f3 ns = s.prim >= sc.n_static ? hf_shading_normal(sc, A.heights, A.nmap, s) : s.ng;
+      nc = ev.cos_in < 0.0f ? ns : ns * -1.0f;
+      if (!(dot(r.w, nc) < 0.0f)) { ev.fail = 9; return ev; }
+    }
+    if (cmode)
+      ev.valid = connect(sc, s, r.w, A.Kfilm, ev.ux, ev.uy, ev.g, stk, ss, cmode == 2, ev.cond ? &nc : nullptr, rough);
     // the tent filter has kinks where u - 1/2 is an integer: within 1e-3 px
     // of one the splat-position derivative is one-sided (rounding picks the side)
     if (ev.valid && (near_kink(ev.ux) || near_kink(ev.uy))) ev.illc = true;
+    if (j < A.D && ev.cond) {
+      f3 wo;
+      float wgt;
+      int code = conductor_scatter(r.w * -1.0f, nc, s.ng, ev.cos_in < 0.0f ? 1.0f : -1.0f, rough, u.u0, u.u1, wo, wgt);
+      if (code) { ev.fail = code; return ev; }
+      ev.gw = wgt;
+      r.w = wo; r.x = s.x; r.offn = s.ng; r.off = true;
+      ev.cont = true;
+      return ev;
+    }
     if (j < A.D) {
       f3 na = ev.cos_in < 0.0f ? s.ng : s.ng * -1.0f;
       const float4* ge = A.gtab ? A.gtab + (size_t)(2 * ev.texel + (ev.cos_in < 0.0f ? 0 : 1)) * kGTabF4 : nullptr;
@@ -128,7 +151,9 @@ __device__ __forceinline__ uint32_t sig_event(uint32_t h, const Event& ev) {
   h = fnv1a(h, (uint32_t)ev.prim + 1u);
   if (ev.kind == 1) {
     h = fnv1a(h, (uint32_t)ev.texel + 1u);
+    if (ev.fail == 9) return fnv1a(h, 9u);
     h = fnv1a(h, ev.valid ? 1u : 0u);
+    if (ev.fail) h = fnv1a(h, (uint32_t)ev.fail);
   } else if (ev.kind == 2) {
     if (ev.fail == 7) return fnv1a(h, 7u);
     if (ev.lobe) h = fnv1a(h, (uint32_t)ev.lobe);
