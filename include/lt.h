@@ -94,8 +94,11 @@ typedef struct lt_ctx lt_ctx;
  *                         vertices connect to the sensor, and scatter by
  *                         reflecting about a microfacet normal drawn with density
  *                         D(m)(m.n) from the vertex's first two uniforms, weight
- *                         F0 G1(wi) G1(wo) (wi.m) / ((wi.n)(m.n)).  Detached
- *                         passes only (LT_ATTACHED returns LT_ERR_UNSUPPORTED).
+ *                         F0 G1(wi) G1(wo) (wi.m) / ((wi.n)(m.n)).  Attached
+ *                         passes hold the microfacet normal in the local frame of
+ *                         the shading normal; the weight and the connection then
+ *                         carry derivatives w.r.t. the heights (attached batches
+ *                         reject conductor scenes).
  *  n_tex, tex_res         albedo parameters are [n_tex][tex_res][tex_res][3]
  *  emitter: quad (o, e1, e2; one-sided, normal normalize(e1 x e2)), point (o) or
  *          directional quad (o, e1, e2; the beam leaves along the normal, radiance
@@ -253,9 +256,12 @@ lt_status lt_read_counters(lt_ctx* ctx, uint64_t* out16, int reset);
 lt_status lt_scene_upload(lt_ctx* ctx, const lt_scene_desc* scene);
 
 /* Bytes of caller-provided side state lt_trace writes for these args:
- * LT_RECORD_TAPE: the naive-AD tape, N*D records (linear in depth) plus one
- * path length per path; LT_RECORD_RESERVOIR: one ResLRB record per path
- * (Sec. 4.2.1: selected depth R, weight Omega_k/w_R, u_R, reweighted splat);
+ * LT_RECORD_TAPE: the naive-AD tape, N*D records (32 bytes, 128 attached;
+ * linear in depth) plus one path length per path, and with a diffuse guide
+ * or rough conductors in the scene (detached) a 4-byte scatter weight per
+ * record; LT_RECORD_RESERVOIR: one ResLRB record per path (Sec. 4.2.1:
+ * selected depth R, weight Omega_k/w_R, u_R, reweighted splat; 32 bytes, 160
+ * attached);
  * LT_RECORD_SPLATS: the buffered two-pass buffer, a 16-byte header per path
  * (last connection depth, one validity bit per vertex) and a 20-byte record
  * (u_i, C_i) for every vertex up to max_depth, preallocated (linear in

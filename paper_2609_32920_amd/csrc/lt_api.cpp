@@ -335,8 +335,6 @@ lt_status check_args(lt_ctx* c, const lt_trace_args* a, const lt_params* p) {
   if (p->normal_map && (c->dsc.hf_G < 2 || !p->heights))
     return c->fail(LT_ERR_ARG, "a normal map needs a heightfield and params->heights%s");
   if (p->guide_w && c->dsc.em_type != LT_EMIT_QUAD) return c->fail(LT_ERR_UNSUPPORTED, "the emission guide needs an area emitter%s");
-  if (c->has_conductor && (a->flags & LT_ATTACHED))
-    return c->fail(LT_ERR_UNSUPPORTED, "rough conductors are supported by detached passes only%s");
   if (c->dsc.em_tex_res > 0 && (a->flags & LT_ATTACHED))
     return c->fail(LT_ERR_UNSUPPORTED, "a textured emitter is supported by detached passes only%s");
   if (c->dsc.em_tex_res > 0 && p->guide_w)
@@ -464,6 +462,7 @@ PassArgs base_args(lt_ctx* c, const lt_trace_args* a, const lt_params* p) {
   A.Le = p->emitter_L;
   A.heights = p->heights;
   A.nmap = p->normal_map;
+  A.cond = c->has_conductor ? 1 : 0;
   A.counter = c->d_counter;
   A.stats = reinterpret_cast<unsigned long long*>(c->d_counter + 16);  // same allocation, byte 64
   return A;
@@ -1276,6 +1275,8 @@ lt_status batch_check(lt_batch* b, const lt_instance* inst, int n) {
     if (!c) return b->fail(LT_ERR_ARG, "instance without a context");
     if (c->device != b->device) return b->fail(LT_ERR_ARG, "instance context on another device");
     if (I.args.flags & ~(uint32_t)LT_ATTACHED) return b->fail(LT_ERR_UNSUPPORTED, "batches take flags 0 or LT_ATTACHED only");
+    if ((I.args.flags & LT_ATTACHED) && c->has_conductor)
+      return b->fail(LT_ERR_UNSUPPORTED, "attached batches take no rough-conductor scenes");
     if (I.args.path_sig || I.args.path_info || I.args.path_contrib)
       return b->fail(LT_ERR_UNSUPPORTED, "batches take no signatures, info or contributions");
     lt_status st = check_args(c, &I.args, &I.params);

@@ -40,7 +40,7 @@ struct alignas(16) TapeRec {
 static_assert(sizeof(TapeRec) == 32, "tape layout");
 constexpr uint32_t kTexMask = (1u << 27) - 1u;
 constexpr uint32_t kTfLambert = 1u << 27, kTfValid = 1u << 28, kTfScatter = 1u << 29,
-                   kTfDielectric = 1u << 30;
+                   kTfDielectric = 1u << 30, kTfConductor = 1u << 31;
 
 // ResLRB per-path record (Sec. 4.2.1): selected depth R (0 = none), weight
 // Omega_k/omega_R, film position u_R and the reweighted splat S_hat.
@@ -91,10 +91,13 @@ struct alignas(16) ResRecAtt {
   int32_t slot;
   float v0, v1;
   float br[3];
-  float pad[2];
+  int32_t slot_p;       // chart of x_{R-1} (slot -1: the emitter), for a conductor at x_R
+  float vp0, vp1;
+  float gw[4];          // sum over the rough-conductor scatters before R of d log w_s / d p_s M_s
   float M[16];
+  float pad[3];
 };
-static_assert(sizeof(ResRecAtt) == 128, "attached reservoir record layout");
+static_assert(sizeof(ResRecAtt) == 160, "attached reservoir record layout");
 
 // LRB-3 hand-off between the two replays (Sec. 4.3: the per-sample state of
 // the method), one entry per path that has a sensor connection, appended by

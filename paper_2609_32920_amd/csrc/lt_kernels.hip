@@ -1069,7 +1069,7 @@ __global__ void __launch_bounds__(1024) k_lrb3_batch(const PassArgs* __restrict_
 }
 __global__ void __launch_bounds__(256, 2) k_lrb3_att_batch(const PassArgs* __restrict__ T, int n) {
   extern __shared__ int lds[];
-  for (int i = 0; i < n; ++i) lrb3_att_run(table_entry(T, i), lds);
+  for (int i = 0; i < n; ++i) lrb3_att_run<false>(table_entry(T, i), lds);
 }
 // One attached entry of the table, at the single-instance kernel's three
 // waves per SIMD and workgroup sizes (the loop over entries above costs
@@ -1078,7 +1078,7 @@ __global__ void __launch_bounds__(256, 2) k_lrb3_att_batch(const PassArgs* __res
 // table, so a replayed graph reads each step's seeds.
 __global__ void __launch_bounds__(768, 3) k_lrb3_att_entry(const PassArgs* __restrict__ T) {
   extern __shared__ int lds[];
-  lrb3_att_run(table_entry(T, 0), lds);
+  lrb3_att_run<false>(table_entry(T, 0), lds);
 }
 
 #ifdef LT_COUNTERS
@@ -1094,11 +1094,11 @@ static size_t agrad_bytes(const PassArgs& A) { return A.agrad_lds ? (size_t)A.n_
 
 // allow the backward kernels the device's full LDS per workgroup
 hipError_t set_lds_limit(int bytes) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_lrb3_att, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_reslrb_att, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_naive_att_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  hipError_t e = hipSuccess;
+  for (const void* f : {(const void*)k_lrb3_att<false>, (const void*)k_lrb3_att<true>, (const void*)k_reslrb_att<false>,
+                        (const void*)k_reslrb_att<true>, (const void*)k_naive_att_bwd<false>,
+                        (const void*)k_naive_att_bwd<true>})
+    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_lrb3_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_reslrb_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_naive_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
@@ -1107,8 +1107,9 @@ hipError_t set_lds_limit(int bytes) {
     e = hipFuncSetAttribute((const void*)k_lrb3_att_batch, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_lrb3_att_entry, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  for (const void* f : {(const void*)k_lrb3_p2, (const void*)k_lrb3_p3, (const void*)k_lrb3_att_p2,
-                        (const void*)k_lrb3_att_p3, (const void*)k_lrb2_bwd})
+  for (const void* f : {(const void*)k_lrb3_p2, (const void*)k_lrb3_p3, (const void*)k_lrb3_att_p2<false>,
+                        (const void*)k_lrb3_att_p3<false>, (const void*)k_lrb3_att_p2<true>,
+                        (const void*)k_lrb3_att_p3<true>, (const void*)k_lrb2_bwd})
     if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   return e;
 }
@@ -1130,16 +1131,16 @@ int resident_groups(BwdKernel k, int block, size_t lds) {
     case BwdKernel::naive: f = (const void*)k_naive_bwd; break;
     case BwdKernel::reslrb: f = (const void*)k_reslrb_bwd; break;
     case BwdKernel::lrb3: f = (const void*)k_lrb3_bwd; break;
-    case BwdKernel::naive_att: f = (const void*)k_naive_att_bwd; break;
-    case BwdKernel::reslrb_att: f = (const void*)k_reslrb_att; break;
-    case BwdKernel::lrb3_att: f = (const void*)k_lrb3_att; break;
+    case BwdKernel::naive_att: f = (const void*)k_naive_att_bwd<false>; break;
+    case BwdKernel::reslrb_att: f = (const void*)k_reslrb_att<false>; break;
+    case BwdKernel::lrb3_att: f = (const void*)k_lrb3_att<false>; break;
     case BwdKernel::lrb3_batch: f = (const void*)k_lrb3_batch; break;
     case BwdKernel::lrb3_att_batch: f = (const void*)k_lrb3_att_batch; break;
     case BwdKernel::lrb3_att_entry: f = (const void*)k_lrb3_att_entry; break;
     case BwdKernel::lrb3_p2: f = (const void*)k_lrb3_p2; break;
     case BwdKernel::lrb3_p3: f = (const void*)k_lrb3_p3; break;
-    case BwdKernel::lrb3_att_p2: f = (const void*)k_lrb3_att_p2; break;
-    case BwdKernel::lrb3_att_p3: f = (const void*)k_lrb3_att_p3; break;
+    case BwdKernel::lrb3_att_p2: f = (const void*)k_lrb3_att_p2<false>; break;
+    case BwdKernel::lrb3_att_p3: f = (const void*)k_lrb3_att_p3<false>; break;
     case BwdKernel::lrb2: f = (const void*)k_lrb2_bwd; break;
   }
   int n = 0;
@@ -1153,23 +1154,26 @@ int resident_groups(BwdKernel k, int block, size_t lds) {
 }
 
 hipError_t launch_lrb3_att(const PassArgs& A, int grid, int block, hipStream_t s) {
-  hipLaunchKernelGGL(k_lrb3_att, dim3(grid), dim3(block), stack_bytes(A, block) + hgrad_bytes(A) + agrad_bytes(A), s,
+  hipLaunchKernelGGL(A.cond ? k_lrb3_att<true> : k_lrb3_att<false>, dim3(grid), dim3(block), stack_bytes(A, block) + hgrad_bytes(A) + agrad_bytes(A), s,
                      A);
   return hipGetLastError();
 }
 hipError_t launch_trace_att(const PassArgs& A, bool tape, bool resv, int grid, hipStream_t s) {
   size_t sh = stack_bytes(A, 256);
-  if (tape && resv) hipLaunchKernelGGL((k_trace_att<true, true>), dim3(grid), dim3(256), sh, s, A);
+  if (tape && resv && A.cond) hipLaunchKernelGGL((k_trace_att<true, true, true>), dim3(grid), dim3(256), sh, s, A);
+  else if (tape && resv) hipLaunchKernelGGL((k_trace_att<true, true>), dim3(grid), dim3(256), sh, s, A);
+  else if (tape && A.cond) hipLaunchKernelGGL((k_trace_att<true, false, true>), dim3(grid), dim3(256), sh, s, A);
   else if (tape) hipLaunchKernelGGL((k_trace_att<true, false>), dim3(grid), dim3(256), sh, s, A);
+  else if (A.cond) hipLaunchKernelGGL((k_trace_att<false, true, true>), dim3(grid), dim3(256), sh, s, A);
   else hipLaunchKernelGGL((k_trace_att<false, true>), dim3(grid), dim3(256), sh, s, A);
   return hipGetLastError();
 }
 hipError_t launch_naive_att_bwd(const PassArgs& A, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_naive_att_bwd, dim3(grid), dim3(256), hgrad_bytes(A) + agrad_bytes(A), s, A);
+  hipLaunchKernelGGL(A.cond ? k_naive_att_bwd<true> : k_naive_att_bwd<false>, dim3(grid), dim3(256), hgrad_bytes(A) + agrad_bytes(A), s, A);
   return hipGetLastError();
 }
 hipError_t launch_reslrb_att(const PassArgs& A, int grid, int block, hipStream_t s) {
-  hipLaunchKernelGGL(k_reslrb_att, dim3(grid), dim3(block), stack_bytes(A, block) + hgrad_bytes(A) + agrad_bytes(A), s,
+  hipLaunchKernelGGL(A.cond ? k_reslrb_att<true> : k_reslrb_att<false>, dim3(grid), dim3(block), stack_bytes(A, block) + hgrad_bytes(A) + agrad_bytes(A), s,
                      A);
   return hipGetLastError();
 }
@@ -1258,11 +1262,11 @@ hipError_t launch_lrb3_p3(const PassArgs& A, int grid, int block, hipStream_t s)
   return hipGetLastError();
 }
 hipError_t launch_lrb3_att_p2(const PassArgs& A, int grid, int block, hipStream_t s) {
-  hipLaunchKernelGGL(k_lrb3_att_p2, dim3(grid), dim3(block), stack_bytes(A, block), s, A);
+  hipLaunchKernelGGL(A.cond ? k_lrb3_att_p2<true> : k_lrb3_att_p2<false>, dim3(grid), dim3(block), stack_bytes(A, block), s, A);
   return hipGetLastError();
 }
 hipError_t launch_lrb3_att_p3(const PassArgs& A, int grid, int block, hipStream_t s) {
-  hipLaunchKernelGGL(k_lrb3_att_p3, dim3(grid), dim3(block), stack_bytes(A, block) + hgrad_bytes(A) + agrad_bytes(A),
+  hipLaunchKernelGGL(A.cond ? k_lrb3_att_p3<true> : k_lrb3_att_p3<false>, dim3(grid), dim3(block), stack_bytes(A, block) + hgrad_bytes(A) + agrad_bytes(A),
                      s, A);
   return hipGetLastError();
 }

@@ -47,6 +47,7 @@ struct PassArgs {
   int32_t agrad_lds;          // albedo gradients accumulated per workgroup in LDS
   const float4* guide_rec;    // guided emission (direction, density) per path, or null
   const float4* gtab;         // diffuse guide table [2 n_texels][16], or null (cosine scatter)
+  int32_t cond;               // the scene has rough conductors: attached kernels carry their terms
   float* tape_gw;             // naive tape with a diffuse guide: scatter weight [D][n_paths]
   const float* tape_gw_in;
   float* gsamp;               // diffuse guide training samples [n_paths][12], or null

@@ -101,7 +101,7 @@ def test_attached_side_state_sizes(caustic16):
     res = [g.ctx.side_state_bytes(g.ctx.args(1, n, d, lt.ATTACHED | lt.RECORD_RESERVOIR)) for d in (3, 6, 12)]
     base = [t - 128 * n * d for t, d in zip(tape, (3, 6, 12))]
     assert base[0] == base[1] == base[2]          # 128 B per vertex: linear in depth
-    assert res[0] == res[1] == res[2] == 128 * n  # one record per path: flat in depth
+    assert res[0] == res[1] == res[2] == 160 * n  # one record per path: flat in depth
 
 
 @pytest.mark.parametrize("mode", ["lrb3", "reslrb", "lrb3_fused"])

@@ -1,7 +1,8 @@
 """GPU parity of the rough conductor (the roughened mirror of the paper's
 attached validation, Sec. 6.1) against the FP64 oracle on the same seeded
-paths: forward images and the detached gradients of the albedo and
-reflectance texels in every reverse mode (bar 1e-4, FP32 against FP64)."""
+paths: forward images, the detached gradients of the albedo and reflectance
+texels, and the attached gradients w.r.t. the mirror's heights, in every
+reverse mode (bar 1e-4, FP32 against FP64)."""
 import numpy as np
 import pytest
 
@@ -55,8 +56,29 @@ def test_mirror_detached_parity(mirror):
         assert ea <= TOL and el <= TOL, (mode, split)
 
 
-def test_mirror_attached_is_rejected_until_supported(mirror):
+@pytest.mark.parametrize("mode,split", [("naive", 2), ("reslrb", 2), ("lrb3", 2), ("lrb3", 0)])
+def test_mirror_attached_parity(mirror, mode, split):
+    """Attached gradients w.r.t. the mirror's heights (its vertex positions):
+    the conductor's scatter weight and sensor connection carry geometric
+    derivatives, so every replay mode adds their radiance-channel terms."""
+    from tests.gpu_common import matched_paths, maxrel
     sc, g = mirror
-    with pytest.raises(lt.LTError) as e:
-        g.backward("lrb3", 1, 1024, 4, np.zeros((64, 64, 3)), flags=lt.ATTACHED)
-    assert e.value.status == lt.LT_ERR_UNSUPPORTED
+    seed, n, D = 9, 1 << 16, 4
+    mask, ids, mis, illc = matched_paths(sc, g, seed, n, D, want_illc=True)
+    assert mis <= 1e-3
+    dI = np.random.default_rng(8).normal(size=(64, 64, 3))
+    g.ctx.set_tuning(lrb3_split=split)
+    try:
+        first = g.backward(mode, seed, n, D, dI, flags=lt.ATTACHED, mask=mask, want_info=True)
+        bad = ((first["info"] & 3) != 0) | illc
+        print(f"mirror attached {mode} (split {split}): flagged {bad.mean():.2e}", flush=True)
+        assert bad.mean() <= 5e-2
+        keep = mask.astype(bool) & ~bad
+        gg = g.backward(mode, seed, n, D, dI, flags=lt.ATTACHED, mask=keep.astype(np.uint8))
+    finally:
+        g.ctx.set_tuning()
+    og = O.gradient(sc, seed, n, D, dI, flags=O.ATTACHED, mode=O.MODE_RESLRB if mode == "reslrb" else O.MODE_NAIVE,
+                    path_list=np.nonzero(keep)[0].astype(np.uint32))
+    eh, ea, el = (maxrel(gg[k], og[k]) for k in ("heights", "albedo", "Le"))
+    print(f"mirror attached {mode} (split {split}): heights {eh:.2e} albedo/F0 {ea:.2e} Le {el:.2e}", flush=True)
+    assert eh <= TOL and ea <= TOL and el <= TOL
