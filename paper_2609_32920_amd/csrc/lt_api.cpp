@@ -1216,6 +1216,9 @@ struct lt_batch {
   unsigned int* d_cnt = nullptr;      // work-ticket counters [2n]
   double* d_acc = nullptr;            // per instance: emitter gradient (3) + loss (1)
   size_t inst_cap = 0;
+  char* d_hand = nullptr;             // LRB-3 hand-off of the solo attached instances, one at a time
+  size_t hand_cap = 0;                // bytes
+  unsigned int* d_hcnt = nullptr;     // their hand-off counters [2n]
   // captured step
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1236,10 +1239,10 @@ struct lt_batch {
 
 namespace {
 
-// Attached instances of at least this many paths run their backward as a
-// launch of their own (the one-entry kernel, three waves per SIMD against the
-// multi-entry kernel's two); at that size a launch's tail and gap are small
-// against its work.
+// Attached instances of at least this many paths run their backward as
+// launches of their own (the two-kernel LRB-3 of the single-instance call,
+// three waves per SIMD against the multi-entry kernel's two); at that size a
+// launch's tail and gap are small against its work.
 constexpr int64_t kSoloPaths = (int64_t)1 << 20;
 
 struct BatchPlan {
@@ -1299,13 +1302,27 @@ lt_status batch_reserve(lt_batch* b, const lt_instance* inst, int n) {
     b->tab_cap = need;
   }
   if (b->inst_cap < (size_t)n) {
-    hipFree(b->d_cnt); hipFree(b->d_acc); b->d_cnt = nullptr; b->d_acc = nullptr; b->inst_cap = 0;
+    hipFree(b->d_cnt); hipFree(b->d_acc); hipFree(b->d_hcnt);
+    b->d_cnt = nullptr; b->d_acc = nullptr; b->d_hcnt = nullptr; b->inst_cap = 0;
     if (hipMalloc((void**)&b->d_cnt, (size_t)2 * n * sizeof(unsigned int)) != hipSuccess ||
-        hipMalloc((void**)&b->d_acc, (size_t)4 * n * sizeof(double)) != hipSuccess) {
+        hipMalloc((void**)&b->d_acc, (size_t)4 * n * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&b->d_hcnt, (size_t)2 * n * sizeof(unsigned int)) != hipSuccess) {
       (void)hipGetLastError();
       return b->fail(LT_ERR_OOM, "out of device memory for the batch counters");
     }
     b->inst_cap = n;
+  }
+  size_t hand = 0;  // the largest solo instance's hand-off
+  for (int i = 0; i < n; ++i)
+    if ((inst[i].args.flags & LT_ATTACHED) && inst[i].args.n_paths >= kSoloPaths)
+      hand = std::max(hand, (size_t)inst[i].args.n_paths * sizeof(Lrb3HandAtt));
+  if (b->hand_cap < hand) {
+    hipFree(b->d_hand); b->d_hand = nullptr; b->hand_cap = 0;
+    if (hipMalloc((void**)&b->d_hand, hand) != hipSuccess) {
+      (void)hipGetLastError();
+      return b->fail(LT_ERR_OOM, "out of device memory for the LRB-3 hand-off");
+    }
+    b->hand_cap = hand;
   }
   for (int i = 0; i < n; ++i) {
     lt_ctx* c = inst[i].ctx;
@@ -1388,16 +1405,21 @@ BatchPlan batch_plan(lt_batch* b, const lt_instance* inst, int n, int64_t path_d
     B.hgrad_lds = h && h <= P.att_lds;
     B.agrad_lds = t && t + (B.hgrad_lds ? h : 0) <= P.att_lds;
   }
-  // a solo launch takes the single-instance call's workgroup size and each
-  // copy that fits and costs it no resident workgroups
-  for (int i : P.solo) {
+  // a solo instance runs the single-instance call's two kernels: pass 3 takes
+  // that call's workgroup size and each copy that fits and costs it no
+  // resident workgroups; the hand-off goes through the batch's buffer
+  for (size_t k = 0; k < P.solo.size(); ++k) {
+    const int i = P.solo[k];
     PassArgs& B = P.tab[n + i];
-    const int blk = att_replay_block(inst[i].ctx, inst[i].grads.heights, P.stack_n, BwdKernel::lrb3_att_entry, 768);
+    B.hand_att = reinterpret_cast<Lrb3HandAtt*>(b->d_hand);
+    B.hand_n = b->d_hcnt + 2 * k;
+    B.hand_ticket = b->d_hcnt + 2 * k + 1;
+    const int blk = att_replay_block(inst[i].ctx, inst[i].grads.heights, P.stack_n, BwdKernel::lrb3_att_p3_entry, 768);
     const size_t stack = (size_t)P.stack_n * blk * sizeof(int);
     auto free_of_cost = [&](size_t extra) {
       if (stack + extra > lds_max) return false;
-      int r = resident_groups(BwdKernel::lrb3_att_entry, blk, stack + extra);
-      return r > 0 && r >= resident_groups(BwdKernel::lrb3_att_entry, blk, stack);
+      int r = resident_groups(BwdKernel::lrb3_att_p3_entry, blk, stack + extra);
+      return r > 0 && r >= resident_groups(BwdKernel::lrb3_att_p3_entry, blk, stack);
     };
     size_t h = hf_bytes(inst[i]), t = tex_bytes(inst[i].ctx);
     B.hgrad_lds = h && free_of_cost(h);
@@ -1459,10 +1481,16 @@ lt_status batch_enqueue_on(lt_batch* b, const lt_instance* inst, const BatchPlan
                      "batched attached backward")) != LT_OK)
       return st;
   }
+  if (!P.solo.empty() &&
+      (st = b->hip(launch_fill_u32(b->d_hcnt, 2 * P.solo.size(), 0u, s), "hand-off clear")) != LT_OK)
+    return st;
   for (size_t k = 0; k < P.solo.size(); ++k) {
     const int e = n + nd + na + (int)k;
-    const int grid_one = persistent_grid(inst[P.solo[k]].ctx, P.tab[e].n_paths, P.solo_block[k]);
-    if ((st = b->hip(launch_lrb3_att_entry(b->d_tab + e, P.stack_n, P.solo_lds[k], grid_one, P.solo_block[k], s),
+    const lt_ctx* c = inst[P.solo[k]].ctx;
+    const int grid2 = persistent_grid(c, P.tab[e].n_paths, 256);
+    const int grid3 = persistent_grid(c, P.tab[e].n_paths, P.solo_block[k]);
+    if ((st = b->hip(launch_lrb3_att_split_entry(b->d_tab + e, P.stack_n, P.solo_lds[k], grid2, grid3,
+                                                 P.solo_block[k], s),
                      "attached backward")) != LT_OK)
       return st;
   }
@@ -1596,6 +1624,8 @@ void lt_batch_destroy(lt_batch* b) {
   hipFree(b->d_tab);
   hipFree(b->d_cnt);
   hipFree(b->d_acc);
+  hipFree(b->d_hcnt);
+  hipFree(b->d_hand);
   delete b;
 }
 

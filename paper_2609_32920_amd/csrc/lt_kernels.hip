@@ -1081,6 +1081,18 @@ __global__ void __launch_bounds__(768, 3) k_lrb3_att_entry(const PassArgs* __res
   lrb3_att_run<false>(table_entry(T, 0), lds);
 }
 
+// The two-kernel attached LRB-3 reading one table entry: batches run their
+// large attached instances through this pair, as the single-instance call
+// does (the hand-off buffer and its counters are in the entry).
+__global__ void __launch_bounds__(768, 3) k_lrb3_att_p2_entry(const PassArgs* __restrict__ T) {
+  extern __shared__ int lds[];
+  lrb3_att_p2_run<false>(table_entry(T, 0), lds);
+}
+__global__ void __launch_bounds__(768, 3) k_lrb3_att_p3_entry(const PassArgs* __restrict__ T) {
+  extern __shared__ int lds[];
+  lrb3_att_p3_run<false>(table_entry(T, 0), lds);
+}
+
 #ifdef LT_COUNTERS
 }  // namespace counted
 #endif
@@ -1107,7 +1119,8 @@ hipError_t set_lds_limit(int bytes) {
     e = hipFuncSetAttribute((const void*)k_lrb3_att_batch, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_lrb3_att_entry, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  for (const void* f : {(const void*)k_lrb3_p2, (const void*)k_lrb3_p3, (const void*)k_lrb3_att_p2<false>,
+  for (const void* f : {(const void*)k_lrb3_att_p2_entry, (const void*)k_lrb3_att_p3_entry,
+                        (const void*)k_lrb3_p2, (const void*)k_lrb3_p3, (const void*)k_lrb3_att_p2<false>,
                         (const void*)k_lrb3_att_p3<false>, (const void*)k_lrb3_att_p2<true>,
                         (const void*)k_lrb3_att_p3<true>, (const void*)k_lrb2_bwd})
     if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
@@ -1137,6 +1150,7 @@ int resident_groups(BwdKernel k, int block, size_t lds) {
     case BwdKernel::lrb3_batch: f = (const void*)k_lrb3_batch; break;
     case BwdKernel::lrb3_att_batch: f = (const void*)k_lrb3_att_batch; break;
     case BwdKernel::lrb3_att_entry: f = (const void*)k_lrb3_att_entry; break;
+    case BwdKernel::lrb3_att_p3_entry: f = (const void*)k_lrb3_att_p3_entry; break;
     case BwdKernel::lrb3_p2: f = (const void*)k_lrb3_p2; break;
     case BwdKernel::lrb3_p3: f = (const void*)k_lrb3_p3; break;
     case BwdKernel::lrb3_att_p2: f = (const void*)k_lrb3_att_p2<false>; break;
@@ -1197,6 +1211,15 @@ hipError_t launch_lrb3_att_entry(const PassArgs* entry, int stack_n, size_t grad
                                  hipStream_t s) {
   hipLaunchKernelGGL(k_lrb3_att_entry, dim3(grid), dim3(block), (size_t)stack_n * block * sizeof(int) + grad_lds, s,
                      entry);
+  return hipGetLastError();
+}
+hipError_t launch_lrb3_att_split_entry(const PassArgs* entry, int stack_n, size_t grad_lds, int grid2, int grid3,
+                                      int block3, hipStream_t s) {
+  const size_t st2 = (size_t)stack_n * 256 * sizeof(int), st3 = (size_t)stack_n * block3 * sizeof(int);
+  hipLaunchKernelGGL(k_lrb3_att_p2_entry, dim3(grid2), dim3(256), st2, s, entry);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lrb3_att_p3_entry, dim3(grid3), dim3(block3), st3 + grad_lds, s, entry);
   return hipGetLastError();
 }
 

@@ -114,6 +114,10 @@ hipError_t launch_lrb3_att_batch(const PassArgs* table, int n, int stack_n, size
 // one attached table entry (the table pointer already offset to it)
 hipError_t launch_lrb3_att_entry(const PassArgs* entry, int stack_n, size_t grad_lds, int grid, int block,
                                  hipStream_t s);
+// the same entry through the two-kernel LRB-3 (pass 2 at 256 threads, pass 3
+// at block3 with grad_lds past its stacks)
+hipError_t launch_lrb3_att_split_entry(const PassArgs* entry, int stack_n, size_t grad_lds, int grid2, int grid3,
+                                      int block3, hipStream_t s);
 hipError_t launch_naive_bwd(const PassArgs& A, int grid, hipStream_t s);
 hipError_t launch_reslrb_bwd(const PassArgs& A, int grid, int block, hipStream_t s);
 hipError_t launch_lrb3_bwd(const PassArgs& A, int grid, int block, hipStream_t s);
@@ -138,7 +142,7 @@ hipError_t set_lds_limit(int bytes);
 // Workgroups of a backward kernel resident per CU at `block` threads and
 // `lds` dynamic LDS bytes (0 if it cannot launch or the query fails).
 enum class BwdKernel { naive, reslrb, lrb3, naive_att, reslrb_att, lrb3_att, lrb3_batch, lrb3_att_batch, lrb3_att_entry,
-                       lrb3_p2, lrb3_p3, lrb3_att_p2, lrb3_att_p3, lrb2 };
+                       lrb3_p2, lrb3_p3, lrb3_att_p2, lrb3_att_p3, lrb2, lrb3_att_p3_entry };
 int resident_groups(BwdKernel k, int block, size_t lds);
 hipError_t read_counters(uint64_t* out, bool reset, hipStream_t s);
 hipError_t launch_refit_level(Node* nodes, const Tri* tris, const int32_t* level_nodes, int n, hipStream_t s);
