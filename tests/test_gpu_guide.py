@@ -9,7 +9,8 @@ a bfloat16 rounding boundary with probability ~1e-7 / 2^-9 ~ 1e-4 per
 rounded value: about one item in twenty of a 200-activation network sees
 one flipped ulp (2^-8 relative) somewhere, which moves its outputs by
 ~1e-3 of their scale.  Outputs are therefore compared by the share of
-items that agree to FP32 rounding (most) and a bound for the rest.
+items that agree to FP32 rounding (at least 99%; measured 99.9%) and a
+bound for the rest (1e-2 of scale; measured 1e-3).
 Guided paths whose emitted direction differs beyond FP32 rounding are told
 apart like decision flips and the remaining paths must agree to 1e-4.
 """
@@ -69,8 +70,8 @@ def test_network_outputs(box):
     close = np.mean(err <= 2e-5)
     print(f"guide outputs: share within 2e-5 {close:.4f}, median {np.median(err):.2e}, max {err.max():.2e}; "
           f"median vs unrounded FP64 {np.median(err64):.2e}", flush=True)
-    assert close >= 0.85
-    assert err.max() <= 5e-2
+    assert close >= 0.99
+    assert err.max() <= 1e-2
     # the GPU follows the bfloat16 network, not the unrounded one
     assert np.median(err) * 20 < np.median(err64)
 
@@ -83,7 +84,7 @@ def test_emission_matches_oracle(caustic):
     same, gs, oe = guide_emission_match(sc, g, 11, n)
     comp_same = np.mean(gs[:, 11].astype(np.int32) == oe["comp"])
     print(f"guided emission: component agreement {comp_same:.4f}, full agreement {same.mean():.4f}", flush=True)
-    assert comp_same >= 0.99 and same.mean() >= 0.85
+    assert comp_same >= 0.999 and same.mean() >= 0.99
     np.testing.assert_allclose(gs[:, 0:3], oe["x"], atol=2e-6)
     np.testing.assert_allclose(gs[:, 3:6], np.repeat([[0.0, -1.0, 0.0]], n, 0), atol=1e-7)
     # where a flipped bfloat16 ulp moved the network's outputs (a few in 1e4)
@@ -102,7 +103,7 @@ def test_guided_detached_parity(box, mode):
     same, _, _ = guide_emission_match(sc, g, seed, n)
     mask, ids, mis = matched_paths(sc, g, seed, n, D, keep=same)
     print(f"guided box {mode}: emission agreement {same.mean():.4f}, excluded {mis:.3e}", flush=True)
-    assert same.mean() >= 0.85 and mis <= 0.15
+    assert same.mean() >= 0.99 and mis <= 0.01
     ow = g.guide.cpu().numpy().astype(np.float64)
     if mode == "naive":
         e = maxrel(g.trace(seed, n, D, mask=mask)["image"],
@@ -130,7 +131,7 @@ def test_guided_attached_parity(caustic, mode):
     seed, n, D = 31, 65536, 4
     same, _, _ = guide_emission_match(sc, g, seed, n)
     mask, ids, mis = matched_paths(sc, g, seed, n, D, keep=same)
-    assert same.mean() >= 0.85 and mis <= 0.15
+    assert same.mean() >= 0.99 and mis <= 0.01
     dI = np.random.default_rng(seed).normal(size=(64, 64, 3))
     first = g.backward(mode, seed, n, D, dI, flags=lt.ATTACHED, mask=mask, want_info=True)
     bad = (first["info"] & 3).astype(bool)   # guard fired or ill-conditioned vertex
