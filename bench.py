@@ -493,9 +493,12 @@ def bench_caustic(lt, scenes, dev, stream, bytes_per_path_fn, G=128, film=512, N
         bpp = bytes_per_path_fn(c, sample)
         t = out["lrb3"]["backward_ms"] * 1e-3
         achieved = bpp * N / t / 1e9
+        traffic = profiled_traffic("k_lrb3_att_p2_p3_caustic128_512_d6_16M.txt")
         out["lrb3_roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                 "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_path": round(bpp, 1),
-                                "traffic": profiled_traffic("k_lrb3_att_caustic128_512_d6_16M.txt"),
+                                "kernel": "k_lrb3_att_p2 + k_lrb3_att_p3",
+                                "traffic": traffic,
+                                "traffic_frac": None if traffic is None else round(traffic / t / 1e9 / HBM_PEAK_GBS, 4),
                                 "valu_issue_frac_profiled": profiled_traffic("k_lrb3_caustic128_box256_valu.txt",
                                                                              "valu_issue_frac_k_lrb3_att"),
                                 "l2_hit_rate_profiled": profiled_traffic("k_lrb3_caustic128_box256_valu.txt",
