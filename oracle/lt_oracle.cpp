@@ -15,6 +15,14 @@
 //  * the ResLRB estimator's gradient: the same tape seeded only at the
 //    reservoir-selected connection R with the weight Omega_k / omega_R held
 //    fixed (Sec. 4.2, Eq. 8-11);
+//  * the camera side of the bidirectional combination the paper names as
+//    its next step (Sec. 7): camera samples traced by a path tracer with
+//    next-event estimation at Lambertian and rough-conductor vertices and
+//    emission counted after specular bounces, either restricted to samples
+//    whose first vertex is specular (the paths no light-path connection can
+//    reach: light paths plus these samples partition the measurement of
+//    Eq. 1) or unrestricted (a full path tracer, the tests' reference); and
+//    its detached gradient by taped reverse-mode AD per sample;
 //  * per-path decision signatures (hit primitive, texel, validity, lobe, R)
 //    so that FP32/FP64 decision flips can be told apart from arithmetic
 //    differences.
@@ -26,6 +34,10 @@
 //    counter = (path, vertex, block, 0); u = (x >> 8) * 2^-24.
 //    Vertex 0: u0,u1 emitter position, u2,u3 emitted direction.
 //    Vertex j>=1: u0,u1 diffuse direction, u2 Fresnel lobe, u3 reservoir.
+//    Camera sample s: block 2 at vertex 0 (u0,u1 tent-filtered film offset)
+//    and at vertex j (u0,u1 scatter direction, u2 Fresnel lobe), block 3 at
+//    vertex j (u0,u1 point on the quad emitter for next-event estimation);
+//    its pixel is s mod (W H).
 //  - Only the primitive choice uses the offset ray origin; the differentiable
 //    hit point is recomputed from the true origin and the hit triangle's plane.
 #include <cmath>
@@ -986,6 +998,205 @@ void trace_path(const Scene& S, const ora_args& A, uint32_t path, PathResult& ou
   out.sig = fnv1a(out.sig, (uint32_t)out.R);
 }
 
+// ----------------------------------------------------------------- camera side
+// Camera paths for the bidirectional combination (an extension: the paper
+// names PRB on the camera side with LRB-3-pass on the light side as its next
+// step, without fixing an algorithm).  The light tracer connects only its
+// non-specular vertices to the camera, so it misses exactly the paths whose
+// first camera-side vertex is specular (seen through or in glass).  A camera
+// path tracer restricted to those paths (spec_only) adds them; the two sets
+// are disjoint and together hold every path the camera can see (emitters
+// seen directly stay out of both, as in the light tracer).
+//   Camera sample s: pixel p = s mod (W H), film position u = p + 1/2 + t
+//   with t drawn from the tent filter (so E[estimate] = int F(u, p) L(u) du,
+//   the light tracer's pixel), one radiance estimate per sample, each pixel
+//   averaging spp = n_paths / (W H) samples.
+//   Vertex j: dielectric -> Fresnel lobe (weight 1); Lambertian or rough
+//   conductor -> next-event estimation to the emitter (a uniform point on a
+//   quad emitter, or the point light) and a BSDF-sampled continuation;
+//   emission is counted when a ray leaving a dielectric vertex hits the
+//   quad emitter's front (paths next-event estimation cannot sample).
+//   Uniforms: counter (s, 0, 2) film offsets; (s, j, 2) scattering
+//   (u0, u1 direction, u2 dielectric lobe); (s, j, 3) the emitter point.
+// Without spec_only the same tracer covers every path (the reference of
+// the tests: its image equals the light tracer's plus the spec_only one).
+struct CamTerm { V C[3]; };
+
+double tent_offset(double xi) { return xi < 0.5 ? std::sqrt(2.0 * xi) - 1.0 : 1.0 - std::sqrt(2.0 - 2.0 * xi); }
+
+// front-face hit of the quad emitter: t > 0 or -1, and its quad coordinates
+double emitter_hit(const ora_scene& sc, D3 o, D3 d, double& a, double& b) {
+  D3 O = {sc.em_o[0], sc.em_o[1], sc.em_o[2]}, e1 = {sc.em_e1[0], sc.em_e1[1], sc.em_e1[2]},
+     e2 = {sc.em_e2[0], sc.em_e2[1], sc.em_e2[2]};
+  D3 N = cross(e1, e2);
+  double den = dot(d, N);
+  if (!(den < 0.0)) return -1.0;
+  double t = dot(O - o, N) / den;
+  if (!(t > kTmin)) return -1.0;
+  D3 q = o + d * t - O;
+  double e11 = dot(e1, e1), e12 = dot(e1, e2), e22 = dot(e2, e2), q1 = dot(q, e1), q2 = dot(q, e2);
+  double det = e11 * e22 - e12 * e12;
+  a = (q1 * e22 - q2 * e12) / det; b = (q2 * e11 - q1 * e12) / det;
+  if (a < 0.0 || a > 1.0 || b < 0.0 || b > 1.0) return -1.0;
+  return t;
+}
+
+// emitter radiance leaves at quad coordinates (a, b)
+void emitter_le(const Scene& S, double a, double b, V Le[3]) {
+  const ora_scene& sc = *S.s;
+  long le = 0;
+  if (sc.em_tex_res > 0) {
+    const int R = sc.em_tex_res;
+    int tx = std::min((int)std::floor(a * R), R - 1), ty = std::min((int)std::floor(b * R), R - 1);
+    le = 3L * ((long)ty * R + tx);
+  }
+  for (int c = 0; c < 3; ++c) Le[c] = leaf(S.Le[le + c], S.slot_Le + le + c);
+}
+
+// One camera sample: its pixel (-1 when the film offset leaves the film or
+// the sample contributes nothing) and its estimator terms.
+int camera_path(const Scene& S, const ora_args& A, uint32_t s, bool spec_only, std::vector<CamTerm>& terms,
+                uint32_t& sig) {
+  const ora_scene& sc = *S.s;
+  const int W = sc.width, H = sc.height;
+  terms.clear(); sig = 0x811C9DC5u;
+  const uint32_t p = s % (uint32_t)(W * H);
+  Uniform4 uf = rng4(A.seed, s, 0, 2);
+  const double ux = (double)(p % W) + 0.5 + tent_offset(uf.u[0]), uy = (double)(p / W) + 0.5 + tent_offset(uf.u[1]);
+  if (!(ux >= 0.0 && ux < W && uy >= 0.0 && uy < H)) return -1;
+  const double qx = (2.0 * ux / W - 1.0) * S.aspect * S.tan_half, qy = (1.0 - 2.0 * uy / H) * S.tan_half;
+  D3 d = normalize(S.f + S.r * qx + S.u * qy);
+  D3 o = S.cpos;
+  D3 offn = {0, 0, 0}; bool off = false, prev_spec = false;
+  V beta[3] = {V(1.0), V(1.0), V(1.0)};
+  const bool quad = sc.em_type == ORA_EMIT_QUAD;
+  D3 eO = {sc.em_o[0], sc.em_o[1], sc.em_o[2]}, ee1 = {sc.em_e1[0], sc.em_e1[1], sc.em_e1[2]},
+     ee2 = {sc.em_e2[0], sc.em_e2[1], sc.em_e2[2]};
+  D3 eN = cross(ee1, ee2);
+  const double earea = std::sqrt(dot(eN, eN));
+  eN = eN * (1.0 / std::max(earea, 1e-300));
+  for (int j = 1; j <= A.max_depth; ++j) {
+    D3 xo = o;
+    if (off) xo = xo + offn * (dot(d, offn) >= 0 ? kEps : -kEps);
+    double th = 1e300;
+    int tri = S.closest(xo, d, kTmin, 1e300, &th);
+    if (quad && prev_spec) {  // emission seen through a specular chain
+      double a, b;
+      double te = emitter_hit(sc, xo, d, a, b);
+      if (te > 0.0 && te <= th * (1.0 + 1e-9) + 1e-9) {
+        V Le[3]; emitter_le(S, a, b, Le);
+        CamTerm t; for (int c = 0; c < 3; ++c) t.C[c] = beta[c] * Le[c];
+        terms.push_back(t);
+        sig = fnv1a(sig, 0xE0u);  // the emitter is no occluder: the ray goes on
+      }
+    }
+    if (tri < 0) { sig = fnv1a(sig, 0u); break; }
+    sig = fnv1a(sig, (uint32_t)tri + 1u);
+    int mat = S.mat_of(tri);
+    int mtype = sc.mat_type[mat];
+    if (mtype == ORA_ABSORBER) break;
+    D3 x = xo + d * th;
+    D3 P0 = S.tv[tri * 3], e1 = S.tv[tri * 3 + 1] - P0, e2 = S.tv[tri * 3 + 2] - P0;
+    D3 Nn = cross(e1, e2);
+    D3 ng = normalize(Nn);
+    double nn = dot(Nn, Nn);
+    D3 dx = x - P0;
+    double b1 = dot(cross(dx, e2), Nn) / nn, b2 = dot(cross(e1, dx), Nn) / nn;
+    const double cos_in = dot(d, ng);
+    D3 ns = ng;
+    if (tri >= S.n_static) {
+      V sxv[3], szv[3];
+      for (int k = 0; k < 3; ++k) { int gi, gj; S.hf_corner(tri, k, gi, gj); S.slope(gi, gj, sxv[k], szv[k]); }
+      double c0 = 1.0 - b1 - b2;
+      double Sx = c0 * sxv[0].v + b1 * sxv[1].v + b2 * sxv[2].v, Sz = c0 * szv[0].v + b1 * szv[1].v + b2 * szv[2].v;
+      ns = normalize(D3{-Sx, 1.0, -Sz});
+    }
+    Uniform4 uj = rng4(A.seed, s, (uint32_t)j, 2);
+    if (mtype == ORA_DIELECTRIC) {
+      if (j == A.max_depth) break;
+      V3 wo; bool reflect = false; double F = 0.0;
+      int code = dielectric_event(cst(d), cst(ns), ng, sc.mat_ior[mat], uj.u[2], wo, reflect, F);
+      if (code == 7) { sig = fnv1a(sig, 7u); break; }
+      sig = fnv1a(sig, reflect ? 2u : 4u);
+      if (code == 8) { sig = fnv1a(sig, 8u); break; }
+      o = x; d = val(wo); offn = ng; off = true; prev_spec = true;
+      continue;
+    }
+    if (spec_only && j == 1) return -1;  // the light tracer's paths
+    // Lambertian or rough conductor: its texel, the arrival-side normal
+    const bool cond = mtype == ORA_CONDUCTOR;
+    int tex = sc.mat_tex[mat], R = sc.tex_res;
+    double uvx = 0.0, uvy = 0.0;
+    if (tri < S.n_static) {
+      const double* uv = sc.tri_uv + (size_t)tri * 6;
+      double c0 = 1.0 - b1 - b2;
+      uvx = c0 * uv[0] + b1 * uv[2] + b2 * uv[4];
+      uvy = c0 * uv[1] + b1 * uv[3] + b2 * uv[5];
+    }
+    int tx = std::min(std::max((int)std::floor(uvx * R), 0), R - 1), ty = std::min(std::max((int)std::floor(uvy * R), 0), R - 1);
+    long texel = ((long)tex * R + ty) * R + tx;
+    sig = fnv1a(sig, (uint32_t)texel + 1u);
+    V rho[3];
+    for (int c = 0; c < 3; ++c) rho[c] = leaf(S.albedo[texel * 3 + c], texel * 3 + c);
+    const D3 na = cond ? (cos_in < 0 ? ns : ns * -1.0) : (cos_in < 0 ? ng : ng * -1.0);
+    const D3 wv = d * -1.0;  // toward the camera side
+    if (cond && !(dot(wv, na) > 0.0)) { sig = fnv1a(sig, 9u); break; }
+    // --- next-event estimation
+    {
+      Uniform4 ue = rng4(A.seed, s, (uint32_t)j, 3);
+      D3 y; double geo; V Le[3];
+      if (quad) {
+        y = eO + ee1 * ue.u[0] + ee2 * ue.u[1];
+        emitter_le(S, ue.u[0], ue.u[1], Le);
+      } else {
+        y = eO;
+        for (int c = 0; c < 3; ++c) Le[c] = leaf(S.Le[c], S.slot_Le + c);
+      }
+      D3 dl = y - x;
+      double r2 = dot(dl, dl), r = std::sqrt(r2);
+      D3 wl = dl * (1.0 / r);
+      double cy = quad ? -dot(wl, eN) : 1.0;
+      double cx = dot(wl, na), cg = dot(wl, ng) * (cos_in < 0 ? 1.0 : -1.0);
+      uint32_t vis = 0;
+      if (cy > 0.0 && cx > 0.0 && cg > 0.0) {
+        D3 so = x + ng * (dot(wl, ng) >= 0 ? kEps : -kEps);
+        D3 sd = y - so;
+        double sl = std::sqrt(dot(sd, sd));
+        if (S.closest(so, sd * (1.0 / sl), kTmin, sl * (1.0 - 1e-4), nullptr) < 0) {
+          vis = 1;
+          geo = quad ? cy * earea / r2 : 1.0 / r2;
+          double fb;  // f cos_x / rho
+          if (!cond) fb = kInvPi * cx;
+          else {
+            // conductor: f(wv, wl) (wl.na) / F0 = D G1 G1 / (4 wv.na)
+            fb = conductor_conn(cst(wv), cst(wl), cst(na), sc.mat_ior[mat]).v;
+          }
+          CamTerm t;
+          for (int c = 0; c < 3; ++c) t.C[c] = beta[c] * rho[c] * Le[c] * V(fb * geo);
+          terms.push_back(t);
+        }
+      }
+      sig = fnv1a(sig, vis);
+    }
+    if (j == A.max_depth) break;
+    // --- BSDF-sampled continuation
+    if (cond) {
+      V3 wo; V wgt;
+      int code = conductor_event(cst(wv), cst(na), ng, cos_in < 0 ? 1.0 : -1.0, sc.mat_ior[mat], uj.u[0], uj.u[1], wo, wgt);
+      if (code) { sig = fnv1a(sig, (uint32_t)code); break; }
+      for (int c = 0; c < 3; ++c) beta[c] = beta[c] * rho[c] * V(wgt.v);
+      d = val(wo);
+    } else {
+      double rr = std::sqrt(uj.u[0]), phi = 2.0 * M_PI * uj.u[1];
+      D3 t1, t2; onb(na, t1, t2);
+      d = t1 * (rr * std::cos(phi)) + t2 * (rr * std::sin(phi)) + na * std::sqrt(std::max(0.0, 1.0 - uj.u[0]));
+      for (int c = 0; c < 3; ++c) beta[c] = beta[c] * rho[c];
+    }
+    o = x; offn = ng; off = true; prev_spec = false;
+  }
+  return terms.empty() ? -1 : (int)p;
+}
+
 // tent filter taps (radius 1 pixel, taps outside the film dropped)
 struct Tap { int px, py; V w; };
 int taps(const Conn& cn, int W, int H, Tap t[4]) {
@@ -1126,6 +1337,92 @@ int ora_render(const ora_scene* sc, const ora_args* A, const double* albedo, con
   if (slices)
     for (long p = 0; p < npix * D; ++p) { double s = 0; for (int t = 0; t < nt; ++t) s += sl[t][p]; slices[p] = s; }
   if (flux) for (int c = 0; c < 3; ++c) { double s = 0; for (int t = 0; t < nt; ++t) s += fl[t * 3 + c]; flux[c] = s; }
+  return 0;
+}
+
+// Camera-side image (see camera_path): image [H][W][3] (overwritten) from
+// the listed camera samples (A->path_list, else [0, n_paths)); each pixel
+// averages spp = n_paths / (W H) samples (n_paths a multiple of W H).
+// spec_only 1: only samples whose first vertex is specular.  sig per listed
+// sample when given.  Returns -1 for an emitter the camera cannot sample
+// (directional) or n_paths not a multiple of W H.
+int ora_render_camera(const ora_scene* sc, const ora_args* A, int spec_only, const double* albedo, const double* Le,
+                      const double* heights, const double* nmap, double* image, uint32_t* sig) {
+  const long npx = (long)sc->width * sc->height;
+  if (sc->em_type == ORA_EMIT_DIRECTIONAL || A->n_paths % npx != 0) return -1;
+  Scene S; S.init(sc, albedo, Le, heights, nmap, false);
+  const double inv_spp = (double)npx / (double)A->n_paths;
+  const int64_t n = A->path_list ? A->n_list : A->n_paths;
+  int nt = A->n_threads > 0 ? A->n_threads : omp_get_max_threads();
+  std::vector<std::vector<double>> img(nt, std::vector<double>(npx * 3, 0.0));
+#pragma omp parallel num_threads(nt)
+  {
+    int tid = omp_get_thread_num();
+    Tape tape; g_tape = &tape;
+    std::vector<CamTerm> terms;
+#pragma omp for schedule(dynamic, 256)
+    for (int64_t k = 0; k < n; ++k) {
+      uint32_t smp = A->path_list ? A->path_list[k] : (uint32_t)k;
+      tape.clear();
+      uint32_t sg;
+      int px = camera_path(S, *A, smp, spec_only != 0, terms, sg);
+      if (sig) sig[k] = sg;
+      if (px < 0) continue;
+      for (const CamTerm& t : terms)
+        for (int c = 0; c < 3; ++c) img[tid][px * 3 + c] += inv_spp * t.C[c].v;
+    }
+    g_tape = nullptr;
+  }
+  for (long q = 0; q < npx * 3; ++q) { double v = 0; for (int t = 0; t < nt; ++t) v += img[t][q]; image[q] = v; }
+  return 0;
+}
+
+// Gradient of <dI, I_camera> w.r.t. albedo texels and emitter radiance
+// (detached) by taped reverse-mode AD of each camera sample; accumulated.
+int ora_gradient_camera(const ora_scene* sc, const ora_args* A, int spec_only, const double* albedo, const double* Le,
+                        const double* heights, const double* nmap, const double* dI, double* g_albedo, double* g_Le) {
+  const long npx = (long)sc->width * sc->height;
+  if (sc->em_type == ORA_EMIT_DIRECTIONAL || A->n_paths % npx != 0) return -1;
+  Scene S; S.init(sc, albedo, Le, heights, nmap, false);
+  const double inv_spp = (double)npx / (double)A->n_paths;
+  const int64_t n = A->path_list ? A->n_list : A->n_paths;
+  const long n_alb = S.slot_Le, nslot = n_alb + S.n_le;
+  int nt = A->n_threads > 0 ? A->n_threads : omp_get_max_threads();
+  std::vector<std::vector<double>> gr(nt, std::vector<double>(nslot, 0.0));
+#pragma omp parallel num_threads(nt)
+  {
+    int tid = omp_get_thread_num();
+    Tape tape; g_tape = &tape;
+    std::vector<CamTerm> terms;
+    std::vector<double> adj;
+#pragma omp for schedule(dynamic, 256)
+    for (int64_t k = 0; k < n; ++k) {
+      uint32_t smp = A->path_list ? A->path_list[k] : (uint32_t)k;
+      tape.clear();
+      uint32_t sg;
+      int px = camera_path(S, *A, smp, spec_only != 0, terms, sg);
+      if (px < 0) continue;
+      V lam(0.0);
+      for (const CamTerm& t : terms)
+        for (int c = 0; c < 3; ++c) lam = lam + t.C[c] * V(inv_spp * dI[px * 3 + c]);
+      if (lam.i < 0) continue;
+      adj.assign(tape.a.size(), 0.0);
+      adj[lam.i] = 1.0;
+      for (int q = lam.i; q >= 0; --q) {
+        double g = adj[q];
+        if (g == 0.0) continue;
+        if (tape.a[q] >= 0) adj[tape.a[q]] += g * tape.da[q];
+        if (tape.b[q] >= 0) adj[tape.b[q]] += g * tape.db[q];
+      }
+      for (auto& lf : tape.leaves) if (lf.second < nslot) gr[tid][lf.second] += adj[lf.first];
+    }
+    g_tape = nullptr;
+  }
+  for (long q = 0; q < nslot; ++q) {
+    double v = 0; for (int t = 0; t < nt; ++t) v += gr[t][q];
+    if (q < n_alb) { if (g_albedo) g_albedo[q] += v; }
+    else if (g_Le) g_Le[q - n_alb] += v;
+  }
   return 0;
 }
 

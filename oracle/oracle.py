@@ -105,6 +105,10 @@ def _load():
         _lib.ora_conductor.restype = C.c_int
         _lib.ora_conductor_conn.argtypes = [dp, dp, dp, C.c_double]
         _lib.ora_conductor_conn.restype = C.c_double
+        _lib.ora_render_camera.argtypes = [C.POINTER(_Scene), C.POINTER(_Args), C.c_int, dp, dp, dp, dp, dp, up]
+        _lib.ora_render_camera.restype = C.c_int
+        _lib.ora_gradient_camera.argtypes = [C.POINTER(_Scene), C.POINTER(_Args), C.c_int, dp, dp, dp, dp, dp, dp, dp]
+        _lib.ora_gradient_camera.restype = C.c_int
         _lib.ora_dielectric.argtypes = [dp, dp, dp, C.c_double, C.c_double, dp, ip, dp]
         _lib.ora_dielectric.restype = C.c_int
         assert _lib.ora_guide_nparams() == GUIDE_NPARAMS
@@ -257,6 +261,48 @@ def gradient(sc, seed, n_paths, depth, dI, mode=MODE_NAIVE, albedo=None, Le=None
     if rc != 0:
         raise ValueError("oracle gradient rejected its arguments")
     return dict(albedo=g_alb, Le=g_le, heights=g_h, normal_map=g_n)
+
+
+def render_camera(sc, seed, n_paths, depth, spec_only=True, albedo=None, Le=None, heights=None, path_list=None,
+                  threads=0, per_path=False):
+    """Camera-side image [H,W,3] of the bidirectional combination: n_paths
+    camera samples (a multiple of W*H), each pixel averaging n_paths/(W*H);
+    spec_only: only samples whose first vertex is specular (the paths the
+    light tracer cannot connect), else every path (a full path tracer with
+    next-event estimation, the reference of the tests)."""
+    lib = _load()
+    keep = _Keep()
+    s = _scene(sc, keep)
+    a = _args(seed, n_paths, depth, 0, threads, path_list, keep)
+    alb, le, h, nm = _params(sc, albedo, Le, heights, keep)
+    H, W = int(sc["camera"]["height"]), int(sc["camera"]["width"])
+    img = np.zeros((H, W, 3))
+    n = len(path_list) if path_list is not None else int(n_paths)
+    sig = np.zeros(n, np.uint32) if per_path else None
+    if lib.ora_render_camera(C.byref(s), C.byref(a), int(bool(spec_only)), _p(alb), _p(le), _p(h), _p(nm), _p(img),
+                             _p(sig, C.c_uint32)) != 0:
+        raise ValueError("camera samples need a quad or point emitter and n_paths a multiple of the pixel count")
+    out = dict(image=img)
+    if per_path:
+        out["sig"] = sig
+    return out
+
+
+def gradient_camera(sc, seed, n_paths, depth, dI, spec_only=True, albedo=None, Le=None, heights=None,
+                    path_list=None, threads=0):
+    """Gradient of <dI, I_camera> w.r.t. albedo texels and emitter radiance
+    (detached) by taped reverse-mode AD of each camera sample."""
+    lib = _load()
+    keep = _Keep()
+    s = _scene(sc, keep)
+    a = _args(seed, n_paths, depth, 0, threads, path_list, keep)
+    alb, le, h, nm = _params(sc, albedo, Le, heights, keep)
+    dI = keep.f64(dI)
+    g_alb, g_le = np.zeros_like(alb), np.zeros_like(le)
+    if lib.ora_gradient_camera(C.byref(s), C.byref(a), int(bool(spec_only)), _p(alb), _p(le), _p(h), _p(nm), _p(dI),
+                               _p(g_alb), _p(g_le)) != 0:
+        raise ValueError("camera samples need a quad or point emitter and n_paths a multiple of the pixel count")
+    return dict(albedo=g_alb, Le=g_le)
 
 
 def loss_and_adjoint(image, target):

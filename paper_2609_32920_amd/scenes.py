@@ -284,6 +284,91 @@ def glass_panel_scene(G=16, width=64, height=64, seed=SCENE_SEED, target_seed=TA
     return sc
 
 
+def glass_slab_scene(G=16, width=64, height=64, tex_res=8, seed=SCENE_SEED, target_seed=TARGET_SEED,
+                     Le=40.0, ior=1.5):
+    """Glass slab over a textured diffuse receiver, seen from above (the
+    Glass Slab scene of the paper, framed so that the camera looks through
+    the glass: the workload of the bidirectional combination).
+
+    Receiver: y = 0, x,z in [-1.2, 1.2], albedo texture tex_res^2 drawn
+    U(0.3, 0.9) per channel (texture 0).  Slab: dielectric (IOR `ior`)
+    closed solid over x,z in [-0.5, 0.5]; flat bottom at y = 0.3, walls up
+    to y = 0.4, G x G vertex heightfield top at y = 0.4 (heights zero).
+    Emitter: 0.4 x 0.4 quad centred at (0, 1, 0.2) facing down (an absorber
+    quad in the geometry).  Camera at (0, 1.2, -1.4) looking at
+    (0, 0.1, 0.15), 45 degree FOV: part of the receiver is seen directly,
+    part through the slab.  Target albedo: another seeded texture.
+    """
+    b = _Builder()
+    mat_type = np.array([MAT_LAMBERT, MAT_DIELECTRIC, MAT_ABSORBER], np.int32)
+    mat_tex = np.array([0, -1, -1], np.int32)
+    mat_ior = np.array([1.0, ior, 1.0])
+    b.quad((-1.2, 0, -1.2), (0, 0, 2.4), (2.4, 0, 0), 0)     # receiver, normal +y
+    b.quad((-0.5, 0.3, -0.5), (1, 0, 0), (0, 0, 1), 1)       # slab bottom, normal -y
+    b.quad((-0.5, 0.3, -0.5), (0, 0.1, 0), (1, 0, 0), 1)     # wall z=-0.5, normal -z
+    b.quad((-0.5, 0.3, 0.5), (1, 0, 0), (0, 0.1, 0), 1)      # wall z=+0.5, normal +z
+    b.quad((-0.5, 0.3, -0.5), (0, 0, 1), (0, 0.1, 0), 1)     # wall x=-0.5, normal -x
+    b.quad((0.5, 0.3, -0.5), (0, 0.1, 0), (0, 0, 1), 1)      # wall x=+0.5, normal +x
+    em_o, em_e1, em_e2 = (-0.2, 1.0, 0.0), (0.4, 0, 0), (0, 0, 0.4)   # e1 x e2 along -y
+    b.quad(em_o, em_e1, em_e2, 2)
+    tri_v, tri_uv, tri_mat = b.arrays()
+    rng = np.random.default_rng(seed)
+    albedo = rng.uniform(0.3, 0.9, size=(1, tex_res, tex_res, 3))
+    trng = np.random.default_rng(target_seed)
+    albedo_t = trng.uniform(0.3, 0.9, size=(1, tex_res, tex_res, 3))
+    return dict(
+        name=f"slab{G}_{width}x{height}",
+        tri_v=tri_v, tri_uv=tri_uv, tri_mat=tri_mat,
+        mat_type=mat_type, mat_tex=mat_tex, mat_ior=mat_ior,
+        n_tex=1, tex_res=tex_res,
+        emitter=dict(type=EMIT_QUAD, o=np.array(em_o, float), e1=np.array(em_e1, float),
+                     e2=np.array(em_e2, float)),
+        camera=dict(pos=np.array([0.0, 1.2, -1.4]), target=np.array([0.0, 0.1, 0.15]),
+                    up=np.array([0.0, 1.0, 0.0]), fov_deg=45.0, width=width, height=height),
+        hf=dict(G=G, x0=-0.5, z0=-0.5, dx=1.0 / (G - 1), base=0.4, mat=1),
+        albedo=albedo, Le=np.full(3, float(Le)),
+        heights=np.zeros(G * G),
+        albedo_target=albedo_t, heights_target=None,
+    )
+
+
+def slab_view_scene(width=8, height=8, ior=1.5, Le=2.0, fov_deg=20.0):
+    """A camera looking straight down through a wide flat glass slab at a
+    large emitter (closed-form pin of camera paths through specular chains).
+
+    Emitter: quad over x,z in [-5, 5] at y = 0 facing +y, radiance Le (not
+    geometry).  Slab: dielectric closed box over x,z in [-4, 4], faces at
+    y = 0.4 and y = 0.6.  Camera at (0, 1.5, 0) looking down (up = +z).  A
+    camera ray at angle theta to the vertical crosses the slab after 2k
+    internal reflections with weight (1 - F)^2 F^(2k), F the unpolarized
+    Fresnel reflectance at theta (the same at both faces).
+    """
+    b = _Builder()
+    mat_type = np.array([MAT_DIELECTRIC], np.int32)
+    mat_tex = np.array([-1], np.int32)
+    mat_ior = np.array([ior])
+    lo, hi, s = 0.4, 0.6, 4.0
+    b.quad((-s, hi, -s), (0, 0, 2 * s), (2 * s, 0, 0), 0)     # top, normal +y
+    b.quad((-s, lo, -s), (2 * s, 0, 0), (0, 0, 2 * s), 0)     # bottom, normal -y
+    b.quad((-s, lo, -s), (0, hi - lo, 0), (2 * s, 0, 0), 0)   # wall z=-s, normal -z
+    b.quad((-s, lo, s), (2 * s, 0, 0), (0, hi - lo, 0), 0)    # wall z=+s, normal +z
+    b.quad((-s, lo, -s), (0, 0, 2 * s), (0, hi - lo, 0), 0)   # wall x=-s, normal -x
+    b.quad((s, lo, -s), (0, hi - lo, 0), (0, 0, 2 * s), 0)    # wall x=+s, normal +x
+    tri_v, tri_uv, tri_mat = b.arrays()
+    return dict(
+        name=f"slabview_{width}x{height}",
+        tri_v=tri_v, tri_uv=tri_uv, tri_mat=tri_mat,
+        mat_type=mat_type, mat_tex=mat_tex, mat_ior=mat_ior,
+        n_tex=1, tex_res=1,
+        emitter=dict(type=EMIT_QUAD, o=np.array([-5.0, 0.0, 5.0]), e1=np.array([10.0, 0.0, 0.0]),
+                     e2=np.array([0.0, 0.0, -10.0])),
+        camera=dict(pos=np.array([0.0, 1.5, 0.0]), target=np.array([0.0, 0.0, 0.0]),
+                    up=np.array([0.0, 0.0, 1.0]), fov_deg=fov_deg, width=width, height=height),
+        albedo=np.full((1, 1, 1, 3), 0.5), Le=np.full(3, float(Le)),
+        albedo_target=None, heights_target=None,
+    )
+
+
 def directional_plane_scene(width=16, height=16, rho=0.6, tex_res=4, seed=SCENE_SEED, cam_h=2.0, fov_deg=60.0):
     """A textured directional emitter over a Lambertian plane, seen by a
     pinhole camera looking straight down (closed-form pin only).
