@@ -22,7 +22,8 @@ HBM_PEAK_GBS = 8000.0
 B_NODE, B_TRI, B_SPLAT, B_GATHER, B_GRAD, B_TAPE = 64, 48, 96, 48, 8, 32
 
 
-KERNEL_SOURCES = ["lt_common.h", "lt_device.h", "lt_launch.h", "lt_kernels.hip", "lt_attached.inc", "lt_api.cpp"]
+KERNEL_SOURCES = ["lt_common.h", "lt_device.h", "lt_launch.h", "lt_kernels.hip", "lt_attached.inc", "lt_camera.inc",
+                  "lt_api.cpp"]
 
 
 def profiled_traffic(name, field="traffic_bytes_per_launch"):
@@ -64,6 +65,7 @@ def parse():
     ap.add_argument("--guide-seeds", type=int, default=32, help="seeds per gradient-variance estimate")
     ap.add_argument("--ee-seeds", type=int, default=16, help="seeds per equal-error variance estimate")
     ap.add_argument("--no-inverse", action="store_true", help="skip the heightfield inverse-rendering loop")
+    ap.add_argument("--no-bidir", action="store_true", help="skip the bidirectional glass-slab workload")
     ap.add_argument("--inverse-iters", type=int, default=200, help="Adam iterations of the inverse-rendering loop")
     ap.add_argument("--cpu-paths", type=int, default=1 << 22, help="paths in the CPU-oracle sample")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="least CPU-oracle time (whole steps)")
@@ -302,6 +304,11 @@ def main():
     if not (args.no_batch or args.no_guide):
         guided_batch = bench_guided_batch(lt, scenes, dev, stream)
 
+    # ---- bidirectional: LRB-3 light paths + path-replay camera samples
+    bidir = None
+    if not args.no_bidir:
+        bidir = bench_bidirectional(lt, scenes, dev, stream, bytes_per_path, cpu=not args.no_cpu)
+
     # ---- CPU baseline: the FP64 oracle, forward + naive backward, on a sample
     cpu = cpu1 = cpu_more = None
     if not args.no_cpu:
@@ -362,6 +369,7 @@ def main():
         "batch_small_instances": batch_small,
         "guided_batch": guided_batch,
         "guide_diffuse_detail_box": guide_diffuse,
+        "bidirectional": bidir,
     }
     print(json.dumps(out), flush=True)
 
@@ -728,6 +736,99 @@ def bench_guide_diffuse(lt, scenes, dev, stream, film=256, N=1 << 22, D=8, iters
               f"median-texel {mr:.3f} {out[name]['median_texel_ratio_bootstrap_90']}, {t0:.2f} -> {t1:.2f} ms, "
               f"gain {out[name]['efficiency_gain']} (robust {out[name]['robust_efficiency_gain']}), "
               f"z^2 {out[name]['bias_mean_z2']}", file=sys.stderr, flush=True)
+    return out
+
+
+def bench_bidirectional(lt, scenes, dev, stream, bytes_per_path_fn, G=64, film=256, N_lt=1 << 22, spp=16, D=8,
+                        reps=6, cpu=True):
+    """Glass slab seen from above: the light tracer (LRB-3 backward) covers
+    the camera paths whose first vertex is diffuse, camera samples with a
+    path-replay backward those whose first vertex is specular (the surface
+    seen through the glass).  One step: both forwards into one image, the L2
+    loss, both backwards into one gradient."""
+    import numpy as np
+    import torch
+    sc = scenes.glass_slab_scene(G=G, width=film, height=film)
+    ctx = lt.Context(0).scene_upload(sc)
+    t32 = lambda a: torch.as_tensor(np.asarray(a, np.float32), device=dev).contiguous()
+    albedo, Le, h = t32(sc["albedo"]), t32(sc["Le"]), t32(sc["heights"])
+    alb_t = t32(sc["albedo_target"])
+    n_cam = spp * film * film
+    img = torch.zeros((film, film, 3), dtype=torch.float32, device=dev)
+    target = torch.zeros_like(img)
+    dI = torch.empty_like(img)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    g_alb, g_le = torch.zeros_like(albedo), torch.zeros_like(Le)
+    p = ctx.params(albedo, Le, h)
+    pt = ctx.params(alb_t, Le, h)
+    ctx.trace(ctx.args(0x7A6, N_lt, D), pt, target)
+    ctx.camera_trace(ctx.args(0x7A7, n_cam, D), pt, target)
+
+    def step(seed, ev=None):
+        a_l, a_c = ctx.args(seed, N_lt, D), ctx.args(seed + 0x10000, n_cam, D)
+        rec = (lambda i: ev[i].record(stream)) if ev else (lambda i: None)
+        rec(0); ctx.trace(a_l, p, img)
+        rec(1); ctx.camera_trace(a_c, p, img)
+        rec(2); ctx.loss_l2(img, target, dI, loss)
+        rec(3); ctx.backward_lrb3(a_l, p, dI, g_alb, g_le)
+        rec(4); ctx.camera_backward_prb(a_c, p, dI, g_alb, g_le)
+        rec(5)
+
+    for k in range(2):
+        step(100 + k)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(reps)]
+    for k in range(reps):
+        step(200 + k, evs[k])
+    torch.cuda.synchronize()
+    med = lambda i, j: float(np.median([e[i].elapsed_time(e[j]) for e in evs]))
+    t = {"lt_forward": med(0, 1), "camera_forward": med(1, 2), "loss": med(2, 3), "lrb3_backward": med(3, 4),
+         "camera_prb_backward": med(4, 5), "step": med(0, 5)}
+    # share of the image only camera samples reach (through the glass)
+    cam = torch.zeros_like(img)
+    ctx.camera_trace(ctx.args(300, n_cam, D), p, cam)
+    ctx.trace(ctx.args(301, N_lt, D), p, img)
+    torch.cuda.synchronize()
+    share = float(cam.sum() / (cam.sum() + img.sum()))
+    roof = None
+    try:
+        cctx = lt.Context(0, counters=True).scene_upload(sc)
+        n_s = min(n_cam, 1 << 18)
+        cctx.read_counters(reset=True)
+        cctx.camera_backward_prb(cctx.args(200, n_s, D), p, dI, torch.zeros_like(albedo), torch.zeros_like(Le))
+        c = cctx.read_counters(reset=True)
+        del cctx
+        # the model's node, triangle and gradient bytes plus the pixel adjoint read
+        bps = bytes_per_path_fn(c, n_s) + 12.0
+        t_l = t["camera_prb_backward"] * 1e-3
+        ach = bps * n_cam / t_l / 1e9
+        roof = {"bound": "hbm", "kernel": "k_camera_prb", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_sample": round(bps, 1),
+                "events_per_sample": {k: round(v / n_s, 3) for k, v in c.items()}}
+    except Exception as e:  # the diagnostic build is optional
+        print(f"# counters unavailable: {e}", file=sys.stderr)
+    cpu_rate = None
+    if cpu:
+        from oracle import oracle as O
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+        ids = np.arange(1 << 18, dtype=np.uint32)
+        dIh = dI.cpu().numpy().astype(np.float64)
+        t0 = time.perf_counter()
+        O.render_camera(sc, 200, n_cam, D, path_list=ids, threads=threads)
+        O.gradient_camera(sc, 200, n_cam, D, dIh, path_list=ids, threads=threads)
+        tc = time.perf_counter() - t0
+        cpu_rate = {"value": round(len(ids) / tc, 1), "unit": "camera samples/s (fwd+bwd)", "cores": threads,
+                    "kind": "oracle", "sample": f"first {len(ids)} of {n_cam} camera samples, {tc:.2f} s"}
+    out = {"workload": f"glass slab (heightfield top {G}x{G}) seen from above, film {film}x{film}, depth {D}: "
+                       f"{N_lt} light paths (LRB-3) + {spp} camera samples per pixel ({n_cam}, path replay)",
+           "ms": {k: round(v, 3) for k, v in t.items()},
+           "light_paths_per_s": round(N_lt / (t["lt_forward"] + t["lrb3_backward"]) * 1e3, 1),
+           "camera_samples_per_s": round(n_cam / (t["camera_forward"] + t["camera_prb_backward"]) * 1e3, 1),
+           "camera_image_share": round(share, 4),
+           "camera_roofline": roof, "camera_cpu_baseline": cpu_rate}
+    print(f"# bidirectional: step {t['step']:.2f} ms (light fwd {t['lt_forward']:.2f}, camera fwd "
+          f"{t['camera_forward']:.2f}, LRB-3 bwd {t['lrb3_backward']:.2f}, PRB bwd {t['camera_prb_backward']:.2f}); "
+          f"camera share of the image {share:.3f}", file=sys.stderr, flush=True)
     return out
 
 

@@ -73,8 +73,10 @@ enum {
   LT_RECORD_RESERVOIR = 8u, /* lt_trace writes the per-path ResLRB record */
   LT_CONTRIB_ADJOINT = 16u, /* attached backward: path_contrib gets |delta_total| (below) */
   LT_RECORD_SPLATS = 32u,   /* lt_trace writes the buffered two-pass splat records (detached) */
-  LT_GUIDE_DIFFUSE = 64u    /* with params->guide_w: Lambertian vertices scatter from the
+  LT_GUIDE_DIFFUSE = 64u,   /* with params->guide_w: Lambertian vertices scatter from the
                                learned guide too (diffuse guide table, see the guide section) */
+  LT_CAMERA_ALL = 128u      /* camera side (lt_camera_trace, lt_camera_backward_prb): every
+                               camera sample, not only those whose first vertex is specular */
 };
 
 typedef struct lt_ctx lt_ctx;
@@ -352,6 +354,53 @@ lt_status lt_backward_lrb3(lt_ctx* ctx, const lt_trace_args* args, const lt_para
  * device). */
 lt_status lt_backward_lrb3_noalloc(lt_ctx* ctx, const lt_trace_args* args, const lt_params* params,
                                    const float* d_image, lt_grads* grads);
+
+/* ------------------------------------------------------------------------
+ * Camera side of the bidirectional combination.  Sec. 7 names a
+ * bidirectional formulation with path replay (Sec. 3.2) on the camera side
+ * and LRB-3 on the light side as the next step.  Every path of the
+ * measurement (Eq. 1) leaves the camera through a specular (dielectric) or
+ * a non-specular vertex; light-path sensor connections reach only the
+ * second kind, so light tracing plus camera samples restricted to the first
+ * kind estimate the whole image, each path by exactly one of the two:
+ *   image = lt_trace(...) then lt_camera_trace(...) (which adds),
+ *   grads = lt_backward_lrb3(...) + lt_camera_backward_prb(...) (both add).
+ * Camera sample s (args->n_paths samples N, a multiple of width*height)
+ * renders pixel s mod (width*height) through a film offset drawn from the
+ * tent filter of Eq. 20 around the pixel centre, and weighs
+ * width*height / N.  It is traced by a path tracer: next-event estimation at
+ * Lambertian and rough-conductor vertices (a point on the quad emitter, or
+ * the point emitter; shadow ray against the scene), emission counted when a
+ * ray leaving a specular vertex meets the quad emitter's front face before
+ * any scene hit (the emitter occludes nothing, the ray goes on), cosine
+ * (Lambertian) or microfacet (conductor) continuation, the Fresnel lobe at
+ * dielectrics, at most max_depth vertices; without LT_CAMERA_ALL a sample
+ * whose first vertex is not specular contributes nothing.
+ * Random numbers: Philox counter (s, 0, 2) for the film offset (u0, u1),
+ * (s, j, 2) at vertex j (u0, u1 direction, u2 Fresnel lobe), (s, j, 3) for
+ * the next-event point (u0 along e1, u1 along e2).
+ * Detached only (albedo and emitter radiance); args->flags may hold
+ * LT_CAMERA_ALL only (LT_ERR_UNSUPPORTED otherwise); a directional emitter
+ * is rejected (LT_ERR_UNSUPPORTED: a camera path cannot reach it); the
+ * emission guide does not apply to camera samples (params->guide_w is
+ * ignored).  path_mask / path_sig index camera samples.
+ * ------------------------------------------------------------------------ */
+/* Adds the camera samples' estimate to image (DEVICE float
+ * [height][width][3], not cleared).  path_sig: each sample's decision
+ * signature (FNV-1a of hit primitives, texels, next-event visibility, lobes,
+ * emission hits).  Errors: LT_ERR_ARG (n_paths not a multiple of the pixel
+ * count, ...), LT_ERR_UNSUPPORTED, LT_ERR_STATE, LT_ERR_HIP. */
+lt_status lt_camera_trace(lt_ctx* ctx, const lt_trace_args* args, const lt_params* params, float* image);
+/* Path-replay backward of the camera samples (Sec. 3.2): each sample's
+ * pixel adjoint d_image[p] is known before the replay; a primal pass
+ * recomputes the sample's radiance L (and adds the emitter gradient of each
+ * term), a replay then adds d_image[p] (L - sum of the terms before vertex
+ * i) / rho_i to the gradient of vertex i's albedo texel, per channel (a
+ * texel with rho = 0 gets nothing from the later terms).  Needs no side
+ * state.  Gradients accumulate into grads (albedo required).
+ * Errors: as lt_camera_trace. */
+lt_status lt_camera_backward_prb(lt_ctx* ctx, const lt_trace_args* args, const lt_params* params,
+                                 const float* d_image, lt_grads* grads);
 
 /* ------------------------------------------------------------------------
  * Learned emission guide.  An extension of the method, not in the paper:

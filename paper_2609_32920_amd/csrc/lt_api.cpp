@@ -1090,6 +1090,69 @@ lt_status lt_backward_lrb3_noalloc(lt_ctx* c, const lt_trace_args* a, const lt_p
   return lrb3_enqueue(c, a, p, d_image, g, w);
 }
 
+// Camera side: the light-tracing argument checks on the same args with no
+// flags, then the camera's own conditions.
+static lt_status camera_check(lt_ctx* c, const lt_trace_args* a, const lt_params* p, lt_trace_args& b,
+                              lt_params& q) {
+  if (!c) return LT_ERR_ARG;
+  if (!a || !p) return c->fail(LT_ERR_ARG, "null args or params%s");
+  b = *a;
+  b.flags = 0;
+  b.path_info = nullptr;
+  b.path_contrib = nullptr;
+  q = *p;
+  q.guide_w = nullptr;
+  lt_status st = check_args(c, &b, &q);
+  if (st != LT_OK) return st;
+  if (a->flags & ~(uint32_t)LT_CAMERA_ALL)
+    return c->fail(LT_ERR_UNSUPPORTED, "camera samples take LT_CAMERA_ALL only (detached)%s");
+  if (c->dsc.em_type == LT_EMIT_DIRECTIONAL)
+    return c->fail(LT_ERR_UNSUPPORTED, "camera samples cannot reach a directional emitter%s");
+  const int64_t npx = (int64_t)c->dsc.W * c->dsc.H;
+  if (a->n_paths % npx != 0) return c->fail(LT_ERR_ARG, "camera samples: n_paths must be a multiple of width*height%s");
+  return LT_OK;
+}
+
+static void camera_fields(const lt_ctx* c, const lt_trace_args* a, PassArgs& A) {
+  A.flags = (a->flags & LT_CAMERA_ALL) ? 1u : 0u;
+  A.spp_inv = (float)((double)c->dsc.W * c->dsc.H / (double)a->n_paths);
+  A.guide_rec = nullptr;
+  A.gtab = nullptr;
+}
+
+lt_status lt_camera_trace(lt_ctx* c, const lt_trace_args* a, const lt_params* p, float* image) {
+  lt_trace_args b;
+  lt_params q;
+  lt_status st = camera_check(c, a, p, b, q);
+  if (st != LT_OK) return st;
+  if (!image) return c->fail(LT_ERR_ARG, "null image%s");
+  if ((st = prepare_geometry(c, &q)) != LT_OK) return st;
+  PassArgs A = base_args(c, &b, &q);
+  camera_fields(c, a, A);
+  A.image = image;
+  if ((st = c->hip(launch_fill_u32(c->d_counter, 1, 0u, c->stream), "counter clear")) != LT_OK) return st;
+  if ((st = c->hip(launch_fill_u32(c->d_counter + 16, 4, 0u, c->stream), "stats clear")) != LT_OK) return st;
+  const int blk = c->tune.block;
+  return c->hip(launch_camera(A, persistent_grid(c, a->n_paths, blk), blk, c->stream), "camera launch");
+}
+
+lt_status lt_camera_backward_prb(lt_ctx* c, const lt_trace_args* a, const lt_params* p, const float* d_image,
+                                 lt_grads* g) {
+  lt_trace_args b;
+  lt_params q;
+  lt_status st = camera_check(c, a, p, b, q);
+  if (st != LT_OK) return st;
+  PassArgs A;
+  if ((st = backward_common(c, &b, &q, d_image, g, A, 0)) != LT_OK) return st;
+  camera_fields(c, a, A);
+  const int blk = c->tune.block;
+  A.agrad_lds = agrad_in_lds(c, BwdKernel::camera_prb, blk, stack_lds(c, blk));
+  if ((st = c->hip(launch_camera_prb(A, persistent_grid(c, a->n_paths, blk), blk, c->stream), "camera backward")) !=
+      LT_OK)
+    return st;
+  return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
+}
+
 lt_status lt_guide_eval(lt_ctx* c, const float* guide_w, const float* x, const float* n, int64_t count,
                         float* out) {
   if (!c) return LT_ERR_ARG;

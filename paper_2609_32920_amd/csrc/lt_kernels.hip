@@ -1036,6 +1036,7 @@ __global__ void k_refit_level(Node* nodes, const Tri* tris, const int32_t* level
 }
 
 #include "lt_attached.inc"
+#include "lt_camera.inc"
 
 // ---------------------------------------------------------------- batches
 // One persistent launch over a table of instances (scenes, films, path
@@ -1122,7 +1123,7 @@ hipError_t set_lds_limit(int bytes) {
   for (const void* f : {(const void*)k_lrb3_att_p2_entry, (const void*)k_lrb3_att_p3_entry,
                         (const void*)k_lrb3_p2, (const void*)k_lrb3_p3, (const void*)k_lrb3_att_p2<false>,
                         (const void*)k_lrb3_att_p3<false>, (const void*)k_lrb3_att_p2<true>,
-                        (const void*)k_lrb3_att_p3<true>, (const void*)k_lrb2_bwd})
+                        (const void*)k_lrb3_att_p3<true>, (const void*)k_lrb2_bwd, (const void*)k_camera_prb})
     if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   return e;
 }
@@ -1156,6 +1157,7 @@ int resident_groups(BwdKernel k, int block, size_t lds) {
     case BwdKernel::lrb3_att_p2: f = (const void*)k_lrb3_att_p2<false>; break;
     case BwdKernel::lrb3_att_p3: f = (const void*)k_lrb3_att_p3<false>; break;
     case BwdKernel::lrb2: f = (const void*)k_lrb2_bwd; break;
+    case BwdKernel::camera_prb: f = (const void*)k_camera_prb; break;
   }
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, block, lds) != hipSuccess) {
@@ -1243,6 +1245,15 @@ hipError_t launch_trace(const PassArgs& A, bool tape, bool resv, int grid, int b
   else if (tape) hipLaunchKernelGGL((k_trace<true, false>), dim3(grid), dim3(block), sh, s, A);
   else if (resv) hipLaunchKernelGGL((k_trace<false, true>), dim3(grid), dim3(block), sh, s, A);
   else hipLaunchKernelGGL((k_trace<false, false>), dim3(grid), dim3(block), sh, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_camera(const PassArgs& A, int grid, int block, hipStream_t s) {
+  hipLaunchKernelGGL(k_camera, dim3(grid), dim3(block), stack_bytes(A, block), s, A);
+  return hipGetLastError();
+}
+hipError_t launch_camera_prb(const PassArgs& A, int grid, int block, hipStream_t s) {
+  hipLaunchKernelGGL(k_camera_prb, dim3(grid), dim3(block), stack_bytes(A, block) + agrad_bytes(A), s, A);
   return hipGetLastError();
 }
 

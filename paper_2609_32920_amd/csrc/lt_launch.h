@@ -62,6 +62,9 @@ struct PassArgs {
   Lrb3HandAtt* hand_att;      // attached entries [n_paths]
   unsigned int* hand_n;       // entries appended (pass 2) / available (pass 3)
   unsigned int* hand_ticket;  // pass-3 work tickets
+  // camera side (k_camera, k_camera_prb): flags bit 0 = every sample, not only
+  // those whose first vertex is specular; each sample weighs W*H / N
+  float spp_inv;
 };
 
 typedef unsigned int lt_u32x4 __attribute__((ext_vector_type(4)));
@@ -130,6 +133,10 @@ hipError_t launch_lrb3_att(const PassArgs& A, int grid, int block, hipStream_t s
 hipError_t launch_trace_att(const PassArgs& A, bool tape, bool resv, int grid, hipStream_t s);
 hipError_t launch_naive_att_bwd(const PassArgs& A, int grid, hipStream_t s);
 hipError_t launch_reslrb_att(const PassArgs& A, int grid, int block, hipStream_t s);
+// camera side of the bidirectional combination: forward (adds to A.image)
+// and the path-replay backward (A.dI in, albedo / emitter gradients out)
+hipError_t launch_camera(const PassArgs& A, int grid, int block, hipStream_t s);
+hipError_t launch_camera_prb(const PassArgs& A, int grid, int block, hipStream_t s);
 hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t s);
 hipError_t launch_fill_u32(unsigned int* p, size_t n, unsigned int v, hipStream_t s);
 hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s);
@@ -142,7 +149,7 @@ hipError_t set_lds_limit(int bytes);
 // Workgroups of a backward kernel resident per CU at `block` threads and
 // `lds` dynamic LDS bytes (0 if it cannot launch or the query fails).
 enum class BwdKernel { naive, reslrb, lrb3, naive_att, reslrb_att, lrb3_att, lrb3_batch, lrb3_att_batch, lrb3_att_entry,
-                       lrb3_p2, lrb3_p3, lrb3_att_p2, lrb3_att_p3, lrb2, lrb3_att_p3_entry };
+                       lrb3_p2, lrb3_p3, lrb3_att_p2, lrb3_att_p3, lrb2, lrb3_att_p3_entry, camera_prb };
 int resident_groups(BwdKernel k, int block, size_t lds);
 hipError_t read_counters(uint64_t* out, bool reset, hipStream_t s);
 hipError_t launch_refit_level(Node* nodes, const Tri* tris, const int32_t* level_nodes, int n, hipStream_t s);

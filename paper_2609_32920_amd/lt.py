@@ -8,6 +8,7 @@ fallback.
 The functions carry the C ABI's names (include/lt.h):
   lt_create / lt_scene_upload / lt_trace / lt_loss_l2 /
   lt_backward_naive / lt_backward_reslrb / lt_backward_lrb3 / lt_backward_lrb2 /
+  lt_camera_trace / lt_camera_backward_prb /
   lt_guide_eval / lt_guide_emit / lt_guide_vertex_samples / lt_guide_grad / lt_guide_adam /
   lt_guide_train_step /
   lt_batch_create / lt_batch_step / lt_batch_autotune
@@ -30,6 +31,7 @@ COUNTERS_LIB_PATH = os.path.join(_HERE, "liblt_counters.so")
 LT_OK, LT_ERR_ARG, LT_ERR_OOM, LT_ERR_HIP, LT_ERR_STATE, LT_ERR_UNSUPPORTED = range(6)
 ATTACHED, SPLAT_SELECTED, RECORD_TAPE, RECORD_RESERVOIR, CONTRIB_ADJOINT, RECORD_SPLATS = 1, 2, 4, 8, 16, 32
 GUIDE_DIFFUSE = 64
+CAMERA_ALL = 128
 _STATUS = {1: "LT_ERR_ARG", 2: "LT_ERR_OOM", 3: "LT_ERR_HIP", 4: "LT_ERR_STATE", 5: "LT_ERR_UNSUPPORTED"}
 
 
@@ -123,6 +125,9 @@ def library(path=LIB_PATH):
                                   C.POINTER(Grads)], C.c_int),
             "lt_backward_lrb3_noalloc": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp, C.POINTER(Grads)],
                                          C.c_int),
+            "lt_camera_trace": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp], C.c_int),
+            "lt_camera_backward_prb": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp, C.POINTER(Grads)],
+                                       C.c_int),
             "lt_guide_eval": ([vp, vp, vp, vp, C.c_int64, vp], C.c_int),
             "lt_guide_emit": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp, vp], C.c_int),
             "lt_guide_vertex_samples": ([vp, C.POINTER(TraceArgs), C.POINTER(Params), vp], C.c_int),
@@ -151,7 +156,7 @@ def exported_symbols():
             "lt_set_memory_cap", "lt_get_stats", "lt_read_counters", "lt_scene_upload", "lt_side_state_bytes",
             "lt_workspace_bytes", "lt_trace", "lt_loss_l2", "lt_backward_naive", "lt_backward_reslrb",
             "lt_backward_lrb3", "lt_backward_lrb2", "lt_backward_lrb3_noalloc", "lt_guide_eval", "lt_guide_emit", "lt_guide_grad", "lt_guide_adam",
-            "lt_guide_train_step", "lt_guide_vertex_samples",
+            "lt_guide_train_step", "lt_guide_vertex_samples", "lt_camera_trace", "lt_camera_backward_prb",
             "lt_batch_create", "lt_batch_destroy", "lt_batch_last_error", "lt_batch_step", "lt_batch_set_tuning",
             "lt_batch_get_tuning", "lt_batch_autotune"]
 
@@ -372,6 +377,18 @@ class Context:
         g = self._grads(g_albedo, g_Le, g_heights, g_normal_map)
         self._status(self.lib.lt_backward_lrb3_noalloc(self.h, C.byref(a), C.byref(p), _ptr(d_image), C.byref(g)))
 
+    def camera_trace(self, a, p, image):
+        """lt_camera_trace: adds the camera samples' estimate to image."""
+        self._stream()
+        self._status(self.lib.lt_camera_trace(self.h, C.byref(a), C.byref(p), _ptr(image)))
+
+    def camera_backward_prb(self, a, p, d_image, g_albedo, g_Le):
+        """lt_camera_backward_prb: path-replay gradients of the camera samples
+        (accumulated)."""
+        self._stream()
+        g = self._grads(g_albedo, g_Le, None)
+        self._status(self.lib.lt_camera_backward_prb(self.h, C.byref(a), C.byref(p), _ptr(d_image), C.byref(g)))
+
     # ------------------------------------------------------------ guide
     def guide_eval(self, guide_w, x, n, out):
         """Raw network outputs out [count, 41] at x, n [count, 3] (device float32)."""
@@ -505,6 +522,14 @@ def lt_backward_lrb2(ctx, args, params, d_image, records, g_albedo, g_Le):
 
 def lt_backward_lrb3(ctx, args, params, d_image, g_albedo, g_Le, g_heights=None):
     return ctx.backward_lrb3(args, params, d_image, g_albedo, g_Le, g_heights)
+
+
+def lt_camera_trace(ctx, args, params, image):
+    return ctx.camera_trace(args, params, image)
+
+
+def lt_camera_backward_prb(ctx, args, params, d_image, g_albedo, g_Le):
+    return ctx.camera_backward_prb(args, params, d_image, g_albedo, g_Le)
 
 
 def lt_guide_eval(ctx, guide_w, x, n, out):

@@ -103,6 +103,49 @@ class GpuRun:
         return out
 
 
+def camera_trace(g, seed, n, depth, flags=0, mask=None, want_sig=False):
+    """Camera samples through lt_camera_trace (added to a zeroed image)."""
+    sig = torch.zeros(n, dtype=torch.int32, device=g.dev) if want_sig else None
+    m = None if mask is None else torch.as_tensor(np.asarray(mask, np.uint8), device=g.dev)
+    a = g.ctx.args(seed, n, depth, flags, m, sig)
+    img = torch.zeros((g.H, g.W, 3), dtype=torch.float32, device=g.dev)
+    g.ctx.camera_trace(a, g.params(), img)
+    torch.cuda.synchronize()
+    out = dict(image=img.cpu().numpy().astype(np.float64))
+    if want_sig:
+        out["sig"] = sig.cpu().numpy().view(np.uint32)
+    return out
+
+
+def camera_backward(g, seed, n, depth, dI, flags=0, mask=None):
+    """Path-replay gradients of the camera samples (lt_camera_backward_prb)."""
+    m = None if mask is None else torch.as_tensor(np.asarray(mask, np.uint8), device=g.dev)
+    a = g.ctx.args(seed, n, depth, flags, m)
+    dIt = torch.as_tensor(np.asarray(dI, np.float32), device=g.dev).contiguous()
+    g_alb = torch.zeros_like(g.albedo)
+    g_le = torch.zeros_like(g.Le)
+    g.ctx.camera_backward_prb(a, g.params(), dIt, g_alb, g_le)
+    torch.cuda.synchronize()
+    return dict(albedo=g_alb.cpu().numpy().astype(np.float64), Le=g_le.cpu().numpy().astype(np.float64),
+                stats=g.ctx.stats())
+
+
+def camera_matched(sc, g, seed, n, depth, flags=0, ids=None):
+    """Camera samples whose decision signatures agree on both sides (all n,
+    or the sample `ids`): (kept ids, mismatch fraction)."""
+    all_ = (flags & lt.CAMERA_ALL) != 0
+    if ids is None:
+        gs = camera_trace(g, seed, n, depth, flags, want_sig=True)["sig"]
+        r = O.render_camera(sc, seed, n, depth, spec_only=not all_, per_path=True)
+        same = gs == r["sig"]
+        return np.nonzero(same)[0].astype(np.uint32), 1.0 - same.mean()
+    ids = np.asarray(ids, np.uint32)
+    gs = camera_trace(g, seed, n, depth, flags, mask=mask_of(n, ids), want_sig=True)["sig"][ids]
+    r = O.render_camera(sc, seed, n, depth, spec_only=not all_, path_list=ids, per_path=True)
+    same = gs == r["sig"]
+    return ids[same], 1.0 - same.mean()
+
+
 def diffuse_table_flags(sc, g, rel=1e-5):
     """Entries of the diffuse guide table whose network outputs differ on the
     two sides beyond FP32 rounding (a bfloat16 rounding that flipped between

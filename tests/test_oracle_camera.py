@@ -208,3 +208,15 @@ def test_camera_emitter_radiance_scaling_identity():
     lhs = sc["Le"] * g["Le"]
     rhs = (dI * img).sum((0, 1))
     np.testing.assert_allclose(lhs, rhs, rtol=1e-10)
+
+
+def test_camera_matches_light_tracer_with_textured_emitter():
+    # next-event texel lookup against the light tracer's emission texel
+    sc = scenes.box_scene(width=16, height=16)
+    sc["emitter"]["tex_res"] = 4
+    sc["Le"] = np.random.default_rng(8).uniform(2.0, 20.0, size=(4, 4, 3))
+    depth, seeds = 2, 6
+    lt = np.stack([_blocks(O.render(sc, 800 + s, 1 << 18, depth)["image"], 4) for s in range(seeds)])
+    pt = np.stack([_blocks(O.render_camera(sc, 900 + s, 256 * 256, depth, spec_only=False)["image"], 4)
+                   for s in range(seeds)])
+    _agree(lt, pt, 0.015)
