@@ -13,7 +13,8 @@ The functions carry the C ABI's names (include/lt.h):
   lt_guide_train_step /
   lt_batch_create / lt_batch_step / lt_batch_autotune
 and ``LightTrace`` wraps forward + a chosen reverse mode as a
-``torch.autograd.Function``.
+``torch.autograd.Function``; ``CameraTrace`` does the same for the camera
+side of the bidirectional combination.
 """
 from __future__ import annotations
 
@@ -571,6 +572,47 @@ def lt_batch_autotune(batch, instances, cache_path=None):
 
 # ------------------------------------------------------------ autograd
 MODES = ("naive", "reslrb", "lrb3", "lrb2")
+
+
+class CameraTrace(torch.autograd.Function):
+    """image = CameraTrace.apply(albedo, Le, heights, ctx, seed, n_samples, depth, flags, mask)
+
+    The camera side of the bidirectional combination: lt_camera_trace into a
+    zeroed image forward, lt_camera_backward_prb with the incoming image
+    adjoint backward (path replay: nothing is kept between the two but the
+    arguments).  Without CAMERA_ALL in flags only samples whose first vertex
+    is specular contribute, so that
+        LightTrace.apply(...) + CameraTrace.apply(...)
+    estimates the whole image, each path through exactly one of the two.
+    Detached: albedo and Le receive gradients, heights (the geometry the
+    samples see, or None) none.  mask (optional, uint8 [n_samples]):
+    samples whose byte is 0 contribute nothing.
+    """
+
+    @staticmethod
+    def forward(fctx, albedo, Le, heights, ctx, seed, n_samples, depth, flags=0, mask=None):
+        if mask is not None and (mask.dtype != torch.uint8 or mask.numel() != n_samples or not mask.is_contiguous()):
+            raise ValueError("mask must be a contiguous uint8 tensor with one byte per sample")
+        a = ctx.args(seed, n_samples, depth, flags, mask)
+        p = ctx.params(albedo, Le, heights)
+        image = torch.zeros((ctx.H, ctx.W, 3), dtype=torch.float32, device=albedo.device)
+        ctx.camera_trace(a, p, image)
+        fctx.lt = (ctx, seed, n_samples, depth, flags, mask)
+        fctx.save_for_backward(albedo, Le, heights if heights is not None else torch.empty(0, device=albedo.device))
+        return image
+
+    @staticmethod
+    def backward(fctx, grad_image):
+        ctx, seed, n_samples, depth, flags, mask = fctx.lt
+        albedo, Le, heights = fctx.saved_tensors
+        heights = heights if heights.numel() else None
+        a = ctx.args(seed, n_samples, depth, flags, mask)
+        p = ctx.params(albedo, Le, heights)
+        dI = grad_image.to(torch.float32).contiguous()
+        g_alb = torch.zeros_like(albedo)
+        g_le = torch.zeros_like(Le)
+        ctx.camera_backward_prb(a, p, dI, g_alb, g_le)
+        return g_alb, g_le, None, None, None, None, None, None, None
 
 
 class LightTrace(torch.autograd.Function):

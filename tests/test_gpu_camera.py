@@ -134,3 +134,38 @@ def test_camera_rejects_what_it_does_not_support():
     imgd = torch.zeros((gd.H, gd.W, 3), dtype=torch.float32, device=gd.dev)
     with pytest.raises(lt.LTError, match="LT_ERR_UNSUPPORTED"):
         gd.ctx.camera_trace(gd.ctx.args(1, gd.W * gd.H, 4), gd.params(), imgd)
+
+
+def test_bidirectional_autograd_against_oracle():
+    """LightTrace (LRB-3) + CameraTrace under torch autograd with a scaled L2
+    loss on the glass slab, against the oracle's light-tracing and camera
+    gradients of the same loss (each side's image adjoint from its own
+    image), on signature-matched paths and samples."""
+    from gpu_common import matched_paths
+    sc = _slab()
+    g = GpuRun(sc)
+    seed_l, seed_c, n_l, spp, D, scale = 5, 6, 1 << 16, 32, 6, 2.0
+    n_c = spp * g.W * g.H
+    mask_l, ids_l, mis_l = matched_paths(sc, g, seed_l, n_l, D)
+    ids_c, mis_c = camera_matched(sc, g, seed_c, n_c, D)
+    assert mis_l <= 2e-3 and mis_c <= 2e-3
+    T = O.render(sc, 99, 1 << 16, D, albedo=sc["albedo_target"])["image"] + \
+        O.render_camera(sc, 98, 16 * g.W * g.H, D, albedo=sc["albedo_target"])["image"]
+    Io = O.render(sc, seed_l, n_l, D, path_list=ids_l)["image"] + \
+        O.render_camera(sc, seed_c, n_c, D, path_list=ids_c)["image"]
+    Lo, dIo = O.loss_and_adjoint(Io, T)
+    gl = O.gradient(sc, seed_l, n_l, D, scale * dIo, path_list=ids_l)
+    gc = O.gradient_camera(sc, seed_c, n_c, D, scale * dIo, path_list=ids_c)
+    alb = g.albedo.clone().requires_grad_(True)
+    le = g.Le.clone().requires_grad_(True)
+    ml = torch.as_tensor(mask_l, device=g.dev)
+    mc = torch.as_tensor(mask_of(n_c, ids_c), device=g.dev)
+    img = lt.LightTrace.apply(alb, le, g.heights, g.ctx, seed_l, n_l, D, "lrb3", 0, ml) + \
+        lt.CameraTrace.apply(alb, le, g.heights, g.ctx, seed_c, n_c, D, 0, mc)
+    loss = scale * ((img - torch.as_tensor(T, dtype=torch.float32, device=g.dev)) ** 2).mean()
+    loss.backward()
+    assert abs(loss.item() / (scale * Lo) - 1) <= 1e-4
+    assert maxrel(alb.grad.cpu().numpy().reshape(-1), (gl["albedo"] + gc["albedo"]).reshape(-1)) <= 5e-4
+    assert maxrel(le.grad.cpu().numpy(), gl["Le"] + gc["Le"]) <= 5e-4
+    # both sides carry gradient
+    assert np.abs(gc["albedo"]).sum() > 0.05 * np.abs(gl["albedo"]).sum()
