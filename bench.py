@@ -802,8 +802,11 @@ def bench_bidirectional(lt, scenes, dev, stream, bytes_per_path_fn, G=64, film=2
         bps = bytes_per_path_fn(c, n_s) + 12.0
         t_l = t["camera_prb_backward"] * 1e-3
         ach = bps * n_cam / t_l / 1e9
+        traffic = profiled_traffic("k_camera_prb_slab64_256_d8_1M.txt") if (G, film, spp, D) == (64, 256, 16, 8) else None
         roof = {"bound": "hbm", "kernel": "k_camera_prb", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_sample": round(bps, 1),
+                "traffic": traffic,
+                "traffic_frac": None if traffic is None else round(traffic / t_l / 1e9 / HBM_PEAK_GBS, 4),
                 "events_per_sample": {k: round(v / n_s, 3) for k, v in c.items()}}
     except Exception as e:  # the diagnostic build is optional
         print(f"# counters unavailable: {e}", file=sys.stderr)
