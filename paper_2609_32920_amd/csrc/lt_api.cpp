@@ -162,7 +162,7 @@ hipError_t upload(T** dst, const T* src, size_t n) {
 // end; host code reaches it only through the address hipGetSymbolAddress
 // returns for the current device (the array's name is a host-side stand-in).
 constexpr size_t kScratchBytes = (size_t)32 << 20;
-constexpr size_t kScratchCounters = 0, kScratchAcc = 256, kScratchHand = 512;
+constexpr size_t kScratchCounters = 0, kScratchAcc = kCtrBytes, kScratchHand = kCtrBytes + 256;
 static __device__ __align__(256) char scratch[kScratchBytes];
 
 struct lt_ctx {
@@ -464,7 +464,7 @@ PassArgs base_args(lt_ctx* c, const lt_trace_args* a, const lt_params* p) {
   A.nmap = p->normal_map;
   A.cond = c->has_conductor ? 1 : 0;
   A.counter = c->d_counter;
-  A.stats = reinterpret_cast<unsigned long long*>(c->d_counter + 16);  // same allocation, byte 64
+  A.stats = reinterpret_cast<unsigned long long*>(c->d_counter + kCtrStats);  // same allocation
   return A;
 }
 
@@ -505,7 +505,7 @@ lt_status lt_create(int device, void* stream, lt_ctx** out) {
   }
   c->guide_ok = guide_init() == hipSuccess;
   if (!c->guide_ok) (void)hipGetLastError();
-  if (hipMalloc((void**)&c->d_counter, 256) != hipSuccess || hipMalloc((void**)&c->d_acc, 256) != hipSuccess) {
+  if (hipMalloc((void**)&c->d_counter, kCtrBytes) != hipSuccess || hipMalloc((void**)&c->d_acc, 256) != hipSuccess) {
     hipFree(c->d_counter); hipFree(c->d_acc);
     delete c;
     return LT_ERR_OOM;
@@ -571,7 +571,7 @@ lt_status lt_get_stats(const lt_ctx* c, lt_stats* out) {
   if (!c || !out) return LT_ERR_ARG;
   uint64_t s[2] = {0, 0};
   if (hipStreamSynchronize(c->stream) != hipSuccess ||
-      hipMemcpy(s, c->d_counter + 16, sizeof(s), hipMemcpyDeviceToHost) != hipSuccess)
+      hipMemcpy(s, c->d_counter + kCtrStats, sizeof(s), hipMemcpyDeviceToHost) != hipSuccess)
     return LT_ERR_HIP;
   out->guard_triggers = s[0];
   out->nonfinite = s[1];
@@ -877,8 +877,8 @@ lt_status lt_trace(lt_ctx* c, const lt_trace_args* a, const lt_params* p, float*
   }
   size_t npix = (size_t)c->dsc.W * c->dsc.H * 3;
   if ((st = c->hip(launch_fill_f32(image, npix, 0.f, c->stream), "image clear")) != LT_OK) return st;
-  if ((st = c->hip(launch_fill_u32(c->d_counter, 1, 0u, c->stream), "counter clear")) != LT_OK) return st;
-  if ((st = c->hip(launch_fill_u32(c->d_counter + 16, 4, 0u, c->stream), "stats clear")) != LT_OK) return st;
+  if ((st = c->hip(launch_fill_u32(c->d_counter, kCtrBlock, 0u, c->stream), "counter clear")) != LT_OK) return st;
+  if ((st = c->hip(launch_fill_u32(c->d_counter + kCtrStats, 4, 0u, c->stream), "stats clear")) != LT_OK) return st;
   bool tape = (a->flags & LT_RECORD_TAPE) != 0;
   if (att_rec) {
     bool rec = (a->flags & LT_RECORD_RESERVOIR) != 0;
@@ -901,9 +901,10 @@ lt_status lt_loss_l2(lt_ctx* c, const float* image, const float* target, int64_t
   return c->hip(launch_loss(image, target, (size_t)n, d_image, c->d_acc + 3, loss, c->stream), "loss launch");
 }
 
-// Where a backward call keeps its working memory: u32 counters ([0] work
-// tickets, [1] LRB-3 hand-off entries, [2] pass-3 tickets, [16..19] two u64
-// statistics), the FP64 emitter-gradient accumulators and the LRB-3 hand-off.
+// Where a backward call keeps its working memory: the counter area (the
+// pass's eight work counters, LRB-3 pass 3's eight, the two u64 statistics;
+// lt_common.h), the FP64 emitter-gradient accumulators and the LRB-3
+// hand-off.
 // The ordinary entry points use the context's buffers and grow the hand-off
 // on demand; the no-allocation entry point points all three into the static
 // scratch.
@@ -925,7 +926,7 @@ static lt_status backward_common(lt_ctx* c, const lt_trace_args* a, const lt_par
   if ((st = prepare_geometry(c, p)) != LT_OK) return st;
   A = base_args(c, a, p);
   A.counter = w.counter;
-  A.stats = reinterpret_cast<unsigned long long*>(w.counter + 16);
+  A.stats = reinterpret_cast<unsigned long long*>(w.counter + kCtrStats);
   if ((st = guide_prepass(c, a, p, A)) != LT_OK) return st;
   A.dI = d_image;
   A.g_albedo = g->albedo;
@@ -934,8 +935,8 @@ static lt_status backward_common(lt_ctx* c, const lt_trace_args* a, const lt_par
   A.g_heights = g->heights;
   A.g_nmap = (a->flags & LT_ATTACHED) ? g->normal_map : nullptr;
   if ((st = c->hip(launch_fill_f64(w.acc, 3, 0.0, c->stream), "acc clear")) != LT_OK) return st;
-  if ((st = c->hip(launch_fill_u32(w.counter + 16, 4, 0u, c->stream), "stats clear")) != LT_OK) return st;
-  return c->hip(launch_fill_u32(w.counter, 1, 0u, c->stream), "counter clear");
+  if ((st = c->hip(launch_fill_u32(w.counter + kCtrStats, 4, 0u, c->stream), "stats clear")) != LT_OK) return st;
+  return c->hip(launch_fill_u32(w.counter, kCtrBlock, 0u, c->stream), "counter clear");
 }
 static lt_status backward_common(lt_ctx* c, const lt_trace_args* a, const lt_params* p, const float* d_image,
                                  lt_grads* g, PassArgs& A, size_t side) {
@@ -1022,7 +1023,7 @@ static lt_status lrb3_enqueue(lt_ctx* c, const lt_trace_args* a, const lt_params
   A.contrib = a->path_contrib;
   const bool att = (a->flags & LT_ATTACHED) != 0;
   if (lrb3_split(c, a)) {
-    // pass 2 appends one hand-off entry per connected path; pass 3 replays those
+    // pass 2 writes a hand-off entry per path; pass 3 replays the connected ones
     char* hand = w.hand;
     if (!hand) {
       if ((st = grow(c, &c->d_hand, c->hand_n, hand_bytes(c, a), "the LRB-3 hand-off")) != LT_OK) return st;
@@ -1030,9 +1031,8 @@ static lt_status lrb3_enqueue(lt_ctx* c, const lt_trace_args* a, const lt_params
     }
     A.hand = reinterpret_cast<Lrb3Hand*>(hand);
     A.hand_att = reinterpret_cast<Lrb3HandAtt*>(hand);
-    A.hand_n = w.counter + 1;
-    A.hand_ticket = w.counter + 2;
-    if ((st = c->hip(launch_fill_u32(w.counter + 1, 2, 0u, c->stream), "hand-off clear")) != LT_OK) return st;
+    A.counter3 = w.counter + kCtrBlock;
+    if ((st = c->hip(launch_fill_u32(A.counter3, kCtrBlock, 0u, c->stream), "pass-3 counter clear")) != LT_OK) return st;
     if (att) {
       const int blk2 = 256;
       if ((st = c->hip(launch_lrb3_att_p2(A, persistent_grid(c, a->n_paths, blk2), blk2, c->stream),
@@ -1130,8 +1130,8 @@ lt_status lt_camera_trace(lt_ctx* c, const lt_trace_args* a, const lt_params* p,
   PassArgs A = base_args(c, &b, &q);
   camera_fields(c, a, A);
   A.image = image;
-  if ((st = c->hip(launch_fill_u32(c->d_counter, 1, 0u, c->stream), "counter clear")) != LT_OK) return st;
-  if ((st = c->hip(launch_fill_u32(c->d_counter + 16, 4, 0u, c->stream), "stats clear")) != LT_OK) return st;
+  if ((st = c->hip(launch_fill_u32(c->d_counter, kCtrBlock, 0u, c->stream), "counter clear")) != LT_OK) return st;
+  if ((st = c->hip(launch_fill_u32(c->d_counter + kCtrStats, 4, 0u, c->stream), "stats clear")) != LT_OK) return st;
   const int blk = c->tune.block;
   return c->hip(launch_camera(A, persistent_grid(c, a->n_paths, blk), blk, c->stream), "camera launch");
 }
@@ -1197,7 +1197,7 @@ lt_status lt_guide_vertex_samples(lt_ctx* c, const lt_trace_args* a, const lt_pa
   PassArgs A = base_args(c, &e, p);
   A.gsamp = reinterpret_cast<float*>(out);
   if ((st = guide_prepass(c, &e, p, A)) != LT_OK) return st;
-  if ((st = c->hip(launch_fill_u32(c->d_counter, 1, 0u, c->stream), "counter clear")) != LT_OK) return st;
+  if ((st = c->hip(launch_fill_u32(c->d_counter, kCtrBlock, 0u, c->stream), "counter clear")) != LT_OK) return st;
   int grid = persistent_grid(c, a->n_paths, c->tune.block);
   return c->hip(launch_trace_gsamples(A, grid, c->tune.block, c->stream), "diffuse guide samples");
 }
@@ -1276,12 +1276,12 @@ struct lt_batch {
   // device tables: trace [n], detached backward [n_det], attached backward [n_att]
   PassArgs* d_tab = nullptr;
   size_t tab_cap = 0;                 // PassArgs entries allocated
-  unsigned int* d_cnt = nullptr;      // work-ticket counters [2n]
+  unsigned int* d_cnt = nullptr;      // work counters, a block per pass of each instance [2n][kCtrBlock]
   double* d_acc = nullptr;            // per instance: emitter gradient (3) + loss (1)
   size_t inst_cap = 0;
   char* d_hand = nullptr;             // LRB-3 hand-off of the solo attached instances, one at a time
   size_t hand_cap = 0;                // bytes
-  unsigned int* d_hcnt = nullptr;     // their hand-off counters [2n]
+  unsigned int* d_hcnt = nullptr;     // LRB-3 pass-3 counters of the solo instances [n][kCtrBlock]
   // captured step
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1367,9 +1367,9 @@ lt_status batch_reserve(lt_batch* b, const lt_instance* inst, int n) {
   if (b->inst_cap < (size_t)n) {
     hipFree(b->d_cnt); hipFree(b->d_acc); hipFree(b->d_hcnt);
     b->d_cnt = nullptr; b->d_acc = nullptr; b->d_hcnt = nullptr; b->inst_cap = 0;
-    if (hipMalloc((void**)&b->d_cnt, (size_t)2 * n * sizeof(unsigned int)) != hipSuccess ||
+    if (hipMalloc((void**)&b->d_cnt, (size_t)2 * n * kCtrBlock * sizeof(unsigned int)) != hipSuccess ||
         hipMalloc((void**)&b->d_acc, (size_t)4 * n * sizeof(double)) != hipSuccess ||
-        hipMalloc((void**)&b->d_hcnt, (size_t)2 * n * sizeof(unsigned int)) != hipSuccess) {
+        hipMalloc((void**)&b->d_hcnt, (size_t)n * kCtrBlock * sizeof(unsigned int)) != hipSuccess) {
       (void)hipGetLastError();
       return b->fail(LT_ERR_OOM, "out of device memory for the batch counters");
     }
@@ -1417,7 +1417,7 @@ BatchPlan batch_plan(lt_batch* b, const lt_instance* inst, int n, int64_t path_d
     P.stack_n = std::max(P.stack_n, c->dsc.stack_n);
     PassArgs T = A;
     T.image = I.image;
-    T.counter = b->d_cnt + i;
+    T.counter = b->d_cnt + (size_t)i * kCtrBlock;
     P.tab[i] = T;
     PassArgs B = A;
     B.dI = I.d_image;
@@ -1426,7 +1426,7 @@ BatchPlan batch_plan(lt_batch* b, const lt_instance* inst, int n, int64_t path_d
     B.g_nmap = (I.args.flags & LT_ATTACHED) ? I.grads.normal_map : nullptr;
     B.g_Le_acc = b->d_acc + 4 * i;
     B.g_le_tex = c->dsc.em_tex_res > 0 ? I.grads.emitter_L : nullptr;
-    B.counter = b->d_cnt + n + i;
+    B.counter = b->d_cnt + (size_t)(n + i) * kCtrBlock;
     // by the caller's path count, so the autotuner's shortened steps keep the plan's shape
     ((a.flags & LT_ATTACHED) ? (I.args.n_paths >= kSoloPaths ? P.solo : P.att) : P.det).push_back(i);
     P.tab[n + i] = B;  // reordered below
@@ -1475,8 +1475,7 @@ BatchPlan batch_plan(lt_batch* b, const lt_instance* inst, int n, int64_t path_d
     const int i = P.solo[k];
     PassArgs& B = P.tab[n + i];
     B.hand_att = reinterpret_cast<Lrb3HandAtt*>(b->d_hand);
-    B.hand_n = b->d_hcnt + 2 * k;
-    B.hand_ticket = b->d_hcnt + 2 * k + 1;
+    B.counter3 = b->d_hcnt + k * kCtrBlock;
     const int blk = att_replay_block(inst[i].ctx, inst[i].grads.heights, P.stack_n, BwdKernel::lrb3_att_p3_entry, 768);
     const size_t stack = (size_t)P.stack_n * blk * sizeof(int);
     auto free_of_cost = [&](size_t extra) {
@@ -1523,7 +1522,7 @@ lt_status batch_enqueue_on(lt_batch* b, const lt_instance* inst, const BatchPlan
     if ((st = b->hip(launch_fill_f32(I.image, npix, 0.f, s), "image clear")) != LT_OK) return st;
   }
   lt_status st;
-  if ((st = b->hip(launch_fill_u32(b->d_cnt, (size_t)2 * n, 0u, s), "counter clear")) != LT_OK) return st;
+  if ((st = b->hip(launch_fill_u32(b->d_cnt, (size_t)2 * n * kCtrBlock, 0u, s), "counter clear")) != LT_OK) return st;
   if ((st = b->hip(launch_fill_f64(b->d_acc, (size_t)4 * n, 0.0, s), "accumulator clear")) != LT_OK) return st;
   int grid = (int)std::max<int64_t>(1, (int64_t)b->n_cu * b->tune.blocks_per_cu);
   if ((st = b->hip(launch_trace_batch(b->d_tab, n, P.stack_n, grid, b->tune.block, s), "batched trace")) != LT_OK)
@@ -1545,7 +1544,7 @@ lt_status batch_enqueue_on(lt_batch* b, const lt_instance* inst, const BatchPlan
       return st;
   }
   if (!P.solo.empty() &&
-      (st = b->hip(launch_fill_u32(b->d_hcnt, 2 * P.solo.size(), 0u, s), "hand-off clear")) != LT_OK)
+      (st = b->hip(launch_fill_u32(b->d_hcnt, P.solo.size() * kCtrBlock, 0u, s), "pass-3 counter clear")) != LT_OK)
     return st;
   for (size_t k = 0; k < P.solo.size(); ++k) {
     const int e = n + nd + na + (int)k;

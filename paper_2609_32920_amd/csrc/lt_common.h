@@ -9,6 +9,16 @@ constexpr int kMaxDepth = 64;     // largest max_depth accepted
 constexpr float kEps = 1e-4f;     // ray-origin offset along the geometric normal
 constexpr float kTmin = 1e-4f;    // closest/any-hit lower bound
 
+// Work counters of a pass: eight, counter c dealing out the path indices
+// p = 8k + c, each on a 128-byte line of its own; a context's counter area
+// holds two such blocks (LRB-3 pass 3 takes the second) and, after them,
+// the two 64-bit statistics.
+constexpr int kWorkClasses = 8;
+constexpr int kCtrStride = 32;                        // u32 from one counter to the next
+constexpr int kCtrBlock = kWorkClasses * kCtrStride;  // u32 of one pass's counters (1 KB)
+constexpr int kCtrStats = 2 * kCtrBlock;              // u32 index of the statistics (byte 2048)
+constexpr int kCtrBytes = 4096;                       // bytes of a counter area
+
 // Two-child BVH node, 64 bytes: both child boxes arrive with one fetch.
 // count > 0: the child is a leaf holding `count` triangles from `child`;
 // count == 0: `child` is an inner node index; child < 0: empty.
@@ -100,10 +110,11 @@ struct alignas(16) ResRecAtt {
 static_assert(sizeof(ResRecAtt) == 160, "attached reservoir record layout");
 
 // LRB-3 hand-off between the two replays (Sec. 4.3: the per-sample state of
-// the method), one entry per path that has a sensor connection, appended by
-// the pass-2 kernel and consumed by the pass-3 kernel: the path, the depth of
-// its last connection, one bit per vertex for a valid connection and
-// delta_total (FP64, Eq. 14); attached also A = sum_i a_i M_i (Eq. 18).
+// the method), one entry per path at the path's index, written by the
+// pass-2 kernel (klast 0: the path has nothing to back-propagate) and read
+// by the pass-3 kernel: the path, the depth of its last connection, one bit
+// per vertex for a valid connection and delta_total (FP64, Eq. 14);
+// attached also A = sum_i a_i M_i (Eq. 18).
 struct alignas(8) Lrb3Hand {
   uint32_t path;
   int32_t klast;

@@ -661,8 +661,17 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return (1ull << __lane_id()) - 1ull;
 }
 
+// XCD (accelerator complex die) of the executing workgroup: hardware
+// register XCC_ID, bits 3:0.  A workgroup stays on its XCD.
+__device__ __forceinline__ int xcd_id() { return __builtin_amdgcn_s_getreg((3 << 11) | 20) & 7; }
+
+// A wave's place in the work distribution: the counter block of the pass,
+// the residue class it draws from and how many classes it has found used up.
+struct WorkQ { unsigned int* base; int cls; int tried; };
+__device__ __forceinline__ WorkQ work_begin(unsigned int* base) { return {base, xcd_id(), 0}; }
+
 // Wave-aggregated work fetch: every lane with `need` set gets the next
-// unused path index (one atomic per wave).
+// unused index of `counter` (one atomic per wave).
 __device__ __forceinline__ uint32_t fetch_paths(unsigned int* counter, bool need) {
   uint64_t m = __ballot(need);
   unsigned int base = 0;

@@ -21,7 +21,7 @@ struct PassArgs {
   const float* Le;
   const float* heights;
   const float* nmap;          // normal-map slopes [G][G][2] of the heightfield, or null
-  unsigned int* counter;
+  unsigned int* counter;      // work counters (a block of kCtrBlock u32, zero at launch)
   // forward outputs
   float* image;
   TapeRec* tape;
@@ -52,16 +52,15 @@ struct PassArgs {
   const float* tape_gw_in;
   float* gsamp;               // diffuse guide training samples [n_paths][12], or null
   float* contrib;             // per-path image contribution sum_i lum(C_i), or null
-  // LRB-3 as two kernels: pass 2 appends a hand-off entry per connected path,
-  // pass 3 replays the queued paths
+  // LRB-3 as two kernels: pass 2 writes a hand-off entry per path, pass 3
+  // replays the paths whose entry holds a connection
   SplatHdr* spl_hdr;          // buffered two-pass: per-path header [n_paths] (forward writes)
   SplatRec* spl;              // and splat records [D][n_paths]
   const SplatHdr* spl_hdr_in; // (backward reads)
   const SplatRec* spl_in;
-  Lrb3Hand* hand;             // detached entries [n_paths]
-  Lrb3HandAtt* hand_att;      // attached entries [n_paths]
-  unsigned int* hand_n;       // entries appended (pass 2) / available (pass 3)
-  unsigned int* hand_ticket;  // pass-3 work tickets
+  Lrb3Hand* hand;             // detached entries [n_paths], indexed by path (klast 0: none)
+  Lrb3HandAtt* hand_att;      // attached entries [n_paths], indexed by path
+  unsigned int* counter3;     // pass 3's work counters (a block of kCtrBlock u32)
   // camera side (k_camera, k_camera_prb): flags bit 0 = every sample, not only
   // those whose first vertex is specular; each sample weighs W*H / N
   float spp_inv;
