@@ -203,9 +203,9 @@ typedef struct {
                               the kernel no resident workgroups; 0: never (waves then
                               write-combine them into the gradient array) */
   int32_t lrb3_split;      /* how lt_backward_lrb3 runs its two replays.  Split: pass 2 and
-                              pass 3 as two kernels, each path's state (delta_total, validity
-                              bits, last connection depth; attached also A) handed over in
-                              library workspace, 40 or 64 bytes per path, flat in
+                              pass 3 as two kernels, each connected path's state (delta_total,
+                              validity bits, last connection depth; attached also A) handed
+                              over in library workspace, 40 or 64 bytes per path, flat in
                               depth.  Fused: one kernel runs both passes per path, state in
                               registers.  0: fused always; 1: split always; 2 (default):
                               split for LT_ATTACHED calls, fused for detached ones */
@@ -343,7 +343,7 @@ lt_status lt_backward_lrb3(lt_ctx* ctx, const lt_trace_args* args, const lt_para
  * library holds on each GPU it runs on until the process ends.  The call
  * allocates nothing; the caller still passes inputs and outputs.
  * Limits: with the two-kernel form (lt_tuning.lrb3_split) n_paths is at most
- * 524,220 attached (64-byte hand-off entries) or 838,752 detached (40-byte
+ * 524,216 attached (64-byte hand-off entries) or 838,752 detached (40-byte
  * entries); the fused form has no limit.  No emission guide (its per-path
  * records are allocated).  lt_get_stats does not report its counters.
  * Every call on a GPU shares that GPU's array (all contexts on it included)

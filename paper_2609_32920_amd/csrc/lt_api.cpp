@@ -356,9 +356,12 @@ size_t guide_bytes(const lt_trace_args* a, const lt_params* p) {
 bool lrb3_split(const lt_ctx* c, const lt_trace_args* a) {
   return c->tune.lrb3_split == 1 || (c->tune.lrb3_split == 2 && (a->flags & LT_ATTACHED));
 }
+// entries per class region of the hand-off: ceil(n_paths / 8)
+uint32_t hand_region(int64_t n_paths) { return (uint32_t)((n_paths + kWorkClasses - 1) / kWorkClasses); }
 size_t hand_bytes(const lt_ctx* c, const lt_trace_args* a) {
   if (!lrb3_split(c, a) || a->n_paths < 1) return 0;
-  return (size_t)a->n_paths * ((a->flags & LT_ATTACHED) ? sizeof(Lrb3HandAtt) : sizeof(Lrb3Hand));
+  return (size_t)kWorkClasses * hand_region(a->n_paths) *
+         ((a->flags & LT_ATTACHED) ? sizeof(Lrb3HandAtt) : sizeof(Lrb3Hand));
 }
 
 template <typename T>
@@ -902,9 +905,9 @@ lt_status lt_loss_l2(lt_ctx* c, const float* image, const float* target, int64_t
 }
 
 // Where a backward call keeps its working memory: the counter area (the
-// pass's eight work counters, LRB-3 pass 3's eight, the two u64 statistics;
-// lt_common.h), the FP64 emitter-gradient accumulators and the LRB-3
-// hand-off.
+// pass's eight work counters, LRB-3 pass 3's eight, pass 2's eight append
+// counters, the two u64 statistics; lt_common.h), the FP64 emitter-gradient
+// accumulators and the LRB-3 hand-off.
 // The ordinary entry points use the context's buffers and grow the hand-off
 // on demand; the no-allocation entry point points all three into the static
 // scratch.
@@ -1023,7 +1026,7 @@ static lt_status lrb3_enqueue(lt_ctx* c, const lt_trace_args* a, const lt_params
   A.contrib = a->path_contrib;
   const bool att = (a->flags & LT_ATTACHED) != 0;
   if (lrb3_split(c, a)) {
-    // pass 2 writes a hand-off entry per path; pass 3 replays the connected ones
+    // pass 2 appends a hand-off entry per connected path; pass 3 replays those
     char* hand = w.hand;
     if (!hand) {
       if ((st = grow(c, &c->d_hand, c->hand_n, hand_bytes(c, a), "the LRB-3 hand-off")) != LT_OK) return st;
@@ -1031,8 +1034,11 @@ static lt_status lrb3_enqueue(lt_ctx* c, const lt_trace_args* a, const lt_params
     }
     A.hand = reinterpret_cast<Lrb3Hand*>(hand);
     A.hand_att = reinterpret_cast<Lrb3HandAtt*>(hand);
+    A.hand_region = hand_region(a->n_paths);
     A.counter3 = w.counter + kCtrBlock;
-    if ((st = c->hip(launch_fill_u32(A.counter3, kCtrBlock, 0u, c->stream), "pass-3 counter clear")) != LT_OK) return st;
+    A.hand_app = w.counter + 2 * kCtrBlock;
+    if ((st = c->hip(launch_fill_u32(A.counter3, 2 * kCtrBlock, 0u, c->stream), "hand-off counter clear")) != LT_OK)
+      return st;
     if (att) {
       const int blk2 = 256;
       if ((st = c->hip(launch_lrb3_att_p2(A, persistent_grid(c, a->n_paths, blk2), blk2, c->stream),
@@ -1281,7 +1287,7 @@ struct lt_batch {
   size_t inst_cap = 0;
   char* d_hand = nullptr;             // LRB-3 hand-off of the solo attached instances, one at a time
   size_t hand_cap = 0;                // bytes
-  unsigned int* d_hcnt = nullptr;     // LRB-3 pass-3 counters of the solo instances [n][kCtrBlock]
+  unsigned int* d_hcnt = nullptr;     // LRB-3 pass-3 and append counters of the solo instances [n][2][kCtrBlock]
   // captured step
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1369,7 +1375,7 @@ lt_status batch_reserve(lt_batch* b, const lt_instance* inst, int n) {
     b->d_cnt = nullptr; b->d_acc = nullptr; b->d_hcnt = nullptr; b->inst_cap = 0;
     if (hipMalloc((void**)&b->d_cnt, (size_t)2 * n * kCtrBlock * sizeof(unsigned int)) != hipSuccess ||
         hipMalloc((void**)&b->d_acc, (size_t)4 * n * sizeof(double)) != hipSuccess ||
-        hipMalloc((void**)&b->d_hcnt, (size_t)n * kCtrBlock * sizeof(unsigned int)) != hipSuccess) {
+        hipMalloc((void**)&b->d_hcnt, (size_t)n * 2 * kCtrBlock * sizeof(unsigned int)) != hipSuccess) {
       (void)hipGetLastError();
       return b->fail(LT_ERR_OOM, "out of device memory for the batch counters");
     }
@@ -1378,7 +1384,7 @@ lt_status batch_reserve(lt_batch* b, const lt_instance* inst, int n) {
   size_t hand = 0;  // the largest solo instance's hand-off
   for (int i = 0; i < n; ++i)
     if ((inst[i].args.flags & LT_ATTACHED) && inst[i].args.n_paths >= kSoloPaths)
-      hand = std::max(hand, (size_t)inst[i].args.n_paths * sizeof(Lrb3HandAtt));
+      hand = std::max(hand, (size_t)kWorkClasses * hand_region(inst[i].args.n_paths) * sizeof(Lrb3HandAtt));
   if (b->hand_cap < hand) {
     hipFree(b->d_hand); b->d_hand = nullptr; b->hand_cap = 0;
     if (hipMalloc((void**)&b->d_hand, hand) != hipSuccess) {
@@ -1475,7 +1481,9 @@ BatchPlan batch_plan(lt_batch* b, const lt_instance* inst, int n, int64_t path_d
     const int i = P.solo[k];
     PassArgs& B = P.tab[n + i];
     B.hand_att = reinterpret_cast<Lrb3HandAtt*>(b->d_hand);
-    B.counter3 = b->d_hcnt + k * kCtrBlock;
+    B.counter3 = b->d_hcnt + k * 2 * kCtrBlock;
+    B.hand_app = B.counter3 + kCtrBlock;
+    B.hand_region = hand_region(B.n_paths);
     const int blk = att_replay_block(inst[i].ctx, inst[i].grads.heights, P.stack_n, BwdKernel::lrb3_att_p3_entry, 768);
     const size_t stack = (size_t)P.stack_n * blk * sizeof(int);
     auto free_of_cost = [&](size_t extra) {
@@ -1544,7 +1552,7 @@ lt_status batch_enqueue_on(lt_batch* b, const lt_instance* inst, const BatchPlan
       return st;
   }
   if (!P.solo.empty() &&
-      (st = b->hip(launch_fill_u32(b->d_hcnt, P.solo.size() * kCtrBlock, 0u, s), "pass-3 counter clear")) != LT_OK)
+      (st = b->hip(launch_fill_u32(b->d_hcnt, P.solo.size() * 2 * kCtrBlock, 0u, s), "hand-off counter clear")) != LT_OK)
     return st;
   for (size_t k = 0; k < P.solo.size(); ++k) {
     const int e = n + nd + na + (int)k;

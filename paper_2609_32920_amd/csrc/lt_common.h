@@ -11,12 +11,13 @@ constexpr float kTmin = 1e-4f;    // closest/any-hit lower bound
 
 // Work counters of a pass: eight, counter c dealing out the path indices
 // p = 8k + c, each on a 128-byte line of its own; a context's counter area
-// holds two such blocks (LRB-3 pass 3 takes the second) and, after them,
-// the two 64-bit statistics.
+// holds three such blocks (the pass's; LRB-3 pass 3's; pass 2's append
+// counters of the hand-off, one per class) and, after them, the two 64-bit
+// statistics.
 constexpr int kWorkClasses = 8;
 constexpr int kCtrStride = 32;                        // u32 from one counter to the next
 constexpr int kCtrBlock = kWorkClasses * kCtrStride;  // u32 of one pass's counters (1 KB)
-constexpr int kCtrStats = 2 * kCtrBlock;              // u32 index of the statistics (byte 2048)
+constexpr int kCtrStats = 3 * kCtrBlock;              // u32 index of the statistics (byte 3072)
 constexpr int kCtrBytes = 4096;                       // bytes of a counter area
 
 // Two-child BVH node, 64 bytes: both child boxes arrive with one fetch.
@@ -110,11 +111,12 @@ struct alignas(16) ResRecAtt {
 static_assert(sizeof(ResRecAtt) == 160, "attached reservoir record layout");
 
 // LRB-3 hand-off between the two replays (Sec. 4.3: the per-sample state of
-// the method), one entry per path at the path's index, written by the
-// pass-2 kernel (klast 0: the path has nothing to back-propagate) and read
-// by the pass-3 kernel: the path, the depth of its last connection, one bit
-// per vertex for a valid connection and delta_total (FP64, Eq. 14);
-// attached also A = sum_i a_i M_i (Eq. 18).
+// the method), one entry per path that has something to back-propagate,
+// appended by the pass-2 kernel to the region of the path's class (p mod 8;
+// eight regions of ceil(N / 8) entries, eight append counters) and read by
+// the pass-3 kernel: the path, the depth of its last connection, one bit per
+// vertex for a valid connection and delta_total (FP64, Eq. 14); attached
+// also A = sum_i a_i M_i (Eq. 18).
 struct alignas(8) Lrb3Hand {
   uint32_t path;
   int32_t klast;

@@ -172,9 +172,11 @@ __device__ __forceinline__ uint32_t sig_event(uint32_t h, const Event& ev) {
 // index below n_paths is handed out exactly once whatever the XCD reads.
 // Paths that `accept` rejects (default: the path mask) get their per-path
 // outputs cleared by `on_skip`.
-template <typename Skip, typename Accept>
-__device__ __forceinline__ void refill(const PassArgs& A, WorkQ& q, bool& alive, bool& exhausted, uint32_t& path,
-                                       Skip on_skip, Accept accept) {
+// The same over any eight classes of work: class c holds limit(c) items,
+// the k-th of them being index(c, k).
+template <typename Limit, typename Index, typename Skip, typename Accept>
+__device__ __forceinline__ void refill_classes(WorkQ& q, bool& alive, bool& exhausted, uint32_t& item, Limit limit,
+                                               Index index, Skip on_skip, Accept accept) {
   while (true) {
     bool need = !alive && !exhausted;
     if (__ballot(need) == 0ull) break;
@@ -183,22 +185,58 @@ __device__ __forceinline__ void refill(const PassArgs& A, WorkQ& q, bool& alive,
       break;
     }
     const uint32_t k = fetch_paths(q.base + q.cls * kCtrStride, need);
-    const uint32_t p = k * (uint32_t)kWorkClasses + (uint32_t)q.cls;
-    const bool over = need && p >= (uint32_t)A.n_paths;
+    const bool over = need && k >= limit(q.cls);
+    const uint32_t p = index(q.cls, k);
     if (__ballot(over) != 0ull) {  // this class is used up: the next one
       q.cls = (q.cls + 1) & (kWorkClasses - 1);
       ++q.tried;
     }
     if (need && !over) {
       if (!accept(p)) on_skip(p);
-      else { alive = true; path = p; }
+      else { alive = true; item = p; }
     }
   }
+}
+// paths: class c holds p = 8k + c below n_paths
+template <typename Skip, typename Accept>
+__device__ __forceinline__ void refill(const PassArgs& A, WorkQ& q, bool& alive, bool& exhausted, uint32_t& path,
+                                       Skip on_skip, Accept accept) {
+  const uint32_t N = (uint32_t)A.n_paths;
+  refill_classes(
+      q, alive, exhausted, path,
+      [&](int c) { return N > (uint32_t)c ? (N - (uint32_t)c + (uint32_t)kWorkClasses - 1u) / (uint32_t)kWorkClasses : 0u; },
+      [&](int c, uint32_t k) { return k * (uint32_t)kWorkClasses + (uint32_t)c; }, on_skip, accept);
 }
 template <typename Skip>
 __device__ __forceinline__ void refill(const PassArgs& A, WorkQ& q, bool& alive, bool& exhausted, uint32_t& path,
                                        Skip on_skip) {
   refill(A, q, alive, exhausted, path, on_skip, [&](uint32_t p) { return !(A.mask && A.mask[p] == 0); });
+}
+// LRB-3 pass 3: the entries pass 2 appended, region by region
+__device__ __forceinline__ void refill_hand(const PassArgs& A, WorkQ& q, bool& alive, bool& exhausted,
+                                            uint32_t& item) {
+  refill_classes(
+      q, alive, exhausted, item, [&](int c) { return A.hand_app[c * kCtrStride]; },
+      [&](int c, uint32_t k) { return (uint32_t)c * A.hand_region + k; }, [&](uint32_t) {},
+      [&](uint32_t) { return true; });
+}
+
+// Pass 2's append of one entry per path that has one (`put`): grouped by the
+// path's class, one atomic per class present in the wave; returns the
+// entry's index (valid where put).  Every lane of the wave calls it.
+__device__ __forceinline__ uint32_t hand_append(const PassArgs& A, bool put, uint32_t path) {
+  const int c = (int)(path & (uint32_t)(kWorkClasses - 1));
+  uint32_t slot = 0;
+  bool todo = put;
+  while (true) {
+    const uint64_t m = __ballot(todo);
+    if (m == 0ull) break;
+    const int cl = __shfl(c, __ffsll((unsigned long long)m) - 1);
+    const bool mine = todo && c == cl;
+    const uint32_t k = fetch_paths(A.hand_app + cl * kCtrStride, mine);
+    if (mine) { slot = (uint32_t)cl * A.hand_region + k; todo = false; }
+  }
+  return slot;
 }
 
 // Non-finite values (a division by a vanishing cosine, length or
@@ -811,16 +849,16 @@ __global__ void __launch_bounds__(1024) k_lrb2_bwd(PassArgs A) {
 // ---------------------------------------------------------------- LRB-3, two kernels
 // The same two replays as k_lrb3_bwd, each a kernel of its own with the
 // method's per-path state handed over in memory (Lrb3Hand, 40 bytes per
-// path at the path's index, flat in depth).  Every wave then runs one phase:
-// pass 2's shadow rays and pass 3's gradient scatters never share a wave, and
-// pass 3 takes only the paths with a sensor connection (its refill skips the
-// others without replaying them).
+// connected path, appended per class of the path index, flat in depth).
+// Every wave then runs one phase: pass 2's shadow rays and pass 3's gradient
+// scatters never share a wave, and pass 3 visits only the paths with a
+// sensor connection, compacted by the append.
 
 // Pass 2 (Eq. 14): replay with the sensor connections (shadow rays
 // included), delta_total = sum_i dI(u_i) C_i in FP64, one bit per vertex for
 // a valid connection, the depth of the last one.  A path whose delta_total is
 // nonzero gets its emitter gradient delta_total / L_e here and a hand-off
-// entry at its index; every other path an entry with klast 0.
+// entry (appended to its class's region).
 __device__ __forceinline__ void lrb3_p2_run(const PassArgs& A, int* lds) {
   int* stk = lds + threadIdx.x;
   const int ss = blockDim.x;
@@ -837,11 +875,9 @@ __device__ __forceinline__ void lrb3_p2_run(const PassArgs& A, int* lds) {
   double gl0 = 0.0, gl1 = 0.0, gl2 = 0.0;
   WorkQ wq = work_begin(A.counter);
   while (true) {
-    refill(A, wq, alive, exhausted, path, [&](uint32_t p) {
-      if (A.contrib) A.contrib[p] = 0.f;
-      A.hand[p].klast = 0;
-    });
+    refill(A, wq, alive, exhausted, path, [&](uint32_t p) { if (A.contrib) A.contrib[p] = 0.f; });
     if (__ballot(alive) == 0ull) break;
+    bool put = false;
     if (alive) {
       if (j == 0) {
         const float f = emit_path(A, path, r);
@@ -863,19 +899,18 @@ __device__ __forceinline__ void lrb3_p2_run(const PassArgs& A, int* lds) {
       if (ev.cont) {
         ++j;
       } else {
-        const bool put = klast > 0 && (d0 != 0.0 || d1 != 0.0 || d2 != 0.0);
-        if (put) {
-          add_le(A, gl0, gl1, gl2, d0 * iLe.x, d1 * iLe.y, d2 * iLe.z, etex);
-          Lrb3Hand h;
-          h.path = path; h.klast = klast; h.vmask = vmask; h.d[0] = d0; h.d[1] = d1; h.d[2] = d2;
-          A.hand[path] = h;
-        } else {
-          A.hand[path].klast = 0;
-        }
+        put = klast > 0 && (d0 != 0.0 || d1 != 0.0 || d2 != 0.0);
+        if (put) add_le(A, gl0, gl1, gl2, d0 * iLe.x, d1 * iLe.y, d2 * iLe.z, etex);
         // the path's adjoint-weighted contribution |delta_total|
         if (A.contrib) A.contrib[path] = put ? (float)(fabs(d0) + fabs(d1) + fabs(d2)) : 0.f;
         alive = false; j = 0;
       }
+    }
+    const uint32_t slot = hand_append(A, put, path);
+    if (put) {
+      Lrb3Hand h;
+      h.path = path; h.klast = klast; h.vmask = vmask; h.d[0] = d0; h.d[1] = d1; h.d[2] = d2;
+      A.hand[slot] = h;
     }
   }
   flush_le(A, gl0, gl1, gl2);
@@ -890,7 +925,7 @@ __device__ __forceinline__ void lrb3_p3_run(const PassArgs& A, int* lds) {
   const int ss = blockDim.x;
   AGrad ga = agrad_begin(A, lds + A.sc.stack_n * blockDim.x);
   bool alive = false, exhausted = false;
-  uint32_t path = 0;
+  uint32_t item = 0, path = 0;
   int j = 0, klast = 0;
   uint64_t vmask = 0ull;
   Ray r;
@@ -901,16 +936,15 @@ __device__ __forceinline__ void lrb3_p3_run(const PassArgs& A, int* lds) {
   int etex = -1;
   WorkQ wq = work_begin(A.counter3);
   while (true) {
-    // only the paths pass 2 handed over
-    refill(A, wq, alive, exhausted, path, [&](uint32_t) {}, [&](uint32_t p) { return A.hand[p].klast > 0; });
+    refill_hand(A, wq, alive, exhausted, item);
     if (__ballot(alive) == 0ull) break;
     bool has = false;
     int texel = 0;
     f3 gv = {0.f, 0.f, 0.f};
     if (alive) {
       if (j == 0) {
-        const Lrb3Hand h = A.hand[path];
-        klast = h.klast; vmask = h.vmask; d0 = h.d[0]; d1 = h.d[1]; d2 = h.d[2];
+        const Lrb3Hand h = A.hand[item];
+        path = h.path; klast = h.klast; vmask = h.vmask; d0 = h.d[0]; d1 = h.d[1]; d2 = h.d[2];
         const float f = emit_path(A, path, r);
         path_emitter(A, path, Le, iLe, etex);
         beta = Le * f;

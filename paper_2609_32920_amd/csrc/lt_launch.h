@@ -52,14 +52,16 @@ struct PassArgs {
   const float* tape_gw_in;
   float* gsamp;               // diffuse guide training samples [n_paths][12], or null
   float* contrib;             // per-path image contribution sum_i lum(C_i), or null
-  // LRB-3 as two kernels: pass 2 writes a hand-off entry per path, pass 3
-  // replays the paths whose entry holds a connection
+  // LRB-3 as two kernels: pass 2 appends a hand-off entry per path with a
+  // connection, pass 3 replays the appended paths
   SplatHdr* spl_hdr;          // buffered two-pass: per-path header [n_paths] (forward writes)
   SplatRec* spl;              // and splat records [D][n_paths]
   const SplatHdr* spl_hdr_in; // (backward reads)
   const SplatRec* spl_in;
-  Lrb3Hand* hand;             // detached entries [n_paths], indexed by path (klast 0: none)
-  Lrb3HandAtt* hand_att;      // attached entries [n_paths], indexed by path
+  Lrb3Hand* hand;             // detached entries [8][hand_region]
+  Lrb3HandAtt* hand_att;      // attached entries [8][hand_region]
+  uint32_t hand_region;       // entries per class region, ceil(n_paths / 8)
+  unsigned int* hand_app;     // pass 2's append counter of each class (a block of kCtrBlock u32)
   unsigned int* counter3;     // pass 3's work counters (a block of kCtrBlock u32)
   // camera side (k_camera, k_camera_prb): flags bit 0 = every sample, not only
   // those whose first vertex is specular; each sample weighs W*H / N
