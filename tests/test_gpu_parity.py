@@ -114,7 +114,8 @@ def test_reslrb_selected_image_and_records(box64):
 def test_deeper_paths_and_ragged_sizes(box64):
     from tests.gpu_common import matched_paths, maxrel
     sc, g = box64
-    for seed, n, D in ((21, 1000, 12), (22, 1, 3), (23, 4097, 1), (24, 777, 64)):
+    # fewer paths than work classes (eight) and sizes that leave classes uneven
+    for seed, n, D in ((21, 1000, 12), (22, 1, 3), (25, 5, 4), (26, 9, 4), (23, 4097, 1), (24, 777, 64)):
         mask, ids, mis = matched_paths(sc, g, seed, n, D)
         assert mis <= max(1e-3, 1.0 / n)
         if len(ids) == 0:
@@ -127,8 +128,13 @@ def test_deeper_paths_and_ragged_sizes(box64):
         assert maxrel(gi, oi) <= TOL, (n, D)
         dI = _dI((64, 64, 3), seed)
         on = O.gradient(sc, seed, n, D, dI, path_list=ids)
-        for mode in ("naive", "lrb3", "lrb2"):
-            gg = g.backward(mode, seed, n, D, dI, mask=mask)
+        for mode in ("naive", "lrb3", "lrb2", "lrb3_split"):
+            if mode == "lrb3_split":  # the two-kernel LRB-3 with its per-class hand-off
+                g.ctx.set_tuning(lrb3_split=1)
+            try:
+                gg = g.backward(mode.split("_")[0], seed, n, D, dI, mask=mask)
+            finally:
+                g.ctx.set_tuning()
             assert maxrel(gg["albedo"], on["albedo"]) <= TOL, (mode, n, D)
             assert maxrel(gg["Le"], on["Le"]) <= TOL, (mode, n, D)
 
