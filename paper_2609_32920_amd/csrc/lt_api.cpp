@@ -182,9 +182,7 @@ struct lt_ctx {
   int32_t* d_mat_type = nullptr;
   int32_t* d_mat_tex = nullptr;
   float* d_mat_ior = nullptr;
-  int32_t* d_slot_of_prim = nullptr;
-  int32_t* d_levels = nullptr;
-  std::vector<int> level_off;  // node-level ranges into d_levels, deepest last
+  float* d_hfb = nullptr;          // least and greatest height [2]
   DevScene dsc{};
   size_t scene_bytes = 0;
   unsigned int* d_counter = nullptr;
@@ -218,10 +216,10 @@ struct lt_ctx {
   }
   void free_scene() {
     hipFree(d_nodes); hipFree(d_tris); hipFree(d_prim_mat); hipFree(d_prim_uv);
-    hipFree(d_mat_type); hipFree(d_mat_tex); hipFree(d_mat_ior); hipFree(d_slot_of_prim); hipFree(d_levels);
+    hipFree(d_mat_type); hipFree(d_mat_tex); hipFree(d_mat_ior); hipFree(d_hfb);
     hipFree(d_tcx); hipFree(d_tcn); hipFree(d_gtab);
     d_nodes = nullptr; d_tris = nullptr; d_prim_mat = nullptr; d_prim_uv = nullptr; d_mat_type = nullptr;
-    d_mat_tex = nullptr; d_mat_ior = nullptr; d_slot_of_prim = nullptr; d_levels = nullptr;
+    d_mat_tex = nullptr; d_mat_ior = nullptr; d_hfb = nullptr;
     d_tcx = nullptr; d_tcn = nullptr; d_gtab = nullptr;
     has_scene = false; scene_bytes = 0;
   }
@@ -431,18 +429,11 @@ lt_status guide_prepass(lt_ctx* c, const lt_trace_args* a, const lt_params* p, P
   return LT_OK;
 }
 
+// The heightfield's triangles and height bounds from params->heights (the
+// BVH holds the static triangles only, so nothing else changes with them).
 lt_status prepare_geometry(lt_ctx* c, const lt_params* p) {
   if (c->dsc.hf_G < 2 || !p->heights) return LT_OK;
-  lt_status s = c->hip(launch_hf_tris(c->dsc, c->d_slot_of_prim, c->d_tris, p->heights, c->stream), "hf tris");
-  if (s != LT_OK) return s;
-  for (int lv = (int)c->level_off.size() - 2; lv >= 0; --lv) {
-    int b = c->level_off[lv], e = c->level_off[lv + 1];
-    if (e > b) {
-      s = c->hip(launch_refit_level(c->d_nodes, c->d_tris, c->d_levels + b, e - b, c->stream), "refit");
-      if (s != LT_OK) return s;
-    }
-  }
-  return LT_OK;
+  return c->hip(launch_hf_tris(c->dsc, c->d_tris, p->heights, c->d_hfb, c->stream), "hf tris");
 }
 
 PassArgs base_args(lt_ctx* c, const lt_trace_args* a, const lt_params* p) {
@@ -649,23 +640,25 @@ lt_status lt_scene_upload(lt_ctx* c, const lt_scene_desc* s) {
     setv(tri[n_static + q], v[0], v[1], v[2], n_static + q);
   }
 
+  // the BVH over the static triangles (the heightfield is walked as a grid)
   Builder B;
-  B.prims.resize(n_prims);
-  for (int i = 0; i < n_prims; ++i) {
+  B.prims.resize(n_static);
+  for (int i = 0; i < n_static; ++i) {
     BPrim& p = B.prims[i];
     const Tri& t = tri[i];
     for (int a = 0; a < 3; ++a) {
       float v0 = t.p0[a], v1 = t.p0[a] + t.e1[a], v2 = t.p0[a] + t.e2[a];
       p.lo[a] = std::min(v0, std::min(v1, v2));
       p.hi[a] = std::max(v0, std::max(v1, v2));
-      // a heightfield vertex can move in y: leave room for the refit
       p.c[a] = 0.5f * (p.lo[a] + p.hi[a]);
     }
     p.id = i;
   }
-  int root = B.build(0, n_prims, 0);
   Flat F;
-  if (B.bn[root].left < 0) {  // the whole scene is one leaf
+  const int root = n_static > 0 ? B.build(0, n_static, 0) : -1;
+  if (root < 0) {
+    // no static triangles: an empty BVH
+  } else if (B.bn[root].left < 0) {  // the whole scene is one leaf
     Node nd;
     std::memset(&nd, 0, sizeof(nd));
     pad_box(B.bn[root].lo, B.bn[root].hi, nd.lo0, nd.hi0);
@@ -679,9 +672,10 @@ lt_status lt_scene_upload(lt_ctx* c, const lt_scene_desc* s) {
   int maxd = 0;
   for (int d : F.depth) maxd = std::max(maxd, d);
   if (maxd + 2 > kStackMax) return c->fail(LT_ERR_UNSUPPORTED, "BVH deeper than the traversal stack%s");
+  // static triangles in BVH order, then the heightfield's in grid order
   std::vector<Tri> ordered(n_prims);
-  std::vector<int32_t> slot(n_prims);
-  for (int k = 0; k < n_prims; ++k) { ordered[k] = tri[B.prims[k].id]; slot[B.prims[k].id] = k; }
+  for (int k = 0; k < n_static; ++k) ordered[k] = tri[B.prims[k].id];
+  for (int q = 0; q < n_hf; ++q) ordered[n_static + q] = tri[n_static + q];
   std::vector<int32_t> pmat(n_prims);
   for (int t = 0; t < n_static; ++t) pmat[t] = s->tri_mat[t];
   for (int q = 0; q < n_hf; ++q) pmat[n_static + q] = s->hf_mat;
@@ -691,14 +685,6 @@ lt_status lt_scene_upload(lt_ctx* c, const lt_scene_desc* s) {
   std::vector<int32_t> mtype(s->mat_type, s->mat_type + s->n_mats), mtex(s->mat_tex, s->mat_tex + s->n_mats);
   std::vector<float> mior(s->n_mats);
   for (int m = 0; m < s->n_mats; ++m) mior[m] = (float)s->mat_ior[m];
-  // refit levels: node indices grouped by depth
-  std::vector<int32_t> levels;
-  std::vector<int> loff;
-  for (int d = 0; d <= maxd; ++d) {
-    loff.push_back((int)levels.size());
-    for (size_t k = 0; k < F.nodes.size(); ++k) if (F.depth[k] == d) levels.push_back((int32_t)k);
-  }
-  loff.push_back((int)levels.size());
 
   c->free_scene();
   hipError_t e = hipSuccess;
@@ -709,15 +695,14 @@ lt_status lt_scene_upload(lt_ctx* c, const lt_scene_desc* s) {
   if (e == hipSuccess) e = upload(&c->d_mat_type, mtype.data(), mtype.size());
   if (e == hipSuccess) e = upload(&c->d_mat_tex, mtex.data(), mtex.size());
   if (e == hipSuccess) e = upload(&c->d_mat_ior, mior.data(), mior.size());
-  if (e == hipSuccess) e = upload(&c->d_slot_of_prim, slot.data(), slot.size());
-  if (e == hipSuccess) e = upload(&c->d_levels, levels.data(), levels.size());
+  const float hb0[2] = {0.f, 0.f};  // a flat heightfield until heights arrive
+  if (e == hipSuccess) e = upload(&c->d_hfb, hb0, 2);
   if (e != hipSuccess) { c->free_scene(); return c->hip(e, "scene upload"); }
-  c->level_off = loff;
   c->has_conductor = false;
   for (int t = 0; t < s->n_tris; ++t) c->has_conductor |= s->mat_type[s->tri_mat[t]] == LT_MAT_CONDUCTOR;
   if (G >= 2) c->has_conductor |= s->mat_type[s->hf_mat] == LT_MAT_CONDUCTOR;
   c->scene_bytes = F.nodes.size() * sizeof(Node) + ordered.size() * sizeof(Tri) + pmat.size() * 4 +
-                   puv.size() * 4 + slot.size() * 4 + levels.size() * 4 +
+                   puv.size() * 4 + 8 +
                    (size_t)s->n_tex * s->tex_res * s->tex_res * 6 * sizeof(float) + 512;
 
   DevScene& d = c->dsc;
@@ -728,6 +713,7 @@ lt_status lt_scene_upload(lt_ctx* c, const lt_scene_desc* s) {
   d.hf_G = G >= 2 ? G : 0;
   d.hf_x0 = (float)s->hf_x0; d.hf_z0 = (float)s->hf_z0; d.hf_dx = (float)s->hf_dx; d.hf_base = (float)s->hf_base;
   d.hf_mat = s->hf_mat;
+  d.hf_hb = c->d_hfb;
   d.n_tex = s->n_tex; d.tex_res = s->tex_res;
   d.em_type = s->em_type;
   d.em_tex_res = s->em_tex_res;

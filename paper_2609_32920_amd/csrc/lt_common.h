@@ -147,6 +147,7 @@ struct DevScene {
   const float* mat_ior;
   int32_t n_nodes, n_tris, n_static;
   int32_t hf_G; float hf_x0, hf_z0, hf_dx, hf_base; int32_t hf_mat;
+  const float* hf_hb;       // [2] least and greatest height (device), refreshed with the heights
   int32_t n_tex, tex_res;
   int32_t em_type;          // 0 area quad, 1 point, 2 directional quad
   int32_t em_tex_res;       // > 0: L_e is an em_tex_res^2 RGB texture over the quad

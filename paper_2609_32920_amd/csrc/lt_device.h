@@ -244,14 +244,61 @@ __device__ __forceinline__ f3 safe_inv(f3 d) {
   return {1.0f / d.x, 1.0f / d.y, 1.0f / d.z};
 }
 
-// Closest hit with t in (tmin, tmax): smallest t, ties to the lower
-// primitive id.  `stk` is this lane's LDS stack slice (stride `ss`).
-__device__ __forceinline__ Hit closest_hit(const DevScene& sc, f3 o, f3 d, float tmin, float tmax,
-                                           int* stk, int ss) {
-  Hit h{-1, tmax};
-  int best_prim = 0x7fffffff;
-  if (sc.n_nodes == 0) return h;
-  LT_COUNT(0, 1);
+// ------------------------------------------------------------ heightfield
+// The heightfield's triangles are not in the BVH: a ray walks the grid
+// cells its (x, z) projection crosses inside the heightfield's bounding box
+// (footprint x [x0, x0 + (G-1) dx], z likewise, y between the least and the
+// greatest height), in order along the ray, and tests the two triangles of
+// each cell (slots n_static + 2 cell + half).  A hit inside a cell lies in
+// that cell's stretch of the ray, so the walk stops at the first cell that
+// starts beyond the best hit; cells that start exactly at it are still
+// tested, for the tie rule.  The grid's heights (G^2 floats) and triangles
+// stay cache-resident where a BVH over them (16 MB of nodes at G = 256)
+// did not, and a ray crosses a few cells where it visited ~15 BVH levels.
+// Returns false when the ray misses the box; else the clipped interval.
+__device__ __forceinline__ bool hf_span(const DevScene& sc, f3 o, f3 inv, float tmin, float tmax, float& t0,
+                                        float& t1) {
+  const float ext = (float)(sc.hf_G - 1) * sc.hf_dx;
+  const float xl = sc.hf_x0, xh = sc.hf_x0 + ext, zl = sc.hf_z0, zh = sc.hf_z0 + ext;
+  const float yl = sc.hf_base + sc.hf_hb[0], yh = sc.hf_base + sc.hf_hb[1];
+  const float px = 1e-5f + 1e-6f * fmaxf(fabsf(xl), fabsf(xh)), pz = 1e-5f + 1e-6f * fmaxf(fabsf(zl), fabsf(zh));
+  const float py = 1e-5f + 1e-6f * fmaxf(fabsf(yl), fabsf(yh));
+  float tn;
+  if (!slab(xl - px, yl - py, zl - pz, xh + px, yh + py, zh + pz, o, inv, tmin, tmax, tn)) return false;
+  float tx0 = (xl - px - o.x) * inv.x, tx1 = (xh + px - o.x) * inv.x;
+  float ty0 = (yl - py - o.y) * inv.y, ty1 = (yh + py - o.y) * inv.y;
+  float tz0 = (zl - pz - o.z) * inv.z, tz1 = (zh + pz - o.z) * inv.z;
+  t0 = tn;
+  t1 = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tmax));
+  return true;
+}
+
+// Walks the cells of the span; visit(slot0 of the cell) returns true to stop
+// (any-hit), and `limit` is re-read after every cell (closest hit).
+template <typename Visit>
+__device__ __forceinline__ void hf_walk(const DevScene& sc, f3 o, f3 d, f3 inv, float t0, float t1,
+                                        const float& limit, Visit visit) {
+  const int G = sc.hf_G, last = G - 2;
+  const float dx = sc.hf_dx, idx = 1.0f / dx;
+  const float xs = o.x + d.x * t0, zs = o.z + d.z * t0;
+  int ci = min(max((int)floorf((xs - sc.hf_x0) * idx), 0), last);
+  int cj = min(max((int)floorf((zs - sc.hf_z0) * idx), 0), last);
+  const int sx = d.x > 0.0f ? 1 : -1, sz = d.z > 0.0f ? 1 : -1;
+  for (int it = 0; it < 2 * G; ++it) {
+    if (visit(sc.n_static + 2 * (cj * (G - 1) + ci))) return;
+    // where the ray leaves this cell in x and in z (from the cell index, no drift)
+    const float tX = d.x != 0.0f ? (sc.hf_x0 + (float)(ci + (sx > 0)) * dx - o.x) * inv.x : 3.0e38f;
+    const float tZ = d.z != 0.0f ? (sc.hf_z0 + (float)(cj + (sz > 0)) * dx - o.z) * inv.z : 3.0e38f;
+    const float tn = fminf(tX, tZ);
+    if (!(tn <= fminf(limit, t1))) return;
+    if (tX < tZ) { ci += sx; if (ci < 0 || ci > last) return; }
+    else { cj += sz; if (cj < 0 || cj > last) return; }
+  }
+}
+
+// The static triangles' part: the BVH.
+__device__ __forceinline__ void bvh_closest(const DevScene& sc, f3 o, f3 d, float tmin, Hit& h, int& best_prim,
+                                            int* stk, int ss) {
   f3 inv = safe_inv(d);
   int sp = 0, node = 0;
   while (true) {
@@ -291,14 +338,34 @@ __device__ __forceinline__ Hit closest_hit(const DevScene& sc, f3 o, f3 d, float
       --sp; node = stk[sp * ss];
     }
   }
+}
+
+
+// Closest hit with t in (tmin, tmax): smallest t, ties to the lower
+// primitive id.  `stk` is this lane's LDS stack slice (stride `ss`).
+__device__ __forceinline__ Hit closest_hit(const DevScene& sc, f3 o, f3 d, float tmin, float tmax,
+                                           int* stk, int ss) {
+  LT_COUNT(0, 1);
+  Hit h{-1, tmax};
+  int best_prim = 0x7fffffff;
+  if (sc.n_nodes > 0) bvh_closest(sc, o, d, tmin, h, best_prim, stk, ss);
+  if (sc.hf_G >= 2) {
+    const f3 inv = safe_inv(d);
+    float t0, t1;
+    if (hf_span(sc, o, inv, tmin, h.t, t0, t1))
+      hf_walk(sc, o, d, inv, t0, t1, h.t, [&](int s0) {
+        for (int k = s0; k < s0 + 2; ++k) {
+          int prim; float t = tri_t(sc.tris, k, o, d, prim);
+          if (t > tmin && (t < h.t || (t == h.t && prim < best_prim))) { h.t = t; h.tri = k; best_prim = prim; }
+        }
+        return false;
+      });
+  }
   return h;
 }
 
-// Any hit with t in (tmin, tmax).
-__device__ __forceinline__ bool any_hit(const DevScene& sc, f3 o, f3 d, float tmin, float tmax,
-                                        int* stk, int ss) {
-  if (sc.n_nodes == 0) return false;
-  LT_COUNT(1, 1);
+// Any static triangle with t in (tmin, tmax): the BVH.
+__device__ __forceinline__ bool bvh_any(const DevScene& sc, f3 o, f3 d, float tmin, float tmax, int* stk, int ss) {
   f3 inv = safe_inv(d);
   int sp = 0, node = 0;
   while (true) {
@@ -338,6 +405,26 @@ __device__ __forceinline__ bool any_hit(const DevScene& sc, f3 o, f3 d, float tm
     }
   }
   return false;
+}
+
+// Any hit with t in (tmin, tmax).
+__device__ __forceinline__ bool any_hit(const DevScene& sc, f3 o, f3 d, float tmin, float tmax,
+                                        int* stk, int ss) {
+  LT_COUNT(1, 1);
+  if (sc.n_nodes > 0 && bvh_any(sc, o, d, tmin, tmax, stk, ss)) return true;
+  if (sc.hf_G < 2) return false;
+  const f3 inv = safe_inv(d);
+  float t0, t1;
+  if (!hf_span(sc, o, inv, tmin, tmax, t0, t1)) return false;
+  bool hit = false;
+  hf_walk(sc, o, d, inv, t0, t1, tmax, [&](int s0) {
+    for (int q = s0; q < s0 + 2; ++q) {
+      int prim; float t = tri_t(sc.tris, q, o, d, prim);
+      if (t > tmin && t < tmax) { hit = true; break; }
+    }
+    return hit;
+  });
+  return hit;
 }
 
 // ------------------------------------------------------------ path pieces

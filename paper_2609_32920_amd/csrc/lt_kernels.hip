@@ -1028,7 +1028,7 @@ __global__ void k_loss_finish(const double* acc, size_t n, float* loss) { loss[0
 // subtracting rounded corner positions: base + h rounds to about 6e-8 at
 // base 0.6, which on a 1/127 grid spacing would put ~1e-5 of error on every
 // facet slope, whereas h_k - h_0 and (i_k - i_0) dx are exact or nearly so.
-__global__ void k_hf_tris(DevScene sc, const int32_t* slot_of_prim, Tri* tris, const float* h) {
+__global__ void k_hf_tris(DevScene sc, Tri* tris, const float* h) {
   int nhf = 2 * (sc.hf_G - 1) * (sc.hf_G - 1);
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nhf) return;
@@ -1046,45 +1046,24 @@ __global__ void k_hf_tris(DevScene sc, const int32_t* slot_of_prim, Tri* tris, c
   t.e1[0] = (float)(gi[1] - gi[0]) * sc.hf_dx; t.e1[1] = hv[1] - hv[0]; t.e1[2] = (float)(gj[1] - gj[0]) * sc.hf_dx;
   t.e2[0] = (float)(gi[2] - gi[0]) * sc.hf_dx; t.e2[1] = hv[2] - hv[0]; t.e2[2] = (float)(gj[2] - gj[0]) * sc.hf_dx;
   t.pad1 = 0.f; t.pad2 = 0.f;
-  tris[slot_of_prim[sc.n_static + q]] = t;
+  tris[sc.n_static + q] = t;  // the heightfield's slots follow the static triangles
 }
 
-__device__ __forceinline__ void tri_box(const Tri& t, float* lo, float* hi) {
-  for (int a = 0; a < 3; ++a) {
-    float v0 = t.p0[a], v1 = t.p0[a] + t.e1[a], v2 = t.p0[a] + t.e2[a];
-    lo[a] = fminf(lo[a], fminf(v0, fminf(v1, v2)));
-    hi[a] = fmaxf(hi[a], fmaxf(v0, fmaxf(v1, v2)));
-  }
-}
-
-__device__ __forceinline__ void child_box(const Node* nodes, const Tri* tris, int child, int count, float* lo, float* hi) {
-  for (int a = 0; a < 3; ++a) { lo[a] = 3.0e38f; hi[a] = -3.0e38f; }
-  if (child < 0) return;
-  if (count > 0) {
-    for (int k = child; k < child + count; ++k) tri_box(tris[k], lo, hi);
-  } else {
-    const Node& n = nodes[child];
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = fminf(n.lo0[a], n.lo1[a]);
-      hi[a] = fmaxf(n.hi0[a], n.hi1[a]);
+// least and greatest height into hb[0], hb[1] (one workgroup of 1024)
+__global__ void __launch_bounds__(1024) k_hf_bounds(const float* h, int n, float* hb) {
+  __shared__ float lo[1024], hi[1024];
+  float a = 3.0e38f, b = -3.0e38f;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) { a = fminf(a, h[i]); b = fmaxf(b, h[i]); }
+  lo[threadIdx.x] = a; hi[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      lo[threadIdx.x] = fminf(lo[threadIdx.x], lo[threadIdx.x + w]);
+      hi[threadIdx.x] = fmaxf(hi[threadIdx.x], hi[threadIdx.x + w]);
     }
+    __syncthreads();
   }
-  for (int a = 0; a < 3; ++a) {
-    float pad = 1e-5f + 1e-6f * fmaxf(fabsf(lo[a]), fabsf(hi[a]));
-    lo[a] -= pad; hi[a] += pad;
-  }
-}
-
-// Bottom-up refit of one tree level (children are always deeper).
-__global__ void k_refit_level(Node* nodes, const Tri* tris, const int32_t* level_nodes, int n) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n) return;
-  Node& nd = nodes[level_nodes[q]];
-  float lo[3], hi[3];
-  child_box(nodes, tris, nd.child0, nd.count0, lo, hi);
-  for (int a = 0; a < 3; ++a) { nd.lo0[a] = lo[a]; nd.hi0[a] = hi[a]; }
-  child_box(nodes, tris, nd.child1, nd.count1, lo, hi);
-  for (int a = 0; a < 3; ++a) { nd.lo1[a] = lo[a]; nd.hi1[a] = hi[a]; }
+  if (threadIdx.x == 0) { hb[0] = lo[0]; hb[1] = hi[0]; }
 }
 
 #include "lt_attached.inc"
@@ -1386,13 +1365,10 @@ hipError_t launch_loss(const float* I, const float* T, size_t n, float* dI, doub
   hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(1), 0, s, acc, n, loss);
   return hipGetLastError();
 }
-hipError_t launch_hf_tris(const DevScene& sc, const int32_t* slot_of_prim, Tri* tris, const float* h, hipStream_t s) {
+hipError_t launch_hf_tris(const DevScene& sc, Tri* tris, const float* h, float* hb, hipStream_t s) {
   int nhf = 2 * (sc.hf_G - 1) * (sc.hf_G - 1);
-  hipLaunchKernelGGL(k_hf_tris, dim3((nhf + 255) / 256), dim3(256), 0, s, sc, slot_of_prim, tris, h);
-  return hipGetLastError();
-}
-hipError_t launch_refit_level(Node* nodes, const Tri* tris, const int32_t* level_nodes, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_refit_level, dim3((n + 127) / 128), dim3(128), 0, s, nodes, tris, level_nodes, n);
+  hipLaunchKernelGGL(k_hf_tris, dim3((nhf + 255) / 256), dim3(256), 0, s, sc, tris, h);
+  hipLaunchKernelGGL(k_hf_bounds, dim3(1), dim3(1024), 0, s, h, sc.hf_G * sc.hf_G, hb);
   return hipGetLastError();
 }
 

@@ -144,8 +144,9 @@ hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s);
 hipError_t launch_add_le(const double* acc, float* dst, hipStream_t s);
 hipError_t launch_loss(const float* I, const float* T, size_t n, float* dI, double* acc, float* loss,
                        hipStream_t s);
-hipError_t launch_hf_tris(const DevScene& sc, const int32_t* slot_of_prim, Tri* tris, const float* h,
-                          hipStream_t s);
+// heightfield triangles from the heights (slots n_static...) and the
+// heights' least and greatest value into hb[2]
+hipError_t launch_hf_tris(const DevScene& sc, Tri* tris, const float* h, float* hb, hipStream_t s);
 hipError_t set_lds_limit(int bytes);
 // Workgroups of a backward kernel resident per CU at `block` threads and
 // `lds` dynamic LDS bytes (0 if it cannot launch or the query fails).
@@ -153,6 +154,5 @@ enum class BwdKernel { naive, reslrb, lrb3, naive_att, reslrb_att, lrb3_att, lrb
                        lrb3_p2, lrb3_p3, lrb3_att_p2, lrb3_att_p3, lrb2, lrb3_att_p3_entry, camera_prb };
 int resident_groups(BwdKernel k, int block, size_t lds);
 hipError_t read_counters(uint64_t* out, bool reset, hipStream_t s);
-hipError_t launch_refit_level(Node* nodes, const Tri* tris, const int32_t* level_nodes, int n, hipStream_t s);
 
 }  // namespace lt
