@@ -343,13 +343,16 @@ __device__ __forceinline__ void bvh_closest(const DevScene& sc, f3 o, f3 d, floa
 
 // Closest hit with t in (tmin, tmax): smallest t, ties to the lower
 // primitive id.  `stk` is this lane's LDS stack slice (stride `ss`).
+// HF = false: a kernel instantiated for scenes without a heightfield (the
+// grid walk's registers then cost it nothing).
+template <bool HF = true>
 __device__ __forceinline__ Hit closest_hit(const DevScene& sc, f3 o, f3 d, float tmin, float tmax,
                                            int* stk, int ss) {
   LT_COUNT(0, 1);
   Hit h{-1, tmax};
   int best_prim = 0x7fffffff;
   if (sc.n_nodes > 0) bvh_closest(sc, o, d, tmin, h, best_prim, stk, ss);
-  if (sc.hf_G >= 2) {
+  if (HF && sc.hf_G >= 2) {
     const f3 inv = safe_inv(d);
     float t0, t1;
     if (hf_span(sc, o, inv, tmin, h.t, t0, t1))
@@ -408,11 +411,12 @@ __device__ __forceinline__ bool bvh_any(const DevScene& sc, f3 o, f3 d, float tm
 }
 
 // Any hit with t in (tmin, tmax).
+template <bool HF = true>
 __device__ __forceinline__ bool any_hit(const DevScene& sc, f3 o, f3 d, float tmin, float tmax,
                                         int* stk, int ss) {
   LT_COUNT(1, 1);
   if (sc.n_nodes > 0 && bvh_any(sc, o, d, tmin, tmax, stk, ss)) return true;
-  if (sc.hf_G < 2) return false;
+  if (!HF || sc.hf_G < 2) return false;
   const f3 inv = safe_inv(d);
   float t0, t1;
   if (!hf_span(sc, o, inv, tmin, tmax, t0, t1)) return false;
@@ -506,6 +510,7 @@ __device__ __forceinline__ int texel_of(const DevScene& sc, const Surf& s, int t
 // A conductor vertex passes its arrival-side shading normal na and
 // roughness a: the camera must lie on na's side too, and g carries the
 // microfacet factor instead of the Lambertian cos / pi.
+template <bool HF = true>
 __device__ __forceinline__ bool connect(const DevScene& sc, const Surf& s, f3 w_in, float Kfilm,
                                         float& ux, float& uy, float& g, int* stk, int ss,
                                         bool visible = false, const f3* na = nullptr, float a = 0.f) {
@@ -528,7 +533,7 @@ __device__ __forceinline__ bool connect(const DevScene& sc, const Surf& s, f3 w_
   f3 sd = cpos - so;
   float sl = sqrtf(dot(sd, sd));
   sd = sd * (1.0f / sl);
-  if (!visible && any_hit(sc, so, sd, kTmin, sl * (1.0f - 1e-4f), stk, ss)) return false;
+  if (!visible && any_hit<HF>(sc, so, sd, kTmin, sl * (1.0f - 1e-4f), stk, ss)) return false;
   float cosc = zc / dist;
   if (na) {
     g = Kfilm * ggx_conn(w_in * -1.0f, wc, *na, a) / (cosc * cosc * cosc * dist2);

@@ -54,6 +54,7 @@ __device__ __forceinline__ bool near_kink(float u) {
 
 // cmode: 0 no sensor connection, 1 full connection test (with shadow
 // ray), 2 connection geometry only (known visible from an earlier replay).
+template <bool HF = true>
 __device__ __forceinline__ Event bounce(const PassArgs& A, uint32_t path, int j, Ray& r, int cmode,
                                         int* stk, int ss) {
   const DevScene& sc = A.sc;
@@ -61,7 +62,7 @@ __device__ __forceinline__ Event bounce(const PassArgs& A, uint32_t path, int j,
   ev.prim = -1; ev.kind = 0; ev.cond = false; ev.texel = -1; ev.rho = {0.f, 0.f, 0.f}; ev.valid = false;
   ev.ux = ev.uy = ev.g = 0.f; ev.lobe = 0; ev.fail = 0; ev.cont = false; ev.u_res = 1.0f; ev.cos_in = 0.f;
   ev.slot = -1; ev.x = {0.f, 0.f, 0.f}; ev.illc = false; ev.gw = 1.0f; ev.gq = 0.f; ev.gcomp = 0;
-  Hit h = closest_hit(sc, ray_origin(r), r.w, kTmin, 3.0e38f, stk, ss);
+  Hit h = closest_hit<HF>(sc, ray_origin(r), r.w, kTmin, 3.0e38f, stk, ss);
   if (h.tri < 0) return ev;
   Surf s = surface(sc, h.tri, r);
   ev.prim = s.prim;
@@ -91,7 +92,7 @@ __device__ __forceinline__ Event bounce(const PassArgs& A, uint32_t path, int j,
       if (!(dot(r.w, nc) < 0.0f)) { ev.fail = 9; return ev; }
     }
     if (cmode)
-      ev.valid = connect(sc, s, r.w, A.Kfilm, ev.ux, ev.uy, ev.g, stk, ss, cmode == 2, ev.cond ? &nc : nullptr, rough);
+      ev.valid = connect<HF>(sc, s, r.w, A.Kfilm, ev.ux, ev.uy, ev.g, stk, ss, cmode == 2, ev.cond ? &nc : nullptr, rough);
     // the tent filter has kinks where u - 1/2 is an integer: within 1e-3 px
     // of one the splat-position derivative is one-sided (rounding picks the side)
     if (ev.valid && (near_kink(ev.ux) || near_kink(ev.uy))) ev.illc = true;
@@ -407,7 +408,7 @@ __device__ __forceinline__ float luminance(f3 c) { return 0.2126f * c.x + 0.7152
 // density, S = sum of lum(C_i) over the later connections, component).
 // Each loop iteration advances every live lane by one vertex; the splat is
 // issued cooperatively by the whole wave after the step.
-template <bool TAPE, bool RESV, bool SPL = false, bool GS = false>
+template <bool TAPE, bool RESV, bool SPL = false, bool GS = false, bool HF = true>
 __device__ __forceinline__ void trace_run(const PassArgs& A, int* lds) {
   int* stk = lds + threadIdx.x;
   const int ss = blockDim.x;
@@ -457,7 +458,7 @@ __device__ __forceinline__ void trace_run(const PassArgs& A, int* lds) {
           for (int q = 0; q < 12; ++q) gs[q] = 0.f;
         }
       }
-      Event ev = bounce(A, path, j, r, 1, stk, ss);
+      Event ev = bounce<HF>(A, path, j, r, 1, stk, ss);
       if (A.sig) sig = sig_event(sig, ev);
       if (ev.kind == 1 && ev.valid) {
         f3 C = mul(beta, ev.rho) * ev.g;
@@ -533,10 +534,10 @@ __device__ __forceinline__ void trace_run(const PassArgs& A, int* lds) {
 // At most 96 VGPRs (five waves per SIMD, with the default 10 x 128-thread
 // workgroups per CU): a few registers spill and the caustic forward runs 5%
 // faster than at four waves; the box forward is unchanged.
-template <bool TAPE, bool RESV, bool SPL = false, bool GS = false>
+template <bool TAPE, bool RESV, bool SPL = false, bool GS = false, bool HF = true>
 __global__ void __launch_bounds__(1024, 5) k_trace(PassArgs A) {
   extern __shared__ int lds[];
-  trace_run<TAPE, RESV, SPL, GS>(A, lds);
+  trace_run<TAPE, RESV, SPL, GS, HF>(A, lds);
 }
 
 // ---------------------------------------------------------------- naive AD
@@ -677,6 +678,7 @@ __global__ void __launch_bounds__(1024) k_reslrb_bwd(PassArgs A) {
 // the last valid connection: phase 3 then re-evaluates only the connection
 // geometry where the bit is set (no shadow rays) and stops at that depth,
 // where delta_rem is exactly zero and nothing further contributes.
+template <bool HF = true>
 __device__ __forceinline__ void lrb3_run(const PassArgs& A, int* lds) {
   int* stk = lds + threadIdx.x;
   const int ss = blockDim.x;
@@ -708,7 +710,7 @@ __device__ __forceinline__ void lrb3_run(const PassArgs& A, int* lds) {
         if (phase == 2) { d0 = d1 = d2 = 0.0; vmask = 0ull; klast = 0; }
       }
       const int cmode = phase == 2 ? 1 : (((vmask >> (j - 1)) & 1ull) ? 2 : 0);
-      Event ev = bounce(A, path, j, r, cmode, stk, ss);
+      Event ev = bounce<HF>(A, path, j, r, cmode, stk, ss);
       if (phase == 3 && j >= klast) ev.cont = false;  // nothing after the last connection
       if (ev.kind == 1) {
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
@@ -752,9 +754,11 @@ __device__ __forceinline__ void lrb3_run(const PassArgs& A, int* lds) {
   lds_grads_done(A);
 }
 
+// HF = false: the instantiation for scenes without a heightfield
+template <bool HF>
 __global__ void __launch_bounds__(1024) k_lrb3_bwd(PassArgs A) {
   extern __shared__ int lds[];
-  lrb3_run(A, lds);
+  lrb3_run<HF>(A, lds);
 }
 
 // ---------------------------------------------------------------- buffered two-pass
@@ -1097,7 +1101,7 @@ __global__ void __launch_bounds__(1024) k_trace_batch(const PassArgs* __restrict
 }
 __global__ void __launch_bounds__(1024) k_lrb3_batch(const PassArgs* __restrict__ T, int n) {
   extern __shared__ int lds[];
-  for (int i = 0; i < n; ++i) lrb3_run(table_entry(T, i), lds);
+  for (int i = 0; i < n; ++i) lrb3_run<true>(table_entry(T, i), lds);
 }
 __global__ void __launch_bounds__(256, 2) k_lrb3_att_batch(const PassArgs* __restrict__ T, int n) {
   extern __shared__ int lds[];
@@ -1143,7 +1147,8 @@ hipError_t set_lds_limit(int bytes) {
                         (const void*)k_reslrb_att<true>, (const void*)k_naive_att_bwd<false>,
                         (const void*)k_naive_att_bwd<true>})
     if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_lrb3_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  for (const void* f : {(const void*)k_lrb3_bwd<true>, (const void*)k_lrb3_bwd<false>})
+    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_reslrb_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_naive_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_lrb3_batch, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
@@ -1175,7 +1180,7 @@ int resident_groups(BwdKernel k, int block, size_t lds) {
   switch (k) {
     case BwdKernel::naive: f = (const void*)k_naive_bwd; break;
     case BwdKernel::reslrb: f = (const void*)k_reslrb_bwd; break;
-    case BwdKernel::lrb3: f = (const void*)k_lrb3_bwd; break;
+    case BwdKernel::lrb3: f = (const void*)k_lrb3_bwd<true>; break;
     case BwdKernel::naive_att: f = (const void*)k_naive_att_bwd<false>; break;
     case BwdKernel::reslrb_att: f = (const void*)k_reslrb_att<false>; break;
     case BwdKernel::lrb3_att: f = (const void*)k_lrb3_att<false>; break;
@@ -1275,7 +1280,8 @@ hipError_t launch_trace(const PassArgs& A, bool tape, bool resv, int grid, int b
   if (tape && resv) hipLaunchKernelGGL((k_trace<true, true>), dim3(grid), dim3(block), sh, s, A);
   else if (tape) hipLaunchKernelGGL((k_trace<true, false>), dim3(grid), dim3(block), sh, s, A);
   else if (resv) hipLaunchKernelGGL((k_trace<false, true>), dim3(grid), dim3(block), sh, s, A);
-  else hipLaunchKernelGGL((k_trace<false, false>), dim3(grid), dim3(block), sh, s, A);
+  else if (A.sc.hf_G >= 2) hipLaunchKernelGGL((k_trace<false, false>), dim3(grid), dim3(block), sh, s, A);
+  else hipLaunchKernelGGL((k_trace<false, false, false, false, false>), dim3(grid), dim3(block), sh, s, A);
   return hipGetLastError();
 }
 
@@ -1299,7 +1305,8 @@ hipError_t launch_reslrb_bwd(const PassArgs& A, int grid, int block, hipStream_t
 }
 
 hipError_t launch_lrb3_bwd(const PassArgs& A, int grid, int block, hipStream_t s) {
-  hipLaunchKernelGGL(k_lrb3_bwd, dim3(grid), dim3(block), stack_bytes(A, block) + agrad_bytes(A), s, A);
+  hipLaunchKernelGGL(A.sc.hf_G >= 2 ? k_lrb3_bwd<true> : k_lrb3_bwd<false>, dim3(grid), dim3(block),
+                     stack_bytes(A, block) + agrad_bytes(A), s, A);
   return hipGetLastError();
 }
 
