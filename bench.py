@@ -66,7 +66,7 @@ def parse():
     ap.add_argument("--ee-seeds", type=int, default=16, help="seeds per equal-error variance estimate")
     ap.add_argument("--no-inverse", action="store_true", help="skip the heightfield inverse-rendering loop")
     ap.add_argument("--no-bidir", action="store_true", help="skip the bidirectional glass-slab workload")
-    ap.add_argument("--inverse-iters", type=int, default=200, help="Adam iterations of the inverse-rendering loop")
+    ap.add_argument("--inverse-iters", type=int, default=1000, help="Adam iterations of the inverse-rendering loop")
     ap.add_argument("--cpu-paths", type=int, default=1 << 22, help="paths in the CPU-oracle sample")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="least CPU-oracle time (whole steps)")
     ap.add_argument("--copy-ref", action="store_true",
@@ -835,7 +835,7 @@ def bench_bidirectional(lt, scenes, dev, stream, bytes_per_path_fn, G=64, film=2
     return out
 
 
-def bench_inverse(lt, scenes, dev, stream, G=128, film=512, N=1 << 24, D=6, iters=200, lr=1e-4, log_every=20):
+def bench_inverse(lt, scenes, dev, stream, G=128, film=512, N=1 << 24, D=6, iters=1000, lr=1e-4, log_every=50):
     """Heightfield inverse rendering: Adam on the slab's free heights (the
     boundary ring stays at zero) toward the image of the seeded sinusoid
     target heights, one attached backward per iteration, per reverse mode.
