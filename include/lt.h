@@ -251,10 +251,12 @@ lt_status lt_get_stats(const lt_ctx* ctx, lt_stats* out);
 lt_status lt_read_counters(lt_ctx* ctx, uint64_t* out16, int reset);
 
 /* Upload a scene (Sec. 3.1 setting): copies the host arrays, builds a
- * binned-SAH BVH over static and heightfield triangles on the host and
- * uploads it.  Synchronizes the context's stream.  Replaces any previous
- * scene.  Errors: LT_ERR_ARG (inconsistent sizes/indices), LT_ERR_OOM,
- * LT_ERR_HIP. */
+ * binned-SAH BVH over the static triangles on the host and uploads it; rays
+ * find the heightfield by walking its grid cells (each cell's two
+ * triangles tested as a BVH leaf's, the same tie rule), so a call that
+ * brings new heights rewrites only the heightfield's triangles and height
+ * range.  Synchronizes the context's stream.  Replaces any previous scene.
+ * Errors: LT_ERR_ARG (inconsistent sizes/indices), LT_ERR_OOM, LT_ERR_HIP. */
 lt_status lt_scene_upload(lt_ctx* ctx, const lt_scene_desc* scene);
 
 /* Bytes of caller-provided side state lt_trace writes for these args:
