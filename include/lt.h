@@ -67,7 +67,9 @@ enum { LT_EMIT_QUAD = 0, LT_EMIT_POINT = 1, LT_EMIT_DIRECTIONAL = 2 };
 
 /* lt_trace_args.flags */
 enum {
-  LT_ATTACHED = 1u,         /* differentiate geometry (heightfield heights), Sec. 3.3 */
+  LT_ATTACHED = 1u,         /* differentiate geometry (heightfield heights), Sec. 3.3: a
+                               dielectric or rough-conductor heightfield (a Lambertian
+                               heightfield is rejected, LT_ERR_UNSUPPORTED) */
   LT_SPLAT_SELECTED = 2u,   /* primal image splats only (Omega_k/w_R) L_R (Eq. 9) */
   LT_RECORD_TAPE = 4u,      /* lt_trace writes the naive-AD tape */
   LT_RECORD_RESERVOIR = 8u, /* lt_trace writes the per-path ResLRB record */

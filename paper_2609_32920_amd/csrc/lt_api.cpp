@@ -200,6 +200,7 @@ struct lt_ctx {
   size_t hand_n = 0;
   char* d_scratch = nullptr; // this device's copy of the static scratch (null: unavailable)
   bool has_conductor = false; // the uploaded scene has rough-conductor surfaces
+  bool hf_lambert = false;    // the heightfield is Lambertian
 
   lt_status fail(lt_status s, const char* fmt, const char* a = "") {
     char buf[512];
@@ -329,6 +330,10 @@ lt_status check_args(lt_ctx* c, const lt_trace_args* a, const lt_params* p) {
     return c->fail(LT_ERR_UNSUPPORTED, "LT_RECORD_SPLATS is detached and not combined with LT_RECORD_TAPE%s");
   if (!p->albedo || !p->emitter_L) return c->fail(LT_ERR_ARG, "albedo and emitter_L are required%s");
   if ((a->flags & LT_ATTACHED) && c->dsc.hf_G < 2) return c->fail(LT_ERR_ARG, "LT_ATTACHED needs a heightfield%s");
+  if ((a->flags & LT_ATTACHED) && c->hf_lambert)
+    return c->fail(LT_ERR_UNSUPPORTED,
+                   "LT_ATTACHED differentiates dielectric and rough-conductor heightfields; a Lambertian one is "
+                   "detached only%s");
   if ((a->flags & LT_ATTACHED) && !p->heights) return c->fail(LT_ERR_ARG, "LT_ATTACHED needs params->heights%s");
   if (p->normal_map && (c->dsc.hf_G < 2 || !p->heights))
     return c->fail(LT_ERR_ARG, "a normal map needs a heightfield and params->heights%s");
@@ -701,6 +706,7 @@ lt_status lt_scene_upload(lt_ctx* c, const lt_scene_desc* s) {
   c->has_conductor = false;
   for (int t = 0; t < s->n_tris; ++t) c->has_conductor |= s->mat_type[s->tri_mat[t]] == LT_MAT_CONDUCTOR;
   if (G >= 2) c->has_conductor |= s->mat_type[s->hf_mat] == LT_MAT_CONDUCTOR;
+  c->hf_lambert = G >= 2 && s->mat_type[s->hf_mat] == LT_MAT_LAMBERT;
   c->scene_bytes = F.nodes.size() * sizeof(Node) + ordered.size() * sizeof(Tri) + pmat.size() * 4 +
                    puv.size() * 4 + 8 +
                    (size_t)s->n_tex * s->tex_res * s->tex_res * 6 * sizeof(float) + 512;
