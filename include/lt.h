@@ -202,8 +202,11 @@ typedef struct {
   int32_t blocks_per_cu;   /* persistent workgroups per compute unit, 1..64 */
   int32_t lds_grad;        /* 1 (default): each workgroup pre-reduces albedo gradients in LDS
                               when the texture set takes at most 48 KB and the copy costs
-                              the kernel no resident workgroups; 0: never (waves then
-                              write-combine them into the gradient array) */
+                              the kernel no resident workgroups; the detached replay
+                              backwards then run the same threads per CU in workgroups of
+                              block, 2 block, 4 block ... threads (at most 1024, dividing
+                              blocks_per_cu), the first at which the copy fits; 0: never
+                              (waves then write-combine them into the gradient array) */
   int32_t lrb3_split;      /* how lt_backward_lrb3 runs its two replays.  Split: pass 2 and
                               pass 3 as two kernels, each connected path's state (delta_total,
                               validity bits, last connection depth; attached also A) handed

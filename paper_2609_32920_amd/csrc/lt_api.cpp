@@ -282,6 +282,26 @@ int agrad_in_lds(const lt_ctx* c, BwdKernel k, int block, size_t used) {
   return with > 0 && with >= resident_groups(k, block, used) ? 1 : 0;
 }
 size_t stack_lds(const lt_ctx* c, int block) { return (size_t)c->dsc.stack_n * block * sizeof(int); }
+
+// Launch shape of a detached replay backward.  An LDS copy of the albedo
+// gradients is held per workgroup, so at the tuned shape (128 threads, ten
+// workgroups per CU) it would cost resident workgroups and is left out; the
+// same threads per CU in fewer, larger workgroups hold fewer copies.  The
+// first of block, 2 block, 4 block ... (at most 1024 threads, while the
+// workgroups per CU divide evenly) at which the copy fits without a loss of
+// residency is taken (256x256 box, fused LRB-3 backward: 6.83 -> 6.31 ms),
+// the tuned shape when there is none.
+struct Shape { int block, grid, agrad_lds; };
+Shape replay_shape(const lt_ctx* c, BwdKernel k, int64_t n) {
+  const int b0 = c->tune.block, k0 = c->tune.blocks_per_cu;
+  for (int f = 1; b0 * f <= 1024 && k0 % f == 0; f *= 2) {
+    const int blk = b0 * f;
+    if (!agrad_in_lds(c, k, blk, stack_lds(c, blk))) continue;
+    const int64_t g = (int64_t)c->n_cu * (k0 / f), need = (n + blk - 1) / blk;
+    return {blk, (int)std::max<int64_t>(1, std::min(g, need)), 1};
+  }
+  return {b0, persistent_grid(c, n, b0), 0};
+}
 size_t hgrad_lds_bytes(const lt_ctx* c, int on) { return on ? (size_t)c->dsc.hf_G * c->dsc.hf_G * sizeof(float) : 0; }
 
 struct SideLayout { size_t tape = 0, len = 0, emit = 0, gw = 0, res = 0, spl_hdr = 0, spl = 0, total = 0; };
@@ -352,10 +372,12 @@ size_t guide_bytes(const lt_trace_args* a, const lt_params* p) {
 
 // LRB-3 hand-off between the pass-2 and pass-3 kernels: one entry per path
 // at most (flat in depth).
-// Whether lt_backward_lrb3 runs its passes as two kernels for these args:
-// measured on the 256x256 box at depth 32 the fused kernel is faster (8.4
-// against 13.5 ms), on the 128x128 caustic (attached) the split pair (40.3
-// against 49.8 ms), hence the default 2.
+// Whether lt_backward_lrb3 runs its passes as two kernels for these args
+// (default 2: attached only).  On the 128x128 caustic (attached) the split
+// pair runs 15.9 against 23.1 ms fused; detached it gains 3% on the 256x256
+// box at depth 32 (6.37 against 6.55 ms) and 11% on the glass slab (1.67
+// against 1.88 ms) at 40 bytes of hand-off per path, against none for the
+// fused kernel, so the detached backward stays fused unless asked.
 bool lrb3_split(const lt_ctx* c, const lt_trace_args* a) {
   return c->tune.lrb3_split == 1 || (c->tune.lrb3_split == 2 && (a->flags & LT_ATTACHED));
 }
@@ -984,9 +1006,9 @@ lt_status lt_backward_reslrb(lt_ctx* c, const lt_trace_args* a, const lt_params*
     return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
   }
   A.res_in = (const ResRec*)((const char*)records + L.res);
-  int grid = persistent_grid(c, a->n_paths, c->tune.block);
-  A.agrad_lds = agrad_in_lds(c, BwdKernel::reslrb, c->tune.block, stack_lds(c, c->tune.block));
-  if ((st = c->hip(launch_reslrb_bwd(A, grid, c->tune.block, c->stream), "reslrb backward")) != LT_OK) return st;
+  const Shape sh = replay_shape(c, BwdKernel::reslrb, a->n_paths);
+  A.agrad_lds = sh.agrad_lds;
+  if ((st = c->hip(launch_reslrb_bwd(A, sh.grid, sh.block, c->stream), "reslrb backward")) != LT_OK) return st;
   return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
 }
 
@@ -1003,9 +1025,9 @@ lt_status lt_backward_lrb2(lt_ctx* c, const lt_trace_args* a, const lt_params* p
   A.contrib = a->path_contrib;
   A.spl_hdr_in = (const SplatHdr*)((const char*)records + L.spl_hdr);
   A.spl_in = (const SplatRec*)((const char*)records + L.spl);
-  const int blk = c->tune.block, grid = persistent_grid(c, a->n_paths, blk);
-  A.agrad_lds = agrad_in_lds(c, BwdKernel::lrb2, blk, stack_lds(c, blk));
-  if ((st = c->hip(launch_lrb2_bwd(A, grid, blk, c->stream), "two-pass backward")) != LT_OK) return st;
+  const Shape sh = replay_shape(c, BwdKernel::lrb2, a->n_paths);
+  A.agrad_lds = sh.agrad_lds;
+  if ((st = c->hip(launch_lrb2_bwd(A, sh.grid, sh.block, c->stream), "two-pass backward")) != LT_OK) return st;
   return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
 }
 
@@ -1043,10 +1065,13 @@ static lt_status lrb3_enqueue(lt_ctx* c, const lt_trace_args* a, const lt_params
                        "lrb3 attached pass 3")) != LT_OK)
         return st;
     } else {
-      const int blk = c->tune.block, grid = persistent_grid(c, a->n_paths, blk);
-      if ((st = c->hip(launch_lrb3_p2(A, grid, blk, c->stream), "lrb3 pass 2")) != LT_OK) return st;
-      A.agrad_lds = agrad_in_lds(c, BwdKernel::lrb3_p3, blk, stack_lds(c, blk));
-      if ((st = c->hip(launch_lrb3_p3(A, grid, blk, c->stream), "lrb3 pass 3")) != LT_OK) return st;
+      const int blk = c->tune.block;
+      if ((st = c->hip(launch_lrb3_p2(A, persistent_grid(c, a->n_paths, blk), blk, c->stream), "lrb3 pass 2")) !=
+          LT_OK)
+        return st;
+      const Shape sh = replay_shape(c, BwdKernel::lrb3_p3, a->n_paths);
+      A.agrad_lds = sh.agrad_lds;
+      if ((st = c->hip(launch_lrb3_p3(A, sh.grid, sh.block, c->stream), "lrb3 pass 3")) != LT_OK) return st;
     }
   } else if (att) {
     const int blk = att_replay_block(c, g->heights, c->dsc.stack_n, BwdKernel::lrb3_att, 768);
@@ -1055,9 +1080,9 @@ static lt_status lrb3_enqueue(lt_ctx* c, const lt_trace_args* a, const lt_params
     A.agrad_lds = agrad_in_lds(c, BwdKernel::lrb3_att, blk, stack_lds(c, blk) + hgrad_lds_bytes(c, A.hgrad_lds));
     if ((st = c->hip(launch_lrb3_att(A, grid, blk, c->stream), "lrb3 attached backward")) != LT_OK) return st;
   } else {
-    int grid = persistent_grid(c, a->n_paths, c->tune.block);
-    A.agrad_lds = agrad_in_lds(c, BwdKernel::lrb3, c->tune.block, stack_lds(c, c->tune.block));
-    if ((st = c->hip(launch_lrb3_bwd(A, grid, c->tune.block, c->stream), "lrb3 backward")) != LT_OK) return st;
+    const Shape sh = replay_shape(c, BwdKernel::lrb3, a->n_paths);
+    A.agrad_lds = sh.agrad_lds;
+    if ((st = c->hip(launch_lrb3_bwd(A, sh.grid, sh.block, c->stream), "lrb3 backward")) != LT_OK) return st;
   }
   return c->hip(launch_add_le(w.acc, g->emitter_L, c->stream), "emitter gradient");
 }
@@ -1143,11 +1168,9 @@ lt_status lt_camera_backward_prb(lt_ctx* c, const lt_trace_args* a, const lt_par
   PassArgs A;
   if ((st = backward_common(c, &b, &q, d_image, g, A, 0)) != LT_OK) return st;
   camera_fields(c, a, A);
-  const int blk = c->tune.block;
-  A.agrad_lds = agrad_in_lds(c, BwdKernel::camera_prb, blk, stack_lds(c, blk));
-  if ((st = c->hip(launch_camera_prb(A, persistent_grid(c, a->n_paths, blk), blk, c->stream), "camera backward")) !=
-      LT_OK)
-    return st;
+  const Shape sh = replay_shape(c, BwdKernel::camera_prb, a->n_paths);
+  A.agrad_lds = sh.agrad_lds;
+  if ((st = c->hip(launch_camera_prb(A, sh.grid, sh.block, c->stream), "camera backward")) != LT_OK) return st;
   return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
 }
 
