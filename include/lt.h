@@ -527,8 +527,10 @@ lt_status lt_guide_train_step(lt_ctx* ctx, const lt_trace_args* args, float* gui
  * lt_backward_lrb3 (Sec. 4.3) - as one persistent launch per pass over an
  * instance table: every wave takes work tickets (path indices) from one
  * instance at a time and moves to the next when it has drained it.
- * Attached instances of 2^20 paths or more take a backward launch each (a
- * kernel with more waves resident than the multi-instance one).  With
+ * Instances of 2^20 paths or more take a backward launch each, and those
+ * of 2^22 or more a forward launch each, through kernels with the
+ * single-instance calls' register budgets and launch shapes (the
+ * multi-instance kernels hold fewer waves or spill more).  With
  * use_graph the step is captured once into a hipGraph and replayed; between
  * replays only the seeds may change (they are read from device memory).
  * Results equal the per-instance calls up to the order of floating-point
@@ -566,7 +568,10 @@ const char* lt_batch_last_error(const lt_batch* b);
 lt_status lt_batch_step(lt_batch* b, const lt_instance* inst, int32_t n, int32_t use_graph);
 /* Launch shape of the batched passes: block and blocks_per_cu as in
  * lt_set_tuning (the attached backward chooses its own workgroup size;
- * lrb3_split is ignored: batches run both LRB-3 passes in one kernel).
+ * lrb3_split is ignored: batches run both LRB-3 passes in one kernel, and
+ * the attached instances that run on their own the two-kernel pair).  The
+ * instances that run on their own take their contexts' tuning, as the
+ * single-instance calls do.
  * Default {256, 4, 1, 0}.  The backward passes keep per-workgroup LDS copies of
  * the gradient arrays (heights always, albedo with lds_grad = 1) for the
  * instances whose arrays fit one budget per pass: the largest requested size

@@ -291,17 +291,20 @@ size_t stack_lds(const lt_ctx* c, int block) { return (size_t)c->dsc.stack_n * b
 // workgroups per CU divide evenly) at which the copy fits without a loss of
 // residency is taken (256x256 box, fused LRB-3 backward: 6.83 -> 6.31 ms),
 // the tuned shape when there is none.
+// stack_n: traversal stack entries per lane (a batch's common depth, else
+// the scene's)
 struct Shape { int block, grid, agrad_lds; };
-Shape replay_shape(const lt_ctx* c, BwdKernel k, int64_t n) {
+Shape replay_shape(const lt_ctx* c, BwdKernel k, int64_t n, int stack_n) {
   const int b0 = c->tune.block, k0 = c->tune.blocks_per_cu;
   for (int f = 1; b0 * f <= 1024 && k0 % f == 0; f *= 2) {
     const int blk = b0 * f;
-    if (!agrad_in_lds(c, k, blk, stack_lds(c, blk))) continue;
+    if (!agrad_in_lds(c, k, blk, (size_t)stack_n * blk * sizeof(int))) continue;
     const int64_t g = (int64_t)c->n_cu * (k0 / f), need = (n + blk - 1) / blk;
     return {blk, (int)std::max<int64_t>(1, std::min(g, need)), 1};
   }
   return {b0, persistent_grid(c, n, b0), 0};
 }
+Shape replay_shape(const lt_ctx* c, BwdKernel k, int64_t n) { return replay_shape(c, k, n, c->dsc.stack_n); }
 size_t hgrad_lds_bytes(const lt_ctx* c, int on) { return on ? (size_t)c->dsc.hf_G * c->dsc.hf_G * sizeof(float) : 0; }
 
 struct SideLayout { size_t tape = 0, len = 0, emit = 0, gw = 0, res = 0, spl_hdr = 0, spl = 0, total = 0; };
@@ -1323,19 +1326,33 @@ struct lt_batch {
 
 namespace {
 
-// Attached instances of at least this many paths run their backward as
-// launches of their own (the two-kernel LRB-3 of the single-instance call,
-// three waves per SIMD against the multi-entry kernel's two); at that size a
-// launch's tail and gap are small against its work.
+// Instances of at least this many paths run their backward as launches of
+// their own: attached ones the two-kernel LRB-3 of the single-instance call
+// (three waves per SIMD against the multi-entry kernel's two), detached ones
+// the single-instance kernel's body (the multi-entry kernel spills more;
+// 48-instance step, 20 detached of 1M-32M paths: 183.5 -> 149.6 ms).  At that
+// size a launch's tail and gap are small against its work.
 constexpr int64_t kSoloPaths = (int64_t)1 << 20;
+// Instances of at least this many paths run their forward as a launch of its
+// own, the single-instance kernel at five waves per SIMD; smaller ones gain
+// more from sharing one launch's tail.
+constexpr int64_t kSoloTracePaths = (int64_t)1 << 22;
 
 struct BatchPlan {
-  std::vector<PassArgs> tab;   // [n trace][n_det detached][n_att attached][n_solo attached, own launch each]
-  std::vector<int> det, att, solo;  // instance indices of each backward kind
+  // [n trace: n_bt batched, then the solo ones][n_det detached][n_att attached][n_solo attached]
+  // [n_solo_det detached], the solo ones a launch each
+  std::vector<PassArgs> tab;
+  std::vector<int> trace_pos;       // table position of each instance's forward entry
+  std::vector<int> solo_trace;      // instances whose forward runs on its own: block, grid, heightfield each
+  std::vector<int> solo_trace_shape;
+  int n_bt = 0;
+  std::vector<int> det, att, solo, solo_det;  // instance indices of each backward kind
   int n = 0, stack_n = 1;      // traversal stack entries per lane, the same for every entry
+  bool det_hf = false;         // some batched detached entry has a heightfield
   size_t det_lds = 0, att_lds = 0;  // LDS bytes past the stacks for gradient copies, per launch
   std::vector<size_t> solo_lds;     // the same for each solo launch
   std::vector<int> solo_block;      // workgroup size of each solo launch
+  std::vector<int> solo_det_shape;  // per solo detached launch: block, grid, LDS bytes past the stacks, heightfield
 };
 
 // Largest of the sizes the instances ask for that fits next to the traversal
@@ -1449,7 +1466,8 @@ BatchPlan batch_plan(lt_batch* b, const lt_instance* inst, int n, int64_t path_d
     B.g_le_tex = c->dsc.em_tex_res > 0 ? I.grads.emitter_L : nullptr;
     B.counter = b->d_cnt + (size_t)(n + i) * kCtrBlock;
     // by the caller's path count, so the autotuner's shortened steps keep the plan's shape
-    ((a.flags & LT_ATTACHED) ? (I.args.n_paths >= kSoloPaths ? P.solo : P.att) : P.det).push_back(i);
+    const bool big = I.args.n_paths >= kSoloPaths;
+    ((a.flags & LT_ATTACHED) ? (big ? P.solo : P.att) : (big ? P.solo_det : P.det)).push_back(i);
     P.tab[n + i] = B;  // reordered below
   }
   // Gradient copies in LDS.  Every entry lays its LDS out past stacks of the
@@ -1482,6 +1500,19 @@ BatchPlan batch_plan(lt_batch* b, const lt_instance* inst, int n, int64_t path_d
   for (int i : P.det) {
     size_t t = tex_bytes(inst[i].ctx);
     P.tab[n + i].agrad_lds = t && t <= P.det_lds;
+    P.det_hf = P.det_hf || inst[i].ctx->dsc.hf_G >= 2;
+  }
+  // a solo detached instance takes the single-instance call's launch shape
+  // (its LDS copy only where the batch's tuning allows copies)
+  for (int i : P.solo_det) {
+    PassArgs& B = P.tab[n + i];
+    const lt_ctx* c = inst[i].ctx;
+    const Shape sh = b->tune.lds_grad ? replay_shape(c, BwdKernel::lrb3_entry, B.n_paths, P.stack_n)
+                                      : Shape{c->tune.block, persistent_grid(c, B.n_paths, c->tune.block), 0};
+    B.agrad_lds = sh.agrad_lds;
+    P.solo_det_shape.insert(P.solo_det_shape.end(),
+                            {sh.block, sh.grid, sh.agrad_lds ? (int)(B.n_texels * 3 * sizeof(float)) : 0,
+                             c->dsc.hf_G >= 2 ? 1 : 0});
   }
   for (int i : P.att) {
     PassArgs& B = P.tab[n + i];
@@ -1513,11 +1544,28 @@ BatchPlan batch_plan(lt_batch* b, const lt_instance* inst, int n, int64_t path_d
     P.solo_lds.push_back(hb + (B.agrad_lds ? t : 0));
     P.solo_block.push_back(blk);
   }
+  // forward entries: the batched ones first, then the solo ones
+  std::vector<PassArgs> fw;
+  P.trace_pos.assign(n, 0);
+  for (int i = 0; i < n; ++i)
+    if (inst[i].args.n_paths < kSoloTracePaths) { P.trace_pos[i] = (int)fw.size(); fw.push_back(P.tab[i]); }
+  P.n_bt = (int)fw.size();
+  for (int i = 0; i < n; ++i)
+    if (inst[i].args.n_paths >= kSoloTracePaths) {
+      const lt_ctx* c = inst[i].ctx;
+      P.trace_pos[i] = (int)fw.size();
+      fw.push_back(P.tab[i]);
+      P.solo_trace.push_back(i);
+      P.solo_trace_shape.insert(P.solo_trace_shape.end(), {c->tune.block, persistent_grid(c, P.tab[i].n_paths,
+                                                           c->tune.block), c->dsc.hf_G >= 2 ? 1 : 0});
+    }
+  for (int k = 0; k < n; ++k) P.tab[k] = fw[k];
   // backward entries: detached ones first, then attached ones, then solo ones
   std::vector<PassArgs> bw;
   for (int i : P.det) bw.push_back(P.tab[n + i]);
   for (int i : P.att) bw.push_back(P.tab[n + i]);
   for (int i : P.solo) bw.push_back(P.tab[n + i]);
+  for (int i : P.solo_det) bw.push_back(P.tab[n + i]);
   for (int k = 0; k < n; ++k) P.tab[n + k] = bw[k];
   return P;
 }
@@ -1535,10 +1583,11 @@ lt_status batch_enqueue_on(lt_batch* b, const lt_instance* inst, const BatchPlan
     if (st != LT_OK) return b->fail(st, c->err.c_str());
     if (I.params.guide_w) {
       if ((st = guide_pack(c, I.params.guide_w)) != LT_OK) return b->fail(st, c->err.c_str());
-      GuideArgs G = guide_args(c, I.params.guide_w, P.tab[i].n_paths);
-      G.seed_ptr = &b->d_tab[i].seed;  // the seed as updated before every replay
+      const int64_t np = P.tab[P.trace_pos[i]].n_paths;
+      GuideArgs G = guide_args(c, I.params.guide_w, np);
+      G.seed_ptr = &b->d_tab[P.trace_pos[i]].seed;  // the seed as updated before every replay
       G.rec = c->d_grec;
-      if ((st = c->hip(launch_guide_emit(G, guide_grid(c, P.tab[i].n_paths), s), "guide emit")) != LT_OK)
+      if ((st = c->hip(launch_guide_emit(G, guide_grid(c, np), s), "guide emit")) != LT_OK)
         return b->fail(st, c->err.c_str());
     }
     size_t npix = (size_t)c->dsc.W * c->dsc.H * 3;
@@ -1548,8 +1597,15 @@ lt_status batch_enqueue_on(lt_batch* b, const lt_instance* inst, const BatchPlan
   if ((st = b->hip(launch_fill_u32(b->d_cnt, (size_t)2 * n * kCtrBlock, 0u, s), "counter clear")) != LT_OK) return st;
   if ((st = b->hip(launch_fill_f64(b->d_acc, (size_t)4 * n, 0.0, s), "accumulator clear")) != LT_OK) return st;
   int grid = (int)std::max<int64_t>(1, (int64_t)b->n_cu * b->tune.blocks_per_cu);
-  if ((st = b->hip(launch_trace_batch(b->d_tab, n, P.stack_n, grid, b->tune.block, s), "batched trace")) != LT_OK)
+  if (P.n_bt && (st = b->hip(launch_trace_batch(b->d_tab, P.n_bt, P.stack_n, grid, b->tune.block, s),
+                             "batched trace")) != LT_OK)
     return st;
+  for (size_t k = 0; k < P.solo_trace.size(); ++k) {
+    const int* sh = P.solo_trace_shape.data() + 3 * k;
+    if ((st = b->hip(launch_trace_entry(b->d_tab + P.trace_pos[P.solo_trace[k]], sh[2] != 0, P.stack_n, sh[1],
+                                        sh[0], s), "trace")) != LT_OK)
+      return st;
+  }
   for (int i = 0; i < n; ++i) {
     const lt_instance& I = inst[i];
     size_t npix = (size_t)I.ctx->dsc.W * I.ctx->dsc.H * 3;
@@ -1557,7 +1613,7 @@ lt_status batch_enqueue_on(lt_batch* b, const lt_instance* inst, const BatchPlan
       return st;
   }
   const int nd = (int)P.det.size(), na = (int)P.att.size();
-  if (nd && (st = b->hip(launch_lrb3_batch(b->d_tab + n, nd, P.stack_n, P.det_lds, grid, b->tune.block, s),
+  if (nd && (st = b->hip(launch_lrb3_batch(b->d_tab + n, nd, P.det_hf, P.stack_n, P.det_lds, grid, b->tune.block, s),
                          "batched backward")) != LT_OK)
     return st;
   if (na) {
@@ -1577,6 +1633,13 @@ lt_status batch_enqueue_on(lt_batch* b, const lt_instance* inst, const BatchPlan
     if ((st = b->hip(launch_lrb3_att_split_entry(b->d_tab + e, P.stack_n, P.solo_lds[k], grid2, grid3,
                                                  P.solo_block[k], s),
                      "attached backward")) != LT_OK)
+      return st;
+  }
+  for (size_t k = 0; k < P.solo_det.size(); ++k) {
+    const int e = n + nd + na + (int)P.solo.size() + (int)k;
+    const int* sh = P.solo_det_shape.data() + 4 * k;
+    if ((st = b->hip(launch_lrb3_entry(b->d_tab + e, sh[3] != 0, P.stack_n, (size_t)sh[2], sh[1], sh[0], s),
+                     "detached backward")) != LT_OK)
       return st;
   }
   for (int i = 0; i < n; ++i)
@@ -1600,8 +1663,14 @@ std::vector<char> batch_key(const lt_batch* b, const lt_instance* inst, int n, c
   std::vector<char> k((const char*)v.data(), (const char*)(v.data() + n));
   const char* t = (const char*)&b->tune;
   k.insert(k.end(), t, t + sizeof(lt_tuning));
-  const size_t sz[4] = {(size_t)P.stack_n, P.det_lds, P.att_lds, P.solo.size()};
-  k.insert(k.end(), (const char*)sz, (const char*)(sz + 4));
+  const size_t sz[6] = {(size_t)P.stack_n, P.det_lds, P.att_lds, P.solo.size(), P.solo_det.size(), (size_t)P.det_hf};
+  k.insert(k.end(), (const char*)sz, (const char*)(sz + 6));
+  k.insert(k.end(), (const char*)P.solo_det.data(), (const char*)(P.solo_det.data() + P.solo_det.size()));
+  k.insert(k.end(), (const char*)P.solo_trace.data(), (const char*)(P.solo_trace.data() + P.solo_trace.size()));
+  k.insert(k.end(), (const char*)P.solo_trace_shape.data(),
+           (const char*)(P.solo_trace_shape.data() + P.solo_trace_shape.size()));
+  k.insert(k.end(), (const char*)P.solo_det_shape.data(),
+           (const char*)(P.solo_det_shape.data() + P.solo_det_shape.size()));
   k.insert(k.end(), (const char*)P.solo.data(), (const char*)(P.solo.data() + P.solo.size()));
   k.insert(k.end(), (const char*)P.solo_lds.data(), (const char*)(P.solo_lds.data() + P.solo_lds.size()));
   k.insert(k.end(), (const char*)P.solo_block.data(), (const char*)(P.solo_block.data() + P.solo_block.size()));

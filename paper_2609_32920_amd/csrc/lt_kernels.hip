@@ -1099,9 +1099,28 @@ __global__ void __launch_bounds__(1024) k_trace_batch(const PassArgs* __restrict
   extern __shared__ int lds[];
   for (int i = 0; i < n; ++i) trace_run<false, false>(table_entry(T, i), lds);
 }
+// One table entry through the single-instance forward: five waves per SIMD
+// (the multi-entry kernel holds four), without the heightfield walk where the
+// scene has none.  Batches run their largest instances' forwards through it.
+template <bool HF>
+__global__ void __launch_bounds__(1024, 5) k_trace_entry(const PassArgs* __restrict__ T) {
+  extern __shared__ int lds[];
+  trace_run<false, false, false, false, HF>(table_entry(T, 0), lds);
+}
+// HF = false: no entry's scene has a heightfield
+template <bool HF>
 __global__ void __launch_bounds__(1024) k_lrb3_batch(const PassArgs* __restrict__ T, int n) {
   extern __shared__ int lds[];
-  for (int i = 0; i < n; ++i) lrb3_run<true>(table_entry(T, i), lds);
+  for (int i = 0; i < n; ++i) lrb3_run<HF>(table_entry(T, i), lds);
+}
+// One detached entry of the table as the single-instance kernel runs it:
+// without the loop over entries, which holds live state across the
+// instances and costs the multi-entry kernel spill space (140 against 60
+// bytes per lane).  Batches run their large detached instances through it.
+template <bool HF>
+__global__ void __launch_bounds__(1024) k_lrb3_entry(const PassArgs* __restrict__ T) {
+  extern __shared__ int lds[];
+  lrb3_run<HF>(table_entry(T, 0), lds);
 }
 __global__ void __launch_bounds__(256, 2) k_lrb3_att_batch(const PassArgs* __restrict__ T, int n) {
   extern __shared__ int lds[];
@@ -1151,7 +1170,9 @@ hipError_t set_lds_limit(int bytes) {
     if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_reslrb_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_naive_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_lrb3_batch, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  for (const void* f : {(const void*)k_lrb3_batch<true>, (const void*)k_lrb3_batch<false>,
+                        (const void*)k_lrb3_entry<true>, (const void*)k_lrb3_entry<false>})
+    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_lrb3_att_batch, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e == hipSuccess)
@@ -1184,7 +1205,8 @@ int resident_groups(BwdKernel k, int block, size_t lds) {
     case BwdKernel::naive_att: f = (const void*)k_naive_att_bwd<false>; break;
     case BwdKernel::reslrb_att: f = (const void*)k_reslrb_att<false>; break;
     case BwdKernel::lrb3_att: f = (const void*)k_lrb3_att<false>; break;
-    case BwdKernel::lrb3_batch: f = (const void*)k_lrb3_batch; break;
+    case BwdKernel::lrb3_batch: f = (const void*)k_lrb3_batch<true>; break;
+    case BwdKernel::lrb3_entry: f = (const void*)k_lrb3_entry<true>; break;
     case BwdKernel::lrb3_att_batch: f = (const void*)k_lrb3_att_batch; break;
     case BwdKernel::lrb3_att_entry: f = (const void*)k_lrb3_att_entry; break;
     case BwdKernel::lrb3_att_p3_entry: f = (const void*)k_lrb3_att_p3_entry; break;
@@ -1234,10 +1256,21 @@ hipError_t launch_trace_batch(const PassArgs* table, int n, int stack_n, int gri
   hipLaunchKernelGGL(k_trace_batch, dim3(grid), dim3(block), (size_t)stack_n * block * sizeof(int), s, table, n);
   return hipGetLastError();
 }
-hipError_t launch_lrb3_batch(const PassArgs* table, int n, int stack_n, size_t grad_lds, int grid, int block,
+hipError_t launch_trace_entry(const PassArgs* entry, bool hf, int stack_n, int grid, int block, hipStream_t s) {
+  hipLaunchKernelGGL(hf ? k_trace_entry<true> : k_trace_entry<false>, dim3(grid), dim3(block),
+                     (size_t)stack_n * block * sizeof(int), s, entry);
+  return hipGetLastError();
+}
+hipError_t launch_lrb3_batch(const PassArgs* table, int n, bool hf, int stack_n, size_t grad_lds, int grid, int block,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_lrb3_batch, dim3(grid), dim3(block), (size_t)stack_n * block * sizeof(int) + grad_lds, s, table,
-                     n);
+  hipLaunchKernelGGL(hf ? k_lrb3_batch<true> : k_lrb3_batch<false>, dim3(grid), dim3(block),
+                     (size_t)stack_n * block * sizeof(int) + grad_lds, s, table, n);
+  return hipGetLastError();
+}
+hipError_t launch_lrb3_entry(const PassArgs* entry, bool hf, int stack_n, size_t grad_lds, int grid, int block,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(hf ? k_lrb3_entry<true> : k_lrb3_entry<false>, dim3(grid), dim3(block),
+                     (size_t)stack_n * block * sizeof(int) + grad_lds, s, entry);
   return hipGetLastError();
 }
 hipError_t launch_lrb3_att_batch(const PassArgs* table, int n, int stack_n, size_t grad_lds, int grid, hipStream_t s) {

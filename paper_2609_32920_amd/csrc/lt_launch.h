@@ -111,8 +111,14 @@ hipError_t launch_lrb2_bwd(const PassArgs& A, int grid, int block, hipStream_t s
 // batches: `table` is a DEVICE array of n PassArgs; stack_n the largest
 // traversal stack among them
 hipError_t launch_trace_batch(const PassArgs* table, int n, int stack_n, int grid, int block, hipStream_t s);
-// grad_lds: LDS bytes past the traversal stacks for per-workgroup gradient copies
-hipError_t launch_lrb3_batch(const PassArgs* table, int n, int stack_n, size_t grad_lds, int grid, int block,
+// one table entry's forward (the table pointer already offset to it)
+hipError_t launch_trace_entry(const PassArgs* entry, bool hf, int stack_n, int grid, int block, hipStream_t s);
+// grad_lds: LDS bytes past the traversal stacks for per-workgroup gradient
+// copies; hf: some entry's scene has a heightfield
+hipError_t launch_lrb3_batch(const PassArgs* table, int n, bool hf, int stack_n, size_t grad_lds, int grid, int block,
+                             hipStream_t s);
+// one detached table entry (the table pointer already offset to it)
+hipError_t launch_lrb3_entry(const PassArgs* entry, bool hf, int stack_n, size_t grad_lds, int grid, int block,
                              hipStream_t s);
 hipError_t launch_lrb3_att_batch(const PassArgs* table, int n, int stack_n, size_t grad_lds, int grid, hipStream_t s);
 // one attached table entry (the table pointer already offset to it)
@@ -151,7 +157,7 @@ hipError_t set_lds_limit(int bytes);
 // Workgroups of a backward kernel resident per CU at `block` threads and
 // `lds` dynamic LDS bytes (0 if it cannot launch or the query fails).
 enum class BwdKernel { naive, reslrb, lrb3, naive_att, reslrb_att, lrb3_att, lrb3_batch, lrb3_att_batch, lrb3_att_entry,
-                       lrb3_p2, lrb3_p3, lrb3_att_p2, lrb3_att_p3, lrb2, lrb3_att_p3_entry, camera_prb };
+                       lrb3_p2, lrb3_p3, lrb3_att_p2, lrb3_att_p3, lrb2, lrb3_att_p3_entry, camera_prb, lrb3_entry };
 int resident_groups(BwdKernel k, int block, size_t lds);
 hipError_t read_counters(uint64_t* out, bool reset, hipStream_t s);
 
