@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--ee-seeds", type=int, default=16, help="seeds per equal-error variance estimate")
     ap.add_argument("--no-inverse", action="store_true", help="skip the heightfield inverse-rendering loop")
     ap.add_argument("--no-bidir", action="store_true", help="skip the bidirectional glass-slab workload")
+    ap.add_argument("--no-materials", action="store_true",
+                    help="skip the mirror / glass-panel / tumbler material workloads")
     ap.add_argument("--inverse-iters", type=int, default=1000, help="Adam iterations of the inverse-rendering loop")
     ap.add_argument("--cpu-paths", type=int, default=1 << 22, help="paths in the CPU-oracle sample")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="least CPU-oracle time (whole steps)")
@@ -309,6 +311,11 @@ def main():
     if not args.no_bidir:
         bidir = bench_bidirectional(lt, scenes, dev, stream, bytes_per_path, cpu=not args.no_cpu)
 
+    # ---- further materials: rough conductor, normal map, textured directional emitter
+    materials = None
+    if not args.no_materials:
+        materials = bench_materials(lt, scenes, dev, stream, bytes_per_path)
+
     # ---- CPU baseline: the FP64 oracle, forward + naive backward, on a sample
     cpu = cpu1 = cpu_more = None
     if not args.no_cpu:
@@ -370,6 +377,7 @@ def main():
         "guided_batch": guided_batch,
         "guide_diffuse_detail_box": guide_diffuse,
         "bidirectional": bidir,
+        "materials": materials,
     }
     print(json.dumps(out), flush=True)
 
@@ -736,6 +744,90 @@ def bench_guide_diffuse(lt, scenes, dev, stream, film=256, N=1 << 22, D=8, iters
               f"median-texel {mr:.3f} {out[name]['median_texel_ratio_bootstrap_90']}, {t0:.2f} -> {t1:.2f} ms, "
               f"gain {out[name]['efficiency_gain']} (robust {out[name]['robust_efficiency_gain']}), "
               f"z^2 {out[name]['bias_mean_z2']}", file=sys.stderr, flush=True)
+    return out
+
+
+def bench_materials(lt, scenes, dev, stream, bytes_per_path_fn, G=128, film=512, N=1 << 24, D=6, reps=4):
+    """The further materials and parameters of the paper's validation scenes
+    at the attached workload's size (G x G heightfield, film^2, depth D, N
+    paths), one LRB-3 optimisation step each (forward, L2 loss, backward):
+    Mirror (rough-conductor heightfield, attached gradients w.r.t. the
+    heights), Glass Panel (normal-mapped dielectric, attached gradients
+    w.r.t. the normal map), Tumbler (glass under a directional emitter with
+    a radiance texture, detached gradients w.r.t. that texture and the
+    albedo).  The backward's roofline uses the byte model of the counters
+    build on a 2^18-path sample."""
+    import numpy as np
+    import torch
+    t32 = lambda a: torch.as_tensor(np.asarray(a, np.float32), device=dev).contiguous()
+    cases = (
+        ("mirror", scenes.mirror_scene(G=G, width=film, height=film), lt.ATTACHED,
+         "rough-conductor heightfield (GGX) lighting a diffuse wall, attached gradients w.r.t. the heights"),
+        ("glass_panel", scenes.glass_panel_scene(G=G, width=film, height=film), lt.ATTACHED,
+         "normal-mapped glass panel over a diffuse receiver, attached gradients w.r.t. the normal map"),
+        ("tumbler", scenes.tumbler_scene(G=G, width=film, height=film), 0,
+         "glass heightfield under a directional emitter with an 8x8 radiance texture, detached gradients "
+         "w.r.t. the emitter texture and the albedo"),
+    )
+    out = {}
+    for name, sc, flags, what in cases:
+        ctx = lt.Context(0).scene_upload(sc)
+        albedo, Le, h = t32(sc["albedo"]), t32(sc["Le"]), t32(sc["heights"])
+        nm = t32(sc["normal_map"]) if "normal_map" in sc else None
+        img = torch.empty((film, film, 3), dtype=torch.float32, device=dev)
+        target, dI = torch.empty_like(img), torch.empty_like(img)
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+        ga, gl = torch.zeros_like(albedo), torch.zeros_like(Le)
+        gh = torch.zeros_like(h) if flags else None
+        gn = torch.zeros_like(nm) if (flags and nm is not None) else None
+        tgt = ctx.params(t32(sc["albedo_target"]) if sc.get("albedo_target") is not None else albedo,
+                         t32(sc["Le_target"]) if "Le_target" in sc else Le,
+                         t32(sc["heights_target"]) if sc.get("heights_target") is not None else h,
+                         normal_map=t32(sc["normal_map_target"]) if "normal_map_target" in sc else nm)
+        ctx.trace(ctx.args(0x7A6, N, D, flags), tgt, target)
+        p = ctx.params(albedo, Le, h, normal_map=nm)
+        ts, tb = [], []
+        for k in range(reps + 1):
+            a = ctx.args(100 + k, N, D, flags)
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record(stream)
+            ctx.trace(a, p, img)
+            ctx.loss_l2(img, target, dI, loss)
+            e[1].record(stream)
+            ctx.backward_lrb3(a, p, dI, ga, gl, gh, gn)
+            e[2].record(stream)
+            e[2].synchronize()
+            if k:
+                ts.append(e[0].elapsed_time(e[2]))
+                tb.append(e[1].elapsed_time(e[2]))
+        ms, bms = float(np.median(ts)), float(np.median(tb))
+        r = {"workload": f"{what}; {G}x{G} heightfield, film {film}x{film}, depth {D}, {N} paths",
+             "ms": round(ms, 3), "backward_ms": round(bms, 3), "paths_per_s": round(N / (ms * 1e-3)),
+             "guard_triggers_per_path": round(ctx.stats()["guard_triggers"] / N, 6) if flags else 0.0}
+        try:
+            sample = 1 << 18
+            cctx = lt.Context(0, counters=True).scene_upload(sc)
+            a = cctx.args(100, sample, D, flags)
+            cctx.trace(a, p, img)
+            cctx.read_counters(reset=True)
+            cctx.backward_lrb3(a, p, dI, torch.zeros_like(albedo), torch.zeros_like(Le),
+                               None if gh is None else torch.zeros_like(h), None if gn is None else torch.zeros_like(nm))
+            c = cctx.read_counters(reset=True)
+            del cctx
+            bpp = bytes_per_path_fn(c, sample)
+            achieved = bpp * N / (bms * 1e-3) / 1e9
+            r["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_path": round(bpp, 1),
+                             "kernel": "LRB-3 backward (attached pair)" if flags else "k_lrb3_bwd",
+                             "traffic": None,
+                             "events_per_path": {k: round(v / sample, 3) for k, v in c.items()}}
+        except Exception as e:
+            print(f"# {name} counters unavailable: {e}", file=sys.stderr)
+        out[name] = r
+        fr = r.get("roofline", {}).get("frac")
+        print(f"# {name}: step {ms:.2f} ms (backward {bms:.2f} ms), {N / (ms * 1e-3) / 1e6:.0f}M paths/s"
+              + (f", backward frac {fr:.3f}" if fr is not None else ""), file=sys.stderr, flush=True)
+        del ctx
     return out
 
 

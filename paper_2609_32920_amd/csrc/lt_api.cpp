@@ -282,6 +282,20 @@ int agrad_in_lds(const lt_ctx* c, BwdKernel k, int block, size_t used) {
   return with > 0 && with >= resident_groups(k, block, used) ? 1 : 0;
 }
 size_t stack_lds(const lt_ctx* c, int block) { return (size_t)c->dsc.stack_n * block * sizeof(int); }
+size_t agrad_lds_bytes(const lt_ctx* c, int on) {
+  return on ? (size_t)c->dsc.n_tex * c->dsc.tex_res * c->dsc.tex_res * 3 * sizeof(float) : 0;
+}
+// Textured-emitter gradients go to a per-workgroup LDS copy (after the
+// albedo copy; `used` bytes before it) when lds_grad allows copies, the
+// texture takes at most 16 KB and the copy costs the kernel no resident
+// workgroups; otherwise each path adds to the caller's array.
+int legrad_in_lds(const lt_ctx* c, BwdKernel k, int block, size_t used) {
+  if (!c->tune.lds_grad || c->dsc.em_tex_res <= 0) return 0;
+  const size_t need = (size_t)c->dsc.em_tex_res * c->dsc.em_tex_res * 3 * sizeof(float);
+  if (need > 16 * 1024 || used + need > (size_t)c->lds_max) return 0;
+  const int with = resident_groups(k, block, used + need);
+  return with > 0 && with >= resident_groups(k, block, used) ? 1 : 0;
+}
 
 // Launch shape of a detached replay backward.  An LDS copy of the albedo
 // gradients is held per workgroup, so at the tuned shape (128 threads, ten
@@ -985,6 +999,7 @@ lt_status lt_backward_naive(lt_ctx* c, const lt_trace_args* a, const lt_params* 
     if ((st = c->hip(launch_naive_att_bwd(A, grid, c->stream), "naive attached backward")) != LT_OK) return st;
   } else {
     A.agrad_lds = agrad_in_lds(c, BwdKernel::naive, 256, 0);
+    A.legrad_lds = legrad_in_lds(c, BwdKernel::naive, 256, agrad_lds_bytes(c, A.agrad_lds));
     if ((st = c->hip(launch_naive_bwd(A, grid, c->stream), "naive backward")) != LT_OK) return st;
   }
   return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
@@ -1011,6 +1026,7 @@ lt_status lt_backward_reslrb(lt_ctx* c, const lt_trace_args* a, const lt_params*
   A.res_in = (const ResRec*)((const char*)records + L.res);
   const Shape sh = replay_shape(c, BwdKernel::reslrb, a->n_paths);
   A.agrad_lds = sh.agrad_lds;
+  A.legrad_lds = legrad_in_lds(c, BwdKernel::reslrb, sh.block, stack_lds(c, sh.block) + agrad_lds_bytes(c, sh.agrad_lds));
   if ((st = c->hip(launch_reslrb_bwd(A, sh.grid, sh.block, c->stream), "reslrb backward")) != LT_OK) return st;
   return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
 }
@@ -1030,6 +1046,7 @@ lt_status lt_backward_lrb2(lt_ctx* c, const lt_trace_args* a, const lt_params* p
   A.spl_in = (const SplatRec*)((const char*)records + L.spl);
   const Shape sh = replay_shape(c, BwdKernel::lrb2, a->n_paths);
   A.agrad_lds = sh.agrad_lds;
+  A.legrad_lds = legrad_in_lds(c, BwdKernel::lrb2, sh.block, stack_lds(c, sh.block) + agrad_lds_bytes(c, sh.agrad_lds));
   if ((st = c->hip(launch_lrb2_bwd(A, sh.grid, sh.block, c->stream), "two-pass backward")) != LT_OK) return st;
   return c->hip(launch_add_le(c->d_acc, g->emitter_L, c->stream), "emitter gradient");
 }
@@ -1069,11 +1086,14 @@ static lt_status lrb3_enqueue(lt_ctx* c, const lt_trace_args* a, const lt_params
         return st;
     } else {
       const int blk = c->tune.block;
+      A.agrad_lds = 0;  // pass 2 scatters no albedo gradients
+      A.legrad_lds = legrad_in_lds(c, BwdKernel::lrb3_p2, blk, stack_lds(c, blk));
       if ((st = c->hip(launch_lrb3_p2(A, persistent_grid(c, a->n_paths, blk), blk, c->stream), "lrb3 pass 2")) !=
           LT_OK)
         return st;
       const Shape sh = replay_shape(c, BwdKernel::lrb3_p3, a->n_paths);
       A.agrad_lds = sh.agrad_lds;
+      A.legrad_lds = 0;  // pass 3 adds no emitter gradients
       if ((st = c->hip(launch_lrb3_p3(A, sh.grid, sh.block, c->stream), "lrb3 pass 3")) != LT_OK) return st;
     }
   } else if (att) {
@@ -1085,6 +1105,7 @@ static lt_status lrb3_enqueue(lt_ctx* c, const lt_trace_args* a, const lt_params
   } else {
     const Shape sh = replay_shape(c, BwdKernel::lrb3, a->n_paths);
     A.agrad_lds = sh.agrad_lds;
+    A.legrad_lds = legrad_in_lds(c, BwdKernel::lrb3, sh.block, stack_lds(c, sh.block) + agrad_lds_bytes(c, sh.agrad_lds));
     if ((st = c->hip(launch_lrb3_bwd(A, sh.grid, sh.block, c->stream), "lrb3 backward")) != LT_OK) return st;
   }
   return c->hip(launch_add_le(w.acc, g->emitter_L, c->stream), "emitter gradient");

@@ -249,14 +249,47 @@ __device__ __forceinline__ void count_nonfinite(const PassArgs& A) {
 __device__ __forceinline__ void keep_finite(const PassArgs& A, bool& has, f3 v) {
   if (has && !(isfinite(v.x) && isfinite(v.y) && isfinite(v.z))) { has = false; count_nonfinite(A); }
 }
+// Textured-emitter gradients.  Every path adds to the texel it was emitted
+// from, so a small texture takes all of them on a few cache lines, where
+// the atomics serialize.  With A.legrad_lds each workgroup pre-reduces them
+// in an LDS copy of the texture (`le`, past the albedo copy) and adds that
+// to the caller's array once, at its end.  Every thread of the workgroup
+// calls begin and end.
+__device__ __forceinline__ float* legrad_begin(const PassArgs& A, int* lds) {
+  float* le = reinterpret_cast<float*>(lds);
+  if (!A.legrad_lds) return le;
+  const int n = A.sc.em_tex_res * A.sc.em_tex_res * 3;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) le[i] = 0.f;
+  __syncthreads();
+  return le;
+}
+__device__ __forceinline__ void legrad_end(const PassArgs& A, float* le) {
+  if (!A.legrad_lds) return;
+  __syncthreads();
+  if (!A.g_le_tex) return;
+  const int n = A.sc.em_tex_res * A.sc.em_tex_res * 3;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    float v = le[i];
+    if (v != 0.f) atomicAdd(A.g_le_tex + i, v);
+  }
+}
+
 // emitter-gradient accumulation of one path, (a0, a1, a2) in place of zeros
 // when any is non-finite: into the lane's FP64 sums (one radiance), or onto
-// the path's texel of a textured emitter (texel >= 0)
+// the path's texel of a textured emitter (texel >= 0; the workgroup's LDS
+// copy `le` with A.legrad_lds)
 __device__ __forceinline__ void add_le(const PassArgs& A, double& g0, double& g1, double& g2, double a0, double a1,
-                                       double a2, int texel = -1) {
+                                       double a2, int texel = -1, float* le = nullptr) {
   if (!(isfinite(a0) && isfinite(a1) && isfinite(a2))) { count_nonfinite(A); return; }
   if (texel >= 0) {
     if (!A.g_le_tex) return;
+    if (A.legrad_lds) {
+      float* d = le + 3 * texel;
+      if (a0 != 0.0) atomicAdd(d + 0, (float)a0);
+      if (a1 != 0.0) atomicAdd(d + 1, (float)a1);
+      if (a2 != 0.0) atomicAdd(d + 2, (float)a2);
+      return;
+    }
     float* d = A.g_le_tex + 3 * texel;
     if (a0 != 0.0) atomicAdd(d + 0, (float)a0);
     if (a1 != 0.0) atomicAdd(d + 1, (float)a1);
@@ -345,7 +378,11 @@ __device__ __forceinline__ void agrad_end(const PassArgs& A, AGrad& g) {
 // The workgroup's next instance of a batch reuses the LDS past the traversal
 // stacks: no wave may start on it before every wave has flushed the copies.
 __device__ __forceinline__ void lds_grads_done(const PassArgs& A) {
-  if (A.hgrad_lds || A.agrad_lds) __syncthreads();
+  if (A.hgrad_lds || A.agrad_lds || A.legrad_lds) __syncthreads();
+}
+// LDS past the traversal stacks (stack_n entries per lane) and the albedo copy
+__device__ __forceinline__ int* past_agrad(const PassArgs& A, int* lds, int stack_n) {
+  return lds + stack_n * (int)blockDim.x + (A.agrad_lds ? A.n_texels * 3 : 0);
 }
 
 __device__ __forceinline__ void flush_le(const PassArgs& A, double g0, double g1, double g2) {
@@ -550,6 +587,7 @@ __global__ void __launch_bounds__(1024, 5) k_trace(PassArgs A) {
 __global__ void __launch_bounds__(256) k_naive_bwd(PassArgs A) {
   extern __shared__ int lds[];
   AGrad ga = agrad_begin(A, lds);
+  float* le = legrad_begin(A, past_agrad(A, lds, 0));
   const size_t N = (size_t)A.n_paths;
   double gl0 = 0.0, gl1 = 0.0, gl2 = 0.0;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -599,7 +637,7 @@ __global__ void __launch_bounds__(256) k_naive_bwd(PassArgs A) {
       D3R iLp = {0.0, 0.0, 0.0};
       int etex = -1;
       path_emitter(A, (uint32_t)path, Lp, iLp, etex);
-      add_le(A, gl0, gl1, gl2, (double)bb.x * fac, (double)bb.y * fac, (double)bb.z * fac, etex);
+      add_le(A, gl0, gl1, gl2, (double)bb.x * fac, (double)bb.y * fac, (double)bb.z * fac, etex, le);
     }
     // the path's adjoint-weighted contribution |delta_total| = sum_c |L_e,c f bb_c|
     if (A.contrib && path < N)
@@ -607,6 +645,7 @@ __global__ void __launch_bounds__(256) k_naive_bwd(PassArgs A) {
   }
   flush_le(A, gl0, gl1, gl2);
   agrad_end(A, ga);
+  legrad_end(A, le);
 }
 
 // ---------------------------------------------------------------- ResLRB
@@ -619,6 +658,7 @@ __global__ void __launch_bounds__(1024) k_reslrb_bwd(PassArgs A) {
   int* stk = lds + threadIdx.x;
   const int ss = blockDim.x;
   AGrad ga = agrad_begin(A, lds + A.sc.stack_n * blockDim.x);
+  float* le = legrad_begin(A, past_agrad(A, lds, A.sc.stack_n));
   bool alive = false, exhausted = false;
   uint32_t path = 0;
   int j = 0, R = 0;
@@ -644,7 +684,7 @@ __global__ void __launch_bounds__(1024) k_reslrb_bwd(PassArgs A) {
         f3 Lb = gather(A.sc, A.dI, rec.ux, rec.uy);
         w = mul(Lb, mk(rec.S[0], rec.S[1], rec.S[2]));
         path_emitter(A, path, Le, iLe, etex);
-        add_le(A, gl0, gl1, gl2, (double)w.x * iLe.x, (double)w.y * iLe.y, (double)w.z * iLe.z, etex);
+        add_le(A, gl0, gl1, gl2, (double)w.x * iLe.x, (double)w.y * iLe.y, (double)w.z * iLe.z, etex, le);
         emit_path(A, path, r);
         j = 1;
       }
@@ -665,6 +705,7 @@ __global__ void __launch_bounds__(1024) k_reslrb_bwd(PassArgs A) {
   }
   flush_le(A, gl0, gl1, gl2);
   agrad_end(A, ga);
+  legrad_end(A, le);
 }
 
 // ---------------------------------------------------------------- LRB-3
@@ -683,6 +724,7 @@ __device__ __forceinline__ void lrb3_run(const PassArgs& A, int* lds) {
   int* stk = lds + threadIdx.x;
   const int ss = blockDim.x;
   AGrad ga = agrad_begin(A, lds + A.sc.stack_n * blockDim.x);
+  float* le = legrad_begin(A, past_agrad(A, lds, A.sc.stack_n));
   bool alive = false, exhausted = false;
   uint32_t path = 0;
   int j = 0, phase = 2, klast = 0;
@@ -737,7 +779,7 @@ __device__ __forceinline__ void lrb3_run(const PassArgs& A, int* lds) {
       if (ev.cont) {
         ++j;
       } else if (phase == 2 && klast > 0 && (d0 != 0.0 || d1 != 0.0 || d2 != 0.0)) {  // consuming replay
-        add_le(A, gl0, gl1, gl2, d0 * iLe.x, d1 * iLe.y, d2 * iLe.z, etex);
+        add_le(A, gl0, gl1, gl2, d0 * iLe.x, d1 * iLe.y, d2 * iLe.z, etex, le);
         // the path's adjoint-weighted contribution |delta_total|
         if (A.contrib) A.contrib[path] = (float)(fabs(d0) + fabs(d1) + fabs(d2));
         phase = 3; j = 0;
@@ -751,6 +793,7 @@ __device__ __forceinline__ void lrb3_run(const PassArgs& A, int* lds) {
   }
   flush_le(A, gl0, gl1, gl2);
   agrad_end(A, ga);
+  legrad_end(A, le);
   lds_grads_done(A);
 }
 
@@ -773,6 +816,7 @@ __device__ __forceinline__ void lrb2_run(const PassArgs& A, int* lds) {
   int* stk = lds + threadIdx.x;
   const int ss = blockDim.x;
   AGrad ga = agrad_begin(A, lds + A.sc.stack_n * blockDim.x);
+  float* le = legrad_begin(A, past_agrad(A, lds, A.sc.stack_n));
   const size_t N = (size_t)A.n_paths;
   bool alive = false, exhausted = false;
   uint32_t path = 0;
@@ -806,7 +850,7 @@ __device__ __forceinline__ void lrb2_run(const PassArgs& A, int* lds) {
       }
       if (klast > 0 && (d0 != 0.0 || d1 != 0.0 || d2 != 0.0)) {
         path_emitter(A, path, Le, iLe, etex);
-        add_le(A, gl0, gl1, gl2, d0 * iLe.x, d1 * iLe.y, d2 * iLe.z, etex);
+        add_le(A, gl0, gl1, gl2, d0 * iLe.x, d1 * iLe.y, d2 * iLe.z, etex, le);
         if (A.contrib) A.contrib[path] = (float)(fabs(d0) + fabs(d1) + fabs(d2));
         emit_path(A, path, r);
         j = 1;
@@ -843,6 +887,7 @@ __device__ __forceinline__ void lrb2_run(const PassArgs& A, int* lds) {
   }
   flush_le(A, gl0, gl1, gl2);
   agrad_end(A, ga);
+  legrad_end(A, le);
 }
 
 __global__ void __launch_bounds__(1024) k_lrb2_bwd(PassArgs A) {
@@ -866,6 +911,7 @@ __global__ void __launch_bounds__(1024) k_lrb2_bwd(PassArgs A) {
 __device__ __forceinline__ void lrb3_p2_run(const PassArgs& A, int* lds) {
   int* stk = lds + threadIdx.x;
   const int ss = blockDim.x;
+  float* le = legrad_begin(A, past_agrad(A, lds, A.sc.stack_n));
   bool alive = false, exhausted = false;
   uint32_t path = 0;
   int j = 0, klast = 0;
@@ -904,7 +950,7 @@ __device__ __forceinline__ void lrb3_p2_run(const PassArgs& A, int* lds) {
         ++j;
       } else {
         put = klast > 0 && (d0 != 0.0 || d1 != 0.0 || d2 != 0.0);
-        if (put) add_le(A, gl0, gl1, gl2, d0 * iLe.x, d1 * iLe.y, d2 * iLe.z, etex);
+        if (put) add_le(A, gl0, gl1, gl2, d0 * iLe.x, d1 * iLe.y, d2 * iLe.z, etex, le);
         // the path's adjoint-weighted contribution |delta_total|
         if (A.contrib) A.contrib[path] = put ? (float)(fabs(d0) + fabs(d1) + fabs(d2)) : 0.f;
         alive = false; j = 0;
@@ -918,6 +964,7 @@ __device__ __forceinline__ void lrb3_p2_run(const PassArgs& A, int* lds) {
     }
   }
   flush_le(A, gl0, gl1, gl2);
+  legrad_end(A, le);
 }
 
 // Pass 3 (Eq. 15-17) over the handed-over paths: replay to the last
@@ -1158,6 +1205,9 @@ static size_t hgrad_bytes(const PassArgs& A) {
   return A.hgrad_lds ? (size_t)A.sc.hf_G * A.sc.hf_G * sizeof(float) : 0;
 }
 static size_t agrad_bytes(const PassArgs& A) { return A.agrad_lds ? (size_t)A.n_texels * 3 * sizeof(float) : 0; }
+static size_t legrad_bytes(const PassArgs& A) {
+  return A.legrad_lds ? (size_t)A.sc.em_tex_res * A.sc.em_tex_res * 3 * sizeof(float) : 0;
+}
 
 // allow the backward kernels the device's full LDS per workgroup
 hipError_t set_lds_limit(int bytes) {
@@ -1328,18 +1378,19 @@ hipError_t launch_camera_prb(const PassArgs& A, int grid, int block, hipStream_t
 }
 
 hipError_t launch_naive_bwd(const PassArgs& A, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_naive_bwd, dim3(grid), dim3(256), agrad_bytes(A), s, A);
+  hipLaunchKernelGGL(k_naive_bwd, dim3(grid), dim3(256), agrad_bytes(A) + legrad_bytes(A), s, A);
   return hipGetLastError();
 }
 
 hipError_t launch_reslrb_bwd(const PassArgs& A, int grid, int block, hipStream_t s) {
-  hipLaunchKernelGGL(k_reslrb_bwd, dim3(grid), dim3(block), stack_bytes(A, block) + agrad_bytes(A), s, A);
+  hipLaunchKernelGGL(k_reslrb_bwd, dim3(grid), dim3(block), stack_bytes(A, block) + agrad_bytes(A) + legrad_bytes(A), s,
+                     A);
   return hipGetLastError();
 }
 
 hipError_t launch_lrb3_bwd(const PassArgs& A, int grid, int block, hipStream_t s) {
   hipLaunchKernelGGL(A.sc.hf_G >= 2 ? k_lrb3_bwd<true> : k_lrb3_bwd<false>, dim3(grid), dim3(block),
-                     stack_bytes(A, block) + agrad_bytes(A), s, A);
+                     stack_bytes(A, block) + agrad_bytes(A) + legrad_bytes(A), s, A);
   return hipGetLastError();
 }
 
@@ -1354,12 +1405,14 @@ hipError_t launch_trace_gsamples(const PassArgs& A, int grid, int block, hipStre
   return hipGetLastError();
 }
 hipError_t launch_lrb2_bwd(const PassArgs& A, int grid, int block, hipStream_t s) {
-  hipLaunchKernelGGL(k_lrb2_bwd, dim3(grid), dim3(block), stack_bytes(A, block) + agrad_bytes(A), s, A);
+  hipLaunchKernelGGL(k_lrb2_bwd, dim3(grid), dim3(block), stack_bytes(A, block) + agrad_bytes(A) + legrad_bytes(A), s,
+                     A);
   return hipGetLastError();
 }
 
 hipError_t launch_lrb3_p2(const PassArgs& A, int grid, int block, hipStream_t s) {
-  hipLaunchKernelGGL(k_lrb3_p2, dim3(grid), dim3(block), stack_bytes(A, block), s, A);
+  hipLaunchKernelGGL(k_lrb3_p2, dim3(grid), dim3(block), stack_bytes(A, block) + agrad_bytes(A) + legrad_bytes(A), s,
+                     A);
   return hipGetLastError();
 }
 hipError_t launch_lrb3_p3(const PassArgs& A, int grid, int block, hipStream_t s) {

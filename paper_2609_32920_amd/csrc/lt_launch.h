@@ -45,6 +45,7 @@ struct PassArgs {
   unsigned long long* stats;  // [0] guard triggers, [1] non-finite drops
   int32_t hgrad_lds;          // heights gradients accumulated per workgroup in LDS
   int32_t agrad_lds;          // albedo gradients accumulated per workgroup in LDS
+  int32_t legrad_lds;         // textured-emitter gradients accumulated per workgroup in LDS (past the albedo copy)
   const float4* guide_rec;    // guided emission (direction, density) per path, or null
   const float4* gtab;         // diffuse guide table [2 n_texels][16], or null (cosine scatter)
   int32_t cond;               // the scene has rough conductors: attached kernels carry their terms

@@ -45,15 +45,19 @@ def test_tumbler_forward_and_gradients(tumbler):
     _, dI = O.loss_and_adjoint(O.render(sc, seed, n, D, path_list=ids)["image"], T)
     on = O.gradient(sc, seed, n, D, dI, path_list=ids)
     orr = O.gradient(sc, seed, n, D, dI, mode=O.MODE_RESLRB, path_list=ids)
-    for mode, ref, split in (("naive", on, 2), ("reslrb", orr, 2), ("lrb3", on, 2), ("lrb3", on, 1), ("lrb2", on, 2)):
-        g.ctx.set_tuning(lrb3_split=split)
+    # lds_grad 1 (default): each workgroup pre-reduces the emitter-texture
+    # gradients in LDS; 0: every path adds to the gradient array
+    for mode, ref, split, lds in (("naive", on, 2, 1), ("reslrb", orr, 2, 1), ("lrb3", on, 2, 1), ("lrb3", on, 1, 1),
+                                  ("lrb2", on, 2, 1), ("lrb3", on, 2, 0), ("lrb3", on, 1, 0)):
+        g.ctx.set_tuning(lds_grad=lds, lrb3_split=split)
         try:
             gg = g.backward(mode, seed, n, D, dI, mask=mask)
         finally:
             g.ctx.set_tuning()
         el, ea = maxrel(gg["Le"], ref["Le"]), maxrel(gg["albedo"], ref["albedo"])
-        print(f"tumbler {mode} (split {split}): emitter texture maxrel {el:.2e} albedo {ea:.2e}", flush=True)
-        assert el <= TOL and ea <= TOL, (mode, split)
+        print(f"tumbler {mode} (split {split}, lds_grad {lds}): emitter texture maxrel {el:.2e} albedo {ea:.2e}",
+              flush=True)
+        assert el <= TOL and ea <= TOL, (mode, split, lds)
 
 
 def test_textured_emitter_identity(tumbler):
