@@ -205,8 +205,12 @@ typedef struct {
                               the kernel no resident workgroups; the detached replay
                               backwards then run the same threads per CU in workgroups of
                               block, 2 block, 4 block ... threads (at most 1024, dividing
-                              blocks_per_cu), the first at which the copy fits; 0: never
-                              (waves then write-combine them into the gradient array) */
+                              blocks_per_cu), the first at which the copy fits.  The
+                              detached backwards (single-instance calls) also pre-reduce a
+                              textured emitter's gradients in LDS when that texture takes
+                              at most 16 KB and costs no resident workgroups.  0: never
+                              (waves then write-combine albedo gradients into the gradient
+                              array; every path adds its emitter-texel gradient there) */
   int32_t lrb3_split;      /* how lt_backward_lrb3 runs its two replays.  Split: pass 2 and
                               pass 3 as two kernels, each connected path's state (delta_total,
                               validity bits, last connection depth; attached also A) handed
