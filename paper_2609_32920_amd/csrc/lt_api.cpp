@@ -1078,9 +1078,11 @@ static lt_status lrb3_enqueue(lt_ctx* c, const lt_trace_args* a, const lt_params
       if ((st = c->hip(launch_lrb3_att_p2(A, persistent_grid(c, a->n_paths, blk2), blk2, c->stream),
                        "lrb3 attached pass 2")) != LT_OK)
         return st;
-      const int blk = att_replay_block(c, g->heights, c->dsc.stack_n, BwdKernel::lrb3_att_p3, 768);
-      A.hgrad_lds = hgrad_in_lds(c, g->heights, BwdKernel::lrb3_att_p3, blk, stack_lds(c, blk), true);
-      A.agrad_lds = agrad_in_lds(c, BwdKernel::lrb3_att_p3, blk, stack_lds(c, blk) + hgrad_lds_bytes(c, A.hgrad_lds));
+      // rough conductors: the pass-3 kernel at two waves per SIMD, workgroups of at most 512 threads
+      const BwdKernel k3 = A.cond ? BwdKernel::lrb3_att_p3_cond : BwdKernel::lrb3_att_p3;
+      const int blk = att_replay_block(c, g->heights, c->dsc.stack_n, k3, A.cond ? 512 : 768);
+      A.hgrad_lds = hgrad_in_lds(c, g->heights, k3, blk, stack_lds(c, blk), true);
+      A.agrad_lds = agrad_in_lds(c, k3, blk, stack_lds(c, blk) + hgrad_lds_bytes(c, A.hgrad_lds));
       if ((st = c->hip(launch_lrb3_att_p3(A, persistent_grid(c, a->n_paths, blk), blk, c->stream),
                        "lrb3 attached pass 3")) != LT_OK)
         return st;
