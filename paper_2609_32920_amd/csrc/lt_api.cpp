@@ -1099,10 +1099,12 @@ static lt_status lrb3_enqueue(lt_ctx* c, const lt_trace_args* a, const lt_params
       if ((st = c->hip(launch_lrb3_p3(A, sh.grid, sh.block, c->stream), "lrb3 pass 3")) != LT_OK) return st;
     }
   } else if (att) {
-    const int blk = att_replay_block(c, g->heights, c->dsc.stack_n, BwdKernel::lrb3_att, 768);
+    // rough conductors: two waves per SIMD, workgroups of at most 512 threads
+    const BwdKernel k = A.cond ? BwdKernel::lrb3_att_cond : BwdKernel::lrb3_att;
+    const int blk = att_replay_block(c, g->heights, c->dsc.stack_n, k, A.cond ? 512 : 768);
     int grid = persistent_grid(c, a->n_paths, blk);
-    A.hgrad_lds = hgrad_in_lds(c, g->heights, BwdKernel::lrb3_att, blk, stack_lds(c, blk), true);
-    A.agrad_lds = agrad_in_lds(c, BwdKernel::lrb3_att, blk, stack_lds(c, blk) + hgrad_lds_bytes(c, A.hgrad_lds));
+    A.hgrad_lds = hgrad_in_lds(c, g->heights, k, blk, stack_lds(c, blk), true);
+    A.agrad_lds = agrad_in_lds(c, k, blk, stack_lds(c, blk) + hgrad_lds_bytes(c, A.hgrad_lds));
     if ((st = c->hip(launch_lrb3_att(A, grid, blk, c->stream), "lrb3 attached backward")) != LT_OK) return st;
   } else {
     const Shape sh = replay_shape(c, BwdKernel::lrb3, a->n_paths);
@@ -1366,9 +1368,9 @@ struct BatchPlan {
   // [n_solo_det detached], the solo ones a launch each
   std::vector<PassArgs> tab;
   std::vector<int> trace_pos;       // table position of each instance's forward entry
-  std::vector<int> solo_trace;      // instances whose forward runs on its own: block, grid, heightfield each
-  std::vector<int> solo_trace_shape;
-  int n_bt = 0;
+  std::vector<int> solo_trace;      // instances whose forward runs on its own
+  std::vector<int> solo_trace_shape;  // per solo forward launch: block, grid, heightfield
+  int n_bt = 0;                     // batched forward entries (the table's first)
   std::vector<int> det, att, solo, solo_det;  // instance indices of each backward kind
   int n = 0, stack_n = 1;      // traversal stack entries per lane, the same for every entry
   bool det_hf = false;         // some batched detached entry has a heightfield

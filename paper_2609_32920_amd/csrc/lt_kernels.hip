@@ -1258,6 +1258,7 @@ int resident_groups(BwdKernel k, int block, size_t lds) {
     case BwdKernel::lrb3_batch: f = (const void*)k_lrb3_batch<true>; break;
     case BwdKernel::lrb3_entry: f = (const void*)k_lrb3_entry<true>; break;
     case BwdKernel::lrb3_att_p3_cond: f = (const void*)k_lrb3_att_p3<true>; break;
+    case BwdKernel::lrb3_att_cond: f = (const void*)k_lrb3_att<true>; break;
     case BwdKernel::lrb3_att_batch: f = (const void*)k_lrb3_att_batch; break;
     case BwdKernel::lrb3_att_entry: f = (const void*)k_lrb3_att_entry; break;
     case BwdKernel::lrb3_att_p3_entry: f = (const void*)k_lrb3_att_p3_entry; break;

@@ -159,7 +159,7 @@ hipError_t set_lds_limit(int bytes);
 // `lds` dynamic LDS bytes (0 if it cannot launch or the query fails).
 enum class BwdKernel { naive, reslrb, lrb3, naive_att, reslrb_att, lrb3_att, lrb3_batch, lrb3_att_batch, lrb3_att_entry,
                        lrb3_p2, lrb3_p3, lrb3_att_p2, lrb3_att_p3, lrb2, lrb3_att_p3_entry, camera_prb, lrb3_entry,
-                       lrb3_att_p3_cond };
+                       lrb3_att_p3_cond, lrb3_att_cond };
 int resident_groups(BwdKernel k, int block, size_t lds);
 hipError_t read_counters(uint64_t* out, bool reset, hipStream_t s);
 
