@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--ee-seeds", type=int, default=16, help="seeds per equal-error variance estimate")
     ap.add_argument("--no-inverse", action="store_true", help="skip the heightfield inverse-rendering loop")
     ap.add_argument("--no-bidir", action="store_true", help="skip the bidirectional glass-slab workload")
+    ap.add_argument("--lrb3-split", type=int, choices=(0, 1, 2), default=2,
+                    help="lt_tuning.lrb3_split of the headline step (2: the library's default, fused when detached)")
     ap.add_argument("--no-materials", action="store_true",
                     help="skip the mirror / glass-panel / tumbler material workloads")
     ap.add_argument("--inverse-iters", type=int, default=1000, help="Adam iterations of the inverse-rendering loop")
@@ -92,6 +94,8 @@ def main():
     sc = scenes.box_scene(width=args.film, height=args.film)
     N, D = args.paths, args.depth
     ctx = lt.Context(0).scene_upload(sc)
+    if args.lrb3_split != 2:
+        ctx.set_tuning(lrb3_split=args.lrb3_split)
     albedo = torch.as_tensor(sc["albedo"], dtype=torch.float32, device=dev).contiguous()
     Le = torch.as_tensor(sc["Le"], dtype=torch.float32, device=dev)
     alb_t = torch.as_tensor(sc["albedo_target"], dtype=torch.float32, device=dev).contiguous()
@@ -168,14 +172,16 @@ def main():
         bpp = bytes_per_path(counts["lrb3"])
         t_launch = float(np.mean(bwd)) * 1e-3
         achieved = bpp * N / t_launch / 1e9
-        traffic = profiled_traffic("k_lrb3_bwd_box256_d32_4M.txt") if (N == 1 << 22 and D == 32 and W == 256) else None
+        fused = args.lrb3_split != 1
+        traffic = profiled_traffic("k_lrb3_bwd_box256_d32_4M.txt") if (fused and N == 1 << 22 and D == 32 and W == 256) \
+            else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     # the same launch's measured DRAM bytes (rocprofv3) over its time: the
                     # share of the HBM peak the kernel actually moves, beside the
                     # algorithmic-byte fraction above
                     "traffic_frac": None if traffic is None else round(traffic / t_launch / 1e9 / HBM_PEAK_GBS, 4),
-                    "kernel": "k_lrb3_bwd", "bytes_per_path": round(bpp, 1),
+                    "kernel": "k_lrb3_bwd" if fused else "k_lrb3_p2 + k_lrb3_p3", "bytes_per_path": round(bpp, 1),
                     "valu_issue_frac_profiled": profiled_traffic("k_lrb3_caustic128_box256_valu.txt",
                                                                  "valu_issue_frac_k_lrb3_bwd"),
                     "l2_hit_rate_profiled": profiled_traffic("k_lrb3_caustic128_box256_valu.txt",
