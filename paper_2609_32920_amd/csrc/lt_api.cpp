@@ -391,10 +391,11 @@ size_t guide_bytes(const lt_trace_args* a, const lt_params* p) {
 // at most (flat in depth).
 // Whether lt_backward_lrb3 runs its passes as two kernels for these args
 // (default 2: attached only).  On the 128x128 caustic (attached) the split
-// pair runs 15.9 against 23.1 ms fused; detached it gains 3% on the 256x256
-// box at depth 32 (6.37 against 6.55 ms) and 11% on the glass slab (1.67
-// against 1.88 ms) at 40 bytes of hand-off per path, against none for the
-// fused kernel, so the detached backward stays fused unless asked.
+// pair runs 15.9 against 23.1 ms fused; detached the two run alike on the
+// 256x256 box at depth 32 (6.28 against 6.24 ms) and the pair gains 11% on
+// the glass slab (1.67 against 1.88 ms) for 40 bytes of hand-off per path,
+// where the fused kernel needs none, so the detached backward stays fused
+// unless asked.
 bool lrb3_split(const lt_ctx* c, const lt_trace_args* a) {
   return c->tune.lrb3_split == 1 || (c->tune.lrb3_split == 2 && (a->flags & LT_ATTACHED));
 }
