@@ -593,10 +593,18 @@ __device__ __forceinline__ void splat_wave(const DevScene& sc, float* image, boo
   const int slot = lane / 12, v = lane - slot * 12;
   const int row = v / 6, k = v - row * 6, tx = k / 3, ch = k - tx * 3;
   while (m) {
-    uint64_t mm = m;
-    for (int i = 0; i < slot && mm; ++i) mm &= mm - 1ull;
-    int src = mm ? (__ffsll((unsigned long long)mm) - 1) : 0;
-    bool act = mm != 0ull && slot < 5;
+    // the next five pending splats in lane order, found on the wave-uniform
+    // mask (-1 past the last); lane slot s takes the s-th
+    uint64_t r = m;
+    int b[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      b[i] = r ? __ffsll((unsigned long long)r) - 1 : -1;
+      r &= r - 1ull;
+    }
+    const int pick = slot == 0 ? b[0] : slot == 1 ? b[1] : slot == 2 ? b[2] : slot == 3 ? b[3] : slot == 4 ? b[4] : -1;
+    const bool act = pick >= 0;
+    const int src = act ? pick : 0;
     int spx = __shfl(px0, src), spy = __shfl(py0, src);
     float sux = __shfl(ux, src), suy = __shfl(uy, src);
     float c0 = __shfl(C.x, src), c1 = __shfl(C.y, src), c2 = __shfl(C.z, src);
@@ -607,8 +615,19 @@ __device__ __forceinline__ void splat_wave(const DevScene& sc, float* image, boo
       float c = ch == 0 ? c0 : (ch == 1 ? c1 : c2);
       atomicAdd(image + (py * sc.W + px) * 3 + ch, wx * wy * c);
     }
-    for (int i = 0; i < 5 && m; ++i) m &= m - 1ull;
+    m = r;
   }
+}
+
+// Lane position of the s-th (from 0) set bit of m, which has more than s set
+// bits: the largest p with fewer than s + 1 set bits below it, by binary
+// lifting on popcounts (six steps, the same for every lane).
+__device__ __forceinline__ int nth_set_bit(uint64_t m, int s) {
+  int pos = 0;
+#pragma unroll
+  for (int w = 32; w > 0; w >>= 1)
+    if (__popcll(m & ((1ull << (pos + w)) - 1ull)) <= s) pos += w;
+  return pos;
 }
 
 // Wave-cooperative add of RGB triplets: every lane with `has` adds v to
@@ -644,10 +663,9 @@ __device__ __forceinline__ void scatter3_wave(float* dst, bool has, int idx, f3 
   has = has && ((m >> lane) & 1ull);
   const int slot = lane / 3, ch = lane - slot * 3;
   while (m) {
-    uint64_t mm = m;
-    for (int i = 0; i < slot && mm; ++i) mm &= mm - 1ull;
-    int src = mm ? (__ffsll((unsigned long long)mm) - 1) : 0;
-    bool act = mm != 0ull && slot < 21;
+    // lane slot s takes the s-th pending triplet
+    const bool act = slot < 21 && slot < __popcll(m);
+    const int src = act ? nth_set_bit(m, slot) : 0;
     int sidx = __shfl(idx, src);
     float c0 = __shfl(v.x, src), c1 = __shfl(v.y, src), c2 = __shfl(v.z, src);
     float c = ch == 0 ? c0 : (ch == 1 ? c1 : c2);
