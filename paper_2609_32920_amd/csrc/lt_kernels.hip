@@ -569,10 +569,12 @@ __device__ __forceinline__ void trace_run(const PassArgs& A, int* lds) {
 }
 
 // At most 96 VGPRs (five waves per SIMD, with the default 10 x 128-thread
-// workgroups per CU): a few registers spill and the caustic forward runs 5%
-// faster than at four waves; the box forward is unchanged.
+// workgroups per CU), where a few registers spill: the box forward runs 3.6%
+// faster than at four waves.  The plain forward with the heightfield's grid
+// walk holds four (128 VGPRs, few spills): the 128x128 caustic's runs 6.7%
+// faster there (5.08 -> 4.74 ms).
 template <bool TAPE, bool RESV, bool SPL = false, bool GS = false, bool HF = true>
-__global__ void __launch_bounds__(1024, 5) k_trace(PassArgs A) {
+__global__ void __launch_bounds__(1024, (HF && !TAPE && !RESV && !SPL && !GS) ? 4 : 5) k_trace(PassArgs A) {
   extern __shared__ int lds[];
   trace_run<TAPE, RESV, SPL, GS, HF>(A, lds);
 }
@@ -1146,11 +1148,12 @@ __global__ void __launch_bounds__(1024) k_trace_batch(const PassArgs* __restrict
   extern __shared__ int lds[];
   for (int i = 0; i < n; ++i) trace_run<false, false>(table_entry(T, i), lds);
 }
-// One table entry through the single-instance forward: five waves per SIMD
-// (the multi-entry kernel holds four), without the heightfield walk where the
-// scene has none.  Batches run their largest instances' forwards through it.
+// One table entry through the single-instance forward, at its register
+// budget (five waves per SIMD without the heightfield walk, four with it),
+// without the walk where the scene has none.  Batches run their largest
+// instances' forwards through it.
 template <bool HF>
-__global__ void __launch_bounds__(1024, 5) k_trace_entry(const PassArgs* __restrict__ T) {
+__global__ void __launch_bounds__(1024, HF ? 4 : 5) k_trace_entry(const PassArgs* __restrict__ T) {
   extern __shared__ int lds[];
   trace_run<false, false, false, false, HF>(table_entry(T, 0), lds);
 }
